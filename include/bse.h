@@ -1,0 +1,173 @@
+/*
+ * bse.h -- C ABI of the gfx950 (MI355X) structure-preserving eigensolver for
+ * Bethe-Salpeter Hamiltonians
+ *
+ *     H = [ A        B      ]     A = A^H,  B = B^T  (complex n x n),
+ *         [ -conj(B) -conj(A)]    Omega = [A B; conj(B) conj(A)] > 0,
+ *
+ * (Shao, da Jornada, Yang, Deslippe, Louie, arXiv:1501.03830: eq. H-complex,
+ * eq. symmetry and the definiteness condition eq. cond).  The solver computes
+ * the n positive eigenvalues lambda_1 <= ... <= lambda_n of H and the right
+ * eigenvectors x_j = [X1; X2] e_j normalised as in Theorem 3 / Algorithm 1,
+ *     H [X1; X2] = [X1; X2] Lambda_+,   X1^H X1 - X2^H X2 = I_n,
+ * by the structure-preserving route of Algorithm 1 (real embedding M,
+ * Cholesky M = L L^T, skew-symmetric W = L^T J L) carried out as in
+ * Algorithm 3 (Householder tridiagonalisation W = U T U^T, bisection and
+ * inverse iteration on -i D^H T D, back-transformation).  Left eigenvectors
+ * are y_j = S x_j with S = diag(I_n, -I_n), and the eigenvectors of -lambda_j
+ * are [conj X2; conj X1] (Theorem 3); neither is stored.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - All matrix and vector arguments are DEVICE pointers on the context's
+ *    device unless stated otherwise.  The caller owns every buffer it passes;
+ *    the library never frees or retains caller memory after a call returns.
+ *  - Complex data are complex128, interleaved (re, im), COLUMN-MAJOR with the
+ *    given leading dimension counted in complex elements.
+ *  - Only the LOWER triangles (diagonal included) of A and B are read.  A row-
+ *    major Hermitian array handed over as column-major is conj(A); pass its
+ *    transpose.  The imaginary part of A's diagonal is ignored.
+ *  - All work is ordered on the context's stream.  Calls are synchronous:
+ *    they return after the device work has completed.
+ *  - A context is not thread-safe: use one per host thread or serialise.
+ *
+ * Return values
+ * -------------
+ *  BSE_OK (0) on success;  -i when argument i (1-based) is invalid;  +k when
+ *  the leading k x k minor of the real embedding M is not positive definite,
+ *  i.e. eq. cond fails (Algorithm 1 requires it), in which case no outputs
+ *  are written;  BSE_ENOMEM when a caller-provided arena is too small;
+ *  BSE_EDEVICE on a HIP runtime error (details from bse_last_error()).
+ */
+#ifndef BSE_H_
+#define BSE_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BSE_OK 0
+#define BSE_ENOMEM (-1000)
+#define BSE_EDEVICE (-1001)
+#define BSE_ENOTICKET (-1002)
+#define BSE_EUNSUPPORTED (-1003)
+
+/* precision policies */
+#define BSE_PREC_FP64 0        /* every stage in FP64                          */
+
+/* flags for bse_solve */
+#define BSE_WANT_VECTORS 1u    /* write X (else only lambda)                   */
+#define BSE_WANT_WEIGHTS 2u    /* write the absorption weights w (needs X)      */
+
+/* stage indices of bse_report.stage_ms */
+#define BSE_STAGE_BUILD_M 0    /* Algorithm 1 step 1                           */
+#define BSE_STAGE_POTRF 1      /* Algorithm 1 step 2                           */
+#define BSE_STAGE_FORM_W 2     /* Algorithm 1 step 3                           */
+#define BSE_STAGE_SKTRD 3      /* Algorithm 3 step 1                           */
+#define BSE_STAGE_BISECT 4     /* Algorithm 3 step 2, eigenvalues              */
+#define BSE_STAGE_INVIT 5      /* Algorithm 3 step 2, eigenvectors             */
+#define BSE_STAGE_REORTH 6     /* Algorithm 3 step 2, reorthogonalisation      */
+#define BSE_STAGE_APPLY_U 7    /* Algorithm 3 step 3 (U applied to D V_+)      */
+#define BSE_STAGE_APPLY_L 8    /* Algorithm 3 step 3 (L applied)               */
+#define BSE_STAGE_FINISH 9     /* Algorithm 3 steps 4-6, phase, weights        */
+#define BSE_NUM_STAGES 10
+
+typedef struct bse_ctx bse_ctx;
+
+/* Per-call timing, filled when a non-NULL pointer is passed (host memory). */
+typedef struct bse_report {
+  double total_ms;                 /* device time of the whole call          */
+  double stage_ms[BSE_NUM_STAGES]; /* device time per stage (hipEvents)      */
+  int n;                           /* problem size of the call               */
+  int prec;                        /* precision policy used                  */
+  size_t workspace_bytes;          /* device workspace the call used         */
+} bse_report;
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int bse_version(void);
+
+/* Text of the last error recorded on this host thread ("" if none).  The
+ * returned pointer stays valid until the next failing call on the thread. */
+const char* bse_last_error(void);
+
+/* Create a context bound to HIP device `device` and HIP stream `stream`
+ * (a hipStream_t, NULL for the default stream).  `arena`/`arena_bytes`: an
+ * optional caller-owned device buffer used for all workspace; when NULL the
+ * library allocates workspace itself with hipMalloc, grows it on demand and
+ * frees it in bse_ctx_destroy.  Returns -1 if ctx is NULL, -2 for a bad
+ * device, -4 if arena_bytes is non-zero without an arena. */
+int bse_ctx_create(bse_ctx** ctx, int device, void* arena, size_t arena_bytes, void* stream);
+
+/* Destroy a context (waits for its stream).  NULL is accepted. */
+int bse_ctx_destroy(bse_ctx* ctx);
+
+/* Device workspace, in bytes, that bse_solve needs for size n (host-only
+ * arithmetic, callable without a GPU).  0 for invalid arguments. */
+size_t bse_footprint_bytes(int n, int prec, unsigned flags);
+
+/*
+ * Full structure-preserving eigensolve (Algorithm 1 as organised by
+ * Algorithm 3).
+ *   ctx      context (argument 1)
+ *   n        order of A and B, n >= 1 (2)
+ *   A, lda   complex n x n, lda >= n, lower triangle read (3, 4)
+ *   B, ldb   complex n x n, ldb >= n, lower triangle read (5, 6)
+ *   prec     BSE_PREC_FP64 (7)
+ *   flags    BSE_WANT_VECTORS | BSE_WANT_WEIGHTS (8)
+ *   lambda   out: n doubles, the positive eigenvalues ascending (9)
+ *   X, ldx   out: complex 2n x n, ldx >= 2n; rows 0..n-1 hold X1, rows
+ *            n..2n-1 hold X2; each column is scaled by a unit phase so that
+ *            its largest-modulus entry (lowest row on ties) is real positive
+ *            (10, 11).  May be NULL without BSE_WANT_VECTORS.
+ *   d_r, d_l in: complex 2n dipole vectors of eq. absp (12, 13); d_l NULL
+ *            means d_l = d_r.  Read only with BSE_WANT_WEIGHTS.
+ *   w        out: n complex weights w_j = (d_r^H x_j)(y_j^H d_l)/(y_j^H x_j)
+ *            of eq. absp, y_j = S x_j (14).
+ *   rep      optional host report (15).
+ */
+int bse_solve(bse_ctx* ctx, int n, const void* A, int lda, const void* B, int ldb, int prec,
+              unsigned flags, double* lambda, void* X, int ldx, const void* d_r, const void* d_l,
+              void* w, bse_report* rep);
+
+/* ---------------------------------------------------------------------------
+ * Stage entry points.  Each runs one step of the chain on caller buffers so
+ * that it can be checked on its own.  Real matrices are FP64 column-major.
+ * ------------------------------------------------------------------------ */
+
+/* Algorithm 1 step 1 (Theorem 2, eq. embedding):
+ *   M = [Re(A+B) Im(A-B); -Im(A+B) Re(A-B)],  2n x 2n, ldm >= 2n.
+ * Writes the lower triangle of M and zeros above the diagonal. */
+int bse_build_M(bse_ctx* ctx, int n, const void* A, int lda, const void* B, int ldb, double* M,
+                int ldm);
+
+/* Algorithm 1 step 2: lower Cholesky factor M = L L^T in place (N x N,
+ * ldm >= N; lower triangle read, L written to the lower triangle, the strict
+ * upper triangle set to zero).  Returns +k if the leading k x k minor is not
+ * positive definite (M is then left partially factored). */
+int bse_potrf(bse_ctx* ctx, int N, double* M, int ldm);
+
+/* Algorithm 1 step 3: W = L^T J_n L for N = 2n, from lower-triangular L
+ * (strict upper triangle of L ignored).  Writes the full skew-symmetric W. */
+int bse_form_W(bse_ctx* ctx, int N, const double* L, int ldl, double* W, int ldw);
+
+/* Algorithm 3 step 1 (remark 1): W = U T U^T with U = H_0 ... H_{N-3},
+ * H_k = I - tau_k v_k v_k^T.  In: skew W (lower triangle read).  Out:
+ * alpha[k] = T[k,k+1] for k = 0..N-2 (T[k+1,k] = -alpha[k]), tau[k] for
+ * k = 0..N-2 (tau[N-2] = 0), and v_k below the subdiagonal of W's column k
+ * (v_k[k+1] = 1 implicit).  N >= 2. */
+int bse_sktrd(bse_ctx* ctx, int N, double* W, int ldw, double* alpha, double* tau);
+
+/* Algorithm 3 step 2 (remark 2): the n = N/2 positive eigenvalues of
+ * T_s = tridiag(alpha, 0, alpha) (ascending, by bisection) and, when V is
+ * non-NULL, orthonormal eigenvectors V (N x n, ldv >= N) by inverse iteration
+ * reorthogonalised inside clusters.  alpha: N-1 doubles.  N even, >= 2. */
+int bse_tridiag_eig(bse_ctx* ctx, int N, const double* alpha, double* lambda, double* V, int ldv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSE_H_ */

@@ -1,0 +1,102 @@
+"""ctypes view of libbse.so (include/bse.h).  Argument marshalling only."""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbse.so")
+
+BSE_OK = 0
+BSE_ENOMEM = -1000
+BSE_EDEVICE = -1001
+BSE_ENOTICKET = -1002
+BSE_EUNSUPPORTED = -1003
+
+BSE_PREC_FP64 = 0
+
+BSE_WANT_VECTORS = 1
+BSE_WANT_WEIGHTS = 2
+
+BSE_NUM_STAGES = 10
+STAGE_NAMES = ["build_M", "potrf", "form_W", "sktrd", "bisect", "invit", "reorth", "apply_U",
+               "apply_L", "finish"]
+
+
+class BseReport(ctypes.Structure):
+    _fields_ = [
+        ("total_ms", ctypes.c_double),
+        ("stage_ms", ctypes.c_double * BSE_NUM_STAGES),
+        ("n", ctypes.c_int),
+        ("prec", ctypes.c_int),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+    def as_dict(self):
+        return {
+            "total_ms": self.total_ms,
+            "stage_ms": {name: self.stage_ms[i] for i, name in enumerate(STAGE_NAMES)},
+            "n": self.n,
+            "prec": self.prec,
+            "workspace_bytes": self.workspace_bytes,
+        }
+
+
+# (name, restype, argtypes) for every symbol declared in include/bse.h
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_U = ctypes.c_uint
+_D = ctypes.POINTER(ctypes.c_double)
+SIGNATURES = [
+    ("bse_version", _I, []),
+    ("bse_last_error", ctypes.c_char_p, []),
+    ("bse_ctx_create", _I, [ctypes.POINTER(_P), _I, _P, ctypes.c_size_t, _P]),
+    ("bse_ctx_destroy", _I, [_P]),
+    ("bse_footprint_bytes", ctypes.c_size_t, [_I, _I, _U]),
+    ("bse_solve", _I, [_P, _I, _P, _I, _P, _I, _I, _U, _P, _P, _I, _P, _P, _P, ctypes.POINTER(BseReport)]),
+    ("bse_build_M", _I, [_P, _I, _P, _I, _P, _I, _P, _I]),
+    ("bse_potrf", _I, [_P, _I, _P, _I]),
+    ("bse_form_W", _I, [_P, _I, _P, _I, _P, _I]),
+    ("bse_sktrd", _I, [_P, _I, _P, _I, _P, _P]),
+    ("bse_tridiag_eig", _I, [_P, _I, _P, _P, _P, _I]),
+]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libbse.so.  Raises if it has not been built: there is no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} not found: build the HIP library first (python -m paper_1501_03830_amd.build)")
+    lib = ctypes.CDLL(path)
+    for name, res, args in SIGNATURES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    lib = load()
+    s = lib.bse_last_error()
+    return s.decode() if s else ""
+
+
+class BseError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what} returned {code}: {last_error()}")
+
+
+def check(code: int, what: str) -> int:
+    """Raise on negative codes; positive codes (leading minor not definite)
+    are returned to the caller."""
+    if code < 0:
+        raise BseError(code, what)
+    return code

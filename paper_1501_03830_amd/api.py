@@ -1,0 +1,143 @@
+"""Python front end of libbse: torch tensors in, torch tensors out.
+
+Only argument marshalling happens here.  Every step of the solve runs in the
+HIP kernels behind the C ABI; torch provides device memory and the stream.
+Matrices cross the boundary column-major, so a logical (rows x cols) matrix
+is held in a contiguous torch tensor of shape (cols, rows) and passed by
+pointer.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+
+_P = ctypes.c_void_p
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def to_colmajor(M: torch.Tensor, device) -> torch.Tensor:
+    """Column-major device copy of a logical matrix M: a contiguous tensor
+    holding M^T row-major (same bytes as M column-major)."""
+    return M.to(device).transpose(0, 1).contiguous()
+
+
+def from_colmajor(buf: torch.Tensor) -> torch.Tensor:
+    """Logical matrix from a column-major buffer created by to_colmajor."""
+    return buf.transpose(0, 1)
+
+
+class Context:
+    """A bse_ctx bound to a CUDA/HIP device and the current torch stream."""
+
+    def __init__(self, device: int | torch.device = 0, stream: torch.cuda.Stream | None = None,
+                 arena: torch.Tensor | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libbse needs a GPU; none is visible")
+        self.lib = _lib.load()
+        self.device = torch.device("cuda", device if isinstance(device, int) else device.index or 0)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._arena = arena
+        h = _P()
+        arena_ptr = _ptr(arena)
+        arena_bytes = 0 if arena is None else arena.numel() * arena.element_size()
+        _lib.check(self.lib.bse_ctx_create(ctypes.byref(h), self.device.index, arena_ptr, arena_bytes,
+                                           _P(self.stream.cuda_stream)), "bse_ctx_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.bse_ctx_destroy(self.h)
+            self.h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ solve
+    def solve(self, A: torch.Tensor, B: torch.Tensor, d_r: torch.Tensor | None = None,
+              d_l: torch.Tensor | None = None, vectors: bool = True, report: bool = False):
+        """Full eigensolve.  A, B: complex128 (n, n) logical matrices (lower
+        triangles used).  Returns dict with lam (n,), X (2n, n) or None,
+        w (n,) or None, info, report."""
+        n = A.shape[0]
+        dev = self.device
+        Ac = to_colmajor(A.to(torch.complex128), dev)
+        Bc = to_colmajor(B.to(torch.complex128), dev)
+        lam = torch.empty(n, dtype=torch.float64, device=dev)
+        flags = 0
+        Xbuf = None
+        w = None
+        drb = dlb = None
+        if vectors:
+            flags |= _lib.BSE_WANT_VECTORS
+            Xbuf = torch.empty((n, 2 * n), dtype=torch.complex128, device=dev)
+        if d_r is not None:
+            flags |= _lib.BSE_WANT_WEIGHTS | _lib.BSE_WANT_VECTORS
+            if Xbuf is None:
+                Xbuf = torch.empty((n, 2 * n), dtype=torch.complex128, device=dev)
+            drb = d_r.to(dev, torch.complex128).contiguous()
+            dlb = None if d_l is None else d_l.to(dev, torch.complex128).contiguous()
+            w = torch.empty(n, dtype=torch.complex128, device=dev)
+        rep = _lib.BseReport() if report else None
+        info = _lib.check(self.lib.bse_solve(
+            self.h, n, _ptr(Ac), n, _ptr(Bc), n, _lib.BSE_PREC_FP64, flags, _ptr(lam),
+            _ptr(Xbuf), 2 * n, _ptr(drb), _ptr(dlb), _ptr(w),
+            ctypes.byref(rep) if rep is not None else None), "bse_solve")
+        return {
+            "info": info,
+            "lam": lam,
+            "X": None if Xbuf is None else from_colmajor(Xbuf),
+            "w": w,
+            "report": rep.as_dict() if rep is not None else None,
+        }
+
+    # ----------------------------------------------------------------- stages
+    def build_M(self, A: torch.Tensor, B: torch.Tensor) -> torch.Tensor:
+        n = A.shape[0]
+        Ac = to_colmajor(A.to(torch.complex128), self.device)
+        Bc = to_colmajor(B.to(torch.complex128), self.device)
+        Mb = torch.empty((2 * n, 2 * n), dtype=torch.float64, device=self.device)
+        _lib.check(self.lib.bse_build_M(self.h, n, _ptr(Ac), n, _ptr(Bc), n, _ptr(Mb), 2 * n), "bse_build_M")
+        return from_colmajor(Mb)
+
+    def potrf(self, M: torch.Tensor):
+        N = M.shape[0]
+        Mb = to_colmajor(M.to(torch.float64), self.device)
+        info = _lib.check(self.lib.bse_potrf(self.h, N, _ptr(Mb), N), "bse_potrf")
+        return from_colmajor(Mb), info
+
+    def form_W(self, L: torch.Tensor) -> torch.Tensor:
+        N = L.shape[0]
+        Lb = to_colmajor(L.to(torch.float64), self.device)
+        Wb = torch.empty((N, N), dtype=torch.float64, device=self.device)
+        _lib.check(self.lib.bse_form_W(self.h, N, _ptr(Lb), N, _ptr(Wb), N), "bse_form_W")
+        return from_colmajor(Wb)
+
+    def sktrd(self, W: torch.Tensor):
+        N = W.shape[0]
+        Wb = to_colmajor(W.to(torch.float64), self.device)
+        alpha = torch.empty(N - 1, dtype=torch.float64, device=self.device)
+        tau = torch.empty(N - 1, dtype=torch.float64, device=self.device)
+        _lib.check(self.lib.bse_sktrd(self.h, N, _ptr(Wb), N, _ptr(alpha), _ptr(tau)), "bse_sktrd")
+        return from_colmajor(Wb), alpha, tau
+
+    def tridiag_eig(self, alpha: torch.Tensor, vectors: bool = True):
+        N = alpha.shape[0] + 1
+        a = alpha.to(self.device, torch.float64).contiguous()
+        lam = torch.empty(N // 2, dtype=torch.float64, device=self.device)
+        Vb = torch.empty((N // 2, N), dtype=torch.float64, device=self.device) if vectors else None
+        _lib.check(self.lib.bse_tridiag_eig(self.h, N, _ptr(a), _ptr(lam), _ptr(Vb), N), "bse_tridiag_eig")
+        return lam, (None if Vb is None else from_colmajor(Vb))
+
+
+def footprint_bytes(n: int, prec: int = _lib.BSE_PREC_FP64, flags: int = 0) -> int:
+    return int(_lib.load().bse_footprint_bytes(n, prec, flags))

@@ -1,0 +1,94 @@
+// Shared definitions for the gfx950 kernels of the Bethe-Salpeter solver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/bse.h"
+
+namespace bse {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+// Leading dimension used for every N x N device matrix: a multiple of 64 so
+// that 64 x 64 tiles are aligned, with all tiles of the padded square
+// allocated (kernels read whole tiles and mask, they never read past ld x ld).
+inline long round_up(long x, long m) { return (x + m - 1) / m * m; }
+inline long square_ld(long N) { return round_up(N < 64 ? 64 : N, 64); }
+
+// Record a HIP failure for bse_last_error() and turn it into BSE_EDEVICE.
+int set_hip_error(hipError_t e, const char* what, const char* file, int line);
+
+#define BSE_HIP(call)                                                        \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess) return ::bse::set_hip_error(e_, #call, __FILE__, __LINE__); \
+  } while (0)
+
+#define BSE_LAUNCHED()                                                       \
+  do {                                                                       \
+    hipError_t e_ = hipGetLastError();                                       \
+    if (e_ != hipSuccess) return ::bse::set_hip_error(e_, "kernel launch", __FILE__, __LINE__); \
+  } while (0)
+
+#define BSE_TRY(expr)                                                        \
+  do {                                                                       \
+    int rc_ = (expr);                                                        \
+    if (rc_ != 0) return rc_;                                                \
+  } while (0)
+
+// Row/column decomposition of a linear index over the lower triangle of an
+// nt x nt tile grid: t = R (R + 1) / 2 + C with 0 <= C <= R < nt.
+__device__ inline void tri_index(long t, int& R, int& C) {
+  long r = (long)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while (r * (r + 1) / 2 > t) --r;
+  while ((r + 1) * (r + 2) / 2 <= t) ++r;
+  R = (int)r;
+  C = (int)(t - r * (r + 1) / 2);
+}
+
+// Sum over the 64 lanes of a wavefront; every lane gets the total.
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block-wide sum for blockDim.x <= 1024 (multiple of 64).  `red` must hold
+// blockDim.x / 64 doubles.  Every thread returns the total.
+__device__ inline double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  const int nw = blockDim.x >> 6;
+  for (int i = 0; i < nw; ++i) t += red[i];
+  return t;
+}
+
+// Device-wide "last workgroup" detection: every workgroup calls this once
+// after writing its partial results; it returns true in exactly one (the
+// last to arrive), which may then read all partials.  The counter is
+// restored to zero by the last workgroup so it can be reused by the next
+// launch on the same stream.
+__device__ inline bool arrive_last(unsigned int* counter, unsigned int expected, int* flag_smem) {
+  // every thread publishes its own writes at device (agent) scope
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned int prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    int last = (prev == expected - 1) ? 1 : 0;
+    if (last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *flag_smem = last;
+  }
+  __syncthreads();
+  const bool last = *flag_smem != 0;
+  if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return last;
+}
+
+}  // namespace bse

@@ -1,0 +1,337 @@
+// Eigenpairs of the real symmetric tridiagonal T_s = -i D^H T D =
+// tridiag(alpha, 0, alpha), D = diag(i^k) (Algorithm 3 step 2; Section 3.3,
+// remark 2).  Only the n positive eigenvalues and their eigenvectors are
+// computed, as in the paper:
+//
+//  * bisection with Sturm counts, one eigenvalue per thread.  The recurrence
+//    q_0 = -x,  q_k = -x - alpha_{k-1}^2 / q_{k-1}  (pivots smaller than
+//    pivmin replaced by -pivmin) counts the eigenvalues below x; T_s is
+//    nonsingular, so exactly n eigenvalues are negative and the j-th positive
+//    one is the (n+j)-th smallest.  Intervals start at [0, Gershgorin bound]
+//    and are halved to a relative width of 2 eps.
+//  * inverse iteration, one eigenvector per thread: Gaussian elimination with
+//    partial pivoting of T_s - sigma I (factors kept in HBM, interleaved over
+//    the eigenvectors so that every access is coalesced), three solves from a
+//    pseudo-random start.  Shifts closer than 10 eps |lambda| are pushed apart.
+//  * reorthogonalisation inside clusters (eigenvalues closer than
+//    1e-3 ||T_s||_1): Gram-Schmidt in ascending order, realised as a Cholesky
+//    QR of the Gram matrix with the entries between different clusters
+//    removed (the Q factor of that QR is exactly the Gram-Schmidt result).
+#include <cfloat>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace bse {
+
+namespace {
+
+constexpr double EPS = DBL_EPSILON;   // 2^-52
+constexpr double SAFMIN = DBL_MIN;
+
+// scal[0] = pivmin, scal[1] = Gershgorin bound ||T_s||_1, scal[2] = max alpha^2
+__global__ __launch_bounds__(1024) void k_tridiag_prep(const double* __restrict__ alpha, int N,
+                                                       double* __restrict__ e2, double* __restrict__ scal) {
+  __shared__ double smax[16], sg[16];
+  double m = 0.0, g = 0.0;
+  for (int k = threadIdx.x; k < N; k += blockDim.x) {
+    const double a = (k < N - 1) ? alpha[k] : 0.0;
+    if (k < N - 1) e2[k] = a * a;
+    m = fmax(m, a * a);
+    const double left = (k > 0) ? fabs(alpha[k - 1]) : 0.0;
+    g = fmax(g, left + fabs(a));
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    m = fmax(m, __shfl_xor(m, off, 64));
+    g = fmax(g, __shfl_xor(g, off, 64));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    smax[w] = m;
+    sg[w] = g;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mm = 0.0, gg = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+      mm = fmax(mm, smax[i]);
+      gg = fmax(gg, sg[i]);
+    }
+    scal[0] = SAFMIN * fmax(1.0, mm);
+    scal[1] = gg;
+    scal[2] = mm;
+  }
+}
+
+__device__ inline int sturm_count(const double* __restrict__ e2, int N, double x, double pivmin) {
+  double q = -x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  int c = q < 0.0;
+  for (int k = 1; k < N; ++k) {
+    q = -x - e2[k - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    c += q < 0.0;
+  }
+  return c;
+}
+
+__global__ __launch_bounds__(64) void k_bisect(const double* __restrict__ e2, int N,
+                                               const double* __restrict__ scal, double* __restrict__ lam) {
+  const int n = N / 2;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const double pivmin = scal[0];
+  double lo = 0.0;
+  double hi = scal[1] * (1.0 + 4.0 * EPS) + 4.0 * pivmin;
+  const int target = n + j;
+  for (int it = 0; it < 200; ++it) {
+    const double tol = fmax(2.0 * EPS * fmax(fabs(lo), fabs(hi)), 4.0 * pivmin);
+    if (hi - lo <= tol) break;
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) {
+      hi = lo;
+      break;
+    }
+    const int c = sturm_count(e2, N, mid, pivmin);
+    if (c <= target) lo = mid;
+    else hi = mid;
+  }
+  lam[j] = 0.5 * (lo + hi);
+}
+
+__global__ void k_shifts(const double* __restrict__ lam, int n, double* __restrict__ shift) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double prev = lam[0];
+  shift[0] = prev;
+  for (int j = 1; j < n; ++j) {
+    double sj = lam[j];
+    const double pertol = 10.0 * EPS * fabs(sj);
+    if (sj - prev < pertol) sj = prev + pertol;
+    shift[j] = sj;
+    prev = sj;
+  }
+}
+
+__device__ inline double hash_uniform(unsigned long long key) {
+  // splitmix64 finaliser, mapped to [-1, 1)
+  unsigned long long z = key + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+__device__ inline double perturb(double d, double pert) {
+  return (fabs(d) < pert) ? (d < 0.0 ? -pert : pert) : d;
+}
+
+// Workspace per eigenvector j (n of them), element k at [k*n + j]:
+//   fd (U diagonal), fu (first superdiagonal), fu2 (second), fl (multiplier),
+//   fs (row interchange flag).  Vt holds the iterate.
+__global__ __launch_bounds__(64) void k_invit(const double* __restrict__ alpha, int N,
+                                              const double* __restrict__ scal,
+                                              const double* __restrict__ shift,
+                                              double* __restrict__ fd, double* __restrict__ fu,
+                                              double* __restrict__ fu2, double* __restrict__ fl,
+                                              unsigned char* __restrict__ fs, double* __restrict__ Vt) {
+  const int n = N / 2;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const long ldn = n;
+  const double pert = EPS * fmax(scal[1], SAFMIN);
+  const double sh = shift[j];
+
+  // factorisation (LAPACK dgttrf scheme) of T_s - sh I
+  double cur_d = -sh;
+  double cur_du = (N > 1) ? alpha[0] : 0.0;
+  for (int k = 0; k < N - 1; ++k) {
+    const double dlk = alpha[k];
+    const double next_d = -sh;
+    const double next_du = (k + 1 < N - 1) ? alpha[k + 1] : 0.0;
+    const long o = (long)k * ldn + j;
+    if (fabs(cur_d) >= fabs(dlk)) {
+      const double dk = perturb(cur_d, pert);
+      const double l = dlk / dk;
+      fd[o] = dk;
+      fu[o] = cur_du;
+      fu2[o] = 0.0;
+      fl[o] = l;
+      fs[o] = 0;
+      cur_d = next_d - l * cur_du;
+      cur_du = next_du;
+    } else {
+      const double l = cur_d / dlk;
+      fd[o] = perturb(dlk, pert);
+      fu[o] = next_d;
+      fu2[o] = next_du;
+      fl[o] = l;
+      fs[o] = 1;
+      cur_d = cur_du - l * next_d;
+      cur_du = -l * next_du;
+    }
+  }
+  fd[(long)(N - 1) * ldn + j] = perturb(cur_d, pert);
+
+  // start vector
+  for (int k = 0; k < N; ++k)
+    Vt[(long)k * ldn + j] = hash_uniform(((unsigned long long)j << 32) ^ (unsigned long long)k ^ 0x5bd1e995ull);
+
+  for (int it = 0; it < 3; ++it) {
+    // forward: apply the row interchanges and multipliers
+    double cur = Vt[j];
+    for (int k = 0; k < N - 1; ++k) {
+      const long o = (long)k * ldn + j;
+      const double nxt = Vt[o + ldn];
+      const double l = fl[o];
+      double outk;
+      if (fs[o]) {
+        outk = nxt;
+        cur = cur - l * nxt;
+      } else {
+        outk = cur;
+        cur = nxt - l * cur;
+      }
+      Vt[o] = outk;
+    }
+    Vt[(long)(N - 1) * ldn + j] = cur;
+    // back substitution with the upper factor
+    double x2 = 0.0, x1 = 0.0, ss = 0.0;
+    for (int k = N - 1; k >= 0; --k) {
+      const long o = (long)k * ldn + j;
+      double v = Vt[o];
+      if (k <= N - 2) v -= fu[o] * x1;
+      if (k <= N - 3) v -= fu2[o] * x2;
+      const double x = v / fd[o];
+      Vt[o] = x;
+      ss += x * x;
+      x2 = x1;
+      x1 = x;
+    }
+    const double inv = 1.0 / sqrt(ss);
+    for (int k = 0; k < N; ++k) Vt[(long)k * ldn + j] *= inv;
+  }
+}
+
+// cid[j] = index of the cluster of eigenvalue j (consecutive gaps <= ortol)
+__global__ __launch_bounds__(1024) void k_cluster_ids(const double* __restrict__ lam, int n,
+                                                      const double* __restrict__ scal, int* __restrict__ cid) {
+  __shared__ int sums[1024];
+  const double ortol = 1e-3 * scal[1];
+  const int T = blockDim.x;
+  const int chunk = (n + T - 1) / T;
+  const int b = threadIdx.x * chunk, e = min(n, b + chunk);
+  int local = 0;
+  for (int jj = b; jj < e; ++jj)
+    if (jj > 0 && lam[jj] - lam[jj - 1] > ortol) ++local;
+  sums[threadIdx.x] = local;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int t = 0; t < T; ++t) {
+      const int v = sums[t];
+      sums[t] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  int run = sums[threadIdx.x];
+  for (int jj = b; jj < e; ++jj) {
+    if (jj > 0 && lam[jj] - lam[jj - 1] > ortol) ++run;
+    cid[jj] = run;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mask_gram(double* __restrict__ G, long ldg, int n,
+                                                   const int* __restrict__ cid) {
+  const long r = (long)blockIdx.x * 64 + (threadIdx.x & 63);
+  const long c0 = (long)blockIdx.y * 64 + (threadIdx.x >> 6) * 16;
+  if (r >= n) return;
+  const int cr = cid[r];
+  for (int q = 0; q < 16; ++q) {
+    const long c = c0 + q;
+    if (c >= n || c > r) break;
+    if (cid[c] != cr) G[r + c * ldg] = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_transpose(int rows, int cols, const double* __restrict__ src, long lds,
+                                                   double* __restrict__ dst, long ldd) {
+  __shared__ double t[64][65];
+  const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+  for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
+    const int i = idx & 63, jj = idx >> 6;
+    const int r = r0 + i, c = c0 + jj;
+    t[jj][i] = (r < rows && c < cols) ? src[(long)r + (long)c * lds] : 0.0;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
+    const int i = idx & 63, jj = idx >> 6;   // dst row = c0 + i, dst col = r0 + jj
+    const int dr = c0 + i, dc = r0 + jj;
+    if (dr < cols && dc < rows) dst[(long)dr + (long)dc * ldd] = t[i][jj];
+  }
+}
+
+}  // namespace
+
+int tridiag_bisect(hipStream_t s, int N, const double* alpha, double* e2, double* scal, double* lam) {
+  const int n = N / 2;
+  k_tridiag_prep<<<1, 1024, 0, s>>>(alpha, N, e2, scal);
+  BSE_LAUNCHED();
+  k_bisect<<<(n + 63) / 64, 64, 0, s>>>(e2, N, scal, lam);
+  BSE_LAUNCHED();
+  return 0;
+}
+
+int tridiag_invit(hipStream_t s, int N, const double* alpha, const double* scal, const double* lam,
+                  double* shift, double* work, double* Vt) {
+  const int n = N / 2;
+  const long sz = (long)N * n;
+  double* fd = work;
+  double* fu = work + sz;
+  double* fu2 = work + 2 * sz;
+  double* fl = work + 3 * sz;
+  unsigned char* fs = reinterpret_cast<unsigned char*>(work + 4 * sz);
+  k_shifts<<<1, 64, 0, s>>>(lam, n, shift);
+  BSE_LAUNCHED();
+  k_invit<<<(n + 63) / 64, 64, 0, s>>>(alpha, N, scal, shift, fd, fu, fu2, fl, fs, Vt);
+  BSE_LAUNCHED();
+  return 0;
+}
+
+int tridiag_reorth(hipStream_t s, int N, const double* lam, const double* scal, double* Vt, double* G,
+                   int* cid, int* info_dev, double* linv) {
+  const int n = N / 2;
+  k_cluster_ids<<<1, 1024, 0, s>>>(lam, n, scal, cid);
+  BSE_LAUNCHED();
+  // Two passes of Cholesky QR ("twice is enough"): the second restores full
+  // orthogonality when a degenerate cluster's start vectors were close.
+  dim3 g2((unsigned)((n + 63) / 64), (unsigned)((n + 63) / 64));
+  for (int pass = 0; pass < 2; ++pass) {
+    // G = Vt Vt^T (lower), then drop the entries between clusters
+    BSE_TRY(gemm_f64(s, false, true, n, n, N, 1.0, Vt, n, Vt, n, 0.0, G, n, 1, 0, 0));
+    k_mask_gram<<<g2, 256, 0, s>>>(G, n, n, cid);
+    BSE_LAUNCHED();
+    BSE_TRY(potrf_f64(s, n, G, n, info_dev, linv, pass == 0));
+    // Vt <- L^{-1} Vt  (blocked forward substitution; the diagonal block is
+    // applied through its inverse, in place: one row tile of output)
+    for (int b0 = 0; b0 < n; b0 += 64) {
+      const int nbk = (n - b0 < 64) ? n - b0 : 64;
+      BSE_TRY(trtri_diag64(s, G, n, b0, nbk, linv, info_dev));
+      BSE_TRY(gemm_f64(s, false, false, nbk, N, nbk, 1.0, linv, 64, Vt + b0, n, 0.0, Vt + b0, n, 0, 0, 0));
+      const int rest = n - b0 - nbk;
+      if (rest > 0)
+        BSE_TRY(gemm_f64(s, false, false, rest, N, nbk, -1.0, G + (b0 + nbk) + (long)b0 * n, n, Vt + b0, n, 1.0,
+                         Vt + b0 + nbk, n, 0, 0, 0));
+    }
+  }
+  return 0;
+}
+
+int transpose_to(hipStream_t s, int rows, int cols, const double* src, long lds, double* dst, long ldd) {
+  dim3 g((unsigned)((rows + 63) / 64), (unsigned)((cols + 63) / 64));
+  k_transpose<<<g, 256, 0, s>>>(rows, cols, src, lds, dst, ldd);
+  BSE_LAUNCHED();
+  return 0;
+}
+
+}  // namespace bse
