@@ -84,6 +84,14 @@ typedef struct bse_report {
   int n;                           /* problem size of the call               */
   int prec;                        /* precision policy used                  */
   size_t workspace_bytes;          /* device workspace the call used         */
+  /* Filled only while kernel timing is on (bse_ctx_set_timing): hipEvents
+   * around every launch of the tiled skew matrix-vector kernel of the
+   * tridiagonalisation (Algorithm 3 step 1), the dominant HBM-bound kernel. */
+  double symv_ms;                  /* summed device time of those launches   */
+  double symv_bytes;               /* algorithmic bytes they must read: the
+                                      strictly lower triangle of each trailing
+                                      matrix, 8 bytes per element             */
+  long long symv_launches;         /* number of launches                     */
 } bse_report;
 
 /* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
@@ -103,6 +111,11 @@ int bse_ctx_create(bse_ctx** ctx, int device, void* arena, size_t arena_bytes, v
 
 /* Destroy a context (waits for its stream).  NULL is accepted. */
 int bse_ctx_destroy(bse_ctx* ctx);
+
+/* Turn per-launch timing of the dominant kernel on (enable != 0) or off for
+ * later calls on this context.  Adds two hipEventRecord per launch.
+ * Returns -1 for a NULL context. */
+int bse_ctx_set_timing(bse_ctx* ctx, int enable);
 
 /* Device workspace, in bytes, that bse_solve needs for size n (host-only
  * arithmetic, callable without a GPU).  0 for invalid arguments. */

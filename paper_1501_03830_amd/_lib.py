@@ -31,6 +31,9 @@ class BseReport(ctypes.Structure):
         ("n", ctypes.c_int),
         ("prec", ctypes.c_int),
         ("workspace_bytes", ctypes.c_size_t),
+        ("symv_ms", ctypes.c_double),
+        ("symv_bytes", ctypes.c_double),
+        ("symv_launches", ctypes.c_longlong),
     ]
 
     def as_dict(self):
@@ -40,6 +43,9 @@ class BseReport(ctypes.Structure):
             "n": self.n,
             "prec": self.prec,
             "workspace_bytes": self.workspace_bytes,
+            "symv_ms": self.symv_ms,
+            "symv_bytes": self.symv_bytes,
+            "symv_launches": self.symv_launches,
         }
 
 
@@ -53,6 +59,7 @@ SIGNATURES = [
     ("bse_last_error", ctypes.c_char_p, []),
     ("bse_ctx_create", _I, [ctypes.POINTER(_P), _I, _P, ctypes.c_size_t, _P]),
     ("bse_ctx_destroy", _I, [_P]),
+    ("bse_ctx_set_timing", _I, [_P, _I]),
     ("bse_footprint_bytes", ctypes.c_size_t, [_I, _I, _U]),
     ("bse_solve", _I, [_P, _I, _P, _I, _P, _I, _I, _U, _P, _P, _I, _P, _P, _P, ctypes.POINTER(BseReport)]),
     ("bse_build_M", _I, [_P, _I, _P, _I, _P, _I, _P, _I]),

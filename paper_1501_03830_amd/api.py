@@ -51,6 +51,10 @@ class Context:
                                            _P(self.stream.cuda_stream)), "bse_ctx_create")
         self.h = h
 
+    def set_timing(self, enable: bool):
+        """Per-launch hipEvent timing of the dominant skew matvec kernel."""
+        _lib.check(self.lib.bse_ctx_set_timing(self.h, 1 if enable else 0), "bse_ctx_set_timing")
+
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
             self.lib.bse_ctx_destroy(self.h)
@@ -99,6 +103,23 @@ class Context:
             "w": w,
             "report": rep.as_dict() if rep is not None else None,
         }
+
+    def solve_raw(self, n: int, Ac: torch.Tensor, Bc: torch.Tensor, lam: torch.Tensor,
+                  Xbuf: torch.Tensor | None, drb: torch.Tensor | None = None, dlb: torch.Tensor | None = None,
+                  w: torch.Tensor | None = None, report: bool = False):
+        """bse_solve on buffers that are already column-major on the device
+        (as made by to_colmajor); nothing is copied.  Returns (info, report)."""
+        flags = 0
+        if Xbuf is not None:
+            flags |= _lib.BSE_WANT_VECTORS
+        if drb is not None:
+            flags |= _lib.BSE_WANT_WEIGHTS
+        rep = _lib.BseReport() if report else None
+        info = _lib.check(self.lib.bse_solve(
+            self.h, n, _ptr(Ac), n, _ptr(Bc), n, _lib.BSE_PREC_FP64, flags, _ptr(lam),
+            _ptr(Xbuf), 2 * n, _ptr(drb), _ptr(dlb), _ptr(w),
+            ctypes.byref(rep) if rep is not None else None), "bse_solve")
+        return info, (rep.as_dict() if rep is not None else None)
 
     # ----------------------------------------------------------------- stages
     def build_M(self, A: torch.Tensor, B: torch.Tensor) -> torch.Tensor:

@@ -17,7 +17,10 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 // that 64 x 64 tiles are aligned, with all tiles of the padded square
 // allocated (kernels read whole tiles and mask, they never read past ld x ld).
 inline long round_up(long x, long m) { return (x + m - 1) / m * m; }
-inline long square_ld(long N) { return round_up(N < 64 ? 64 : N, 64); }
+// Extra columns of padding (multiple of 64) added to ld; read once from the
+// environment variable BSE_LD_PAD (tuning knob, default 0).
+long ld_pad();
+inline long square_ld(long N) { return round_up(N < 64 ? 64 : N, 64) + ld_pad(); }
 
 // Record a HIP failure for bse_last_error() and turn it into BSE_EDEVICE.
 int set_hip_error(hipError_t e, const char* what, const char* file, int line);
@@ -48,6 +51,14 @@ __device__ inline void tri_index(long t, int& R, int& C) {
   while ((r + 1) * (r + 2) / 2 <= t) ++r;
   R = (int)r;
   C = (int)(t - r * (r + 1) / 2);
+}
+
+// A value known to be equal in every lane, moved to scalar registers.
+__device__ inline double uniform_double(double x) {
+  const unsigned long long u = __double_as_longlong(x);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(u & 0xffffffffu));
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+  return __longlong_as_double(((unsigned long long)hi << 32) | lo);
 }
 
 // Sum over the 64 lanes of a wavefront; every lane gets the total.

@@ -35,7 +35,8 @@ int zero_upper(hipStream_t s, int N, double* A, long lda);
 struct SktrdWork {
   double* Y1;        // ld x 2*nb  (v_l, p_l interleaved)
   double* Y2;        // ld x 2*nb  (p_l, -v_l interleaved)
-  double* Ypart;     // symv partial sums
+  double* Yrow;      // symv partial row sums, one per 64 x 64 tile
+  double* Ycol;      // symv partial column sums, one per strip chunk
   double* dotpart;   // per-block partial dot products
   double* normpart;  // per-block partial squared norms
   void* ctrl;        // device control block
@@ -43,7 +44,15 @@ struct SktrdWork {
 };
 size_t sktrd_work_bytes(long N, long ld, int nb);
 int sktrd_bind_work(void* base, long N, long ld, int nb, SktrdWork* w);
-int sktrd_f64(hipStream_t s, int N, double* W, long ldw, double* alpha, double* tau, const SktrdWork& w);
+// Optional per-launch timing of the skew matvec (event pairs from a pool).
+struct KernelTimer {
+  hipEvent_t* ev = nullptr;
+  int cap = 0;    // number of events in the pool
+  int used = 0;   // events recorded so far (pairs)
+  double bytes = 0.0;
+};
+int sktrd_f64(hipStream_t s, int N, double* W, long ldw, double* alpha, double* tau, const SktrdWork& w,
+              KernelTimer* timer = nullptr);
 
 // ---------------------------------------------------------------- stein.hip
 // positive eigenvalues of tridiag(alpha, 0, alpha) by bisection

@@ -15,12 +15,11 @@
 //
 // Per column two kernels run:
 //   sk_symv   the HBM-bound product S v over the strictly-lower triangle of
-//             the trailing matrix.  One 64 x 64 tile per workgroup, each
-//             element read once and used twice (row sum for y, column sum for
-//             -S^T v).  Partial sums go to a buffer indexed so that every
-//             output block has exactly nblk+1 partial slots, summed in a fixed
-//             order (deterministic).  Diagonal tiles also store v and the
-//             partial dot products V^T v, P^T v.
+//             the trailing matrix, each element read once and used twice
+//             (row sum for S v, column sum for -S^T v).  Workgroups stream
+//             64-column strips; partial sums go to fixed slots and are summed
+//             in a fixed order (deterministic).  Extra workgroups store v and
+//             the partial dot products V^T v, P^T v.
 //   sk_update reduces the partials into p, applies the panel corrections,
 //             brings the next column up to date, and the last workgroup to
 //             finish computes the next reflector (dlarfg convention).
@@ -79,130 +78,192 @@ __global__ __launch_bounds__(256) void sk_start(const double* __restrict__ W, lo
   }
 }
 
-__global__ __launch_bounds__(256) void sk_symv(const double* __restrict__ W, long ld, int N, int j,
-                                               int i, int nblk, int R0, Ctrl* __restrict__ ctrl,
-                                               double* __restrict__ Y1, double* __restrict__ Y2,
-                                               long ldy, double* __restrict__ Ypart,
-                                               double* __restrict__ dotpart) {
-  __shared__ double vr[TS], vc[TS];
-  __shared__ double red[2][16][TS + 1];
-  __shared__ int last_flag;
-  int Rl, Cl;
-  tri_index(blockIdx.x, Rl, Cl);
-  const int R = R0 + Rl, C = R0 + Cl;
-  const int s = j + 1;
-  const int tid = threadIdx.x;
-  const double scale = ctrl->scale;
-  if (tid < 2 * TS) {
-    const int which = tid >> 6;
-    const long r = (long)(which ? C : R) * TS + (tid & 63);
-    double v = 0.0;
-    if (r == s) v = 1.0;
-    else if (r > s && r < N) v = scale * W[r + (long)j * ld];
-    if (which) vc[tid & 63] = v;
-    else vr[tid & 63] = v;
-  }
-  __syncthreads();
-
-  const int tx = tid & 15, ty = tid >> 4;
-  const long rb = (long)R * TS + 4 * tx;
-  const long cb = (long)C * TS + 4 * ty;
-  double yr[4] = {0.0, 0.0, 0.0, 0.0}, yc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const long col = cb + c;
-    const double* p = W + rb + col * ld;
-    const double2 lo = *reinterpret_cast<const double2*>(p);
-    const double2 hi = *reinterpret_cast<const double2*>(p + 2);
-    const double a4[4] = {lo.x, lo.y, hi.x, hi.y};
-    const double vcc = vc[4 * ty + c];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const long row = rb + q;
-      const bool valid = (row > col) && (col >= s) && (row < N);
-      const double a = valid ? a4[q] : 0.0;
-      yr[q] += a * vcc;
-      yc[c] += a * vr[4 * tx + q];
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) red[0][ty][4 * tx + q] = yr[q];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) red[1][tx][4 * ty + c] = yc[c];
-  __syncthreads();
-  if (tid < TS) {
-    double acc = 0.0;
-    for (int k = 0; k < 16; ++k) acc += red[0][k][tid];
-    Ypart[((long)Rl * (nblk + 1) + Cl) * TS + tid] = acc;
-  } else if (tid < 2 * TS) {
-    const int t = tid - TS;
-    double acc = 0.0;
-    for (int k = 0; k < 16; ++k) acc += red[1][k][t];
-    Ypart[((long)Cl * (nblk + 1) + Rl + 1) * TS + t] = -acc;
-  }
-
-  if (Rl != Cl) return;  // uniform per workgroup
-  // diagonal tile: store v_i and the partial dot products of the panel
-  if (tid < TS) {
-    const long r = (long)R * TS + tid;
-    if (r >= s && r < N) {
-      Y1[r + (long)(2 * i) * ldy] = vr[tid];
-      Y2[r + (long)(2 * i + 1) * ldy] = -vr[tid];
-    }
-  }
-  if (i == 0) return;
-  if (tid < 2 * i) {
-    const double* col = Y1 + (long)tid * ldy;
-    double acc = 0.0;
-    for (int q = 0; q < TS; ++q) {
-      const long r = (long)R * TS + q;
-      if (r >= s && r < N) acc += col[r] * vr[q];
-    }
-    dotpart[(long)Rl * (2 * NBMAX) + tid] = acc;
-  }
-  if (arrive_last(&ctrl->cnt_diag, (unsigned)nblk, &last_flag)) {
-    if (tid < 2 * i) {
-      double acc = 0.0;
-      for (int b = 0; b < nblk; ++b) acc += dotpart[(long)b * (2 * NBMAX) + tid];
-      ctrl->c[tid] = acc;
-    }
-  }
+__device__ inline double vval(const double* __restrict__ W, long ld, int j, int s, int N, double scale, long r) {
+  if (r == s) return 1.0;
+  if (r > s && r < N) return scale * W[r + (long)j * ld];
+  return 0.0;
 }
 
+// y = S v over the strictly lower triangle of the trailing matrix.
+//
+// blockIdx.y = k + 1 >= 1: workgroup (Cl, k) streams the 64-column strip Cl over
+//   row tiles Cl + k*T .. Cl + k*T + T - 1.  Lane = row inside a tile, wave w
+//   owns columns 16w..16w+15 of the strip, so every load instruction reads
+//   64 consecutive doubles of one column.  Row sums (S v) of each tile go to
+//   Yrow[rl][Cl]; column sums (-S^T v) accumulate in registers over the tiles
+//   and are reduced across the wave once, into Ycol[Cl][k].
+// blockIdx.y == 0 (dispatched first): workgroup b stores v_i for row block b and the panel
+//   dot products V^T v, P^T v over its rows; the last of these workgroups
+//   reduces the dot products into ctrl->c.
+__global__ __launch_bounds__(256) void sk_symv(const double* __restrict__ W, long ld, int N, int j,
+                                               int i, int nblk, int R0, int T, int nchunk,
+                                               Ctrl* __restrict__ ctrl, double* __restrict__ Y1,
+                                               double* __restrict__ Y2, long ldy, double* __restrict__ Yrow,
+                                               double* __restrict__ Ycol, double* __restrict__ dotpart,
+                                               int dstride) {
+  __shared__ double vcs[TS];
+  __shared__ double vrs[16 * TS];   // T <= 16 row tiles per workgroup
+  __shared__ double red[2][4][TS];
+  __shared__ int last_flag;
+  const int s = j + 1;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double scale = ctrl->scale;
+
+  if (blockIdx.y == 0) {
+    const int b = blockIdx.x;
+    const long r = (long)(R0 + b) * TS + lane;
+    const double v = vval(W, ld, j, s, N, scale, r);
+    const bool inrange = r >= s && r < N;
+    if (wv == 0 && inrange) {
+      Y1[r + (long)(2 * i) * ldy] = v;
+      Y2[r + (long)(2 * i + 1) * ldy] = -v;
+    }
+    if (i == 0) return;  // uniform
+    double prod[2 * NBMAX / 4];
+#pragma unroll
+    for (int q = 0; q < 2 * NBMAX / 4; ++q) {   // issue every load first
+      const int l = wv + 4 * q;
+      prod[q] = (l < 2 * i && inrange) ? Y1[r + (long)l * ldy] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 2 * NBMAX / 4; ++q) {
+      const int l = wv + 4 * q;
+      if (l < 2 * i) {
+        const double sum = wave_sum(prod[q] * v);
+        if (lane == 0) dotpart[(long)l * dstride + b] = sum;
+      }
+    }
+    if (arrive_last(&ctrl->cnt_diag, (unsigned)nblk, &last_flag)) {
+      // wave w reduces columns l = w, w+4, ...; lanes stride over the blocks
+      for (int l = wv; l < 2 * i; l += 4) {
+        double acc = 0.0;
+        for (int bb = lane; bb < nblk; bb += 64) acc += dotpart[(long)l * dstride + bb];
+        acc = wave_sum(acc);
+        if (lane == 0) ctrl->c[l] = acc;
+      }
+    }
+    return;
+  }
+
+  const int Cl = blockIdx.x, k = blockIdx.y - 1;
+  const int rl0 = Cl + k * T;
+  if (rl0 >= nblk) return;  // uniform: empty corner of the launch grid
+  const int rl1 = min(nblk, rl0 + T);
+  const long C0 = (long)(R0 + Cl) * TS;
+  // wave-uniform values live in scalar registers: the 16 column base
+  // pointers and v at those columns (keeps VGPR use, and so occupancy, low)
+  const int wvu = __builtin_amdgcn_readfirstlane(wv);
+  const long col0 = C0 + 16 * wvu;
+  // v for the strip's columns and for every row of the chunk, staged once so
+  // that the tile loop issues nothing but the matrix loads
+  if (threadIdx.x < TS) vcs[threadIdx.x] = vval(W, ld, j, s, N, scale, C0 + threadIdx.x);
+  for (int q = threadIdx.x; q < (rl1 - rl0) * TS; q += 256)
+    vrs[q] = vval(W, ld, j, s, N, scale, (long)(R0 + rl0) * TS + q);
+  __syncthreads();
+  double vc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) vc[q] = uniform_double(vcs[16 * wvu + q]);
+  double cacc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) cacc[q] = 0.0;
+  const bool strip_inside = C0 >= s;
+  const double* colbase = W + col0 * ld;
+  for (int rl = rl0; rl < rl1; ++rl) {
+    const long rbase = (long)(R0 + rl) * TS;
+    const int row_off = (int)rbase + lane;   // < 2^31 / 8: 32-bit lane offset
+    double a[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) a[q] = (colbase + (long)q * ld)[row_off];
+    const double vr = vrs[(rl - rl0) * TS + lane];
+    const bool interior = (rl > Cl) && strip_inside && (rbase + TS <= N);
+    if (!interior) {
+      const long row = rbase + lane;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const long col = col0 + q;
+        if (!(row > col && col >= s && row < N)) a[q] = 0.0;
+      }
+    }
+    double racc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      racc += a[q] * vc[q];
+      cacc[q] += a[q] * vr;
+    }
+    const int bsel = (rl - rl0) & 1;
+    red[bsel][wv][lane] = racc;
+    __syncthreads();
+    if (wv == 0)
+      Yrow[((long)rl * nblk + Cl) * TS + lane] =
+          red[bsel][0][lane] + red[bsel][1][lane] + red[bsel][2][lane] + red[bsel][3][lane];
+  }
+  double mine = 0.0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const double t = wave_sum(cacc[q]);
+    if (lane == q) mine = t;
+  }
+  if (lane < 16) Ycol[((long)Cl * nchunk + k) * TS + 16 * wv + lane] = -mine;
+}
+
+// p_i = tau (S v + V c_P - P c_V) for the rows of block b, the in-place store
+// of v_i, the update of the next column and, in the last workgroup, its
+// reflector.  The panel sums over l are split over the four wavefronts.
 __global__ __launch_bounds__(256) void sk_update(double* __restrict__ W, long ld, int N, int j, int i,
-                                                 int nbp, int nblk, int R0, Ctrl* __restrict__ ctrl,
-                                                 double* __restrict__ Y1, double* __restrict__ Y2,
-                                                 long ldy, const double* __restrict__ Ypart,
-                                                 double* __restrict__ normpart,
-                                                 double* __restrict__ alpha, double* __restrict__ tau_arr) {
+                                                 int nbp, int nblk, int R0, int T, int nchunk,
+                                                 Ctrl* __restrict__ ctrl, double* __restrict__ Y1,
+                                                 double* __restrict__ Y2, long ldy,
+                                                 const double* __restrict__ Yrow,
+                                                 const double* __restrict__ Ycol,
+                                                 double* __restrict__ normpart, double* __restrict__ alpha,
+                                                 double* __restrict__ tau_arr) {
   __shared__ double cs[2 * NBMAX];
+  __shared__ double ys_row[2 * NBMAX];   // Y1 row s (v_l[s], p_l[s])
   __shared__ double red[4][TS];
+  __shared__ double red2[4][TS];
   __shared__ double pr[TS];
   __shared__ double red4[4];
   __shared__ double sval_s;
   __shared__ int last_flag;
   const int b = blockIdx.x;
-  const int R = R0 + b;
   const int s = j + 1;
   const int tid = threadIdx.x;
-  const double tau = ctrl->tau;
-  if (tid < 2 * i) cs[tid] = ctrl->c[tid];
   const int t = tid & 63, part = tid >> 6;
+  const double tau = ctrl->tau;
+  if (tid < 2 * i) {
+    cs[tid] = ctrl->c[tid];
+    ys_row[tid] = Y1[s + (long)tid * ldy];
+  }
+  const long r = (long)(R0 + b) * TS + t;
+  const bool inrange = r >= s && r < N;
   {
     double acc = 0.0;
-    const double* base = Ypart + (long)b * (nblk + 1) * TS + t;
-    for (int x = part; x <= nblk; x += 4) acc += base[(long)x * TS];
+    const double* yr = Yrow + (long)b * nblk * TS + t;
+    for (int c = part; c <= b; c += 4) acc += yr[(long)c * TS];
+    const int nch = (nblk - b + T - 1) / T;
+    const double* yc = Ycol + (long)b * nchunk * TS + t;
+    for (int c = part; c < nch; c += 4) acc += yc[(long)c * TS];
     red[part][t] = acc;
   }
   __syncthreads();
-  const long r = (long)R * TS + t;
+  {
+    double corr = 0.0;
+    if (inrange) {
+#pragma unroll
+      for (int q = 0; q < NBMAX / 4; ++q) {
+        const int l = part + 4 * q;
+        if (l < i)
+          corr += Y1[r + (long)(2 * l) * ldy] * cs[2 * l + 1] - Y1[r + (long)(2 * l + 1) * ldy] * cs[2 * l];
+      }
+    }
+    red2[part][t] = corr;
+  }
+  __syncthreads();
   if (part == 0) {
     double p = 0.0;
-    if (r >= s && r < N) {
+    if (inrange) {
       const double y = red[0][t] + red[1][t] + red[2][t] + red[3][t];
-      double corr = 0.0;
-      for (int l = 0; l < i; ++l)
-        corr += Y1[r + (long)(2 * l) * ldy] * cs[2 * l + 1] - Y1[r + (long)(2 * l + 1) * ldy] * cs[2 * l];
+      const double corr = red2[0][t] + red2[1][t] + red2[2][t] + red2[3][t];
       p = tau * (y + corr);
       Y1[r + (long)(2 * i + 1) * ldy] = p;
       Y2[r + (long)(2 * i) * ldy] = p;
@@ -212,29 +273,39 @@ __global__ __launch_bounds__(256) void sk_update(double* __restrict__ W, long ld
   }
   const bool next_col = (i + 1 < nbp) && (s <= N - 2);
   if (!next_col) return;  // uniform
-  // p_i at row s, needed by every block for the update of column s
+  // p_i at row s (first row of block 0), needed by every block
+  if (part == 1) {
+    const long os = s - (long)R0 * TS;
+    const int nch0 = (nblk + T - 1) / T;
+    double acc = (t == 0) ? Yrow[os] : 0.0;
+    for (int c = t; c < nch0; c += 64) acc += Ycol[(long)c * TS + os];
+    acc = wave_sum(acc);
+    if (t == 0) red4[1] = acc;
+  } else if (part == 2) {
+    double acc = 0.0;
+    if (t < i) acc = ys_row[2 * t] * cs[2 * t + 1] - ys_row[2 * t + 1] * cs[2 * t];
+    acc = wave_sum(acc);
+    if (t == 0) red4[2] = acc;
+  }
+  __syncthreads();
+  if (tid == 0) sval_s = tau * (red4[1] + red4[2]);
   {
-    double ys = 0.0;
-    for (int x = tid; x <= nblk; x += 256) ys += Ypart[(long)x * TS + (s - (long)R0 * TS)];
-    ys = block_sum(ys, red4);
-    if (tid == 0) {
-      double corr = 0.0;
-      for (int l = 0; l < i; ++l)
-        corr += Y1[s + (long)(2 * l) * ldy] * cs[2 * l + 1] - Y1[s + (long)(2 * l + 1) * ldy] * cs[2 * l];
-      sval_s = tau * (ys + corr);
+    double upd = 0.0;
+    if (r >= s + 1 && r < N) {
+#pragma unroll
+      for (int q = 0; q < NBMAX / 4; ++q) {
+        const int l = part + 4 * q;
+        if (l < i)
+          upd += Y1[r + (long)(2 * l) * ldy] * ys_row[2 * l + 1] - Y1[r + (long)(2 * l + 1) * ldy] * ys_row[2 * l];
+      }
     }
+    red2[part][t] = upd;
   }
   __syncthreads();
   double nrm = 0.0;
   if (part == 0 && r >= s + 1 && r < N) {
-    const double sval = sval_s;
-    double upd = W[r + (long)s * ld];
-    for (int l = 0; l < i; ++l) {
-      const double vrl = Y1[r + (long)(2 * l) * ldy], prl = Y1[r + (long)(2 * l + 1) * ldy];
-      const double vsl = Y1[s + (long)(2 * l) * ldy], psl = Y1[s + (long)(2 * l + 1) * ldy];
-      upd += vrl * psl - prl * vsl;
-    }
-    upd += Y1[r + (long)(2 * i) * ldy] * sval - pr[t];
+    double upd = W[r + (long)s * ld] + red2[0][t] + red2[1][t] + red2[2][t] + red2[3][t];
+    upd += Y1[r + (long)(2 * i) * ldy] * sval_s - pr[t];
     W[r + (long)s * ld] = upd;
     if (r == s + 1) ctrl->x0 = upd;
     if (r >= s + 2) nrm = upd * upd;
@@ -242,9 +313,10 @@ __global__ __launch_bounds__(256) void sk_update(double* __restrict__ W, long ld
   nrm = block_sum(nrm, red4);
   if (tid == 0) normpart[b] = nrm;
   if (arrive_last(&ctrl->cnt_upd, (unsigned)nblk, &last_flag)) {
+    double ss = 0.0;
+    for (int kk = tid; kk < nblk; kk += 256) ss += normpart[kk];
+    ss = block_sum(ss, red4);
     if (tid == 0) {
-      double ss = 0.0;
-      for (int k = 0; k < nblk; ++k) ss += normpart[k];
       double beta, tn, sc;
       larfg(ctrl->x0, sqrt(ss), beta, tn, sc);
       ctrl->tau = tn;
@@ -269,7 +341,7 @@ size_t sktrd_work_bytes(long N, long ld, int nb) {
   const long nt = ld / TS;
   size_t bytes = 0;
   bytes += 2 * (size_t)ld * 2 * NBMAX * sizeof(double);            // Y1, Y2
-  bytes += (size_t)nt * (nt + 1) * TS * sizeof(double);           // Ypart
+  bytes += 2 * (size_t)nt * nt * TS * sizeof(double);             // Yrow, Ycol
   bytes += (size_t)nt * 2 * NBMAX * sizeof(double);               // dotpart
   bytes += (size_t)nt * sizeof(double);                           // normpart
   bytes += 4096;                                                  // ctrl
@@ -289,7 +361,8 @@ int sktrd_bind_work(void* base, long N, long ld, int nb, SktrdWork* w) {
   };
   w->Y1 = reinterpret_cast<double*>(take((size_t)ld * 2 * NBMAX * sizeof(double)));
   w->Y2 = reinterpret_cast<double*>(take((size_t)ld * 2 * NBMAX * sizeof(double)));
-  w->Ypart = reinterpret_cast<double*>(take((size_t)nt * (nt + 1) * TS * sizeof(double)));
+  w->Yrow = reinterpret_cast<double*>(take((size_t)nt * nt * TS * sizeof(double)));
+  w->Ycol = reinterpret_cast<double*>(take((size_t)nt * nt * TS * sizeof(double)));
   w->dotpart = reinterpret_cast<double*>(take((size_t)nt * 2 * NBMAX * sizeof(double)));
   w->normpart = reinterpret_cast<double*>(take((size_t)nt * sizeof(double)));
   w->ctrl = take(sizeof(Ctrl));
@@ -297,7 +370,8 @@ int sktrd_bind_work(void* base, long N, long ld, int nb, SktrdWork* w) {
   return 0;
 }
 
-int sktrd_f64(hipStream_t s, int N, double* W, long ld, double* alpha, double* tau, const SktrdWork& w) {
+int sktrd_f64(hipStream_t s, int N, double* W, long ld, double* alpha, double* tau, const SktrdWork& w,
+              KernelTimer* timer) {
   if (N < 2) return 0;
   Ctrl* ctrl = static_cast<Ctrl*>(w.ctrl);
   const long ldy = ld;
@@ -314,11 +388,24 @@ int sktrd_f64(hipStream_t s, int N, double* W, long ld, double* alpha, double* t
       const int sidx = j + 1;
       const int R0 = sidx / TS;
       const int nblk = (N - 1) / TS - R0 + 1;
-      const unsigned ntiles = (unsigned)((long)nblk * (nblk + 1) / 2);
-      sk_symv<<<ntiles, 256, 0, s>>>(W, ld, N, j, i, nblk, R0, ctrl, w.Y1, w.Y2, ldy, w.Ypart, w.dotpart);
+      const long ntiles = (long)nblk * (nblk + 1) / 2;
+      // tiles per workgroup: keep about 4096 workgroups in flight
+      int T = (int)(ntiles / 4096);
+      T = T < 1 ? 1 : (T > 16 ? 16 : T);
+      const int nchunk = (nblk + T - 1) / T;
+      const bool timed = timer && timer->used + 2 <= timer->cap;
+      if (timed) BSE_HIP(hipEventRecord(timer->ev[timer->used], s));
+      sk_symv<<<dim3((unsigned)nblk, (unsigned)(nchunk + 1)), 256, 0, s>>>(
+          W, ld, N, j, i, nblk, R0, T, nchunk, ctrl, w.Y1, w.Y2, ldy, w.Yrow, w.Ycol, w.dotpart, (int)(ld / TS));
       BSE_LAUNCHED();
-      sk_update<<<(unsigned)nblk, 256, 0, s>>>(W, ld, N, j, i, nbp, nblk, R0, ctrl, w.Y1, w.Y2, ldy,
-                                               w.Ypart, w.normpart, alpha, tau);
+      if (timed) {
+        BSE_HIP(hipEventRecord(timer->ev[timer->used + 1], s));
+        timer->used += 2;
+        const double m = (double)(N - sidx);   // trailing order
+        timer->bytes += 8.0 * m * (m - 1.0) * 0.5;
+      }
+      sk_update<<<(unsigned)nblk, 256, 0, s>>>(W, ld, N, j, i, nbp, nblk, R0, T, nchunk, ctrl, w.Y1, w.Y2,
+                                               ldy, w.Yrow, w.Ycol, w.normpart, alpha, tau);
       BSE_LAUNCHED();
     }
     const int e = k0 + nbp;

@@ -1,9 +1,11 @@
 // Solver driver and C ABI: stage sequencing, workspace layout, argument
 // checking and timing for the chain of Algorithm 1 / Algorithm 3.
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "common.h"
 #include "kernels.h"
@@ -17,12 +19,24 @@ struct bse_ctx {
   size_t own_bytes = 0;
   hipEvent_t ev[BSE_NUM_STAGES + 1] = {};
   bool events = false;
+  bool timing = false;               // per-launch timing of the skew matvec
+  std::vector<hipEvent_t> kev;       // event pool for it
 };
 
 namespace bse {
 
 namespace {
 thread_local std::string g_last_error;
+}
+
+long ld_pad() {
+  static long pad = [] {
+    const char* e = getenv("BSE_LD_PAD");
+    long v = e ? atol(e) : 0;
+    if (v < 0) v = 0;
+    return round_up(v, 64);
+  }();
+  return pad;
 }
 
 int set_hip_error(hipError_t e, const char* what, const char* file, int line) {
@@ -166,7 +180,18 @@ static int solve_fp64(bse_ctx* ctx, int n, const double* A, long lda, const doub
   if (info != 0) return info;
   BSE_TRY(form_W(s, (int)N, b.L, p.ld, b.W, p.ld, false));
   BSE_TRY(mark(ctx, timed, 3));
-  BSE_TRY(sktrd_f64(s, (int)N, b.W, p.ld, b.alpha, b.tau, b.sk));
+  KernelTimer ktimer;
+  if (ctx->timing) {
+    const size_t need = 2 * (size_t)(N > 2 ? N - 2 : 0);
+    while (ctx->kev.size() < need) {
+      hipEvent_t e;
+      BSE_HIP(hipEventCreate(&e));
+      ctx->kev.push_back(e);
+    }
+    ktimer.ev = ctx->kev.data();
+    ktimer.cap = (int)ctx->kev.size();
+  }
+  BSE_TRY(sktrd_f64(s, (int)N, b.W, p.ld, b.alpha, b.tau, b.sk, ctx->timing ? &ktimer : nullptr));
   BSE_TRY(mark(ctx, timed, 4));
   BSE_TRY(tridiag_bisect(s, (int)N, b.alpha, b.e2, b.scal, lambda));
   BSE_TRY(mark(ctx, timed, 5));
@@ -207,6 +232,16 @@ static int solve_fp64(bse_ctx* ctx, int n, const double* A, long lda, const doub
     rep->n = n;
     rep->prec = BSE_PREC_FP64;
     rep->workspace_bytes = p.total;
+    if (ctx->timing) {
+      double tot = 0.0;
+      for (int i = 0; i + 1 < ktimer.used; i += 2) {
+        BSE_HIP(hipEventElapsedTime(&ms, ktimer.ev[i], ktimer.ev[i + 1]));
+        tot += ms;
+      }
+      rep->symv_ms = tot;
+      rep->symv_bytes = ktimer.bytes;
+      rep->symv_launches = ktimer.used / 2;
+    }
   }
   return 0;
 }
@@ -252,7 +287,14 @@ int bse_ctx_destroy(bse_ctx* ctx) {
   if (ctx->own) (void)hipFree(ctx->own);
   if (ctx->events)
     for (int i = 0; i <= BSE_NUM_STAGES; ++i) (void)hipEventDestroy(ctx->ev[i]);
+  for (hipEvent_t e : ctx->kev) (void)hipEventDestroy(e);
   delete ctx;
+  return 0;
+}
+
+int bse_ctx_set_timing(bse_ctx* ctx, int enable) {
+  if (!ctx) return set_error(-1, "ctx is NULL");
+  ctx->timing = enable != 0;
   return 0;
 }
 
