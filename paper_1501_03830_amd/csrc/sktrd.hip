@@ -32,6 +32,8 @@ namespace {
 
 constexpr int TS = 64;       // symv tile
 constexpr int NBMAX = 64;    // panel width bound
+constexpr int DUTY_BLK = 16; // row blocks per workgroup of the panel dot products
+constexpr int TMAX = 8;      // row tiles per strip workgroup (upper bound)
 
 struct Ctrl {
   double tau;
@@ -90,94 +92,112 @@ __device__ inline double vval(const double* __restrict__ W, long ld, int j, int 
 //   row tiles Cl + k*T .. Cl + k*T + T - 1.  Lane = row inside a tile, wave w
 //   owns columns 16w..16w+15 of the strip, so every load instruction reads
 //   64 consecutive doubles of one column.  Row sums (S v) of each tile go to
-//   Yrow[rl][Cl]; column sums (-S^T v) accumulate in registers over the tiles
-//   and are reduced across the wave once, into Ycol[Cl][k].
-// blockIdx.y == 0 (dispatched first): workgroup b stores v_i for row block b and the panel
-//   dot products V^T v, P^T v over its rows; the last of these workgroups
-//   reduces the dot products into ctrl->c.
+//   Yrow[Cl][rl] (written once per workgroup, contiguously); column sums
+//   (-S^T v) accumulate in registers over the tiles and are reduced across
+//   the wave once, into Ycol[Cl][k].
+// blockIdx.y == 0 (dispatched first): workgroups (d, g) store v_i for row
+//   blocks d*16 .. d*16+15 and their share of the panel dot products V^T v,
+//   P^T v (summed by the update kernel).
 __global__ __launch_bounds__(256) void sk_symv(const double* __restrict__ W, long ld, int N, int j,
                                                int i, int nblk, int R0, int T, int nchunk,
                                                Ctrl* __restrict__ ctrl, double* __restrict__ Y1,
                                                double* __restrict__ Y2, long ldy, double* __restrict__ Yrow,
                                                double* __restrict__ Ycol, double* __restrict__ dotpart,
                                                int dstride) {
-  __shared__ double vcs[TS];
-  __shared__ double vrs[16 * TS];   // T <= 16 row tiles per workgroup
-  __shared__ double red[2][4][TS];
-  __shared__ int last_flag;
+  __shared__ double rsum[TMAX][4][TS];   // per-wave row sums of every tile
   const int s = j + 1;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const double scale = ctrl->scale;
 
   if (blockIdx.y == 0) {
-    const int b = blockIdx.x;
-    const long r = (long)(R0 + b) * TS + lane;
-    const double v = vval(W, ld, j, s, N, scale, r);
-    const bool inrange = r >= s && r < N;
-    if (wv == 0 && inrange) {
-      Y1[r + (long)(2 * i) * ldy] = v;
-      Y2[r + (long)(2 * i + 1) * ldy] = -v;
+    // duty workgroup (d, g) covers row blocks d*DUTY_BLK .. +DUTY_BLK-1 and the
+    // panel columns 32g .. 32g+31: group 0 stores v_i, every group writes its
+    // partial dot products of those panel columns with v_i; the update kernel
+    // adds the (at most 16) partials of each column.
+    const int d = blockIdx.x >> 2, g = blockIdx.x & 3;
+    const int nd = (nblk + DUTY_BLK - 1) / DUTY_BLK;
+    if (d >= nd) return;              // uniform
+    if (g > 0 && 32 * g >= 2 * i) return;
+    const int b0 = d * DUTY_BLK, b1 = min(nblk, b0 + DUTY_BLK);
+    double acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    for (int b = b0; b < b1; ++b) {
+      const long r = (long)(R0 + b) * TS + lane;
+      const double v = vval(W, ld, j, s, N, scale, r);
+      const bool inrange = r >= s && r < N;
+      if (g == 0 && wv == 0 && inrange) {
+        Y1[r + (long)(2 * i) * ldy] = v;
+        Y2[r + (long)(2 * i + 1) * ldy] = -v;
+      }
+      double y[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int l = 32 * g + wv + 4 * q;
+        y[q] = (l < 2 * i && inrange) ? Y1[r + (long)l * ldy] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] += y[q] * v;
     }
     if (i == 0) return;  // uniform
-    double prod[2 * NBMAX / 4];
+    // butterfly over the 64 lanes, all columns interleaved
 #pragma unroll
-    for (int q = 0; q < 2 * NBMAX / 4; ++q) {   // issue every load first
-      const int l = wv + 4 * q;
-      prod[q] = (l < 2 * i && inrange) ? Y1[r + (long)l * ldy] : 0.0;
-    }
+    for (int off = 32; off >= 1; off >>= 1)
 #pragma unroll
-    for (int q = 0; q < 2 * NBMAX / 4; ++q) {
-      const int l = wv + 4 * q;
-      if (l < 2 * i) {
-        const double sum = wave_sum(prod[q] * v);
-        if (lane == 0) dotpart[(long)l * dstride + b] = sum;
-      }
-    }
-    if (arrive_last(&ctrl->cnt_diag, (unsigned)nblk, &last_flag)) {
-      // wave w reduces columns l = w, w+4, ...; lanes stride over the blocks
-      for (int l = wv; l < 2 * i; l += 4) {
-        double acc = 0.0;
-        for (int bb = lane; bb < nblk; bb += 64) acc += dotpart[(long)l * dstride + bb];
-        acc = wave_sum(acc);
-        if (lane == 0) ctrl->c[l] = acc;
-      }
+      for (int q = 0; q < 8; ++q) acc[q] += __shfl_xor(acc[q], off, 64);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int l = 32 * g + wv + 4 * q;
+      if (l < 2 * i && lane == 0) dotpart[(long)l * dstride + d] = acc[q];
     }
     return;
   }
 
   const int Cl = blockIdx.x, k = blockIdx.y - 1;
   const int rl0 = Cl + k * T;
-  if (rl0 >= nblk) return;  // uniform: empty corner of the launch grid
+  if (Cl >= nblk || rl0 >= nblk) return;  // uniform: empty corner of the launch grid
   const int rl1 = min(nblk, rl0 + T);
   const long C0 = (long)(R0 + Cl) * TS;
-  // wave-uniform values live in scalar registers: the 16 column base
-  // pointers and v at those columns (keeps VGPR use, and so occupancy, low)
+  // wave-uniform values live in scalar registers: the column base pointer and
+  // v at the wave's 16 columns (keeps VGPR use, and so occupancy, low)
   const int wvu = __builtin_amdgcn_readfirstlane(wv);
   const long col0 = C0 + 16 * wvu;
-  // v for the strip's columns and for every row of the chunk, staged once so
-  // that the tile loop issues nothing but the matrix loads
-  if (threadIdx.x < TS) vcs[threadIdx.x] = vval(W, ld, j, s, N, scale, C0 + threadIdx.x);
-  for (int q = threadIdx.x; q < (rl1 - rl0) * TS; q += 256)
-    vrs[q] = vval(W, ld, j, s, N, scale, (long)(R0 + rl0) * TS + q);
-  __syncthreads();
+  const double* vcol = W + (long)j * ld;   // column j holds x; v = scale * x below row s
   double vc[16];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) vc[q] = uniform_double(vcs[16 * wvu + q]);
+  for (int q = 0; q < 16; ++q) {
+    const long c = col0 + q;
+    const double x = vcol[c < N ? c : 0];
+    vc[q] = (c == s) ? 1.0 : ((c > s && c < N) ? scale * x : 0.0);
+  }
   double cacc[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) cacc[q] = 0.0;
   const bool strip_inside = C0 >= s;
   const double* colbase = W + col0 * ld;
-  for (int rl = rl0; rl < rl1; ++rl) {
-    const long rbase = (long)(R0 + rl) * TS;
-    const int row_off = (int)rbase + lane;   // < 2^31 / 8: 32-bit lane offset
-    double a[16];
+  // no barrier, no global store and no dependent load inside this loop: v at
+  // the tile's rows is fetched with the tile itself, and the next tile's
+  // loads are issued before the current tile is used (software pipeline)
+  double a[16], xr;
+  {
+    const int row_off = (int)((long)(R0 + rl0) * TS) + lane;
 #pragma unroll
     for (int q = 0; q < 16; ++q) a[q] = (colbase + (long)q * ld)[row_off];
-    const double vr = vrs[(rl - rl0) * TS + lane];
+    xr = vcol[row_off];
+  }
+  for (int rl = rl0; rl < rl1; ++rl) {
+    const long rbase = (long)(R0 + rl) * TS;
+    const long row = rbase + lane;
+    double an[16], xn = 0.0;
+    if (rl + 1 < rl1) {
+      const int noff = (int)(rbase + TS) + lane;   // 32-bit lane offset (rows < 2^28)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) an[q] = (colbase + (long)q * ld)[noff];
+      xn = vcol[noff];
+    }
+    const double vr = (row == s) ? 1.0 : ((row > s && row < N) ? scale * xr : 0.0);
     const bool interior = (rl > Cl) && strip_inside && (rbase + TS <= N);
     if (!interior) {
-      const long row = rbase + lane;
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const long col = col0 + q;
@@ -190,20 +210,28 @@ __global__ __launch_bounds__(256) void sk_symv(const double* __restrict__ W, lon
       racc += a[q] * vc[q];
       cacc[q] += a[q] * vr;
     }
-    const int bsel = (rl - rl0) & 1;
-    red[bsel][wv][lane] = racc;
-    __syncthreads();
-    if (wv == 0)
-      Yrow[((long)rl * nblk + Cl) * TS + lane] =
-          red[bsel][0][lane] + red[bsel][1][lane] + red[bsel][2][lane] + red[bsel][3][lane];
+    rsum[rl - rl0][wv][lane] = racc;
+    if (rl + 1 < rl1) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) a[q] = an[q];
+      xr = xn;
+    }
   }
+  // column sums: butterfly over the 64 lanes, the 16 columns interleaved
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+    for (int q = 0; q < 16; ++q) cacc[q] += __shfl_xor(cacc[q], off, 64);
   double mine = 0.0;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const double t = wave_sum(cacc[q]);
-    if (lane == q) mine = t;
-  }
+  for (int q = 0; q < 16; ++q)
+    if (lane == q) mine = cacc[q];
   if (lane < 16) Ycol[((long)Cl * nchunk + k) * TS + 16 * wv + lane] = -mine;
+  __syncthreads();
+  // the chunk's row sums are contiguous in Yrow ([strip][row block][64])
+  for (int t = wv; t < rl1 - rl0; t += 4)
+    Yrow[((long)Cl * nblk + rl0 + t) * TS + lane] =
+        rsum[t][0][lane] + rsum[t][1][lane] + rsum[t][2][lane] + rsum[t][3][lane];
 }
 
 // p_i = tau (S v + V c_P - P c_V) for the rows of block b, the in-place store
@@ -216,7 +244,8 @@ __global__ __launch_bounds__(256) void sk_update(double* __restrict__ W, long ld
                                                  const double* __restrict__ Yrow,
                                                  const double* __restrict__ Ycol,
                                                  double* __restrict__ normpart, double* __restrict__ alpha,
-                                                 double* __restrict__ tau_arr) {
+                                                 double* __restrict__ tau_arr,
+                                                 const double* __restrict__ dotpart, int dstride) {
   __shared__ double cs[2 * NBMAX];
   __shared__ double ys_row[2 * NBMAX];   // Y1 row s (v_l[s], p_l[s])
   __shared__ double red[4][TS];
@@ -231,15 +260,19 @@ __global__ __launch_bounds__(256) void sk_update(double* __restrict__ W, long ld
   const int t = tid & 63, part = tid >> 6;
   const double tau = ctrl->tau;
   if (tid < 2 * i) {
-    cs[tid] = ctrl->c[tid];
+    // c[l] = sum of the symv duty workgroups' partial dot products
+    const int nd = (nblk + DUTY_BLK - 1) / DUTY_BLK;
+    double c = 0.0;
+    for (int dd = 0; dd < nd; ++dd) c += dotpart[(long)tid * dstride + dd];
+    cs[tid] = c;
     ys_row[tid] = Y1[s + (long)tid * ldy];
   }
   const long r = (long)(R0 + b) * TS + t;
   const bool inrange = r >= s && r < N;
   {
     double acc = 0.0;
-    const double* yr = Yrow + (long)b * nblk * TS + t;
-    for (int c = part; c <= b; c += 4) acc += yr[(long)c * TS];
+    const double* yr = Yrow + (long)b * TS + t;      // Yrow[c][b][t]
+    for (int c = part; c <= b; c += 4) acc += yr[(long)c * nblk * TS];
     const int nch = (nblk - b + T - 1) / T;
     const double* yc = Ycol + (long)b * nchunk * TS + t;
     for (int c = part; c < nch; c += 4) acc += yc[(long)c * TS];
@@ -391,11 +424,13 @@ int sktrd_f64(hipStream_t s, int N, double* W, long ld, double* alpha, double* t
       const long ntiles = (long)nblk * (nblk + 1) / 2;
       // tiles per workgroup: keep about 4096 workgroups in flight
       int T = (int)(ntiles / 4096);
-      T = T < 1 ? 1 : (T > 16 ? 16 : T);
+      T = T < 1 ? 1 : (T > TMAX ? TMAX : T);
       const int nchunk = (nblk + T - 1) / T;
       const bool timed = timer && timer->used + 2 <= timer->cap;
       if (timed) BSE_HIP(hipEventRecord(timer->ev[timer->used], s));
-      sk_symv<<<dim3((unsigned)nblk, (unsigned)(nchunk + 1)), 256, 0, s>>>(
+      const int nduty = 4 * ((nblk + DUTY_BLK - 1) / DUTY_BLK);
+      const unsigned gx = (unsigned)(nblk > nduty ? nblk : nduty);
+      sk_symv<<<dim3(gx, (unsigned)(nchunk + 1)), 256, 0, s>>>(
           W, ld, N, j, i, nblk, R0, T, nchunk, ctrl, w.Y1, w.Y2, ldy, w.Yrow, w.Ycol, w.dotpart, (int)(ld / TS));
       BSE_LAUNCHED();
       if (timed) {
@@ -405,7 +440,8 @@ int sktrd_f64(hipStream_t s, int N, double* W, long ld, double* alpha, double* t
         timer->bytes += 8.0 * m * (m - 1.0) * 0.5;
       }
       sk_update<<<(unsigned)nblk, 256, 0, s>>>(W, ld, N, j, i, nbp, nblk, R0, T, nchunk, ctrl, w.Y1, w.Y2,
-                                               ldy, w.Yrow, w.Ycol, w.normpart, alpha, tau);
+                                               ldy, w.Yrow, w.Ycol, w.normpart, alpha, tau, w.dotpart,
+                                               (int)(ld / TS));
       BSE_LAUNCHED();
     }
     const int e = k0 + nbp;
