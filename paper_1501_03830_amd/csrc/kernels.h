@@ -7,6 +7,9 @@
 namespace bse {
 
 // ---------------------------------------------------------------- gemm.hip
+// Scratch buffer for split-K products issued from this host thread (set by
+// the driver before a solve; NULL disables splitting).
+void gemm_set_scratch(double* scratch, size_t bytes);
 int gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
              long lda, const double* B, long ldb, double beta, double* C, long ldc, int c_uplo,
              int a_tri, int b_tri);

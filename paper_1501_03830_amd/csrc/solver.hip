@@ -57,7 +57,8 @@ static int set_error(int code, const char* msg) {
 struct Plan {
   long N = 0, n = 0, ld = 0;
   size_t off_L = 0, off_W = 0, off_Z = 0, off_Vt = 0, off_inv = 0, off_small = 0, off_sk = 0,
-         off_bt = 0, off_linv = 0;
+         off_bt = 0, off_linv = 0, off_gscr = 0;
+  size_t gscr_bytes = 0;
   size_t total = 0;
   int nb = 64, nbq = 64;
 };
@@ -85,6 +86,8 @@ static Plan make_plan(long N) {
   p.off_sk = take(sktrd_work_bytes(N, p.ld, p.nb));
   p.off_bt = take(backtr_work_bytes(N, p.ld, p.nbq));
   p.off_linv = take(64 * 64 * sizeof(double));
+  p.gscr_bytes = (size_t)16 * 64 * p.ld * sizeof(double);   // split-K partials
+  p.off_gscr = take(p.gscr_bytes);
   p.total = cur;
   return p;
 }
@@ -112,6 +115,7 @@ static void bind(const Plan& p, char* base, Bufs* b) {
   b->cid = reinterpret_cast<int*>(sm + 4 * p.ld + p.n + 16);
   b->info = reinterpret_cast<int*>(sm + 4 * p.ld + 3 * p.n + 32);
   b->linv = reinterpret_cast<double*>(base + p.off_linv);
+  gemm_set_scratch(reinterpret_cast<double*>(base + p.off_gscr), p.gscr_bytes);
   sktrd_bind_work(base + p.off_sk, p.N, p.ld, p.nb, &b->sk);
   backtr_bind_work(base + p.off_bt, p.N, p.ld, p.nbq, &b->bt);
 }
