@@ -261,22 +261,45 @@ __global__ __launch_bounds__(256) void sk_update(double* __restrict__ W, long ld
   const double tau = ctrl->tau;
   if (tid < 2 * i) {
     // c[l] = sum of the symv duty workgroups' partial dot products
-    const int nd = (nblk + DUTY_BLK - 1) / DUTY_BLK;
+    const int nd = (nblk + DUTY_BLK - 1) / DUTY_BLK;   // 16 partials per 16384 rows
     double c = 0.0;
-    for (int dd = 0; dd < nd; ++dd) c += dotpart[(long)tid * dstride + dd];
+    for (int d0 = 0; d0 < nd; d0 += 16) {
+      double pc[16];
+#pragma unroll
+      for (int dd = 0; dd < 16; ++dd) pc[dd] = (d0 + dd < nd) ? dotpart[(long)tid * dstride + d0 + dd] : 0.0;
+#pragma unroll
+      for (int dd = 0; dd < 16; ++dd) c += pc[dd];
+    }
     cs[tid] = c;
     ys_row[tid] = Y1[s + (long)tid * ldy];
   }
   const long r = (long)(R0 + b) * TS + t;
   const bool inrange = r >= s && r < N;
   {
-    double acc = 0.0;
+    // partial sums of this row block: b+1 row parts (one per strip c <= b)
+    // and nch column parts (one per chunk of strip b); loads are issued in
+    // batches of 8 so that each thread has many in flight
+    double acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
     const double* yr = Yrow + (long)b * TS + t;      // Yrow[c][b][t]
-    for (int c = part; c <= b; c += 4) acc += yr[(long)c * nblk * TS];
+    for (int c0 = part; c0 <= b; c0 += 32) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int c = c0 + 4 * q;
+        if (c <= b) acc[q] += yr[(long)c * nblk * TS];
+      }
+    }
     const int nch = (nblk - b + T - 1) / T;
     const double* yc = Ycol + (long)b * nchunk * TS + t;
-    for (int c = part; c < nch; c += 4) acc += yc[(long)c * TS];
-    red[part][t] = acc;
+    for (int c0 = part; c0 < nch; c0 += 32) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int c = c0 + 4 * q;
+        if (c < nch) acc[q] += yc[(long)c * TS];
+      }
+    }
+    red[part][t] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   }
   __syncthreads();
   {
