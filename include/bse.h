@@ -145,6 +145,51 @@ int bse_solve(bse_ctx* ctx, int n, const void* A, int lda, const void* B, int ld
               unsigned flags, double* lambda, void* X, int ldx, const void* d_r, const void* d_l,
               void* w, bse_report* rep);
 
+/* Device workspace, in bytes, of one bse_solve_batched call over `count`
+ * problems of orders n[0..count) (host-only arithmetic, callable without a
+ * GPU).  0 for invalid arguments. */
+size_t bse_footprint_batched_bytes(int count, const int* n, int prec, unsigned flags);
+
+/*
+ * Many independent eigensolves in one call: the batched form of bse_solve
+ * (Algorithm 1 as organised by Algorithm 3 for each problem).  The problems
+ * may differ in n.  They go through the chain together: each step is one
+ * launch covering every problem that still has work at that step, so that
+ * many small problems fill the device instead of running one after another.
+ * Each problem's arithmetic, and so its result, is bit for bit the same as
+ * that of bse_solve on the problem alone.
+ *
+ * Every array argument is a HOST array of `count` entries; the pointers in
+ * them are device pointers with the meaning, layout and ownership of the
+ * corresponding bse_solve argument.
+ *   ctx        context (argument 1)
+ *   count      number of problems, >= 0; 0 is a no-op (2)
+ *   n, A, lda, B, ldb   per problem, as in bse_solve (3, 4, 5, 6, 7)
+ *   prec       BSE_PREC_FP64, shared (8)
+ *   flags      BSE_WANT_VECTORS | BSE_WANT_WEIGHTS, shared (9)
+ *   lambda     out: lambda[i] -> n[i] doubles, ascending (10)
+ *   X, ldx     out: X[i] -> complex 2n[i] x n[i], ldx[i] >= 2 n[i], laid out
+ *              and phased as in bse_solve; both arrays may be NULL without
+ *              BSE_WANT_VECTORS (11, 12)
+ *   d          in: d[i] -> complex 2n[i] dipole vector, used as d_r = d_l of
+ *              eq. absp; read with BSE_WANT_WEIGHTS, else may be NULL (13)
+ *   w          out: w[i] -> n[i] complex weights (14)
+ *   info       out, HOST int[count]: 0 on success; +k when the leading k x k
+ *              minor of problem i's M is not positive definite (eq. cond
+ *              fails; that problem's outputs are not written); BSE_EDEVICE
+ *              when its cluster reorthogonalisation failed (15)
+ *   rep        optional host report for the whole batch; rep->n is the
+ *              largest n (16)
+ * Returns 0 when the batch ran (per-problem status in info), -i for invalid
+ * argument i (bse_last_error() names the problem), BSE_ENOMEM when the
+ * arena is too small for bse_footprint_batched_bytes, BSE_EDEVICE on a HIP
+ * error.
+ */
+int bse_solve_batched(bse_ctx* ctx, int count, const int* n, const void* const* A, const int* lda,
+                      const void* const* B, const int* ldb, int prec, unsigned flags,
+                      double* const* lambda, void* const* X, const int* ldx, const void* const* d,
+                      void* const* w, int* info, bse_report* rep);
+
 /* ---------------------------------------------------------------------------
  * Stage entry points.  Each runs one step of the chain on caller buffers so
  * that it can be checked on its own.  Real matrices are FP64 column-major.

@@ -62,6 +62,11 @@ SIGNATURES = [
     ("bse_ctx_set_timing", _I, [_P, _I]),
     ("bse_footprint_bytes", ctypes.c_size_t, [_I, _I, _U]),
     ("bse_solve", _I, [_P, _I, _P, _I, _P, _I, _I, _U, _P, _P, _I, _P, _P, _P, ctypes.POINTER(BseReport)]),
+    ("bse_footprint_batched_bytes", ctypes.c_size_t, [_I, ctypes.POINTER(_I), _I, _U]),
+    ("bse_solve_batched", _I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_P), ctypes.POINTER(_I),
+                               ctypes.POINTER(_P), ctypes.POINTER(_I), _I, _U, ctypes.POINTER(_P),
+                               ctypes.POINTER(_P), ctypes.POINTER(_I), ctypes.POINTER(_P),
+                               ctypes.POINTER(_P), ctypes.POINTER(_I), ctypes.POINTER(BseReport)]),
     ("bse_build_M", _I, [_P, _I, _P, _I, _P, _I, _P, _I]),
     ("bse_potrf", _I, [_P, _I, _P, _I]),
     ("bse_form_W", _I, [_P, _I, _P, _I, _P, _I]),

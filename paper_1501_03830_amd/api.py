@@ -121,6 +121,60 @@ class Context:
             ctypes.byref(rep) if rep is not None else None), "bse_solve")
         return info, (rep.as_dict() if rep is not None else None)
 
+    def solve_batched_raw(self, ns, Acs, Bcs, lams, Xbufs=None, ds=None, ws=None, report: bool = False):
+        """bse_solve_batched on column-major device buffers (as made by
+        to_colmajor), one entry per problem; nothing is copied.  Returns
+        (info list, report)."""
+        count = len(ns)
+        flags = 0
+        if Xbufs is not None:
+            flags |= _lib.BSE_WANT_VECTORS
+        if ds is not None:
+            flags |= _lib.BSE_WANT_WEIGHTS
+        IA = ctypes.c_int * count
+        PA = _P * count
+        n_arr = IA(*ns)
+        A_arr = PA(*[t.data_ptr() for t in Acs])
+        B_arr = PA(*[t.data_ptr() for t in Bcs])
+        ld_arr = IA(*ns)
+        lam_arr = PA(*[t.data_ptr() for t in lams])
+        X_arr = PA(*[t.data_ptr() for t in Xbufs]) if Xbufs is not None else None
+        ldx_arr = IA(*[2 * k for k in ns]) if Xbufs is not None else None
+        d_arr = PA(*[t.data_ptr() for t in ds]) if ds is not None else None
+        w_arr = PA(*[t.data_ptr() for t in ws]) if ws is not None else None
+        info = IA()
+        rep = _lib.BseReport() if report else None
+        _lib.check(self.lib.bse_solve_batched(
+            self.h, count, n_arr, A_arr, ld_arr, B_arr, ld_arr, _lib.BSE_PREC_FP64, flags, lam_arr,
+            X_arr, ldx_arr, d_arr, w_arr, info, ctypes.byref(rep) if rep is not None else None),
+            "bse_solve_batched")
+        return list(info), (rep.as_dict() if rep is not None else None)
+
+    def solve_batched(self, As, Bs, ds=None, vectors: bool = True, report: bool = False):
+        """Batched eigensolve of independent problems (lists of complex128
+        (n_i, n_i) logical matrices; ds: optional list of complex 2n_i dipole
+        vectors used as d_r = d_l).  Returns a list of per-problem dicts like
+        solve() and the batch report."""
+        dev = self.device
+        ns = [int(A.shape[0]) for A in As]
+        Acs = [to_colmajor(A.to(torch.complex128), dev) for A in As]
+        Bcs = [to_colmajor(B.to(torch.complex128), dev) for B in Bs]
+        lams = [torch.empty(k, dtype=torch.float64, device=dev) for k in ns]
+        want_x = vectors or ds is not None
+        Xbufs = [torch.empty((k, 2 * k), dtype=torch.complex128, device=dev) for k in ns] if want_x else None
+        dbs = [d.to(dev, torch.complex128).contiguous() for d in ds] if ds is not None else None
+        ws = [torch.empty(k, dtype=torch.complex128, device=dev) for k in ns] if ds is not None else None
+        info, rep = self.solve_batched_raw(ns, Acs, Bcs, lams, Xbufs, dbs, ws, report)
+        out = []
+        for i in range(len(ns)):
+            out.append({
+                "info": info[i],
+                "lam": lams[i],
+                "X": None if Xbufs is None else from_colmajor(Xbufs[i]),
+                "w": None if ws is None else ws[i],
+            })
+        return out, rep
+
     # ----------------------------------------------------------------- stages
     def build_M(self, A: torch.Tensor, B: torch.Tensor) -> torch.Tensor:
         n = A.shape[0]
@@ -162,3 +216,8 @@ class Context:
 
 def footprint_bytes(n: int, prec: int = _lib.BSE_PREC_FP64, flags: int = 0) -> int:
     return int(_lib.load().bse_footprint_bytes(n, prec, flags))
+
+
+def footprint_batched_bytes(ns, prec: int = _lib.BSE_PREC_FP64, flags: int = 0) -> int:
+    arr = (ctypes.c_int * len(ns))(*ns)
+    return int(_lib.load().bse_footprint_batched_bytes(len(ns), arr, prec, flags))

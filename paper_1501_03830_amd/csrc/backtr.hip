@@ -23,11 +23,17 @@ namespace bse {
 
 namespace {
 
-__global__ __launch_bounds__(256) void k_scatter_DV(int N, const double* __restrict__ Vt, double* __restrict__ Z,
-                                                    long ldz) {
+constexpr int NBQ = 64;   // reflectors per block
+
+__global__ __launch_bounds__(256) void k_scatter_DV(const Prob* __restrict__ probs) {
   __shared__ double t[64][65];
-  const int n = N / 2;
+  const Prob& P = probs[blockIdx.z];
+  const int N = P.N, n = P.n;
   const int k0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  if (k0 >= N || j0 >= n) return;  // uniform
+  const double* __restrict__ Vt = P.Vt;
+  double* __restrict__ Z = P.Z;
+  const long ldz = P.ld;
   for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
     const int jj = idx & 63, kk = idx >> 6;
     const int j = j0 + jj, k = k0 + kk;
@@ -46,10 +52,18 @@ __global__ __launch_bounds__(256) void k_scatter_DV(int N, const double* __restr
   }
 }
 
-// Explicit reflector block: Vb[r, l] for rows r in [j0+1, N):
+// Explicit reflector block q: Vb[r, l] for rows r in [j0+1, N), j0 = 64 q:
 //   0 above row j0+l+1, 1 at row j0+l+1, W[r, j0+l] below.
-__global__ __launch_bounds__(256) void k_extract_V(const double* __restrict__ W, long ldw, int N, int j0,
-                                                   int nbk, double* __restrict__ Vb, long ldv) {
+__global__ __launch_bounds__(256) void k_extract_V(const Prob* __restrict__ probs, int q) {
+  const Prob& P = probs[blockIdx.z];
+  const int N = P.N;
+  const int nrefl = N - 2;
+  const int j0 = q * NBQ;
+  if (j0 >= nrefl) return;  // uniform
+  const int nbk = min(NBQ, nrefl - j0);
+  const double* __restrict__ W = P.W;
+  double* __restrict__ Vb = P.Vb;
+  const long ldw = P.ld, ldv = P.ld;
   const long r = (long)j0 + 1 + (long)blockIdx.x * 64 + (threadIdx.x & 63);
   if (r >= N) return;
   for (int l = threadIdx.x >> 6; l < nbk; l += 4) {
@@ -62,12 +76,20 @@ __global__ __launch_bounds__(256) void k_extract_V(const double* __restrict__ W,
   }
 }
 
-// T (upper, nbk x nbk, ld nbq) with H_{j0} ... H_{j0+nbk-1} = I - V T V^T,
+// T (upper, nbk x nbk, ld NBQ) with H_{j0} ... H_{j0+nbk-1} = I - V T V^T,
 // from S = V^T V:  T[l,l] = tau_l,  T[0:l, l] = -tau_l T[0:l,0:l] S[0:l, l].
-__global__ __launch_bounds__(64) void k_larft(const double* __restrict__ S, int nbq, int nbk,
-                                              const double* __restrict__ tau, int j0, double* __restrict__ T) {
+__global__ __launch_bounds__(64) void k_larft(const Prob* __restrict__ probs, int q) {
   __shared__ double Ts[64][65];   // Ts[col][row]
   __shared__ double u[64];
+  const Prob& P = probs[blockIdx.z];
+  const int nrefl = P.N - 2;
+  const int j0 = q * NBQ;
+  if (j0 >= nrefl) return;  // uniform
+  const int nbk = min(NBQ, nrefl - j0);
+  const int nbq = NBQ;
+  const double* __restrict__ S = P.S;
+  const double* __restrict__ tau = P.tau;
+  double* __restrict__ T = P.T;
   const int i = threadIdx.x;
   for (int c = 0; c < 64; ++c) Ts[c][i] = 0.0;
   __syncthreads();
@@ -87,9 +109,15 @@ __global__ __launch_bounds__(64) void k_larft(const double* __restrict__ S, int 
     if (i < nbk) T[i + (long)c * nbq] = Ts[c][i];
 }
 
-__global__ __launch_bounds__(256) void k_finish_X(int n, const double* __restrict__ G, long ldg,
-                                                  const double* __restrict__ lam, double* __restrict__ X,
-                                                  long ldx) {
+// X = S Q G Lambda^{-1/2} from G = L U D V_+ = [Re | Im] held in P.W
+__global__ __launch_bounds__(256) void k_finish_X(const Prob* __restrict__ probs) {
+  const Prob& P = probs[blockIdx.z];
+  const int n = P.n;
+  const double* __restrict__ G = P.W;
+  const long ldg = P.ld;
+  const double* __restrict__ lam = P.lambda;
+  double* __restrict__ X = P.X;
+  const long ldx = P.ldx;
   const long r = (long)blockIdx.x * 64 + (threadIdx.x & 63);
   const long c0 = (long)blockIdx.y * 64 + (threadIdx.x >> 6) * 16;
   if (r >= n) return;
@@ -110,14 +138,21 @@ __global__ __launch_bounds__(256) void k_finish_X(int n, const double* __restric
 
 // One workgroup per column: canonical phase (largest modulus, lowest index on
 // ties, made real positive), then the weights of eq. absp with y = S x.
-__global__ __launch_bounds__(256) void k_phase_weights(int n, double* __restrict__ X, long ldx,
-                                                       const double* __restrict__ dr,
-                                                       const double* __restrict__ dl, double* __restrict__ w) {
+__global__ __launch_bounds__(256) void k_phase_weights(const Prob* __restrict__ probs) {
   __shared__ double sval[4];
   __shared__ int sidx[4];
   __shared__ double red[4];
   __shared__ double ph[2];
+  const Prob& P = probs[blockIdx.z];
+  const int n = P.n;
   const int j = blockIdx.x;
+  if (j >= n) return;  // uniform
+  const long ldx = P.ldx;
+  double* __restrict__ X = P.X;
+  const bool weights = (P.flags & BSE_WANT_WEIGHTS) != 0 && P.dr != nullptr && P.w != nullptr;
+  const double* __restrict__ dr = weights ? P.dr : nullptr;
+  const double* __restrict__ dl = weights ? (P.dl ? P.dl : P.dr) : nullptr;
+  double* __restrict__ w = P.w;
   const int N = 2 * n;
   double* x = X + 2 * (long)j * ldx;
   double best = -1.0;
@@ -151,6 +186,7 @@ __global__ __launch_bounds__(256) void k_phase_weights(int n, double* __restrict
         b = sval[k];
         ix = sidx[k];
       }
+    if (ix < 0 || ix >= N) ix = 0;  // no finite maximum (NaN input): keep index 0
     const double pr = x[2 * ix], pi = x[2 * ix + 1];
     const double m = hypot(pr, pi);
     ph[0] = (m > 0.0) ? pr / m : 1.0;
@@ -193,70 +229,58 @@ __global__ __launch_bounds__(256) void k_phase_weights(int n, double* __restrict
 
 }  // namespace
 
-size_t backtr_work_bytes(long N, long ld, int nbq) {
+size_t backtr_work_bytes(long N, long ld) {
   (void)N;
-  return ((size_t)ld * nbq + 2 * (size_t)nbq * nbq + 2 * (size_t)nbq * ld) * sizeof(double) + 5 * 256;
+  return ((size_t)ld * NBQ + 2 * (size_t)NBQ * NBQ + 2 * (size_t)NBQ * ld) * sizeof(double) + 5 * 256;
 }
 
-int backtr_bind_work(void* base, long N, long ld, int nbq, BacktrWork* w) {
+void backtr_bind_work(char* base, long N, long ld, Prob* P) {
   (void)N;
-  char* p = static_cast<char*>(base);
+  char* p = base;
   auto take = [&](size_t bytes) {
     char* q = p;
     p += round_up((long)bytes, 256);
     return q;
   };
-  w->Vb = reinterpret_cast<double*>(take((size_t)ld * nbq * sizeof(double)));
-  w->S = reinterpret_cast<double*>(take((size_t)nbq * nbq * sizeof(double)));
-  w->T = reinterpret_cast<double*>(take((size_t)nbq * nbq * sizeof(double)));
-  w->W1 = reinterpret_cast<double*>(take((size_t)nbq * ld * sizeof(double)));
-  w->W2 = reinterpret_cast<double*>(take((size_t)nbq * ld * sizeof(double)));
-  w->nbq = nbq;
-  return 0;
+  P->Vb = reinterpret_cast<double*>(take((size_t)ld * NBQ * sizeof(double)));
+  P->S = reinterpret_cast<double*>(take((size_t)NBQ * NBQ * sizeof(double)));
+  P->T = reinterpret_cast<double*>(take((size_t)NBQ * NBQ * sizeof(double)));
+  P->W1 = reinterpret_cast<double*>(take((size_t)NBQ * ld * sizeof(double)));
+  P->W2 = reinterpret_cast<double*>(take((size_t)NBQ * ld * sizeof(double)));
 }
 
-int scatter_DV(hipStream_t s, int N, const double* Vt, double* Z, long ldz) {
-  const int n = N / 2;
-  dim3 g((unsigned)((N + 63) / 64), (unsigned)((n + 63) / 64));
-  k_scatter_DV<<<g, 256, 0, s>>>(N, Vt, Z, ldz);
+int apply_UD_batched(hipStream_t s, const Batch& b) {
+  if (b.count <= 0) return 0;
+  const int N0 = b.maxN(), n0 = b.maxn();
+  // Z = [Re(D V_+) | Im(D V_+)]
+  k_scatter_DV<<<dim3((unsigned)((N0 + 63) / 64), (unsigned)((n0 + 63) / 64), (unsigned)b.count), 256, 0, s>>>(b.dev);
   BSE_LAUNCHED();
-  return 0;
-}
-
-int apply_U(hipStream_t s, int N, const double* W, long ldw, const double* tau, double* Z, long ldz,
-            int ncols, const BacktrWork& w) {
-  const int nrefl = N - 2;  // H_0 .. H_{N-3}; H_{N-2} is the identity
-  if (nrefl <= 0) return 0;
-  const int nbq = w.nbq;
-  const int nblocks = (nrefl + nbq - 1) / nbq;
-  for (int q = nblocks - 1; q >= 0; --q) {
-    const int j0 = q * nbq;
-    const int nbk = (nrefl - j0 < nbq) ? nrefl - j0 : nbq;
-    const int m = N - j0 - 1;
-    double* Vb = w.Vb + (j0 + 1);
-    double* Zs = Z + (j0 + 1);
-    k_extract_V<<<(unsigned)((m + 63) / 64), 256, 0, s>>>(W, ldw, N, j0, nbk, w.Vb, ldw);
+  // Z <- U Z with U = H_0 ... H_{N-3}, last block of reflectors first
+  const int nrefl0 = N0 - 2;   // H_{N-2} is the identity
+  if (nrefl0 <= 0) return 0;
+  const int nblocks0 = (nrefl0 + NBQ - 1) / NBQ;
+  for (int q = nblocks0 - 1; q >= 0; --q) {
+    const int j0 = q * NBQ;
+    const int nact = b.active_N_above(j0 + 2);   // N - 2 > j0
+    const int m0 = N0 - j0 - 1;
+    k_extract_V<<<dim3((unsigned)((m0 + 63) / 64), 1, (unsigned)nact), 256, 0, s>>>(b.dev, q);
     BSE_LAUNCHED();
-    BSE_TRY(gemm_f64(s, true, false, nbk, nbk, m, 1.0, Vb, ldw, Vb, ldw, 0.0, w.S, nbq, 0, 0, 0));
-    k_larft<<<1, 64, 0, s>>>(w.S, nbq, nbk, tau, j0, w.T);
+    BSE_TRY(gemm_batched(s, b, nact, GOP_APPLYU_S, q));
+    k_larft<<<dim3(1, 1, (unsigned)nact), 64, 0, s>>>(b.dev, q);
     BSE_LAUNCHED();
-    BSE_TRY(gemm_f64(s, true, false, nbk, ncols, m, 1.0, Vb, ldw, Zs, ldz, 0.0, w.W1, nbq, 0, 0, 0));
-    BSE_TRY(gemm_f64(s, false, false, nbk, ncols, nbk, 1.0, w.T, nbq, w.W1, nbq, 0.0, w.W2, nbq, 0, 0, 0));
-    BSE_TRY(gemm_f64(s, false, false, m, ncols, nbk, -1.0, Vb, ldw, w.W2, nbq, 1.0, Zs, ldz, 0, 0, 0));
+    BSE_TRY(gemm_batched(s, b, nact, GOP_APPLYU_W1, q));
+    BSE_TRY(gemm_batched(s, b, nact, GOP_APPLYU_W2, q));
+    BSE_TRY(gemm_batched(s, b, nact, GOP_APPLYU_Z, q));
   }
   return 0;
 }
 
-int finish_X(hipStream_t s, int n, const double* G, long ldg, const double* lam, double* X, long ldx) {
-  dim3 g((unsigned)((n + 63) / 64), (unsigned)((n + 63) / 64));
-  k_finish_X<<<g, 256, 0, s>>>(n, G, ldg, lam, X, ldx);
+int finish_batched(hipStream_t s, const Batch& b) {
+  if (b.count <= 0) return 0;
+  const int n0 = b.maxn();
+  k_finish_X<<<dim3((unsigned)((n0 + 63) / 64), (unsigned)((n0 + 63) / 64), (unsigned)b.count), 256, 0, s>>>(b.dev);
   BSE_LAUNCHED();
-  return 0;
-}
-
-int phase_and_weights(hipStream_t s, int n, double* X, long ldx, const double* dr, const double* dl,
-                      double* w) {
-  k_phase_weights<<<(unsigned)n, 256, 0, s>>>(n, X, ldx, dr, dl, w);
+  k_phase_weights<<<dim3((unsigned)n0, 1, (unsigned)b.count), 256, 0, s>>>(b.dev);
   BSE_LAUNCHED();
   return 0;
 }

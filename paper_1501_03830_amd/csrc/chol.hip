@@ -18,13 +18,16 @@ namespace {
 
 constexpr int TB = 64;
 
-__global__ __launch_bounds__(256) void k_build_M(int n, const double* __restrict__ A, long lda,
-                                                 const double* __restrict__ B, long ldb,
-                                                 double* __restrict__ M, long ldm) {
-  const int N = 2 * n;
+__global__ __launch_bounds__(256) void k_build_M(const Prob* __restrict__ probs) {
+  const Prob& P = probs[blockIdx.z];
+  const int n = P.n, N = P.N;
   const int r = blockIdx.x * TB + (threadIdx.x & 63);
   const int cbase = blockIdx.y * TB + (threadIdx.x >> 6) * 16;
   if (r >= N) return;
+  const double* __restrict__ A = P.A;
+  const double* __restrict__ B = P.B;
+  const long lda = P.lda, ldb = P.ldb, ldm = P.ld;
+  double* __restrict__ M = P.L;
   for (int q = 0; q < 16; ++q) {
     const int c = cbase + q;
     if (c >= N) break;
@@ -55,15 +58,32 @@ __global__ __launch_bounds__(256) void k_build_M(int n, const double* __restrict
   }
 }
 
-__global__ void k_set_int(int* p, int v) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+__global__ void k_reset_info(const Prob* __restrict__ probs, int sel) {
+  if (threadIdx.x == 0) probs[blockIdx.z].info[sel] = 0;
 }
 
-// Unblocked Cholesky of the nb x nb diagonal block at (k0, k0), in LDS.
-__global__ __launch_bounds__(256) void k_potf2(double* __restrict__ M, long ld, int N, int k0,
-                                               int* __restrict__ info) {
+__device__ inline void chol_matrix(const Prob& P, int sel, double*& M, long& ld, int& N) {
+  if (sel == 0) {
+    M = P.L;
+    ld = P.ld;
+    N = P.N;
+  } else {
+    M = P.inv;
+    ld = P.n;
+    N = P.n;
+  }
+}
+
+// Unblocked Cholesky of the diagonal block at (k0, k0), in LDS.
+__global__ __launch_bounds__(256) void k_potf2(const Prob* __restrict__ probs, int sel, int k0) {
   __shared__ double a[TB][TB + 1];  // a[col][row]
-  if (*info != 0) return;
+  const Prob& P = probs[blockIdx.z];
+  double* M;
+  long ld;
+  int N;
+  chol_matrix(P, sel, M, ld, N);
+  int* info = P.info + sel;
+  if (k0 >= N || *info != 0) return;
   const int nbk = min(TB, N - k0);
   const int tid = threadIdx.x;
   for (int idx = tid; idx < TB * TB; idx += 256) {
@@ -95,14 +115,20 @@ __global__ __launch_bounds__(256) void k_potf2(double* __restrict__ M, long ld, 
   }
 }
 
-// Inverse of the lower-triangular nbk x nbk diagonal block at (b0, b0) into
-// Linv (64 x 64, ld 64): thread c solves L y = e_c by forward substitution,
-// with y kept in LDS.
-__global__ __launch_bounds__(64) void k_trtri64(const double* __restrict__ L, long ld, int b0, int nbk,
-                                                double* __restrict__ Linv, const int* __restrict__ info) {
+// Inverse of the lower-triangular diagonal block at (b0, b0) into P.linv
+// (64 x 64, ld 64): thread c solves L y = e_c by forward substitution, with
+// y kept in LDS.
+__global__ __launch_bounds__(64) void k_trtri64(const Prob* __restrict__ probs, int sel, int b0) {
   __shared__ double Lc[TB][TB + 1];  // Lc[col][row]
   __shared__ double Y[TB][TB + 1];   // Y[col][row]
-  if (*info != 0) return;
+  const Prob& P = probs[blockIdx.z];
+  double* L;
+  long ld;
+  int N;
+  chol_matrix(P, sel, L, ld, N);
+  if (b0 >= N || P.info[sel] != 0) return;
+  const int nbk = min(TB, N - b0);
+  double* __restrict__ Linv = P.linv;
   const int c = threadIdx.x;
   for (int r = 0; r < TB; ++r)
     Lc[c][r] = (r < nbk && c < nbk && r >= c) ? L[(long)(b0 + r) + (long)(b0 + c) * ld] : 0.0;
@@ -119,14 +145,20 @@ __global__ __launch_bounds__(64) void k_trtri64(const double* __restrict__ L, lo
   for (int r = 0; r < TB; ++r) Linv[r + (long)c * TB] = Y[c][r];
 }
 
-// For every lower tile pair (R, C), R >= C, of an nrows x nrows matrix:
+// For every lower tile pair (R, C), R >= C, of the leading nrows x nrows
+// part of P.W (nrows = n in mode 0, N in mode 1):
 //  mode 0: lower <- T1 - T2^T  (T1 = tile (R,C), T2 = tile (C,R)); diagonal 0;
 //          with `full` the upper triangle receives the negated transpose.
 //  mode 1: upper <- -lower^T (completion of a skew matrix from its lower part)
-__global__ __launch_bounds__(256) void k_skew_pairs(double* __restrict__ W, long ld, int nrows,
-                                                    int mode, int full) {
+__global__ __launch_bounds__(256) void k_skew_pairs(const Prob* __restrict__ probs, int mode, int full) {
   __shared__ double t1[TB][TB + 1];
   __shared__ double t2[TB][TB + 1];
+  const Prob& P = probs[blockIdx.z];
+  const int nrows = (mode == 0) ? P.n : P.N;
+  const long nt = (nrows + TB - 1) / TB;
+  if ((long)blockIdx.x >= nt * (nt + 1) / 2) return;
+  double* __restrict__ W = P.W;
+  const long ld = P.ld;
   int R, C;
   tri_index(blockIdx.x, R, C);
   const int tid = threadIdx.x;
@@ -152,6 +184,21 @@ __global__ __launch_bounds__(256) void k_skew_pairs(double* __restrict__ W, long
   }
 }
 
+// W22 = 0
+__global__ __launch_bounds__(256) void k_zero_W22(const Prob* __restrict__ probs) {
+  const Prob& P = probs[blockIdx.z];
+  const long n = P.n;
+  const long r = (long)blockIdx.x * 64 + (threadIdx.x & 63);
+  const long c0 = (long)blockIdx.y * 64 + (threadIdx.x >> 6) * 16;
+  if (r >= n) return;
+  double* W22 = P.W + n + n * P.ld;
+  for (int q = 0; q < 16; ++q) {
+    const long c = c0 + q;
+    if (c >= n) break;
+    W22[r + c * P.ld] = 0.0;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_copy(int m, int n, const double* __restrict__ src, long lds,
                                               double* __restrict__ dst, long ldd) {
   const long r = (long)blockIdx.x * 64 + (threadIdx.x & 63);
@@ -164,27 +211,27 @@ __global__ __launch_bounds__(256) void k_copy(int m, int n, const double* __rest
   }
 }
 
-__global__ __launch_bounds__(256) void k_fill(int m, int n, double* __restrict__ dst, long ldd,
-                                              double v, int upper_only) {
+__global__ __launch_bounds__(256) void k_zero_upper(int n, double* __restrict__ dst, long ldd) {
   const long r = (long)blockIdx.x * 64 + (threadIdx.x & 63);
   const long c0 = (long)blockIdx.y * 64 + (threadIdx.x >> 6) * 16;
-  if (r >= m) return;
+  if (r >= n) return;
   for (int q = 0; q < 16; ++q) {
     const long c = c0 + q;
     if (c >= n) break;
-    if (upper_only && r >= c) continue;
-    dst[r + c * ldd] = v;
+    if (r < c) dst[r + c * ldd] = 0.0;
   }
 }
 
-dim3 grid2d(long m, long n) { return dim3((unsigned)((m + 63) / 64), (unsigned)((n + 63) / 64)); }
+dim3 grid2d(long m, long n, int z = 1) {
+  return dim3((unsigned)((m + 63) / 64), (unsigned)((n + 63) / 64), (unsigned)z);
+}
 
 }  // namespace
 
-int launch_build_M(hipStream_t s, int n, const double* A, long lda, const double* B, long ldb,
-                   double* M, long ldm) {
-  const long N = 2L * n;
-  k_build_M<<<grid2d(N, N), 256, 0, s>>>(n, A, lda, B, ldb, M, ldm);
+int build_M_batched(hipStream_t s, const Batch& b) {
+  if (b.count <= 0) return 0;
+  const long N = b.maxN();
+  k_build_M<<<grid2d(N, N, b.count), 256, 0, s>>>(b.dev);
   BSE_LAUNCHED();
   return 0;
 }
@@ -198,58 +245,61 @@ int copy_matrix(hipStream_t s, int m, int n, const double* src, long lds, double
 
 int zero_upper(hipStream_t s, int N, double* A, long lda) {
   if (N <= 0) return 0;
-  k_fill<<<grid2d(N, N), 256, 0, s>>>(N, N, A, lda, 0.0, 1);
+  k_zero_upper<<<grid2d(N, N), 256, 0, s>>>(N, A, lda);
   BSE_LAUNCHED();
   return 0;
 }
 
-int trtri_diag64(hipStream_t s, const double* L, long ld, int b0, int nbk, double* Linv, const int* info_dev) {
-  k_trtri64<<<1, 64, 0, s>>>(L, ld, b0, nbk, Linv, info_dev);
+int trtri_batched(hipStream_t s, const Batch& b, int nact, int sel, int b0) {
+  if (nact <= 0) return 0;
+  k_trtri64<<<dim3(1, 1, (unsigned)nact), 64, 0, s>>>(b.dev, sel, b0);
   BSE_LAUNCHED();
   return 0;
 }
 
-int potrf_f64(hipStream_t s, int N, double* M, long ld, int* info_dev, double* linv, bool reset_info) {
+int potrf_batched(hipStream_t s, const Batch& b, int sel, bool reset_info) {
+  if (b.count <= 0) return 0;
   if (reset_info) {
-    k_set_int<<<1, 64, 0, s>>>(info_dev, 0);
+    k_reset_info<<<dim3(1, 1, (unsigned)b.count), 64, 0, s>>>(b.dev, sel);
     BSE_LAUNCHED();
   }
-  for (int k0 = 0; k0 < N; k0 += TB) {
-    const int nbk = (N - k0 < TB) ? N - k0 : TB;
-    k_potf2<<<1, 256, 0, s>>>(M, ld, N, k0, info_dev);
+  // order of the factored matrix: N (sel 0) or n (sel 1); both sort with N
+  auto order = [sel](const Prob& P) { return sel == 0 ? P.N : P.n; };
+  const int Nmax = order(b.host[0]);
+  const int TOPS = sel == 0 ? GOP_POTRF_TRSM : GOP_GRAM_TRSM;
+  const int SOPS = sel == 0 ? GOP_POTRF_SYRK : GOP_GRAM_SYRK;
+  for (int k0 = 0; k0 < Nmax; k0 += TB) {
+    int nact = 0;  // problems with a diagonal block at k0
+    while (nact < b.count && order(b.host[nact]) > k0) ++nact;
+    k_potf2<<<dim3(1, 1, (unsigned)nact), 256, 0, s>>>(b.dev, sel, k0);
     BSE_LAUNCHED();
-    const int rest = N - k0 - nbk;
-    if (rest > 0) {
-      double* a21 = M + (k0 + nbk) + (long)k0 * ld;
+    int nrest = 0;  // problems with rows below the block
+    while (nrest < nact && order(b.host[nrest]) > k0 + TB) ++nrest;
+    if (nrest > 0) {
       // A21 <- A21 L_kk^{-T}; in place is safe: one column tile of output
-      k_trtri64<<<1, 64, 0, s>>>(M, ld, k0, nbk, linv, info_dev);
-      BSE_LAUNCHED();
-      BSE_TRY(gemm_f64(s, false, true, rest, nbk, nbk, 1.0, a21, ld, linv, TB, 0.0, a21, ld, 0, 0, 0));
-      double* a22 = M + (k0 + nbk) + (long)(k0 + nbk) * ld;
-      BSE_TRY(gemm_f64(s, false, true, rest, rest, nbk, -1.0, a21, ld, a21, ld, 1.0, a22, ld, 1, 0, 0));
+      BSE_TRY(trtri_batched(s, b, nrest, sel, k0));
+      BSE_TRY(gemm_batched(s, b, nrest, TOPS, k0));
+      BSE_TRY(gemm_batched(s, b, nrest, SOPS, k0));
     }
   }
   return 0;
 }
 
-int form_W(hipStream_t s, int N, const double* L, long ldl, double* W, long ldw, bool full) {
-  const int n = N / 2;
-  const double* L11 = L;
-  const double* L21 = L + n;
-  const double* L22 = L + n + (long)n * ldl;
+int form_W_batched(hipStream_t s, const Batch& b, bool full) {
+  if (b.count <= 0) return 0;
+  const long n = b.maxn(), N = b.maxN();
   // C = L11^T L21 into W11, then W11 = C - C^T
-  BSE_TRY(gemm_f64(s, true, false, n, n, n, 1.0, L11, ldl, L21, ldl, 0.0, W, ldw, 0, 1, 0));
+  BSE_TRY(gemm_batched(s, b, b.count, GOP_FORMW_C, 0));
   const long nt = (n + TB - 1) / TB;
-  k_skew_pairs<<<(unsigned)(nt * (nt + 1) / 2), 256, 0, s>>>(W, ldw, n, 0, full ? 1 : 0);
+  k_skew_pairs<<<dim3((unsigned)(nt * (nt + 1) / 2), 1, (unsigned)b.count), 256, 0, s>>>(b.dev, 0, full ? 1 : 0);
   BSE_LAUNCHED();
   // W21 = -L22^T L11
-  BSE_TRY(gemm_f64(s, true, false, n, n, n, -1.0, L22, ldl, L11, ldl, 0.0, W + n, ldw, 0, 1, 1));
-  // W22 = 0
-  k_fill<<<grid2d(n, n), 256, 0, s>>>(n, n, W + n + (long)n * ldw, ldw, 0.0, 0);
+  BSE_TRY(gemm_batched(s, b, b.count, GOP_FORMW_21, 0));
+  k_zero_W22<<<grid2d(n, n, b.count), 256, 0, s>>>(b.dev);
   BSE_LAUNCHED();
   if (full) {
     const long Nt = (N + TB - 1) / TB;
-    k_skew_pairs<<<(unsigned)(Nt * (Nt + 1) / 2), 256, 0, s>>>(W, ldw, N, 1, 1);
+    k_skew_pairs<<<dim3((unsigned)(Nt * (Nt + 1) / 2), 1, (unsigned)b.count), 256, 0, s>>>(b.dev, 1, 1);
     BSE_LAUNCHED();
   }
   return 0;

@@ -43,6 +43,37 @@ int set_hip_error(hipError_t e, const char* what, const char* file, int line);
     if (rc_ != 0) return rc_;                                                \
   } while (0)
 
+// Everything one problem of a (possibly one-element) batch needs on the
+// device: its sizes, the caller's input/output buffers and its own slice of
+// the workspace.  Kernels read it from a device array indexed by the problem
+// number (blockIdx.z), so one launch can serve many problems of different
+// sizes.
+struct Prob {
+  int n, N;             // order of A and B, and of the real embedding (N = 2n)
+  long ld;              // leading dimension of every N x N workspace matrix
+  const double* A;      // complex n x n, column-major, lower triangle used
+  long lda;
+  const double* B;
+  long ldb;
+  double* lambda;       // n positive eigenvalues (output)
+  double* X;            // complex 2n x n (output) or null
+  long ldx;
+  const double* dr;     // complex 2n dipoles or null
+  const double* dl;
+  double* w;            // complex n weights (output) or null
+  unsigned flags;
+  // workspace
+  double *L, *W, *Z, *Vt, *inv, *alpha, *tau, *e2, *scal, *shift, *linv, *gscr;
+  size_t gscr_bytes;
+  int* cid;
+  int* info;            // info[0]: Cholesky of M, info[1]: Cholesky of the Gram matrix
+  // tridiagonalisation work
+  double *Y1, *Y2, *Yrow, *Ycol, *dotpart, *normpart;
+  void* ctrl;
+  // back-transformation work
+  double *Vb, *S, *T, *W1, *W2;
+};
+
 // Row/column decomposition of a linear index over the lower triangle of an
 // nt x nt tile grid: t = R (R + 1) / 2 + C with 0 <= C <= R < nt.
 __device__ inline void tri_index(long t, int& R, int& C) {

@@ -11,15 +11,19 @@
 //   a_tri   the stored A is lower triangular: the K loop skips its zeros
 //   b_tri   the stored B is lower triangular
 //
+// Batched form: the operands of every product in the chain are a function of
+// the problem (Prob) and a step index (panel, block ...), so a launch passes
+// an operation code and the step; each workgroup derives its problem's
+// parameters itself (gemm_params) and the launch covers all problems of a
+// batch (blockIdx.z).  Workgroups beyond a problem's own tile count exit.
+//
 // Tiling: a 256-thread workgroup (4 wavefronts in a 2 x 2 arrangement) owns a
-// 64 x 64 or 128 x 128 C tile (each wave 2 x 2 or 4 x 4 MFMA blocks of
-// 16 x 16); K steps of 16 are staged through LDS with a register prefetch of
-// the next slab.  The epilogue goes through LDS so that C is read and written
-// a whole column (64 or 128 consecutive doubles) per instruction.  Products
-// with few output tiles and a long K (V^T Z in the reflector application)
-// are split along K into a scratch buffer and summed by a second kernel.
-#include <cstdlib>
-
+// 64 x 64 C tile (each wave 2 x 2 MFMA blocks of 16 x 16); K steps of 16 are
+// staged through LDS with a register prefetch of the next slab.  The epilogue
+// goes through LDS so that C is read and written a whole column (64
+// consecutive doubles) per instruction.  Products with few output tiles and a
+// long K (V^T Z in the reflector application) are split along K into the
+// problem's scratch buffer and summed by a second kernel.
 #include "common.h"
 #include "kernels.h"
 
@@ -27,47 +31,169 @@ namespace bse {
 
 namespace {
 
-constexpr int BK = 16, PAD = 2;
+constexpr int BM = 64, BN = 64, BK = 16, PAD = 2;
 
-struct GemmParams {
-  int M, N, K;
-  const double* A;
-  long lda;
-  const double* B;
-  long ldb;
-  double* C;
-  long ldc;
-  double alpha, beta;
-  int c_uplo, a_tri, b_tri;
-  int tiles_m, tiles_n;
-  int splits, kchunk;
-  double* part;  // split-K partial products [splits][M x N], ld M
-};
+}  // namespace
 
-constexpr int cmax(int a, int b) { return a > b ? a : b; }
+// Parameters of product `op` at `step` for problem P (host and device).
+__host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
+  GemmParams g{};
+  g.alpha = 1.0;
+  g.beta = 0.0;
+  const long ld = P.ld;
+  const int NB = 64;
+  switch (op) {
+    case GOP_POTRF_TRSM:
+    case GOP_POTRF_SYRK:
+    case GOP_GRAM_TRSM:
+    case GOP_GRAM_SYRK: {
+      const bool gram = (op == GOP_GRAM_TRSM || op == GOP_GRAM_SYRK);
+      double* Mx = gram ? P.inv : P.L;
+      const int Nm = gram ? P.n : P.N;
+      const long ldm = gram ? (long)P.n : ld;
+      const int k0 = step;
+      const int nbk = (Nm - k0 < NB) ? Nm - k0 : NB;
+      const int rest = Nm - k0 - nbk;
+      if (nbk <= 0 || rest <= 0) break;  // M = N = 0: nothing to do
+      double* a21 = Mx + (k0 + nbk) + (long)k0 * ldm;
+      if (op == GOP_POTRF_TRSM || op == GOP_GRAM_TRSM) {
+        // A21 <- A21 Linv^T (in place: a single column tile of output)
+        g.ta = 0; g.tb = 1; g.M = rest; g.N = nbk; g.K = nbk;
+        g.A = a21; g.lda = ldm; g.B = P.linv; g.ldb = NB; g.C = a21; g.ldc = ldm;
+      } else {
+        g.ta = 0; g.tb = 1; g.M = rest; g.N = rest; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
+        g.A = a21; g.lda = ldm; g.B = a21; g.ldb = ldm;
+        g.C = Mx + (k0 + nbk) + (long)(k0 + nbk) * ldm; g.ldc = ldm; g.c_uplo = 1;
+      }
+      break;
+    }
+    case GOP_FORMW_C:   // W11 <- L11^T L21
+      g.ta = 1; g.tb = 0; g.M = P.n; g.N = P.n; g.K = P.n;
+      g.A = P.L; g.lda = ld; g.B = P.L + P.n; g.ldb = ld; g.C = P.W; g.ldc = ld; g.a_tri = 1;
+      break;
+    case GOP_FORMW_21:  // W21 <- -L22^T L11
+      g.ta = 1; g.tb = 0; g.M = P.n; g.N = P.n; g.K = P.n; g.alpha = -1.0;
+      g.A = P.L + P.n + (long)P.n * ld; g.lda = ld; g.B = P.L; g.ldb = ld; g.C = P.W + P.n; g.ldc = ld;
+      g.a_tri = 1; g.b_tri = 1;
+      break;
+    case GOP_SKTRD_R2K: {  // trailing W += [v p ...][p -v ...]^T after the panel at `step`
+      const int k0 = step;
+      if (k0 > P.N - 2) break;
+      const int nbp = (P.N - 1 - k0 < NB) ? P.N - 1 - k0 : NB;
+      const int e = k0 + nbp;
+      const int m2 = P.N - e;
+      if (m2 < 2 || e > P.N - 2) break;
+      g.ta = 0; g.tb = 1; g.M = m2; g.N = m2; g.K = 2 * nbp; g.beta = 1.0;
+      g.A = P.Y1 + e; g.lda = ld; g.B = P.Y2 + e; g.ldb = ld; g.C = P.W + e + (long)e * ld; g.ldc = ld;
+      g.c_uplo = 2;
+      break;
+    }
+    case GOP_GRAM:  // G <- Vt Vt^T (lower)
+      g.ta = 0; g.tb = 1; g.M = P.n; g.N = P.n; g.K = P.N;
+      g.A = P.Vt; g.lda = P.n; g.B = P.Vt; g.ldb = P.n; g.C = P.inv; g.ldc = P.n; g.c_uplo = 1;
+      break;
+    case GOP_GRAM_DIAG: {  // rows b0.. of Vt <- Linv (rows b0..), in place
+      const int b0 = step;
+      if (b0 >= P.n) break;
+      const int nbk = (P.n - b0 < NB) ? P.n - b0 : NB;
+      g.ta = 0; g.tb = 0; g.M = nbk; g.N = P.N; g.K = nbk;
+      g.A = P.linv; g.lda = NB; g.B = P.Vt + b0; g.ldb = P.n; g.C = P.Vt + b0; g.ldc = P.n;
+      break;
+    }
+    case GOP_GRAM_UPD: {  // rows below the block -= L21 (rows of the block)
+      const int b0 = step;
+      if (b0 >= P.n) break;
+      const int nbk = (P.n - b0 < NB) ? P.n - b0 : NB;
+      const int rest = P.n - b0 - nbk;
+      if (rest <= 0) break;
+      g.ta = 0; g.tb = 0; g.M = rest; g.N = P.N; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
+      g.A = P.inv + (b0 + nbk) + (long)b0 * P.n; g.lda = P.n; g.B = P.Vt + b0; g.ldb = P.n;
+      g.C = P.Vt + b0 + nbk; g.ldc = P.n;
+      break;
+    }
+    case GOP_APPLYU_S:
+    case GOP_APPLYU_W1:
+    case GOP_APPLYU_W2:
+    case GOP_APPLYU_Z: {
+      const int nrefl = P.N - 2;
+      const int j0 = step * NB;
+      if (nrefl <= 0 || j0 >= nrefl) break;
+      const int nbk = (nrefl - j0 < NB) ? nrefl - j0 : NB;
+      const int m = P.N - j0 - 1;
+      const double* Vb = P.Vb + (j0 + 1);
+      double* Zs = P.Z + (j0 + 1);
+      if (op == GOP_APPLYU_S) {
+        g.ta = 1; g.tb = 0; g.M = nbk; g.N = nbk; g.K = m;
+        g.A = Vb; g.lda = ld; g.B = Vb; g.ldb = ld; g.C = P.S; g.ldc = NB;
+      } else if (op == GOP_APPLYU_W1) {
+        g.ta = 1; g.tb = 0; g.M = nbk; g.N = P.N; g.K = m;
+        g.A = Vb; g.lda = ld; g.B = Zs; g.ldb = ld; g.C = P.W1; g.ldc = NB;
+      } else if (op == GOP_APPLYU_W2) {
+        g.ta = 0; g.tb = 0; g.M = nbk; g.N = P.N; g.K = nbk;
+        g.A = P.T; g.lda = NB; g.B = P.W1; g.ldb = NB; g.C = P.W2; g.ldc = NB;
+      } else {
+        g.ta = 0; g.tb = 0; g.M = m; g.N = P.N; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
+        g.A = Vb; g.lda = ld; g.B = P.W2; g.ldb = NB; g.C = Zs; g.ldc = ld;
+      }
+      break;
+    }
+    case GOP_APPLY_L:  // G = L Z into the W buffer
+      g.ta = 0; g.tb = 0; g.M = P.N; g.N = P.N; g.K = P.N;
+      g.A = P.L; g.lda = ld; g.B = P.Z; g.ldb = ld; g.C = P.W; g.ldc = ld; g.a_tri = 1;
+      break;
+    default:
+      break;
+  }
+  // tiles and split-K: few output tiles and a long K are split along K into
+  // the problem's scratch buffer
+  g.tiles_m = (g.M + BM - 1) / BM;
+  g.tiles_n = (g.N + BN - 1) / BN;
+  g.ntiles = (g.M <= 0 || g.N <= 0) ? 0
+             : (g.c_uplo ? (long)g.tiles_m * (g.tiles_m + 1) / 2 : (long)g.tiles_m * g.tiles_n);
+  g.splits = 1;
+  g.kchunk = g.K;
+  g.part = nullptr;
+  if (g.ntiles > 0 && g.ntiles < 512 && g.K >= 2048 && P.gscr != nullptr) {
+    long splits = (1024 + g.ntiles - 1) / g.ntiles;
+    if (splits > 16) splits = 16;
+    const long maxk = g.K / 512;
+    if (splits > maxk) splits = maxk;
+    while (splits > 1 && (size_t)splits * g.M * g.N * sizeof(double) > P.gscr_bytes) --splits;
+    if (splits > 1) {
+      g.splits = (int)splits;
+      g.kchunk = (int)(((g.K + splits - 1) / splits + BK - 1) / BK * BK);
+      g.part = P.gscr;
+    }
+  }
+  return g;
+}
 
-template <int BM, int BN, bool TA, bool TB>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(GemmParams p) {
-  constexpr int WM = BM / 2, WN = BN / 2;   // sub-tile of one wave
-  constexpr int FM = WM / 16, FN = WN / 16; // MFMA blocks per wave
+namespace {
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ probs, int op, int step,
+                                                       GemmParams single) {
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FM = WM / 16, FN = WN / 16;
   constexpr int AS = BK * (BM + PAD), BS = BK * (BN + PAD);
-  constexpr int EPC = 64;                   // columns per epilogue pass
-  constexpr int CS = EPC * (BM + 1);
-  constexpr int SMEM = cmax(2 * (AS + BS), CS);
+  constexpr int CS = BN * (BM + 1);
+  constexpr int SMEM = (2 * (AS + BS) > CS) ? 2 * (AS + BS) : CS;
   __shared__ double smem[SMEM];
-  // LDS layout: A buffers at [0, 2 AS), B buffers at [2 AS, 2 AS + 2 BS)
 
-  int tile = blockIdx.x, slice = 0;
+  const GemmParams p = probs ? gemm_params(op, probs[blockIdx.z], step) : single;
+  long tile = blockIdx.x;
+  int slice = 0;
+  if (tile >= p.ntiles * p.splits) return;  // uniform: beyond this problem's tiles
   if (p.splits > 1) {
-    slice = tile % p.splits;
+    slice = (int)(tile % p.splits);
     tile /= p.splits;
   }
   int tm, tn;
   if (p.c_uplo) {
     tri_index(tile, tm, tn);
   } else {
-    tm = tile % p.tiles_m;
-    tn = tile / p.tiles_m;
+    tm = (int)(tile % p.tiles_m);
+    tn = (int)(tile / p.tiles_m);
   }
   const int i0 = tm * BM, j0 = tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -101,8 +227,8 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmParams p) {
   constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
   double ra[EA], rb[EB];
   auto load_a = [&](int k0) {
-    if (!TA) {  // A[i + k lda]: BK columns of BM contiguous rows
-      constexpr int TPC = BM / EA;      // threads per column
+    if (!TA) {
+      constexpr int TPC = BM / EA;
       const int kk = tid / TPC, ii = (tid % TPC) * EA;
       const int k = k0 + kk;
 #pragma unroll
@@ -110,7 +236,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmParams p) {
         const int i = i0 + ii + q;
         ra[q] = (i < p.M && k < kend) ? p.A[(long)i + (long)k * p.lda] : 0.0;
       }
-    } else {    // A[k + i lda]: BM columns of BK contiguous rows
+    } else {
       constexpr int TPC = BK / EA;
       const int ii = tid / TPC, kk = (tid % TPC) * EA;
       const int i = i0 + ii;
@@ -136,7 +262,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmParams p) {
     }
   };
   auto load_b = [&](int k0) {
-    if (!TB) {  // B[k + j ldb]: BN columns of BK contiguous rows
+    if (!TB) {
       constexpr int TPC = BK / EB;
       const int jj = tid / TPC, kk = (tid % TPC) * EB;
       const int j = j0 + jj;
@@ -145,7 +271,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmParams p) {
         const int k = k0 + kk + q;
         rb[q] = (j < p.N && k < kend) ? p.B[(long)k + (long)j * p.ldb] : 0.0;
       }
-    } else {    // B[j + k ldb]: BK columns of BN contiguous rows
+    } else {
       constexpr int TPC = BN / EB;
       const int kk = tid / TPC, jj = (tid % TPC) * EB;
       const int k = k0 + kk;
@@ -209,47 +335,45 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmParams p) {
     buf ^= 1;
   }
 
-  // Epilogue through LDS, EPC columns at a time.  In a 16 x 16 f64 block the
-  // entry (i, j) lives in lane 16 (i mod 4) + j, accumulator element i / 4.
+  // Epilogue through LDS.  In a 16 x 16 f64 block the entry (i, j) lives in
+  // lane 16 (i mod 4) + j, accumulator element i / 4.
   double* Cs = smem;  // Cs[c * (BM + 1) + r]
-  const bool split = p.splits > 1;
+  __syncthreads();
 #pragma unroll
-  for (int c0 = 0; c0 < BN; c0 += EPC) {
-    __syncthreads();
-    if (wc * WN >= c0 && wc * WN < c0 + EPC) {
+  for (int a = 0; a < FM; ++a)
 #pragma unroll
-      for (int a = 0; a < FM; ++a)
+    for (int b = 0; b < FN; ++b) {
+      const int cl = wc * WN + b * 16 + (lane & 15);
 #pragma unroll
-        for (int b = 0; b < FN; ++b) {
-          const int cl = wc * WN + b * 16 + (lane & 15) - c0;
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int rl = wr * WM + a * 16 + (lane >> 4) + 4 * v;
-            Cs[cl * (BM + 1) + rl] = acc[a][b][v];
-          }
-        }
-    }
-    __syncthreads();
-    for (int idx = tid; idx < EPC * BM; idx += 256) {
-      const int rl = idx % BM, cl = idx / BM;
-      const int row = i0 + rl, col = j0 + c0 + cl;
-      if (row >= p.M || col >= p.N) continue;
-      if (p.c_uplo == 1 && row < col) continue;
-      if (p.c_uplo == 2 && row <= col) continue;
-      const double val = Cs[cl * (BM + 1) + rl];
-      if (split) {
-        p.part[(long)slice * p.M * p.N + (long)row + (long)col * p.M] = val;
-      } else {
-        double* c = p.C + (long)row + (long)col * p.ldc;
-        const double out = p.alpha * val;
-        *c = (p.beta == 0.0) ? out : out + p.beta * (*c);
+      for (int v = 0; v < 4; ++v) {
+        const int rl = wr * WM + a * 16 + (lane >> 4) + 4 * v;
+        Cs[cl * (BM + 1) + rl] = acc[a][b][v];
       }
+    }
+  __syncthreads();
+  const bool split = p.splits > 1;
+  for (int idx = tid; idx < BN * BM; idx += 256) {
+    const int rl = idx % BM, cl = idx / BM;
+    const int row = i0 + rl, col = j0 + cl;
+    if (row >= p.M || col >= p.N) continue;
+    if (p.c_uplo == 1 && row < col) continue;
+    if (p.c_uplo == 2 && row <= col) continue;
+    const double val = Cs[cl * (BM + 1) + rl];
+    if (split) {
+      p.part[(long)slice * p.M * p.N + (long)row + (long)col * p.M] = val;
+    } else {
+      double* c = p.C + (long)row + (long)col * p.ldc;
+      const double out = p.alpha * val;
+      *c = (p.beta == 0.0) ? out : out + p.beta * (*c);
     }
   }
 }
 
 // C = alpha * sum_s part[s] + beta * C over the (uplo-restricted) M x N
-__global__ __launch_bounds__(256) void k_splitk_reduce(GemmParams p) {
+__global__ __launch_bounds__(256) void k_splitk_reduce(const Prob* __restrict__ probs, int op, int step,
+                                                       GemmParams single) {
+  const GemmParams p = probs ? gemm_params(op, probs[blockIdx.z], step) : single;
+  if (p.splits <= 1) return;
   const long r = (long)blockIdx.x * 64 + (threadIdx.x & 63);
   const long c0 = (long)blockIdx.y * 64 + (threadIdx.x >> 6) * 16;
   if (r >= p.M) return;
@@ -266,77 +390,43 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(GemmParams p) {
   }
 }
 
-template <int BM, int BN>
-void launch(hipStream_t s, bool ta, bool tb, dim3 grid, const GemmParams& p) {
-  if (!ta && !tb) gemm_f64_kernel<BM, BN, false, false><<<grid, 256, 0, s>>>(p);
-  else if (!ta && tb) gemm_f64_kernel<BM, BN, false, true><<<grid, 256, 0, s>>>(p);
-  else if (ta && !tb) gemm_f64_kernel<BM, BN, true, false><<<grid, 256, 0, s>>>(p);
-  else gemm_f64_kernel<BM, BN, true, true><<<grid, 256, 0, s>>>(p);
+void launch(hipStream_t s, bool ta, bool tb, dim3 grid, const Prob* probs, int op, int step,
+            const GemmParams& single) {
+  if (!ta && !tb) gemm_f64_kernel<false, false><<<grid, 256, 0, s>>>(probs, op, step, single);
+  else if (!ta && tb) gemm_f64_kernel<false, true><<<grid, 256, 0, s>>>(probs, op, step, single);
+  else if (ta && !tb) gemm_f64_kernel<true, false><<<grid, 256, 0, s>>>(probs, op, step, single);
+  else gemm_f64_kernel<true, true><<<grid, 256, 0, s>>>(probs, op, step, single);
 }
-
-thread_local double* g_scratch = nullptr;
-thread_local size_t g_scratch_bytes = 0;
 
 }  // namespace
 
-void gemm_set_scratch(double* scratch, size_t bytes) {
-  g_scratch = scratch;
-  g_scratch_bytes = bytes;
-}
-
-int gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
-             long lda, const double* B, long ldb, double beta, double* C, long ldc, int c_uplo,
-             int a_tri, int b_tri) {
-  if (M <= 0 || N <= 0) return 0;
-  if (c_uplo && M != N)
-    return set_hip_error(hipErrorInvalidValue, "gemm: triangular C must be square", __FILE__, __LINE__);
-  GemmParams p;
-  p.M = M;
-  p.N = N;
-  p.K = K < 0 ? 0 : K;
-  p.A = A;
-  p.lda = lda;
-  p.B = B;
-  p.ldb = ldb;
-  p.C = C;
-  p.ldc = ldc;
-  p.alpha = alpha;
-  p.beta = beta;
-  p.c_uplo = c_uplo;
-  p.a_tri = a_tri;
-  p.b_tri = b_tri;
-  p.splits = 1;
-  p.kchunk = p.K;
-  p.part = nullptr;
-  // large, compute-bound products use 128 x 128 tiles
-  const long t128 = (long)((M + 127) / 128) * ((N + 127) / 128);
-  // (measured on gfx950: at one wave per SIMD the 128 x 128 tile is slower than
-  // 64 x 64 at four, so it is only selected when BSE_GEMM128 is set)
-  static const bool allow128 = getenv("BSE_GEMM128") != nullptr;
-  const bool big = allow128 && M >= 256 && N >= 256 && K >= 256 && (c_uplo ? t128 / 2 : t128) >= 512;
-  const int BMs = big ? 128 : 64;
-  p.tiles_m = (M + BMs - 1) / BMs;
-  p.tiles_n = (N + BMs - 1) / BMs;
-  long ntiles = c_uplo ? (long)p.tiles_m * (p.tiles_m + 1) / 2 : (long)p.tiles_m * p.tiles_n;
-  // few output tiles and a long K: split K (partials in the scratch buffer)
-  if (!big && ntiles < 512 && p.K >= 2048 && g_scratch != nullptr) {
-    int splits = (int)((1024 + ntiles - 1) / ntiles);
-    splits = splits > 16 ? 16 : splits;
-    const int maxk = p.K / 512;
-    splits = splits > maxk ? maxk : splits;
-    while (splits > 1 && (size_t)splits * M * N * sizeof(double) > g_scratch_bytes) --splits;
-    if (splits > 1) {
-      p.splits = splits;
-      p.kchunk = round_up((p.K + splits - 1) / splits, BK);
-      p.part = g_scratch;
+int gemm_batched(hipStream_t s, const Batch& b, int nact, int op, int step) {
+  if (nact <= 0) return 0;
+  long maxwg = 0, maxm = 0, maxn = 0;
+  bool any_split = false;
+  int ta = -1, tb = -1;
+  for (int i = 0; i < nact; ++i) {
+    const GemmParams g = gemm_params(op, b.host[i], step);
+    if (g.ntiles <= 0) continue;
+    if (ta < 0) {
+      ta = g.ta;
+      tb = g.tb;
+    }
+    const long wg = g.ntiles * g.splits;
+    if (wg > maxwg) maxwg = wg;
+    if (g.splits > 1) {
+      any_split = true;
+      if (g.M > maxm) maxm = g.M;
+      if (g.N > maxn) maxn = g.N;
     }
   }
-  const dim3 grid((unsigned)(ntiles * p.splits));
-  if (big) launch<128, 128>(s, ta, tb, grid, p);
-  else launch<64, 64>(s, ta, tb, grid, p);
+  if (maxwg == 0) return 0;
+  GemmParams dummy{};
+  launch(s, ta != 0, tb != 0, dim3((unsigned)maxwg, 1, (unsigned)nact), b.dev, op, step, dummy);
   BSE_LAUNCHED();
-  if (p.splits > 1) {
-    k_splitk_reduce<<<dim3((unsigned)((M + 63) / 64), (unsigned)((N + 63) / 64)), 256, 0, s>>>(p);
+  if (any_split) {
+    k_splitk_reduce<<<dim3((unsigned)((maxm + 63) / 64), (unsigned)((maxn + 63) / 64), (unsigned)nact), 256, 0, s>>>(
+        b.dev, op, step, dummy);
     BSE_LAUNCHED();
   }
   return 0;

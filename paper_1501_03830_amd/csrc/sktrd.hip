@@ -23,6 +23,8 @@
 //   sk_update reduces the partials into p, applies the panel corrections,
 //             brings the next column up to date, and the last workgroup to
 //             finish computes the next reflector (dlarfg convention).
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -59,10 +61,14 @@ __device__ inline void larfg(double x0, double xnorm, double& beta, double& tau,
 }
 
 // Reflector of column j from the (already up to date) column itself.
-__global__ __launch_bounds__(256) void sk_start(const double* __restrict__ W, long ld, int N, int j,
-                                                Ctrl* __restrict__ ctrl, double* __restrict__ alpha,
-                                                double* __restrict__ tau) {
+__global__ __launch_bounds__(256) void sk_start(const Prob* __restrict__ probs, int j) {
   __shared__ double red[4];
+  const Prob& P = probs[blockIdx.z];
+  const int N = P.N;
+  if (j > N - 2) return;  // uniform
+  const double* __restrict__ W = P.W;
+  const long ld = P.ld;
+  Ctrl* __restrict__ ctrl = static_cast<Ctrl*>(P.ctrl);
   double ss = 0.0;
   for (long r = j + 2 + threadIdx.x; r < N; r += 256) {
     const double v = W[r + (long)j * ld];
@@ -75,9 +81,18 @@ __global__ __launch_bounds__(256) void sk_start(const double* __restrict__ W, lo
     larfg(x0, sqrt(ss), beta, t, sc);
     ctrl->tau = t;
     ctrl->scale = sc;
-    alpha[j] = -beta;
-    tau[j] = t;
+    P.alpha[j] = -beta;
+    P.tau[j] = t;
   }
+}
+
+// Row tiles per strip workgroup of the matvec for a trailing matrix of nblk
+// row blocks: about 4096 workgroups per problem.  It depends on the problem
+// alone, so a problem's summation order -- and its result -- is the same
+// whether it is solved alone or inside a batch.
+__host__ __device__ inline int symv_tiles(int nblk) {
+  const long T = (long)nblk * (nblk + 1) / 2 / 4096;
+  return T < 1 ? 1 : (T > TMAX ? TMAX : (int)T);
 }
 
 __device__ inline double vval(const double* __restrict__ W, long ld, int j, int s, int N, double scale, long r) {
@@ -98,14 +113,25 @@ __device__ inline double vval(const double* __restrict__ W, long ld, int j, int 
 // blockIdx.y == 0 (dispatched first): workgroups (d, g) store v_i for row
 //   blocks d*16 .. d*16+15 and their share of the panel dot products V^T v,
 //   P^T v (summed by the update kernel).
-__global__ __launch_bounds__(256) void sk_symv(const double* __restrict__ W, long ld, int N, int j,
-                                               int i, int nblk, int R0, int T, int nchunk,
-                                               Ctrl* __restrict__ ctrl, double* __restrict__ Y1,
-                                               double* __restrict__ Y2, long ldy, double* __restrict__ Yrow,
-                                               double* __restrict__ Ycol, double* __restrict__ dotpart,
-                                               int dstride) {
+__global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, int j, int i) {
   __shared__ double rsum[TMAX][4][TS];   // per-wave row sums of every tile
+  const Prob& P = probs[blockIdx.z];
+  const int N = P.N;
+  if (j >= N - 2) return;  // uniform: this problem is already reduced
   const int s = j + 1;
+  const int R0 = s / TS;
+  const int nblk = (N - 1) / TS - R0 + 1;
+  const int T = symv_tiles(nblk);
+  const int nchunk = (nblk + T - 1) / T;
+  const long ld = P.ld, ldy = P.ld;
+  const int dstride = (int)(ld / TS);
+  const double* __restrict__ W = P.W;
+  const Ctrl* __restrict__ ctrl = static_cast<const Ctrl*>(P.ctrl);
+  double* __restrict__ Y1 = P.Y1;
+  double* __restrict__ Y2 = P.Y2;
+  double* __restrict__ Yrow = P.Yrow;
+  double* __restrict__ Ycol = P.Ycol;
+  double* __restrict__ dotpart = P.dotpart;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const double scale = ctrl->scale;
 
@@ -237,15 +263,7 @@ __global__ __launch_bounds__(256) void sk_symv(const double* __restrict__ W, lon
 // p_i = tau (S v + V c_P - P c_V) for the rows of block b, the in-place store
 // of v_i, the update of the next column and, in the last workgroup, its
 // reflector.  The panel sums over l are split over the four wavefronts.
-__global__ __launch_bounds__(256) void sk_update(double* __restrict__ W, long ld, int N, int j, int i,
-                                                 int nbp, int nblk, int R0, int T, int nchunk,
-                                                 Ctrl* __restrict__ ctrl, double* __restrict__ Y1,
-                                                 double* __restrict__ Y2, long ldy,
-                                                 const double* __restrict__ Yrow,
-                                                 const double* __restrict__ Ycol,
-                                                 double* __restrict__ normpart, double* __restrict__ alpha,
-                                                 double* __restrict__ tau_arr,
-                                                 const double* __restrict__ dotpart, int dstride) {
+__global__ __launch_bounds__(256) void sk_update(const Prob* __restrict__ probs, int j, int i) {
   __shared__ double cs[2 * NBMAX];
   __shared__ double ys_row[2 * NBMAX];   // Y1 row s (v_l[s], p_l[s])
   __shared__ double red[4][TS];
@@ -254,8 +272,30 @@ __global__ __launch_bounds__(256) void sk_update(double* __restrict__ W, long ld
   __shared__ double red4[4];
   __shared__ double sval_s;
   __shared__ int last_flag;
-  const int b = blockIdx.x;
+  const Prob& P = probs[blockIdx.z];
+  const int N = P.N;
+  if (j >= N - 2) return;  // uniform
   const int s = j + 1;
+  const int R0 = s / TS;
+  const int nblk = (N - 1) / TS - R0 + 1;
+  const int b = blockIdx.x;
+  if (b >= nblk) return;  // uniform: beyond this problem's row blocks
+  const int T = symv_tiles(nblk);
+  const int nchunk = (nblk + T - 1) / T;
+  const int k0 = j - i;   // first column of the panel
+  const int nbp = min(NBMAX, N - 1 - k0);
+  const long ld = P.ld, ldy = P.ld;
+  const int dstride = (int)(ld / TS);
+  double* __restrict__ W = P.W;
+  Ctrl* __restrict__ ctrl = static_cast<Ctrl*>(P.ctrl);
+  double* __restrict__ Y1 = P.Y1;
+  double* __restrict__ Y2 = P.Y2;
+  const double* __restrict__ Yrow = P.Yrow;
+  const double* __restrict__ Ycol = P.Ycol;
+  double* __restrict__ normpart = P.normpart;
+  double* __restrict__ alpha = P.alpha;
+  double* __restrict__ tau_arr = P.tau;
+  const double* __restrict__ dotpart = P.dotpart;
   const int tid = threadIdx.x;
   const int t = tid & 63, part = tid >> 6;
   const double tau = ctrl->tau;
@@ -383,7 +423,8 @@ __global__ __launch_bounds__(256) void sk_update(double* __restrict__ W, long ld
   }
 }
 
-__global__ void k_zero_ctrl(Ctrl* ctrl) {
+__global__ void k_zero_ctrl(const Prob* __restrict__ probs) {
+  Ctrl* ctrl = static_cast<Ctrl*>(probs[blockIdx.z].ctrl);
   if (threadIdx.x == 0) {
     ctrl->cnt_diag = 0u;
     ctrl->cnt_upd = 0u;
@@ -392,7 +433,7 @@ __global__ void k_zero_ctrl(Ctrl* ctrl) {
 
 }  // namespace
 
-size_t sktrd_work_bytes(long N, long ld, int nb) {
+size_t sktrd_work_bytes(long N, long ld) {
   (void)N;
   const long nt = ld / TS;
   size_t bytes = 0;
@@ -400,79 +441,70 @@ size_t sktrd_work_bytes(long N, long ld, int nb) {
   bytes += 2 * (size_t)nt * nt * TS * sizeof(double);             // Yrow, Ycol
   bytes += (size_t)nt * 2 * NBMAX * sizeof(double);               // dotpart
   bytes += (size_t)nt * sizeof(double);                           // normpart
-  bytes += 4096;                                                  // ctrl
-  (void)nb;
-  return bytes + 8 * 256;
+  bytes += sizeof(Ctrl);                                          // ctrl
+  return bytes + 7 * 256;
 }
 
-int sktrd_bind_work(void* base, long N, long ld, int nb, SktrdWork* w) {
+void sktrd_bind_work(char* base, long N, long ld, Prob* P) {
   (void)N;
-  if (nb < 1 || nb > NBMAX) nb = NBMAX;
   const long nt = ld / TS;
-  char* p = static_cast<char*>(base);
+  char* p = base;
   auto take = [&](size_t bytes) {
     char* q = p;
     p += round_up((long)bytes, 256);
     return q;
   };
-  w->Y1 = reinterpret_cast<double*>(take((size_t)ld * 2 * NBMAX * sizeof(double)));
-  w->Y2 = reinterpret_cast<double*>(take((size_t)ld * 2 * NBMAX * sizeof(double)));
-  w->Yrow = reinterpret_cast<double*>(take((size_t)nt * nt * TS * sizeof(double)));
-  w->Ycol = reinterpret_cast<double*>(take((size_t)nt * nt * TS * sizeof(double)));
-  w->dotpart = reinterpret_cast<double*>(take((size_t)nt * 2 * NBMAX * sizeof(double)));
-  w->normpart = reinterpret_cast<double*>(take((size_t)nt * sizeof(double)));
-  w->ctrl = take(sizeof(Ctrl));
-  w->nb = nb;
-  return 0;
+  P->Y1 = reinterpret_cast<double*>(take((size_t)ld * 2 * NBMAX * sizeof(double)));
+  P->Y2 = reinterpret_cast<double*>(take((size_t)ld * 2 * NBMAX * sizeof(double)));
+  P->Yrow = reinterpret_cast<double*>(take((size_t)nt * nt * TS * sizeof(double)));
+  P->Ycol = reinterpret_cast<double*>(take((size_t)nt * nt * TS * sizeof(double)));
+  P->dotpart = reinterpret_cast<double*>(take((size_t)nt * 2 * NBMAX * sizeof(double)));
+  P->normpart = reinterpret_cast<double*>(take((size_t)nt * sizeof(double)));
+  P->ctrl = take(sizeof(Ctrl));
 }
 
-int sktrd_f64(hipStream_t s, int N, double* W, long ld, double* alpha, double* tau, const SktrdWork& w,
-              KernelTimer* timer) {
-  if (N < 2) return 0;
-  Ctrl* ctrl = static_cast<Ctrl*>(w.ctrl);
-  const long ldy = ld;
-  k_zero_ctrl<<<1, 64, 0, s>>>(ctrl);
+int sktrd_batched(hipStream_t s, const Batch& b, KernelTimer* timer) {
+  const int N0 = b.maxN();
+  if (N0 < 2) return 0;
+  k_zero_ctrl<<<dim3(1, 1, (unsigned)b.count), 64, 0, s>>>(b.dev);
   BSE_LAUNCHED();
-  const int nb = w.nb;
-  for (int k0 = 0; k0 <= N - 2; k0 += nb) {
-    const int nbp = (N - 1 - k0 < nb) ? (N - 1 - k0) : nb;
-    sk_start<<<1, 256, 0, s>>>(W, ld, N, k0, ctrl, alpha, tau);
+  const int nb = NBMAX;
+  for (int k0 = 0; k0 <= N0 - 2; k0 += nb) {
+    const int nstart = b.active_N_above(k0 + 1);   // N - 2 >= k0
+    sk_start<<<dim3(1, 1, (unsigned)nstart), 256, 0, s>>>(b.dev, k0);
     BSE_LAUNCHED();
-    for (int i = 0; i < nbp; ++i) {
+    for (int i = 0; i < nb; ++i) {
       const int j = k0 + i;
-      if (j >= N - 2) break;  // the last column has no reflector to apply
+      if (j >= N0 - 2) break;  // the last column has no reflector to apply
+      const int nact = b.active_N_above(j + 2);   // problems with j < N - 2
       const int sidx = j + 1;
       const int R0 = sidx / TS;
-      const int nblk = (N - 1) / TS - R0 + 1;
-      const long ntiles = (long)nblk * (nblk + 1) / 2;
-      // tiles per workgroup: keep about 4096 workgroups in flight
-      int T = (int)(ntiles / 4096);
-      T = T < 1 ? 1 : (T > TMAX ? TMAX : T);
-      const int nchunk = (nblk + T - 1) / T;
+      const int nblk0 = (N0 - 1) / TS - R0 + 1;
+      // strip chunks: the largest count over the active problems
+      int nchunk0 = 1;
+      for (int q = 0; q < nact; ++q) {
+        const int nbq = (b.host[q].N - 1) / TS - R0 + 1;
+        const int T = symv_tiles(nbq);
+        nchunk0 = std::max(nchunk0, (nbq + T - 1) / T);
+      }
       const bool timed = timer && timer->used + 2 <= timer->cap;
       if (timed) BSE_HIP(hipEventRecord(timer->ev[timer->used], s));
-      const int nduty = 4 * ((nblk + DUTY_BLK - 1) / DUTY_BLK);
-      const unsigned gx = (unsigned)(nblk > nduty ? nblk : nduty);
-      sk_symv<<<dim3(gx, (unsigned)(nchunk + 1)), 256, 0, s>>>(
-          W, ld, N, j, i, nblk, R0, T, nchunk, ctrl, w.Y1, w.Y2, ldy, w.Yrow, w.Ycol, w.dotpart, (int)(ld / TS));
+      const int nduty = 4 * ((nblk0 + DUTY_BLK - 1) / DUTY_BLK);
+      const unsigned gx = (unsigned)(nblk0 > nduty ? nblk0 : nduty);
+      sk_symv<<<dim3(gx, (unsigned)(nchunk0 + 1), (unsigned)nact), 256, 0, s>>>(b.dev, j, i);
       BSE_LAUNCHED();
       if (timed) {
         BSE_HIP(hipEventRecord(timer->ev[timer->used + 1], s));
         timer->used += 2;
-        const double m = (double)(N - sidx);   // trailing order
-        timer->bytes += 8.0 * m * (m - 1.0) * 0.5;
+        for (int q = 0; q < nact; ++q) {
+          const double m = (double)(b.host[q].N - sidx);   // trailing order
+          timer->bytes += 8.0 * m * (m - 1.0) * 0.5;
+        }
       }
-      sk_update<<<(unsigned)nblk, 256, 0, s>>>(W, ld, N, j, i, nbp, nblk, R0, T, nchunk, ctrl, w.Y1, w.Y2,
-                                               ldy, w.Yrow, w.Ycol, w.normpart, alpha, tau, w.dotpart,
-                                               (int)(ld / TS));
+      sk_update<<<dim3((unsigned)nblk0, 1, (unsigned)nact), 256, 0, s>>>(b.dev, j, i);
       BSE_LAUNCHED();
     }
-    const int e = k0 + nbp;
-    const int m2 = N - e;
-    if (m2 >= 2 && e <= N - 2) {
-      BSE_TRY(gemm_f64(s, false, true, m2, m2, 2 * nbp, 1.0, w.Y1 + e, ldy, w.Y2 + e, ldy, 1.0,
-                       W + e + (long)e * ld, ld, 2, 0, 0));
-    }
+    BSE_TRY(gemm_batched(s, b, nstart, GOP_SKTRD_R2K, k0));
   }
   return 0;
 }

@@ -1,9 +1,16 @@
 // Solver driver and C ABI: stage sequencing, workspace layout, argument
 // checking and timing for the chain of Algorithm 1 / Algorithm 3.
+//
+// Every solve runs as a batch: one descriptor (Prob) per problem, sorted by
+// decreasing order, uploaded once, and one launch per step of the chain for
+// all problems that still have work at that step.  bse_solve is a batch of
+// one; bse_solve_batched hands many independent problems of uneven sizes to
+// the same kernels.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <mutex>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -21,6 +28,9 @@ struct bse_ctx {
   bool events = false;
   bool timing = false;               // per-launch timing of the skew matvec
   std::vector<hipEvent_t> kev;       // event pool for it
+  bse::Prob* hprobs = nullptr;       // pinned host mirror of the descriptors
+  int* hinfo = nullptr;              // pinned host copy of the info words
+  int hcap = 0;
 };
 
 namespace bse {
@@ -51,8 +61,16 @@ static int set_error(int code, const char* msg) {
   return code;
 }
 
+static int set_errorf(int code, const char* fmt, int i) {
+  char buf[256];
+  snprintf(buf, sizeof(buf), fmt, i);
+  g_last_error = buf;
+  return code;
+}
+
 // ------------------------------------------------------------------------
-// Workspace layout for one solve of order n (N = 2n), FP64.
+// Workspace layout of one problem of order N = 2n, FP64, relative to the
+// start of its block.
 // ------------------------------------------------------------------------
 struct Plan {
   long N = 0, n = 0, ld = 0;
@@ -60,7 +78,6 @@ struct Plan {
          off_bt = 0, off_linv = 0, off_gscr = 0;
   size_t gscr_bytes = 0;
   size_t total = 0;
-  int nb = 64, nbq = 64;
 };
 
 static Plan make_plan(long N) {
@@ -82,42 +99,45 @@ static Plan make_plan(long N) {
   // inverse iteration factors (4 double arrays + 1 byte array, N x n each);
   // later reused for the n x n Gram matrix of the reorthogonalisation
   p.off_inv = take((size_t)4 * N * p.n * sizeof(double) + (size_t)N * p.n + 256);
-  p.off_small = take((size_t)(4 * p.ld + 3 * p.n + 64) * sizeof(double));
-  p.off_sk = take(sktrd_work_bytes(N, p.ld, p.nb));
-  p.off_bt = take(backtr_work_bytes(N, p.ld, p.nbq));
+  // alpha, tau, e2 (ld each), shift (n), scal (16), cid (n ints)
+  p.off_small = take((size_t)(3 * p.ld + p.n + 16) * sizeof(double) + (size_t)p.n * sizeof(int));
+  p.off_sk = take(sktrd_work_bytes(N, p.ld));
+  p.off_bt = take(backtr_work_bytes(N, p.ld));
   p.off_linv = take(64 * 64 * sizeof(double));
-  p.gscr_bytes = (size_t)16 * 64 * p.ld * sizeof(double);   // split-K partials
-  p.off_gscr = take(p.gscr_bytes);
+  // split-K partial products: only products of large problems are split
+  p.gscr_bytes = (N > 2048) ? (size_t)16 * 64 * p.ld * sizeof(double) : 0;
+  if (p.gscr_bytes) p.off_gscr = take(p.gscr_bytes);
   p.total = cur;
   return p;
 }
 
-struct Bufs {
-  double *L, *W, *Z, *Vt, *inv, *alpha, *tau, *e2, *scal, *shift, *lam_tmp, *linv;
-  int *cid, *info;
-  SktrdWork sk;
-  BacktrWork bt;
-};
+// Descriptor array and info words at the start of the workspace.
+static size_t header_bytes(int count) {
+  return (size_t)round_up((long)(count * sizeof(Prob)), 256) + (size_t)round_up((long)(count * 2 * sizeof(int)), 256);
+}
 
-static void bind(const Plan& p, char* base, Bufs* b) {
-  b->L = reinterpret_cast<double*>(base + p.off_L);
-  b->W = reinterpret_cast<double*>(base + p.off_W);
-  b->Z = reinterpret_cast<double*>(base + p.off_Z);
-  b->Vt = reinterpret_cast<double*>(base + p.off_Vt);
-  b->inv = reinterpret_cast<double*>(base + p.off_inv);
+// Workspace pointers of one problem.
+static void bind_problem(const Plan& p, char* base, Prob* P) {
+  P->n = (int)p.n;
+  P->N = (int)p.N;
+  P->ld = p.ld;
+  P->L = reinterpret_cast<double*>(base + p.off_L);
+  P->W = reinterpret_cast<double*>(base + p.off_W);
+  P->Z = reinterpret_cast<double*>(base + p.off_Z);
+  P->Vt = reinterpret_cast<double*>(base + p.off_Vt);
+  P->inv = reinterpret_cast<double*>(base + p.off_inv);
   double* sm = reinterpret_cast<double*>(base + p.off_small);
-  b->alpha = sm;
-  b->tau = sm + p.ld;
-  b->e2 = sm + 2 * p.ld;
-  b->lam_tmp = sm + 3 * p.ld;
-  b->shift = sm + 4 * p.ld;
-  b->scal = sm + 4 * p.ld + p.n;
-  b->cid = reinterpret_cast<int*>(sm + 4 * p.ld + p.n + 16);
-  b->info = reinterpret_cast<int*>(sm + 4 * p.ld + 3 * p.n + 32);
-  b->linv = reinterpret_cast<double*>(base + p.off_linv);
-  gemm_set_scratch(reinterpret_cast<double*>(base + p.off_gscr), p.gscr_bytes);
-  sktrd_bind_work(base + p.off_sk, p.N, p.ld, p.nb, &b->sk);
-  backtr_bind_work(base + p.off_bt, p.N, p.ld, p.nbq, &b->bt);
+  P->alpha = sm;
+  P->tau = sm + p.ld;
+  P->e2 = sm + 2 * p.ld;
+  P->shift = sm + 3 * p.ld;
+  P->scal = sm + 3 * p.ld + p.n;
+  P->cid = reinterpret_cast<int*>(sm + 3 * p.ld + p.n + 16);
+  P->linv = reinterpret_cast<double*>(base + p.off_linv);
+  P->gscr = p.gscr_bytes ? reinterpret_cast<double*>(base + p.off_gscr) : nullptr;
+  P->gscr_bytes = p.gscr_bytes;
+  sktrd_bind_work(base + p.off_sk, p.N, p.ld, P);
+  backtr_bind_work(base + p.off_bt, p.N, p.ld, P);
 }
 
 static int get_workspace(bse_ctx* ctx, size_t bytes, char** base) {
@@ -133,10 +153,33 @@ static int get_workspace(bse_ctx* ctx, size_t bytes, char** base) {
       ctx->own = nullptr;
       ctx->own_bytes = 0;
     }
-    BSE_HIP(hipMalloc(&ctx->own, bytes));
+    hipError_t e = hipMalloc(&ctx->own, bytes);
+    if (e != hipSuccess) {
+      ctx->own = nullptr;
+      (void)hipGetLastError();
+      if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return set_error(BSE_ENOMEM, "device workspace allocation failed");
+      return set_hip_error(e, "hipMalloc", __FILE__, __LINE__);
+    }
     ctx->own_bytes = bytes;
   }
   *base = static_cast<char*>(ctx->own);
+  return 0;
+}
+
+// Pinned host mirror for `count` descriptors (the context's stream is idle
+// between calls, so the old buffer can be released).
+static int ensure_host(bse_ctx* ctx, int count) {
+  if (ctx->hcap >= count) return 0;
+  if (ctx->hprobs) BSE_HIP(hipHostFree(ctx->hprobs));
+  if (ctx->hinfo) BSE_HIP(hipHostFree(ctx->hinfo));
+  ctx->hprobs = nullptr;
+  ctx->hinfo = nullptr;
+  ctx->hcap = 0;
+  const int cap = std::max(count, 16);
+  BSE_HIP(hipHostMalloc(reinterpret_cast<void**>(&ctx->hprobs), cap * sizeof(Prob), hipHostMallocDefault));
+  BSE_HIP(hipHostMalloc(reinterpret_cast<void**>(&ctx->hinfo), cap * 2 * sizeof(int), hipHostMallocDefault));
+  ctx->hcap = cap;
   return 0;
 }
 
@@ -152,41 +195,89 @@ static int mark(bse_ctx* ctx, bool timed, int i) {
   return 0;
 }
 
-static int read_info(bse_ctx* ctx, const int* info_dev, int* info) {
-  BSE_HIP(hipMemcpyAsync(info, info_dev, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+// A batch being set up: workspace, descriptor storage, original order.
+struct Setup {
+  char* base = nullptr;
+  Prob* dprobs = nullptr;   // device descriptors
+  int* dinfo = nullptr;     // device info words, 2 per problem (original order)
+  size_t total = 0;
+};
+
+// Workspace for problems of orders N[0..count) (any order); descriptors are
+// bound in the order given.
+static int setup_batch(bse_ctx* ctx, int count, const long* Ns, Setup* S) {
+  BSE_TRY(ensure_host(ctx, count));
+  size_t total = header_bytes(count);
+  std::vector<Plan> plans(count);
+  for (int i = 0; i < count; ++i) {
+    plans[i] = make_plan(Ns[i]);
+    total += plans[i].total;
+  }
+  BSE_TRY(get_workspace(ctx, total, &S->base));
+  S->total = total;
+  S->dprobs = reinterpret_cast<Prob*>(S->base);
+  S->dinfo = reinterpret_cast<int*>(S->base + round_up((long)(count * sizeof(Prob)), 256));
+  size_t off = header_bytes(count);
+  for (int i = 0; i < count; ++i) {
+    Prob& P = ctx->hprobs[i];
+    memset(&P, 0, sizeof(P));
+    bind_problem(plans[i], S->base + off, &P);
+    P.info = S->dinfo + 2 * i;
+    off += plans[i].total;
+  }
+  return 0;
+}
+
+static int upload(bse_ctx* ctx, const Setup& S, int count) {
+  BSE_HIP(hipMemcpyAsync(S.dprobs, ctx->hprobs, count * sizeof(Prob), hipMemcpyHostToDevice, ctx->stream));
+  return 0;
+}
+
+static int read_infos(bse_ctx* ctx, const Setup& S, int count) {
+  BSE_HIP(hipMemcpyAsync(ctx->hinfo, S.dinfo, count * 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   BSE_HIP(hipStreamSynchronize(ctx->stream));
   return 0;
 }
 
-// The chain for one problem.  lambda: device n doubles.  X: device complex
-// 2n x n (ldx in complex elements) or NULL.
-static int solve_fp64(bse_ctx* ctx, int n, const double* A, long lda, const double* B, long ldb,
-                      unsigned flags, double* lambda, double* X, long ldx, const double* dr,
-                      const double* dl, double* w, bse_report* rep) {
-  const long N = 2L * n;
-  const Plan p = make_plan(N);
-  char* base = nullptr;
-  BSE_TRY(get_workspace(ctx, p.total, &base));
-  Bufs b;
-  bind(p, base, &b);
+// The chain for a batch whose descriptors (sorted by decreasing N) are in
+// ctx->hprobs[0..count).  On return ctx->hinfo holds, per original slot,
+// info[0] (Cholesky of M, > 0 = not definite) and info[1] (Cholesky of a
+// cluster Gram matrix, > 0 = reorthogonalisation failed).
+static int run_chain(bse_ctx* ctx, const Setup& S, int count, bool vectors, bse_report* rep) {
   hipStream_t s = ctx->stream;
   const bool timed = rep != nullptr;
   if (timed) BSE_TRY(ensure_events(ctx));
-  const bool vectors = (flags & BSE_WANT_VECTORS) != 0 && X != nullptr;
+  BSE_TRY(upload(ctx, S, count));
+  Batch b;
+  b.count = count;
+  b.host = ctx->hprobs;
+  b.dev = S.dprobs;
 
   BSE_TRY(mark(ctx, timed, 0));
-  BSE_TRY(launch_build_M(s, n, A, lda, B, ldb, b.L, p.ld));
+  BSE_TRY(build_M_batched(s, b));
   BSE_TRY(mark(ctx, timed, 1));
-  BSE_TRY(potrf_f64(s, (int)N, b.L, p.ld, b.info, b.linv));
+  BSE_TRY(potrf_batched(s, b, 0, true));
   BSE_TRY(mark(ctx, timed, 2));
-  int info = 0;
-  BSE_TRY(read_info(ctx, b.info, &info));
-  if (info != 0) return info;
-  BSE_TRY(form_W(s, (int)N, b.L, p.ld, b.W, p.ld, false));
+  BSE_TRY(read_infos(ctx, S, count));
+  // drop the problems whose M is not definite; the rest keep their order
+  int live = 0;
+  for (int i = 0; i < count; ++i) {
+    const Prob& P = ctx->hprobs[i];
+    if (ctx->hinfo[P.info - S.dinfo] == 0) {
+      if (live != i) ctx->hprobs[live] = P;
+      ++live;
+    }
+  }
+  if (live < count) {
+    b.count = live;
+    if (live > 0) BSE_TRY(upload(ctx, S, live));
+  }
+  BSE_TRY(form_W_batched(s, b, false));
   BSE_TRY(mark(ctx, timed, 3));
   KernelTimer ktimer;
-  if (ctx->timing) {
-    const size_t need = 2 * (size_t)(N > 2 ? N - 2 : 0);
+  if (ctx->timing && b.count > 0) {
+    const long N0 = b.maxN();
+    const size_t need = 2 * (size_t)(N0 > 2 ? N0 - 2 : 0);
     while (ctx->kev.size() < need) {
       hipEvent_t e;
       BSE_HIP(hipEventCreate(&e));
@@ -195,35 +286,25 @@ static int solve_fp64(bse_ctx* ctx, int n, const double* A, long lda, const doub
     ktimer.ev = ctx->kev.data();
     ktimer.cap = (int)ctx->kev.size();
   }
-  BSE_TRY(sktrd_f64(s, (int)N, b.W, p.ld, b.alpha, b.tau, b.sk, ctx->timing ? &ktimer : nullptr));
+  BSE_TRY(sktrd_batched(s, b, ctx->timing ? &ktimer : nullptr));
   BSE_TRY(mark(ctx, timed, 4));
-  BSE_TRY(tridiag_bisect(s, (int)N, b.alpha, b.e2, b.scal, lambda));
+  BSE_TRY(bisect_batched(s, b));
   BSE_TRY(mark(ctx, timed, 5));
   if (vectors) {
-    BSE_TRY(tridiag_invit(s, (int)N, b.alpha, b.scal, lambda, b.shift, b.inv, b.Vt));
+    BSE_TRY(invit_batched(s, b));
     BSE_TRY(mark(ctx, timed, 6));
-    BSE_TRY(tridiag_reorth(s, (int)N, lambda, b.scal, b.Vt, b.inv, b.cid, b.info, b.linv));
+    BSE_TRY(reorth_batched(s, b));
     BSE_TRY(mark(ctx, timed, 7));
-    BSE_TRY(scatter_DV(s, (int)N, b.Vt, b.Z, p.ld));
-    BSE_TRY(apply_U(s, (int)N, b.W, p.ld, b.tau, b.Z, p.ld, (int)N, b.bt));
+    BSE_TRY(apply_UD_batched(s, b));
     BSE_TRY(mark(ctx, timed, 8));
-    // G = L Z into the W buffer (the reflectors are no longer needed)
-    BSE_TRY(gemm_f64(s, false, false, (int)N, (int)N, (int)N, 1.0, b.L, p.ld, b.Z, p.ld, 0.0, b.W, p.ld, 0,
-                     1, 0));
+    BSE_TRY(gemm_batched(s, b, b.count, GOP_APPLY_L, 0));
     BSE_TRY(mark(ctx, timed, 9));
-    BSE_TRY(finish_X(s, n, b.W, p.ld, lambda, X, ldx));
-    const bool weights = (flags & BSE_WANT_WEIGHTS) != 0 && dr != nullptr && w != nullptr;
-    BSE_TRY(phase_and_weights(s, n, X, ldx, weights ? dr : nullptr, weights ? (dl ? dl : dr) : nullptr,
-                              weights ? w : nullptr));
+    BSE_TRY(finish_batched(s, b));
   } else {
     for (int i = 6; i <= 9; ++i) BSE_TRY(mark(ctx, timed, i));
   }
   BSE_TRY(mark(ctx, timed, 10));
-  BSE_HIP(hipStreamSynchronize(s));
-  if (vectors) {
-    BSE_TRY(read_info(ctx, b.info, &info));
-    if (info != 0) return set_error(BSE_EDEVICE, "cluster Gram matrix not positive definite");
-  }
+  BSE_TRY(read_infos(ctx, S, count));
   if (timed) {
     memset(rep, 0, sizeof(*rep));
     float ms = 0.f;
@@ -233,9 +314,8 @@ static int solve_fp64(bse_ctx* ctx, int n, const double* A, long lda, const doub
     }
     BSE_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[BSE_NUM_STAGES]));
     rep->total_ms = ms;
-    rep->n = n;
     rep->prec = BSE_PREC_FP64;
-    rep->workspace_bytes = p.total;
+    rep->workspace_bytes = S.total;
     if (ctx->timing) {
       double tot = 0.0;
       for (int i = 0; i + 1 < ktimer.used; i += 2) {
@@ -256,13 +336,27 @@ static int prologue(bse_ctx* ctx) {
   return 0;
 }
 
+// One problem of order N for the stage entry points.
+static int setup_single(bse_ctx* ctx, long N, Setup* S) {
+  BSE_TRY(setup_batch(ctx, 1, &N, S));
+  return 0;
+}
+
+static Batch single_batch(bse_ctx* ctx, const Setup& S) {
+  Batch b;
+  b.count = 1;
+  b.host = ctx->hprobs;
+  b.dev = S.dprobs;
+  return b;
+}
+
 }  // namespace bse
 
 using namespace bse;
 
 extern "C" {
 
-int bse_version(void) { return 100; }
+int bse_version(void) { return 10100; }
 
 const char* bse_last_error(void) { return g_last_error.c_str(); }
 
@@ -292,6 +386,8 @@ int bse_ctx_destroy(bse_ctx* ctx) {
   if (ctx->events)
     for (int i = 0; i <= BSE_NUM_STAGES; ++i) (void)hipEventDestroy(ctx->ev[i]);
   for (hipEvent_t e : ctx->kev) (void)hipEventDestroy(e);
+  if (ctx->hprobs) (void)hipHostFree(ctx->hprobs);
+  if (ctx->hinfo) (void)hipHostFree(ctx->hinfo);
   delete ctx;
   return 0;
 }
@@ -305,7 +401,18 @@ int bse_ctx_set_timing(bse_ctx* ctx, int enable) {
 size_t bse_footprint_bytes(int n, int prec, unsigned flags) {
   (void)flags;
   if (n <= 0 || prec != BSE_PREC_FP64) return 0;
-  return make_plan(2L * n).total;
+  return header_bytes(1) + make_plan(2L * n).total;
+}
+
+size_t bse_footprint_batched_bytes(int count, const int* n, int prec, unsigned flags) {
+  (void)flags;
+  if (count <= 0 || !n || prec != BSE_PREC_FP64) return 0;
+  size_t total = header_bytes(count);
+  for (int i = 0; i < count; ++i) {
+    if (n[i] <= 0) return 0;
+    total += make_plan(2L * n[i]).total;
+  }
+  return total;
 }
 
 int bse_solve(bse_ctx* ctx, int n, const void* A, int lda, const void* B, int ldb, int prec,
@@ -328,9 +435,95 @@ int bse_solve(bse_ctx* ctx, int n, const void* A, int lda, const void* B, int ld
   if (wts && !d_r) return set_error(-12, "d_r is NULL");
   if (wts && !w) return set_error(-14, "w is NULL");
   BSE_TRY(prologue(ctx));
-  return solve_fp64(ctx, n, static_cast<const double*>(A), lda, static_cast<const double*>(B), ldb, flags,
-                    lambda, static_cast<double*>(X), ldx, static_cast<const double*>(d_r),
-                    static_cast<const double*>(d_l), static_cast<double*>(w), rep);
+  Setup S;
+  const long N = 2L * n;
+  BSE_TRY(setup_batch(ctx, 1, &N, &S));
+  Prob& P = ctx->hprobs[0];
+  P.A = static_cast<const double*>(A);
+  P.lda = lda;
+  P.B = static_cast<const double*>(B);
+  P.ldb = ldb;
+  P.lambda = lambda;
+  P.X = static_cast<double*>(X);
+  P.ldx = ldx;
+  P.dr = static_cast<const double*>(d_r);
+  P.dl = static_cast<const double*>(d_l);
+  P.w = static_cast<double*>(w);
+  P.flags = flags;
+  BSE_TRY(run_chain(ctx, S, 1, vec, rep));
+  if (rep) rep->n = n;
+  if (ctx->hinfo[0] != 0) return ctx->hinfo[0];
+  if (vec && ctx->hinfo[1] != 0) return set_error(BSE_EDEVICE, "cluster Gram matrix not positive definite");
+  return 0;
+}
+
+int bse_solve_batched(bse_ctx* ctx, int count, const int* n, const void* const* A, const int* lda,
+                      const void* const* B, const int* ldb, int prec, unsigned flags,
+                      double* const* lambda, void* const* X, const int* ldx, const void* const* d,
+                      void* const* w, int* info, bse_report* rep) {
+  if (!ctx) return set_error(-1, "ctx is NULL");
+  if (count < 0) return set_error(-2, "count is negative");
+  if (count == 0) return 0;
+  if (!n) return set_error(-3, "n is NULL");
+  if (!A) return set_error(-4, "A is NULL");
+  if (!lda) return set_error(-5, "lda is NULL");
+  if (!B) return set_error(-6, "B is NULL");
+  if (!ldb) return set_error(-7, "ldb is NULL");
+  if (prec != BSE_PREC_FP64) return set_error(-8, "unsupported precision policy");
+  if (flags & ~(BSE_WANT_VECTORS | BSE_WANT_WEIGHTS)) return set_error(-9, "unknown flags");
+  if (!lambda) return set_error(-10, "lambda is NULL");
+  const bool vec = (flags & BSE_WANT_VECTORS) != 0;
+  const bool wts = (flags & BSE_WANT_WEIGHTS) != 0;
+  if (wts && !vec) return set_error(-9, "weights need eigenvectors");
+  if (vec && !X) return set_error(-11, "X is NULL");
+  if (vec && !ldx) return set_error(-12, "ldx is NULL");
+  if (wts && !d) return set_error(-13, "d is NULL");
+  if (wts && !w) return set_error(-14, "w is NULL");
+  if (!info) return set_error(-15, "info is NULL");
+  for (int i = 0; i < count; ++i) {
+    if (n[i] <= 0) return set_errorf(-3, "n[%d] must be positive", i);
+    if (!A[i]) return set_errorf(-4, "A[%d] is NULL", i);
+    if (lda[i] < n[i]) return set_errorf(-5, "lda[%d] < n", i);
+    if (!B[i]) return set_errorf(-6, "B[%d] is NULL", i);
+    if (ldb[i] < n[i]) return set_errorf(-7, "ldb[%d] < n", i);
+    if (!lambda[i]) return set_errorf(-10, "lambda[%d] is NULL", i);
+    if (vec && !X[i]) return set_errorf(-11, "X[%d] is NULL", i);
+    if (vec && ldx[i] < 2 * n[i]) return set_errorf(-12, "ldx[%d] < 2n", i);
+    if (wts && !d[i]) return set_errorf(-13, "d[%d] is NULL", i);
+    if (wts && !w[i]) return set_errorf(-14, "w[%d] is NULL", i);
+  }
+  BSE_TRY(prologue(ctx));
+  // descriptors sorted by decreasing n (stable)
+  std::vector<int> order(count);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b2) { return n[a] > n[b2]; });
+  std::vector<long> Ns(count);
+  for (int k = 0; k < count; ++k) Ns[k] = 2L * n[order[k]];
+  Setup S;
+  BSE_TRY(setup_batch(ctx, count, Ns.data(), &S));
+  for (int k = 0; k < count; ++k) {
+    const int i = order[k];
+    Prob& P = ctx->hprobs[k];
+    P.A = static_cast<const double*>(A[i]);
+    P.lda = lda[i];
+    P.B = static_cast<const double*>(B[i]);
+    P.ldb = ldb[i];
+    P.lambda = lambda[i];
+    P.X = vec ? static_cast<double*>(X[i]) : nullptr;
+    P.ldx = vec ? ldx[i] : 0;
+    P.dr = wts ? static_cast<const double*>(d[i]) : nullptr;
+    P.dl = nullptr;
+    P.w = wts ? static_cast<double*>(w[i]) : nullptr;
+    P.flags = flags;
+  }
+  BSE_TRY(run_chain(ctx, S, count, vec, rep));
+  if (rep) rep->n = n[order[0]];
+  for (int k = 0; k < count; ++k) {
+    const int i = order[k];
+    const int i0 = ctx->hinfo[2 * k], i1 = ctx->hinfo[2 * k + 1];
+    info[i] = (i0 != 0) ? i0 : ((vec && i1 != 0) ? BSE_EDEVICE : 0);
+  }
+  return 0;
 }
 
 // ---------------------------------------------------------------- stages
@@ -345,8 +538,24 @@ int bse_build_M(bse_ctx* ctx, int n, const void* A, int lda, const void* B, int 
   if (!M) return set_error(-7, "M is NULL");
   if (ldm < 2 * n) return set_error(-8, "ldm < 2n");
   BSE_TRY(prologue(ctx));
-  BSE_TRY(launch_build_M(ctx->stream, n, static_cast<const double*>(A), lda, static_cast<const double*>(B), ldb,
-                         M, ldm));
+  BSE_TRY(ensure_host(ctx, 1));
+  char* base = nullptr;
+  BSE_TRY(get_workspace(ctx, header_bytes(1), &base));
+  Prob& P = ctx->hprobs[0];
+  memset(&P, 0, sizeof(P));
+  P.n = n;
+  P.N = 2 * n;
+  P.A = static_cast<const double*>(A);
+  P.lda = lda;
+  P.B = static_cast<const double*>(B);
+  P.ldb = ldb;
+  P.L = M;  // the embedding is written straight into the caller's matrix
+  P.ld = ldm;
+  Setup S;
+  S.base = base;
+  S.dprobs = reinterpret_cast<Prob*>(base);
+  BSE_TRY(upload(ctx, S, 1));
+  BSE_TRY(build_M_batched(ctx->stream, single_batch(ctx, S)));
   BSE_HIP(hipStreamSynchronize(ctx->stream));
   return 0;
 }
@@ -357,19 +566,17 @@ int bse_potrf(bse_ctx* ctx, int N, double* M, int ldm) {
   if (!M) return set_error(-3, "M is NULL");
   if (ldm < N) return set_error(-4, "ldm < N");
   BSE_TRY(prologue(ctx));
-  const Plan p = make_plan(N);
-  char* base = nullptr;
-  BSE_TRY(get_workspace(ctx, p.total, &base));
-  Bufs b;
-  bind(p, base, &b);
+  Setup S;
+  BSE_TRY(setup_single(ctx, N, &S));
+  const Prob& P = ctx->hprobs[0];
   hipStream_t s = ctx->stream;
-  BSE_TRY(copy_matrix(s, N, N, M, ldm, b.L, p.ld));
-  BSE_TRY(zero_upper(s, N, b.L, p.ld));
-  BSE_TRY(potrf_f64(s, N, b.L, p.ld, b.info, b.linv));
-  BSE_TRY(copy_matrix(s, N, N, b.L, p.ld, M, ldm));
-  int info = 0;
-  BSE_TRY(read_info(ctx, b.info, &info));
-  return info;
+  BSE_TRY(upload(ctx, S, 1));
+  BSE_TRY(copy_matrix(s, N, N, M, ldm, P.L, P.ld));
+  BSE_TRY(zero_upper(s, N, P.L, P.ld));
+  BSE_TRY(potrf_batched(s, single_batch(ctx, S), 0, true));
+  BSE_TRY(copy_matrix(s, N, N, P.L, P.ld, M, ldm));
+  BSE_TRY(read_infos(ctx, S, 1));
+  return ctx->hinfo[0];
 }
 
 int bse_form_W(bse_ctx* ctx, int N, const double* L, int ldl, double* W, int ldw) {
@@ -380,16 +587,15 @@ int bse_form_W(bse_ctx* ctx, int N, const double* L, int ldl, double* W, int ldw
   if (!W) return set_error(-5, "W is NULL");
   if (ldw < N) return set_error(-6, "ldw < N");
   BSE_TRY(prologue(ctx));
-  const Plan p = make_plan(N);
-  char* base = nullptr;
-  BSE_TRY(get_workspace(ctx, p.total, &base));
-  Bufs b;
-  bind(p, base, &b);
+  Setup S;
+  BSE_TRY(setup_single(ctx, N, &S));
+  const Prob& P = ctx->hprobs[0];
   hipStream_t s = ctx->stream;
-  BSE_TRY(copy_matrix(s, N, N, L, ldl, b.L, p.ld));
-  BSE_TRY(zero_upper(s, N, b.L, p.ld));
-  BSE_TRY(form_W(s, N, b.L, p.ld, b.W, p.ld, true));
-  BSE_TRY(copy_matrix(s, N, N, b.W, p.ld, W, ldw));
+  BSE_TRY(upload(ctx, S, 1));
+  BSE_TRY(copy_matrix(s, N, N, L, ldl, P.L, P.ld));
+  BSE_TRY(zero_upper(s, N, P.L, P.ld));
+  BSE_TRY(form_W_batched(s, single_batch(ctx, S), true));
+  BSE_TRY(copy_matrix(s, N, N, P.W, P.ld, W, ldw));
   BSE_HIP(hipStreamSynchronize(s));
   return 0;
 }
@@ -402,17 +608,16 @@ int bse_sktrd(bse_ctx* ctx, int N, double* W, int ldw, double* alpha, double* ta
   if (!alpha) return set_error(-5, "alpha is NULL");
   if (!tau) return set_error(-6, "tau is NULL");
   BSE_TRY(prologue(ctx));
-  const Plan p = make_plan(N);
-  char* base = nullptr;
-  BSE_TRY(get_workspace(ctx, p.total, &base));
-  Bufs b;
-  bind(p, base, &b);
+  Setup S;
+  BSE_TRY(setup_single(ctx, N, &S));
+  const Prob& P = ctx->hprobs[0];
   hipStream_t s = ctx->stream;
-  BSE_TRY(copy_matrix(s, N, N, W, ldw, b.W, p.ld));
-  BSE_TRY(sktrd_f64(s, N, b.W, p.ld, b.alpha, b.tau, b.sk));
-  BSE_TRY(copy_matrix(s, N, N, b.W, p.ld, W, ldw));
-  BSE_HIP(hipMemcpyAsync(alpha, b.alpha, (N - 1) * sizeof(double), hipMemcpyDeviceToDevice, s));
-  BSE_HIP(hipMemcpyAsync(tau, b.tau, (N - 1) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  BSE_TRY(upload(ctx, S, 1));
+  BSE_TRY(copy_matrix(s, N, N, W, ldw, P.W, P.ld));
+  BSE_TRY(sktrd_batched(s, single_batch(ctx, S), nullptr));
+  BSE_TRY(copy_matrix(s, N, N, P.W, P.ld, W, ldw));
+  BSE_HIP(hipMemcpyAsync(alpha, P.alpha, (N - 1) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  BSE_HIP(hipMemcpyAsync(tau, P.tau, (N - 1) * sizeof(double), hipMemcpyDeviceToDevice, s));
   BSE_HIP(hipStreamSynchronize(s));
   return 0;
 }
@@ -424,21 +629,21 @@ int bse_tridiag_eig(bse_ctx* ctx, int N, const double* alpha, double* lambda, do
   if (!lambda) return set_error(-4, "lambda is NULL");
   if (V && ldv < N) return set_error(-6, "ldv < N");
   BSE_TRY(prologue(ctx));
-  const Plan p = make_plan(N);
-  char* base = nullptr;
-  BSE_TRY(get_workspace(ctx, p.total, &base));
-  Bufs b;
-  bind(p, base, &b);
+  Setup S;
+  BSE_TRY(setup_single(ctx, N, &S));
+  Prob& P = ctx->hprobs[0];
+  P.lambda = lambda;
   hipStream_t s = ctx->stream;
-  BSE_HIP(hipMemcpyAsync(b.alpha, alpha, (N - 1) * sizeof(double), hipMemcpyDeviceToDevice, s));
-  BSE_TRY(tridiag_bisect(s, N, b.alpha, b.e2, b.scal, lambda));
+  BSE_TRY(upload(ctx, S, 1));
+  const Batch b = single_batch(ctx, S);
+  BSE_HIP(hipMemcpyAsync(P.alpha, alpha, (N - 1) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  BSE_TRY(bisect_batched(s, b));
   if (V) {
-    BSE_TRY(tridiag_invit(s, N, b.alpha, b.scal, lambda, b.shift, b.inv, b.Vt));
-    BSE_TRY(tridiag_reorth(s, N, lambda, b.scal, b.Vt, b.inv, b.cid, b.info, b.linv));
-    BSE_TRY(transpose_to(s, N / 2, N, b.Vt, N / 2, V, ldv));
-    int info = 0;
-    BSE_TRY(read_info(ctx, b.info, &info));
-    if (info != 0) return set_error(BSE_EDEVICE, "cluster Gram matrix not positive definite");
+    BSE_TRY(invit_batched(s, b));
+    BSE_TRY(reorth_batched(s, b));
+    BSE_TRY(transpose_to(s, N / 2, N, P.Vt, N / 2, V, ldv));
+    BSE_TRY(read_infos(ctx, S, 1));
+    if (ctx->hinfo[1] != 0) return set_error(BSE_EDEVICE, "cluster Gram matrix not positive definite");
   }
   BSE_HIP(hipStreamSynchronize(s));
   return 0;

@@ -30,9 +30,13 @@ constexpr double EPS = DBL_EPSILON;   // 2^-52
 constexpr double SAFMIN = DBL_MIN;
 
 // scal[0] = pivmin, scal[1] = Gershgorin bound ||T_s||_1, scal[2] = max alpha^2
-__global__ __launch_bounds__(1024) void k_tridiag_prep(const double* __restrict__ alpha, int N,
-                                                       double* __restrict__ e2, double* __restrict__ scal) {
+__global__ __launch_bounds__(1024) void k_tridiag_prep(const Prob* __restrict__ probs) {
   __shared__ double smax[16], sg[16];
+  const Prob& P = probs[blockIdx.z];
+  const int N = P.N;
+  const double* __restrict__ alpha = P.alpha;
+  double* __restrict__ e2 = P.e2;
+  double* __restrict__ scal = P.scal;
   double m = 0.0, g = 0.0;
   for (int k = threadIdx.x; k < N; k += blockDim.x) {
     const double a = (k < N - 1) ? alpha[k] : 0.0;
@@ -75,11 +79,14 @@ __device__ inline int sturm_count(const double* __restrict__ e2, int N, double x
   return c;
 }
 
-__global__ __launch_bounds__(64) void k_bisect(const double* __restrict__ e2, int N,
-                                               const double* __restrict__ scal, double* __restrict__ lam) {
-  const int n = N / 2;
+__global__ __launch_bounds__(64) void k_bisect(const Prob* __restrict__ probs) {
+  const Prob& P = probs[blockIdx.z];
+  const int N = P.N, n = P.n;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
+  const double* __restrict__ e2 = P.e2;
+  const double* __restrict__ scal = P.scal;
+  double* __restrict__ lam = P.lambda;
   const double pivmin = scal[0];
   double lo = 0.0;
   double hi = scal[1] * (1.0 + 4.0 * EPS) + 4.0 * pivmin;
@@ -99,8 +106,12 @@ __global__ __launch_bounds__(64) void k_bisect(const double* __restrict__ e2, in
   lam[j] = 0.5 * (lo + hi);
 }
 
-__global__ void k_shifts(const double* __restrict__ lam, int n, double* __restrict__ shift) {
+__global__ void k_shifts(const Prob* __restrict__ probs) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const Prob& P = probs[blockIdx.z];
+  const int n = P.n;
+  const double* __restrict__ lam = P.lambda;
+  double* __restrict__ shift = P.shift;
   double prev = lam[0];
   shift[0] = prev;
   for (int j = 1; j < n; ++j) {
@@ -128,15 +139,21 @@ __device__ inline double perturb(double d, double pert) {
 // Workspace per eigenvector j (n of them), element k at [k*n + j]:
 //   fd (U diagonal), fu (first superdiagonal), fu2 (second), fl (multiplier),
 //   fs (row interchange flag).  Vt holds the iterate.
-__global__ __launch_bounds__(64) void k_invit(const double* __restrict__ alpha, int N,
-                                              const double* __restrict__ scal,
-                                              const double* __restrict__ shift,
-                                              double* __restrict__ fd, double* __restrict__ fu,
-                                              double* __restrict__ fu2, double* __restrict__ fl,
-                                              unsigned char* __restrict__ fs, double* __restrict__ Vt) {
-  const int n = N / 2;
+__global__ __launch_bounds__(64) void k_invit(const Prob* __restrict__ probs) {
+  const Prob& P = probs[blockIdx.z];
+  const int N = P.N, n = P.n;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
+  const double* __restrict__ alpha = P.alpha;
+  const double* __restrict__ scal = P.scal;
+  const double* __restrict__ shift = P.shift;
+  const long sz = (long)N * n;
+  double* __restrict__ fd = P.inv;
+  double* __restrict__ fu = P.inv + sz;
+  double* __restrict__ fu2 = P.inv + 2 * sz;
+  double* __restrict__ fl = P.inv + 3 * sz;
+  unsigned char* __restrict__ fs = reinterpret_cast<unsigned char*>(P.inv + 4 * sz);
+  double* __restrict__ Vt = P.Vt;
   const long ldn = n;
   const double pert = EPS * fmax(scal[1], SAFMIN);
   const double sh = shift[j];
@@ -213,9 +230,13 @@ __global__ __launch_bounds__(64) void k_invit(const double* __restrict__ alpha, 
 }
 
 // cid[j] = index of the cluster of eigenvalue j (consecutive gaps <= ortol)
-__global__ __launch_bounds__(1024) void k_cluster_ids(const double* __restrict__ lam, int n,
-                                                      const double* __restrict__ scal, int* __restrict__ cid) {
+__global__ __launch_bounds__(1024) void k_cluster_ids(const Prob* __restrict__ probs) {
   __shared__ int sums[1024];
+  const Prob& P = probs[blockIdx.z];
+  const int n = P.n;
+  const double* __restrict__ lam = P.lambda;
+  const double* __restrict__ scal = P.scal;
+  int* __restrict__ cid = P.cid;
   const double ortol = 1e-3 * scal[1];
   const int T = blockDim.x;
   const int chunk = (n + T - 1) / T;
@@ -241,8 +262,12 @@ __global__ __launch_bounds__(1024) void k_cluster_ids(const double* __restrict__
   }
 }
 
-__global__ __launch_bounds__(256) void k_mask_gram(double* __restrict__ G, long ldg, int n,
-                                                   const int* __restrict__ cid) {
+__global__ __launch_bounds__(256) void k_mask_gram(const Prob* __restrict__ probs) {
+  const Prob& P = probs[blockIdx.z];
+  const int n = P.n;
+  const long ldg = n;
+  double* __restrict__ G = P.inv;
+  const int* __restrict__ cid = P.cid;
   const long r = (long)blockIdx.x * 64 + (threadIdx.x & 63);
   const long c0 = (long)blockIdx.y * 64 + (threadIdx.x >> 6) * 16;
   if (r >= n) return;
@@ -273,55 +298,48 @@ __global__ __launch_bounds__(256) void k_transpose(int rows, int cols, const dou
 
 }  // namespace
 
-int tridiag_bisect(hipStream_t s, int N, const double* alpha, double* e2, double* scal, double* lam) {
-  const int n = N / 2;
-  k_tridiag_prep<<<1, 1024, 0, s>>>(alpha, N, e2, scal);
+int bisect_batched(hipStream_t s, const Batch& b) {
+  if (b.count <= 0) return 0;
+  const int n0 = b.maxn();
+  k_tridiag_prep<<<dim3(1, 1, (unsigned)b.count), 1024, 0, s>>>(b.dev);
   BSE_LAUNCHED();
-  k_bisect<<<(n + 63) / 64, 64, 0, s>>>(e2, N, scal, lam);
-  BSE_LAUNCHED();
-  return 0;
-}
-
-int tridiag_invit(hipStream_t s, int N, const double* alpha, const double* scal, const double* lam,
-                  double* shift, double* work, double* Vt) {
-  const int n = N / 2;
-  const long sz = (long)N * n;
-  double* fd = work;
-  double* fu = work + sz;
-  double* fu2 = work + 2 * sz;
-  double* fl = work + 3 * sz;
-  unsigned char* fs = reinterpret_cast<unsigned char*>(work + 4 * sz);
-  k_shifts<<<1, 64, 0, s>>>(lam, n, shift);
-  BSE_LAUNCHED();
-  k_invit<<<(n + 63) / 64, 64, 0, s>>>(alpha, N, scal, shift, fd, fu, fu2, fl, fs, Vt);
+  k_bisect<<<dim3((unsigned)((n0 + 63) / 64), 1, (unsigned)b.count), 64, 0, s>>>(b.dev);
   BSE_LAUNCHED();
   return 0;
 }
 
-int tridiag_reorth(hipStream_t s, int N, const double* lam, const double* scal, double* Vt, double* G,
-                   int* cid, int* info_dev, double* linv) {
-  const int n = N / 2;
-  k_cluster_ids<<<1, 1024, 0, s>>>(lam, n, scal, cid);
+int invit_batched(hipStream_t s, const Batch& b) {
+  if (b.count <= 0) return 0;
+  const int n0 = b.maxn();
+  k_shifts<<<dim3(1, 1, (unsigned)b.count), 64, 0, s>>>(b.dev);
+  BSE_LAUNCHED();
+  k_invit<<<dim3((unsigned)((n0 + 63) / 64), 1, (unsigned)b.count), 64, 0, s>>>(b.dev);
+  BSE_LAUNCHED();
+  return 0;
+}
+
+int reorth_batched(hipStream_t s, const Batch& b) {
+  if (b.count <= 0) return 0;
+  const int n0 = b.maxn();
+  k_cluster_ids<<<dim3(1, 1, (unsigned)b.count), 1024, 0, s>>>(b.dev);
   BSE_LAUNCHED();
   // Two passes of Cholesky QR ("twice is enough"): the second restores full
   // orthogonality when a degenerate cluster's start vectors were close.
-  dim3 g2((unsigned)((n + 63) / 64), (unsigned)((n + 63) / 64));
+  const dim3 g2((unsigned)((n0 + 63) / 64), (unsigned)((n0 + 63) / 64), (unsigned)b.count);
   for (int pass = 0; pass < 2; ++pass) {
     // G = Vt Vt^T (lower), then drop the entries between clusters
-    BSE_TRY(gemm_f64(s, false, true, n, n, N, 1.0, Vt, n, Vt, n, 0.0, G, n, 1, 0, 0));
-    k_mask_gram<<<g2, 256, 0, s>>>(G, n, n, cid);
+    BSE_TRY(gemm_batched(s, b, b.count, GOP_GRAM, 0));
+    k_mask_gram<<<g2, 256, 0, s>>>(b.dev);
     BSE_LAUNCHED();
-    BSE_TRY(potrf_f64(s, n, G, n, info_dev, linv, pass == 0));
+    BSE_TRY(potrf_batched(s, b, 1, pass == 0));
     // Vt <- L^{-1} Vt  (blocked forward substitution; the diagonal block is
     // applied through its inverse, in place: one row tile of output)
-    for (int b0 = 0; b0 < n; b0 += 64) {
-      const int nbk = (n - b0 < 64) ? n - b0 : 64;
-      BSE_TRY(trtri_diag64(s, G, n, b0, nbk, linv, info_dev));
-      BSE_TRY(gemm_f64(s, false, false, nbk, N, nbk, 1.0, linv, 64, Vt + b0, n, 0.0, Vt + b0, n, 0, 0, 0));
-      const int rest = n - b0 - nbk;
-      if (rest > 0)
-        BSE_TRY(gemm_f64(s, false, false, rest, N, nbk, -1.0, G + (b0 + nbk) + (long)b0 * n, n, Vt + b0, n, 1.0,
-                         Vt + b0 + nbk, n, 0, 0, 0));
+    for (int b0 = 0; b0 < n0; b0 += 64) {
+      int nact = 0;
+      while (nact < b.count && b.host[nact].n > b0) ++nact;
+      BSE_TRY(trtri_batched(s, b, nact, 1, b0));
+      BSE_TRY(gemm_batched(s, b, nact, GOP_GRAM_DIAG, b0));
+      BSE_TRY(gemm_batched(s, b, nact, GOP_GRAM_UPD, b0));
     }
   }
   return 0;
