@@ -77,6 +77,55 @@ def cpu_baseline(n_sample: int, n_target: int, s_a: float, s_b: float):
     }
 
 
+def batched_bench(ctx, steps: int, warmup: int, count: int = 256, lo: int = 64, hi: int = 1024,
+                  size_seed: int = 4, s_a: float = 0.1, s_b: float = 0.05):
+    """The batched workload: `count` independent problems, n_i log-uniform in
+    [lo, hi] (seed size_seed), problem i from seed 1000 + i, one
+    bse_solve_batched call per step with inputs resident in HBM, all
+    eigenvalues, eigenvectors and weights."""
+    import torch
+    from bse_inputs import gen_bse, batched_sizes
+    from paper_1501_03830_amd.api import to_colmajor
+
+    dev = torch.device("cuda", 0)
+    ns = [int(k) for k in batched_sizes(count, lo, hi, seed=size_seed)]
+    t0 = time.time()
+    Acs, Bcs, ds = [], [], []
+    for i, k in enumerate(ns):
+        pr = gen_bse(k, s_a=s_a, s_b=s_b, seed=1000 + i, check_definite=False)
+        Acs.append(to_colmajor(torch.from_numpy(pr.A), dev))
+        Bcs.append(to_colmajor(torch.from_numpy(pr.B), dev))
+        ds.append(torch.from_numpy(pr.d).to(dev))
+    print(f"# batched: generated {count} problems in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    lams = [torch.empty(k, dtype=torch.float64, device=dev) for k in ns]
+    Xs = [torch.empty((k, 2 * k), dtype=torch.complex128, device=dev) for k in ns]
+    ws = [torch.empty(k, dtype=torch.complex128, device=dev) for k in ns]
+    for i in range(warmup):
+        info, rep = ctx.solve_batched_raw(ns, Acs, Bcs, lams, Xs, ds, ws, report=True)
+        assert all(v == 0 for v in info), info
+        print(f"# batched warmup {i}: {rep['total_ms']:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    reps = []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        info, rep = ctx.solve_batched_raw(ns, Acs, Bcs, lams, Xs, ds, ws, report=True)
+        assert all(v == 0 for v in info)
+        reps.append(rep)
+        print(f"# batched step {i}: {rep['total_ms']:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return {
+        "workload": f"{count} independent problems, n log-uniform in [{lo},{hi}] (size seed {size_seed}, "
+                    f"problem i seed 1000+i), FP64, eigenvalues + eigenvectors + weights, one bse_solve_batched call",
+        "solves_per_s": round(count / dt, 2),
+        "s_per_batch": round(dt, 4),
+        "device_ms_per_batch": round(float(np.mean([r["total_ms"] for r in reps])), 2),
+        "stage_ms": {k: round(float(np.mean([r["stage_ms"][k] for r in reps])), 2) for k in reps[0]["stage_ms"]},
+        "sum_n3": float(sum(k ** 3 for k in ns)),
+        "n_max": max(ns), "n_min": min(ns),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +138,8 @@ def main():
     ap.add_argument("--cpu-sample-n", type=int, default=768)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip per-launch kernel events")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched workload")
+    ap.add_argument("--batched-only", action="store_true", help="only the batched workload")
     a = ap.parse_args()
 
     if a.gpus != 1:
@@ -99,6 +150,12 @@ def main():
     import torch
     from bse_inputs import gen_bse
     from paper_1501_03830_amd.api import Context, to_colmajor
+
+    if a.batched_only:
+        ctx = Context(0)
+        print(json.dumps({"batched": batched_bench(ctx, a.steps, a.warmup)}), flush=True)
+        ctx.close()
+        return
 
     n = a.n
     t0 = time.time()
@@ -187,6 +244,11 @@ def main():
         "roofline": roofline,
         "cpu_baseline": None,
     }
+    ctx.set_timing(False)
+    if not a.no_batched:
+        del Ac, Bc, Xbuf
+        torch.cuda.empty_cache()
+        out["batched"] = batched_bench(ctx, a.steps, a.warmup)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.cpu_sample_n, n, a.s_a, a.s_b)
     ctx.close()

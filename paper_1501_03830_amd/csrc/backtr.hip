@@ -31,8 +31,8 @@ __global__ __launch_bounds__(256) void k_scatter_DV(const Prob* __restrict__ pro
   const int N = P.N, n = P.n;
   const int k0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
   if (k0 >= N || j0 >= n) return;  // uniform
-  const double* __restrict__ Vt = P.Vt;
-  double* __restrict__ Z = P.Z;
+  const BSE_GLOBAL double* __restrict__ Vt = gbl(P.Vt);
+  BSE_GLOBAL double* __restrict__ Z = gbl(P.Z);
   const long ldz = P.ld;
   for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
     const int jj = idx & 63, kk = idx >> 6;
@@ -61,8 +61,8 @@ __global__ __launch_bounds__(256) void k_extract_V(const Prob* __restrict__ prob
   const int j0 = q * NBQ;
   if (j0 >= nrefl) return;  // uniform
   const int nbk = min(NBQ, nrefl - j0);
-  const double* __restrict__ W = P.W;
-  double* __restrict__ Vb = P.Vb;
+  const BSE_GLOBAL double* __restrict__ W = gbl(P.W);
+  BSE_GLOBAL double* __restrict__ Vb = gbl(P.Vb);
   const long ldw = P.ld, ldv = P.ld;
   const long r = (long)j0 + 1 + (long)blockIdx.x * 64 + (threadIdx.x & 63);
   if (r >= N) return;
@@ -87,9 +87,9 @@ __global__ __launch_bounds__(64) void k_larft(const Prob* __restrict__ probs, in
   if (j0 >= nrefl) return;  // uniform
   const int nbk = min(NBQ, nrefl - j0);
   const int nbq = NBQ;
-  const double* __restrict__ S = P.S;
-  const double* __restrict__ tau = P.tau;
-  double* __restrict__ T = P.T;
+  const BSE_CONST double* __restrict__ S = ro(P.S);
+  const BSE_CONST double* __restrict__ tau = ro(P.tau);
+  BSE_GLOBAL double* __restrict__ T = gbl(P.T);
   const int i = threadIdx.x;
   for (int c = 0; c < 64; ++c) Ts[c][i] = 0.0;
   __syncthreads();
@@ -113,10 +113,10 @@ __global__ __launch_bounds__(64) void k_larft(const Prob* __restrict__ probs, in
 __global__ __launch_bounds__(256) void k_finish_X(const Prob* __restrict__ probs) {
   const Prob& P = probs[blockIdx.z];
   const int n = P.n;
-  const double* __restrict__ G = P.W;
+  const BSE_GLOBAL double* __restrict__ G = gbl(P.W);
   const long ldg = P.ld;
-  const double* __restrict__ lam = P.lambda;
-  double* __restrict__ X = P.X;
+  const BSE_GLOBAL double* __restrict__ lam = gbl(P.lambda);
+  BSE_GLOBAL double* __restrict__ X = gbl(P.X);
   const long ldx = P.ldx;
   const long r = (long)blockIdx.x * 64 + (threadIdx.x & 63);
   const long c0 = (long)blockIdx.y * 64 + (threadIdx.x >> 6) * 16;
@@ -127,8 +127,8 @@ __global__ __launch_bounds__(256) void k_finish_X(const Prob* __restrict__ probs
     const double g1r = G[r + j * ldg], g1i = G[r + (n + j) * ldg];
     const double g2r = G[n + r + j * ldg], g2i = G[n + r + (n + j) * ldg];
     const double c = 1.0 / sqrt(2.0 * lam[j]);
-    double* x1 = X + 2 * (r + j * ldx);
-    double* x2 = X + 2 * (n + r + j * ldx);
+    auto x1 = X + 2 * (r + j * ldx);
+    auto x2 = X + 2 * (n + r + j * ldx);
     x1[0] = (g1r + g2i) * c;
     x1[1] = (g1i - g2r) * c;
     x2[0] = (g2i - g1r) * c;
@@ -148,13 +148,13 @@ __global__ __launch_bounds__(256) void k_phase_weights(const Prob* __restrict__ 
   const int j = blockIdx.x;
   if (j >= n) return;  // uniform
   const long ldx = P.ldx;
-  double* __restrict__ X = P.X;
+  BSE_GLOBAL double* __restrict__ X = gbl(P.X);
   const bool weights = (P.flags & BSE_WANT_WEIGHTS) != 0 && P.dr != nullptr && P.w != nullptr;
-  const double* __restrict__ dr = weights ? P.dr : nullptr;
-  const double* __restrict__ dl = weights ? (P.dl ? P.dl : P.dr) : nullptr;
-  double* __restrict__ w = P.w;
+  const BSE_GLOBAL double* __restrict__ dr = gbl(weights ? P.dr : nullptr);
+  const BSE_GLOBAL double* __restrict__ dl = gbl(weights ? (P.dl ? P.dl : P.dr) : nullptr);
+  BSE_GLOBAL double* __restrict__ w = gbl(P.w);
   const int N = 2 * n;
-  double* x = X + 2 * (long)j * ldx;
+  auto x = X + 2 * (long)j * ldx;
   double best = -1.0;
   int bi = 0x7fffffff;
   for (int r = threadIdx.x; r < N; r += 256) {

@@ -24,10 +24,10 @@ __global__ __launch_bounds__(256) void k_build_M(const Prob* __restrict__ probs)
   const int r = blockIdx.x * TB + (threadIdx.x & 63);
   const int cbase = blockIdx.y * TB + (threadIdx.x >> 6) * 16;
   if (r >= N) return;
-  const double* __restrict__ A = P.A;
-  const double* __restrict__ B = P.B;
+  const BSE_GLOBAL double* __restrict__ A = gbl(P.A);
+  const BSE_GLOBAL double* __restrict__ B = gbl(P.B);
   const long lda = P.lda, ldb = P.ldb, ldm = P.ld;
-  double* __restrict__ M = P.L;
+  BSE_GLOBAL double* __restrict__ M = gbl(P.L);
   for (int q = 0; q < 16; ++q) {
     const int c = cbase + q;
     if (c >= N) break;
@@ -59,16 +59,16 @@ __global__ __launch_bounds__(256) void k_build_M(const Prob* __restrict__ probs)
 }
 
 __global__ void k_reset_info(const Prob* __restrict__ probs, int sel) {
-  if (threadIdx.x == 0) probs[blockIdx.z].info[sel] = 0;
+  if (threadIdx.x == 0) gbl(probs[blockIdx.z].info)[sel] = 0;
 }
 
-__device__ inline void chol_matrix(const Prob& P, int sel, double*& M, long& ld, int& N) {
+__device__ inline void chol_matrix(const Prob& P, int sel, BSE_GLOBAL double*& M, long& ld, int& N) {
   if (sel == 0) {
-    M = P.L;
+    M = gbl(P.L);
     ld = P.ld;
     N = P.N;
   } else {
-    M = P.inv;
+    M = gbl(P.inv);
     ld = P.n;
     N = P.n;
   }
@@ -78,11 +78,11 @@ __device__ inline void chol_matrix(const Prob& P, int sel, double*& M, long& ld,
 __global__ __launch_bounds__(256) void k_potf2(const Prob* __restrict__ probs, int sel, int k0) {
   __shared__ double a[TB][TB + 1];  // a[col][row]
   const Prob& P = probs[blockIdx.z];
-  double* M;
+  BSE_GLOBAL double* M;
   long ld;
   int N;
   chol_matrix(P, sel, M, ld, N);
-  int* info = P.info + sel;
+  BSE_GLOBAL int* info = gbl(P.info + sel);
   if (k0 >= N || *info != 0) return;
   const int nbk = min(TB, N - k0);
   const int tid = threadIdx.x;
@@ -122,13 +122,13 @@ __global__ __launch_bounds__(64) void k_trtri64(const Prob* __restrict__ probs, 
   __shared__ double Lc[TB][TB + 1];  // Lc[col][row]
   __shared__ double Y[TB][TB + 1];   // Y[col][row]
   const Prob& P = probs[blockIdx.z];
-  double* L;
+  BSE_GLOBAL double* L;
   long ld;
   int N;
   chol_matrix(P, sel, L, ld, N);
-  if (b0 >= N || P.info[sel] != 0) return;
+  if (b0 >= N || gbl(P.info)[sel] != 0) return;
   const int nbk = min(TB, N - b0);
-  double* __restrict__ Linv = P.linv;
+  BSE_GLOBAL double* __restrict__ Linv = gbl(P.linv);
   const int c = threadIdx.x;
   for (int r = 0; r < TB; ++r)
     Lc[c][r] = (r < nbk && c < nbk && r >= c) ? L[(long)(b0 + r) + (long)(b0 + c) * ld] : 0.0;
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(256) void k_skew_pairs(const Prob* __restrict__ pro
   const int nrows = (mode == 0) ? P.n : P.N;
   const long nt = (nrows + TB - 1) / TB;
   if ((long)blockIdx.x >= nt * (nt + 1) / 2) return;
-  double* __restrict__ W = P.W;
+  BSE_GLOBAL double* __restrict__ W = gbl(P.W);
   const long ld = P.ld;
   int R, C;
   tri_index(blockIdx.x, R, C);
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(256) void k_zero_W22(const Prob* __restrict__ probs
   const long r = (long)blockIdx.x * 64 + (threadIdx.x & 63);
   const long c0 = (long)blockIdx.y * 64 + (threadIdx.x >> 6) * 16;
   if (r >= n) return;
-  double* W22 = P.W + n + n * P.ld;
+  BSE_GLOBAL double* W22 = gbl(P.W + n + n * P.ld);
   for (int q = 0; q < 16; ++q) {
     const long c = c0 + q;
     if (c >= n) break;

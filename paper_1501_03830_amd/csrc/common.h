@@ -74,6 +74,24 @@ struct Prob {
   double *Vb, *S, *T, *W1, *W2;
 };
 
+// Address-space views of pointers taken from a descriptor.  A pointer loaded
+// from memory is generic to the compiler, which then emits flat instructions
+// (they also hold the LDS counter, so LDS waits stall on global loads) and
+// never scalar loads.  Every buffer here is global memory, so kernels re-type
+// descriptor pointers with gbl(); ro() additionally declares the data
+// read-only for the whole kernel (no thread of the launch writes it), which
+// lets wave-uniform reads use the scalar cache.
+#define BSE_GLOBAL __attribute__((address_space(1)))
+#define BSE_CONST __attribute__((address_space(4)))
+template <class T>
+__device__ inline BSE_GLOBAL T* gbl(T* p) {
+  return (BSE_GLOBAL T*)p;
+}
+template <class T>
+__device__ inline const BSE_CONST T* ro(const T* p) {
+  return (const BSE_CONST T*)p;
+}
+
 // Row/column decomposition of a linear index over the lower triangle of an
 // nt x nt tile grid: t = R (R + 1) / 2 + C with 0 <= C <= R < nt.
 __device__ inline void tri_index(long t, int& R, int& C) {
@@ -117,7 +135,8 @@ __device__ inline double block_sum(double v, double* red) {
 // last to arrive), which may then read all partials.  The counter is
 // restored to zero by the last workgroup so it can be reused by the next
 // launch on the same stream.
-__device__ inline bool arrive_last(unsigned int* counter, unsigned int expected, int* flag_smem) {
+template <class CounterPtr>
+__device__ inline bool arrive_last(CounterPtr counter, unsigned int expected, int* flag_smem) {
   // every thread publishes its own writes at device (agent) scope
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();

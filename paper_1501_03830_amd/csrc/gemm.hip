@@ -181,6 +181,8 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ 
   __shared__ double smem[SMEM];
 
   const GemmParams p = probs ? gemm_params(op, probs[blockIdx.z], step) : single;
+  const BSE_GLOBAL double* __restrict__ Ag = gbl(p.A);
+  const BSE_GLOBAL double* __restrict__ Bg = gbl(p.B);
   long tile = blockIdx.x;
   int slice = 0;
   if (tile >= p.ntiles * p.splits) return;  // uniform: beyond this problem's tiles
@@ -234,7 +236,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ 
 #pragma unroll
       for (int q = 0; q < EA; ++q) {
         const int i = i0 + ii + q;
-        ra[q] = (i < p.M && k < kend) ? p.A[(long)i + (long)k * p.lda] : 0.0;
+        ra[q] = (i < p.M && k < kend) ? Ag[(long)i + (long)k * p.lda] : 0.0;
       }
     } else {
       constexpr int TPC = BK / EA;
@@ -243,7 +245,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ 
 #pragma unroll
       for (int q = 0; q < EA; ++q) {
         const int k = k0 + kk + q;
-        ra[q] = (i < p.M && k < kend) ? p.A[(long)k + (long)i * p.lda] : 0.0;
+        ra[q] = (i < p.M && k < kend) ? Ag[(long)k + (long)i * p.lda] : 0.0;
       }
     }
   };
@@ -269,7 +271,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ 
 #pragma unroll
       for (int q = 0; q < EB; ++q) {
         const int k = k0 + kk + q;
-        rb[q] = (j < p.N && k < kend) ? p.B[(long)k + (long)j * p.ldb] : 0.0;
+        rb[q] = (j < p.N && k < kend) ? Bg[(long)k + (long)j * p.ldb] : 0.0;
       }
     } else {
       constexpr int TPC = BN / EB;
@@ -278,7 +280,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ 
 #pragma unroll
       for (int q = 0; q < EB; ++q) {
         const int j = j0 + jj + q;
-        rb[q] = (j < p.N && k < kend) ? p.B[(long)j + (long)k * p.ldb] : 0.0;
+        rb[q] = (j < p.N && k < kend) ? Bg[(long)j + (long)k * p.ldb] : 0.0;
       }
     }
   };
@@ -360,9 +362,9 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ 
     if (p.c_uplo == 2 && row <= col) continue;
     const double val = Cs[cl * (BM + 1) + rl];
     if (split) {
-      p.part[(long)slice * p.M * p.N + (long)row + (long)col * p.M] = val;
+      gbl(p.part)[(long)slice * p.M * p.N + (long)row + (long)col * p.M] = val;
     } else {
-      double* c = p.C + (long)row + (long)col * p.ldc;
+      BSE_GLOBAL double* c = gbl(p.C + (long)row + (long)col * p.ldc);
       const double out = p.alpha * val;
       *c = (p.beta == 0.0) ? out : out + p.beta * (*c);
     }
@@ -383,8 +385,9 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const Prob* __restrict__ 
     if (p.c_uplo == 1 && r < c) continue;
     if (p.c_uplo == 2 && r <= c) continue;
     double s = 0.0;
-    for (int k = 0; k < p.splits; ++k) s += p.part[(long)k * p.M * p.N + r + c * p.M];
-    double* cp = p.C + r + c * p.ldc;
+    const BSE_GLOBAL double* part = gbl(p.part);
+    for (int k = 0; k < p.splits; ++k) s += part[(long)k * p.M * p.N + r + c * p.M];
+    BSE_GLOBAL double* cp = gbl(p.C + r + c * p.ldc);
     const double out = p.alpha * s;
     *cp = (p.beta == 0.0) ? out : out + p.beta * (*cp);
   }

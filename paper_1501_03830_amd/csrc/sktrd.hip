@@ -66,9 +66,9 @@ __global__ __launch_bounds__(256) void sk_start(const Prob* __restrict__ probs, 
   const Prob& P = probs[blockIdx.z];
   const int N = P.N;
   if (j > N - 2) return;  // uniform
-  const double* __restrict__ W = P.W;
+  const BSE_CONST double* __restrict__ W = ro(P.W);
   const long ld = P.ld;
-  Ctrl* __restrict__ ctrl = static_cast<Ctrl*>(P.ctrl);
+  BSE_GLOBAL Ctrl* __restrict__ ctrl = (BSE_GLOBAL Ctrl*)P.ctrl;
   double ss = 0.0;
   for (long r = j + 2 + threadIdx.x; r < N; r += 256) {
     const double v = W[r + (long)j * ld];
@@ -81,8 +81,8 @@ __global__ __launch_bounds__(256) void sk_start(const Prob* __restrict__ probs, 
     larfg(x0, sqrt(ss), beta, t, sc);
     ctrl->tau = t;
     ctrl->scale = sc;
-    P.alpha[j] = -beta;
-    P.tau[j] = t;
+    gbl(P.alpha)[j] = -beta;
+    gbl(P.tau)[j] = t;
   }
 }
 
@@ -95,7 +95,8 @@ __host__ __device__ inline int symv_tiles(int nblk) {
   return T < 1 ? 1 : (T > TMAX ? TMAX : (int)T);
 }
 
-__device__ inline double vval(const double* __restrict__ W, long ld, int j, int s, int N, double scale, long r) {
+template <class Ptr>
+__device__ inline double vval(Ptr W, long ld, int j, int s, int N, double scale, long r) {
   if (r == s) return 1.0;
   if (r > s && r < N) return scale * W[r + (long)j * ld];
   return 0.0;
@@ -125,13 +126,13 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
   const int nchunk = (nblk + T - 1) / T;
   const long ld = P.ld, ldy = P.ld;
   const int dstride = (int)(ld / TS);
-  const double* __restrict__ W = P.W;
-  const Ctrl* __restrict__ ctrl = static_cast<const Ctrl*>(P.ctrl);
-  double* __restrict__ Y1 = P.Y1;
-  double* __restrict__ Y2 = P.Y2;
-  double* __restrict__ Yrow = P.Yrow;
-  double* __restrict__ Ycol = P.Ycol;
-  double* __restrict__ dotpart = P.dotpart;
+  const BSE_CONST double* __restrict__ W = ro(P.W);
+  const BSE_CONST Ctrl* __restrict__ ctrl = (const BSE_CONST Ctrl*)P.ctrl;
+  BSE_GLOBAL double* __restrict__ Y1 = gbl(P.Y1);
+  BSE_GLOBAL double* __restrict__ Y2 = gbl(P.Y2);
+  BSE_GLOBAL double* __restrict__ Yrow = gbl(P.Yrow);
+  BSE_GLOBAL double* __restrict__ Ycol = gbl(P.Ycol);
+  BSE_GLOBAL double* __restrict__ dotpart = gbl(P.dotpart);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const double scale = ctrl->scale;
 
@@ -188,7 +189,7 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
   // v at the wave's 16 columns (keeps VGPR use, and so occupancy, low)
   const int wvu = __builtin_amdgcn_readfirstlane(wv);
   const long col0 = C0 + 16 * wvu;
-  const double* vcol = W + (long)j * ld;   // column j holds x; v = scale * x below row s
+  const auto vcol = W + (long)j * ld;   // column j holds x; v = scale * x below row s
   double vc[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
@@ -200,7 +201,7 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
 #pragma unroll
   for (int q = 0; q < 16; ++q) cacc[q] = 0.0;
   const bool strip_inside = C0 >= s;
-  const double* colbase = W + col0 * ld;
+  const auto colbase = W + col0 * ld;
   // no barrier, no global store and no dependent load inside this loop: v at
   // the tile's rows is fetched with the tile itself, and the next tile's
   // loads are issued before the current tile is used (software pipeline)
@@ -286,16 +287,16 @@ __global__ __launch_bounds__(256) void sk_update(const Prob* __restrict__ probs,
   const int nbp = min(NBMAX, N - 1 - k0);
   const long ld = P.ld, ldy = P.ld;
   const int dstride = (int)(ld / TS);
-  double* __restrict__ W = P.W;
-  Ctrl* __restrict__ ctrl = static_cast<Ctrl*>(P.ctrl);
-  double* __restrict__ Y1 = P.Y1;
-  double* __restrict__ Y2 = P.Y2;
-  const double* __restrict__ Yrow = P.Yrow;
-  const double* __restrict__ Ycol = P.Ycol;
-  double* __restrict__ normpart = P.normpart;
-  double* __restrict__ alpha = P.alpha;
-  double* __restrict__ tau_arr = P.tau;
-  const double* __restrict__ dotpart = P.dotpart;
+  BSE_GLOBAL double* __restrict__ W = gbl(P.W);
+  BSE_GLOBAL Ctrl* __restrict__ ctrl = (BSE_GLOBAL Ctrl*)P.ctrl;
+  BSE_GLOBAL double* __restrict__ Y1 = gbl(P.Y1);
+  BSE_GLOBAL double* __restrict__ Y2 = gbl(P.Y2);
+  const BSE_CONST double* __restrict__ Yrow = ro(P.Yrow);
+  const BSE_CONST double* __restrict__ Ycol = ro(P.Ycol);
+  BSE_GLOBAL double* __restrict__ normpart = gbl(P.normpart);
+  BSE_GLOBAL double* __restrict__ alpha = gbl(P.alpha);
+  BSE_GLOBAL double* __restrict__ tau_arr = gbl(P.tau);
+  const BSE_CONST double* __restrict__ dotpart = ro(P.dotpart);
   const int tid = threadIdx.x;
   const int t = tid & 63, part = tid >> 6;
   const double tau = ctrl->tau;
@@ -322,7 +323,7 @@ __global__ __launch_bounds__(256) void sk_update(const Prob* __restrict__ probs,
     double acc[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-    const double* yr = Yrow + (long)b * TS + t;      // Yrow[c][b][t]
+    const auto yr = Yrow + (long)b * TS + t;      // Yrow[c][b][t]
     for (int c0 = part; c0 <= b; c0 += 32) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
@@ -331,7 +332,7 @@ __global__ __launch_bounds__(256) void sk_update(const Prob* __restrict__ probs,
       }
     }
     const int nch = (nblk - b + T - 1) / T;
-    const double* yc = Ycol + (long)b * nchunk * TS + t;
+    const auto yc = Ycol + (long)b * nchunk * TS + t;
     for (int c0 = part; c0 < nch; c0 += 32) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
@@ -424,7 +425,7 @@ __global__ __launch_bounds__(256) void sk_update(const Prob* __restrict__ probs,
 }
 
 __global__ void k_zero_ctrl(const Prob* __restrict__ probs) {
-  Ctrl* ctrl = static_cast<Ctrl*>(probs[blockIdx.z].ctrl);
+  BSE_GLOBAL Ctrl* ctrl = (BSE_GLOBAL Ctrl*)probs[blockIdx.z].ctrl;
   if (threadIdx.x == 0) {
     ctrl->cnt_diag = 0u;
     ctrl->cnt_upd = 0u;

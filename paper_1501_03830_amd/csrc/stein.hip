@@ -34,9 +34,9 @@ __global__ __launch_bounds__(1024) void k_tridiag_prep(const Prob* __restrict__ 
   __shared__ double smax[16], sg[16];
   const Prob& P = probs[blockIdx.z];
   const int N = P.N;
-  const double* __restrict__ alpha = P.alpha;
-  double* __restrict__ e2 = P.e2;
-  double* __restrict__ scal = P.scal;
+  const BSE_GLOBAL double* __restrict__ alpha = gbl(P.alpha);
+  BSE_GLOBAL double* __restrict__ e2 = gbl(P.e2);
+  BSE_GLOBAL double* __restrict__ scal = gbl(P.scal);
   double m = 0.0, g = 0.0;
   for (int k = threadIdx.x; k < N; k += blockDim.x) {
     const double a = (k < N - 1) ? alpha[k] : 0.0;
@@ -67,7 +67,8 @@ __global__ __launch_bounds__(1024) void k_tridiag_prep(const Prob* __restrict__ 
   }
 }
 
-__device__ inline int sturm_count(const double* __restrict__ e2, int N, double x, double pivmin) {
+template <class Ptr>
+__device__ inline int sturm_count(Ptr e2, int N, double x, double pivmin) {
   double q = -x;
   if (fabs(q) < pivmin) q = -pivmin;
   int c = q < 0.0;
@@ -84,9 +85,9 @@ __global__ __launch_bounds__(64) void k_bisect(const Prob* __restrict__ probs) {
   const int N = P.N, n = P.n;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
-  const double* __restrict__ e2 = P.e2;
-  const double* __restrict__ scal = P.scal;
-  double* __restrict__ lam = P.lambda;
+  const BSE_CONST double* __restrict__ e2 = ro(P.e2);
+  const BSE_CONST double* __restrict__ scal = ro(P.scal);
+  BSE_GLOBAL double* __restrict__ lam = gbl(P.lambda);
   const double pivmin = scal[0];
   double lo = 0.0;
   double hi = scal[1] * (1.0 + 4.0 * EPS) + 4.0 * pivmin;
@@ -110,8 +111,8 @@ __global__ void k_shifts(const Prob* __restrict__ probs) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const Prob& P = probs[blockIdx.z];
   const int n = P.n;
-  const double* __restrict__ lam = P.lambda;
-  double* __restrict__ shift = P.shift;
+  const BSE_CONST double* __restrict__ lam = ro(P.lambda);
+  BSE_GLOBAL double* __restrict__ shift = gbl(P.shift);
   double prev = lam[0];
   shift[0] = prev;
   for (int j = 1; j < n; ++j) {
@@ -144,16 +145,16 @@ __global__ __launch_bounds__(64) void k_invit(const Prob* __restrict__ probs) {
   const int N = P.N, n = P.n;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
-  const double* __restrict__ alpha = P.alpha;
-  const double* __restrict__ scal = P.scal;
-  const double* __restrict__ shift = P.shift;
+  const BSE_CONST double* __restrict__ alpha = ro(P.alpha);
+  const BSE_CONST double* __restrict__ scal = ro(P.scal);
+  const BSE_GLOBAL double* __restrict__ shift = gbl(P.shift);
   const long sz = (long)N * n;
-  double* __restrict__ fd = P.inv;
-  double* __restrict__ fu = P.inv + sz;
-  double* __restrict__ fu2 = P.inv + 2 * sz;
-  double* __restrict__ fl = P.inv + 3 * sz;
-  unsigned char* __restrict__ fs = reinterpret_cast<unsigned char*>(P.inv + 4 * sz);
-  double* __restrict__ Vt = P.Vt;
+  BSE_GLOBAL double* __restrict__ fd = gbl(P.inv);
+  BSE_GLOBAL double* __restrict__ fu = gbl(P.inv + sz);
+  BSE_GLOBAL double* __restrict__ fu2 = gbl(P.inv + 2 * sz);
+  BSE_GLOBAL double* __restrict__ fl = gbl(P.inv + 3 * sz);
+  BSE_GLOBAL unsigned char* __restrict__ fs = gbl(reinterpret_cast<unsigned char*>(P.inv + 4 * sz));
+  BSE_GLOBAL double* __restrict__ Vt = gbl(P.Vt);
   const long ldn = n;
   const double pert = EPS * fmax(scal[1], SAFMIN);
   const double sh = shift[j];
@@ -234,9 +235,9 @@ __global__ __launch_bounds__(1024) void k_cluster_ids(const Prob* __restrict__ p
   __shared__ int sums[1024];
   const Prob& P = probs[blockIdx.z];
   const int n = P.n;
-  const double* __restrict__ lam = P.lambda;
-  const double* __restrict__ scal = P.scal;
-  int* __restrict__ cid = P.cid;
+  const BSE_GLOBAL double* __restrict__ lam = gbl(P.lambda);
+  const BSE_CONST double* __restrict__ scal = ro(P.scal);
+  BSE_GLOBAL int* __restrict__ cid = gbl(P.cid);
   const double ortol = 1e-3 * scal[1];
   const int T = blockDim.x;
   const int chunk = (n + T - 1) / T;
@@ -266,8 +267,8 @@ __global__ __launch_bounds__(256) void k_mask_gram(const Prob* __restrict__ prob
   const Prob& P = probs[blockIdx.z];
   const int n = P.n;
   const long ldg = n;
-  double* __restrict__ G = P.inv;
-  const int* __restrict__ cid = P.cid;
+  BSE_GLOBAL double* __restrict__ G = gbl(P.inv);
+  const BSE_GLOBAL int* __restrict__ cid = gbl(P.cid);
   const long r = (long)blockIdx.x * 64 + (threadIdx.x & 63);
   const long c0 = (long)blockIdx.y * 64 + (threadIdx.x >> 6) * 16;
   if (r >= n) return;
