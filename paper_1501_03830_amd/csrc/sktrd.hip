@@ -19,10 +19,16 @@
 //             (row sum for S v, column sum for -S^T v).  Workgroups stream
 //             64-column strips; partial sums go to fixed slots and are summed
 //             in a fixed order (deterministic).  Extra workgroups store v and
-//             the partial dot products V^T v, P^T v.
+//             the partial dot products V^T v, P^T v.  Every workgroup first
+//             builds the column's reflector (dlarfg convention) from the norm
+//             partials left by the previous update, all in the same order, so
+//             all of them hold the same tau and scale.
 //   sk_update reduces the partials into p, applies the panel corrections,
-//             brings the next column up to date, and the last workgroup to
-//             finish computes the next reflector (dlarfg convention).
+//             brings the next column up to date and leaves one partial
+//             squared norm of it per workgroup.
+// No workgroup waits for or signals another inside a launch: on this
+// multi-XCD device a release fence per workgroup costs tens of nanoseconds
+// each, serialised over the whole device.
 #include <algorithm>
 
 #include "common.h"
@@ -37,15 +43,13 @@ constexpr int NBMAX = 64;    // panel width bound
 constexpr int DUTY_BLK = 16; // row blocks per workgroup of the panel dot products
 constexpr int TMAX = 8;      // row tiles per strip workgroup (upper bound)
 
+// Reflector of the first column of a panel (sk_start) and the subdiagonal
+// entry of the column brought up to date by the last update.
 struct Ctrl {
   double tau;
   double scale;
   double x0;
   double pad0;
-  unsigned int cnt_diag;
-  unsigned int cnt_upd;
-  unsigned int pad1[2];
-  double c[2 * NBMAX];   // c[2l] = v_l . v,  c[2l+1] = p_l . v
 };
 
 __device__ inline void larfg(double x0, double xnorm, double& beta, double& tau, double& scale) {
@@ -134,7 +138,30 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
   BSE_GLOBAL double* __restrict__ Ycol = gbl(P.Ycol);
   BSE_GLOBAL double* __restrict__ dotpart = gbl(P.dotpart);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const double scale = ctrl->scale;
+  // Scale 1 / (x0 - beta) of column j's reflector.  The first column of a
+  // panel got it from sk_start.  Any other column was brought up to date by
+  // the previous update, whose workgroups (one per row block from row j)
+  // left partial squared norms of rows j+2.. and the subdiagonal entry x0;
+  // every workgroup reduces them in the same fixed order, so all hold the
+  // same tau and scale.  Branch-free, so that callers can issue their first
+  // loads before it.
+  auto column_scale = [&]() -> double {
+    const BSE_CONST double* __restrict__ normpart = ro(P.normpart);
+    const int nprev = (N - 1) / TS - j / TS + 1;
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = (lane + 64 * u < nprev) ? normpart[lane + 64 * u] : 0.0;
+    double ss = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
+    for (int q = lane + 512; q < nprev; q += 64) ss += normpart[q];
+    ss = wave_sum(ss);   // the same value in every lane
+    double beta, tau, sc;
+    larfg(ctrl->x0, sqrt(ss), beta, tau, sc);
+    if (i > 0 && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+      gbl(P.alpha)[j] = -beta;
+      gbl(P.tau)[j] = tau;
+    }
+    return uniform_double(i == 0 ? ctrl->scale : sc);
+  };
 
   if (blockIdx.y == 0) {
     // duty workgroup (d, g) covers row blocks d*DUTY_BLK .. +DUTY_BLK-1 and the
@@ -146,6 +173,7 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
     if (d >= nd) return;              // uniform
     if (g > 0 && 32 * g >= 2 * i) return;
     const int b0 = d * DUTY_BLK, b1 = min(nblk, b0 + DUTY_BLK);
+    const double scale = column_scale();
     double acc[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc[q] = 0.0;
@@ -190,28 +218,35 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
   const int wvu = __builtin_amdgcn_readfirstlane(wv);
   const long col0 = C0 + 16 * wvu;
   const auto vcol = W + (long)j * ld;   // column j holds x; v = scale * x below row s
-  double vc[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const long c = col0 + q;
-    const double x = vcol[c < N ? c : 0];
-    vc[q] = (c == s) ? 1.0 : ((c > s && c < N) ? scale * x : 0.0);
-  }
-  double cacc[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) cacc[q] = 0.0;
-  const bool strip_inside = C0 >= s;
   const auto colbase = W + col0 * ld;
-  // no barrier, no global store and no dependent load inside this loop: v at
-  // the tile's rows is fetched with the tile itself, and the next tile's
-  // loads are issued before the current tile is used (software pipeline)
-  double a[16], xr;
+  // the first tile and x at the strip's columns are loaded before the
+  // reflector is known
+  double a[16], xr, xc[16];
   {
     const int row_off = (int)((long)(R0 + rl0) * TS) + lane;
 #pragma unroll
     for (int q = 0; q < 16; ++q) a[q] = (colbase + (long)q * ld)[row_off];
     xr = vcol[row_off];
   }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const long c = col0 + q;
+    xc[q] = vcol[c < N ? c : 0];
+  }
+  const double scale = column_scale();
+  double vc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const long c = col0 + q;
+    vc[q] = (c == s) ? 1.0 : ((c > s && c < N) ? scale * xc[q] : 0.0);
+  }
+  double cacc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) cacc[q] = 0.0;
+  const bool strip_inside = C0 >= s;
+  // no barrier, no global store and no dependent load inside this loop: v at
+  // the tile's rows is fetched with the tile itself, and the next tile's
+  // loads are issued before the current tile is used (software pipeline)
   for (int rl = rl0; rl < rl1; ++rl) {
     const long rbase = (long)(R0 + rl) * TS;
     const long row = rbase + lane;
@@ -272,7 +307,6 @@ __global__ __launch_bounds__(256) void sk_update(const Prob* __restrict__ probs,
   __shared__ double pr[TS];
   __shared__ double red4[4];
   __shared__ double sval_s;
-  __shared__ int last_flag;
   const Prob& P = probs[blockIdx.z];
   const int N = P.N;
   if (j >= N - 2) return;  // uniform
@@ -299,7 +333,7 @@ __global__ __launch_bounds__(256) void sk_update(const Prob* __restrict__ probs,
   const BSE_CONST double* __restrict__ dotpart = ro(P.dotpart);
   const int tid = threadIdx.x;
   const int t = tid & 63, part = tid >> 6;
-  const double tau = ctrl->tau;
+  const double tau = tau_arr[j];   // written by sk_start or by this column's matvec
   if (tid < 2 * i) {
     // c[l] = sum of the symv duty workgroups' partial dot products
     const int nd = (nblk + DUTY_BLK - 1) / DUTY_BLK;   // 16 partials per 16384 rows
@@ -404,32 +438,19 @@ __global__ __launch_bounds__(256) void sk_update(const Prob* __restrict__ probs,
     double upd = W[r + (long)s * ld] + red2[0][t] + red2[1][t] + red2[2][t] + red2[3][t];
     upd += Y1[r + (long)(2 * i) * ldy] * sval_s - pr[t];
     W[r + (long)s * ld] = upd;
-    if (r == s + 1) ctrl->x0 = upd;
+    if (r == s + 1) {
+      ctrl->x0 = upd;
+      if (s == N - 2) {
+        // the last column has nothing below its subdiagonal: its reflector
+        // is the identity (dlarfg with a zero norm)
+        alpha[s] = -upd;
+        tau_arr[s] = 0.0;
+      }
+    }
     if (r >= s + 2) nrm = upd * upd;
   }
   nrm = block_sum(nrm, red4);
   if (tid == 0) normpart[b] = nrm;
-  if (arrive_last(&ctrl->cnt_upd, (unsigned)nblk, &last_flag)) {
-    double ss = 0.0;
-    for (int kk = tid; kk < nblk; kk += 256) ss += normpart[kk];
-    ss = block_sum(ss, red4);
-    if (tid == 0) {
-      double beta, tn, sc;
-      larfg(ctrl->x0, sqrt(ss), beta, tn, sc);
-      ctrl->tau = tn;
-      ctrl->scale = sc;
-      alpha[s] = -beta;
-      tau_arr[s] = tn;
-    }
-  }
-}
-
-__global__ void k_zero_ctrl(const Prob* __restrict__ probs) {
-  BSE_GLOBAL Ctrl* ctrl = (BSE_GLOBAL Ctrl*)probs[blockIdx.z].ctrl;
-  if (threadIdx.x == 0) {
-    ctrl->cnt_diag = 0u;
-    ctrl->cnt_upd = 0u;
-  }
 }
 
 }  // namespace
@@ -467,8 +488,6 @@ void sktrd_bind_work(char* base, long N, long ld, Prob* P) {
 int sktrd_batched(hipStream_t s, const Batch& b, KernelTimer* timer) {
   const int N0 = b.maxN();
   if (N0 < 2) return 0;
-  k_zero_ctrl<<<dim3(1, 1, (unsigned)b.count), 64, 0, s>>>(b.dev);
-  BSE_LAUNCHED();
   const int nb = NBMAX;
   for (int k0 = 0; k0 <= N0 - 2; k0 += nb) {
     const int nstart = b.active_N_above(k0 + 1);   // N - 2 >= k0
