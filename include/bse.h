@@ -54,6 +54,7 @@ extern "C" {
 #define BSE_EDEVICE (-1001)
 #define BSE_ENOTICKET (-1002)
 #define BSE_EUNSUPPORTED (-1003)
+#define BSE_EBUSY (-1004)
 
 /* precision policies */
 #define BSE_PREC_FP64 0        /* every stage in FP64                          */
@@ -75,7 +76,43 @@ extern "C" {
 #define BSE_STAGE_FINISH 9     /* Algorithm 3 steps 4-6, phase, weights        */
 #define BSE_NUM_STAGES 10
 
+/* request states reported by bse_poll */
+#define BSE_QUEUED 0           /* waiting for a slot and device memory          */
+#define BSE_RUNNING 1          /* in a batch on the device                      */
+#define BSE_DONE 2             /* outputs written; factors resident             */
+#define BSE_FAILED 3           /* info holds the reason                         */
+
 typedef struct bse_ctx bse_ctx;
+
+/* One eigensolve request for bse_submit: the arguments of bse_solve. */
+typedef struct bse_request {
+  int n;                 /* order of A and B, >= 1                            */
+  const void* A;         /* complex n x n, lower triangle read                */
+  int lda;               /* >= n                                              */
+  const void* B;         /* complex n x n, lower triangle read                */
+  int ldb;               /* >= n                                              */
+  int prec;              /* BSE_PREC_FP64                                     */
+  unsigned flags;        /* BSE_WANT_VECTORS | BSE_WANT_WEIGHTS               */
+  double* lambda;        /* out: n doubles                                    */
+  void* X;               /* out: complex 2n x n or NULL without vectors       */
+  int ldx;               /* >= 2n with vectors                                */
+  const void* d_r;       /* complex 2n, read with BSE_WANT_WEIGHTS            */
+  const void* d_l;       /* NULL means d_l = d_r                              */
+  void* w;               /* out: n complex weights with BSE_WANT_WEIGHTS      */
+} bse_request;
+
+/* Server counters (bse_serve_stats). */
+typedef struct bse_serve_counters {
+  size_t pool_bytes;         /* device memory of the request pool            */
+  size_t used_bytes;         /* held now: running batches + resident results */
+  size_t peak_used_bytes;    /* largest value of used_bytes at an admission  */
+  long long queued;          /* requests waiting                             */
+  long long inflight;        /* requests in batches on the device            */
+  long long max_inflight;    /* largest inflight seen                        */
+  long long batches;         /* batches started                              */
+  long long solved;          /* requests finished (done or failed)           */
+  int slots;                 /* concurrent batches (worker streams)          */
+} bse_serve_counters;
 
 /* Per-call timing, filled when a non-NULL pointer is passed (host memory). */
 typedef struct bse_report {
@@ -189,6 +226,65 @@ int bse_solve_batched(bse_ctx* ctx, int count, const int* n, const void* const* 
                       const void* const* B, const int* ldb, int prec, unsigned flags,
                       double* const* lambda, void* const* X, const int* ldx, const void* const* d,
                       void* const* w, int* info, bse_report* rep);
+
+/* ---------------------------------------------------------------------------
+ * Request serving (continuous batching).  bse_submit queues a solve and
+ * returns at once.  A fixed number of slots -- each a library worker thread
+ * with its own HIP stream -- takes work from the queue: the oldest request
+ * that fits in the free part of the request pool, with queued requests of
+ * similar order (within a factor of two) and kind up to a batch limit, is
+ * solved as one bse_solve_batched-style batch.  Requests that arrive while
+ * other batches run are admitted as soon as a slot and pool memory are
+ * free, and their work overlaps with the running batches on the device.
+ * The oldest request is never bypassed (no starvation).  Each result is bit
+ * for bit the one bse_solve gives for the request alone.
+ *
+ * Ordering: work queued on the context's stream before bse_submit (for
+ * instance the writes that produced A and B) is complete before the request's
+ * batch reads its inputs.  Outputs may be read once bse_poll reports
+ * BSE_DONE.
+ *
+ * Ownership: the request's input and output buffers must stay valid until
+ * bse_poll reports BSE_DONE or BSE_FAILED.  The request's workspace (its
+ * factors L, the reflectors of W and the eigenvector workspace) stays
+ * resident in the pool until bse_release; an unreleased result keeps its
+ * pool memory, so later requests wait for it.  The server's threads are
+ * internal; the context itself is still not thread-safe for callers.
+ * ------------------------------------------------------------------------ */
+
+/* Configure the server before the first bse_submit (else defaults are used):
+ * pool_bytes of device memory for request workspaces (0: half of the free
+ * device memory), `slots` concurrent batches (0: 4; at most 16) and at most
+ * `max_batch` requests per batch (0: 64; at most 4096).  The pool is a
+ * separate device allocation, independent of the context's arena.  Returns
+ * BSE_EBUSY if the server is already running, -3 / -4 for bad slots /
+ * max_batch, BSE_ENOMEM if the pool cannot be allocated. */
+int bse_serve_config(bse_ctx* ctx, size_t pool_bytes, int slots, int max_batch);
+
+/* Queue a request (argument 2, copied); *ticket (argument 3) identifies it.
+ * Returns -2 for an invalid request field (bse_last_error() names it), -3
+ * for a NULL ticket, BSE_ENOMEM if its footprint can never fit the pool. */
+int bse_submit(bse_ctx* ctx, const bse_request* req, uint64_t* ticket);
+
+/* State of a request: *state one of BSE_QUEUED, BSE_RUNNING, BSE_DONE,
+ * BSE_FAILED; *info as bse_solve would return it (0, +k for a minor of M
+ * that is not positive definite, or a negative BSE_* code).  Either pointer
+ * may be NULL.  Returns BSE_ENOTICKET for an unknown or released ticket. */
+int bse_poll(bse_ctx* ctx, uint64_t ticket, int* state, int* info);
+
+/* Release a request: frees its resident workspace (DONE / FAILED) or
+ * cancels it (QUEUED).  Returns BSE_EBUSY while it is running and
+ * BSE_ENOTICKET for an unknown ticket. */
+int bse_release(bse_ctx* ctx, uint64_t ticket);
+
+/* Server-side timestamps of a request in microseconds since the server
+ * started: submission, start of its batch, completion (0 if not reached).
+ * Any pointer may be NULL. */
+int bse_ticket_times(bse_ctx* ctx, uint64_t ticket, double* t_submit_us, double* t_start_us,
+                     double* t_done_us);
+
+/* Counters of the server (all zero before the first bse_submit). */
+int bse_serve_stats(bse_ctx* ctx, bse_serve_counters* stats);
 
 /* ---------------------------------------------------------------------------
  * Stage entry points.  Each runs one step of the chain on caller buffers so

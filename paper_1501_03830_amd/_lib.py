@@ -13,6 +13,10 @@ BSE_ENOMEM = -1000
 BSE_EDEVICE = -1001
 BSE_ENOTICKET = -1002
 BSE_EUNSUPPORTED = -1003
+BSE_EBUSY = -1004
+
+BSE_QUEUED, BSE_RUNNING, BSE_DONE, BSE_FAILED = 0, 1, 2, 3
+STATE_NAMES = {0: "queued", 1: "running", 2: "done", 3: "failed"}
 
 BSE_PREC_FP64 = 0
 
@@ -49,6 +53,41 @@ class BseReport(ctypes.Structure):
         }
 
 
+class BseRequest(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int),
+        ("A", ctypes.c_void_p),
+        ("lda", ctypes.c_int),
+        ("B", ctypes.c_void_p),
+        ("ldb", ctypes.c_int),
+        ("prec", ctypes.c_int),
+        ("flags", ctypes.c_uint),
+        ("lambda_", ctypes.c_void_p),
+        ("X", ctypes.c_void_p),
+        ("ldx", ctypes.c_int),
+        ("d_r", ctypes.c_void_p),
+        ("d_l", ctypes.c_void_p),
+        ("w", ctypes.c_void_p),
+    ]
+
+
+class BseServeCounters(ctypes.Structure):
+    _fields_ = [
+        ("pool_bytes", ctypes.c_size_t),
+        ("used_bytes", ctypes.c_size_t),
+        ("peak_used_bytes", ctypes.c_size_t),
+        ("queued", ctypes.c_longlong),
+        ("inflight", ctypes.c_longlong),
+        ("max_inflight", ctypes.c_longlong),
+        ("batches", ctypes.c_longlong),
+        ("solved", ctypes.c_longlong),
+        ("slots", ctypes.c_int),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 # (name, restype, argtypes) for every symbol declared in include/bse.h
 _P = ctypes.c_void_p
 _I = ctypes.c_int
@@ -67,6 +106,12 @@ SIGNATURES = [
                                ctypes.POINTER(_P), ctypes.POINTER(_I), _I, _U, ctypes.POINTER(_P),
                                ctypes.POINTER(_P), ctypes.POINTER(_I), ctypes.POINTER(_P),
                                ctypes.POINTER(_P), ctypes.POINTER(_I), ctypes.POINTER(BseReport)]),
+    ("bse_serve_config", _I, [_P, ctypes.c_size_t, _I, _I]),
+    ("bse_submit", _I, [_P, ctypes.POINTER(BseRequest), ctypes.POINTER(ctypes.c_uint64)]),
+    ("bse_poll", _I, [_P, ctypes.c_uint64, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    ("bse_release", _I, [_P, ctypes.c_uint64]),
+    ("bse_ticket_times", _I, [_P, ctypes.c_uint64, _D, _D, _D]),
+    ("bse_serve_stats", _I, [_P, ctypes.POINTER(BseServeCounters)]),
     ("bse_build_M", _I, [_P, _I, _P, _I, _P, _I, _P, _I]),
     ("bse_potrf", _I, [_P, _I, _P, _I]),
     ("bse_form_W", _I, [_P, _I, _P, _I, _P, _I]),

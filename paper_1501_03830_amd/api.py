@@ -175,6 +175,74 @@ class Context:
             })
         return out, rep
 
+    # ---------------------------------------------------------------- serving
+    def serve_config(self, pool_bytes: int = 0, slots: int = 0, max_batch: int = 0):
+        """Configure the request server before the first submit."""
+        _lib.check(self.lib.bse_serve_config(self.h, pool_bytes, slots, max_batch), "bse_serve_config")
+
+    def submit_raw(self, n: int, Ac: torch.Tensor, Bc: torch.Tensor, lam: torch.Tensor,
+                   Xbuf: torch.Tensor | None = None, drb: torch.Tensor | None = None,
+                   dlb: torch.Tensor | None = None, w: torch.Tensor | None = None) -> int:
+        """bse_submit on column-major device buffers; returns the ticket.  The
+        buffers are kept referenced here until the ticket is released."""
+        flags = 0
+        if Xbuf is not None:
+            flags |= _lib.BSE_WANT_VECTORS
+        if drb is not None:
+            flags |= _lib.BSE_WANT_WEIGHTS
+        req = _lib.BseRequest(n, Ac.data_ptr(), n, Bc.data_ptr(), n, _lib.BSE_PREC_FP64, flags, lam.data_ptr(),
+                              None if Xbuf is None else Xbuf.data_ptr(), 2 * n,
+                              None if drb is None else drb.data_ptr(), None if dlb is None else dlb.data_ptr(),
+                              None if w is None else w.data_ptr())
+        t = ctypes.c_uint64()
+        _lib.check(self.lib.bse_submit(self.h, ctypes.byref(req), ctypes.byref(t)), "bse_submit")
+        if not hasattr(self, "_keep"):
+            self._keep = {}
+        self._keep[t.value] = (Ac, Bc, lam, Xbuf, drb, dlb, w)
+        return t.value
+
+    def submit(self, A: torch.Tensor, B: torch.Tensor, d_r: torch.Tensor | None = None, vectors: bool = True):
+        """Queue a solve of logical complex matrices; returns (ticket, outputs)
+        where outputs = {lam, X, w} are filled once the ticket is done."""
+        n = A.shape[0]
+        dev = self.device
+        Ac = to_colmajor(A.to(torch.complex128), dev)
+        Bc = to_colmajor(B.to(torch.complex128), dev)
+        lam = torch.empty(n, dtype=torch.float64, device=dev)
+        want_x = vectors or d_r is not None
+        Xbuf = torch.empty((n, 2 * n), dtype=torch.complex128, device=dev) if want_x else None
+        drb = d_r.to(dev, torch.complex128).contiguous() if d_r is not None else None
+        w = torch.empty(n, dtype=torch.complex128, device=dev) if d_r is not None else None
+        t = self.submit_raw(n, Ac, Bc, lam, Xbuf, drb, None, w)
+        return t, {"lam": lam, "X": None if Xbuf is None else from_colmajor(Xbuf), "w": w}
+
+    def poll(self, ticket: int):
+        """(state, info) of a ticket; raises for unknown tickets."""
+        st, info = ctypes.c_int(), ctypes.c_int()
+        _lib.check(self.lib.bse_poll(self.h, ticket, ctypes.byref(st), ctypes.byref(info)), "bse_poll")
+        return st.value, info.value
+
+    def release(self, ticket: int) -> int:
+        """bse_release; returns its code (0, or BSE_EBUSY while running)."""
+        rc = self.lib.bse_release(self.h, ticket)
+        if rc == 0 and getattr(self, "_keep", None) is not None:
+            self._keep.pop(ticket, None)
+        elif rc not in (0, _lib.BSE_EBUSY):
+            _lib.check(rc, "bse_release")
+        return rc
+
+    def ticket_times(self, ticket: int):
+        """(submit, start, done) server timestamps in microseconds."""
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _lib.check(self.lib.bse_ticket_times(self.h, ticket, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+                   "bse_ticket_times")
+        return a.value, b.value, c.value
+
+    def serve_stats(self) -> dict:
+        st = _lib.BseServeCounters()
+        _lib.check(self.lib.bse_serve_stats(self.h, ctypes.byref(st)), "bse_serve_stats")
+        return st.as_dict()
+
     # ----------------------------------------------------------------- stages
     def build_M(self, A: torch.Tensor, B: torch.Tensor) -> torch.Tensor:
         n = A.shape[0]

@@ -1,0 +1,53 @@
+// Internal interface between the solve driver (solver.hip) and the request
+// server (serve.hip): per-problem workspace layout, execution lanes and the
+// batched chain of Algorithm 1 / Algorithm 3.
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace bse {
+
+// Execution resources of one chain at a time: a stream and pinned host
+// mirrors of the batch descriptors and info words.
+struct Lane {
+  hipStream_t stream = nullptr;
+  Prob* hprobs = nullptr;   // pinned host mirror of the descriptors
+  int* hinfo = nullptr;     // pinned host copy of the info words
+  int hcap = 0;
+  hipEvent_t ev[BSE_NUM_STAGES + 1] = {};
+  bool events = false;
+  bool timing = false;                 // per-launch timing of the skew matvec
+  std::vector<hipEvent_t> kev;         // event pool for it
+};
+int lane_reserve(Lane* L, int count);   // host mirrors for `count` problems
+void lane_release(Lane* L);             // frees events and host mirrors
+
+// Device workspace of one problem of order N (bytes, 256-aligned) and of the
+// descriptor/info header of a batch of `count` problems.
+size_t problem_bytes(long N);
+size_t header_bytes(int count);
+
+// Descriptor storage of a batch in device memory.
+struct Setup {
+  Prob* dprobs = nullptr;   // device descriptors (count)
+  int* dinfo = nullptr;     // device info words, 2 per problem slot
+  size_t total = 0;         // workspace bytes of the batch (for reports)
+};
+// Header at `header` (header_bytes(count)); descriptor slot i gets the
+// workspace at bases[i] (problem_bytes(Ns[i])) and info words 2i, 2i+1.
+// The host mirror L->hprobs[0..count) is filled; callers then set the
+// caller-buffer fields (A, B, lambda, X, ...).
+int setup_batch(Lane* L, int count, const long* Ns, char* header, char* const* bases, Setup* S);
+
+// The chain for the batch in L->hprobs[0..count) (sorted by decreasing N).
+// Blocks until the device work is done.  On return L->hinfo[2i], [2i+1]
+// hold, for descriptor slot i, the Cholesky info of M (> 0: not definite)
+// and of the cluster Gram matrix (> 0: reorthogonalisation failed).
+int run_chain(Lane* L, const Setup& S, int count, bool vectors, bse_report* rep);
+
+int set_error(int code, const char* msg);
+
+}  // namespace bse

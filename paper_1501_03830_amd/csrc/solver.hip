@@ -14,23 +14,17 @@
 #include <string>
 #include <vector>
 
-#include "common.h"
-#include "kernels.h"
+#include "driver.h"
+#include "serve.h"
 
 struct bse_ctx {
   int device = 0;
-  hipStream_t stream = nullptr;
   void* arena = nullptr;        // caller-provided workspace (not owned)
   size_t arena_bytes = 0;
   void* own = nullptr;          // library-owned workspace
   size_t own_bytes = 0;
-  hipEvent_t ev[BSE_NUM_STAGES + 1] = {};
-  bool events = false;
-  bool timing = false;               // per-launch timing of the skew matvec
-  std::vector<hipEvent_t> kev;       // event pool for it
-  bse::Prob* hprobs = nullptr;       // pinned host mirror of the descriptors
-  int* hinfo = nullptr;              // pinned host copy of the info words
-  int hcap = 0;
+  bse::Lane lane;               // the caller's stream and host mirrors
+  bse::Server* server = nullptr;   // request server, made on first use
 };
 
 namespace bse {
@@ -56,7 +50,7 @@ int set_hip_error(hipError_t e, const char* what, const char* file, int line) {
   return BSE_EDEVICE;
 }
 
-static int set_error(int code, const char* msg) {
+int set_error(int code, const char* msg) {
   g_last_error = msg;
   return code;
 }
@@ -111,8 +105,10 @@ static Plan make_plan(long N) {
   return p;
 }
 
-// Descriptor array and info words at the start of the workspace.
-static size_t header_bytes(int count) {
+size_t problem_bytes(long N) { return make_plan(N).total; }
+
+// Descriptor array and info words of a batch.
+size_t header_bytes(int count) {
   return (size_t)round_up((long)(count * sizeof(Prob)), 256) + (size_t)round_up((long)(count * 2 * sizeof(int)), 256);
 }
 
@@ -148,7 +144,7 @@ static int get_workspace(bse_ctx* ctx, size_t bytes, char** base) {
   }
   if (ctx->own_bytes < bytes) {
     if (ctx->own) {
-      BSE_HIP(hipStreamSynchronize(ctx->stream));
+      BSE_HIP(hipStreamSynchronize(ctx->lane.stream));
       BSE_HIP(hipFree(ctx->own));
       ctx->own = nullptr;
       ctx->own_bytes = 0;
@@ -167,156 +163,168 @@ static int get_workspace(bse_ctx* ctx, size_t bytes, char** base) {
   return 0;
 }
 
-// Pinned host mirror for `count` descriptors (the context's stream is idle
-// between calls, so the old buffer can be released).
-static int ensure_host(bse_ctx* ctx, int count) {
-  if (ctx->hcap >= count) return 0;
-  if (ctx->hprobs) BSE_HIP(hipHostFree(ctx->hprobs));
-  if (ctx->hinfo) BSE_HIP(hipHostFree(ctx->hinfo));
-  ctx->hprobs = nullptr;
-  ctx->hinfo = nullptr;
-  ctx->hcap = 0;
+// Pinned host mirrors for `count` descriptors (the lane's stream is idle
+// between calls, so the old buffers can be released).
+int lane_reserve(Lane* L, int count) {
+  if (L->hcap >= count) return 0;
+  if (L->hprobs) BSE_HIP(hipHostFree(L->hprobs));
+  if (L->hinfo) BSE_HIP(hipHostFree(L->hinfo));
+  L->hprobs = nullptr;
+  L->hinfo = nullptr;
+  L->hcap = 0;
   const int cap = std::max(count, 16);
-  BSE_HIP(hipHostMalloc(reinterpret_cast<void**>(&ctx->hprobs), cap * sizeof(Prob), hipHostMallocDefault));
-  BSE_HIP(hipHostMalloc(reinterpret_cast<void**>(&ctx->hinfo), cap * 2 * sizeof(int), hipHostMallocDefault));
-  ctx->hcap = cap;
+  BSE_HIP(hipHostMalloc(reinterpret_cast<void**>(&L->hprobs), cap * sizeof(Prob), hipHostMallocDefault));
+  BSE_HIP(hipHostMalloc(reinterpret_cast<void**>(&L->hinfo), cap * 2 * sizeof(int), hipHostMallocDefault));
+  L->hcap = cap;
   return 0;
 }
 
-static int ensure_events(bse_ctx* ctx) {
-  if (ctx->events) return 0;
-  for (int i = 0; i <= BSE_NUM_STAGES; ++i) BSE_HIP(hipEventCreate(&ctx->ev[i]));
-  ctx->events = true;
+void lane_release(Lane* L) {
+  if (L->events)
+    for (int i = 0; i <= BSE_NUM_STAGES; ++i) (void)hipEventDestroy(L->ev[i]);
+  L->events = false;
+  for (hipEvent_t e : L->kev) (void)hipEventDestroy(e);
+  L->kev.clear();
+  if (L->hprobs) (void)hipHostFree(L->hprobs);
+  if (L->hinfo) (void)hipHostFree(L->hinfo);
+  L->hprobs = nullptr;
+  L->hinfo = nullptr;
+  L->hcap = 0;
+}
+
+static int ensure_events(Lane* L) {
+  if (L->events) return 0;
+  for (int i = 0; i <= BSE_NUM_STAGES; ++i) BSE_HIP(hipEventCreate(&L->ev[i]));
+  L->events = true;
   return 0;
 }
 
-static int mark(bse_ctx* ctx, bool timed, int i) {
-  if (timed) BSE_HIP(hipEventRecord(ctx->ev[i], ctx->stream));
+static int mark(Lane* L, bool timed, int i) {
+  if (timed) BSE_HIP(hipEventRecord(L->ev[i], L->stream));
   return 0;
 }
 
-// A batch being set up: workspace, descriptor storage, original order.
-struct Setup {
-  char* base = nullptr;
-  Prob* dprobs = nullptr;   // device descriptors
-  int* dinfo = nullptr;     // device info words, 2 per problem (original order)
-  size_t total = 0;
-};
-
-// Workspace for problems of orders N[0..count) (any order); descriptors are
-// bound in the order given.
-static int setup_batch(bse_ctx* ctx, int count, const long* Ns, Setup* S) {
-  BSE_TRY(ensure_host(ctx, count));
-  size_t total = header_bytes(count);
-  std::vector<Plan> plans(count);
+int setup_batch(Lane* L, int count, const long* Ns, char* header, char* const* bases, Setup* S) {
+  BSE_TRY(lane_reserve(L, count));
+  S->dprobs = reinterpret_cast<Prob*>(header);
+  S->dinfo = reinterpret_cast<int*>(header + round_up((long)(count * sizeof(Prob)), 256));
+  S->total = header_bytes(count);
   for (int i = 0; i < count; ++i) {
-    plans[i] = make_plan(Ns[i]);
-    total += plans[i].total;
-  }
-  BSE_TRY(get_workspace(ctx, total, &S->base));
-  S->total = total;
-  S->dprobs = reinterpret_cast<Prob*>(S->base);
-  S->dinfo = reinterpret_cast<int*>(S->base + round_up((long)(count * sizeof(Prob)), 256));
-  size_t off = header_bytes(count);
-  for (int i = 0; i < count; ++i) {
-    Prob& P = ctx->hprobs[i];
+    const Plan plan = make_plan(Ns[i]);
+    Prob& P = L->hprobs[i];
     memset(&P, 0, sizeof(P));
-    bind_problem(plans[i], S->base + off, &P);
+    bind_problem(plan, bases[i], &P);
     P.info = S->dinfo + 2 * i;
-    off += plans[i].total;
+    S->total += plan.total;
   }
   return 0;
 }
 
-static int upload(bse_ctx* ctx, const Setup& S, int count) {
-  BSE_HIP(hipMemcpyAsync(S.dprobs, ctx->hprobs, count * sizeof(Prob), hipMemcpyHostToDevice, ctx->stream));
+// Workspace from the context (arena or own allocation) for problems of
+// orders Ns[0..count), laid out header first, then problem by problem.
+static int setup_ctx_batch(bse_ctx* ctx, int count, const long* Ns, Setup* S) {
+  size_t total = header_bytes(count);
+  std::vector<size_t> offs(count);
+  for (int i = 0; i < count; ++i) {
+    offs[i] = total;
+    total += problem_bytes(Ns[i]);
+  }
+  char* base = nullptr;
+  BSE_TRY(get_workspace(ctx, total, &base));
+  std::vector<char*> bases(count);
+  for (int i = 0; i < count; ++i) bases[i] = base + offs[i];
+  return setup_batch(&ctx->lane, count, Ns, base, bases.data(), S);
+}
+
+static int upload(Lane* L, const Setup& S, int count) {
+  BSE_HIP(hipMemcpyAsync(S.dprobs, L->hprobs, count * sizeof(Prob), hipMemcpyHostToDevice, L->stream));
   return 0;
 }
 
-static int read_infos(bse_ctx* ctx, const Setup& S, int count) {
-  BSE_HIP(hipMemcpyAsync(ctx->hinfo, S.dinfo, count * 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-  BSE_HIP(hipStreamSynchronize(ctx->stream));
+static int read_infos(Lane* L, const Setup& S, int count) {
+  BSE_HIP(hipMemcpyAsync(L->hinfo, S.dinfo, count * 2 * sizeof(int), hipMemcpyDeviceToHost, L->stream));
+  BSE_HIP(hipStreamSynchronize(L->stream));
   return 0;
 }
 
 // The chain for a batch whose descriptors (sorted by decreasing N) are in
-// ctx->hprobs[0..count).  On return ctx->hinfo holds, per original slot,
+// L->hprobs[0..count).  On return L->hinfo holds, per original slot,
 // info[0] (Cholesky of M, > 0 = not definite) and info[1] (Cholesky of a
 // cluster Gram matrix, > 0 = reorthogonalisation failed).
-static int run_chain(bse_ctx* ctx, const Setup& S, int count, bool vectors, bse_report* rep) {
-  hipStream_t s = ctx->stream;
+int run_chain(Lane* L, const Setup& S, int count, bool vectors, bse_report* rep) {
+  hipStream_t s = L->stream;
   const bool timed = rep != nullptr;
-  if (timed) BSE_TRY(ensure_events(ctx));
-  BSE_TRY(upload(ctx, S, count));
+  if (timed) BSE_TRY(ensure_events(L));
+  BSE_TRY(upload(L, S, count));
   Batch b;
   b.count = count;
-  b.host = ctx->hprobs;
+  b.host = L->hprobs;
   b.dev = S.dprobs;
 
-  BSE_TRY(mark(ctx, timed, 0));
+  BSE_TRY(mark(L, timed, 0));
   BSE_TRY(build_M_batched(s, b));
-  BSE_TRY(mark(ctx, timed, 1));
+  BSE_TRY(mark(L, timed, 1));
   BSE_TRY(potrf_batched(s, b, 0, true));
-  BSE_TRY(mark(ctx, timed, 2));
-  BSE_TRY(read_infos(ctx, S, count));
+  BSE_TRY(mark(L, timed, 2));
+  BSE_TRY(read_infos(L, S, count));
   // drop the problems whose M is not definite; the rest keep their order
   int live = 0;
   for (int i = 0; i < count; ++i) {
-    const Prob& P = ctx->hprobs[i];
-    if (ctx->hinfo[P.info - S.dinfo] == 0) {
-      if (live != i) ctx->hprobs[live] = P;
+    const Prob& P = L->hprobs[i];
+    if (L->hinfo[P.info - S.dinfo] == 0) {
+      if (live != i) L->hprobs[live] = P;
       ++live;
     }
   }
   if (live < count) {
     b.count = live;
-    if (live > 0) BSE_TRY(upload(ctx, S, live));
+    if (live > 0) BSE_TRY(upload(L, S, live));
   }
   BSE_TRY(form_W_batched(s, b, false));
-  BSE_TRY(mark(ctx, timed, 3));
+  BSE_TRY(mark(L, timed, 3));
   KernelTimer ktimer;
-  if (ctx->timing && b.count > 0) {
+  if (L->timing && b.count > 0) {
     const long N0 = b.maxN();
     const size_t need = 2 * (size_t)(N0 > 2 ? N0 - 2 : 0);
-    while (ctx->kev.size() < need) {
+    while (L->kev.size() < need) {
       hipEvent_t e;
       BSE_HIP(hipEventCreate(&e));
-      ctx->kev.push_back(e);
+      L->kev.push_back(e);
     }
-    ktimer.ev = ctx->kev.data();
-    ktimer.cap = (int)ctx->kev.size();
+    ktimer.ev = L->kev.data();
+    ktimer.cap = (int)L->kev.size();
   }
-  BSE_TRY(sktrd_batched(s, b, ctx->timing ? &ktimer : nullptr));
-  BSE_TRY(mark(ctx, timed, 4));
+  BSE_TRY(sktrd_batched(s, b, L->timing ? &ktimer : nullptr));
+  BSE_TRY(mark(L, timed, 4));
   BSE_TRY(bisect_batched(s, b));
-  BSE_TRY(mark(ctx, timed, 5));
+  BSE_TRY(mark(L, timed, 5));
   if (vectors) {
     BSE_TRY(invit_batched(s, b));
-    BSE_TRY(mark(ctx, timed, 6));
+    BSE_TRY(mark(L, timed, 6));
     BSE_TRY(reorth_batched(s, b));
-    BSE_TRY(mark(ctx, timed, 7));
+    BSE_TRY(mark(L, timed, 7));
     BSE_TRY(apply_UD_batched(s, b));
-    BSE_TRY(mark(ctx, timed, 8));
+    BSE_TRY(mark(L, timed, 8));
     BSE_TRY(gemm_batched(s, b, b.count, GOP_APPLY_L, 0));
-    BSE_TRY(mark(ctx, timed, 9));
+    BSE_TRY(mark(L, timed, 9));
     BSE_TRY(finish_batched(s, b));
   } else {
-    for (int i = 6; i <= 9; ++i) BSE_TRY(mark(ctx, timed, i));
+    for (int i = 6; i <= 9; ++i) BSE_TRY(mark(L, timed, i));
   }
-  BSE_TRY(mark(ctx, timed, 10));
-  BSE_TRY(read_infos(ctx, S, count));
+  BSE_TRY(mark(L, timed, 10));
+  BSE_TRY(read_infos(L, S, count));
   if (timed) {
     memset(rep, 0, sizeof(*rep));
     float ms = 0.f;
     for (int i = 0; i < BSE_NUM_STAGES; ++i) {
-      BSE_HIP(hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]));
+      BSE_HIP(hipEventElapsedTime(&ms, L->ev[i], L->ev[i + 1]));
       rep->stage_ms[i] = ms;
     }
-    BSE_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[BSE_NUM_STAGES]));
+    BSE_HIP(hipEventElapsedTime(&ms, L->ev[0], L->ev[BSE_NUM_STAGES]));
     rep->total_ms = ms;
     rep->prec = BSE_PREC_FP64;
     rep->workspace_bytes = S.total;
-    if (ctx->timing) {
+    if (L->timing) {
       double tot = 0.0;
       for (int i = 0; i + 1 < ktimer.used; i += 2) {
         BSE_HIP(hipEventElapsedTime(&ms, ktimer.ev[i], ktimer.ev[i + 1]));
@@ -337,15 +345,12 @@ static int prologue(bse_ctx* ctx) {
 }
 
 // One problem of order N for the stage entry points.
-static int setup_single(bse_ctx* ctx, long N, Setup* S) {
-  BSE_TRY(setup_batch(ctx, 1, &N, S));
-  return 0;
-}
+static int setup_single(bse_ctx* ctx, long N, Setup* S) { return setup_ctx_batch(ctx, 1, &N, S); }
 
 static Batch single_batch(bse_ctx* ctx, const Setup& S) {
   Batch b;
   b.count = 1;
-  b.host = ctx->hprobs;
+  b.host = ctx->lane.hprobs;
   b.dev = S.dprobs;
   return b;
 }
@@ -373,7 +378,7 @@ int bse_ctx_create(bse_ctx** ctx, int device, void* arena, size_t arena_bytes, v
   c->device = device;
   c->arena = arena;
   c->arena_bytes = arena_bytes;
-  c->stream = static_cast<hipStream_t>(stream);
+  c->lane.stream = static_cast<hipStream_t>(stream);
   *ctx = c;
   return 0;
 }
@@ -381,20 +386,17 @@ int bse_ctx_create(bse_ctx** ctx, int device, void* arena, size_t arena_bytes, v
 int bse_ctx_destroy(bse_ctx* ctx) {
   if (!ctx) return 0;
   (void)hipSetDevice(ctx->device);
-  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->server) server_destroy(ctx->server);
+  (void)hipStreamSynchronize(ctx->lane.stream);
   if (ctx->own) (void)hipFree(ctx->own);
-  if (ctx->events)
-    for (int i = 0; i <= BSE_NUM_STAGES; ++i) (void)hipEventDestroy(ctx->ev[i]);
-  for (hipEvent_t e : ctx->kev) (void)hipEventDestroy(e);
-  if (ctx->hprobs) (void)hipHostFree(ctx->hprobs);
-  if (ctx->hinfo) (void)hipHostFree(ctx->hinfo);
+  lane_release(&ctx->lane);
   delete ctx;
   return 0;
 }
 
 int bse_ctx_set_timing(bse_ctx* ctx, int enable) {
   if (!ctx) return set_error(-1, "ctx is NULL");
-  ctx->timing = enable != 0;
+  ctx->lane.timing = enable != 0;
   return 0;
 }
 
@@ -437,8 +439,8 @@ int bse_solve(bse_ctx* ctx, int n, const void* A, int lda, const void* B, int ld
   BSE_TRY(prologue(ctx));
   Setup S;
   const long N = 2L * n;
-  BSE_TRY(setup_batch(ctx, 1, &N, &S));
-  Prob& P = ctx->hprobs[0];
+  BSE_TRY(setup_ctx_batch(ctx, 1, &N, &S));
+  Prob& P = ctx->lane.hprobs[0];
   P.A = static_cast<const double*>(A);
   P.lda = lda;
   P.B = static_cast<const double*>(B);
@@ -450,10 +452,10 @@ int bse_solve(bse_ctx* ctx, int n, const void* A, int lda, const void* B, int ld
   P.dl = static_cast<const double*>(d_l);
   P.w = static_cast<double*>(w);
   P.flags = flags;
-  BSE_TRY(run_chain(ctx, S, 1, vec, rep));
+  BSE_TRY(run_chain(&ctx->lane, S, 1, vec, rep));
   if (rep) rep->n = n;
-  if (ctx->hinfo[0] != 0) return ctx->hinfo[0];
-  if (vec && ctx->hinfo[1] != 0) return set_error(BSE_EDEVICE, "cluster Gram matrix not positive definite");
+  if (ctx->lane.hinfo[0] != 0) return ctx->lane.hinfo[0];
+  if (vec && ctx->lane.hinfo[1] != 0) return set_error(BSE_EDEVICE, "cluster Gram matrix not positive definite");
   return 0;
 }
 
@@ -500,10 +502,10 @@ int bse_solve_batched(bse_ctx* ctx, int count, const int* n, const void* const* 
   std::vector<long> Ns(count);
   for (int k = 0; k < count; ++k) Ns[k] = 2L * n[order[k]];
   Setup S;
-  BSE_TRY(setup_batch(ctx, count, Ns.data(), &S));
+  BSE_TRY(setup_ctx_batch(ctx, count, Ns.data(), &S));
   for (int k = 0; k < count; ++k) {
     const int i = order[k];
-    Prob& P = ctx->hprobs[k];
+    Prob& P = ctx->lane.hprobs[k];
     P.A = static_cast<const double*>(A[i]);
     P.lda = lda[i];
     P.B = static_cast<const double*>(B[i]);
@@ -516,14 +518,82 @@ int bse_solve_batched(bse_ctx* ctx, int count, const int* n, const void* const* 
     P.w = wts ? static_cast<double*>(w[i]) : nullptr;
     P.flags = flags;
   }
-  BSE_TRY(run_chain(ctx, S, count, vec, rep));
+  BSE_TRY(run_chain(&ctx->lane, S, count, vec, rep));
   if (rep) rep->n = n[order[0]];
   for (int k = 0; k < count; ++k) {
     const int i = order[k];
-    const int i0 = ctx->hinfo[2 * k], i1 = ctx->hinfo[2 * k + 1];
+    const int i0 = ctx->lane.hinfo[2 * k], i1 = ctx->lane.hinfo[2 * k + 1];
     info[i] = (i0 != 0) ? i0 : ((vec && i1 != 0) ? BSE_EDEVICE : 0);
   }
   return 0;
+}
+
+// ---------------------------------------------------------------- serving
+
+static int check_request(const bse_request* r) {
+  if (!r) return set_error(-2, "request is NULL");
+  if (r->n <= 0) return set_error(-2, "request: n must be positive");
+  if (!r->A) return set_error(-2, "request: A is NULL");
+  if (r->lda < r->n) return set_error(-2, "request: lda < n");
+  if (!r->B) return set_error(-2, "request: B is NULL");
+  if (r->ldb < r->n) return set_error(-2, "request: ldb < n");
+  if (r->prec != BSE_PREC_FP64) return set_error(-2, "request: unsupported precision policy");
+  if (r->flags & ~(BSE_WANT_VECTORS | BSE_WANT_WEIGHTS)) return set_error(-2, "request: unknown flags");
+  if (!r->lambda) return set_error(-2, "request: lambda is NULL");
+  const bool vec = (r->flags & BSE_WANT_VECTORS) != 0;
+  const bool wts = (r->flags & BSE_WANT_WEIGHTS) != 0;
+  if (wts && !vec) return set_error(-2, "request: weights need eigenvectors");
+  if (vec && !r->X) return set_error(-2, "request: X is NULL");
+  if (vec && r->ldx < 2 * r->n) return set_error(-2, "request: ldx < 2n");
+  if (wts && !r->d_r) return set_error(-2, "request: d_r is NULL");
+  if (wts && !r->w) return set_error(-2, "request: w is NULL");
+  return 0;
+}
+
+int bse_serve_config(bse_ctx* ctx, size_t pool_bytes, int slots, int max_batch) {
+  if (!ctx) return set_error(-1, "ctx is NULL");
+  if (ctx->server) return set_error(BSE_EBUSY, "the server is already running");
+  if (slots < 0 || slots > 16) return set_error(-3, "slots must be in [0, 16]");
+  if (max_batch < 0 || max_batch > 4096) return set_error(-4, "max_batch must be in [0, 4096]");
+  BSE_TRY(prologue(ctx));
+  return server_create(ctx->device, pool_bytes, slots, max_batch, &ctx->server);
+}
+
+int bse_submit(bse_ctx* ctx, const bse_request* req, uint64_t* ticket) {
+  if (!ctx) return set_error(-1, "ctx is NULL");
+  BSE_TRY(check_request(req));
+  if (!ticket) return set_error(-3, "ticket is NULL");
+  BSE_TRY(prologue(ctx));
+  if (!ctx->server) BSE_TRY(server_create(ctx->device, 0, 0, 0, &ctx->server));
+  return server_submit(ctx->server, req, ctx->lane.stream, ticket);
+}
+
+int bse_poll(bse_ctx* ctx, uint64_t ticket, int* state, int* info) {
+  if (!ctx) return set_error(-1, "ctx is NULL");
+  if (!ctx->server) return set_error(BSE_ENOTICKET, "unknown ticket");
+  return server_poll(ctx->server, ticket, state, info);
+}
+
+int bse_release(bse_ctx* ctx, uint64_t ticket) {
+  if (!ctx) return set_error(-1, "ctx is NULL");
+  if (!ctx->server) return set_error(BSE_ENOTICKET, "unknown ticket");
+  return server_release(ctx->server, ticket);
+}
+
+int bse_ticket_times(bse_ctx* ctx, uint64_t ticket, double* t_submit_us, double* t_start_us, double* t_done_us) {
+  if (!ctx) return set_error(-1, "ctx is NULL");
+  if (!ctx->server) return set_error(BSE_ENOTICKET, "unknown ticket");
+  return server_times(ctx->server, ticket, t_submit_us, t_start_us, t_done_us);
+}
+
+int bse_serve_stats(bse_ctx* ctx, bse_serve_counters* stats) {
+  if (!ctx) return set_error(-1, "ctx is NULL");
+  if (!stats) return set_error(-2, "stats is NULL");
+  if (!ctx->server) {
+    memset(stats, 0, sizeof(*stats));
+    return 0;
+  }
+  return server_stats(ctx->server, stats);
 }
 
 // ---------------------------------------------------------------- stages
@@ -538,10 +608,10 @@ int bse_build_M(bse_ctx* ctx, int n, const void* A, int lda, const void* B, int 
   if (!M) return set_error(-7, "M is NULL");
   if (ldm < 2 * n) return set_error(-8, "ldm < 2n");
   BSE_TRY(prologue(ctx));
-  BSE_TRY(ensure_host(ctx, 1));
+  BSE_TRY(lane_reserve(&ctx->lane, 1));
   char* base = nullptr;
   BSE_TRY(get_workspace(ctx, header_bytes(1), &base));
-  Prob& P = ctx->hprobs[0];
+  Prob& P = ctx->lane.hprobs[0];
   memset(&P, 0, sizeof(P));
   P.n = n;
   P.N = 2 * n;
@@ -552,11 +622,10 @@ int bse_build_M(bse_ctx* ctx, int n, const void* A, int lda, const void* B, int 
   P.L = M;  // the embedding is written straight into the caller's matrix
   P.ld = ldm;
   Setup S;
-  S.base = base;
   S.dprobs = reinterpret_cast<Prob*>(base);
-  BSE_TRY(upload(ctx, S, 1));
-  BSE_TRY(build_M_batched(ctx->stream, single_batch(ctx, S)));
-  BSE_HIP(hipStreamSynchronize(ctx->stream));
+  BSE_TRY(upload(&ctx->lane, S, 1));
+  BSE_TRY(build_M_batched(ctx->lane.stream, single_batch(ctx, S)));
+  BSE_HIP(hipStreamSynchronize(ctx->lane.stream));
   return 0;
 }
 
@@ -568,15 +637,15 @@ int bse_potrf(bse_ctx* ctx, int N, double* M, int ldm) {
   BSE_TRY(prologue(ctx));
   Setup S;
   BSE_TRY(setup_single(ctx, N, &S));
-  const Prob& P = ctx->hprobs[0];
-  hipStream_t s = ctx->stream;
-  BSE_TRY(upload(ctx, S, 1));
+  const Prob& P = ctx->lane.hprobs[0];
+  hipStream_t s = ctx->lane.stream;
+  BSE_TRY(upload(&ctx->lane, S, 1));
   BSE_TRY(copy_matrix(s, N, N, M, ldm, P.L, P.ld));
   BSE_TRY(zero_upper(s, N, P.L, P.ld));
   BSE_TRY(potrf_batched(s, single_batch(ctx, S), 0, true));
   BSE_TRY(copy_matrix(s, N, N, P.L, P.ld, M, ldm));
-  BSE_TRY(read_infos(ctx, S, 1));
-  return ctx->hinfo[0];
+  BSE_TRY(read_infos(&ctx->lane, S, 1));
+  return ctx->lane.hinfo[0];
 }
 
 int bse_form_W(bse_ctx* ctx, int N, const double* L, int ldl, double* W, int ldw) {
@@ -589,9 +658,9 @@ int bse_form_W(bse_ctx* ctx, int N, const double* L, int ldl, double* W, int ldw
   BSE_TRY(prologue(ctx));
   Setup S;
   BSE_TRY(setup_single(ctx, N, &S));
-  const Prob& P = ctx->hprobs[0];
-  hipStream_t s = ctx->stream;
-  BSE_TRY(upload(ctx, S, 1));
+  const Prob& P = ctx->lane.hprobs[0];
+  hipStream_t s = ctx->lane.stream;
+  BSE_TRY(upload(&ctx->lane, S, 1));
   BSE_TRY(copy_matrix(s, N, N, L, ldl, P.L, P.ld));
   BSE_TRY(zero_upper(s, N, P.L, P.ld));
   BSE_TRY(form_W_batched(s, single_batch(ctx, S), true));
@@ -610,9 +679,9 @@ int bse_sktrd(bse_ctx* ctx, int N, double* W, int ldw, double* alpha, double* ta
   BSE_TRY(prologue(ctx));
   Setup S;
   BSE_TRY(setup_single(ctx, N, &S));
-  const Prob& P = ctx->hprobs[0];
-  hipStream_t s = ctx->stream;
-  BSE_TRY(upload(ctx, S, 1));
+  const Prob& P = ctx->lane.hprobs[0];
+  hipStream_t s = ctx->lane.stream;
+  BSE_TRY(upload(&ctx->lane, S, 1));
   BSE_TRY(copy_matrix(s, N, N, W, ldw, P.W, P.ld));
   BSE_TRY(sktrd_batched(s, single_batch(ctx, S), nullptr));
   BSE_TRY(copy_matrix(s, N, N, P.W, P.ld, W, ldw));
@@ -631,10 +700,10 @@ int bse_tridiag_eig(bse_ctx* ctx, int N, const double* alpha, double* lambda, do
   BSE_TRY(prologue(ctx));
   Setup S;
   BSE_TRY(setup_single(ctx, N, &S));
-  Prob& P = ctx->hprobs[0];
+  Prob& P = ctx->lane.hprobs[0];
   P.lambda = lambda;
-  hipStream_t s = ctx->stream;
-  BSE_TRY(upload(ctx, S, 1));
+  hipStream_t s = ctx->lane.stream;
+  BSE_TRY(upload(&ctx->lane, S, 1));
   const Batch b = single_batch(ctx, S);
   BSE_HIP(hipMemcpyAsync(P.alpha, alpha, (N - 1) * sizeof(double), hipMemcpyDeviceToDevice, s));
   BSE_TRY(bisect_batched(s, b));
@@ -642,8 +711,8 @@ int bse_tridiag_eig(bse_ctx* ctx, int N, const double* alpha, double* lambda, do
     BSE_TRY(invit_batched(s, b));
     BSE_TRY(reorth_batched(s, b));
     BSE_TRY(transpose_to(s, N / 2, N, P.Vt, N / 2, V, ldv));
-    BSE_TRY(read_infos(ctx, S, 1));
-    if (ctx->hinfo[1] != 0) return set_error(BSE_EDEVICE, "cluster Gram matrix not positive definite");
+    BSE_TRY(read_infos(&ctx->lane, S, 1));
+    if (ctx->lane.hinfo[1] != 0) return set_error(BSE_EDEVICE, "cluster Gram matrix not positive definite");
   }
   BSE_HIP(hipStreamSynchronize(s));
   return 0;
