@@ -126,6 +126,109 @@ def batched_bench(ctx, steps: int, warmup: int, count: int = 256, lo: int = 64, 
     }
 
 
+def serving_bench(big_inputs, count: int = 200, lo: int = 128, hi: int = 2048, big: int = 8192,
+                  big_frac: float = 0.02, seed: int = 5, load: float = 0.7, pool_gib: int = 128,
+                  slots: int = 4, max_batch: int = 64):
+    """Serving workload: a Poisson stream of `count` requests, n log-uniform in
+    [lo, hi] with probability 1 - big_frac, else n = big (stream seed `seed`,
+    request i from seed 100000 + i; the n = big requests reuse the problem in
+    big_inputs).  Inputs are resident in HBM before the clock starts.  Pass 1
+    submits every request at once (closed loop) to find the saturation
+    throughput; pass 2 replays the arrivals at `load` x that rate (open loop).
+    Latency = completion - submission, from the server's own timestamps."""
+    import torch
+    from bse_inputs import gen_bse, serving_stream
+    from paper_1501_03830_amd.api import Context, to_colmajor
+
+    dev = torch.device("cuda", 0)
+    _, ns = serving_stream(count, 1.0, lo, hi, big, big_frac, seed)
+    ns = [int(k) for k in ns]
+    t0 = time.time()
+    inputs = []
+    for i, k in enumerate(ns):
+        if k == big:
+            inputs.append(big_inputs)
+            continue
+        pr = gen_bse(k, seed=100000 + i, check_definite=False)
+        inputs.append((to_colmajor(torch.from_numpy(pr.A), dev), to_colmajor(torch.from_numpy(pr.B), dev),
+                       torch.from_numpy(pr.d).to(dev)))
+    outs = [(torch.empty(k, dtype=torch.float64, device=dev),
+             torch.empty((k, 2 * k), dtype=torch.complex128, device=dev),
+             torch.empty(k, dtype=torch.complex128, device=dev)) for k in ns]
+    torch.cuda.synchronize()
+    print(f"# serving: {count} requests ({sum(1 for k in ns if k == big)} at n={big}) prepared in "
+          f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+
+    def run(arrivals):
+        ctx = Context(0)
+        ctx.serve_config(pool_gib << 30, slots, max_batch)
+        pending = {}
+        lat = []
+        nxt = 0
+        t_start = time.perf_counter()
+        while nxt < count or pending:
+            now = time.perf_counter() - t_start
+            while nxt < count and arrivals[nxt] <= now:
+                k = ns[nxt]
+                Ac, Bc, d = inputs[nxt]
+                lam, X, w = outs[nxt]
+                pending[ctx.submit_raw(k, Ac, Bc, lam, X, d, None, w)] = nxt
+                nxt += 1
+            for t in list(pending):
+                st, info = ctx.poll(t)
+                if st >= 2:
+                    assert info == 0, (pending[t], info)
+                    a, _, c = ctx.ticket_times(t)
+                    lat.append((c - a) * 1e-3)
+                    ctx.release(t)
+                    del pending[t]
+            time.sleep(0.0005)
+        makespan = time.perf_counter() - t_start
+        stats = ctx.serve_stats()
+        ctx.close()
+        return makespan, lat, stats
+
+    span1, lat1, st1 = run([0.0] * count)
+    sat = count / span1
+    print(f"# serving closed loop: {span1:.2f}s, {sat:.2f} solves/s", file=sys.stderr, flush=True)
+    qps = load * sat
+    arrivals, _ = serving_stream(count, qps, lo, hi, big, big_frac, seed)
+    arrivals = [float(a) - float(arrivals[0]) for a in arrivals]
+    span2, lat2, st2 = run(arrivals)
+    lat2 = np.array(lat2)
+    print(f"# serving open loop at {qps:.2f} req/s: {span2:.2f}s", file=sys.stderr, flush=True)
+    return {
+        "workload": f"{count} requests, Poisson arrivals, n log-uniform in [{lo},{hi}] w.p. {1 - big_frac:.2f} "
+                    f"else n={big} (stream seed {seed}, request i seed 100000+i; n={big} requests reuse the "
+                    f"single-solve problem), FP64, eigenvalues + eigenvectors + weights",
+        "reduced_from": "2000 requests, n in [128,4096] + 2% at n=16384",
+        "slots": slots, "max_batch": max_batch, "pool_gib": pool_gib,
+        "saturation_solves_per_s": round(sat, 3),
+        "load": load, "qps": round(qps, 3),
+        "solves_per_s": round(count / span2, 3),
+        "p50_ms": round(float(np.percentile(lat2, 50)), 2),
+        "p99_ms": round(float(np.percentile(lat2, 99)), 2),
+        "max_ms": round(float(lat2.max()), 2),
+        "batches": st2["batches"], "max_inflight": st2["max_inflight"],
+        "peak_pool_gib": round(st2["peak_used_bytes"] / 2 ** 30, 2),
+    }
+
+
+def calibrate_copy(gib: int = 1, reps: int = 5):
+    """A plain device copy of a known size (gib GiB read + gib GiB written per
+    launch), for scaling the HBM byte counters of rocprofv3 --pmc
+    (FETCH_SIZE, WRITE_SIZE) run on the same command line."""
+    import torch
+    n = (gib << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy": {"bytes_read_per_launch": n * 8, "bytes_written_per_launch": n * 8,
+                                         "launches": reps}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,12 +243,20 @@ def main():
     ap.add_argument("--no-timing", action="store_true", help="skip per-launch kernel events")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched workload")
     ap.add_argument("--batched-only", action="store_true", help="only the batched workload")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
+    ap.add_argument("--serving-count", type=int, default=200)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration)")
     a = ap.parse_args()
 
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); a multi-GPU solve is not "
               f"part of this build", file=sys.stderr)
         sys.exit(2)
+
+    if a.calibrate_copy:
+        calibrate_copy()
+        return
 
     import torch
     from bse_inputs import gen_bse
@@ -245,10 +356,11 @@ def main():
         "cpu_baseline": None,
     }
     ctx.set_timing(False)
+    del Xbuf
     if not a.no_batched:
-        del Ac, Bc, Xbuf
-        torch.cuda.empty_cache()
         out["batched"] = batched_bench(ctx, a.steps, a.warmup)
+    if not a.no_serving:
+        out["serving"] = serving_bench((Ac, Bc, drb), count=a.serving_count, big=n)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.cpu_sample_n, n, a.s_a, a.s_b)
     ctx.close()
