@@ -3,7 +3,8 @@
 Usage:  python -m paper_1501_03830_amd.build [--jobs N] [--verbose]
 
 Objects go to _build/ at the repository root; the shared library is written
-next to this file so it travels with the package.
+next to this file so it travels with the package, with bse_bench, a native
+driver of the C ABI (csrc/bse_bench.cpp).
 """
 
 from __future__ import annotations
@@ -19,6 +20,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libbse.so")
+BENCH_EXE = os.path.join(HERE, "bse_bench")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -67,6 +69,16 @@ def build(jobs: int = 8, verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    # native driver of the C ABI (links libbse.so from its own directory)
+    drv = os.path.join(CSRC, "bse_bench.cpp")
+    cmd = [HIPCC, *CFLAGS, "-x", "hip", drv, "-o", BENCH_EXE + ".tmp", f"-L{HERE}", "-lbse",
+           "-Wl,-rpath,$ORIGIN"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"bse_bench build failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(BENCH_EXE + ".tmp", BENCH_EXE)
     return LIB
 
 
