@@ -58,6 +58,10 @@ extern "C" {
 
 /* precision policies */
 #define BSE_PREC_FP64 0        /* every stage in FP64                          */
+#define BSE_PREC_FP32_REFINE 1 /* W stored and reduced in FP32 (FP64 sums and
+                                  norms), FP64 tridiagonal solve and
+                                  back-transform, then FP64 refinement of the
+                                  eigenpairs against the FP64 W               */
 
 /* flags for bse_solve */
 #define BSE_WANT_VECTORS 1u    /* write X (else only lambda)                   */
@@ -74,7 +78,8 @@ extern "C" {
 #define BSE_STAGE_APPLY_U 7    /* Algorithm 3 step 3 (U applied to D V_+)      */
 #define BSE_STAGE_APPLY_L 8    /* Algorithm 3 step 3 (L applied)               */
 #define BSE_STAGE_FINISH 9     /* Algorithm 3 steps 4-6, phase, weights        */
-#define BSE_NUM_STAGES 10
+#define BSE_STAGE_REFINE 10    /* mixed path: FP64 refinement (after APPLY_U)  */
+#define BSE_NUM_STAGES 11
 
 /* request states reported by bse_poll */
 #define BSE_QUEUED 0           /* waiting for a slot and device memory          */
@@ -129,6 +134,11 @@ typedef struct bse_report {
                                       strictly lower triangle of each trailing
                                       matrix, 8 bytes per element             */
   long long symv_launches;         /* number of launches                     */
+  int refine_sweeps;               /* mixed path: refinement sweeps run      */
+  double refine_first_correction;  /* mixed path: largest correction entry of
+                                      the first sweep (the size of the
+                                      unrefined eigenvector error)           */
+  double refine_correction;        /* ... and of the last sweep              */
 } bse_report;
 
 /* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
@@ -165,7 +175,15 @@ size_t bse_footprint_bytes(int n, int prec, unsigned flags);
  *   n        order of A and B, n >= 1 (2)
  *   A, lda   complex n x n, lda >= n, lower triangle read (3, 4)
  *   B, ldb   complex n x n, ldb >= n, lower triangle read (5, 6)
- *   prec     BSE_PREC_FP64 (7)
+ *   prec     BSE_PREC_FP64, or BSE_PREC_FP32_REFINE: W is reduced to
+ *            tridiagonal form in FP32 storage (FP64 sums and norms), the
+ *            tridiagonal eigensolve and the back-transformation run in FP64,
+ *            then the eigenpairs are refined in FP64 against the FP64 W by
+ *            sweeps of an Ogita-Aishima-type iteration on the real Schur
+ *            form of W (not in the paper), until the largest correction is
+ *            below 1e-3 with no near-degenerate pair left out (at most 4
+ *            sweeps); eigenvalues are then taken from the refined basis,
+ *            which puts their error near FP64 rounding (7)
  *   flags    BSE_WANT_VECTORS | BSE_WANT_WEIGHTS (8)
  *   lambda   out: n doubles, the positive eigenvalues ascending (9)
  *   X, ldx   out: complex 2n x n, ldx >= 2n; rows 0..n-1 hold X1, rows

@@ -19,13 +19,14 @@ BSE_QUEUED, BSE_RUNNING, BSE_DONE, BSE_FAILED = 0, 1, 2, 3
 STATE_NAMES = {0: "queued", 1: "running", 2: "done", 3: "failed"}
 
 BSE_PREC_FP64 = 0
+BSE_PREC_FP32_REFINE = 1
 
 BSE_WANT_VECTORS = 1
 BSE_WANT_WEIGHTS = 2
 
-BSE_NUM_STAGES = 10
+BSE_NUM_STAGES = 11
 STAGE_NAMES = ["build_M", "potrf", "form_W", "sktrd", "bisect", "invit", "reorth", "apply_U",
-               "apply_L", "finish"]
+               "apply_L", "finish", "refine"]
 
 
 class BseReport(ctypes.Structure):
@@ -38,6 +39,9 @@ class BseReport(ctypes.Structure):
         ("symv_ms", ctypes.c_double),
         ("symv_bytes", ctypes.c_double),
         ("symv_launches", ctypes.c_longlong),
+        ("refine_sweeps", ctypes.c_int),
+        ("refine_first_correction", ctypes.c_double),
+        ("refine_correction", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -50,6 +54,9 @@ class BseReport(ctypes.Structure):
             "symv_ms": self.symv_ms,
             "symv_bytes": self.symv_bytes,
             "symv_launches": self.symv_launches,
+            "refine_sweeps": self.refine_sweeps,
+            "refine_first_correction": self.refine_first_correction,
+            "refine_correction": self.refine_correction,
         }
 
 

@@ -68,7 +68,8 @@ class Context:
 
     # ------------------------------------------------------------------ solve
     def solve(self, A: torch.Tensor, B: torch.Tensor, d_r: torch.Tensor | None = None,
-              d_l: torch.Tensor | None = None, vectors: bool = True, report: bool = False):
+              d_l: torch.Tensor | None = None, vectors: bool = True, report: bool = False,
+              prec: int = _lib.BSE_PREC_FP64):
         """Full eigensolve.  A, B: complex128 (n, n) logical matrices (lower
         triangles used).  Returns dict with lam (n,), X (2n, n) or None,
         w (n,) or None, info, report."""
@@ -93,7 +94,7 @@ class Context:
             w = torch.empty(n, dtype=torch.complex128, device=dev)
         rep = _lib.BseReport() if report else None
         info = _lib.check(self.lib.bse_solve(
-            self.h, n, _ptr(Ac), n, _ptr(Bc), n, _lib.BSE_PREC_FP64, flags, _ptr(lam),
+            self.h, n, _ptr(Ac), n, _ptr(Bc), n, prec, flags, _ptr(lam),
             _ptr(Xbuf), 2 * n, _ptr(drb), _ptr(dlb), _ptr(w),
             ctypes.byref(rep) if rep is not None else None), "bse_solve")
         return {
@@ -106,7 +107,7 @@ class Context:
 
     def solve_raw(self, n: int, Ac: torch.Tensor, Bc: torch.Tensor, lam: torch.Tensor,
                   Xbuf: torch.Tensor | None, drb: torch.Tensor | None = None, dlb: torch.Tensor | None = None,
-                  w: torch.Tensor | None = None, report: bool = False):
+                  w: torch.Tensor | None = None, report: bool = False, prec: int = _lib.BSE_PREC_FP64):
         """bse_solve on buffers that are already column-major on the device
         (as made by to_colmajor); nothing is copied.  Returns (info, report)."""
         flags = 0
@@ -116,12 +117,13 @@ class Context:
             flags |= _lib.BSE_WANT_WEIGHTS
         rep = _lib.BseReport() if report else None
         info = _lib.check(self.lib.bse_solve(
-            self.h, n, _ptr(Ac), n, _ptr(Bc), n, _lib.BSE_PREC_FP64, flags, _ptr(lam),
+            self.h, n, _ptr(Ac), n, _ptr(Bc), n, prec, flags, _ptr(lam),
             _ptr(Xbuf), 2 * n, _ptr(drb), _ptr(dlb), _ptr(w),
             ctypes.byref(rep) if rep is not None else None), "bse_solve")
         return info, (rep.as_dict() if rep is not None else None)
 
-    def solve_batched_raw(self, ns, Acs, Bcs, lams, Xbufs=None, ds=None, ws=None, report: bool = False):
+    def solve_batched_raw(self, ns, Acs, Bcs, lams, Xbufs=None, ds=None, ws=None, report: bool = False,
+                          prec: int = _lib.BSE_PREC_FP64):
         """bse_solve_batched on column-major device buffers (as made by
         to_colmajor), one entry per problem; nothing is copied.  Returns
         (info list, report)."""
@@ -145,12 +147,13 @@ class Context:
         info = IA()
         rep = _lib.BseReport() if report else None
         _lib.check(self.lib.bse_solve_batched(
-            self.h, count, n_arr, A_arr, ld_arr, B_arr, ld_arr, _lib.BSE_PREC_FP64, flags, lam_arr,
+            self.h, count, n_arr, A_arr, ld_arr, B_arr, ld_arr, prec, flags, lam_arr,
             X_arr, ldx_arr, d_arr, w_arr, info, ctypes.byref(rep) if rep is not None else None),
             "bse_solve_batched")
         return list(info), (rep.as_dict() if rep is not None else None)
 
-    def solve_batched(self, As, Bs, ds=None, vectors: bool = True, report: bool = False):
+    def solve_batched(self, As, Bs, ds=None, vectors: bool = True, report: bool = False,
+                      prec: int = _lib.BSE_PREC_FP64):
         """Batched eigensolve of independent problems (lists of complex128
         (n_i, n_i) logical matrices; ds: optional list of complex 2n_i dipole
         vectors used as d_r = d_l).  Returns a list of per-problem dicts like
@@ -164,7 +167,7 @@ class Context:
         Xbufs = [torch.empty((k, 2 * k), dtype=torch.complex128, device=dev) for k in ns] if want_x else None
         dbs = [d.to(dev, torch.complex128).contiguous() for d in ds] if ds is not None else None
         ws = [torch.empty(k, dtype=torch.complex128, device=dev) for k in ns] if ds is not None else None
-        info, rep = self.solve_batched_raw(ns, Acs, Bcs, lams, Xbufs, dbs, ws, report)
+        info, rep = self.solve_batched_raw(ns, Acs, Bcs, lams, Xbufs, dbs, ws, report, prec)
         out = []
         for i in range(len(ns)):
             out.append({
@@ -182,7 +185,8 @@ class Context:
 
     def submit_raw(self, n: int, Ac: torch.Tensor, Bc: torch.Tensor, lam: torch.Tensor,
                    Xbuf: torch.Tensor | None = None, drb: torch.Tensor | None = None,
-                   dlb: torch.Tensor | None = None, w: torch.Tensor | None = None) -> int:
+                   dlb: torch.Tensor | None = None, w: torch.Tensor | None = None,
+                   prec: int = _lib.BSE_PREC_FP64) -> int:
         """bse_submit on column-major device buffers; returns the ticket.  The
         buffers are kept referenced here until the ticket is released."""
         flags = 0
@@ -190,7 +194,7 @@ class Context:
             flags |= _lib.BSE_WANT_VECTORS
         if drb is not None:
             flags |= _lib.BSE_WANT_WEIGHTS
-        req = _lib.BseRequest(n, Ac.data_ptr(), n, Bc.data_ptr(), n, _lib.BSE_PREC_FP64, flags, lam.data_ptr(),
+        req = _lib.BseRequest(n, Ac.data_ptr(), n, Bc.data_ptr(), n, prec, flags, lam.data_ptr(),
                               None if Xbuf is None else Xbuf.data_ptr(), 2 * n,
                               None if drb is None else drb.data_ptr(), None if dlb is None else dlb.data_ptr(),
                               None if w is None else w.data_ptr())
@@ -283,6 +287,7 @@ class Context:
 
 
 def footprint_bytes(n: int, prec: int = _lib.BSE_PREC_FP64, flags: int = 0) -> int:
+    """Device workspace of one bse_solve of order n."""
     return int(_lib.load().bse_footprint_bytes(n, prec, flags))
 
 

@@ -62,6 +62,8 @@ __global__ __launch_bounds__(256) void k_extract_V(const Prob* __restrict__ prob
   if (j0 >= nrefl) return;  // uniform
   const int nbk = min(NBQ, nrefl - j0);
   const BSE_GLOBAL double* __restrict__ W = gbl(P.W);
+  const BSE_GLOBAL float* __restrict__ W32 = gbl(P.W32);
+  const bool f32 = P.prec == BSE_PREC_FP32_REFINE;   // reflectors stored in FP32
   BSE_GLOBAL double* __restrict__ Vb = gbl(P.Vb);
   const long ldw = P.ld, ldv = P.ld;
   const long r = (long)j0 + 1 + (long)blockIdx.x * 64 + (threadIdx.x & 63);
@@ -71,7 +73,7 @@ __global__ __launch_bounds__(256) void k_extract_V(const Prob* __restrict__ prob
     double v;
     if (r < diag) v = 0.0;
     else if (r == diag) v = 1.0;
-    else v = W[r + (long)(j0 + l) * ldw];
+    else v = f32 ? (double)W32[r + (long)(j0 + l) * ldw] : W[r + (long)(j0 + l) * ldw];
     Vb[r + (long)l * ldv] = v;
   }
 }
@@ -116,6 +118,7 @@ __global__ __launch_bounds__(256) void k_finish_X(const Prob* __restrict__ probs
   const BSE_GLOBAL double* __restrict__ G = gbl(P.W);
   const long ldg = P.ld;
   const BSE_GLOBAL double* __restrict__ lam = gbl(P.lambda);
+  const BSE_GLOBAL int* __restrict__ perm = gbl(P.perm);   // null: identity order
   BSE_GLOBAL double* __restrict__ X = gbl(P.X);
   const long ldx = P.ldx;
   const long r = (long)blockIdx.x * 64 + (threadIdx.x & 63);
@@ -124,8 +127,9 @@ __global__ __launch_bounds__(256) void k_finish_X(const Prob* __restrict__ probs
   for (int q = 0; q < 16; ++q) {
     const long j = c0 + q;
     if (j >= n) break;
-    const double g1r = G[r + j * ldg], g1i = G[r + (n + j) * ldg];
-    const double g2r = G[n + r + j * ldg], g2i = G[n + r + (n + j) * ldg];
+    const long js = perm ? (long)perm[j] : j;   // eigenpair written to column j
+    const double g1r = G[r + js * ldg], g1i = G[r + (n + js) * ldg];
+    const double g2r = G[n + r + js * ldg], g2i = G[n + r + (n + js) * ldg];
     const double c = 1.0 / sqrt(2.0 * lam[j]);
     auto x1 = X + 2 * (r + j * ldx);
     auto x2 = X + 2 * (n + r + j * ldx);
@@ -227,7 +231,32 @@ __global__ __launch_bounds__(256) void k_phase_weights(const Prob* __restrict__ 
   }
 }
 
+// strictly lower triangle of W into its FP32 copy (the part the reduction
+// reads)
+__global__ __launch_bounds__(256) void k_to_f32(const Prob* __restrict__ probs) {
+  const Prob& P = probs[blockIdx.z];
+  const long N = P.N;
+  const long r = (long)blockIdx.x * 64 + (threadIdx.x & 63);
+  const long c0 = (long)blockIdx.y * 64 + (threadIdx.x >> 6) * 16;
+  if (r >= N) return;
+  const BSE_GLOBAL double* __restrict__ W = gbl(P.W);
+  BSE_GLOBAL float* __restrict__ W32 = gbl(P.W32);
+  for (int q = 0; q < 16; ++q) {
+    const long c = c0 + q;
+    if (c >= N || c >= r) break;
+    W32[r + c * P.ld] = (float)W[r + c * P.ld];
+  }
+}
+
 }  // namespace
+
+int to_f32_batched(hipStream_t s, const Batch& b) {
+  if (b.count <= 0) return 0;
+  const long N0 = b.maxN();
+  k_to_f32<<<dim3((unsigned)((N0 + 63) / 64), (unsigned)((N0 + 63) / 64), (unsigned)b.count), 256, 0, s>>>(b.dev);
+  BSE_LAUNCHED();
+  return 0;
+}
 
 size_t backtr_work_bytes(long N, long ld) {
   (void)N;

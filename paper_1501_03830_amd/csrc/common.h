@@ -72,6 +72,14 @@ struct Prob {
   void* ctrl;
   // back-transformation work
   double *Vb, *S, *T, *W1, *W2;
+  // mixed-precision path (prec == BSE_PREC_FP32_REFINE)
+  int prec;
+  float* W32;           // FP32 copy of W reduced to tridiagonal form (ld x ld)
+  double *R1, *R2, *R3, *R4;   // refinement work, ld x ld each
+  double* refmax;       // refinement: per-tile partial maxima (2 per tile)
+  double* refout;       // refinement: [largest correction, clamped pairs] (header)
+  int* refstate;        // refinement: sweeps done once converged, else 0 (header)
+  int* perm;            // n: output column j takes eigenpair perm[j]
 };
 
 // Address-space views of pointers taken from a descriptor.  A pointer loaded

@@ -16,6 +16,8 @@ struct Lane {
   hipStream_t stream = nullptr;
   Prob* hprobs = nullptr;   // pinned host mirror of the descriptors
   int* hinfo = nullptr;     // pinned host copy of the info words
+  int* hstate = nullptr;    // pinned host copy of the refinement state words
+  double* hrefout = nullptr;   // pinned host copy of the refinement maxima
   int hcap = 0;
   hipEvent_t ev[BSE_NUM_STAGES + 1] = {};
   bool events = false;
@@ -27,20 +29,23 @@ void lane_release(Lane* L);             // frees events and host mirrors
 
 // Device workspace of one problem of order N (bytes, 256-aligned) and of the
 // descriptor/info header of a batch of `count` problems.
-size_t problem_bytes(long N);
+size_t problem_bytes(long N, int prec);
 size_t header_bytes(int count);
 
 // Descriptor storage of a batch in device memory.
 struct Setup {
+  int count = 0;            // descriptor slots
   Prob* dprobs = nullptr;   // device descriptors (count)
   int* dinfo = nullptr;     // device info words, 2 per problem slot
+  int* dstate = nullptr;    // device refinement state words, 1 per slot
+  double* dref = nullptr;   // device refinement maxima, 2 per slot
   size_t total = 0;         // workspace bytes of the batch (for reports)
 };
 // Header at `header` (header_bytes(count)); descriptor slot i gets the
-// workspace at bases[i] (problem_bytes(Ns[i])) and info words 2i, 2i+1.
+// workspace at bases[i] (problem_bytes(Ns[i], prec)) and info words 2i, 2i+1.
 // The host mirror L->hprobs[0..count) is filled; callers then set the
 // caller-buffer fields (A, B, lambda, X, ...).
-int setup_batch(Lane* L, int count, const long* Ns, char* header, char* const* bases, Setup* S);
+int setup_batch(Lane* L, int count, const long* Ns, int prec, char* header, char* const* bases, Setup* S);
 
 // The chain for the batch in L->hprobs[0..count) (sorted by decreasing N).
 // Blocks until the device work is done.  On return L->hinfo[2i], [2i+1]

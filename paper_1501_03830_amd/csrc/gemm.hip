@@ -86,6 +86,10 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
       g.ta = 0; g.tb = 1; g.M = m2; g.N = m2; g.K = 2 * nbp; g.beta = 1.0;
       g.A = P.Y1 + e; g.lda = ld; g.B = P.Y2 + e; g.ldb = ld; g.C = P.W + e + (long)e * ld; g.ldc = ld;
       g.c_uplo = 2;
+      if (P.prec == BSE_PREC_FP32_REFINE) {   // W held in FP32
+        g.C = nullptr;
+        g.Cf = P.W32 + e + (long)e * ld;
+      }
       break;
     }
     case GOP_GRAM:  // G <- Vt Vt^T (lower)
@@ -141,6 +145,25 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
       g.ta = 0; g.tb = 0; g.M = P.N; g.N = P.N; g.K = P.N;
       g.A = P.L; g.lda = ld; g.B = P.Z; g.ldb = ld; g.C = P.W; g.ldc = ld; g.a_tri = 1;
       break;
+    case GOP_REF_P:
+    case GOP_REF_S:
+    case GOP_REF_G:
+    case GOP_REF_U: {
+      // the basis of sweep `step` alternates between Z (even) and R4 (odd)
+      double* Ub = (step & 1) ? P.R4 : P.Z;
+      double* Un = (step & 1) ? P.Z : P.R4;
+      g.M = P.N; g.N = P.N; g.K = P.N;
+      if (op == GOP_REF_P) {         // W (full, FP64) times the basis
+        g.ta = 0; g.tb = 0; g.A = P.W; g.lda = ld; g.B = Ub; g.ldb = ld; g.C = P.R1; g.ldc = ld;
+      } else if (op == GOP_REF_S) {  // Ub^T (W Ub), lower triangle
+        g.ta = 1; g.tb = 0; g.A = Ub; g.lda = ld; g.B = P.R1; g.ldb = ld; g.C = P.R2; g.ldc = ld; g.c_uplo = 1;
+      } else if (op == GOP_REF_G) {  // Ub^T Ub, lower triangle
+        g.ta = 1; g.tb = 0; g.A = Ub; g.lda = ld; g.B = Ub; g.ldb = ld; g.C = P.R3; g.ldc = ld; g.c_uplo = 1;
+      } else {                       // Ub (I + F), I + F in R1
+        g.ta = 0; g.tb = 0; g.A = Ub; g.lda = ld; g.B = P.R1; g.ldb = ld; g.C = Un; g.ldc = ld;
+      }
+      break;
+    }
     default:
       break;
   }
@@ -180,7 +203,15 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ 
   constexpr int SMEM = (2 * (AS + BS) > CS) ? 2 * (AS + BS) : CS;
   __shared__ double smem[SMEM];
 
-  const GemmParams p = probs ? gemm_params(op, probs[blockIdx.z], step) : single;
+  int stp = step;
+  if (probs && op >= GOP_REF_P) {
+    // refinement products: skip problems that finished in an earlier sweep;
+    // step < 0 means the problem's own final sweep
+    const int st = *gbl(probs[blockIdx.z].refstate);
+    if (step >= 0 && st != 0 && st <= step) return;
+    if (step < 0) stp = st;
+  }
+  const GemmParams p = probs ? gemm_params(op, probs[blockIdx.z], stp) : single;
   const BSE_GLOBAL double* __restrict__ Ag = gbl(p.A);
   const BSE_GLOBAL double* __restrict__ Bg = gbl(p.B);
   long tile = blockIdx.x;
@@ -363,6 +394,10 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ 
     const double val = Cs[cl * (BM + 1) + rl];
     if (split) {
       gbl(p.part)[(long)slice * p.M * p.N + (long)row + (long)col * p.M] = val;
+    } else if (p.Cf) {
+      BSE_GLOBAL float* c = gbl(p.Cf + (long)row + (long)col * p.ldc);
+      const double out = p.alpha * val;
+      *c = (float)((p.beta == 0.0) ? out : out + p.beta * (double)(*c));
     } else {
       BSE_GLOBAL double* c = gbl(p.C + (long)row + (long)col * p.ldc);
       const double out = p.alpha * val;
@@ -374,7 +409,13 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ 
 // C = alpha * sum_s part[s] + beta * C over the (uplo-restricted) M x N
 __global__ __launch_bounds__(256) void k_splitk_reduce(const Prob* __restrict__ probs, int op, int step,
                                                        GemmParams single) {
-  const GemmParams p = probs ? gemm_params(op, probs[blockIdx.z], step) : single;
+  int stp = step;
+  if (probs && op >= GOP_REF_P) {
+    const int st = *gbl(probs[blockIdx.z].refstate);
+    if (step >= 0 && st != 0 && st <= step) return;
+    if (step < 0) stp = st;
+  }
+  const GemmParams p = probs ? gemm_params(op, probs[blockIdx.z], stp) : single;
   if (p.splits <= 1) return;
   const long r = (long)blockIdx.x * 64 + (threadIdx.x & 63);
   const long c0 = (long)blockIdx.y * 64 + (threadIdx.x >> 6) * 16;
@@ -387,9 +428,14 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const Prob* __restrict__ 
     double s = 0.0;
     const BSE_GLOBAL double* part = gbl(p.part);
     for (int k = 0; k < p.splits; ++k) s += part[(long)k * p.M * p.N + r + c * p.M];
-    BSE_GLOBAL double* cp = gbl(p.C + r + c * p.ldc);
     const double out = p.alpha * s;
-    *cp = (p.beta == 0.0) ? out : out + p.beta * (*cp);
+    if (p.Cf) {
+      BSE_GLOBAL float* cf = gbl(p.Cf + r + c * p.ldc);
+      *cf = (float)((p.beta == 0.0) ? out : out + p.beta * (double)(*cf));
+    } else {
+      BSE_GLOBAL double* cp = gbl(p.C + r + c * p.ldc);
+      *cp = (p.beta == 0.0) ? out : out + p.beta * (*cp);
+    }
   }
 }
 

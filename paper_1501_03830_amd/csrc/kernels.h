@@ -43,6 +43,7 @@ struct GemmParams {
   long ntiles;
   int splits, kchunk;
   double* part;  // split-K partial products [splits][M x N], ld M
+  float* Cf;     // C in FP32 (when non-null C is unused), ld ldc
 };
 
 // The products of the chain, as functions of (problem, step).
@@ -63,6 +64,10 @@ enum GemmOp {
   GOP_APPLYU_W2,   // T (V^T Z)
   GOP_APPLYU_Z,    // Z -= V T V^T Z
   GOP_APPLY_L,     // G = L Z
+  GOP_REF_P,       // refinement: P = W Ub (basis Ub of sweep `step`)
+  GOP_REF_S,       // refinement: S = Ub^T P (lower)
+  GOP_REF_G,       // refinement: G = Ub^T Ub (lower)
+  GOP_REF_U,       // refinement: next basis = Ub (I + F)
 };
 __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step);
 // Product `op` at `step` for the first nact problems of the batch.
@@ -117,5 +122,27 @@ int apply_UD_batched(hipStream_t s, const Batch& b);
 // P.X from G = L Z (in P.W, made by GOP_APPLY_L), canonical phase and the
 // weights
 int finish_batched(hipStream_t s, const Batch& b);
+// lower triangle of P.W into P.W32 (mixed-precision path)
+int to_f32_batched(hipStream_t s, const Batch& b);
+
+// ---------------------------------------------------------------- refine.hip
+// Refinement of the eigenpairs against the FP64 W (mixed-precision path).
+// Reads the basis from P.Z, leaves refined eigenvectors in P.Z, eigenvalues
+// ascending in P.lambda and the output order in P.perm.  The batch header's
+// per-slot state words and correction maxima (device) are copied to pinned
+// host arrays after each sweep to decide whether to go on.
+struct RefineIO {
+  const int* dstate;      // device, nslots (P.refstate points into it)
+  const double* dout;     // device, 2 per slot (P.refout points into it)
+  int* hstate;            // pinned host copies
+  double* hout;
+  int nslots;
+};
+struct RefineStats {
+  int sweeps = 0;
+  double first_correction = 0.0;
+  double last_correction = 0.0;
+};
+int refine_batched(hipStream_t s, const Batch& b, const RefineIO& io, RefineStats* st);
 
 }  // namespace bse

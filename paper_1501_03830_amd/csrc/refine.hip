@@ -1,0 +1,325 @@
+// FP64 refinement of the eigenpairs produced by the mixed-precision path.
+//
+// Not in the paper: this is an iterative refinement in the style of Ogita and
+// Aishima (symmetric eigendecomposition refinement, 2018), carried over to
+// the real Schur form of the skew-symmetric W = L^T J L.  If W z = i lambda z
+// with z = a + i b, then W a = -lambda b and W b = lambda a, and the columns
+// Ub = sqrt(2) [a_1 .. a_n | b_1 .. b_n] satisfy
+//     Ub^T Ub = I,   Ub^T W Ub = Sigma = [0 Lambda; -Lambda 0].
+// Given an approximate Ub (from the FP32 reduction), one sweep computes in
+// FP64 (W is the exact FP64 W of Algorithm 1 step 3)
+//     P = W Ub,  S = Ub^T P,  G = Ub^T Ub,  R = I - G,
+// the refined lambda_k of each pair from its 2 x 2 blocks,
+//     lambda_k = s_k / sqrt(det G_kk),  s_k = -S[n+k, k],
+// and the correction Ub <- Ub (I + F), F = R/2 + E with E skew.  E is zero on
+// the 2 x 2 diagonal blocks (the phase of z_k is free) and, for k != l,
+// solves the first-order Sylvester equation
+//     sigma_k E_kl - E_kl sigma_l = -S_kl - (R_kl sigma_l + sigma_k R_kl)/2,
+// sigma_k = lambda_k [0 1; -1 0], which has the closed form used below.  A
+// block whose solution exceeds GCAP (nearly equal eigenvalues) is left to
+// the orthogonalisation part alone, as in the original method's treatment of
+// clusters.  The error of Ub falls quadratically; a problem stops after the
+// sweep whose largest correction is below STOP_TOL with no clamped block,
+// then its eigenvalues are taken from the refined basis (error of order
+// ||W|| STOP_TOL^4) and sorted.  Each problem converges on its own: kernels
+// skip problems that finished in an earlier sweep.
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace bse {
+
+namespace {
+
+constexpr int MAX_SWEEPS = 4;
+constexpr double GCAP = 0.25;
+constexpr double STOP_TOL = 1e-3;
+
+// skip problems whose refinement finished before sweep `sweep`
+__device__ inline bool finished_before(const Prob& P, int sweep) {
+  const int st = *gbl(P.refstate);
+  return st != 0 && st <= sweep;
+}
+
+__device__ inline double* basis(const Prob& P, int sweep) { return (sweep & 1) ? P.R4 : P.Z; }
+
+// Z <- f Z over the N x N block (the basis of sweep 0)
+__global__ __launch_bounds__(256) void k_ref_scale(const Prob* __restrict__ probs, double f) {
+  const Prob& P = probs[blockIdx.z];
+  const long N = P.N;
+  const long r = (long)blockIdx.x * 64 + (threadIdx.x & 63);
+  const long c0 = (long)blockIdx.y * 64 + (threadIdx.x >> 6) * 16;
+  if (r >= N) return;
+  BSE_GLOBAL double* __restrict__ Z = gbl(P.Z);
+  for (int q = 0; q < 16; ++q) {
+    const long c = c0 + q;
+    if (c >= N) break;
+    Z[r + c * P.ld] *= f;
+  }
+}
+
+__global__ void k_ref_reset(const Prob* __restrict__ probs) {
+  if (threadIdx.x == 0) *gbl(probs[blockIdx.z].refstate) = 0;
+}
+
+// lambda_k of each pair from the 2 x 2 diagonal blocks of S (R2) and G (R3)
+__global__ __launch_bounds__(64) void k_ref_lambda(const Prob* __restrict__ probs, int sweep) {
+  const Prob& P = probs[blockIdx.z];
+  const int n = P.n;
+  const int k = blockIdx.x * 64 + threadIdx.x;
+  if (k >= n || finished_before(P, sweep)) return;
+  const long ld = P.ld;
+  const BSE_GLOBAL double* __restrict__ S = gbl(P.R2);
+  const BSE_GLOBAL double* __restrict__ G = gbl(P.R3);
+  const double s = -S[(n + k) + (long)k * ld];
+  const double gaa = G[k + (long)k * ld], gbb = G[(n + k) + (long)(n + k) * ld];
+  const double gab = G[(n + k) + (long)k * ld];
+  gbl(P.shift)[k] = s / sqrt(gaa * gbb - gab * gab);
+}
+
+// entry (i, j) of the full matrices from their stored lower triangles
+__device__ inline double skew_at(const BSE_GLOBAL double* S, long ld, long i, long j) {
+  return (i >= j) ? S[i + j * ld] : -S[j + i * ld];
+}
+__device__ inline double sym_at(const BSE_GLOBAL double* G, long ld, long i, long j) {
+  return (i >= j) ? G[i + j * ld] : G[j + i * ld];
+}
+
+// I + F into R1 (P = W Ub is no longer needed), and per-tile maxima of the
+// correction and of the number of clamped blocks.
+__global__ __launch_bounds__(256) void k_ref_F(const Prob* __restrict__ probs, int sweep) {
+  __shared__ double red[2][4];
+  const Prob& P = probs[blockIdx.z];
+  const long N = P.N, n = P.n, ld = P.ld;
+  const long ntile = (N + 63) / 64;
+  if ((long)blockIdx.x >= ntile || (long)blockIdx.y >= ntile) return;   // uniform
+  if (finished_before(P, sweep)) return;
+  const BSE_GLOBAL double* __restrict__ S = gbl(P.R2);
+  const BSE_GLOBAL double* __restrict__ G = gbl(P.R3);
+  const BSE_CONST double* __restrict__ lam = ro(P.shift);
+  BSE_GLOBAL double* __restrict__ IF = gbl(P.R1);
+  const long r = (long)blockIdx.x * 64 + (threadIdx.x & 63);
+  const long c0 = (long)blockIdx.y * 64 + (threadIdx.x >> 6) * 16;
+  double cmax = 0.0, nclamp = 0.0;
+  if (r < N) {
+    const long k = r < n ? r : r - n;
+    const int pr = r < n ? 0 : 1;
+    const double lk = lam[k];
+    for (int q = 0; q < 16; ++q) {
+      const long c = c0 + q;
+      if (c >= N) break;
+      const long l = c < n ? c : c - n;
+      const int qc = c < n ? 0 : 1;
+      const double rrc = ((r == c) ? 1.0 : 0.0) - sym_at(G, ld, r, c);
+      double e = 0.0;
+      if (k != l) {
+        const double ll = lam[l];
+        const long ka = k, kb = n + k, la = l, lb = n + l;
+        const double S11 = skew_at(S, ld, ka, la), S12 = skew_at(S, ld, ka, lb);
+        const double S21 = skew_at(S, ld, kb, la), S22 = skew_at(S, ld, kb, lb);
+        const double R11 = -sym_at(G, ld, ka, la), R12 = -sym_at(G, ld, ka, lb);
+        const double R21 = -sym_at(G, ld, kb, la), R22 = -sym_at(G, ld, kb, lb);
+        // C = -S_kl - (R_kl sigma_l + sigma_k R_kl) / 2
+        const double c11 = -S11 - 0.5 * (-R12 * ll + lk * R21);
+        const double c12 = -S12 - 0.5 * (R11 * ll + lk * R22);
+        const double c21 = -S21 - 0.5 * (-R22 * ll - lk * R11);
+        const double c22 = -S22 - 0.5 * (R21 * ll - lk * R12);
+        const double det = lk * lk - ll * ll;
+        const double e11 = (c12 * ll - lk * c21) / det;
+        const double e22 = (-ll * c21 + lk * c12) / det;
+        const double e12 = (-ll * c11 - lk * c22) / det;
+        const double e21 = (ll * c22 + lk * c11) / det;
+        const double emax = fmax(fmax(fabs(e11), fabs(e12)), fmax(fabs(e21), fabs(e22)));
+        if (emax <= GCAP) {   // NaN or a near-degenerate pair: orthogonalise only
+          e = pr == 0 ? (qc == 0 ? e11 : e12) : (qc == 0 ? e21 : e22);
+        } else {
+          nclamp += 1.0;
+        }
+      }
+      const double f = 0.5 * rrc + e;
+      if (r != c) cmax = fmax(cmax, fabs(f));
+      IF[r + c * ld] = ((r == c) ? 1.0 : 0.0) + f;
+    }
+  }
+  // workgroup maxima / sums
+  for (int off = 32; off >= 1; off >>= 1) {
+    cmax = fmax(cmax, __shfl_xor(cmax, off, 64));
+    nclamp += __shfl_xor(nclamp, off, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][w] = cmax;
+    red[1][w] = nclamp;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0, cl = 0.0;
+    for (int i = 0; i < 4; ++i) {
+      m = fmax(m, red[0][i]);
+      cl += red[1][i];
+    }
+    const long t = (long)blockIdx.x + (long)blockIdx.y * ntile;
+    BSE_GLOBAL double* __restrict__ part = gbl(P.refmax);
+    part[2 * t] = m;
+    part[2 * t + 1] = cl;
+  }
+}
+
+// reduce the tile maxima; decide whether this problem is done after `sweep`
+__global__ __launch_bounds__(256) void k_ref_decide(const Prob* __restrict__ probs, int sweep) {
+  __shared__ double red[2][4];
+  const Prob& P = probs[blockIdx.z];
+  if (finished_before(P, sweep)) return;
+  const long ntile = (P.N + 63) / 64;
+  const long nt2 = ntile * ntile;
+  const BSE_GLOBAL double* __restrict__ part = gbl(P.refmax);
+  double m = 0.0, cl = 0.0;
+  for (long t = threadIdx.x; t < nt2; t += 256) {
+    m = fmax(m, part[2 * t]);
+    cl += part[2 * t + 1];
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    m = fmax(m, __shfl_xor(m, off, 64));
+    cl += __shfl_xor(cl, off, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][w] = m;
+    red[1][w] = cl;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mm = 0.0, cc = 0.0;
+    for (int i = 0; i < 4; ++i) {
+      mm = fmax(mm, red[0][i]);
+      cc += red[1][i];
+    }
+    gbl(P.refout)[0] = mm;
+    gbl(P.refout)[1] = cc;
+    const bool converged = (mm < STOP_TOL) && (cc == 0.0);
+    if (converged || sweep == MAX_SWEEPS - 1) *gbl(P.refstate) = sweep + 1;
+  }
+}
+
+// lambda_k from the final basis Ub (sweep count = refstate) and P = W Ub (R1):
+// one workgroup per pair
+__global__ __launch_bounds__(256) void k_ref_final(const Prob* __restrict__ probs) {
+  __shared__ double red[4][4];
+  const Prob& P = probs[blockIdx.z];
+  const long n = P.n, N = P.N, ld = P.ld;
+  const long k = blockIdx.x;
+  if (k >= n) return;   // uniform
+  const BSE_GLOBAL double* __restrict__ U = gbl(basis(P, *gbl(P.refstate)));
+  const BSE_GLOBAL double* __restrict__ PW = gbl(P.R1);
+  const BSE_GLOBAL double* ua = U + k * ld;
+  const BSE_GLOBAL double* ub = U + (n + k) * ld;
+  const BSE_GLOBAL double* pa = PW + k * ld;
+  double s = 0.0, gaa = 0.0, gbb = 0.0, gab = 0.0;
+  for (long r = threadIdx.x; r < N; r += 256) {
+    const double a = ua[r], b = ub[r];
+    s += b * pa[r];
+    gaa += a * a;
+    gbb += b * b;
+    gab += a * b;
+  }
+  s = block_sum(s, red[0]);
+  gaa = block_sum(gaa, red[1]);
+  gbb = block_sum(gbb, red[2]);
+  gab = block_sum(gab, red[3]);
+  if (threadIdx.x == 0) gbl(P.shift)[k] = -s / sqrt(gaa * gbb - gab * gab);
+}
+
+// ascending order: rank of each eigenvalue by counting (ties by index)
+__global__ __launch_bounds__(256) void k_ref_sort(const Prob* __restrict__ probs) {
+  const Prob& P = probs[blockIdx.z];
+  const int n = P.n;
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= n) return;
+  const BSE_CONST double* __restrict__ lam = ro(P.shift);
+  const double x = lam[k];
+  int rank = 0;
+  for (int m = 0; m < n; ++m) {
+    const double y = lam[m];
+    rank += (y < x) || (y == x && m < k);
+  }
+  gbl(P.perm)[rank] = k;
+  gbl(P.lambda)[rank] = x;
+}
+
+// final basis / sqrt(2) into Z
+__global__ __launch_bounds__(256) void k_ref_out(const Prob* __restrict__ probs) {
+  const Prob& P = probs[blockIdx.z];
+  const long N = P.N;
+  const long r = (long)blockIdx.x * 64 + (threadIdx.x & 63);
+  const long c0 = (long)blockIdx.y * 64 + (threadIdx.x >> 6) * 16;
+  if (r >= N) return;
+  const BSE_GLOBAL double* __restrict__ U = gbl(basis(P, *gbl(P.refstate)));
+  BSE_GLOBAL double* __restrict__ Z = gbl(P.Z);
+  const double f = 0.70710678118654752440;   // 1/sqrt(2)
+  for (int q = 0; q < 16; ++q) {
+    const long c = c0 + q;
+    if (c >= N) break;
+    Z[r + c * P.ld] = f * U[r + c * P.ld];
+  }
+}
+
+dim3 grid_NN(const Batch& b) {
+  const long N0 = b.maxN();
+  return dim3((unsigned)((N0 + 63) / 64), (unsigned)((N0 + 63) / 64), (unsigned)b.count);
+}
+
+}  // namespace
+
+int refine_batched(hipStream_t s, const Batch& b, const RefineIO& io, RefineStats* st) {
+  if (b.count <= 0) return 0;
+  const int n0 = b.maxn();
+  k_ref_reset<<<dim3(1, 1, (unsigned)b.count), 64, 0, s>>>(b.dev);
+  BSE_LAUNCHED();
+  k_ref_scale<<<grid_NN(b), 256, 0, s>>>(b.dev, 1.41421356237309504880);
+  BSE_LAUNCHED();
+  int sweeps = 0;
+  for (int sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
+    BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_P, sweep));
+    BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_S, sweep));
+    BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_G, sweep));
+    k_ref_lambda<<<dim3((unsigned)((n0 + 63) / 64), 1, (unsigned)b.count), 64, 0, s>>>(b.dev, sweep);
+    BSE_LAUNCHED();
+    k_ref_F<<<grid_NN(b), 256, 0, s>>>(b.dev, sweep);
+    BSE_LAUNCHED();
+    k_ref_decide<<<dim3(1, 1, (unsigned)b.count), 256, 0, s>>>(b.dev, sweep);
+    BSE_LAUNCHED();
+    BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_U, sweep));
+    sweeps = sweep + 1;
+    // every problem's state and largest correction, to decide on the host
+    BSE_HIP(hipMemcpyAsync(io.hstate, io.dstate, io.nslots * sizeof(int), hipMemcpyDeviceToHost, s));
+    BSE_HIP(hipMemcpyAsync(io.hout, io.dout, io.nslots * 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    BSE_HIP(hipStreamSynchronize(s));
+    bool all_done = true;
+    double worst = 0.0;
+    for (int i = 0; i < b.count; ++i) {
+      const long slot = b.host[i].refstate - io.dstate;
+      const int state = io.hstate[slot];
+      if (state == 0) all_done = false;
+      if (state == 0 || state == sweep + 1) worst = fmax(worst, io.hout[2 * slot]);
+    }
+    if (st) {
+      st->last_correction = worst;
+      if (sweep == 0) st->first_correction = worst;
+    }
+    if (all_done) break;
+  }
+  if (st) st->sweeps = sweeps;
+  // eigenvalues from each problem's final basis, sorted; eigenvectors to Z
+  BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_P, -1));
+  k_ref_final<<<dim3((unsigned)n0, 1, (unsigned)b.count), 256, 0, s>>>(b.dev);
+  BSE_LAUNCHED();
+  k_ref_sort<<<dim3((unsigned)((n0 + 255) / 256), 1, (unsigned)b.count), 256, 0, s>>>(b.dev);
+  BSE_LAUNCHED();
+  k_ref_out<<<grid_NN(b), 256, 0, s>>>(b.dev);
+  BSE_LAUNCHED();
+  return 0;
+}
+
+}  // namespace bse

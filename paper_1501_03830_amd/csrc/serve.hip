@@ -139,7 +139,7 @@ int solve_batch(Server* S, int k, std::vector<Req*>& batch, size_t hdr_off) {
     bases[i] = S->pool + batch[i]->off;
   }
   Setup St;
-  BSE_TRY(setup_batch(L, count, Ns.data(), S->pool + hdr_off, bases.data(), &St));
+  BSE_TRY(setup_batch(L, count, Ns.data(), batch[0]->r.prec, S->pool + hdr_off, bases.data(), &St));
   for (int i = 0; i < count; ++i) {
     const bse_request& r = batch[i]->r;
     Prob& P = L->hprobs[i];
@@ -289,7 +289,7 @@ int server_submit(Server* S, const bse_request* r, hipStream_t caller, uint64_t*
   Req q;
   q.r = *r;
   q.N = 2L * r->n;
-  q.bytes = problem_bytes(q.N);
+  q.bytes = problem_bytes(q.N, r->prec);
   if (q.bytes + header_bytes(S->max_batch) > S->alloc.size())
     return set_error(BSE_ENOMEM, "request footprint exceeds the request pool");
   BSE_HIP(hipEventCreateWithFlags(&q.ready, hipEventDisableTiming));

@@ -26,6 +26,9 @@
 //   sk_update reduces the partials into p, applies the panel corrections,
 //             brings the next column up to date and leaves one partial
 //             squared norm of it per workgroup.
+// W is held in FP64, or in FP32 for the mixed-precision path (the kernels are
+// templates on its element type); sums, norms, v and p are always FP64.
+//
 // No workgroup waits for or signals another inside a launch: on this
 // multi-XCD device a release fence per workgroup costs tens of nanoseconds
 // each, serialised over the whole device.
@@ -64,13 +67,26 @@ __device__ inline void larfg(double x0, double xnorm, double& beta, double& tau,
   scale = 1.0 / (x0 - beta);
 }
 
+// The matrix being reduced: P.W (FP64) or its FP32 copy P.W32.
+template <class WT>
+__device__ inline WT* wmat(const Prob& P);
+template <>
+__device__ inline double* wmat<double>(const Prob& P) {
+  return P.W;
+}
+template <>
+__device__ inline float* wmat<float>(const Prob& P) {
+  return P.W32;
+}
+
 // Reflector of column j from the (already up to date) column itself.
+template <class WT>
 __global__ __launch_bounds__(256) void sk_start(const Prob* __restrict__ probs, int j) {
   __shared__ double red[4];
   const Prob& P = probs[blockIdx.z];
   const int N = P.N;
   if (j > N - 2) return;  // uniform
-  const BSE_CONST double* __restrict__ W = ro(P.W);
+  const BSE_CONST WT* __restrict__ W = ro(wmat<WT>(P));
   const long ld = P.ld;
   BSE_GLOBAL Ctrl* __restrict__ ctrl = (BSE_GLOBAL Ctrl*)P.ctrl;
   double ss = 0.0;
@@ -118,6 +134,7 @@ __device__ inline double vval(Ptr W, long ld, int j, int s, int N, double scale,
 // blockIdx.y == 0 (dispatched first): workgroups (d, g) store v_i for row
 //   blocks d*16 .. d*16+15 and their share of the panel dot products V^T v,
 //   P^T v (summed by the update kernel).
+template <class WT>
 __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, int j, int i) {
   __shared__ double rsum[TMAX][4][TS];   // per-wave row sums of every tile
   const Prob& P = probs[blockIdx.z];
@@ -130,7 +147,7 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
   const int nchunk = (nblk + T - 1) / T;
   const long ld = P.ld, ldy = P.ld;
   const int dstride = (int)(ld / TS);
-  const BSE_CONST double* __restrict__ W = ro(P.W);
+  const BSE_CONST WT* __restrict__ W = ro(wmat<WT>(P));
   const BSE_CONST Ctrl* __restrict__ ctrl = (const BSE_CONST Ctrl*)P.ctrl;
   BSE_GLOBAL double* __restrict__ Y1 = gbl(P.Y1);
   BSE_GLOBAL double* __restrict__ Y2 = gbl(P.Y2);
@@ -299,6 +316,7 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
 // p_i = tau (S v + V c_P - P c_V) for the rows of block b, the in-place store
 // of v_i, the update of the next column and, in the last workgroup, its
 // reflector.  The panel sums over l are split over the four wavefronts.
+template <class WT>
 __global__ __launch_bounds__(256) void sk_update(const Prob* __restrict__ probs, int j, int i) {
   __shared__ double cs[2 * NBMAX];
   __shared__ double ys_row[2 * NBMAX];   // Y1 row s (v_l[s], p_l[s])
@@ -321,7 +339,7 @@ __global__ __launch_bounds__(256) void sk_update(const Prob* __restrict__ probs,
   const int nbp = min(NBMAX, N - 1 - k0);
   const long ld = P.ld, ldy = P.ld;
   const int dstride = (int)(ld / TS);
-  BSE_GLOBAL double* __restrict__ W = gbl(P.W);
+  BSE_GLOBAL WT* __restrict__ W = gbl(wmat<WT>(P));
   BSE_GLOBAL Ctrl* __restrict__ ctrl = (BSE_GLOBAL Ctrl*)P.ctrl;
   BSE_GLOBAL double* __restrict__ Y1 = gbl(P.Y1);
   BSE_GLOBAL double* __restrict__ Y2 = gbl(P.Y2);
@@ -437,17 +455,19 @@ __global__ __launch_bounds__(256) void sk_update(const Prob* __restrict__ probs,
   if (part == 0 && r >= s + 1 && r < N) {
     double upd = W[r + (long)s * ld] + red2[0][t] + red2[1][t] + red2[2][t] + red2[3][t];
     upd += Y1[r + (long)(2 * i) * ldy] * sval_s - pr[t];
-    W[r + (long)s * ld] = upd;
+    // the column as stored (rounded to T) is what the next reflector sees
+    const double upds = (double)(WT)upd;
+    W[r + (long)s * ld] = (WT)upd;
     if (r == s + 1) {
-      ctrl->x0 = upd;
+      ctrl->x0 = upds;
       if (s == N - 2) {
         // the last column has nothing below its subdiagonal: its reflector
         // is the identity (dlarfg with a zero norm)
-        alpha[s] = -upd;
+        alpha[s] = -upds;
         tau_arr[s] = 0.0;
       }
     }
-    if (r >= s + 2) nrm = upd * upd;
+    if (r >= s + 2) nrm = upds * upds;
   }
   nrm = block_sum(nrm, red4);
   if (tid == 0) normpart[b] = nrm;
@@ -485,13 +505,14 @@ void sktrd_bind_work(char* base, long N, long ld, Prob* P) {
   P->ctrl = take(sizeof(Ctrl));
 }
 
-int sktrd_batched(hipStream_t s, const Batch& b, KernelTimer* timer) {
+template <class WT>
+static int sktrd_run(hipStream_t s, const Batch& b, KernelTimer* timer) {
   const int N0 = b.maxN();
   if (N0 < 2) return 0;
   const int nb = NBMAX;
   for (int k0 = 0; k0 <= N0 - 2; k0 += nb) {
     const int nstart = b.active_N_above(k0 + 1);   // N - 2 >= k0
-    sk_start<<<dim3(1, 1, (unsigned)nstart), 256, 0, s>>>(b.dev, k0);
+    sk_start<WT><<<dim3(1, 1, (unsigned)nstart), 256, 0, s>>>(b.dev, k0);
     BSE_LAUNCHED();
     for (int i = 0; i < nb; ++i) {
       const int j = k0 + i;
@@ -511,22 +532,28 @@ int sktrd_batched(hipStream_t s, const Batch& b, KernelTimer* timer) {
       if (timed) BSE_HIP(hipEventRecord(timer->ev[timer->used], s));
       const int nduty = 4 * ((nblk0 + DUTY_BLK - 1) / DUTY_BLK);
       const unsigned gx = (unsigned)(nblk0 > nduty ? nblk0 : nduty);
-      sk_symv<<<dim3(gx, (unsigned)(nchunk0 + 1), (unsigned)nact), 256, 0, s>>>(b.dev, j, i);
+      sk_symv<WT><<<dim3(gx, (unsigned)(nchunk0 + 1), (unsigned)nact), 256, 0, s>>>(b.dev, j, i);
       BSE_LAUNCHED();
       if (timed) {
         BSE_HIP(hipEventRecord(timer->ev[timer->used + 1], s));
         timer->used += 2;
         for (int q = 0; q < nact; ++q) {
           const double m = (double)(b.host[q].N - sidx);   // trailing order
-          timer->bytes += 8.0 * m * (m - 1.0) * 0.5;
+          timer->bytes += sizeof(WT) * m * (m - 1.0) * 0.5;
         }
       }
-      sk_update<<<dim3((unsigned)nblk0, 1, (unsigned)nact), 256, 0, s>>>(b.dev, j, i);
+      sk_update<WT><<<dim3((unsigned)nblk0, 1, (unsigned)nact), 256, 0, s>>>(b.dev, j, i);
       BSE_LAUNCHED();
     }
     BSE_TRY(gemm_batched(s, b, nstart, GOP_SKTRD_R2K, k0));
   }
   return 0;
+}
+
+int sktrd_batched(hipStream_t s, const Batch& b, KernelTimer* timer) {
+  if (b.count <= 0) return 0;
+  if (b.host[0].prec == BSE_PREC_FP32_REFINE) return sktrd_run<float>(s, b, timer);
+  return sktrd_run<double>(s, b, timer);
 }
 
 }  // namespace bse

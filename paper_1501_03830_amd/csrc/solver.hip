@@ -68,15 +68,19 @@ static int set_errorf(int code, const char* fmt, int i) {
 // ------------------------------------------------------------------------
 struct Plan {
   long N = 0, n = 0, ld = 0;
+  int prec = BSE_PREC_FP64;
   size_t off_L = 0, off_W = 0, off_Z = 0, off_Vt = 0, off_inv = 0, off_small = 0, off_sk = 0,
          off_bt = 0, off_linv = 0, off_gscr = 0;
   size_t gscr_bytes = 0;
+  // mixed-precision path only
+  size_t off_W32 = 0, off_R = 0, off_refmax = 0, off_perm = 0;
   size_t total = 0;
 };
 
-static Plan make_plan(long N) {
+static Plan make_plan(long N, int prec) {
   Plan p;
   p.N = N;
+  p.prec = prec;
   p.n = N / 2;
   p.ld = square_ld(N);
   size_t cur = 0;
@@ -101,16 +105,25 @@ static Plan make_plan(long N) {
   // split-K partial products: only products of large problems are split
   p.gscr_bytes = (N > 2048) ? (size_t)16 * 64 * p.ld * sizeof(double) : 0;
   if (p.gscr_bytes) p.off_gscr = take(p.gscr_bytes);
+  if (prec == BSE_PREC_FP32_REFINE) {
+    p.off_W32 = take((size_t)p.ld * p.ld * sizeof(float));
+    p.off_R = take(4 * sq);   // R1..R4
+    const size_t nt = (size_t)(p.ld / 64);
+    p.off_refmax = take(2 * nt * nt * sizeof(double));
+    p.off_perm = take((size_t)p.n * sizeof(int));
+  }
   p.total = cur;
   return p;
 }
 
-size_t problem_bytes(long N) { return make_plan(N).total; }
+size_t problem_bytes(long N, int prec) { return make_plan(N, prec).total; }
 
-// Descriptor array and info words of a batch.
-size_t header_bytes(int count) {
-  return (size_t)round_up((long)(count * sizeof(Prob)), 256) + (size_t)round_up((long)(count * 2 * sizeof(int)), 256);
-}
+// Descriptor array, then per slot: two info words, the refinement state word
+// and two refinement maxima.
+static size_t hdr_info_off(int count) { return (size_t)round_up((long)(count * sizeof(Prob)), 256); }
+static size_t hdr_state_off(int count) { return hdr_info_off(count) + (size_t)round_up((long)(count * 2 * sizeof(int)), 256); }
+static size_t hdr_ref_off(int count) { return hdr_state_off(count) + (size_t)round_up((long)(count * sizeof(int)), 256); }
+size_t header_bytes(int count) { return hdr_ref_off(count) + (size_t)round_up((long)(count * 2 * sizeof(double)), 256); }
 
 // Workspace pointers of one problem.
 static void bind_problem(const Plan& p, char* base, Prob* P) {
@@ -134,6 +147,18 @@ static void bind_problem(const Plan& p, char* base, Prob* P) {
   P->gscr_bytes = p.gscr_bytes;
   sktrd_bind_work(base + p.off_sk, p.N, p.ld, P);
   backtr_bind_work(base + p.off_bt, p.N, p.ld, P);
+  P->prec = p.prec;
+  if (p.prec == BSE_PREC_FP32_REFINE) {
+    P->W32 = reinterpret_cast<float*>(base + p.off_W32);
+    double* R = reinterpret_cast<double*>(base + p.off_R);
+    const size_t sq = (size_t)p.ld * p.ld;
+    P->R1 = R;
+    P->R2 = R + sq;
+    P->R3 = R + 2 * sq;
+    P->R4 = R + 3 * sq;
+    P->refmax = reinterpret_cast<double*>(base + p.off_refmax);
+    P->perm = reinterpret_cast<int*>(base + p.off_perm);
+  }
 }
 
 static int get_workspace(bse_ctx* ctx, size_t bytes, char** base) {
@@ -169,12 +194,18 @@ int lane_reserve(Lane* L, int count) {
   if (L->hcap >= count) return 0;
   if (L->hprobs) BSE_HIP(hipHostFree(L->hprobs));
   if (L->hinfo) BSE_HIP(hipHostFree(L->hinfo));
+  if (L->hstate) BSE_HIP(hipHostFree(L->hstate));
+  if (L->hrefout) BSE_HIP(hipHostFree(L->hrefout));
   L->hprobs = nullptr;
   L->hinfo = nullptr;
+  L->hstate = nullptr;
+  L->hrefout = nullptr;
   L->hcap = 0;
   const int cap = std::max(count, 16);
   BSE_HIP(hipHostMalloc(reinterpret_cast<void**>(&L->hprobs), cap * sizeof(Prob), hipHostMallocDefault));
   BSE_HIP(hipHostMalloc(reinterpret_cast<void**>(&L->hinfo), cap * 2 * sizeof(int), hipHostMallocDefault));
+  BSE_HIP(hipHostMalloc(reinterpret_cast<void**>(&L->hstate), cap * sizeof(int), hipHostMallocDefault));
+  BSE_HIP(hipHostMalloc(reinterpret_cast<void**>(&L->hrefout), cap * 2 * sizeof(double), hipHostMallocDefault));
   L->hcap = cap;
   return 0;
 }
@@ -187,8 +218,12 @@ void lane_release(Lane* L) {
   L->kev.clear();
   if (L->hprobs) (void)hipHostFree(L->hprobs);
   if (L->hinfo) (void)hipHostFree(L->hinfo);
+  if (L->hstate) (void)hipHostFree(L->hstate);
+  if (L->hrefout) (void)hipHostFree(L->hrefout);
   L->hprobs = nullptr;
   L->hinfo = nullptr;
+  L->hstate = nullptr;
+  L->hrefout = nullptr;
   L->hcap = 0;
 }
 
@@ -204,17 +239,22 @@ static int mark(Lane* L, bool timed, int i) {
   return 0;
 }
 
-int setup_batch(Lane* L, int count, const long* Ns, char* header, char* const* bases, Setup* S) {
+int setup_batch(Lane* L, int count, const long* Ns, int prec, char* header, char* const* bases, Setup* S) {
   BSE_TRY(lane_reserve(L, count));
+  S->count = count;
   S->dprobs = reinterpret_cast<Prob*>(header);
-  S->dinfo = reinterpret_cast<int*>(header + round_up((long)(count * sizeof(Prob)), 256));
+  S->dinfo = reinterpret_cast<int*>(header + hdr_info_off(count));
+  S->dstate = reinterpret_cast<int*>(header + hdr_state_off(count));
+  S->dref = reinterpret_cast<double*>(header + hdr_ref_off(count));
   S->total = header_bytes(count);
   for (int i = 0; i < count; ++i) {
-    const Plan plan = make_plan(Ns[i]);
+    const Plan plan = make_plan(Ns[i], prec);
     Prob& P = L->hprobs[i];
     memset(&P, 0, sizeof(P));
     bind_problem(plan, bases[i], &P);
     P.info = S->dinfo + 2 * i;
+    P.refstate = S->dstate + i;
+    P.refout = S->dref + 2 * i;
     S->total += plan.total;
   }
   return 0;
@@ -222,18 +262,18 @@ int setup_batch(Lane* L, int count, const long* Ns, char* header, char* const* b
 
 // Workspace from the context (arena or own allocation) for problems of
 // orders Ns[0..count), laid out header first, then problem by problem.
-static int setup_ctx_batch(bse_ctx* ctx, int count, const long* Ns, Setup* S) {
+static int setup_ctx_batch(bse_ctx* ctx, int count, const long* Ns, int prec, Setup* S) {
   size_t total = header_bytes(count);
   std::vector<size_t> offs(count);
   for (int i = 0; i < count; ++i) {
     offs[i] = total;
-    total += problem_bytes(Ns[i]);
+    total += problem_bytes(Ns[i], prec);
   }
   char* base = nullptr;
   BSE_TRY(get_workspace(ctx, total, &base));
   std::vector<char*> bases(count);
   for (int i = 0; i < count; ++i) bases[i] = base + offs[i];
-  return setup_batch(&ctx->lane, count, Ns, base, bases.data(), S);
+  return setup_batch(&ctx->lane, count, Ns, prec, base, bases.data(), S);
 }
 
 static int upload(Lane* L, const Setup& S, int count) {
@@ -251,6 +291,11 @@ static int read_infos(Lane* L, const Setup& S, int count) {
 // L->hprobs[0..count).  On return L->hinfo holds, per original slot,
 // info[0] (Cholesky of M, > 0 = not definite) and info[1] (Cholesky of a
 // cluster Gram matrix, > 0 = reorthogonalisation failed).
+// Stages in the order they run (event i marks the start of stage order[i]).
+static const int kStageOrder[BSE_NUM_STAGES] = {
+    BSE_STAGE_BUILD_M, BSE_STAGE_POTRF,   BSE_STAGE_FORM_W,  BSE_STAGE_SKTRD,   BSE_STAGE_BISECT, BSE_STAGE_INVIT,
+    BSE_STAGE_REORTH,  BSE_STAGE_APPLY_U, BSE_STAGE_REFINE,  BSE_STAGE_APPLY_L, BSE_STAGE_FINISH};
+
 int run_chain(Lane* L, const Setup& S, int count, bool vectors, bse_report* rep) {
   hipStream_t s = L->stream;
   const bool timed = rep != nullptr;
@@ -260,12 +305,15 @@ int run_chain(Lane* L, const Setup& S, int count, bool vectors, bse_report* rep)
   b.count = count;
   b.host = L->hprobs;
   b.dev = S.dprobs;
+  const int prec = count > 0 ? L->hprobs[0].prec : BSE_PREC_FP64;
+  const bool mixed = prec == BSE_PREC_FP32_REFINE;
+  int ev = 0;
 
-  BSE_TRY(mark(L, timed, 0));
+  BSE_TRY(mark(L, timed, ev++));
   BSE_TRY(build_M_batched(s, b));
-  BSE_TRY(mark(L, timed, 1));
+  BSE_TRY(mark(L, timed, ev++));
   BSE_TRY(potrf_batched(s, b, 0, true));
-  BSE_TRY(mark(L, timed, 2));
+  BSE_TRY(mark(L, timed, ev++));
   BSE_TRY(read_infos(L, S, count));
   // drop the problems whose M is not definite; the rest keep their order
   int live = 0;
@@ -280,8 +328,11 @@ int run_chain(Lane* L, const Setup& S, int count, bool vectors, bse_report* rep)
     b.count = live;
     if (live > 0) BSE_TRY(upload(L, S, live));
   }
-  BSE_TRY(form_W_batched(s, b, false));
-  BSE_TRY(mark(L, timed, 3));
+  // the mixed path keeps the full FP64 W for the refinement and reduces an
+  // FP32 copy of its lower triangle
+  BSE_TRY(form_W_batched(s, b, mixed));
+  if (mixed) BSE_TRY(to_f32_batched(s, b));
+  BSE_TRY(mark(L, timed, ev++));
   KernelTimer ktimer;
   if (L->timing && b.count > 0) {
     const long N0 = b.maxN();
@@ -295,35 +346,55 @@ int run_chain(Lane* L, const Setup& S, int count, bool vectors, bse_report* rep)
     ktimer.cap = (int)L->kev.size();
   }
   BSE_TRY(sktrd_batched(s, b, L->timing ? &ktimer : nullptr));
-  BSE_TRY(mark(L, timed, 4));
+  BSE_TRY(mark(L, timed, ev++));
   BSE_TRY(bisect_batched(s, b));
-  BSE_TRY(mark(L, timed, 5));
-  if (vectors) {
+  BSE_TRY(mark(L, timed, ev++));
+  RefineStats rstats;
+  // the refinement needs the eigenvector basis even when only eigenvalues
+  // are wanted
+  if (vectors || mixed) {
     BSE_TRY(invit_batched(s, b));
-    BSE_TRY(mark(L, timed, 6));
+    BSE_TRY(mark(L, timed, ev++));
     BSE_TRY(reorth_batched(s, b));
-    BSE_TRY(mark(L, timed, 7));
+    BSE_TRY(mark(L, timed, ev++));
     BSE_TRY(apply_UD_batched(s, b));
-    BSE_TRY(mark(L, timed, 8));
-    BSE_TRY(gemm_batched(s, b, b.count, GOP_APPLY_L, 0));
-    BSE_TRY(mark(L, timed, 9));
-    BSE_TRY(finish_batched(s, b));
+    BSE_TRY(mark(L, timed, ev++));
+    if (mixed) {
+      RefineIO io;
+      io.dstate = S.dstate;
+      io.dout = S.dref;
+      io.hstate = L->hstate;
+      io.hout = L->hrefout;
+      io.nslots = S.count;
+      BSE_TRY(refine_batched(s, b, io, &rstats));
+    }
+    BSE_TRY(mark(L, timed, ev++));
+    if (vectors) {
+      BSE_TRY(gemm_batched(s, b, b.count, GOP_APPLY_L, 0));
+      BSE_TRY(mark(L, timed, ev++));
+      BSE_TRY(finish_batched(s, b));
+    } else {
+      BSE_TRY(mark(L, timed, ev++));
+    }
   } else {
-    for (int i = 6; i <= 9; ++i) BSE_TRY(mark(L, timed, i));
+    for (int i = 0; i < 5; ++i) BSE_TRY(mark(L, timed, ev++));
   }
-  BSE_TRY(mark(L, timed, 10));
+  BSE_TRY(mark(L, timed, ev++));
   BSE_TRY(read_infos(L, S, count));
   if (timed) {
     memset(rep, 0, sizeof(*rep));
     float ms = 0.f;
     for (int i = 0; i < BSE_NUM_STAGES; ++i) {
       BSE_HIP(hipEventElapsedTime(&ms, L->ev[i], L->ev[i + 1]));
-      rep->stage_ms[i] = ms;
+      rep->stage_ms[kStageOrder[i]] = ms;
     }
     BSE_HIP(hipEventElapsedTime(&ms, L->ev[0], L->ev[BSE_NUM_STAGES]));
     rep->total_ms = ms;
-    rep->prec = BSE_PREC_FP64;
+    rep->prec = prec;
     rep->workspace_bytes = S.total;
+    rep->refine_sweeps = rstats.sweeps;
+    rep->refine_first_correction = rstats.first_correction;
+    rep->refine_correction = rstats.last_correction;
     if (L->timing) {
       double tot = 0.0;
       for (int i = 0; i + 1 < ktimer.used; i += 2) {
@@ -345,7 +416,7 @@ static int prologue(bse_ctx* ctx) {
 }
 
 // One problem of order N for the stage entry points.
-static int setup_single(bse_ctx* ctx, long N, Setup* S) { return setup_ctx_batch(ctx, 1, &N, S); }
+static int setup_single(bse_ctx* ctx, long N, Setup* S) { return setup_ctx_batch(ctx, 1, &N, BSE_PREC_FP64, S); }
 
 static Batch single_batch(bse_ctx* ctx, const Setup& S) {
   Batch b;
@@ -400,19 +471,21 @@ int bse_ctx_set_timing(bse_ctx* ctx, int enable) {
   return 0;
 }
 
+static bool valid_prec(int prec) { return prec == BSE_PREC_FP64 || prec == BSE_PREC_FP32_REFINE; }
+
 size_t bse_footprint_bytes(int n, int prec, unsigned flags) {
   (void)flags;
-  if (n <= 0 || prec != BSE_PREC_FP64) return 0;
-  return header_bytes(1) + make_plan(2L * n).total;
+  if (n <= 0 || !valid_prec(prec)) return 0;
+  return header_bytes(1) + make_plan(2L * n, prec).total;
 }
 
 size_t bse_footprint_batched_bytes(int count, const int* n, int prec, unsigned flags) {
   (void)flags;
-  if (count <= 0 || !n || prec != BSE_PREC_FP64) return 0;
+  if (count <= 0 || !n || !valid_prec(prec)) return 0;
   size_t total = header_bytes(count);
   for (int i = 0; i < count; ++i) {
     if (n[i] <= 0) return 0;
-    total += make_plan(2L * n[i]).total;
+    total += make_plan(2L * n[i], prec).total;
   }
   return total;
 }
@@ -426,7 +499,7 @@ int bse_solve(bse_ctx* ctx, int n, const void* A, int lda, const void* B, int ld
   if (lda < n) return set_error(-4, "lda < n");
   if (!B) return set_error(-5, "B is NULL");
   if (ldb < n) return set_error(-6, "ldb < n");
-  if (prec != BSE_PREC_FP64) return set_error(-7, "unsupported precision policy");
+  if (!valid_prec(prec)) return set_error(-7, "unsupported precision policy");
   if (flags & ~(BSE_WANT_VECTORS | BSE_WANT_WEIGHTS)) return set_error(-8, "unknown flags");
   if (!lambda) return set_error(-9, "lambda is NULL");
   const bool vec = (flags & BSE_WANT_VECTORS) != 0;
@@ -439,7 +512,7 @@ int bse_solve(bse_ctx* ctx, int n, const void* A, int lda, const void* B, int ld
   BSE_TRY(prologue(ctx));
   Setup S;
   const long N = 2L * n;
-  BSE_TRY(setup_ctx_batch(ctx, 1, &N, &S));
+  BSE_TRY(setup_ctx_batch(ctx, 1, &N, prec, &S));
   Prob& P = ctx->lane.hprobs[0];
   P.A = static_cast<const double*>(A);
   P.lda = lda;
@@ -471,7 +544,7 @@ int bse_solve_batched(bse_ctx* ctx, int count, const int* n, const void* const* 
   if (!lda) return set_error(-5, "lda is NULL");
   if (!B) return set_error(-6, "B is NULL");
   if (!ldb) return set_error(-7, "ldb is NULL");
-  if (prec != BSE_PREC_FP64) return set_error(-8, "unsupported precision policy");
+  if (!valid_prec(prec)) return set_error(-8, "unsupported precision policy");
   if (flags & ~(BSE_WANT_VECTORS | BSE_WANT_WEIGHTS)) return set_error(-9, "unknown flags");
   if (!lambda) return set_error(-10, "lambda is NULL");
   const bool vec = (flags & BSE_WANT_VECTORS) != 0;
@@ -502,7 +575,7 @@ int bse_solve_batched(bse_ctx* ctx, int count, const int* n, const void* const* 
   std::vector<long> Ns(count);
   for (int k = 0; k < count; ++k) Ns[k] = 2L * n[order[k]];
   Setup S;
-  BSE_TRY(setup_ctx_batch(ctx, count, Ns.data(), &S));
+  BSE_TRY(setup_ctx_batch(ctx, count, Ns.data(), prec, &S));
   for (int k = 0; k < count; ++k) {
     const int i = order[k];
     Prob& P = ctx->lane.hprobs[k];
@@ -537,7 +610,7 @@ static int check_request(const bse_request* r) {
   if (r->lda < r->n) return set_error(-2, "request: lda < n");
   if (!r->B) return set_error(-2, "request: B is NULL");
   if (r->ldb < r->n) return set_error(-2, "request: ldb < n");
-  if (r->prec != BSE_PREC_FP64) return set_error(-2, "request: unsupported precision policy");
+  if (!valid_prec(r->prec)) return set_error(-2, "request: unsupported precision policy");
   if (r->flags & ~(BSE_WANT_VECTORS | BSE_WANT_WEIGHTS)) return set_error(-2, "request: unknown flags");
   if (!r->lambda) return set_error(-2, "request: lambda is NULL");
   const bool vec = (r->flags & BSE_WANT_VECTORS) != 0;
