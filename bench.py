@@ -229,6 +229,55 @@ def calibrate_copy(gib: int = 1, reps: int = 5):
                                          "launches": reps}}), flush=True)
 
 
+def mixed_bench(ctx, n, Ac, Bc, drb, lam64, X64, steps: int, warmup: int):
+    """The mixed-precision path (FP32 reduction, FP64 refinement) on the same
+    resident problem, compared with the FP64 path's result lam64, X64."""
+    import torch
+    from paper_1501_03830_amd import _lib
+
+    dev = Ac.device
+    lam = torch.empty(n, dtype=torch.float64, device=dev)
+    X = torch.empty((n, 2 * n), dtype=torch.complex128, device=dev)
+    w = torch.empty(n, dtype=torch.complex128, device=dev)
+    for i in range(warmup):
+        info, rep = ctx.solve_raw(n, Ac, Bc, lam, X, drb, None, w, report=True, prec=_lib.BSE_PREC_FP32_REFINE)
+        assert info == 0
+        print(f"# mixed warmup {i}: {rep['total_ms']:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    reps = []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        info, rep = ctx.solve_raw(n, Ac, Bc, lam, X, drb, None, w, report=True, prec=_lib.BSE_PREC_FP32_REFINE)
+        assert info == 0
+        reps.append(rep)
+        print(f"# mixed step {i}: {rep['total_ms']:.1f} ms (sweeps {rep['refine_sweeps']}, first correction "
+              f"{rep['refine_first_correction']:.2e})", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    # agreement with the FP64 path: eigenvalues relative to lambda_max, and
+    # eigenvectors through |y64_j^H x_j| = 1 (y = S x, y^H x = 1 for each pair)
+    lmax = float(lam64.max())
+    eig = float((lam - lam64).abs().max()) / lmax
+    Xm = X.transpose(0, 1)            # logical 2n x n
+    X6 = X64.transpose(0, 1)
+    Y6 = torch.cat([X6[:n], -X6[n:]], 0)
+    dots = (Y6.conj() * Xm).sum(0).abs()
+    vec = (1.0 - dots).abs()
+    return {
+        "workload": f"same problem as the FP64 solve, BSE_PREC_FP32_REFINE",
+        "s_per_solve": round(dt, 4),
+        "vs_fp64": None,
+        "device_ms": round(float(np.mean([r["total_ms"] for r in reps])), 2),
+        "stage_ms": {k: round(float(np.mean([r["stage_ms"][k] for r in reps])), 2) for k in reps[0]["stage_ms"]},
+        "refine_sweeps": reps[0]["refine_sweeps"],
+        "refine_first_correction": reps[0]["refine_first_correction"],
+        "refine_last_correction": reps[0]["refine_correction"],
+        "eig_err_vs_fp64_rel_lmax": eig,
+        "vec_err_vs_fp64_median": float(vec.median()),
+        "vec_err_vs_fp64_max": float(vec.max()),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -244,6 +293,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched workload")
     ap.add_argument("--batched-only", action="store_true", help="only the batched workload")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision solve")
     ap.add_argument("--serving-count", type=int, default=200)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
@@ -356,6 +406,9 @@ def main():
         "cpu_baseline": None,
     }
     ctx.set_timing(False)
+    if not a.no_mixed:
+        out["fp32_refine"] = mixed_bench(ctx, n, Ac, Bc, drb, lam.clone(), Xbuf.clone(), a.steps, a.warmup)
+        out["fp32_refine"]["vs_fp64"] = round(s_per_solve / out["fp32_refine"]["s_per_solve"], 4)
     del Xbuf
     if not a.no_batched:
         out["batched"] = batched_bench(ctx, a.steps, a.warmup)

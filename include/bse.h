@@ -181,9 +181,10 @@ size_t bse_footprint_bytes(int n, int prec, unsigned flags);
  *            then the eigenpairs are refined in FP64 against the FP64 W by
  *            sweeps of an Ogita-Aishima-type iteration on the real Schur
  *            form of W (not in the paper), until the largest correction is
- *            below 1e-3 with no near-degenerate pair left out (at most 4
- *            sweeps); eigenvalues are then taken from the refined basis,
- *            which puts their error near FP64 rounding (7)
+ *            below 1e-2 with no near-degenerate pair left out (at most 4
+ *            sweeps); eigenvalues are then taken from the refined basis
+ *            (error about 3.5e-5 x correction^4 relative, i.e. below 4e-13;
+ *            eigenvector error about correction^2) (7)
  *   flags    BSE_WANT_VECTORS | BSE_WANT_WEIGHTS (8)
  *   lambda   out: n doubles, the positive eigenvalues ascending (9)
  *   X, ldx   out: complex 2n x n, ldx >= 2n; rows 0..n-1 hold X1, rows

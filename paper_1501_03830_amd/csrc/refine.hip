@@ -21,7 +21,7 @@
 // clusters.  The error of Ub falls quadratically; a problem stops after the
 // sweep whose largest correction is below STOP_TOL with no clamped block,
 // then its eigenvalues are taken from the refined basis (error of order
-// ||W|| STOP_TOL^4) and sorted.  Each problem converges on its own: kernels
+// STOP_TOL^4 relative) and sorted.  Each problem converges on its own: kernels
 // skip problems that finished in an earlier sweep.
 #include <cmath>
 #include <cstring>
@@ -35,7 +35,10 @@ namespace {
 
 constexpr int MAX_SWEEPS = 4;
 constexpr double GCAP = 0.25;
-constexpr double STOP_TOL = 1e-3;
+// A sweep whose largest correction entry is e leaves an eigenvalue error of
+// about 3.5e-5 e^4 relative (measured on clustered s_a = 0.3 spectra,
+// e = 6e-3 .. 6e-2); e <= 1e-2 keeps it near 4e-13, far below 1e-10.
+constexpr double STOP_TOL = 1e-2;
 
 // skip problems whose refinement finished before sweep `sweep`
 __device__ inline bool finished_before(const Prob& P, int sweep) {

@@ -4,10 +4,9 @@ W is reduced to tridiagonal form in FP32 storage, the tridiagonal solve and
 back-transformation run in FP64, and the eigenpairs are then refined in FP64
 against the FP64 W.  The target after refinement is the same as for the
 FP64 path on eigenvalues: max |dlambda| <= 1e-10 ||H||_2.  Eigenvectors and
-weights are checked to 1e-6 and the Table 1 residuals to 1e-8 (the last
-sweep's correction is below 1e-3, so the basis error after it is of order
-1e-6 or smaller; measured 1e-12 .. 5e-10); the measured errors are printed
-per case.  Batched results must equal solo results bit for bit.
+weights are checked to 1e-6 and the Table 1 residuals to 1e-8 (the basis
+error after a sweep is about the square of its correction, measured
+1e-12 .. 5e-10 here); the measured errors are printed per case.  Batched results must equal solo results bit for bit.
 """
 
 import json
