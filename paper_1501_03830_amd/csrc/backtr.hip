@@ -9,9 +9,10 @@
 //     (-1)^((k-1)/2)); the real and imaginary parts of all n vectors are kept
 //     side by side as one real N x N matrix Z = [Re | Im], so that U and L
 //     are applied with real products only (remark 4's real/imaginary split).
-//   * U = H_0 ... H_{N-3} is applied from the left in blocks of reflectors,
-//     last block first, each block as I - V T V^T (compact WY, T from the
-//     forward column-wise recurrence of LAPACK's larft).
+//   * U = H_0 ... H_{N-3} is applied from the left in blocks of 64
+//     reflectors, last block first, each block as I - V T V^T (compact WY);
+//     T is applied by a triangular solve with its inverse
+//     diag(1/tau) + strict_upper(V^T V) (trsm.hip), never formed.
 //   * L is applied by a triangular MFMA product.
 //   * Q = (1/sqrt 2)[I -iI; I iI] and S = diag(I, -I) only combine rows, so
 //     they are folded with the 1/sqrt(lambda) scaling into the kernel that
@@ -76,39 +77,6 @@ __global__ __launch_bounds__(256) void k_extract_V(const Prob* __restrict__ prob
     else v = f32 ? (double)W32[r + (long)(j0 + l) * ldw] : W[r + (long)(j0 + l) * ldw];
     Vb[r + (long)l * ldv] = v;
   }
-}
-
-// T (upper, nbk x nbk, ld NBQ) with H_{j0} ... H_{j0+nbk-1} = I - V T V^T,
-// from S = V^T V:  T[l,l] = tau_l,  T[0:l, l] = -tau_l T[0:l,0:l] S[0:l, l].
-__global__ __launch_bounds__(64) void k_larft(const Prob* __restrict__ probs, int q) {
-  __shared__ double Ts[64][65];   // Ts[col][row]
-  __shared__ double u[64];
-  const Prob& P = probs[blockIdx.z];
-  const int nrefl = P.N - 2;
-  const int j0 = q * NBQ;
-  if (j0 >= nrefl) return;  // uniform
-  const int nbk = min(NBQ, nrefl - j0);
-  const int nbq = NBQ;
-  const BSE_CONST double* __restrict__ S = ro(P.S);
-  const BSE_CONST double* __restrict__ tau = ro(P.tau);
-  BSE_GLOBAL double* __restrict__ T = gbl(P.T);
-  const int i = threadIdx.x;
-  for (int c = 0; c < 64; ++c) Ts[c][i] = 0.0;
-  __syncthreads();
-  for (int l = 0; l < nbk; ++l) {
-    const double tl = tau[j0 + l];
-    if (i < l) u[i] = -tl * S[i + (long)l * nbq];
-    __syncthreads();
-    if (i < l) {
-      double acc = 0.0;
-      for (int m = i; m < l; ++m) acc += Ts[m][i] * u[m];
-      Ts[l][i] = acc;
-    }
-    if (i == l) Ts[l][l] = tl;
-    __syncthreads();
-  }
-  for (int c = 0; c < nbk; ++c)
-    if (i < nbk) T[i + (long)c * nbq] = Ts[c][i];
 }
 
 // X = S Q G Lambda^{-1/2} from G = L U D V_+ = [Re | Im] held in P.W
@@ -295,10 +263,8 @@ int apply_UD_batched(hipStream_t s, const Batch& b) {
     k_extract_V<<<dim3((unsigned)((m0 + 63) / 64), 1, (unsigned)nact), 256, 0, s>>>(b.dev, q);
     BSE_LAUNCHED();
     BSE_TRY(gemm_batched(s, b, nact, GOP_APPLYU_S, q));
-    k_larft<<<dim3(1, 1, (unsigned)nact), 64, 0, s>>>(b.dev, q);
-    BSE_LAUNCHED();
     BSE_TRY(gemm_batched(s, b, nact, GOP_APPLYU_W1, q));
-    BSE_TRY(gemm_batched(s, b, nact, GOP_APPLYU_W2, q));
+    BSE_TRY(wy_solve_batched(s, b, nact, q));
     BSE_TRY(gemm_batched(s, b, nact, GOP_APPLYU_Z, q));
   }
   return 0;

@@ -91,6 +91,8 @@ __global__ __launch_bounds__(256) void k_potf2(const Prob* __restrict__ probs, i
     a[c][r] = (r < nbk && c < nbk && r >= c) ? M[(long)(k0 + r) + (long)(k0 + c) * ld] : 0.0;
   }
   __syncthreads();
+  // thread (row rr, column class cq): updates a[c][rr] for c = cq mod 4
+  const int rr = tid & 63, cq = tid >> 6;
   for (int j = 0; j < nbk; ++j) {
     const double piv = a[j][j];
     if (!(piv > 0.0) || !isfinite(piv)) {
@@ -99,13 +101,12 @@ __global__ __launch_bounds__(256) void k_potf2(const Prob* __restrict__ probs, i
     }
     const double ljj = sqrt(piv);
     __syncthreads();
-    for (int r = j + 1 + tid; r < nbk; r += 256) a[j][r] /= ljj;
+    if (tid < 64 && rr > j && rr < nbk) a[j][rr] /= ljj;
     if (tid == 0) a[j][j] = ljj;
     __syncthreads();
-    const int nc = nbk - j - 1;
-    for (int idx = tid; idx < nc * nc; idx += 256) {
-      const int r = j + 1 + idx % nc, c = j + 1 + idx / nc;
-      if (r >= c) a[c][r] -= a[j][r] * a[j][c];
+    if (rr > j && rr < nbk) {
+      const double lrj = a[j][rr];
+      for (int c = j + 1 + ((cq - (j + 1)) & 3); c <= rr; c += 4) a[c][rr] -= lrj * a[j][c];
     }
     __syncthreads();
   }
@@ -113,36 +114,6 @@ __global__ __launch_bounds__(256) void k_potf2(const Prob* __restrict__ probs, i
     const int r = idx & 63, c = idx >> 6;
     if (r < nbk && c < nbk && r >= c) M[(long)(k0 + r) + (long)(k0 + c) * ld] = a[c][r];
   }
-}
-
-// Inverse of the lower-triangular diagonal block at (b0, b0) into P.linv
-// (64 x 64, ld 64): thread c solves L y = e_c by forward substitution, with
-// y kept in LDS.
-__global__ __launch_bounds__(64) void k_trtri64(const Prob* __restrict__ probs, int sel, int b0) {
-  __shared__ double Lc[TB][TB + 1];  // Lc[col][row]
-  __shared__ double Y[TB][TB + 1];   // Y[col][row]
-  const Prob& P = probs[blockIdx.z];
-  BSE_GLOBAL double* L;
-  long ld;
-  int N;
-  chol_matrix(P, sel, L, ld, N);
-  if (b0 >= N || gbl(P.info)[sel] != 0) return;
-  const int nbk = min(TB, N - b0);
-  BSE_GLOBAL double* __restrict__ Linv = gbl(P.linv);
-  const int c = threadIdx.x;
-  for (int r = 0; r < TB; ++r)
-    Lc[c][r] = (r < nbk && c < nbk && r >= c) ? L[(long)(b0 + r) + (long)(b0 + c) * ld] : 0.0;
-  __syncthreads();
-  for (int r = 0; r < TB; ++r) {
-    double y = 0.0;
-    if (c < nbk && r < nbk && r >= c) {
-      double acc = (r == c) ? 1.0 : 0.0;
-      for (int l = c; l < r; ++l) acc -= Lc[l][r] * Y[c][l];
-      y = acc / Lc[r][r];
-    }
-    Y[c][r] = y;
-  }
-  for (int r = 0; r < TB; ++r) Linv[r + (long)c * TB] = Y[c][r];
 }
 
 // For every lower tile pair (R, C), R >= C, of the leading nrows x nrows
@@ -250,13 +221,6 @@ int zero_upper(hipStream_t s, int N, double* A, long lda) {
   return 0;
 }
 
-int trtri_batched(hipStream_t s, const Batch& b, int nact, int sel, int b0) {
-  if (nact <= 0) return 0;
-  k_trtri64<<<dim3(1, 1, (unsigned)nact), 64, 0, s>>>(b.dev, sel, b0);
-  BSE_LAUNCHED();
-  return 0;
-}
-
 int potrf_batched(hipStream_t s, const Batch& b, int sel, bool reset_info) {
   if (b.count <= 0) return 0;
   if (reset_info) {
@@ -266,7 +230,6 @@ int potrf_batched(hipStream_t s, const Batch& b, int sel, bool reset_info) {
   // order of the factored matrix: N (sel 0) or n (sel 1); both sort with N
   auto order = [sel](const Prob& P) { return sel == 0 ? P.N : P.n; };
   const int Nmax = order(b.host[0]);
-  const int TOPS = sel == 0 ? GOP_POTRF_TRSM : GOP_GRAM_TRSM;
   const int SOPS = sel == 0 ? GOP_POTRF_SYRK : GOP_GRAM_SYRK;
   for (int k0 = 0; k0 < Nmax; k0 += TB) {
     int nact = 0;  // problems with a diagonal block at k0
@@ -276,9 +239,8 @@ int potrf_batched(hipStream_t s, const Batch& b, int sel, bool reset_info) {
     int nrest = 0;  // problems with rows below the block
     while (nrest < nact && order(b.host[nrest]) > k0 + TB) ++nrest;
     if (nrest > 0) {
-      // A21 <- A21 L_kk^{-T}; in place is safe: one column tile of output
-      BSE_TRY(trtri_batched(s, b, nrest, sel, k0));
-      BSE_TRY(gemm_batched(s, b, nrest, TOPS, k0));
+      // A21 <- A21 L_kk^{-T}, then the trailing update
+      BSE_TRY(trsm_rows_batched(s, b, nrest, sel, k0));
       BSE_TRY(gemm_batched(s, b, nrest, SOPS, k0));
     }
   }

@@ -63,7 +63,7 @@ struct Prob {
   double* w;            // complex n weights (output) or null
   unsigned flags;
   // workspace
-  double *L, *W, *Z, *Vt, *inv, *alpha, *tau, *e2, *scal, *shift, *linv, *gscr;
+  double *L, *W, *Z, *Vt, *inv, *alpha, *tau, *e2, *scal, *shift, *gscr;
   size_t gscr_bytes;
   int* cid;
   int* info;            // info[0]: Cholesky of M, info[1]: Cholesky of the Gram matrix

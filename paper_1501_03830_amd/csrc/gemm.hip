@@ -24,6 +24,8 @@
 // consecutive doubles) per instruction.  Products with few output tiles and a
 // long K (V^T Z in the reflector application) are split along K into the
 // problem's scratch buffer and summed by a second kernel.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -43,11 +45,11 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
   const long ld = P.ld;
   const int NB = 64;
   switch (op) {
-    case GOP_POTRF_TRSM:
     case GOP_POTRF_SYRK:
-    case GOP_GRAM_TRSM:
     case GOP_GRAM_SYRK: {
-      const bool gram = (op == GOP_GRAM_TRSM || op == GOP_GRAM_SYRK);
+      // trailing update after the panel at column `step` (the panel itself is
+      // solved by trsm_rows_batched): A22 -= A21 A21^T, lower triangle
+      const bool gram = (op == GOP_GRAM_SYRK);
       double* Mx = gram ? P.inv : P.L;
       const int Nm = gram ? P.n : P.N;
       const long ldm = gram ? (long)P.n : ld;
@@ -56,15 +58,9 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
       const int rest = Nm - k0 - nbk;
       if (nbk <= 0 || rest <= 0) break;  // M = N = 0: nothing to do
       double* a21 = Mx + (k0 + nbk) + (long)k0 * ldm;
-      if (op == GOP_POTRF_TRSM || op == GOP_GRAM_TRSM) {
-        // A21 <- A21 Linv^T (in place: a single column tile of output)
-        g.ta = 0; g.tb = 1; g.M = rest; g.N = nbk; g.K = nbk;
-        g.A = a21; g.lda = ldm; g.B = P.linv; g.ldb = NB; g.C = a21; g.ldc = ldm;
-      } else {
-        g.ta = 0; g.tb = 1; g.M = rest; g.N = rest; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
-        g.A = a21; g.lda = ldm; g.B = a21; g.ldb = ldm;
-        g.C = Mx + (k0 + nbk) + (long)(k0 + nbk) * ldm; g.ldc = ldm; g.c_uplo = 1;
-      }
+      g.ta = 0; g.tb = 1; g.M = rest; g.N = rest; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
+      g.A = a21; g.lda = ldm; g.B = a21; g.ldb = ldm;
+      g.C = Mx + (k0 + nbk) + (long)(k0 + nbk) * ldm; g.ldc = ldm; g.c_uplo = 1;
       break;
     }
     case GOP_FORMW_C:   // W11 <- L11^T L21
@@ -96,14 +92,6 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
       g.ta = 0; g.tb = 1; g.M = P.n; g.N = P.n; g.K = P.N;
       g.A = P.Vt; g.lda = P.n; g.B = P.Vt; g.ldb = P.n; g.C = P.inv; g.ldc = P.n; g.c_uplo = 1;
       break;
-    case GOP_GRAM_DIAG: {  // rows b0.. of Vt <- Linv (rows b0..), in place
-      const int b0 = step;
-      if (b0 >= P.n) break;
-      const int nbk = (P.n - b0 < NB) ? P.n - b0 : NB;
-      g.ta = 0; g.tb = 0; g.M = nbk; g.N = P.N; g.K = nbk;
-      g.A = P.linv; g.lda = NB; g.B = P.Vt + b0; g.ldb = P.n; g.C = P.Vt + b0; g.ldc = P.n;
-      break;
-    }
     case GOP_GRAM_UPD: {  // rows below the block -= L21 (rows of the block)
       const int b0 = step;
       if (b0 >= P.n) break;
@@ -117,7 +105,6 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
     }
     case GOP_APPLYU_S:
     case GOP_APPLYU_W1:
-    case GOP_APPLYU_W2:
     case GOP_APPLYU_Z: {
       const int nrefl = P.N - 2;
       const int j0 = step * NB;
@@ -132,9 +119,6 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
       } else if (op == GOP_APPLYU_W1) {
         g.ta = 1; g.tb = 0; g.M = nbk; g.N = P.N; g.K = m;
         g.A = Vb; g.lda = ld; g.B = Zs; g.ldb = ld; g.C = P.W1; g.ldc = NB;
-      } else if (op == GOP_APPLYU_W2) {
-        g.ta = 0; g.tb = 0; g.M = nbk; g.N = P.N; g.K = nbk;
-        g.A = P.T; g.lda = NB; g.B = P.W1; g.ldb = NB; g.C = P.W2; g.ldc = NB;
       } else {
         g.ta = 0; g.tb = 0; g.M = m; g.N = P.N; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
         g.A = Vb; g.lda = ld; g.B = P.W2; g.ldb = NB; g.C = Zs; g.ldc = ld;
@@ -193,14 +177,42 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
 
 namespace {
 
-template <bool TA, bool TB>
+// Workgroups are dealt to the 8 XCDs round-robin in dispatch order, and each
+// XCD has its own L2.  xcd_remap turns the dispatch index into an index in
+// which every XCD owns one contiguous range, so tiles that share A or B
+// panels run on the same XCD.
+__device__ inline long xcd_remap(long wg, long total) {
+  constexpr long NX = 8;
+  const long q = total / NX, r = total % NX;
+  const long x = wg % NX, local = wg / NX;
+  return (x < r) ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
+}
+
+// Tile (tm, tn) of a full tile grid in bands of GROUP tile rows, column by
+// column inside a band: consecutive tiles share their B panel, and a band's
+// A panels stay in L2 while it is swept.
+__device__ inline void grouped_tile(long t, int tiles_m, int tiles_n, int& tm, int& tn) {
+  constexpr int GROUP = 8;
+  const long per_band = (long)GROUP * tiles_n;
+  const int band = (int)(t / per_band);
+  const int first = band * GROUP;
+  const int rows = min(GROUP, tiles_m - first);
+  const long in_band = t - (long)band * per_band;
+  tm = first + (int)(in_band % rows);
+  tn = (int)(in_band / rows);
+}
+
+template <bool TA, bool TB, int BM, int BN, int BK>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ probs, int op, int step,
                                                        GemmParams single) {
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int FM = WM / 16, FN = WN / 16;
   constexpr int AS = BK * (BM + PAD), BS = BK * (BN + PAD);
-  constexpr int CS = BN * (BM + 1);
-  constexpr int SMEM = (2 * (AS + BS) > CS) ? 2 * (AS + BS) : CS;
+  constexpr int SMEM = 2 * (AS + BS);
+  // the epilogue goes through the same LDS, EC columns at a time
+  constexpr int EC0 = SMEM / (BM + 1);
+  constexpr int EC = EC0 >= BN ? BN : (EC0 >= 64 ? 64 : 32);
+  static_assert(EC * (BM + 1) <= SMEM, "epilogue chunk does not fit");
   __shared__ double smem[SMEM];
 
   int stp = step;
@@ -214,9 +226,17 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ 
   const GemmParams p = probs ? gemm_params(op, probs[blockIdx.z], stp) : single;
   const BSE_GLOBAL double* __restrict__ Ag = gbl(p.A);
   const BSE_GLOBAL double* __restrict__ Bg = gbl(p.B);
-  long tile = blockIdx.x;
+  // tiles of this configuration (the host sized the grid for it)
+  const int tiles_m = (p.M + BM - 1) / BM, tiles_n = (p.N + BN - 1) / BN;
+  const long ntiles = (p.M <= 0 || p.N <= 0) ? 0
+                      : (p.c_uplo ? (long)tiles_m * (tiles_m + 1) / 2 : (long)tiles_m * tiles_n);
+  // With a triangular operand the tiles' K ranges differ: a contiguous range
+  // per XCD would give one XCD all the long tiles, so those products keep the
+  // dispatch order (long and short tiles interleaved over the XCDs).
+  const bool tri = p.a_tri || p.b_tri;
+  long tile = tri ? (long)blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
   int slice = 0;
-  if (tile >= p.ntiles * p.splits) return;  // uniform: beyond this problem's tiles
+  if (tile >= ntiles * p.splits) return;  // uniform: beyond this problem's tiles
   if (p.splits > 1) {
     slice = (int)(tile % p.splits);
     tile /= p.splits;
@@ -224,9 +244,11 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ 
   int tm, tn;
   if (p.c_uplo) {
     tri_index(tile, tm, tn);
+  } else if (tri) {
+    tm = (int)(tile % tiles_m);
+    tn = (int)(tile / tiles_m);
   } else {
-    tm = (int)(tile % p.tiles_m);
-    tn = (int)(tile / p.tiles_m);
+    grouped_tile(tile, tiles_m, tiles_n, tm, tn);
   }
   const int i0 = tm * BM, j0 = tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -368,40 +390,44 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ 
     buf ^= 1;
   }
 
-  // Epilogue through LDS.  In a 16 x 16 f64 block the entry (i, j) lives in
-  // lane 16 (i mod 4) + j, accumulator element i / 4.
-  double* Cs = smem;  // Cs[c * (BM + 1) + r]
-  __syncthreads();
-#pragma unroll
-  for (int a = 0; a < FM; ++a)
-#pragma unroll
-    for (int b = 0; b < FN; ++b) {
-      const int cl = wc * WN + b * 16 + (lane & 15);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int rl = wr * WM + a * 16 + (lane >> 4) + 4 * v;
-        Cs[cl * (BM + 1) + rl] = acc[a][b][v];
-      }
-    }
-  __syncthreads();
+  // Epilogue through LDS, EC columns at a time.  In a 16 x 16 f64 block the
+  // entry (i, j) lives in lane 16 (i mod 4) + j, accumulator element i / 4.
+  double* Cs = smem;  // Cs[(c - c0) * (BM + 1) + r]
   const bool split = p.splits > 1;
-  for (int idx = tid; idx < BN * BM; idx += 256) {
-    const int rl = idx % BM, cl = idx / BM;
-    const int row = i0 + rl, col = j0 + cl;
-    if (row >= p.M || col >= p.N) continue;
-    if (p.c_uplo == 1 && row < col) continue;
-    if (p.c_uplo == 2 && row <= col) continue;
-    const double val = Cs[cl * (BM + 1) + rl];
-    if (split) {
-      gbl(p.part)[(long)slice * p.M * p.N + (long)row + (long)col * p.M] = val;
-    } else if (p.Cf) {
-      BSE_GLOBAL float* c = gbl(p.Cf + (long)row + (long)col * p.ldc);
-      const double out = p.alpha * val;
-      *c = (float)((p.beta == 0.0) ? out : out + p.beta * (double)(*c));
-    } else {
-      BSE_GLOBAL double* c = gbl(p.C + (long)row + (long)col * p.ldc);
-      const double out = p.alpha * val;
-      *c = (p.beta == 0.0) ? out : out + p.beta * (*c);
+#pragma unroll
+  for (int c0 = 0; c0 < BN; c0 += EC) {
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) {
+        const int cl = wc * WN + b * 16 + (lane & 15);
+        if (cl < c0 || cl >= c0 + EC) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int rl = wr * WM + a * 16 + (lane >> 4) + 4 * v;
+          Cs[(cl - c0) * (BM + 1) + rl] = acc[a][b][v];
+        }
+      }
+    __syncthreads();
+    for (int idx = tid; idx < EC * BM; idx += 256) {
+      const int rl = idx % BM, cl = c0 + idx / BM;
+      const int row = i0 + rl, col = j0 + cl;
+      if (row >= p.M || col >= p.N) continue;
+      if (p.c_uplo == 1 && row < col) continue;
+      if (p.c_uplo == 2 && row <= col) continue;
+      const double val = Cs[(cl - c0) * (BM + 1) + rl];
+      if (split) {
+        gbl(p.part)[(long)slice * p.M * p.N + (long)row + (long)col * p.M] = val;
+      } else if (p.Cf) {
+        BSE_GLOBAL float* c = gbl(p.Cf + (long)row + (long)col * p.ldc);
+        const double out = p.alpha * val;
+        *c = (float)((p.beta == 0.0) ? out : out + p.beta * (double)(*c));
+      } else {
+        BSE_GLOBAL double* c = gbl(p.C + (long)row + (long)col * p.ldc);
+        const double out = p.alpha * val;
+        *c = (p.beta == 0.0) ? out : out + p.beta * (*c);
+      }
     }
   }
 }
@@ -439,39 +465,68 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const Prob* __restrict__ 
   }
 }
 
-void launch(hipStream_t s, bool ta, bool tb, dim3 grid, const Prob* probs, int op, int step,
+// Tile configurations: 0 = 64 x 64 (BK 16), 1 = 128 x 128 (BK 16),
+// 2 = 128 x 64 (BK 16, full outputs only: the triangular tile enumeration
+// needs square tiles), 3 = 64 x 64 (BK 32).
+constexpr int NCFG = 4;
+constexpr int CFG_BM[NCFG] = {64, 128, 128, 64};
+constexpr int CFG_BN[NCFG] = {64, 128, 64, 64};
+
+template <bool TA, bool TB>
+void launch_t(hipStream_t s, int cfg, dim3 grid, const Prob* probs, int op, int step, const GemmParams& single) {
+  switch (cfg) {
+    case 1: gemm_f64_kernel<TA, TB, 128, 128, 16><<<grid, 256, 0, s>>>(probs, op, step, single); break;
+    case 2: gemm_f64_kernel<TA, TB, 128, 64, 16><<<grid, 256, 0, s>>>(probs, op, step, single); break;
+    case 3: gemm_f64_kernel<TA, TB, 64, 64, 32><<<grid, 256, 0, s>>>(probs, op, step, single); break;
+    default: gemm_f64_kernel<TA, TB, 64, 64, 16><<<grid, 256, 0, s>>>(probs, op, step, single); break;
+  }
+}
+
+void launch(hipStream_t s, bool ta, bool tb, int cfg, dim3 grid, const Prob* probs, int op, int step,
             const GemmParams& single) {
-  if (!ta && !tb) gemm_f64_kernel<false, false><<<grid, 256, 0, s>>>(probs, op, step, single);
-  else if (!ta && tb) gemm_f64_kernel<false, true><<<grid, 256, 0, s>>>(probs, op, step, single);
-  else if (ta && !tb) gemm_f64_kernel<true, false><<<grid, 256, 0, s>>>(probs, op, step, single);
-  else gemm_f64_kernel<true, true><<<grid, 256, 0, s>>>(probs, op, step, single);
+  if (!ta && !tb) launch_t<false, false>(s, cfg, grid, probs, op, step, single);
+  else if (!ta && tb) launch_t<false, true>(s, cfg, grid, probs, op, step, single);
+  else if (ta && !tb) launch_t<true, false>(s, cfg, grid, probs, op, step, single);
+  else launch_t<true, true>(s, cfg, grid, probs, op, step, single);
+}
+
+// workgroups of a product with configuration cfg
+long cfg_workgroups(const GemmParams& g, int cfg) {
+  if (g.M <= 0 || g.N <= 0) return 0;
+  const long tm = (g.M + CFG_BM[cfg] - 1) / CFG_BM[cfg], tn = (g.N + CFG_BN[cfg] - 1) / CFG_BN[cfg];
+  return (g.c_uplo ? tm * (tm + 1) / 2 : tm * tn) * g.splits;
 }
 
 }  // namespace
 
 int gemm_batched(hipStream_t s, const Batch& b, int nact, int op, int step) {
   if (nact <= 0) return 0;
-  long maxwg = 0, maxm = 0, maxn = 0;
-  bool any_split = false;
+  long maxm = 0, maxn = 0, maxk = 0;
+  bool any_split = false, any = false;
   int ta = -1, tb = -1;
   for (int i = 0; i < nact; ++i) {
     const GemmParams g = gemm_params(op, b.host[i], step);
-    if (g.ntiles <= 0) continue;
+    if (g.M <= 0 || g.N <= 0) continue;
+    any = true;
     if (ta < 0) {
       ta = g.ta;
       tb = g.tb;
     }
-    const long wg = g.ntiles * g.splits;
-    if (wg > maxwg) maxwg = wg;
-    if (g.splits > 1) {
-      any_split = true;
-      if (g.M > maxm) maxm = g.M;
-      if (g.N > maxn) maxn = g.N;
-    }
+    if (g.splits > 1) any_split = true;
+    maxm = std::max(maxm, (long)g.M);
+    maxn = std::max(maxn, (long)g.N);
+    maxk = std::max(maxk, (long)g.K);
   }
+  if (!any) return 0;
+  // 64 x 64 tiles throughout: on this device the 128-wide tiles (one or
+  // two waves per SIMD) measured slower for every product of the chain
+  const int cfg = 0;
+  (void)maxk;
+  long maxwg = 0;
+  for (int i = 0; i < nact; ++i) maxwg = std::max(maxwg, cfg_workgroups(gemm_params(op, b.host[i], step), cfg));
   if (maxwg == 0) return 0;
   GemmParams dummy{};
-  launch(s, ta != 0, tb != 0, dim3((unsigned)maxwg, 1, (unsigned)nact), b.dev, op, step, dummy);
+  launch(s, ta != 0, tb != 0, cfg, dim3((unsigned)maxwg, 1, (unsigned)nact), b.dev, op, step, dummy);
   BSE_LAUNCHED();
   if (any_split) {
     k_splitk_reduce<<<dim3((unsigned)((maxm + 63) / 64), (unsigned)((maxn + 63) / 64), (unsigned)nact), 256, 0, s>>>(

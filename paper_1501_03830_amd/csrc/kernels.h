@@ -49,20 +49,16 @@ struct GemmParams {
 // The products of the chain, as functions of (problem, step).
 enum GemmOp {
   GOP_NONE = 0,
-  GOP_POTRF_TRSM,  // Cholesky of M: panel solve at column `step`
-  GOP_POTRF_SYRK,  // Cholesky of M: trailing update
-  GOP_GRAM_TRSM,   // Cholesky of the Gram matrix: panel solve
+  GOP_POTRF_SYRK,  // Cholesky of M: trailing update after the panel at `step`
   GOP_GRAM_SYRK,   // Cholesky of the Gram matrix: trailing update
   GOP_FORMW_C,     // L11^T L21
   GOP_FORMW_21,    // -L22^T L11
   GOP_SKTRD_R2K,   // skew rank-2k update after the panel starting at column `step`
   GOP_GRAM,        // Gram matrix of the inverse-iteration vectors
-  GOP_GRAM_DIAG,   // forward substitution, diagonal block at row `step`
-  GOP_GRAM_UPD,    // forward substitution, update below it
+  GOP_GRAM_UPD,    // forward substitution: rows below the block at `step`
   GOP_APPLYU_S,    // V^T V of reflector block `step`
   GOP_APPLYU_W1,   // V^T Z
-  GOP_APPLYU_W2,   // T (V^T Z)
-  GOP_APPLYU_Z,    // Z -= V T V^T Z
+  GOP_APPLYU_Z,    // Z -= V (T V^T Z)
   GOP_APPLY_L,     // G = L Z
   GOP_REF_P,       // refinement: P = W Ub (basis Ub of sweep `step`)
   GOP_REF_S,       // refinement: S = Ub^T P (lower)
@@ -81,15 +77,21 @@ int build_M_batched(hipStream_t s, const Batch& b);
 // leading minor goes to P.info[sel] (0 = success); with reset_info false a
 // failure recorded earlier is kept.
 int potrf_batched(hipStream_t s, const Batch& b, int sel, bool reset_info);
-// Inverse of the lower-triangular diagonal block at (b0, b0) of matrix sel
-// into P.linv (64 x 64, ld 64), for the first nact problems.
-int trtri_batched(hipStream_t s, const Batch& b, int nact, int sel, int b0);
 // W = L^T J L into P.W: lower triangle and the W22 = 0 block; `full` also
 // fills the strict upper triangle with -W^T.
 int form_W_batched(hipStream_t s, const Batch& b, bool full);
 // plain copies for the stage entry points
 int copy_matrix(hipStream_t s, int m, int n, const double* src, long lds, double* dst, long ldd);
 int zero_upper(hipStream_t s, int N, double* A, long lda);
+
+// ---------------------------------------------------------------- trsm.hip
+// Cholesky panel of matrix sel (0: M, 1: Gram): rows below the diagonal block
+// at k0 <- themselves times L_kk^{-T} (first nact problems)
+int trsm_rows_batched(hipStream_t s, const Batch& b, int nact, int sel, int k0);
+// rows b0 .. b0+63 of V_+^T <- L_bb^{-1} times themselves (Gram factor)
+int trsm_cols_batched(hipStream_t s, const Batch& b, int nact, int b0);
+// P.W2 = T P.W1 for reflector block q (T from P.S = V^T V and tau)
+int wy_solve_batched(hipStream_t s, const Batch& b, int nact, int q);
 
 // ---------------------------------------------------------------- sktrd.hip
 size_t sktrd_work_bytes(long N, long ld);

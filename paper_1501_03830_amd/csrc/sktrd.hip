@@ -368,6 +368,19 @@ __global__ __launch_bounds__(256) void sk_update(const Prob* __restrict__ probs,
   }
   const long r = (long)(R0 + b) * TS + t;
   const bool inrange = r >= s && r < N;
+  // this row's panel entries (v_l, p_l for l = part, part + 4, ...), v_i, and
+  // W[r, s]: loaded once, before anything waits, and used by both
+  // corrections below
+  double yv[NBMAX / 4], yp[NBMAX / 4];
+#pragma unroll
+  for (int q = 0; q < NBMAX / 4; ++q) {
+    const int l = part + 4 * q;
+    const bool use = inrange && l < i;
+    yv[q] = use ? Y1[r + (long)(2 * l) * ldy] : 0.0;
+    yp[q] = use ? Y1[r + (long)(2 * l + 1) * ldy] : 0.0;
+  }
+  const double vi = inrange ? Y1[r + (long)(2 * i) * ldy] : 0.0;
+  const double wrs = (r >= s + 1 && r < N) ? (double)W[r + (long)s * ld] : 0.0;
   {
     // partial sums of this row block: b+1 row parts (one per strip c <= b)
     // and nch column parts (one per chunk of strip b); loads are issued in
@@ -401,8 +414,7 @@ __global__ __launch_bounds__(256) void sk_update(const Prob* __restrict__ probs,
 #pragma unroll
       for (int q = 0; q < NBMAX / 4; ++q) {
         const int l = part + 4 * q;
-        if (l < i)
-          corr += Y1[r + (long)(2 * l) * ldy] * cs[2 * l + 1] - Y1[r + (long)(2 * l + 1) * ldy] * cs[2 * l];
+        if (l < i) corr += yv[q] * cs[2 * l + 1] - yp[q] * cs[2 * l];
       }
     }
     red2[part][t] = corr;
@@ -416,7 +428,7 @@ __global__ __launch_bounds__(256) void sk_update(const Prob* __restrict__ probs,
       p = tau * (y + corr);
       Y1[r + (long)(2 * i + 1) * ldy] = p;
       Y2[r + (long)(2 * i) * ldy] = p;
-      if (r > s) W[r + (long)j * ld] = Y1[r + (long)(2 * i) * ldy];  // store v_i in place
+      if (r > s) W[r + (long)j * ld] = vi;  // store v_i in place
     }
     pr[t] = p;
   }
@@ -444,8 +456,7 @@ __global__ __launch_bounds__(256) void sk_update(const Prob* __restrict__ probs,
 #pragma unroll
       for (int q = 0; q < NBMAX / 4; ++q) {
         const int l = part + 4 * q;
-        if (l < i)
-          upd += Y1[r + (long)(2 * l) * ldy] * ys_row[2 * l + 1] - Y1[r + (long)(2 * l + 1) * ldy] * ys_row[2 * l];
+        if (l < i) upd += yv[q] * ys_row[2 * l + 1] - yp[q] * ys_row[2 * l];
       }
     }
     red2[part][t] = upd;
@@ -453,8 +464,8 @@ __global__ __launch_bounds__(256) void sk_update(const Prob* __restrict__ probs,
   __syncthreads();
   double nrm = 0.0;
   if (part == 0 && r >= s + 1 && r < N) {
-    double upd = W[r + (long)s * ld] + red2[0][t] + red2[1][t] + red2[2][t] + red2[3][t];
-    upd += Y1[r + (long)(2 * i) * ldy] * sval_s - pr[t];
+    double upd = wrs + red2[0][t] + red2[1][t] + red2[2][t] + red2[3][t];
+    upd += vi * sval_s - pr[t];
     // the column as stored (rounded to T) is what the next reflector sees
     const double upds = (double)(WT)upd;
     W[r + (long)s * ld] = (WT)upd;

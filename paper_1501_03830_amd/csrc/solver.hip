@@ -70,7 +70,7 @@ struct Plan {
   long N = 0, n = 0, ld = 0;
   int prec = BSE_PREC_FP64;
   size_t off_L = 0, off_W = 0, off_Z = 0, off_Vt = 0, off_inv = 0, off_small = 0, off_sk = 0,
-         off_bt = 0, off_linv = 0, off_gscr = 0;
+         off_bt = 0, off_gscr = 0;
   size_t gscr_bytes = 0;
   // mixed-precision path only
   size_t off_W32 = 0, off_R = 0, off_refmax = 0, off_perm = 0;
@@ -101,7 +101,6 @@ static Plan make_plan(long N, int prec) {
   p.off_small = take((size_t)(3 * p.ld + p.n + 16) * sizeof(double) + (size_t)p.n * sizeof(int));
   p.off_sk = take(sktrd_work_bytes(N, p.ld));
   p.off_bt = take(backtr_work_bytes(N, p.ld));
-  p.off_linv = take(64 * 64 * sizeof(double));
   // split-K partial products: only products of large problems are split
   p.gscr_bytes = (N > 2048) ? (size_t)16 * 64 * p.ld * sizeof(double) : 0;
   if (p.gscr_bytes) p.off_gscr = take(p.gscr_bytes);
@@ -142,7 +141,6 @@ static void bind_problem(const Plan& p, char* base, Prob* P) {
   P->shift = sm + 3 * p.ld;
   P->scal = sm + 3 * p.ld + p.n;
   P->cid = reinterpret_cast<int*>(sm + 3 * p.ld + p.n + 16);
-  P->linv = reinterpret_cast<double*>(base + p.off_linv);
   P->gscr = p.gscr_bytes ? reinterpret_cast<double*>(base + p.off_gscr) : nullptr;
   P->gscr_bytes = p.gscr_bytes;
   sktrd_bind_work(base + p.off_sk, p.N, p.ld, P);

@@ -67,12 +67,27 @@ __global__ __launch_bounds__(1024) void k_tridiag_prep(const Prob* __restrict__ 
   }
 }
 
+// The loads of alpha^2 are issued eight steps at a time, ahead of the
+// dependent divisions; the arithmetic and its order are those of the plain
+// recurrence.
 template <class Ptr>
 __device__ inline int sturm_count(Ptr e2, int N, double x, double pivmin) {
   double q = -x;
   if (fabs(q) < pivmin) q = -pivmin;
   int c = q < 0.0;
-  for (int k = 1; k < N; ++k) {
+  int k = 1;
+  for (; k + 8 <= N; k += 8) {
+    double e[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) e[u] = e2[k - 1 + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      q = -x - e[u] / q;
+      if (fabs(q) < pivmin) q = -pivmin;
+      c += q < 0.0;
+    }
+  }
+  for (; k < N; ++k) {
     q = -x - e2[k - 1] / q;
     if (fabs(q) < pivmin) q = -pivmin;
     c += q < 0.0;
@@ -194,10 +209,38 @@ __global__ __launch_bounds__(64) void k_invit(const Prob* __restrict__ probs) {
   for (int k = 0; k < N; ++k)
     Vt[(long)k * ldn + j] = hash_uniform(((unsigned long long)j << 32) ^ (unsigned long long)k ^ 0x5bd1e995ull);
 
+  // Both solves run in blocks of eight steps whose loads (the factors and
+  // the entries of the iterate not yet overwritten) are issued before the
+  // dependent arithmetic; the arithmetic is that of the step-by-step loops.
+  constexpr int UB = 8;
   for (int it = 0; it < 3; ++it) {
     // forward: apply the row interchanges and multipliers
     double cur = Vt[j];
-    for (int k = 0; k < N - 1; ++k) {
+    int k = 0;
+    for (; k + UB <= N - 1; k += UB) {
+      double nx[UB], lv[UB];
+      unsigned char sv[UB];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const long o = (long)(k + u) * ldn + j;
+        nx[u] = Vt[o + ldn];
+        lv[u] = fl[o];
+        sv[u] = fs[o];
+      }
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        double outk;
+        if (sv[u]) {
+          outk = nx[u];
+          cur = cur - lv[u] * nx[u];
+        } else {
+          outk = cur;
+          cur = nx[u] - lv[u] * cur;
+        }
+        Vt[(long)(k + u) * ldn + j] = outk;
+      }
+    }
+    for (; k < N - 1; ++k) {
       const long o = (long)k * ldn + j;
       const double nxt = Vt[o + ldn];
       const double l = fl[o];
@@ -214,7 +257,31 @@ __global__ __launch_bounds__(64) void k_invit(const Prob* __restrict__ probs) {
     Vt[(long)(N - 1) * ldn + j] = cur;
     // back substitution with the upper factor
     double x2 = 0.0, x1 = 0.0, ss = 0.0;
-    for (int k = N - 1; k >= 0; --k) {
+    k = N - 1;
+    for (; k - UB + 1 >= 0; k -= UB) {
+      double vv[UB], u1[UB], u2[UB], dd[UB];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const long o = (long)(k - u) * ldn + j;
+        vv[u] = Vt[o];
+        u1[u] = fu[o];
+        u2[u] = fu2[o];
+        dd[u] = fd[o];
+      }
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const int kk = k - u;
+        double v = vv[u];
+        if (kk <= N - 2) v -= u1[u] * x1;
+        if (kk <= N - 3) v -= u2[u] * x2;
+        const double x = v / dd[u];
+        Vt[(long)kk * ldn + j] = x;
+        ss += x * x;
+        x2 = x1;
+        x1 = x;
+      }
+    }
+    for (; k >= 0; --k) {
       const long o = (long)k * ldn + j;
       double v = Vt[o];
       if (k <= N - 2) v -= fu[o] * x1;
@@ -333,13 +400,12 @@ int reorth_batched(hipStream_t s, const Batch& b) {
     k_mask_gram<<<g2, 256, 0, s>>>(b.dev);
     BSE_LAUNCHED();
     BSE_TRY(potrf_batched(s, b, 1, pass == 0));
-    // Vt <- L^{-1} Vt  (blocked forward substitution; the diagonal block is
-    // applied through its inverse, in place: one row tile of output)
+    // Vt <- L^{-1} Vt  (blocked forward substitution: a direct solve with the
+    // diagonal block, then the update of the rows below)
     for (int b0 = 0; b0 < n0; b0 += 64) {
       int nact = 0;
       while (nact < b.count && b.host[nact].n > b0) ++nact;
-      BSE_TRY(trtri_batched(s, b, nact, 1, b0));
-      BSE_TRY(gemm_batched(s, b, nact, GOP_GRAM_DIAG, b0));
+      BSE_TRY(trsm_cols_batched(s, b, nact, b0));
       BSE_TRY(gemm_batched(s, b, nact, GOP_GRAM_UPD, b0));
     }
   }

@@ -1,0 +1,186 @@
+// Solves with one 64 x 64 triangular block, one thread per right-hand side.
+//
+// Three places of the chain apply the inverse of a small triangular block to
+// many vectors:
+//   * the Cholesky panel (Algorithm 1 step 2): A21 <- A21 L_kk^{-T}, i.e.
+//     L_kk x = a for every row a of A21;
+//   * the forward substitution of the cluster Gram-Schmidt (Algorithm 3
+//     step 2): L_bb X = B for the 64 rows of V_+^T at block b;
+//   * the compact-WY application of the reflectors (Algorithm 3 step 3):
+//     W2 = T W1 with I - V T V^T = H_j0 ... H_j0+63.  For reflectors
+//     H = I - tau v v^T the factor built by LAPACK's larft recurrence is the
+//     inverse of diag(1/tau) + strict_upper(V^T V), so W2 solves
+//     (diag(1/tau) + strict_upper(V^T V)) W2 = W1 and T is never formed.
+// Each thread keeps its vector in registers and runs the substitution in
+// axpy form (once x_l is final it is removed from the remaining rows), so
+// the updates of one step are independent instructions.  The triangular
+// block is the same for every lane: where it is read-only in the launch it
+// is read straight from memory through the scalar cache (FMA operands in
+// scalar registers); the compact-WY factor is assembled in LDS.
+#include "common.h"
+#include "kernels.h"
+
+namespace bse {
+
+namespace {
+
+constexpr int NB = 64;
+
+// x <- L^{-1} x for the lower-triangular L at Lp (column-major, ld), of
+// order 64 (FULL) or nbk < 64 (the remaining unknowns are untouched)
+template <bool FULL>
+__device__ inline void lower_solve64(const BSE_CONST double* Lp, long ld, int nbk, double (&x)[NB]) {
+#pragma unroll
+  for (int l = 0; l < NB; ++l) {
+    if (FULL || l < nbk) {
+      const BSE_CONST double* col = Lp + (long)l * ld;
+      x[l] = x[l] / col[l];
+#pragma unroll
+      for (int r = l + 1; r < NB; ++r)
+        if (FULL || r < nbk) x[r] -= col[r] * x[l];
+    }
+  }
+}
+
+// x <- U^{-1} x, U upper, Us[col][row]
+__device__ inline void upper_solve64(const double (*Us)[NB + 1], double (&x)[NB]) {
+#pragma unroll
+  for (int l = NB - 1; l >= 0; --l) {
+    x[l] = x[l] / Us[l][l];
+#pragma unroll
+    for (int r = 0; r < l; ++r) x[r] -= Us[l][r] * x[l];
+  }
+}
+
+// Cholesky panel: rows k0+nbk .. Nm-1 of the panel columns k0 .. k0+nbk-1
+// of matrix sel (0: M, 1: the Gram matrix) <- themselves times L_kk^{-T}.
+template <bool FULL>
+__global__ __launch_bounds__(256) void k_trsm_rows(const Prob* __restrict__ probs, int sel, int k0) {
+  const Prob& P = probs[blockIdx.z];
+  double* Mp;
+  long ld;
+  int Nm;
+  if (sel == 0) {
+    Mp = P.L;
+    ld = P.ld;
+    Nm = P.N;
+  } else {
+    Mp = P.inv;
+    ld = P.n;
+    Nm = P.n;
+  }
+  if (k0 >= Nm || gbl(P.info)[sel] != 0) return;   // uniform
+  const int nbk = min(NB, Nm - k0);
+  if (FULL != (nbk == NB)) return;                  // uniform: the other variant
+  const int first = k0 + nbk;
+  const long r = first + (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= Nm) return;
+  // the diagonal block is not written by this launch (only the rows below)
+  const BSE_CONST double* Lkk = ro(Mp + (long)k0 + (long)k0 * ld);
+  BSE_GLOBAL double* __restrict__ M = gbl(Mp);
+  double x[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) x[c] = (FULL || c < nbk) ? M[r + (long)(k0 + c) * ld] : 0.0;
+  lower_solve64<FULL>(Lkk, ld, nbk, x);
+#pragma unroll
+  for (int c = 0; c < NB; ++c)
+    if (FULL || c < nbk) M[r + (long)(k0 + c) * ld] = x[c];
+}
+
+// Gram-Schmidt forward substitution, diagonal block b0: rows b0 .. b0+63 of
+// V_+^T (n x N, ld n) <- L_bb^{-1} times themselves, one column per thread.
+template <bool FULL>
+__global__ __launch_bounds__(256) void k_trsm_cols(const Prob* __restrict__ probs, int b0) {
+  const Prob& P = probs[blockIdx.z];
+  const int n = P.n, N = P.N;
+  if (b0 >= n || gbl(P.info)[1] != 0) return;   // uniform
+  const int nbk = min(NB, n - b0);
+  if (FULL != (nbk == NB)) return;              // uniform: the other variant
+  const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const BSE_CONST double* Lbb = ro(P.inv + (long)b0 + (long)b0 * n);   // Gram factor, read-only here
+  BSE_GLOBAL double* __restrict__ v = gbl(P.Vt) + b0 + j * n;
+  double x[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) x[i] = (FULL || i < nbk) ? v[i] : 0.0;
+  lower_solve64<FULL>(Lbb, n, nbk, x);
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+    if (FULL || i < nbk) v[i] = x[i];
+}
+
+// Compact-WY factor of reflector block q: W2 = T W1, solved as
+// (diag(1/tau) + strict_upper(S)) W2 = W1 with S = V^T V.  A reflector with
+// tau = 0 is the identity: its row of W2 is zero.
+__global__ __launch_bounds__(256) void k_wy_solve(const Prob* __restrict__ probs, int q) {
+  __shared__ double Us[NB][NB + 1];
+  __shared__ int zero[NB];
+  const Prob& P = probs[blockIdx.z];
+  const int N = P.N;
+  const int nrefl = N - 2;
+  const int j0 = q * NB;
+  if (j0 >= nrefl) return;   // uniform
+  if ((long)blockIdx.x * blockDim.x >= N) return;   // uniform
+  const int nbk = min(NB, nrefl - j0);
+  const BSE_CONST double* __restrict__ S = ro(P.S);
+  const BSE_CONST double* __restrict__ tau = ro(P.tau);
+  if (threadIdx.x < NB) {
+    const int i = threadIdx.x;
+    zero[i] = (i >= nbk) || (tau[j0 + i] == 0.0);
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
+    const int r = idx & 63, c = idx >> 6;
+    double v;
+    if (r == c) v = zero[r] ? 1.0 : 1.0 / tau[j0 + r];
+    else if (r < c && !zero[r] && !zero[c]) v = S[r + (long)c * NB];
+    else v = 0.0;
+    Us[c][r] = v;
+  }
+  __syncthreads();
+  const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const BSE_GLOBAL double* __restrict__ w1 = gbl(P.W1) + j * NB;
+  BSE_GLOBAL double* __restrict__ w2 = gbl(P.W2) + j * NB;
+  double x[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) x[i] = zero[i] ? 0.0 : w1[i];
+  upper_solve64(Us, x);
+#pragma unroll
+  for (int i = 0; i < NB; ++i) w2[i] = x[i];
+}
+
+}  // namespace
+
+int trsm_rows_batched(hipStream_t s, const Batch& b, int nact, int sel, int k0) {
+  if (nact <= 0) return 0;
+  const long rows = (long)(sel == 0 ? b.host[0].N : b.host[0].n) - k0 - NB;
+  if (rows <= 0) return 0;
+  const dim3 g((unsigned)((rows + 255) / 256), 1, (unsigned)nact);
+  k_trsm_rows<true><<<g, 256, 0, s>>>(b.dev, sel, k0);
+  BSE_LAUNCHED();
+  k_trsm_rows<false><<<g, 256, 0, s>>>(b.dev, sel, k0);
+  BSE_LAUNCHED();
+  return 0;
+}
+
+int trsm_cols_batched(hipStream_t s, const Batch& b, int nact, int b0) {
+  if (nact <= 0) return 0;
+  const long N0 = b.maxN();
+  const dim3 g((unsigned)((N0 + 255) / 256), 1, (unsigned)nact);
+  k_trsm_cols<true><<<g, 256, 0, s>>>(b.dev, b0);
+  BSE_LAUNCHED();
+  k_trsm_cols<false><<<g, 256, 0, s>>>(b.dev, b0);
+  BSE_LAUNCHED();
+  return 0;
+}
+
+int wy_solve_batched(hipStream_t s, const Batch& b, int nact, int q) {
+  if (nact <= 0) return 0;
+  const long N0 = b.maxN();
+  k_wy_solve<<<dim3((unsigned)((N0 + 255) / 256), 1, (unsigned)nact), 256, 0, s>>>(b.dev, q);
+  BSE_LAUNCHED();
+  return 0;
+}
+
+}  // namespace bse
