@@ -84,6 +84,7 @@ __global__ __launch_bounds__(256) void k_potf2(const Prob* __restrict__ probs, i
   chol_matrix(P, sel, M, ld, N);
   BSE_GLOBAL int* info = gbl(P.info + sel);
   if (k0 >= N || *info != 0) return;
+  if (sel == 1 && *gbl(P.reorth) == 0) return;   // no cluster Gram-Schmidt
   const int nbk = min(TB, N - k0);
   const int tid = threadIdx.x;
   for (int idx = tid; idx < TB * TB; idx += 256) {

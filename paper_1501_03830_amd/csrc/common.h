@@ -79,6 +79,7 @@ struct Prob {
   double* refmax;       // refinement: per-tile partial maxima (2 per tile)
   double* refout;       // refinement: [largest correction, clamped pairs] (header)
   int* refstate;        // refinement: sweeps done once converged, else 0 (header)
+  int* reorth;          // 1: run the cluster Gram-Schmidt (header)
   int* perm;            // n: output column j takes eigenpair perm[j]
 };
 

@@ -38,6 +38,7 @@ struct Setup {
   Prob* dprobs = nullptr;   // device descriptors (count)
   int* dinfo = nullptr;     // device info words, 2 per problem slot
   int* dstate = nullptr;    // device refinement state words, 1 per slot
+  int* dreorth = nullptr;   // device Gram-Schmidt flags, 1 per slot
   double* dref = nullptr;   // device refinement maxima, 2 per slot
   size_t total = 0;         // workspace bytes of the batch (for reports)
 };

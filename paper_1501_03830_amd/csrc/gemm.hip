@@ -223,6 +223,8 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ 
     if (step >= 0 && st != 0 && st <= step) return;
     if (step < 0) stp = st;
   }
+  if (probs && (op == GOP_GRAM || op == GOP_GRAM_SYRK || op == GOP_GRAM_UPD) && *gbl(probs[blockIdx.z].reorth) == 0)
+    return;   // no cluster Gram-Schmidt for this problem
   const GemmParams p = probs ? gemm_params(op, probs[blockIdx.z], stp) : single;
   const BSE_GLOBAL double* __restrict__ Ag = gbl(p.A);
   const BSE_GLOBAL double* __restrict__ Bg = gbl(p.B);
@@ -441,6 +443,8 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const Prob* __restrict__ 
     if (step >= 0 && st != 0 && st <= step) return;
     if (step < 0) stp = st;
   }
+  if (probs && (op == GOP_GRAM || op == GOP_GRAM_SYRK || op == GOP_GRAM_UPD) && *gbl(probs[blockIdx.z].reorth) == 0)
+    return;   // no cluster Gram-Schmidt for this problem
   const GemmParams p = probs ? gemm_params(op, probs[blockIdx.z], stp) : single;
   if (p.splits <= 1) return;
   const long r = (long)blockIdx.x * 64 + (threadIdx.x & 63);

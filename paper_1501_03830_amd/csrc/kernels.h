@@ -112,8 +112,13 @@ int sktrd_batched(hipStream_t s, const Batch& b, KernelTimer* timer);
 int bisect_batched(hipStream_t s, const Batch& b);
 // eigenvectors by inverse iteration into P.Vt (n x N, ld n)
 int invit_batched(hipStream_t s, const Batch& b);
-// Gram-Schmidt inside clusters; failures go to P.info[1]
-int reorth_batched(hipStream_t s, const Batch& b);
+// Gram-Schmidt inside clusters; failures go to P.info[1].  The FP64 path
+// groups eigenvalues closer than 1e-3 ||T_s||_1 and always runs it.  The
+// mixed path, whose refinement orthogonalises the basis anyway, only needs it
+// for near-degenerate clusters (closer than 1e-10 ||T_s||_1): a problem
+// without one skips it.  dflags (device, per slot, P.reorth points into it)
+// and hflags (pinned host) carry that decision.
+int reorth_batched(hipStream_t s, const Batch& b, const int* dflags, int* hflags, int nslots);
 int transpose_to(hipStream_t s, int rows, int cols, const double* src, long lds, double* dst, long ldd);
 
 // ---------------------------------------------------------------- backtr.hip

@@ -15,9 +15,14 @@
 // the 2 x 2 diagonal blocks (the phase of z_k is free) and, for k != l,
 // solves the first-order Sylvester equation
 //     sigma_k E_kl - E_kl sigma_l = -S_kl - (R_kl sigma_l + sigma_k R_kl)/2,
-// sigma_k = lambda_k [0 1; -1 0], which has the closed form used below.  A
-// block whose solution exceeds GCAP (nearly equal eigenvalues) is left to
-// the orthogonalisation part alone, as in the original method's treatment of
+// sigma_k = lambda_k [0 1; -1 0], which has the closed form used below.  For
+// lambda_k = lambda_l (a degenerate eigenvalue) the equation is singular
+// only along the E that commute with [0 1; -1 0] (rotations inside the
+// eigenspace, which are free); the anti-commuting part, which pairs the real
+// and imaginary parts, is still determined and is applied (minimum-norm
+// solution) for pairs closer than DEGEN relative.  Any other block whose
+// solution exceeds GCAP (close but distinct eigenvalues) is left to the
+// orthogonalisation part alone, as in the original method's treatment of
 // clusters.  The error of Ub falls quadratically; a problem stops after the
 // sweep whose largest correction is below STOP_TOL with no clamped block,
 // then its eigenvalues are taken from the refined basis (error of order
@@ -35,6 +40,7 @@ namespace {
 
 constexpr int MAX_SWEEPS = 4;
 constexpr double GCAP = 0.25;
+constexpr double DEGEN = 1e-10;
 // A sweep whose largest correction entry is e leaves an eigenvalue error of
 // about 3.5e-5 e^4 relative (measured on clustered s_a = 0.3 spectra,
 // e = 6e-3 .. 6e-2); e <= 1e-2 keeps it near 4e-13, far below 1e-10.
@@ -129,16 +135,23 @@ __global__ __launch_bounds__(256) void k_ref_F(const Prob* __restrict__ probs, i
         const double c12 = -S12 - 0.5 * (R11 * ll + lk * R22);
         const double c21 = -S21 - 0.5 * (-R22 * ll - lk * R11);
         const double c22 = -S22 - 0.5 * (R21 * ll - lk * R12);
-        const double det = lk * lk - ll * ll;
-        const double e11 = (c12 * ll - lk * c21) / det;
-        const double e22 = (-ll * c21 + lk * c12) / det;
-        const double e12 = (-ll * c11 - lk * c22) / det;
-        const double e21 = (ll * c22 + lk * c11) / det;
-        const double emax = fmax(fmax(fabs(e11), fabs(e12)), fmax(fabs(e21), fabs(e22)));
-        if (emax <= GCAP) {   // NaN or a near-degenerate pair: orthogonalise only
-          e = pr == 0 ? (qc == 0 ? e11 : e12) : (qc == 0 ? e21 : e22);
+        if (fabs(lk - ll) <= DEGEN * fmax(lk, ll)) {
+          // degenerate pair: g22 - g11 and g12 + g21 are fixed, the rest is free
+          const double lm = 0.5 * (lk + ll);
+          const double d = (c12 + c21) / (4.0 * lm), h = (c11 - c22) / (4.0 * lm);
+          e = pr == 0 ? (qc == 0 ? -d : h) : (qc == 0 ? h : d);
         } else {
-          nclamp += 1.0;
+          const double det = lk * lk - ll * ll;
+          const double e11 = (c12 * ll - lk * c21) / det;
+          const double e22 = (-ll * c21 + lk * c12) / det;
+          const double e12 = (-ll * c11 - lk * c22) / det;
+          const double e21 = (ll * c22 + lk * c11) / det;
+          const double emax = fmax(fmax(fabs(e11), fabs(e12)), fmax(fabs(e21), fabs(e22)));
+          if (emax <= GCAP) {   // NaN or a close pair: orthogonalise only
+            e = pr == 0 ? (qc == 0 ? e11 : e12) : (qc == 0 ? e21 : e22);
+          } else {
+            nclamp += 1.0;
+          }
         }
       }
       const double f = 0.5 * rrc + e;

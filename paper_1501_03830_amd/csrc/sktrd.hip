@@ -381,6 +381,16 @@ __global__ __launch_bounds__(256) void sk_update(const Prob* __restrict__ probs,
   }
   const double vi = inrange ? Y1[r + (long)(2 * i) * ldy] : 0.0;
   const double wrs = (r >= s + 1 && r < N) ? (double)W[r + (long)s * ld] : 0.0;
+  const bool next_col = (i + 1 < nbp) && (s <= N - 2);
+  // partial sums of S v at row s (first row of block 0), needed by every
+  // block for the next column: wave 1 starts loading them now
+  double srow = 0.0;
+  if (next_col && part == 1) {
+    const long os = s - (long)R0 * TS;
+    const int nch0 = (nblk + T - 1) / T;
+    srow = (t == 0) ? Yrow[os] : 0.0;
+    for (int c = t; c < nch0; c += 64) srow += Ycol[(long)c * TS + os];
+  }
   {
     // partial sums of this row block: b+1 row parts (one per strip c <= b)
     // and nch column parts (one per chunk of strip b); loads are issued in
@@ -432,15 +442,10 @@ __global__ __launch_bounds__(256) void sk_update(const Prob* __restrict__ probs,
     }
     pr[t] = p;
   }
-  const bool next_col = (i + 1 < nbp) && (s <= N - 2);
   if (!next_col) return;  // uniform
   // p_i at row s (first row of block 0), needed by every block
   if (part == 1) {
-    const long os = s - (long)R0 * TS;
-    const int nch0 = (nblk + T - 1) / T;
-    double acc = (t == 0) ? Yrow[os] : 0.0;
-    for (int c = t; c < nch0; c += 64) acc += Ycol[(long)c * TS + os];
-    acc = wave_sum(acc);
+    const double acc = wave_sum(srow);
     if (t == 0) red4[1] = acc;
   } else if (part == 2) {
     double acc = 0.0;

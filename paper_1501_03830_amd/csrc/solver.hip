@@ -121,7 +121,8 @@ size_t problem_bytes(long N, int prec) { return make_plan(N, prec).total; }
 // and two refinement maxima.
 static size_t hdr_info_off(int count) { return (size_t)round_up((long)(count * sizeof(Prob)), 256); }
 static size_t hdr_state_off(int count) { return hdr_info_off(count) + (size_t)round_up((long)(count * 2 * sizeof(int)), 256); }
-static size_t hdr_ref_off(int count) { return hdr_state_off(count) + (size_t)round_up((long)(count * sizeof(int)), 256); }
+static size_t hdr_reorth_off(int count) { return hdr_state_off(count) + (size_t)round_up((long)(count * sizeof(int)), 256); }
+static size_t hdr_ref_off(int count) { return hdr_reorth_off(count) + (size_t)round_up((long)(count * sizeof(int)), 256); }
 size_t header_bytes(int count) { return hdr_ref_off(count) + (size_t)round_up((long)(count * 2 * sizeof(double)), 256); }
 
 // Workspace pointers of one problem.
@@ -243,6 +244,7 @@ int setup_batch(Lane* L, int count, const long* Ns, int prec, char* header, char
   S->dprobs = reinterpret_cast<Prob*>(header);
   S->dinfo = reinterpret_cast<int*>(header + hdr_info_off(count));
   S->dstate = reinterpret_cast<int*>(header + hdr_state_off(count));
+  S->dreorth = reinterpret_cast<int*>(header + hdr_reorth_off(count));
   S->dref = reinterpret_cast<double*>(header + hdr_ref_off(count));
   S->total = header_bytes(count);
   for (int i = 0; i < count; ++i) {
@@ -252,6 +254,7 @@ int setup_batch(Lane* L, int count, const long* Ns, int prec, char* header, char
     bind_problem(plan, bases[i], &P);
     P.info = S->dinfo + 2 * i;
     P.refstate = S->dstate + i;
+    P.reorth = S->dreorth + i;
     P.refout = S->dref + 2 * i;
     S->total += plan.total;
   }
@@ -353,7 +356,7 @@ int run_chain(Lane* L, const Setup& S, int count, bool vectors, bse_report* rep)
   if (vectors || mixed) {
     BSE_TRY(invit_batched(s, b));
     BSE_TRY(mark(L, timed, ev++));
-    BSE_TRY(reorth_batched(s, b));
+    BSE_TRY(reorth_batched(s, b, S.dreorth, L->hstate, S.count));
     BSE_TRY(mark(L, timed, ev++));
     BSE_TRY(apply_UD_batched(s, b));
     BSE_TRY(mark(L, timed, ev++));
@@ -780,7 +783,7 @@ int bse_tridiag_eig(bse_ctx* ctx, int N, const double* alpha, double* lambda, do
   BSE_TRY(bisect_batched(s, b));
   if (V) {
     BSE_TRY(invit_batched(s, b));
-    BSE_TRY(reorth_batched(s, b));
+    BSE_TRY(reorth_batched(s, b, S.dreorth, ctx->lane.hstate, S.count));
     BSE_TRY(transpose_to(s, N / 2, N, P.Vt, N / 2, V, ldv));
     BSE_TRY(read_infos(&ctx->lane, S, 1));
     if (ctx->lane.hinfo[1] != 0) return set_error(BSE_EDEVICE, "cluster Gram matrix not positive definite");

@@ -305,7 +305,8 @@ __global__ __launch_bounds__(1024) void k_cluster_ids(const Prob* __restrict__ p
   const BSE_GLOBAL double* __restrict__ lam = gbl(P.lambda);
   const BSE_CONST double* __restrict__ scal = ro(P.scal);
   BSE_GLOBAL int* __restrict__ cid = gbl(P.cid);
-  const double ortol = 1e-3 * scal[1];
+  const bool mixed = P.prec == BSE_PREC_FP32_REFINE;
+  const double ortol = (mixed ? 1e-10 : 1e-3) * scal[1];
   const int T = blockDim.x;
   const int chunk = (n + T - 1) / T;
   const int b = threadIdx.x * chunk, e = min(n, b + chunk);
@@ -321,6 +322,9 @@ __global__ __launch_bounds__(1024) void k_cluster_ids(const Prob* __restrict__ p
       sums[t] = run;
       run += v;
     }
+    // run = gaps above ortol; fewer than n - 1 means a cluster
+    *gbl(P.reorth) = (!mixed || run < n - 1) ? 1 : 0;
+    gbl(P.info)[1] = 0;   // no Gram-Schmidt failure yet (it may be skipped)
   }
   __syncthreads();
   int run = sums[threadIdx.x];
@@ -332,6 +336,7 @@ __global__ __launch_bounds__(1024) void k_cluster_ids(const Prob* __restrict__ p
 
 __global__ __launch_bounds__(256) void k_mask_gram(const Prob* __restrict__ probs) {
   const Prob& P = probs[blockIdx.z];
+  if (*gbl(P.reorth) == 0) return;   // uniform: no cluster to orthogonalise
   const int n = P.n;
   const long ldg = n;
   BSE_GLOBAL double* __restrict__ G = gbl(P.inv);
@@ -386,11 +391,20 @@ int invit_batched(hipStream_t s, const Batch& b) {
   return 0;
 }
 
-int reorth_batched(hipStream_t s, const Batch& b) {
+int reorth_batched(hipStream_t s, const Batch& b, const int* dflags, int* hflags, int nslots) {
   if (b.count <= 0) return 0;
   const int n0 = b.maxn();
   k_cluster_ids<<<dim3(1, 1, (unsigned)b.count), 1024, 0, s>>>(b.dev);
   BSE_LAUNCHED();
+  if (b.host[0].prec == BSE_PREC_FP32_REFINE) {
+    // skip the launches altogether when no problem has a near-degenerate
+    // cluster (otherwise the kernels skip the problems without one)
+    BSE_HIP(hipMemcpyAsync(hflags, dflags, nslots * sizeof(int), hipMemcpyDeviceToHost, s));
+    BSE_HIP(hipStreamSynchronize(s));
+    bool any = false;
+    for (int i = 0; i < b.count; ++i) any = any || hflags[b.host[i].reorth - dflags] != 0;
+    if (!any) return 0;
+  }
   // Two passes of Cholesky QR ("twice is enough"): the second restores full
   // orthogonality when a degenerate cluster's start vectors were close.
   const dim3 g2((unsigned)((n0 + 63) / 64), (unsigned)((n0 + 63) / 64), (unsigned)b.count);

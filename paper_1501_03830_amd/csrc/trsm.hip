@@ -70,6 +70,7 @@ __global__ __launch_bounds__(256) void k_trsm_rows(const Prob* __restrict__ prob
     Nm = P.n;
   }
   if (k0 >= Nm || gbl(P.info)[sel] != 0) return;   // uniform
+  if (sel == 1 && *gbl(P.reorth) == 0) return;     // uniform: no Gram-Schmidt
   const int nbk = min(NB, Nm - k0);
   if (FULL != (nbk == NB)) return;                  // uniform: the other variant
   const int first = k0 + nbk;
@@ -94,6 +95,7 @@ __global__ __launch_bounds__(256) void k_trsm_cols(const Prob* __restrict__ prob
   const Prob& P = probs[blockIdx.z];
   const int n = P.n, N = P.N;
   if (b0 >= n || gbl(P.info)[1] != 0) return;   // uniform
+  if (*gbl(P.reorth) == 0) return;              // uniform: no Gram-Schmidt
   const int nbk = min(NB, n - b0);
   if (FULL != (nbk == NB)) return;              // uniform: the other variant
   const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;

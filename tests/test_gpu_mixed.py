@@ -120,3 +120,27 @@ def test_mixed_config2_n2048_against_golden(ctx):
         f"eig err {el:.2e} weights err {we:.2e}; stages {rep['stage_ms']}")
     assert el <= 1e-10
     assert we <= 1e-6
+
+
+def test_mixed_exactly_degenerate_spectrum(ctx):
+    """B = 0 and A with eigenvalues repeated eight times: the eigenvalues of
+    H are exactly those of A (eq. H-complex with B = 0), and inverse
+    iteration alone would return nearly parallel vectors inside each
+    eigenspace, so the mixed path must keep the cluster Gram-Schmidt here."""
+    n = 40
+    rng = np.random.default_rng(7)
+    a = np.repeat([1.5, 2.0, 3.25, 4.0, 7.5], 8)
+    G = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    Q, _ = np.linalg.qr(G)
+    A = Q @ np.diag(a) @ Q.conj().T
+    A = (A + A.conj().T) / 2
+    B = np.zeros((n, n), dtype=np.complex128)
+    res = ctx.solve(tt(A), tt(B), report=True, prec=MIXED())
+    lam = npc(res["lam"])
+    el = np.max(np.abs(lam - np.sort(a))) / a.max()
+    X = npc(res["X"])
+    r1, r2 = metrics.table1_metrics(A, B, lam, X)
+    say(f"[mixed] degenerate: sweeps {res['report']['refine_sweeps']} eig {el:.2e} table1 {r1:.2e} {r2:.2e}")
+    assert el <= 1e-10
+    assert r1 <= 1e-8 and r2 <= 1e-8
+    assert metrics.normalization_error(X) <= 1e-8
