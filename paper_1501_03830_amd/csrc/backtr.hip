@@ -9,7 +9,7 @@
 //     (-1)^((k-1)/2)); the real and imaginary parts of all n vectors are kept
 //     side by side as one real N x N matrix Z = [Re | Im], so that U and L
 //     are applied with real products only (remark 4's real/imaginary split).
-//   * U = H_0 ... H_{N-3} is applied from the left in blocks of 64
+//   * U = H_0 ... H_{N-3} is applied from the left in blocks of 128
 //     reflectors, last block first, each block as I - V T V^T (compact WY);
 //     T is applied by a triangular solve with its inverse
 //     diag(1/tau) + strict_upper(V^T V) (trsm.hip), never formed.
@@ -24,7 +24,7 @@ namespace bse {
 
 namespace {
 
-constexpr int NBQ = 64;   // reflectors per block
+constexpr int NBQ = 128;  // reflectors per block
 
 __global__ __launch_bounds__(256) void k_scatter_DV(const Prob* __restrict__ probs) {
   __shared__ double t[64][65];
@@ -228,7 +228,7 @@ int to_f32_batched(hipStream_t s, const Batch& b) {
 
 size_t backtr_work_bytes(long N, long ld) {
   (void)N;
-  return ((size_t)ld * NBQ + 2 * (size_t)NBQ * NBQ + 2 * (size_t)NBQ * ld) * sizeof(double) + 5 * 256;
+  return ((size_t)ld * NBQ + (size_t)NBQ * NBQ + 2 * (size_t)NBQ * ld) * sizeof(double) + 4 * 256;
 }
 
 void backtr_bind_work(char* base, long N, long ld, Prob* P) {
@@ -241,7 +241,6 @@ void backtr_bind_work(char* base, long N, long ld, Prob* P) {
   };
   P->Vb = reinterpret_cast<double*>(take((size_t)ld * NBQ * sizeof(double)));
   P->S = reinterpret_cast<double*>(take((size_t)NBQ * NBQ * sizeof(double)));
-  P->T = reinterpret_cast<double*>(take((size_t)NBQ * NBQ * sizeof(double)));
   P->W1 = reinterpret_cast<double*>(take((size_t)NBQ * ld * sizeof(double)));
   P->W2 = reinterpret_cast<double*>(take((size_t)NBQ * ld * sizeof(double)));
 }
@@ -264,7 +263,9 @@ int apply_UD_batched(hipStream_t s, const Batch& b) {
     BSE_LAUNCHED();
     BSE_TRY(gemm_batched(s, b, nact, GOP_APPLYU_S, q));
     BSE_TRY(gemm_batched(s, b, nact, GOP_APPLYU_W1, q));
-    BSE_TRY(wy_solve_batched(s, b, nact, q));
+    BSE_TRY(wy_solve_batched(s, b, nact, q, 1));
+    BSE_TRY(gemm_batched(s, b, nact, GOP_APPLYU_WB, q));
+    BSE_TRY(wy_solve_batched(s, b, nact, q, 0));
     BSE_TRY(gemm_batched(s, b, nact, GOP_APPLYU_Z, q));
   }
   return 0;

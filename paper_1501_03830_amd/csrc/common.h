@@ -71,7 +71,7 @@ struct Prob {
   double *Y1, *Y2, *Yrow, *Ycol, *dotpart, *normpart;
   void* ctrl;
   // back-transformation work
-  double *Vb, *S, *T, *W1, *W2;
+  double *Vb, *S, *W1, *W2;
   // mixed-precision path (prec == BSE_PREC_FP32_REFINE)
   int prec;
   float* W32;           // FP32 copy of W reduced to tridiagonal form (ld x ld)

@@ -105,23 +105,30 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
     }
     case GOP_APPLYU_S:
     case GOP_APPLYU_W1:
+    case GOP_APPLYU_WB:
     case GOP_APPLYU_Z: {
+      // reflector block `step` of RB = 128 (H_j0 .. H_j0+nbk-1, j0 = 128 step)
+      constexpr int RB = 128;
       const int nrefl = P.N - 2;
-      const int j0 = step * NB;
+      const int j0 = step * RB;
       if (nrefl <= 0 || j0 >= nrefl) break;
-      const int nbk = (nrefl - j0 < NB) ? nrefl - j0 : NB;
+      const int nbk = (nrefl - j0 < RB) ? nrefl - j0 : RB;
       const int m = P.N - j0 - 1;
       const double* Vb = P.Vb + (j0 + 1);
       double* Zs = P.Z + (j0 + 1);
-      if (op == GOP_APPLYU_S) {
+      if (op == GOP_APPLYU_S) {         // S = V^T V
         g.ta = 1; g.tb = 0; g.M = nbk; g.N = nbk; g.K = m;
-        g.A = Vb; g.lda = ld; g.B = Vb; g.ldb = ld; g.C = P.S; g.ldc = NB;
-      } else if (op == GOP_APPLYU_W1) {
+        g.A = Vb; g.lda = ld; g.B = Vb; g.ldb = ld; g.C = P.S; g.ldc = RB;
+      } else if (op == GOP_APPLYU_W1) {  // W1 = V^T Z
         g.ta = 1; g.tb = 0; g.M = nbk; g.N = P.N; g.K = m;
-        g.A = Vb; g.lda = ld; g.B = Zs; g.ldb = ld; g.C = P.W1; g.ldc = NB;
-      } else {
+        g.A = Vb; g.lda = ld; g.B = Zs; g.ldb = ld; g.C = P.W1; g.ldc = RB;
+      } else if (op == GOP_APPLYU_WB) {  // W1[0:64] -= S[0:64, 64:] W2[64:]
+        if (nbk <= NB) break;
+        g.ta = 0; g.tb = 0; g.M = NB; g.N = P.N; g.K = nbk - NB; g.alpha = -1.0; g.beta = 1.0;
+        g.A = P.S + (long)NB * RB; g.lda = RB; g.B = P.W2 + NB; g.ldb = RB; g.C = P.W1; g.ldc = RB;
+      } else {                           // Z -= V W2
         g.ta = 0; g.tb = 0; g.M = m; g.N = P.N; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
-        g.A = Vb; g.lda = ld; g.B = P.W2; g.ldb = NB; g.C = Zs; g.ldc = ld;
+        g.A = Vb; g.lda = ld; g.B = P.W2; g.ldb = RB; g.C = Zs; g.ldc = ld;
       }
       break;
     }
@@ -160,8 +167,8 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
   g.splits = 1;
   g.kchunk = g.K;
   g.part = nullptr;
-  if (g.ntiles > 0 && g.ntiles < 512 && g.K >= 2048 && P.gscr != nullptr) {
-    long splits = (1024 + g.ntiles - 1) / g.ntiles;
+  if (g.ntiles > 0 && g.ntiles < 1024 && g.K >= 2048 && P.gscr != nullptr) {
+    long splits = (2048 + g.ntiles - 1) / g.ntiles;
     if (splits > 16) splits = 16;
     const long maxk = g.K / 512;
     if (splits > maxk) splits = maxk;

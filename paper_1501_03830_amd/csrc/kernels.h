@@ -58,6 +58,7 @@ enum GemmOp {
   GOP_GRAM_UPD,    // forward substitution: rows below the block at `step`
   GOP_APPLYU_S,    // V^T V of reflector block `step`
   GOP_APPLYU_W1,   // V^T Z
+  GOP_APPLYU_WB,   // two-level solve with T^{-1}: top rows -= S_12 (bottom rows)
   GOP_APPLYU_Z,    // Z -= V (T V^T Z)
   GOP_APPLY_L,     // G = L Z
   GOP_REF_P,       // refinement: P = W Ub (basis Ub of sweep `step`)
@@ -90,8 +91,10 @@ int zero_upper(hipStream_t s, int N, double* A, long lda);
 int trsm_rows_batched(hipStream_t s, const Batch& b, int nact, int sel, int k0);
 // rows b0 .. b0+63 of V_+^T <- L_bb^{-1} times themselves (Gram factor)
 int trsm_cols_batched(hipStream_t s, const Batch& b, int nact, int b0);
-// P.W2 = T P.W1 for reflector block q (T from P.S = V^T V and tau)
-int wy_solve_batched(hipStream_t s, const Batch& b, int nact, int q);
+// Rows 64h .. 64h+63 of P.W2 <- solve with the diagonal block h of
+// T^{-1} = diag(1/tau) + strict_upper(V^T V) of reflector block q (128
+// reflectors, S = V^T V in P.S); the right-hand side is the same rows of P.W1
+int wy_solve_batched(hipStream_t s, const Batch& b, int nact, int q, int h);
 
 // ---------------------------------------------------------------- sktrd.hip
 size_t sktrd_work_bytes(long N, long ld);

@@ -111,39 +111,48 @@ __global__ __launch_bounds__(256) void k_trsm_cols(const Prob* __restrict__ prob
     if (FULL || i < nbk) v[i] = x[i];
 }
 
-// Compact-WY factor of reflector block q: W2 = T W1, solved as
-// (diag(1/tau) + strict_upper(S)) W2 = W1 with S = V^T V.  A reflector with
-// tau = 0 is the identity: its row of W2 is zero.
-__global__ __launch_bounds__(256) void k_wy_solve(const Prob* __restrict__ probs, int q) {
+// Compact-WY factor of reflector block q (RB = 128 reflectors):
+// T^{-1} = diag(1/tau) + strict_upper(S), S = V^T V, is [A B; 0 C] in 64 x 64
+// blocks, so W2 = T W1 is the solve with C on the bottom rows (h = 1), then
+// the top rows minus B W2_bottom (a GEMM), then the solve with A (h = 0).  A
+// reflector with tau = 0 is the identity: its row of W2 is zero (its
+// right-hand side is set to zero and its row and column of the block are
+// left out).
+constexpr int RB = 128;
+__global__ __launch_bounds__(256) void k_wy_solve(const Prob* __restrict__ probs, int q, int h) {
   __shared__ double Us[NB][NB + 1];
   __shared__ int zero[NB];
   const Prob& P = probs[blockIdx.z];
   const int N = P.N;
   const int nrefl = N - 2;
-  const int j0 = q * NB;
-  if (j0 >= nrefl) return;   // uniform
+  const int jb = q * RB;
+  if (jb >= nrefl) return;   // uniform
   if ((long)blockIdx.x * blockDim.x >= N) return;   // uniform
-  const int nbk = min(NB, nrefl - j0);
+  const int nbk = min(RB, nrefl - jb);
+  const int off = NB * h;    // first reflector of this half inside the block
+  if (off >= nbk) return;    // uniform: the block has no second half
+  const int nsub = min(NB, nbk - off);
+  const int j0 = jb + off;
   const BSE_CONST double* __restrict__ S = ro(P.S);
   const BSE_CONST double* __restrict__ tau = ro(P.tau);
   if (threadIdx.x < NB) {
     const int i = threadIdx.x;
-    zero[i] = (i >= nbk) || (tau[j0 + i] == 0.0);
+    zero[i] = (i >= nsub) || (tau[j0 + i] == 0.0);
   }
   __syncthreads();
   for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
     const int r = idx & 63, c = idx >> 6;
     double v;
     if (r == c) v = zero[r] ? 1.0 : 1.0 / tau[j0 + r];
-    else if (r < c && !zero[r] && !zero[c]) v = S[r + (long)c * NB];
+    else if (r < c && !zero[r] && !zero[c]) v = S[(off + r) + (long)(off + c) * RB];
     else v = 0.0;
     Us[c][r] = v;
   }
   __syncthreads();
   const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= N) return;
-  const BSE_GLOBAL double* __restrict__ w1 = gbl(P.W1) + j * NB;
-  BSE_GLOBAL double* __restrict__ w2 = gbl(P.W2) + j * NB;
+  const BSE_GLOBAL double* __restrict__ w1 = gbl(P.W1) + off + j * RB;
+  BSE_GLOBAL double* __restrict__ w2 = gbl(P.W2) + off + j * RB;
   double x[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) x[i] = zero[i] ? 0.0 : w1[i];
@@ -177,10 +186,10 @@ int trsm_cols_batched(hipStream_t s, const Batch& b, int nact, int b0) {
   return 0;
 }
 
-int wy_solve_batched(hipStream_t s, const Batch& b, int nact, int q) {
+int wy_solve_batched(hipStream_t s, const Batch& b, int nact, int q, int h) {
   if (nact <= 0) return 0;
   const long N0 = b.maxN();
-  k_wy_solve<<<dim3((unsigned)((N0 + 255) / 256), 1, (unsigned)nact), 256, 0, s>>>(b.dev, q);
+  k_wy_solve<<<dim3((unsigned)((N0 + 255) / 256), 1, (unsigned)nact), 256, 0, s>>>(b.dev, q, h);
   BSE_LAUNCHED();
   return 0;
 }
