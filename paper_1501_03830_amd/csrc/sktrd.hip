@@ -44,7 +44,7 @@ namespace {
 constexpr int TS = 64;       // symv tile
 constexpr int NBMAX = 64;    // panel width bound
 constexpr int DUTY_BLK = 16; // row blocks per workgroup of the panel dot products
-constexpr int TMAX = 8;      // row tiles per strip workgroup (upper bound)
+constexpr int TMAX = 16;     // row tiles per strip workgroup (upper bound)
 
 // Reflector of the first column of a panel (sk_start) and the subdiagonal
 // entry of the column brought up to date by the last update.
@@ -107,12 +107,52 @@ __global__ __launch_bounds__(256) void sk_start(const Prob* __restrict__ probs, 
 }
 
 // Row tiles per strip workgroup of the matvec for a trailing matrix of nblk
-// row blocks: about 4096 workgroups per problem.  It depends on the problem
-// alone, so a problem's summation order -- and its result -- is the same
-// whether it is solved alone or inside a batch.
+// row blocks.  Long strips amortise each workgroup's prologue (the reflector,
+// the first loads) and its reductions; short ones keep enough workgroups in
+// flight.  The steps were measured on a 16384-row trailing matrix swept down
+// to 512 rows.  The count depends on the problem alone, so a problem's
+// summation order -- and its result -- is the same whether it is solved alone
+// or inside a batch.
+template <class WT>
 __host__ __device__ inline int symv_tiles(int nblk) {
-  const long T = (long)nblk * (nblk + 1) / 2 / 4096;
-  return T < 1 ? 1 : (T > TMAX ? TMAX : (int)T);
+  if (sizeof(WT) == 8) {
+    if (nblk >= 224) return 16;
+    if (nblk >= 160) return 12;
+    if (nblk >= 40) return 3;
+    if (nblk >= 24) return 2;
+    return 1;
+  }
+  if (nblk >= 224) return 12;
+  if (nblk >= 160) return 8;
+  if (nblk >= 80) return 6;
+  if (nblk >= 40) return 3;
+  if (nblk >= 24) return 2;
+  return 1;
+}
+
+// Sums NV per-lane values (NV a power of two, at most 64) over the 64 lanes
+// of a wavefront.  Each exchange hands half of the remaining values to the
+// partner lane and keeps the other half, so it takes NV - 1 + log2(64 / NV)
+// shuffles instead of 6 NV.  Lane L returns the total of value L / (64 / NV).
+template <int NV>
+__device__ inline double wave_sum_many(double (&v)[NV]) {
+  const int lane = threadIdx.x & 63;
+  int off = 32;
+#pragma unroll
+  for (int h = NV / 2; h >= 1; h >>= 1) {
+    const bool up = (lane & off) != 0;
+#pragma unroll
+    for (int q = 0; q < h; ++q) {
+      const double snd = up ? v[q] : v[q + h];
+      const double kp = up ? v[q + h] : v[q];
+      v[q] = kp + __shfl_xor(snd, off, 64);
+    }
+    off >>= 1;
+  }
+  double r = v[0];
+#pragma unroll
+  for (; off >= 1; off >>= 1) r += __shfl_xor(r, off, 64);
+  return r;
 }
 
 template <class Ptr>
@@ -128,9 +168,9 @@ __device__ inline double vval(Ptr W, long ld, int j, int s, int N, double scale,
 //   row tiles Cl + k*T .. Cl + k*T + T - 1.  Lane = row inside a tile, wave w
 //   owns columns 16w..16w+15 of the strip, so every load instruction reads
 //   64 consecutive doubles of one column.  Row sums (S v) of each tile go to
-//   Yrow[Cl][rl] (written once per workgroup, contiguously); column sums
+//   Yrow[rl][Cl] (written once per workgroup); column sums
 //   (-S^T v) accumulate in registers over the tiles and are reduced across
-//   the wave once, into Ycol[Cl][k].
+//   the wave once (wave_sum_many), into Ycol[Cl][k].
 // blockIdx.y == 0 (dispatched first): workgroups (d, g) store v_i for row
 //   blocks d*16 .. d*16+15 and their share of the panel dot products V^T v,
 //   P^T v (summed by the update kernel).
@@ -143,7 +183,7 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
   const int s = j + 1;
   const int R0 = s / TS;
   const int nblk = (N - 1) / TS - R0 + 1;
-  const int T = symv_tiles(nblk);
+  const int T = symv_tiles<WT>(nblk);
   const int nchunk = (nblk + T - 1) / T;
   const long ld = P.ld, ldy = P.ld;
   const int dstride = (int)(ld / TS);
@@ -212,16 +252,10 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
       for (int q = 0; q < 8; ++q) acc[q] += y[q] * v;
     }
     if (i == 0) return;  // uniform
-    // butterfly over the 64 lanes, all columns interleaved
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1)
-#pragma unroll
-      for (int q = 0; q < 8; ++q) acc[q] += __shfl_xor(acc[q], off, 64);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int l = 32 * g + wv + 4 * q;
-      if (l < 2 * i && lane == 0) dotpart[(long)l * dstride + d] = acc[q];
-    }
+    // lane 8q ends with the total of acc[q]
+    const double tot = wave_sum_many(acc);
+    const int l = 32 * g + wv + 4 * (lane >> 3);
+    if ((lane & 7) == 0 && l < 2 * i) dotpart[(long)l * dstride + d] = tot;
     return;
   }
 
@@ -251,11 +285,11 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
     xc[q] = vcol[c < N ? c : 0];
   }
   const double scale = column_scale();
-  double vc[16];
+  double vc[16];   // wave-uniform: moved to scalar registers
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const long c = col0 + q;
-    vc[q] = (c == s) ? 1.0 : ((c > s && c < N) ? scale * xc[q] : 0.0);
+    vc[q] = uniform_double((c == s) ? 1.0 : ((c > s && c < N) ? scale * xc[q] : 0.0));
   }
   double cacc[16];
 #pragma unroll
@@ -296,34 +330,31 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
       xr = xn;
     }
   }
-  // column sums: butterfly over the 64 lanes, the 16 columns interleaved
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1)
-#pragma unroll
-    for (int q = 0; q < 16; ++q) cacc[q] += __shfl_xor(cacc[q], off, 64);
-  double mine = 0.0;
-#pragma unroll
-  for (int q = 0; q < 16; ++q)
-    if (lane == q) mine = cacc[q];
-  if (lane < 16) Ycol[((long)Cl * nchunk + k) * TS + 16 * wv + lane] = -mine;
+  // column sums over the 64 lanes: lane 4q ends with the total of column q
+  const double csum = wave_sum_many(cacc);
+  if ((lane & 3) == 0) Ycol[((long)Cl * nchunk + k) * TS + 16 * wv + (lane >> 2)] = -csum;
   __syncthreads();
-  // the chunk's row sums are contiguous in Yrow ([strip][row block][64])
+  // Yrow is [row block][strip][64]: the update kernel of a row block reads
+  // its b + 1 row parts contiguously
   for (int t = wv; t < rl1 - rl0; t += 4)
-    Yrow[((long)Cl * nblk + rl0 + t) * TS + lane] =
+    Yrow[((long)(rl0 + t) * nblk + Cl) * TS + lane] =
         rsum[t][0][lane] + rsum[t][1][lane] + rsum[t][2][lane] + rsum[t][3][lane];
 }
 
 // p_i = tau (S v + V c_P - P c_V) for the rows of block b, the in-place store
-// of v_i, the update of the next column and, in the last workgroup, its
-// reflector.  The panel sums over l are split over the four wavefronts.
+// of v_i, and the update of the next column with one partial squared norm of
+// it per workgroup.  Sixteen wavefronts share the 64-row block: the partial
+// sums of S v and the panel sums over l are split over them, so that every
+// thread has only a few loads to wait for.
+constexpr int UW = 16;   // wavefronts per update workgroup
 template <class WT>
-__global__ __launch_bounds__(256) void sk_update(const Prob* __restrict__ probs, int j, int i) {
+__global__ __launch_bounds__(64 * UW) void sk_update(const Prob* __restrict__ probs, int j, int i) {
   __shared__ double cs[2 * NBMAX];
   __shared__ double ys_row[2 * NBMAX];   // Y1 row s (v_l[s], p_l[s])
-  __shared__ double red[4][TS];
-  __shared__ double red2[4][TS];
+  __shared__ double red[UW][TS];
+  __shared__ double red2[UW][TS];
   __shared__ double pr[TS];
-  __shared__ double red4[4];
+  __shared__ double red4[UW];
   __shared__ double sval_s;
   const Prob& P = probs[blockIdx.z];
   const int N = P.N;
@@ -333,7 +364,7 @@ __global__ __launch_bounds__(256) void sk_update(const Prob* __restrict__ probs,
   const int nblk = (N - 1) / TS - R0 + 1;
   const int b = blockIdx.x;
   if (b >= nblk) return;  // uniform: beyond this problem's row blocks
-  const int T = symv_tiles(nblk);
+  const int T = symv_tiles<WT>(nblk);
   const int nchunk = (nblk + T - 1) / T;
   const int k0 = j - i;   // first column of the panel
   const int nbp = min(NBMAX, N - 1 - k0);
@@ -368,13 +399,14 @@ __global__ __launch_bounds__(256) void sk_update(const Prob* __restrict__ probs,
   }
   const long r = (long)(R0 + b) * TS + t;
   const bool inrange = r >= s && r < N;
-  // this row's panel entries (v_l, p_l for l = part, part + 4, ...), v_i, and
+  // this row's panel entries (v_l, p_l for l = part, part + UW, ...), v_i, and
   // W[r, s]: loaded once, before anything waits, and used by both
   // corrections below
-  double yv[NBMAX / 4], yp[NBMAX / 4];
+  constexpr int NQ = NBMAX / UW;
+  double yv[NQ], yp[NQ];
 #pragma unroll
-  for (int q = 0; q < NBMAX / 4; ++q) {
-    const int l = part + 4 * q;
+  for (int q = 0; q < NQ; ++q) {
+    const int l = part + UW * q;
     const bool use = inrange && l < i;
     yv[q] = use ? Y1[r + (long)(2 * l) * ldy] : 0.0;
     yp[q] = use ? Y1[r + (long)(2 * l + 1) * ldy] : 0.0;
@@ -392,26 +424,26 @@ __global__ __launch_bounds__(256) void sk_update(const Prob* __restrict__ probs,
     for (int c = t; c < nch0; c += 64) srow += Ycol[(long)c * TS + os];
   }
   {
-    // partial sums of this row block: b+1 row parts (one per strip c <= b)
-    // and nch column parts (one per chunk of strip b); loads are issued in
-    // batches of 8 so that each thread has many in flight
+    // partial sums of this row block: b+1 row parts (one per strip c <= b,
+    // contiguous in Yrow[b][c][64]) and nch column parts (one per chunk of
+    // strip b); loads are issued in batches of 8
     double acc[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-    const auto yr = Yrow + (long)b * TS + t;      // Yrow[c][b][t]
-    for (int c0 = part; c0 <= b; c0 += 32) {
+    const auto yr = Yrow + (long)b * nblk * TS + t;
+    for (int c0 = part; c0 <= b; c0 += 8 * UW) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const int c = c0 + 4 * q;
-        if (c <= b) acc[q] += yr[(long)c * nblk * TS];
+        const int c = c0 + UW * q;
+        if (c <= b) acc[q] += yr[(long)c * TS];
       }
     }
     const int nch = (nblk - b + T - 1) / T;
     const auto yc = Ycol + (long)b * nchunk * TS + t;
-    for (int c0 = part; c0 < nch; c0 += 32) {
+    for (int c0 = part; c0 < nch; c0 += 8 * UW) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const int c = c0 + 4 * q;
+        const int c = c0 + UW * q;
         if (c < nch) acc[q] += yc[(long)c * TS];
       }
     }
@@ -422,8 +454,8 @@ __global__ __launch_bounds__(256) void sk_update(const Prob* __restrict__ probs,
     double corr = 0.0;
     if (inrange) {
 #pragma unroll
-      for (int q = 0; q < NBMAX / 4; ++q) {
-        const int l = part + 4 * q;
+      for (int q = 0; q < NQ; ++q) {
+        const int l = part + UW * q;
         if (l < i) corr += yv[q] * cs[2 * l + 1] - yp[q] * cs[2 * l];
       }
     }
@@ -433,8 +465,12 @@ __global__ __launch_bounds__(256) void sk_update(const Prob* __restrict__ probs,
   if (part == 0) {
     double p = 0.0;
     if (inrange) {
-      const double y = red[0][t] + red[1][t] + red[2][t] + red[3][t];
-      const double corr = red2[0][t] + red2[1][t] + red2[2][t] + red2[3][t];
+      double y = 0.0, corr = 0.0;
+#pragma unroll
+      for (int w = 0; w < UW; ++w) {
+        y += red[w][t];
+        corr += red2[w][t];
+      }
       p = tau * (y + corr);
       Y1[r + (long)(2 * i + 1) * ldy] = p;
       Y2[r + (long)(2 * i) * ldy] = p;
@@ -459,8 +495,8 @@ __global__ __launch_bounds__(256) void sk_update(const Prob* __restrict__ probs,
     double upd = 0.0;
     if (r >= s + 1 && r < N) {
 #pragma unroll
-      for (int q = 0; q < NBMAX / 4; ++q) {
-        const int l = part + 4 * q;
+      for (int q = 0; q < NQ; ++q) {
+        const int l = part + UW * q;
         if (l < i) upd += yv[q] * ys_row[2 * l + 1] - yp[q] * ys_row[2 * l];
       }
     }
@@ -469,7 +505,9 @@ __global__ __launch_bounds__(256) void sk_update(const Prob* __restrict__ probs,
   __syncthreads();
   double nrm = 0.0;
   if (part == 0 && r >= s + 1 && r < N) {
-    double upd = wrs + red2[0][t] + red2[1][t] + red2[2][t] + red2[3][t];
+    double upd = wrs;
+#pragma unroll
+    for (int w = 0; w < UW; ++w) upd += red2[w][t];
     upd += vi * sval_s - pr[t];
     // the column as stored (rounded to T) is what the next reflector sees
     const double upds = (double)(WT)upd;
@@ -541,7 +579,7 @@ static int sktrd_run(hipStream_t s, const Batch& b, KernelTimer* timer) {
       int nchunk0 = 1;
       for (int q = 0; q < nact; ++q) {
         const int nbq = (b.host[q].N - 1) / TS - R0 + 1;
-        const int T = symv_tiles(nbq);
+        const int T = symv_tiles<WT>(nbq);
         nchunk0 = std::max(nchunk0, (nbq + T - 1) / T);
       }
       const bool timed = timer && timer->used + 2 <= timer->cap;
@@ -558,7 +596,7 @@ static int sktrd_run(hipStream_t s, const Batch& b, KernelTimer* timer) {
           timer->bytes += sizeof(WT) * m * (m - 1.0) * 0.5;
         }
       }
-      sk_update<WT><<<dim3((unsigned)nblk0, 1, (unsigned)nact), 256, 0, s>>>(b.dev, j, i);
+      sk_update<WT><<<dim3((unsigned)nblk0, 1, (unsigned)nact), 64 * UW, 0, s>>>(b.dev, j, i);
       BSE_LAUNCHED();
     }
     BSE_TRY(gemm_batched(s, b, nstart, GOP_SKTRD_R2K, k0));
