@@ -80,6 +80,7 @@ struct Prob {
   double* refout;       // refinement: [largest correction, clamped pairs] (header)
   int* refstate;        // refinement: sweeps done once converged, else 0 (header)
   int* reorth;          // 1: run the cluster Gram-Schmidt (header)
+  double* gdef;         // largest |G - I| inside a cluster, first pass (header)
   int* perm;            // n: output column j takes eigenpair perm[j]
 };
 

@@ -123,7 +123,8 @@ static size_t hdr_info_off(int count) { return (size_t)round_up((long)(count * s
 static size_t hdr_state_off(int count) { return hdr_info_off(count) + (size_t)round_up((long)(count * 2 * sizeof(int)), 256); }
 static size_t hdr_reorth_off(int count) { return hdr_state_off(count) + (size_t)round_up((long)(count * sizeof(int)), 256); }
 static size_t hdr_ref_off(int count) { return hdr_reorth_off(count) + (size_t)round_up((long)(count * sizeof(int)), 256); }
-size_t header_bytes(int count) { return hdr_ref_off(count) + (size_t)round_up((long)(count * 2 * sizeof(double)), 256); }
+static size_t hdr_gdef_off(int count) { return hdr_ref_off(count) + (size_t)round_up((long)(count * 2 * sizeof(double)), 256); }
+size_t header_bytes(int count) { return hdr_gdef_off(count) + (size_t)round_up((long)(count * sizeof(double)), 256); }
 
 // Workspace pointers of one problem.
 static void bind_problem(const Plan& p, char* base, Prob* P) {
@@ -256,6 +257,7 @@ int setup_batch(Lane* L, int count, const long* Ns, int prec, char* header, char
     P.refstate = S->dstate + i;
     P.reorth = S->dreorth + i;
     P.refout = S->dref + 2 * i;
+    P.gdef = reinterpret_cast<double*>(header + hdr_gdef_off(count)) + i;
     S->total += plan.total;
   }
   return 0;

@@ -324,6 +324,7 @@ __global__ __launch_bounds__(1024) void k_cluster_ids(const Prob* __restrict__ p
     }
     // run = gaps above ortol; fewer than n - 1 means a cluster
     *gbl(P.reorth) = (!mixed || run < n - 1) ? 1 : 0;
+    *gbl(P.gdef) = 0.0;
     gbl(P.info)[1] = 0;   // no Gram-Schmidt failure yet (it may be skipped)
   }
   __syncthreads();
@@ -343,13 +344,34 @@ __global__ __launch_bounds__(256) void k_mask_gram(const Prob* __restrict__ prob
   const BSE_GLOBAL int* __restrict__ cid = gbl(P.cid);
   const long r = (long)blockIdx.x * 64 + (threadIdx.x & 63);
   const long c0 = (long)blockIdx.y * 64 + (threadIdx.x >> 6) * 16;
-  if (r >= n) return;
-  const int cr = cid[r];
-  for (int q = 0; q < 16; ++q) {
+  __shared__ double wmax[4];
+  double def = 0.0;   // largest |G - I| over this thread's entries inside a cluster
+  const int cr = r < n ? cid[r] : -1;
+  for (int q = 0; q < 16 && r < n; ++q) {
     const long c = c0 + q;
     if (c >= n || c > r) break;
     if (cid[c] != cr) G[r + c * ldg] = 0.0;
+    else def = fmax(def, fabs(G[r + c * ldg] - (c == r ? 1.0 : 0.0)));
   }
+  // the workgroup's largest defect joins the problem's (non-negative doubles
+  // order like their bit patterns)
+  for (int off = 32; off >= 1; off >>= 1) def = fmax(def, __shfl_xor(def, off, 64));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = def;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double m = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+    if (m > 0.0)
+      __hip_atomic_fetch_max((BSE_GLOBAL unsigned long long*)P.gdef, (unsigned long long)__double_as_longlong(m),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// The second Cholesky QR pass runs only where the first Gram matrix was far
+// from the identity.  Its error after one pass grows like u cond(V)^2, and
+// ||G - I||_2 <= n max |G_ij - delta_ij| <= 1e-2 bounds cond(V)^2 by 1.03.
+__global__ void k_reorth_gate(const Prob* __restrict__ probs) {
+  const Prob& P = probs[blockIdx.x];
+  if (threadIdx.x == 0 && *gbl(P.reorth) != 0 && (double)P.n * *gbl(P.gdef) <= 1e-2) *gbl(P.reorth) = 0;
 }
 
 __global__ __launch_bounds__(256) void k_transpose(int rows, int cols, const double* __restrict__ src, long lds,
@@ -406,9 +428,15 @@ int reorth_batched(hipStream_t s, const Batch& b, const int* dflags, int* hflags
     if (!any) return 0;
   }
   // Two passes of Cholesky QR ("twice is enough"): the second restores full
-  // orthogonality when a degenerate cluster's start vectors were close.
+  // orthogonality when a degenerate cluster's start vectors were close, and
+  // is skipped (its kernels return at once) when the first Gram matrix shows
+  // the vectors were already close to orthonormal.
   const dim3 g2((unsigned)((n0 + 63) / 64), (unsigned)((n0 + 63) / 64), (unsigned)b.count);
   for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1) {
+      k_reorth_gate<<<dim3((unsigned)b.count), 64, 0, s>>>(b.dev);
+      BSE_LAUNCHED();
+    }
     // G = Vt Vt^T (lower), then drop the entries between clusters
     BSE_TRY(gemm_batched(s, b, b.count, GOP_GRAM, 0));
     k_mask_gram<<<g2, 256, 0, s>>>(b.dev);
