@@ -137,6 +137,9 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
       g.A = P.L; g.lda = ld; g.B = P.Z; g.ldb = ld; g.C = P.W; g.ldc = ld; g.a_tri = 1;
       break;
     case GOP_REF_P:
+    case GOP_REF_PB:
+    case GOP_REF_PF:
+    case GOP_REF_PFB:
     case GOP_REF_S:
     case GOP_REF_G:
     case GOP_REF_U: {
@@ -144,8 +147,15 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
       double* Ub = (step & 1) ? P.R4 : P.Z;
       double* Un = (step & 1) ? P.Z : P.R4;
       g.M = P.N; g.N = P.N; g.K = P.N;
-      if (op == GOP_REF_P) {         // W (full, FP64) times the basis
+      if (op == GOP_REF_P || op == GOP_REF_PF) {
+        // rows 0..n-1 of W Ub = [W11 W12] Ub (W full, FP64); the final
+        // eigenvalues need only the first n columns
+        g.M = P.n; g.N = (op == GOP_REF_PF) ? P.n : P.N;
         g.ta = 0; g.tb = 0; g.A = P.W; g.lda = ld; g.B = Ub; g.ldb = ld; g.C = P.R1; g.ldc = ld;
+      } else if (op == GOP_REF_PB || op == GOP_REF_PFB) {
+        // rows n..N-1 of W Ub = W21 Ub[0:n, :], since W22 = 0
+        g.M = P.n; g.N = (op == GOP_REF_PFB) ? P.n : P.N; g.K = P.n;
+        g.ta = 0; g.tb = 0; g.A = P.W + P.n; g.lda = ld; g.B = Ub; g.ldb = ld; g.C = P.R1 + P.n; g.ldc = ld;
       } else if (op == GOP_REF_S) {  // Ub^T (W Ub), lower triangle
         g.ta = 1; g.tb = 0; g.A = Ub; g.lda = ld; g.B = P.R1; g.ldb = ld; g.C = P.R2; g.ldc = ld; g.c_uplo = 1;
       } else if (op == GOP_REF_G) {  // Ub^T Ub, lower triangle

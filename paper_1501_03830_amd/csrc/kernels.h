@@ -61,10 +61,13 @@ enum GemmOp {
   GOP_APPLYU_WB,   // two-level solve with T^{-1}: top rows -= S_12 (bottom rows)
   GOP_APPLYU_Z,    // Z -= V (T V^T Z)
   GOP_APPLY_L,     // G = L Z
-  GOP_REF_P,       // refinement: P = W Ub (basis Ub of sweep `step`)
+  GOP_REF_P,       // refinement: rows ..n-1 of P = W Ub (basis Ub of sweep `step`)
   GOP_REF_S,       // refinement: S = Ub^T P (lower)
   GOP_REF_G,       // refinement: G = Ub^T Ub (lower)
   GOP_REF_U,       // refinement: next basis = Ub (I + F)
+  GOP_REF_PB,      // refinement: rows n.. of W Ub = W21 Ub[0:n] (W22 = 0)
+  GOP_REF_PF,      // final eigenvalues: rows ..n-1 of W Ub, first n columns
+  GOP_REF_PFB,     // final eigenvalues: rows n.. of W Ub, first n columns
 };
 __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step);
 // Product `op` at `step` for the first nact problems of the batch.

@@ -9,6 +9,7 @@
 // Given an approximate Ub (from the FP32 reduction), one sweep computes in
 // FP64 (W is the exact FP64 W of Algorithm 1 step 3)
 //     P = W Ub,  S = Ub^T P,  G = Ub^T Ub,  R = I - G,
+// (P in two products: W22 = 0 leaves the bottom rows a product over n only),
 // the refined lambda_k of each pair from its 2 x 2 blocks,
 //     lambda_k = s_k / sqrt(det G_kk),  s_k = -S[n+k, k],
 // and the correction Ub <- Ub (I + F), F = R/2 + E with E skew.  E is zero on
@@ -219,8 +220,8 @@ __global__ __launch_bounds__(256) void k_ref_decide(const Prob* __restrict__ pro
   }
 }
 
-// lambda_k from the final basis Ub (sweep count = refstate) and P = W Ub (R1):
-// one workgroup per pair
+// lambda_k from the final basis Ub (sweep count = refstate) and the first n
+// columns of P = W Ub (R1): one workgroup per pair
 __global__ __launch_bounds__(256) void k_ref_final(const Prob* __restrict__ probs) {
   __shared__ double red[4][4];
   const Prob& P = probs[blockIdx.z];
@@ -298,6 +299,7 @@ int refine_batched(hipStream_t s, const Batch& b, const RefineIO& io, RefineStat
   int sweeps = 0;
   for (int sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
     BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_P, sweep));
+    BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_PB, sweep));
     BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_S, sweep));
     BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_G, sweep));
     k_ref_lambda<<<dim3((unsigned)((n0 + 63) / 64), 1, (unsigned)b.count), 64, 0, s>>>(b.dev, sweep);
@@ -328,7 +330,8 @@ int refine_batched(hipStream_t s, const Batch& b, const RefineIO& io, RefineStat
   }
   if (st) st->sweeps = sweeps;
   // eigenvalues from each problem's final basis, sorted; eigenvectors to Z
-  BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_P, -1));
+  BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_PF, -1));
+  BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_PFB, -1));
   k_ref_final<<<dim3((unsigned)n0, 1, (unsigned)b.count), 256, 0, s>>>(b.dev);
   BSE_LAUNCHED();
   k_ref_sort<<<dim3((unsigned)((n0 + 255) / 256), 1, (unsigned)b.count), 256, 0, s>>>(b.dev);
