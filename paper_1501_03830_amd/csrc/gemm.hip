@@ -28,12 +28,14 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "driver.h"
 
 namespace bse {
 
 namespace {
 
 constexpr int BM = 64, BN = 64, BK = 16, PAD = 2;
+constexpr int F32_TILE = 128;   // tile edge of the FP32 products
 
 }  // namespace
 
@@ -160,8 +162,13 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
         g.ta = 1; g.tb = 0; g.A = Ub; g.lda = ld; g.B = P.R1; g.ldb = ld; g.C = P.R2; g.ldc = ld; g.c_uplo = 1;
       } else if (op == GOP_REF_G) {  // Ub^T Ub, lower triangle
         g.ta = 1; g.tb = 0; g.A = Ub; g.lda = ld; g.B = Ub; g.ldb = ld; g.C = P.R3; g.ldc = ld; g.c_uplo = 1;
-      } else {                       // Ub (I + F), I + F in R1
-        g.ta = 0; g.tb = 0; g.A = Ub; g.lda = ld; g.B = P.R1; g.ldb = ld; g.C = Un; g.ldc = ld;
+      } else {
+        // Un = Ub + Ub F: the correction product in FP32 (F and a rounded
+        // copy of Ub in R1, see the refinement), the sum in FP64
+        const float* F32 = reinterpret_cast<const float*>(P.R1);
+        g.f32 = 1; g.ta = 0; g.tb = 0;
+        g.Af = F32 + ld * ld; g.lda = ld; g.Bf = F32; g.ldb = ld;
+        g.C = Un; g.Cin = Ub; g.ldc = ld; g.beta = 1.0;
       }
       break;
     }
@@ -170,8 +177,9 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
   }
   // tiles and split-K: few output tiles and a long K are split along K into
   // the problem's scratch buffer
-  g.tiles_m = (g.M + BM - 1) / BM;
-  g.tiles_n = (g.N + BN - 1) / BN;
+  const int tbm = g.f32 ? F32_TILE : BM, tbn = g.f32 ? F32_TILE : BN;
+  g.tiles_m = (g.M + tbm - 1) / tbm;
+  g.tiles_n = (g.N + tbn - 1) / tbn;
   g.ntiles = (g.M <= 0 || g.N <= 0) ? 0
              : (g.c_uplo ? (long)g.tiles_m * (g.tiles_m + 1) / 2 : (long)g.tiles_m * g.tiles_n);
   g.splits = 1;
@@ -451,6 +459,184 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ 
   }
 }
 
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+// FP32 products on the FP32 matrix cores: 128 x 128 tiles, K steps of 16,
+// four waves of 64 x 64 outputs, each 4 x 4 blocks of v_mfma_f32_16x16x4f32.
+// (FP32 operands are half the bytes of FP64 ones at over twice the matrix
+// rate, so a tile needs four times the FP64 tile's reuse to stay off the
+// memory bound.)  In a 16 x 16 f32 block the entry (i, j) lives in lane
+// j + 16 (i / 4), accumulator element i mod 4; the f64 instruction
+// interleaves the rows the other way.  Full (not triangular) outputs, B not
+// transposed.
+template <bool TA>
+__global__ __launch_bounds__(256) void gemm_f32_kernel(const Prob* __restrict__ probs, int op, int step,
+                                                       GemmParams single) {
+  constexpr int TBM = F32_TILE, TBN = F32_TILE, TBK = 16;
+  // row pitch of 144 floats: the four K rows read by one MFMA operand fetch
+  // fall 16 banks apart
+  constexpr int LA = TBM + 16, LB = TBN + 16;
+  constexpr int AS = TBK * LA, BS = TBK * LB;
+  constexpr int WM = 64, WN = 64, FM = 4, FN = 4;
+  constexpr int EC = 64;   // epilogue columns per pass through LDS
+  static_assert(EC * (TBM + 1) <= 2 * (AS + BS), "epilogue chunk does not fit");
+  __shared__ float smem[2 * (AS + BS)];
+  int stp = step;
+  if (probs && op >= GOP_REF_P) {
+    const int st = *gbl(probs[blockIdx.z].refstate);
+    if (step >= 0 && st != 0 && st <= step) return;
+    if (step < 0) stp = st;
+  }
+  const GemmParams p = probs ? gemm_params(op, probs[blockIdx.z], stp) : single;
+  const BSE_GLOBAL float* __restrict__ Ag = gbl(p.Af);
+  const BSE_GLOBAL float* __restrict__ Bg = gbl(p.Bf);
+  const int tiles_m = (p.M + TBM - 1) / TBM, tiles_n = (p.N + TBN - 1) / TBN;
+  const long ntiles = (p.M <= 0 || p.N <= 0) ? 0 : (long)tiles_m * tiles_n;
+  long tile = xcd_remap(blockIdx.x, gridDim.x);
+  int slice = 0;
+  if (tile >= ntiles * p.splits) return;  // uniform: beyond this problem's tiles
+  if (p.splits > 1) {
+    slice = (int)(tile % p.splits);
+    tile /= p.splits;
+  }
+  int tm, tn;
+  grouped_tile(tile, tiles_m, tiles_n, tm, tn);
+  const int i0 = tm * TBM, j0 = tn * TBN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 1, wc = wave >> 1;
+  int kbeg = 0, kend = p.K;
+  if (p.splits > 1) {
+    const int s0 = slice * p.kchunk;
+    kbeg = max(kbeg, s0);
+    kend = min(kend, s0 + p.kchunk);
+  }
+
+  f4_t acc[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) acc[a][b] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
+
+  // staging: 8 elements of A and 8 of B per thread and K step, the lanes of
+  // each load running along the operand's contiguous direction
+  constexpr int E = TBM * TBK / 256;
+  float ra[E], rb[E];
+  auto load_a = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      int i, k;
+      if (!TA) {
+        i = i0 + (tid & 127);
+        k = k0 + (tid >> 7) + 2 * q;
+      } else {
+        k = k0 + (tid & 15);
+        i = i0 + (tid >> 4) + 16 * q;
+      }
+      ra[q] = (i < p.M && k < kend) ? (TA ? Ag[(long)k + (long)i * p.lda] : Ag[(long)i + (long)k * p.lda]) : 0.0f;
+    }
+  };
+  auto store_a = [&](int buf) {
+    float* sa = smem + buf * AS;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      if (!TA) sa[((tid >> 7) + 2 * q) * LA + (tid & 127)] = ra[q];
+      else sa[(tid & 15) * LA + (tid >> 4) + 16 * q] = ra[q];
+    }
+  };
+  auto load_b = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const int k = k0 + (tid & 15);
+      const int j = j0 + (tid >> 4) + 16 * q;
+      rb[q] = (j < p.N && k < kend) ? Bg[(long)k + (long)j * p.ldb] : 0.0f;
+    }
+  };
+  auto store_b = [&](int buf) {
+    float* sb = smem + 2 * AS + buf * BS;
+#pragma unroll
+    for (int q = 0; q < E; ++q) sb[(tid & 15) * LB + (tid >> 4) + 16 * q] = rb[q];
+  };
+
+  int buf = 0;
+  if (kbeg < kend) {
+    load_a(kbeg);
+    load_b(kbeg);
+    store_a(0);
+    store_b(0);
+  }
+  __syncthreads();
+  for (int k0 = kbeg; k0 < kend; k0 += TBK) {
+    const bool more = k0 + TBK < kend;
+    if (more) {
+      load_a(k0 + TBK);
+      load_b(k0 + TBK);
+    }
+    const float* a_s = smem + buf * AS;
+    const float* b_s = smem + 2 * AS + buf * BS;
+#pragma unroll
+    for (int ks = 0; ks < TBK; ks += 4) {
+      const int kr = ks + (lane >> 4);
+      float af[FM], bf[FN];
+#pragma unroll
+      for (int a = 0; a < FM; ++a) af[a] = a_s[kr * LA + wr * WM + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < FN; ++b) bf[b] = b_s[kr * LB + wc * WN + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a], bf[b], acc[a][b], 0, 0, 0);
+    }
+    if (more) {
+      store_a(buf ^ 1);
+      store_b(buf ^ 1);
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  // epilogue through LDS, EC columns (the two waves with wc = pass) at a time:
+  // Cs[(c - c0) * (TBM + 1) + r]
+  float* Cs = smem;
+  const bool split = p.splits > 1;
+#pragma unroll
+  for (int pass = 0; pass < TBN / EC; ++pass) {
+    if (pass > 0) __syncthreads();
+    if (wc == pass) {
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+          const int cl = b * 16 + (lane & 15);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int rl = wr * WM + a * 16 + 4 * (lane >> 4) + v;
+            Cs[cl * (TBM + 1) + rl] = acc[a][b][v];
+          }
+        }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < EC * TBM; idx += 256) {
+      const int rl = idx % TBM, cl = idx / TBM;
+      const int row = i0 + rl, col = j0 + pass * EC + cl;
+      if (row >= p.M || col >= p.N) continue;
+      const double val = (double)Cs[cl * (TBM + 1) + rl];
+      if (split) {
+        gbl(p.part)[(long)slice * p.M * p.N + (long)row + (long)col * p.M] = val;
+      } else if (p.Cf) {
+        BSE_GLOBAL float* c = gbl(p.Cf + (long)row + (long)col * p.ldc);
+        const double out = p.alpha * val;
+        *c = (float)((p.beta == 0.0) ? out : out + p.beta * (double)(*c));
+      } else {
+        BSE_GLOBAL double* c = gbl(p.C + (long)row + (long)col * p.ldc);
+        const double out = p.alpha * val;
+        if (p.beta == 0.0) *c = out;
+        else *c = out + p.beta * (p.Cin ? gbl(p.Cin)[(long)row + (long)col * p.ldc] : *c);
+      }
+    }
+  }
+}
+
 // C = alpha * sum_s part[s] + beta * C over the (uplo-restricted) M x N
 __global__ __launch_bounds__(256) void k_splitk_reduce(const Prob* __restrict__ probs, int op, int step,
                                                        GemmParams single) {
@@ -523,7 +709,7 @@ long cfg_workgroups(const GemmParams& g, int cfg) {
 int gemm_batched(hipStream_t s, const Batch& b, int nact, int op, int step) {
   if (nact <= 0) return 0;
   long maxm = 0, maxn = 0, maxk = 0;
-  bool any_split = false, any = false;
+  bool any_split = false, any = false, f32 = false;
   int ta = -1, tb = -1;
   for (int i = 0; i < nact; ++i) {
     const GemmParams g = gemm_params(op, b.host[i], step);
@@ -532,6 +718,7 @@ int gemm_batched(hipStream_t s, const Batch& b, int nact, int op, int step) {
     if (ta < 0) {
       ta = g.ta;
       tb = g.tb;
+      f32 = g.f32 != 0;
     }
     if (g.splits > 1) any_split = true;
     maxm = std::max(maxm, (long)g.M);
@@ -547,7 +734,20 @@ int gemm_batched(hipStream_t s, const Batch& b, int nact, int op, int step) {
   for (int i = 0; i < nact; ++i) maxwg = std::max(maxwg, cfg_workgroups(gemm_params(op, b.host[i], step), cfg));
   if (maxwg == 0) return 0;
   GemmParams dummy{};
-  launch(s, ta != 0, tb != 0, cfg, dim3((unsigned)maxwg, 1, (unsigned)nact), b.dev, op, step, dummy);
+  if (f32) {
+    // 128 x 128 tiles (gemm_params counts them for FP32 products)
+    long wg = 0;
+    for (int i = 0; i < nact; ++i) {
+      const GemmParams g = gemm_params(op, b.host[i], step);
+      if (g.M > 0 && g.N > 0) wg = std::max(wg, g.ntiles * g.splits);
+    }
+    const dim3 grid((unsigned)wg, 1, (unsigned)nact);
+    if (tb != 0) return set_error(BSE_EUNSUPPORTED, "gemm_batched: FP32 product with a transposed B");
+    if (ta == 0) gemm_f32_kernel<false><<<grid, 256, 0, s>>>(b.dev, op, step, dummy);
+    else gemm_f32_kernel<true><<<grid, 256, 0, s>>>(b.dev, op, step, dummy);
+  } else {
+    launch(s, ta != 0, tb != 0, cfg, dim3((unsigned)maxwg, 1, (unsigned)nact), b.dev, op, step, dummy);
+  }
   BSE_LAUNCHED();
   if (any_split) {
     k_splitk_reduce<<<dim3((unsigned)((maxm + 63) / 64), (unsigned)((maxn + 63) / 64), (unsigned)nact), 256, 0, s>>>(

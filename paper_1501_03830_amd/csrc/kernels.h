@@ -44,6 +44,12 @@ struct GemmParams {
   int splits, kchunk;
   double* part;  // split-K partial products [splits][M x N], ld M
   float* Cf;     // C in FP32 (when non-null C is unused), ld ldc
+  // FP32 products (f32 != 0): operands Af, Bf in FP32 (A, B unused), FP32
+  // matrix cores, C = alpha A B + beta Cin (Cin FP64, C when null) or Cf
+  int f32;
+  const float* Af;
+  const float* Bf;
+  const double* Cin;
 };
 
 // The products of the chain, as functions of (problem, step).
@@ -64,7 +70,7 @@ enum GemmOp {
   GOP_REF_P,       // refinement: rows ..n-1 of P = W Ub (basis Ub of sweep `step`)
   GOP_REF_S,       // refinement: S = Ub^T P (lower)
   GOP_REF_G,       // refinement: G = Ub^T Ub (lower)
-  GOP_REF_U,       // refinement: next basis = Ub (I + F)
+  GOP_REF_U,       // refinement: next basis = Ub + Ub F (the product in FP32)
   GOP_REF_PB,      // refinement: rows n.. of W Ub = W21 Ub[0:n] (W22 = 0)
   GOP_REF_PF,      // final eigenvalues: rows ..n-1 of W Ub, first n columns
   GOP_REF_PFB,     // final eigenvalues: rows n.. of W Ub, first n columns

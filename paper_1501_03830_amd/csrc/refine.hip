@@ -12,7 +12,7 @@
 // (P in two products: W22 = 0 leaves the bottom rows a product over n only),
 // the refined lambda_k of each pair from its 2 x 2 blocks,
 //     lambda_k = s_k / sqrt(det G_kk),  s_k = -S[n+k, k],
-// and the correction Ub <- Ub (I + F), F = R/2 + E with E skew.  E is zero on
+// and the correction Ub <- Ub + Ub F, F = R/2 + E with E skew.  E is zero on
 // the 2 x 2 diagonal blocks (the phase of z_k is free) and, for k != l,
 // solves the first-order Sylvester equation
 //     sigma_k E_kl - E_kl sigma_l = -S_kl - (R_kl sigma_l + sigma_k R_kl)/2,
@@ -97,8 +97,11 @@ __device__ inline double sym_at(const BSE_GLOBAL double* G, long ld, long i, lon
   return (i >= j) ? G[i + j * ld] : G[j + i * ld];
 }
 
-// I + F into R1 (P = W Ub is no longer needed), and per-tile maxima of the
-// correction and of the number of clamped blocks.
+// F and a copy of Ub, both rounded to FP32, into R1 (P = W Ub is no longer
+// needed): the basis update Ub + Ub F takes its correction product in FP32,
+// which perturbs Ub by about 1e-7 of the correction (far below the error the
+// sweep leaves).  Also per-tile maxima of the correction and the number of
+// clamped blocks.
 __global__ __launch_bounds__(256) void k_ref_F(const Prob* __restrict__ probs, int sweep) {
   __shared__ double red[2][4];
   const Prob& P = probs[blockIdx.z];
@@ -109,7 +112,9 @@ __global__ __launch_bounds__(256) void k_ref_F(const Prob* __restrict__ probs, i
   const BSE_GLOBAL double* __restrict__ S = gbl(P.R2);
   const BSE_GLOBAL double* __restrict__ G = gbl(P.R3);
   const BSE_CONST double* __restrict__ lam = ro(P.shift);
-  BSE_GLOBAL double* __restrict__ IF = gbl(P.R1);
+  BSE_GLOBAL float* __restrict__ F32 = gbl(reinterpret_cast<float*>(P.R1));
+  BSE_GLOBAL float* __restrict__ U32 = F32 + ld * ld;
+  const BSE_GLOBAL double* __restrict__ Ub = gbl(basis(P, sweep));
   const long r = (long)blockIdx.x * 64 + (threadIdx.x & 63);
   const long c0 = (long)blockIdx.y * 64 + (threadIdx.x >> 6) * 16;
   double cmax = 0.0, nclamp = 0.0;
@@ -157,7 +162,8 @@ __global__ __launch_bounds__(256) void k_ref_F(const Prob* __restrict__ probs, i
       }
       const double f = 0.5 * rrc + e;
       if (r != c) cmax = fmax(cmax, fabs(f));
-      IF[r + c * ld] = ((r == c) ? 1.0 : 0.0) + f;
+      F32[r + c * ld] = (float)f;
+      U32[r + c * ld] = (float)Ub[r + c * ld];
     }
   }
   // workgroup maxima / sums
