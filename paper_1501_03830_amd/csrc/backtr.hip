@@ -34,6 +34,9 @@ __global__ __launch_bounds__(256) void k_scatter_DV(const Prob* __restrict__ pro
   if (k0 >= N || j0 >= n) return;  // uniform
   const BSE_GLOBAL double* __restrict__ Vt = gbl(P.Vt);
   BSE_GLOBAL double* __restrict__ Z = gbl(P.Z);
+  // the mixed-precision path keeps this basis in FP32 until the refinement
+  const bool f32 = P.prec == BSE_PREC_FP32_REFINE;
+  BSE_GLOBAL float* __restrict__ Z32 = gbl(P.Z32);
   const long ldz = P.ld;
   for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
     const int jj = idx & 63, kk = idx >> 6;
@@ -48,13 +51,21 @@ __global__ __launch_bounds__(256) void k_scatter_DV(const Prob* __restrict__ pro
     const double v = t[kk][jj];
     const double sgn = ((k >> 1) & 1) ? -1.0 : 1.0;
     const bool even = (k & 1) == 0;
-    Z[(long)k + (long)j * ldz] = even ? sgn * v : 0.0;
-    Z[(long)k + (long)(n + j) * ldz] = even ? 0.0 : sgn * v;
+    const double re = even ? sgn * v : 0.0, im = even ? 0.0 : sgn * v;
+    if (f32) {
+      Z32[(long)k + (long)j * ldz] = (float)re;
+      Z32[(long)k + (long)(n + j) * ldz] = (float)im;
+    } else {
+      Z[(long)k + (long)j * ldz] = re;
+      Z[(long)k + (long)(n + j) * ldz] = im;
+    }
   }
 }
 
-// Explicit reflector block q: Vb[r, l] for rows r in [j0+1, N), j0 = 64 q:
-//   0 above row j0+l+1, 1 at row j0+l+1, W[r, j0+l] below.
+// Explicit reflector block q: Vb[r, l] for rows r in [j0+1, N), j0 = 128 q:
+//   0 above row j0+l+1, 1 at row j0+l+1, W[r, j0+l] below (and its FP32 copy
+//   Vb32 in the mixed-precision path, whose products with the FP32 basis run
+//   on the FP32 matrix cores).
 __global__ __launch_bounds__(256) void k_extract_V(const Prob* __restrict__ probs, int q) {
   const Prob& P = probs[blockIdx.z];
   const int N = P.N;
@@ -66,6 +77,7 @@ __global__ __launch_bounds__(256) void k_extract_V(const Prob* __restrict__ prob
   const BSE_GLOBAL float* __restrict__ W32 = gbl(P.W32);
   const bool f32 = P.prec == BSE_PREC_FP32_REFINE;   // reflectors stored in FP32
   BSE_GLOBAL double* __restrict__ Vb = gbl(P.Vb);
+  BSE_GLOBAL float* __restrict__ Vb32 = gbl(P.Vb32);
   const long ldw = P.ld, ldv = P.ld;
   const long r = (long)j0 + 1 + (long)blockIdx.x * 64 + (threadIdx.x & 63);
   if (r >= N) return;
@@ -76,6 +88,7 @@ __global__ __launch_bounds__(256) void k_extract_V(const Prob* __restrict__ prob
     else if (r == diag) v = 1.0;
     else v = f32 ? (double)W32[r + (long)(j0 + l) * ldw] : W[r + (long)(j0 + l) * ldw];
     Vb[r + (long)l * ldv] = v;
+    if (f32) Vb32[r + (long)l * ldv] = (float)v;
   }
 }
 
@@ -228,7 +241,8 @@ int to_f32_batched(hipStream_t s, const Batch& b) {
 
 size_t backtr_work_bytes(long N, long ld) {
   (void)N;
-  return ((size_t)ld * NBQ + (size_t)NBQ * NBQ + 2 * (size_t)NBQ * ld) * sizeof(double) + 4 * 256;
+  return ((size_t)ld * NBQ + (size_t)NBQ * NBQ + 2 * (size_t)NBQ * ld) * sizeof(double) +
+         2 * (size_t)NBQ * ld * sizeof(float) + 6 * 256;
 }
 
 void backtr_bind_work(char* base, long N, long ld, Prob* P) {
@@ -243,6 +257,8 @@ void backtr_bind_work(char* base, long N, long ld, Prob* P) {
   P->S = reinterpret_cast<double*>(take((size_t)NBQ * NBQ * sizeof(double)));
   P->W1 = reinterpret_cast<double*>(take((size_t)NBQ * ld * sizeof(double)));
   P->W2 = reinterpret_cast<double*>(take((size_t)NBQ * ld * sizeof(double)));
+  P->Vb32 = reinterpret_cast<float*>(take((size_t)ld * NBQ * sizeof(float)));
+  P->W2f = reinterpret_cast<float*>(take((size_t)NBQ * ld * sizeof(float)));
 }
 
 int apply_UD_batched(hipStream_t s, const Batch& b) {

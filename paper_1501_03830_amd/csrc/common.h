@@ -72,6 +72,8 @@ struct Prob {
   void* ctrl;
   // back-transformation work
   double *Vb, *S, *W1, *W2;
+  float *Vb32, *W2f;    // FP32 copies of Vb and W2 (mixed precision)
+  float* Z32;           // FP32 basis of the mixed-precision back-transformation (in R4)
   // mixed-precision path (prec == BSE_PREC_FP32_REFINE)
   int prec;
   float* W32;           // FP32 copy of W reduced to tridiagonal form (ld x ld)

@@ -124,6 +124,9 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
       } else if (op == GOP_APPLYU_W1) {  // W1 = V^T Z
         g.ta = 1; g.tb = 0; g.M = nbk; g.N = P.N; g.K = m;
         g.A = Vb; g.lda = ld; g.B = Zs; g.ldb = ld; g.C = P.W1; g.ldc = RB;
+        if (P.prec == BSE_PREC_FP32_REFINE) {   // FP32 basis, FP32 matrix cores
+          g.f32 = 1; g.Af = P.Vb32 + (j0 + 1); g.Bf = P.Z32 + (j0 + 1);
+        }
       } else if (op == GOP_APPLYU_WB) {  // W1[0:64] -= S[0:64, 64:] W2[64:]
         if (nbk <= NB) break;
         g.ta = 0; g.tb = 0; g.M = NB; g.N = P.N; g.K = nbk - NB; g.alpha = -1.0; g.beta = 1.0;
@@ -131,6 +134,9 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
       } else {                           // Z -= V W2
         g.ta = 0; g.tb = 0; g.M = m; g.N = P.N; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
         g.A = Vb; g.lda = ld; g.B = P.W2; g.ldb = RB; g.C = Zs; g.ldc = ld;
+        if (P.prec == BSE_PREC_FP32_REFINE) {
+          g.f32 = 1; g.Af = P.Vb32 + (j0 + 1); g.Bf = P.W2f; g.C = nullptr; g.Cf = P.Z32 + (j0 + 1);
+        }
       }
       break;
     }

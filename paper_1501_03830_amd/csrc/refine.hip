@@ -55,7 +55,8 @@ __device__ inline bool finished_before(const Prob& P, int sweep) {
 
 __device__ inline double* basis(const Prob& P, int sweep) { return (sweep & 1) ? P.R4 : P.Z; }
 
-// Z <- f Z over the N x N block (the basis of sweep 0)
+// Z <- f Z32 over the N x N block: the basis of sweep 0, from the FP32
+// basis the back-transformation left in R4
 __global__ __launch_bounds__(256) void k_ref_scale(const Prob* __restrict__ probs, double f) {
   const Prob& P = probs[blockIdx.z];
   const long N = P.N;
@@ -63,10 +64,11 @@ __global__ __launch_bounds__(256) void k_ref_scale(const Prob* __restrict__ prob
   const long c0 = (long)blockIdx.y * 64 + (threadIdx.x >> 6) * 16;
   if (r >= N) return;
   BSE_GLOBAL double* __restrict__ Z = gbl(P.Z);
+  const BSE_GLOBAL float* __restrict__ Z32 = gbl(P.Z32);
   for (int q = 0; q < 16; ++q) {
     const long c = c0 + q;
     if (c >= N) break;
-    Z[r + c * P.ld] *= f;
+    Z[r + c * P.ld] = f * (double)Z32[r + c * P.ld];
   }
 }
 

@@ -156,6 +156,7 @@ static void bind_problem(const Plan& p, char* base, Prob* P) {
     P->R2 = R + sq;
     P->R3 = R + 2 * sq;
     P->R4 = R + 3 * sq;
+    P->Z32 = reinterpret_cast<float*>(P->R4);
     P->refmax = reinterpret_cast<double*>(base + p.off_refmax);
     P->perm = reinterpret_cast<int*>(base + p.off_perm);
   }

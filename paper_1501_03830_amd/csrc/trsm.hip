@@ -159,6 +159,11 @@ __global__ __launch_bounds__(256) void k_wy_solve(const Prob* __restrict__ probs
   upper_solve64(Us, x);
 #pragma unroll
   for (int i = 0; i < NB; ++i) w2[i] = x[i];
+  if (P.prec == BSE_PREC_FP32_REFINE) {   // operand of the FP32 update of Z
+    BSE_GLOBAL float* __restrict__ w2f = gbl(P.W2f) + off + j * RB;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) w2f[i] = (float)x[i];
+  }
 }
 
 }  // namespace
