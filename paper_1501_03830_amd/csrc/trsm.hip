@@ -7,7 +7,8 @@
 //   * the forward substitution of the cluster Gram-Schmidt (Algorithm 3
 //     step 2): L_bb X = B for the 64 rows of V_+^T at block b;
 //   * the compact-WY application of the reflectors (Algorithm 3 step 3):
-//     W2 = T W1 with I - V T V^T = H_j0 ... H_j0+63.  For reflectors
+//     W2 = T W1 with I - V T V^T = H_j0 ... H_j0+127, one 64-row diagonal
+//     block of T^{-1} at a time.  For reflectors
 //     H = I - tau v v^T the factor built by LAPACK's larft recurrence is the
 //     inverse of diag(1/tau) + strict_upper(V^T V), so W2 solves
 //     (diag(1/tau) + strict_upper(V^T V)) W2 = W1 and T is never formed.
