@@ -232,18 +232,31 @@ int potrf_batched(hipStream_t s, const Batch& b, int sel, bool reset_info) {
   auto order = [sel](const Prob& P) { return sel == 0 ? P.N : P.n; };
   const int Nmax = order(b.host[0]);
   const int SOPS = sel == 0 ? GOP_POTRF_SYRK : GOP_GRAM_SYRK;
-  for (int k0 = 0; k0 < Nmax; k0 += TB) {
-    int nact = 0;  // problems with a diagonal block at k0
-    while (nact < b.count && order(b.host[nact]) > k0) ++nact;
+  const int POPS = sel == 0 ? GOP_POTRF_PANEL : GOP_GRAM_PANEL;
+  auto count_above = [&](int from, int k) {
+    int c = 0;
+    while (c < from && order(b.host[c]) > k) ++c;
+    return c;
+  };
+  // Panels of 128 columns, each factored as two 64-column halves: the
+  // diagonal block (k_potf2), the rows below it (trsm_rows_batched), and
+  // between the halves the product that brings the second half up to date.
+  // The trailing update then runs once per 128 columns (K = 128), which
+  // halves the passes over the trailing matrix.
+  for (int k0 = 0; k0 < Nmax; k0 += 2 * TB) {
+    const int nact = count_above(b.count, k0);   // problems with a diagonal block at k0
     k_potf2<<<dim3(1, 1, (unsigned)nact), 256, 0, s>>>(b.dev, sel, k0);
     BSE_LAUNCHED();
-    int nrest = 0;  // problems with rows below the block
-    while (nrest < nact && order(b.host[nrest]) > k0 + TB) ++nrest;
-    if (nrest > 0) {
-      // A21 <- A21 L_kk^{-T}, then the trailing update
-      BSE_TRY(trsm_rows_batched(s, b, nrest, sel, k0));
-      BSE_TRY(gemm_batched(s, b, nrest, SOPS, k0));
-    }
+    const int nrest = count_above(nact, k0 + TB);   // problems with rows below it
+    if (nrest == 0) continue;
+    BSE_TRY(trsm_rows_batched(s, b, nrest, sel, k0));
+    BSE_TRY(gemm_batched(s, b, nrest, POPS, k0));
+    k_potf2<<<dim3(1, 1, (unsigned)nrest), 256, 0, s>>>(b.dev, sel, k0 + TB);
+    BSE_LAUNCHED();
+    const int nrest2 = count_above(nrest, k0 + 2 * TB);
+    if (nrest2 == 0) continue;
+    BSE_TRY(trsm_rows_batched(s, b, nrest2, sel, k0 + TB));
+    BSE_TRY(gemm_batched(s, b, nrest2, SOPS, k0));
   }
   return 0;
 }

@@ -6,7 +6,8 @@
 // update, W = L^T J L, the skew rank-2k update of the tridiagonalisation,
 // the block-reflector applications, the products with L and the Gram
 // matrices of the reorthogonalisation.  Options:
-//   c_uplo  0: full C;  1: lower triangle incl. diagonal;  2: strictly lower
+//   c_uplo  0: full C;  1: lower triangle incl. diagonal;  2: strictly lower;
+//           3: lower triangle incl. diagonal of a tall C (all tiles visited)
 //           (only tiles touching the requested triangle are launched)
 //   a_tri   the stored A is lower triangular: the K loop skips its zeros
 //   b_tri   the stored B is lower triangular
@@ -47,16 +48,35 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
   const long ld = P.ld;
   const int NB = 64;
   switch (op) {
+    case GOP_POTRF_PANEL:
+    case GOP_GRAM_PANEL: {
+      // the 128-column panel at `step`, between its two 64-column halves:
+      // A[k0+64:, k0+64:k0+128] -= A21 A21[0:64]^T with A21 = A[k0+64:, k0:k0+64]
+      // (lower triangle of the diagonal block, all of the rows below it)
+      const bool gram = (op == GOP_GRAM_PANEL);
+      double* Mx = gram ? P.inv : P.L;
+      const int Nm = gram ? P.n : P.N;
+      const long ldm = gram ? (long)P.n : ld;
+      const int k0 = step;
+      const int rest = Nm - k0 - NB;
+      if (rest <= 0) break;
+      double* a21 = Mx + (k0 + NB) + (long)k0 * ldm;
+      g.ta = 0; g.tb = 1; g.M = rest; g.N = rest < NB ? rest : NB; g.K = NB; g.alpha = -1.0; g.beta = 1.0;
+      g.A = a21; g.lda = ldm; g.B = a21; g.ldb = ldm;
+      g.C = Mx + (k0 + NB) + (long)(k0 + NB) * ldm; g.ldc = ldm; g.c_uplo = 3;
+      break;
+    }
     case GOP_POTRF_SYRK:
     case GOP_GRAM_SYRK: {
-      // trailing update after the panel at column `step` (the panel itself is
-      // solved by trsm_rows_batched): A22 -= A21 A21^T, lower triangle
+      // trailing update after the 128-column panel at `step` (the panel itself
+      // is solved by k_potf2, trsm_rows_batched and the panel product):
+      // A22 -= A21 A21^T, lower triangle
       const bool gram = (op == GOP_GRAM_SYRK);
       double* Mx = gram ? P.inv : P.L;
       const int Nm = gram ? P.n : P.N;
       const long ldm = gram ? (long)P.n : ld;
       const int k0 = step;
-      const int nbk = (Nm - k0 < NB) ? Nm - k0 : NB;
+      const int nbk = (Nm - k0 < 2 * NB) ? Nm - k0 : 2 * NB;
       const int rest = Nm - k0 - nbk;
       if (nbk <= 0 || rest <= 0) break;  // M = N = 0: nothing to do
       double* a21 = Mx + (k0 + nbk) + (long)k0 * ldm;
@@ -187,7 +207,7 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
   g.tiles_m = (g.M + tbm - 1) / tbm;
   g.tiles_n = (g.N + tbn - 1) / tbn;
   g.ntiles = (g.M <= 0 || g.N <= 0) ? 0
-             : (g.c_uplo ? (long)g.tiles_m * (g.tiles_m + 1) / 2 : (long)g.tiles_m * g.tiles_n);
+             : ((g.c_uplo == 1 || g.c_uplo == 2) ? (long)g.tiles_m * (g.tiles_m + 1) / 2 : (long)g.tiles_m * g.tiles_n);
   g.splits = 1;
   g.kchunk = g.K;
   g.part = nullptr;
@@ -254,7 +274,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ 
     if (step >= 0 && st != 0 && st <= step) return;
     if (step < 0) stp = st;
   }
-  if (probs && (op == GOP_GRAM || op == GOP_GRAM_SYRK || op == GOP_GRAM_UPD) && *gbl(probs[blockIdx.z].reorth) == 0)
+  if (probs && (op == GOP_GRAM || op == GOP_GRAM_SYRK || op == GOP_GRAM_PANEL || op == GOP_GRAM_UPD) && *gbl(probs[blockIdx.z].reorth) == 0)
     return;   // no cluster Gram-Schmidt for this problem
   const GemmParams p = probs ? gemm_params(op, probs[blockIdx.z], stp) : single;
   const BSE_GLOBAL double* __restrict__ Ag = gbl(p.A);
@@ -262,7 +282,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ 
   // tiles of this configuration (the host sized the grid for it)
   const int tiles_m = (p.M + BM - 1) / BM, tiles_n = (p.N + BN - 1) / BN;
   const long ntiles = (p.M <= 0 || p.N <= 0) ? 0
-                      : (p.c_uplo ? (long)tiles_m * (tiles_m + 1) / 2 : (long)tiles_m * tiles_n);
+                      : ((p.c_uplo == 1 || p.c_uplo == 2) ? (long)tiles_m * (tiles_m + 1) / 2 : (long)tiles_m * tiles_n);
   // With a triangular operand the tiles' K ranges differ: a contiguous range
   // per XCD would give one XCD all the long tiles, so those products keep the
   // dispatch order (long and short tiles interleaved over the XCDs).
@@ -275,7 +295,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ 
     tile /= p.splits;
   }
   int tm, tn;
-  if (p.c_uplo) {
+  if (p.c_uplo == 1 || p.c_uplo == 2) {
     tri_index(tile, tm, tn);
   } else if (tri) {
     tm = (int)(tile % tiles_m);
@@ -447,7 +467,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ 
       const int rl = idx % BM, cl = c0 + idx / BM;
       const int row = i0 + rl, col = j0 + cl;
       if (row >= p.M || col >= p.N) continue;
-      if (p.c_uplo == 1 && row < col) continue;
+      if ((p.c_uplo == 1 || p.c_uplo == 3) && row < col) continue;
       if (p.c_uplo == 2 && row <= col) continue;
       const double val = Cs[(cl - c0) * (BM + 1) + rl];
       if (split) {
@@ -652,7 +672,7 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const Prob* __restrict__ 
     if (step >= 0 && st != 0 && st <= step) return;
     if (step < 0) stp = st;
   }
-  if (probs && (op == GOP_GRAM || op == GOP_GRAM_SYRK || op == GOP_GRAM_UPD) && *gbl(probs[blockIdx.z].reorth) == 0)
+  if (probs && (op == GOP_GRAM || op == GOP_GRAM_SYRK || op == GOP_GRAM_PANEL || op == GOP_GRAM_UPD) && *gbl(probs[blockIdx.z].reorth) == 0)
     return;   // no cluster Gram-Schmidt for this problem
   const GemmParams p = probs ? gemm_params(op, probs[blockIdx.z], stp) : single;
   if (p.splits <= 1) return;
@@ -662,7 +682,7 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const Prob* __restrict__ 
   for (int q = 0; q < 16; ++q) {
     const long c = c0 + q;
     if (c >= p.N) break;
-    if (p.c_uplo == 1 && r < c) continue;
+    if ((p.c_uplo == 1 || p.c_uplo == 3) && r < c) continue;
     if (p.c_uplo == 2 && r <= c) continue;
     double s = 0.0;
     const BSE_GLOBAL double* part = gbl(p.part);
@@ -707,7 +727,7 @@ void launch(hipStream_t s, bool ta, bool tb, int cfg, dim3 grid, const Prob* pro
 long cfg_workgroups(const GemmParams& g, int cfg) {
   if (g.M <= 0 || g.N <= 0) return 0;
   const long tm = (g.M + CFG_BM[cfg] - 1) / CFG_BM[cfg], tn = (g.N + CFG_BN[cfg] - 1) / CFG_BN[cfg];
-  return (g.c_uplo ? tm * (tm + 1) / 2 : tm * tn) * g.splits;
+  return ((g.c_uplo == 1 || g.c_uplo == 2) ? tm * (tm + 1) / 2 : tm * tn) * g.splits;
 }
 
 }  // namespace

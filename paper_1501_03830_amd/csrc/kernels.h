@@ -57,6 +57,8 @@ enum GemmOp {
   GOP_NONE = 0,
   GOP_POTRF_SYRK,  // Cholesky of M: trailing update after the panel at `step`
   GOP_GRAM_SYRK,   // Cholesky of the Gram matrix: trailing update
+  GOP_POTRF_PANEL, // Cholesky of M: second half of a 128-column panel
+  GOP_GRAM_PANEL,  // Cholesky of the Gram matrix: the same
   GOP_FORMW_C,     // L11^T L21
   GOP_FORMW_21,    // -L22^T L11
   GOP_SKTRD_R2K,   // skew rank-2k update after the panel starting at column `step`
