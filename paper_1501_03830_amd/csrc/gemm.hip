@@ -114,10 +114,19 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
       g.ta = 0; g.tb = 1; g.M = P.n; g.N = P.n; g.K = P.N;
       g.A = P.Vt; g.lda = P.n; g.B = P.Vt; g.ldb = P.n; g.C = P.inv; g.ldc = P.n; g.c_uplo = 1;
       break;
-    case GOP_GRAM_UPD: {  // rows below the block -= L21 (rows of the block)
+    case GOP_GRAM_UPD_PANEL: {  // rows b0+64..b0+127 -= L[.., b0:b0+64] (rows b0..b0+63)
+      const int b0 = step;
+      const int rest = P.n - b0 - NB;
+      if (rest <= 0) break;
+      g.ta = 0; g.tb = 0; g.M = rest < NB ? rest : NB; g.N = P.N; g.K = NB; g.alpha = -1.0; g.beta = 1.0;
+      g.A = P.inv + (b0 + NB) + (long)b0 * P.n; g.lda = P.n; g.B = P.Vt + b0; g.ldb = P.n;
+      g.C = P.Vt + b0 + NB; g.ldc = P.n;
+      break;
+    }
+    case GOP_GRAM_UPD: {  // rows below the 128-row block -= L21 (rows of the block)
       const int b0 = step;
       if (b0 >= P.n) break;
-      const int nbk = (P.n - b0 < NB) ? P.n - b0 : NB;
+      const int nbk = (P.n - b0 < 2 * NB) ? P.n - b0 : 2 * NB;
       const int rest = P.n - b0 - nbk;
       if (rest <= 0) break;
       g.ta = 0; g.tb = 0; g.M = rest; g.N = P.N; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
@@ -274,7 +283,8 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ 
     if (step >= 0 && st != 0 && st <= step) return;
     if (step < 0) stp = st;
   }
-  if (probs && (op == GOP_GRAM || op == GOP_GRAM_SYRK || op == GOP_GRAM_PANEL || op == GOP_GRAM_UPD) && *gbl(probs[blockIdx.z].reorth) == 0)
+  if (probs && (op == GOP_GRAM || op == GOP_GRAM_SYRK || op == GOP_GRAM_PANEL || op == GOP_GRAM_UPD ||
+                 op == GOP_GRAM_UPD_PANEL) && *gbl(probs[blockIdx.z].reorth) == 0)
     return;   // no cluster Gram-Schmidt for this problem
   const GemmParams p = probs ? gemm_params(op, probs[blockIdx.z], stp) : single;
   const BSE_GLOBAL double* __restrict__ Ag = gbl(p.A);
@@ -672,7 +682,8 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const Prob* __restrict__ 
     if (step >= 0 && st != 0 && st <= step) return;
     if (step < 0) stp = st;
   }
-  if (probs && (op == GOP_GRAM || op == GOP_GRAM_SYRK || op == GOP_GRAM_PANEL || op == GOP_GRAM_UPD) && *gbl(probs[blockIdx.z].reorth) == 0)
+  if (probs && (op == GOP_GRAM || op == GOP_GRAM_SYRK || op == GOP_GRAM_PANEL || op == GOP_GRAM_UPD ||
+                 op == GOP_GRAM_UPD_PANEL) && *gbl(probs[blockIdx.z].reorth) == 0)
     return;   // no cluster Gram-Schmidt for this problem
   const GemmParams p = probs ? gemm_params(op, probs[blockIdx.z], stp) : single;
   if (p.splits <= 1) return;

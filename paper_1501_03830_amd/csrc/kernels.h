@@ -63,7 +63,8 @@ enum GemmOp {
   GOP_FORMW_21,    // -L22^T L11
   GOP_SKTRD_R2K,   // skew rank-2k update after the panel starting at column `step`
   GOP_GRAM,        // Gram matrix of the inverse-iteration vectors
-  GOP_GRAM_UPD,    // forward substitution: rows below the block at `step`
+  GOP_GRAM_UPD,    // forward substitution: rows below the 128-row block at `step`
+  GOP_GRAM_UPD_PANEL,  // forward substitution: second half of the block at `step`
   GOP_APPLYU_S,    // V^T V of reflector block `step`
   GOP_APPLYU_W1,   // V^T Z
   GOP_APPLYU_WB,   // two-level solve with T^{-1}: top rows -= S_12 (bottom rows)

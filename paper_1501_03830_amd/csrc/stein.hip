@@ -482,13 +482,24 @@ int reorth_batched(hipStream_t s, const Batch& b, const int* dflags, int* hflags
     k_mask_gram<<<g2, 256, 0, s>>>(b.dev);
     BSE_LAUNCHED();
     BSE_TRY(potrf_batched(s, b, 1, pass == 0));
-    // Vt <- L^{-1} Vt  (blocked forward substitution: a direct solve with the
-    // diagonal block, then the update of the rows below)
-    for (int b0 = 0; b0 < n0; b0 += 64) {
-      int nact = 0;
-      while (nact < b.count && b.host[nact].n > b0) ++nact;
+    // Vt <- L^{-1} Vt: blocked forward substitution over 128-row blocks, each
+    // two direct solves with 64 x 64 diagonal blocks around the update of the
+    // block's second half, then one update (K = 128) of the rows below
+    auto count_above = [&](int from, int k) {
+      int c = 0;
+      while (c < from && b.host[c].n > k) ++c;
+      return c;
+    };
+    for (int b0 = 0; b0 < n0; b0 += 128) {
+      const int nact = count_above(b.count, b0);
       BSE_TRY(trsm_cols_batched(s, b, nact, b0));
-      BSE_TRY(gemm_batched(s, b, nact, GOP_GRAM_UPD, b0));
+      const int nrest = count_above(nact, b0 + 64);
+      if (nrest == 0) continue;
+      BSE_TRY(gemm_batched(s, b, nrest, GOP_GRAM_UPD_PANEL, b0));
+      BSE_TRY(trsm_cols_batched(s, b, nrest, b0 + 64));
+      const int nrest2 = count_above(nrest, b0 + 128);
+      if (nrest2 == 0) continue;
+      BSE_TRY(gemm_batched(s, b, nrest2, GOP_GRAM_UPD, b0));
     }
   }
   return 0;
