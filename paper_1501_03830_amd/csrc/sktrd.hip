@@ -107,27 +107,28 @@ __global__ __launch_bounds__(256) void sk_start(const Prob* __restrict__ probs, 
 }
 
 // Row tiles per strip workgroup of the matvec for a trailing matrix of nblk
-// row blocks.  Long strips amortise each workgroup's prologue (the reflector,
-// the first loads) and its reductions; short ones keep enough workgroups in
-// flight.  The steps were measured on a 16384-row trailing matrix swept down
-// to 512 rows.  The count depends on the problem alone, so a problem's
-// summation order -- and its result -- is the same whether it is solved alone
-// or inside a batch.
+// row blocks.  Long strips amortise each workgroup's prologue (the reflector
+// from the norm partials, the first loads) and its reductions; short ones
+// keep enough workgroups in flight.  The steps were measured inside the
+// n = 8192 reduction (an isolated sweep without the prologue preferred about
+// half these counts at mid sizes).  The count depends on the problem alone,
+// so a problem's summation order -- and its result -- is the same whether it
+// is solved alone or inside a batch.
 template <class WT>
 __host__ __device__ inline int symv_tiles(int nblk) {
   if (sizeof(WT) == 8) {
     if (nblk >= 224) return 16;
     if (nblk >= 160) return 12;
-    if (nblk >= 40) return 3;
-    if (nblk >= 24) return 2;
-    return 1;
+    if (nblk >= 80) return 8;
+    if (nblk >= 40) return 6;
+    if (nblk >= 24) return 3;
+    return 2;
   }
-  if (nblk >= 224) return 12;
-  if (nblk >= 160) return 8;
-  if (nblk >= 80) return 6;
-  if (nblk >= 40) return 3;
-  if (nblk >= 24) return 2;
-  return 1;
+  if (nblk >= 160) return 12;
+  if (nblk >= 80) return 8;
+  if (nblk >= 40) return 6;
+  if (nblk >= 24) return 3;
+  return 2;
 }
 
 // Sums NV per-lane values (NV a power of two, at most 64) over the 64 lanes
