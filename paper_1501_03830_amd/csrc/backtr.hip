@@ -9,7 +9,7 @@
 //     (-1)^((k-1)/2)); the real and imaginary parts of all n vectors are kept
 //     side by side as one real N x N matrix Z = [Re | Im], so that U and L
 //     are applied with real products only (remark 4's real/imaginary split).
-//   * U = H_0 ... H_{N-3} is applied from the left in blocks of 128
+//   * U = H_0 ... H_{N-3} is applied from the left in blocks of 256
 //     reflectors, last block first, each block as I - V T V^T (compact WY);
 //     T is applied by a triangular solve with its inverse
 //     diag(1/tau) + strict_upper(V^T V) (trsm.hip), never formed.
@@ -24,7 +24,7 @@ namespace bse {
 
 namespace {
 
-constexpr int NBQ = 128;  // reflectors per block
+constexpr int NBQ = APPLYU_RB;  // reflectors per block
 
 __global__ __launch_bounds__(256) void k_scatter_DV(const Prob* __restrict__ probs) {
   __shared__ double t[64][65];
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(256) void k_scatter_DV(const Prob* __restrict__ pro
   }
 }
 
-// Explicit reflector block q: Vb[r, l] for rows r in [j0+1, N), j0 = 128 q:
+// Explicit reflector block q: Vb[r, l] for rows r in [j0+1, N), j0 = 256 q:
 //   0 above row j0+l+1, 1 at row j0+l+1, W[r, j0+l] below (and its FP32 copy
 //   Vb32 in the mixed-precision path, whose products with the FP32 basis run
 //   on the FP32 matrix cores).
@@ -279,9 +279,10 @@ int apply_UD_batched(hipStream_t s, const Batch& b) {
     BSE_LAUNCHED();
     BSE_TRY(gemm_batched(s, b, nact, GOP_APPLYU_S, q));
     BSE_TRY(gemm_batched(s, b, nact, GOP_APPLYU_W1, q));
-    BSE_TRY(wy_solve_batched(s, b, nact, q, 1));
-    BSE_TRY(gemm_batched(s, b, nact, GOP_APPLYU_WB, q));
-    BSE_TRY(wy_solve_batched(s, b, nact, q, 0));
+    for (int h = NBQ / 64 - 1; h >= 0; --h) {
+      if (h < NBQ / 64 - 1) BSE_TRY(gemm_batched(s, b, nact, GOP_APPLYU_WB, 4 * q + h));
+      BSE_TRY(wy_solve_batched(s, b, nact, q, h));
+    }
     BSE_TRY(gemm_batched(s, b, nact, GOP_APPLYU_Z, q));
   }
   return 0;

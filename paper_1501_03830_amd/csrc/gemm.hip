@@ -138,10 +138,13 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
     case GOP_APPLYU_W1:
     case GOP_APPLYU_WB:
     case GOP_APPLYU_Z: {
-      // reflector block `step` of RB = 128 (H_j0 .. H_j0+nbk-1, j0 = 128 step)
-      constexpr int RB = 128;
+      // reflector block q of RB (H_j0 .. H_j0+nbk-1, j0 = RB q); the block
+      // solve's products carry their sub-block h in step = 4 q + h
+      constexpr int RB = APPLYU_RB;
+      const int q = (op == GOP_APPLYU_WB) ? step / 4 : step;
+      const int h = (op == GOP_APPLYU_WB) ? step % 4 : 0;
       const int nrefl = P.N - 2;
-      const int j0 = step * RB;
+      const int j0 = q * RB;
       if (nrefl <= 0 || j0 >= nrefl) break;
       const int nbk = (nrefl - j0 < RB) ? nrefl - j0 : RB;
       const int m = P.N - j0 - 1;
@@ -156,10 +159,11 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
         if (P.prec == BSE_PREC_FP32_REFINE) {   // FP32 basis, FP32 matrix cores
           g.f32 = 1; g.Af = P.Vb32 + (j0 + 1); g.Bf = P.Z32 + (j0 + 1);
         }
-      } else if (op == GOP_APPLYU_WB) {  // W1[0:64] -= S[0:64, 64:] W2[64:]
-        if (nbk <= NB) break;
-        g.ta = 0; g.tb = 0; g.M = NB; g.N = P.N; g.K = nbk - NB; g.alpha = -1.0; g.beta = 1.0;
-        g.A = P.S + (long)NB * RB; g.lda = RB; g.B = P.W2 + NB; g.ldb = RB; g.C = P.W1; g.ldc = RB;
+      } else if (op == GOP_APPLYU_WB) {  // W1[h] -= S[h, h+1:] W2[h+1:] (64-row sub-blocks)
+        const int r0 = NB * h, c0 = NB * (h + 1);
+        if (c0 >= nbk) break;
+        g.ta = 0; g.tb = 0; g.M = NB; g.N = P.N; g.K = nbk - c0; g.alpha = -1.0; g.beta = 1.0;
+        g.A = P.S + r0 + (long)c0 * RB; g.lda = RB; g.B = P.W2 + c0; g.ldb = RB; g.C = P.W1 + r0; g.ldc = RB;
       } else {                           // Z -= V W2
         g.ta = 0; g.tb = 0; g.M = m; g.N = P.N; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
         g.A = Vb; g.lda = ld; g.B = P.W2; g.ldb = RB; g.C = Zs; g.ldc = ld;

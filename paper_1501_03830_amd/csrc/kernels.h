@@ -52,6 +52,10 @@ struct GemmParams {
   const double* Cin;
 };
 
+// Reflectors per block of the back-transformation with U (four 64-row
+// sub-blocks of the compact-WY factor).
+constexpr int APPLYU_RB = 256;
+
 // The products of the chain, as functions of (problem, step).
 enum GemmOp {
   GOP_NONE = 0,
@@ -67,7 +71,7 @@ enum GemmOp {
   GOP_GRAM_UPD_PANEL,  // forward substitution: second half of the block at `step`
   GOP_APPLYU_S,    // V^T V of reflector block `step`
   GOP_APPLYU_W1,   // V^T Z
-  GOP_APPLYU_WB,   // two-level solve with T^{-1}: top rows -= S_12 (bottom rows)
+  GOP_APPLYU_WB,   // block solve with T^{-1}: sub-block h -= S_h,>h (later rows); step 4q + h
   GOP_APPLYU_Z,    // Z -= V (T V^T Z)
   GOP_APPLY_L,     // G = L Z
   GOP_REF_P,       // refinement: rows ..n-1 of P = W Ub (basis Ub of sweep `step`)
@@ -104,8 +108,9 @@ int trsm_rows_batched(hipStream_t s, const Batch& b, int nact, int sel, int k0);
 // rows b0 .. b0+63 of V_+^T <- L_bb^{-1} times themselves (Gram factor)
 int trsm_cols_batched(hipStream_t s, const Batch& b, int nact, int b0);
 // Rows 64h .. 64h+63 of P.W2 <- solve with the diagonal block h of
-// T^{-1} = diag(1/tau) + strict_upper(V^T V) of reflector block q (128
-// reflectors, S = V^T V in P.S); the right-hand side is the same rows of P.W1
+// T^{-1} = diag(1/tau) + strict_upper(V^T V) of reflector block q
+// (APPLYU_RB reflectors, S = V^T V in P.S); the right-hand side is the same
+// rows of P.W1
 int wy_solve_batched(hipStream_t s, const Batch& b, int nact, int q, int h);
 
 // ---------------------------------------------------------------- sktrd.hip

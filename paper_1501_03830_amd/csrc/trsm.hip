@@ -112,14 +112,15 @@ __global__ __launch_bounds__(256) void k_trsm_cols(const Prob* __restrict__ prob
     if (FULL || i < nbk) v[i] = x[i];
 }
 
-// Compact-WY factor of reflector block q (RB = 128 reflectors):
-// T^{-1} = diag(1/tau) + strict_upper(S), S = V^T V, is [A B; 0 C] in 64 x 64
-// blocks, so W2 = T W1 is the solve with C on the bottom rows (h = 1), then
-// the top rows minus B W2_bottom (a GEMM), then the solve with A (h = 0).  A
+// Compact-WY factor of reflector block q (RB = 256 reflectors):
+// T^{-1} = diag(1/tau) + strict_upper(S), S = V^T V, is block upper
+// triangular in 64 x 64 blocks, so W2 = T W1 is a block back substitution:
+// for h = 3 .. 0, rows h of W1 minus S[h, h+1:] W2[h+1:] (a GEMM, skipped
+// for h = 3), then the solve with the diagonal block (this kernel).  A
 // reflector with tau = 0 is the identity: its row of W2 is zero (its
 // right-hand side is set to zero and its row and column of the block are
 // left out).
-constexpr int RB = 128;
+constexpr int RB = APPLYU_RB;
 __global__ __launch_bounds__(256) void k_wy_solve(const Prob* __restrict__ probs, int q, int h) {
   __shared__ double Us[NB][NB + 1];
   __shared__ int zero[NB];
