@@ -249,10 +249,10 @@ __global__ __launch_bounds__(64) void k_invit(const Prob* __restrict__ probs) {
   for (int k = 0; k < N; ++k)
     Vt[(long)k * ldn + j] = hash_uniform(((unsigned long long)j << 32) ^ (unsigned long long)k ^ 0x5bd1e995ull);
 
-  // Both solves run in blocks of eight steps whose loads (the factors and
+  // Both solves run in blocks of 32 steps whose loads (the factors and
   // the entries of the iterate not yet overwritten) are issued before the
   // dependent arithmetic; the arithmetic is that of the step-by-step loops.
-  constexpr int UB = 8;
+  constexpr int UB = 32;
   for (int it = 0; it < 3; ++it) {
     // forward: apply the row interchanges and multipliers
     double cur = Vt[j];
@@ -333,7 +333,17 @@ __global__ __launch_bounds__(64) void k_invit(const Prob* __restrict__ probs) {
       x1 = x;
     }
     const double inv = 1.0 / sqrt(ss);
-    for (int k = 0; k < N; ++k) Vt[(long)k * ldn + j] *= inv;
+    // normalise, UB loads in flight at a time (a load-multiply-store chain per
+    // element waits out a full memory round trip each)
+    k = 0;
+    for (; k + UB <= N; k += UB) {
+      double vv[UB];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) vv[u] = Vt[(long)(k + u) * ldn + j];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) Vt[(long)(k + u) * ldn + j] = vv[u] * inv;
+    }
+    for (; k < N; ++k) Vt[(long)k * ldn + j] *= inv;
   }
 }
 
