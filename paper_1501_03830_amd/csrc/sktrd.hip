@@ -131,6 +131,22 @@ __host__ __device__ inline int symv_tiles(int nblk) {
   return 2;
 }
 
+// Strip workgroups of the matvec: strip Cl (Cl = 0 .. nblk-1) has
+// ceil((nblk - Cl) / T) chunks of T row tiles.  strip_prefix(Cl) counts the
+// chunks of the strips before Cl, from F(M) = sum_{m=1..M} ceil(m / T).
+__host__ __device__ inline long chunk_sum(long M, long T) {
+  const long q = M / T, r = M % T;
+  return T * q * (q + 1) / 2 + r * (q + 1);
+}
+__host__ __device__ inline long strip_prefix(int Cl, int nblk, int T) {
+  return chunk_sum(nblk, T) - chunk_sum(nblk - Cl, T);
+}
+// Workgroups of one problem's matvec launch: the duty workgroups, then every
+// (strip, chunk) of the trailing triangle, none empty.
+__host__ __device__ inline long symv_workgroups(int nblk, int T) {
+  return 4L * ((nblk + DUTY_BLK - 1) / DUTY_BLK) + chunk_sum(nblk, T);
+}
+
 // Sums NV per-lane values (NV a power of two, at most 64) over the 64 lanes
 // of a wavefront.  Each exchange hands half of the remaining values to the
 // partner lane and keeps the other half, so it takes NV - 1 + log2(64 / NV)
@@ -165,16 +181,19 @@ __device__ inline double vval(Ptr W, long ld, int j, int s, int N, double scale,
 
 // y = S v over the strictly lower triangle of the trailing matrix.
 //
-// blockIdx.y = k + 1 >= 1: workgroup (Cl, k) streams the 64-column strip Cl over
-//   row tiles Cl + k*T .. Cl + k*T + T - 1.  Lane = row inside a tile, wave w
-//   owns columns 16w..16w+15 of the strip, so every load instruction reads
-//   64 consecutive doubles of one column.  Row sums (S v) of each tile go to
-//   Yrow[rl][Cl] (written once per workgroup); column sums
-//   (-S^T v) accumulate in registers over the tiles and are reduced across
-//   the wave once (wave_sum_many), into Ycol[Cl][k].
-// blockIdx.y == 0 (dispatched first): workgroups (d, g) store v_i for row
+// The launch is one row of workgroups per problem (blockIdx.z), with no empty
+// ones (a batch of small problems otherwise spends its time dispatching
+// workgroups that only exit):
+// blockIdx.x < nduty (dispatched first): workgroups (d, g) store v_i for row
 //   blocks d*16 .. d*16+15 and their share of the panel dot products V^T v,
 //   P^T v (summed by the update kernel).
+// the rest: workgroup (Cl, k), in strip-major order, streams the 64-column
+//   strip Cl over row tiles Cl + k*T .. Cl + k*T + T - 1.  Lane = row inside
+//   a tile, wave w owns columns 16w..16w+15 of the strip, so every load
+//   instruction reads 64 consecutive doubles of one column.  Row sums (S v)
+//   of each tile go to Yrow[rl][Cl] (written once per workgroup); column
+//   sums (-S^T v) accumulate in registers over the tiles and are reduced
+//   across the wave once (wave_sum_many), into Ycol[Cl][k].
 template <class WT>
 __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, int j, int i) {
   __shared__ double rsum[TMAX][4][TS];   // per-wave row sums of every tile
@@ -214,19 +233,20 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
     ss = wave_sum(ss);   // the same value in every lane
     double beta, tau, sc;
     larfg(ctrl->x0, sqrt(ss), beta, tau, sc);
-    if (i > 0 && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    if (i > 0 && blockIdx.x == 0 && threadIdx.x == 0) {   // the first duty workgroup
       gbl(P.alpha)[j] = -beta;
       gbl(P.tau)[j] = tau;
     }
     return uniform_double(i == 0 ? ctrl->scale : sc);
   };
 
-  if (blockIdx.y == 0) {
+  const int nduty = 4 * ((nblk + DUTY_BLK - 1) / DUTY_BLK);
+  if ((int)blockIdx.x < nduty) {
     // duty workgroup (d, g) covers row blocks d*DUTY_BLK .. +DUTY_BLK-1 and the
     // panel columns 32g .. 32g+31: group 0 stores v_i, every group writes its
     // partial dot products of those panel columns with v_i; the update kernel
     // adds the (at most 16) partials of each column.
-    const int d = blockIdx.x >> 2, g = blockIdx.x & 3;
+    const int d = (int)blockIdx.x >> 2, g = (int)blockIdx.x & 3;
     const int nd = (nblk + DUTY_BLK - 1) / DUTY_BLK;
     if (d >= nd) return;              // uniform
     if (g > 0 && 32 * g >= 2 * i) return;
@@ -260,9 +280,20 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
     return;
   }
 
-  const int Cl = blockIdx.x, k = blockIdx.y - 1;
+  // (strip, chunk) of this workgroup: the largest Cl with strip_prefix(Cl) <= w
+  const long w = (long)blockIdx.x - nduty;
+  if (w >= chunk_sum(nblk, T)) return;  // uniform: beyond this problem's workgroups
+  int Cl = 0;
+  {
+    int hi = nblk - 1;
+    while (Cl < hi) {
+      const int mid = (Cl + hi + 1) >> 1;
+      if (strip_prefix(mid, nblk, T) <= w) Cl = mid;
+      else hi = mid - 1;
+    }
+  }
+  const int k = (int)(w - strip_prefix(Cl, nblk, T));
   const int rl0 = Cl + k * T;
-  if (Cl >= nblk || rl0 >= nblk) return;  // uniform: empty corner of the launch grid
   const int rl1 = min(nblk, rl0 + T);
   const long C0 = (long)(R0 + Cl) * TS;
   // wave-uniform values live in scalar registers: the column base pointer and
@@ -576,18 +607,15 @@ static int sktrd_run(hipStream_t s, const Batch& b, KernelTimer* timer) {
       const int sidx = j + 1;
       const int R0 = sidx / TS;
       const int nblk0 = (N0 - 1) / TS - R0 + 1;
-      // strip chunks: the largest count over the active problems
-      int nchunk0 = 1;
+      // workgroups: the largest count over the active problems
+      long gx = 1;
       for (int q = 0; q < nact; ++q) {
         const int nbq = (b.host[q].N - 1) / TS - R0 + 1;
-        const int T = symv_tiles<WT>(nbq);
-        nchunk0 = std::max(nchunk0, (nbq + T - 1) / T);
+        gx = std::max(gx, symv_workgroups(nbq, symv_tiles<WT>(nbq)));
       }
       const bool timed = timer && timer->used + 2 <= timer->cap;
       if (timed) BSE_HIP(hipEventRecord(timer->ev[timer->used], s));
-      const int nduty = 4 * ((nblk0 + DUTY_BLK - 1) / DUTY_BLK);
-      const unsigned gx = (unsigned)(nblk0 > nduty ? nblk0 : nduty);
-      sk_symv<WT><<<dim3(gx, (unsigned)(nchunk0 + 1), (unsigned)nact), 256, 0, s>>>(b.dev, j, i);
+      sk_symv<WT><<<dim3((unsigned)gx, 1, (unsigned)nact), 256, 0, s>>>(b.dev, j, i);
       BSE_LAUNCHED();
       if (timed) {
         BSE_HIP(hipEventRecord(timer->ev[timer->used + 1], s));
