@@ -147,6 +147,24 @@ __host__ __device__ inline long symv_workgroups(int nblk, int T) {
   return 4L * ((nblk + DUTY_BLK - 1) / DUTY_BLK) + chunk_sum(nblk, T);
 }
 
+// Problem and workgroup index of this workgroup.  A single problem (or a
+// launch sized per problem) has its problem in blockIdx.z; a batch launch puts
+// all problems' workgroups back to back, problem p from wgpre[2p + which] on
+// (the prefixes of the per-problem counts, written by k_plan just before).
+__device__ inline int locate_problem(const int* __restrict__ wgpre, int which, int nact, long& wid) {
+  wid = blockIdx.x;
+  if (wgpre == nullptr) return blockIdx.z;
+  const BSE_CONST int* __restrict__ pre = ro(wgpre);
+  int lo = 0, hi = nact - 1;
+  while (lo < hi) {   // the last problem whose first workgroup is at or before this one
+    const int mid = (lo + hi + 1) >> 1;
+    if (pre[2 * mid + which] <= (long)blockIdx.x) lo = mid;
+    else hi = mid - 1;
+  }
+  wid = (long)blockIdx.x - pre[2 * lo + which];
+  return lo;
+}
+
 // Sums NV per-lane values (NV a power of two, at most 64) over the 64 lanes
 // of a wavefront.  Each exchange hands half of the remaining values to the
 // partner lane and keeps the other half, so it takes NV - 1 + log2(64 / NV)
@@ -195,9 +213,11 @@ __device__ inline double vval(Ptr W, long ld, int j, int s, int N, double scale,
 //   sums (-S^T v) accumulate in registers over the tiles and are reduced
 //   across the wave once (wave_sum_many), into Ycol[Cl][k].
 template <class WT>
-__global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, int j, int i) {
+__global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, int j, int i,
+                                               const int* __restrict__ wgpre, int nact) {
   __shared__ double rsum[TMAX][4][TS];   // per-wave row sums of every tile
-  const Prob& P = probs[blockIdx.z];
+  long wid;
+  const Prob& P = probs[locate_problem(wgpre, 0, nact, wid)];
   const int N = P.N;
   if (j >= N - 2) return;  // uniform: this problem is already reduced
   const int s = j + 1;
@@ -233,7 +253,7 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
     ss = wave_sum(ss);   // the same value in every lane
     double beta, tau, sc;
     larfg(ctrl->x0, sqrt(ss), beta, tau, sc);
-    if (i > 0 && blockIdx.x == 0 && threadIdx.x == 0) {   // the first duty workgroup
+    if (i > 0 && wid == 0 && threadIdx.x == 0) {   // the first duty workgroup
       gbl(P.alpha)[j] = -beta;
       gbl(P.tau)[j] = tau;
     }
@@ -241,12 +261,12 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
   };
 
   const int nduty = 4 * ((nblk + DUTY_BLK - 1) / DUTY_BLK);
-  if ((int)blockIdx.x < nduty) {
+  if (wid < nduty) {
     // duty workgroup (d, g) covers row blocks d*DUTY_BLK .. +DUTY_BLK-1 and the
     // panel columns 32g .. 32g+31: group 0 stores v_i, every group writes its
     // partial dot products of those panel columns with v_i; the update kernel
     // adds the (at most 16) partials of each column.
-    const int d = (int)blockIdx.x >> 2, g = (int)blockIdx.x & 3;
+    const int d = (int)wid >> 2, g = (int)wid & 3;
     const int nd = (nblk + DUTY_BLK - 1) / DUTY_BLK;
     if (d >= nd) return;              // uniform
     if (g > 0 && 32 * g >= 2 * i) return;
@@ -281,7 +301,7 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
   }
 
   // (strip, chunk) of this workgroup: the largest Cl with strip_prefix(Cl) <= w
-  const long w = (long)blockIdx.x - nduty;
+  const long w = wid - nduty;
   if (w >= chunk_sum(nblk, T)) return;  // uniform: beyond this problem's workgroups
   int Cl = 0;
   {
@@ -380,7 +400,8 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
 // thread has only a few loads to wait for.
 constexpr int UW = 16;   // wavefronts per update workgroup
 template <class WT>
-__global__ __launch_bounds__(64 * UW) void sk_update(const Prob* __restrict__ probs, int j, int i) {
+__global__ __launch_bounds__(64 * UW) void sk_update(const Prob* __restrict__ probs, int j, int i,
+                                                     const int* __restrict__ wgpre, int nact) {
   __shared__ double cs[2 * NBMAX];
   __shared__ double ys_row[2 * NBMAX];   // Y1 row s (v_l[s], p_l[s])
   __shared__ double red[UW][TS];
@@ -388,13 +409,14 @@ __global__ __launch_bounds__(64 * UW) void sk_update(const Prob* __restrict__ pr
   __shared__ double pr[TS];
   __shared__ double red4[UW];
   __shared__ double sval_s;
-  const Prob& P = probs[blockIdx.z];
+  long wid;
+  const Prob& P = probs[locate_problem(wgpre, 1, nact, wid)];
   const int N = P.N;
   if (j >= N - 2) return;  // uniform
   const int s = j + 1;
   const int R0 = s / TS;
   const int nblk = (N - 1) / TS - R0 + 1;
-  const int b = blockIdx.x;
+  const int b = (int)wid;
   if (b >= nblk) return;  // uniform: beyond this problem's row blocks
   const int T = symv_tiles<WT>(nblk);
   const int nchunk = (nblk + T - 1) / T;
@@ -559,6 +581,56 @@ __global__ __launch_bounds__(64 * UW) void sk_update(const Prob* __restrict__ pr
   if (tid == 0) normpart[b] = nrm;
 }
 
+// Workgroup prefixes of a batch launch at column j: wgpre[2p] (matvec) and
+// wgpre[2p + 1] (update) count the workgroups of the active problems before p.
+template <class WT>
+__global__ __launch_bounds__(1024) void k_plan(const Prob* __restrict__ probs, int nact, int j,
+                                               int* __restrict__ wgpre) {
+  __shared__ int ssum[1024], usum[1024];
+  const int tid = threadIdx.x;
+  const int per = (nact + 1023) / 1024;
+  const int p0 = min(nact, tid * per), p1 = min(nact, p0 + per);
+  auto counts = [&](int p, int& cs, int& cu) {
+    const int N = probs[p].N;
+    const int s = j + 1;
+    const int nblk = (N - 1) / TS - s / TS + 1;
+    cs = (int)symv_workgroups(nblk, symv_tiles<WT>(nblk));
+    cu = nblk;
+  };
+  int ts = 0, tu = 0;
+  for (int p = p0; p < p1; ++p) {
+    int cs, cu;
+    counts(p, cs, cu);
+    ts += cs;
+    tu += cu;
+  }
+  ssum[tid] = ts;
+  usum[tid] = tu;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {   // inclusive scan
+    const int a = tid >= off ? ssum[tid - off] : 0;
+    const int c = tid >= off ? usum[tid - off] : 0;
+    __syncthreads();
+    ssum[tid] += a;
+    usum[tid] += c;
+    __syncthreads();
+  }
+  int es = ssum[tid] - ts, eu = usum[tid] - tu;
+  BSE_GLOBAL int* __restrict__ pre = gbl(wgpre);
+  for (int p = p0; p < p1; ++p) {
+    int cs, cu;
+    counts(p, cs, cu);
+    pre[2 * p] = es;
+    pre[2 * p + 1] = eu;
+    es += cs;
+    eu += cu;
+  }
+  if (tid == 1023) {
+    pre[2 * nact] = ssum[1023];
+    pre[2 * nact + 1] = usum[1023];
+  }
+}
+
 }  // namespace
 
 size_t sktrd_work_bytes(long N, long ld) {
@@ -607,15 +679,25 @@ static int sktrd_run(hipStream_t s, const Batch& b, KernelTimer* timer) {
       const int sidx = j + 1;
       const int R0 = sidx / TS;
       const int nblk0 = (N0 - 1) / TS - R0 + 1;
-      // workgroups: the largest count over the active problems
-      long gx = 1;
+      // workgroups: a batch runs every problem's back to back (prefixes from
+      // k_plan), a single problem its own row
+      const bool packed = nact > 1 && b.wgpre != nullptr;
+      long gx = 0, gu = 0;
       for (int q = 0; q < nact; ++q) {
         const int nbq = (b.host[q].N - 1) / TS - R0 + 1;
-        gx = std::max(gx, symv_workgroups(nbq, symv_tiles<WT>(nbq)));
+        gx += symv_workgroups(nbq, symv_tiles<WT>(nbq));
+        gu += nbq;
       }
+      if (packed) {
+        k_plan<WT><<<1, 1024, 0, s>>>(b.dev, nact, j, b.wgpre);
+        BSE_LAUNCHED();
+      }
+      const int* pre = packed ? b.wgpre : nullptr;
+      const dim3 gs = packed ? dim3((unsigned)gx, 1, 1) : dim3((unsigned)gx, 1, (unsigned)nact);
+      const dim3 gup = packed ? dim3((unsigned)gu, 1, 1) : dim3((unsigned)nblk0, 1, (unsigned)nact);
       const bool timed = timer && timer->used + 2 <= timer->cap;
       if (timed) BSE_HIP(hipEventRecord(timer->ev[timer->used], s));
-      sk_symv<WT><<<dim3((unsigned)gx, 1, (unsigned)nact), 256, 0, s>>>(b.dev, j, i);
+      sk_symv<WT><<<gs, 256, 0, s>>>(b.dev, j, i, pre, nact);
       BSE_LAUNCHED();
       if (timed) {
         BSE_HIP(hipEventRecord(timer->ev[timer->used + 1], s));
@@ -625,7 +707,7 @@ static int sktrd_run(hipStream_t s, const Batch& b, KernelTimer* timer) {
           timer->bytes += sizeof(WT) * m * (m - 1.0) * 0.5;
         }
       }
-      sk_update<WT><<<dim3((unsigned)nblk0, 1, (unsigned)nact), 64 * UW, 0, s>>>(b.dev, j, i);
+      sk_update<WT><<<gup, 64 * UW, 0, s>>>(b.dev, j, i, pre, nact);
       BSE_LAUNCHED();
     }
     BSE_TRY(gemm_batched(s, b, nstart, GOP_SKTRD_R2K, k0));

@@ -124,7 +124,8 @@ static size_t hdr_state_off(int count) { return hdr_info_off(count) + (size_t)ro
 static size_t hdr_reorth_off(int count) { return hdr_state_off(count) + (size_t)round_up((long)(count * sizeof(int)), 256); }
 static size_t hdr_ref_off(int count) { return hdr_reorth_off(count) + (size_t)round_up((long)(count * sizeof(int)), 256); }
 static size_t hdr_gdef_off(int count) { return hdr_ref_off(count) + (size_t)round_up((long)(count * 2 * sizeof(double)), 256); }
-size_t header_bytes(int count) { return hdr_gdef_off(count) + (size_t)round_up((long)(count * sizeof(double)), 256); }
+static size_t hdr_wgpre_off(int count) { return hdr_gdef_off(count) + (size_t)round_up((long)(count * sizeof(double)), 256); }
+size_t header_bytes(int count) { return hdr_wgpre_off(count) + (size_t)round_up((long)(2 * (count + 1) * sizeof(int)), 256); }
 
 // Workspace pointers of one problem.
 static void bind_problem(const Plan& p, char* base, Prob* P) {
@@ -248,6 +249,7 @@ int setup_batch(Lane* L, int count, const long* Ns, int prec, char* header, char
   S->dstate = reinterpret_cast<int*>(header + hdr_state_off(count));
   S->dreorth = reinterpret_cast<int*>(header + hdr_reorth_off(count));
   S->dref = reinterpret_cast<double*>(header + hdr_ref_off(count));
+  S->dwgpre = reinterpret_cast<int*>(header + hdr_wgpre_off(count));
   S->total = header_bytes(count);
   for (int i = 0; i < count; ++i) {
     const Plan plan = make_plan(Ns[i], prec);
@@ -309,6 +311,7 @@ int run_chain(Lane* L, const Setup& S, int count, bool vectors, bse_report* rep)
   b.count = count;
   b.host = L->hprobs;
   b.dev = S.dprobs;
+  b.wgpre = S.dwgpre;
   const int prec = count > 0 ? L->hprobs[0].prec : BSE_PREC_FP64;
   const bool mixed = prec == BSE_PREC_FP32_REFINE;
   int ev = 0;
@@ -427,6 +430,7 @@ static Batch single_batch(bse_ctx* ctx, const Setup& S) {
   b.count = 1;
   b.host = ctx->lane.hprobs;
   b.dev = S.dprobs;
+  b.wgpre = S.dwgpre;
   return b;
 }
 
