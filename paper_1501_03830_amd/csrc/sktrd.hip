@@ -154,15 +154,23 @@ __host__ __device__ inline long symv_workgroups(int nblk, int T) {
 __device__ inline int locate_problem(const int* __restrict__ wgpre, int which, int nact, long& wid) {
   wid = blockIdx.x;
   if (wgpre == nullptr) return blockIdx.z;
-  const BSE_CONST int* __restrict__ pre = ro(wgpre);
-  int lo = 0, hi = nact - 1;
-  while (lo < hi) {   // the last problem whose first workgroup is at or before this one
-    const int mid = (lo + hi + 1) >> 1;
-    if (pre[2 * mid + which] <= (long)blockIdx.x) lo = mid;
-    else hi = mid - 1;
+  // count the problems whose first workgroup is at or before this one, 64
+  // prefixes per vector load and ballot (one round trip for up to 64
+  // problems, instead of a chain of dependent loads)
+  const BSE_GLOBAL int* __restrict__ pre = gbl(wgpre);
+  const int lane = threadIdx.x & 63;
+  const long x = blockIdx.x;
+  int cnt = 0;
+  for (int base = 0; base < nact; base += 64) {
+    const int q = base + lane;
+    const bool le = q < nact && pre[2 * q + which] <= x;
+    const int c = __popcll(__ballot(le));
+    cnt += c;
+    if (c < 64) break;
   }
-  wid = (long)blockIdx.x - pre[2 * lo + which];
-  return lo;
+  const int p = cnt - 1;
+  wid = x - pre[2 * p + which];
+  return p;
 }
 
 // Sums NV per-lane values (NV a power of two, at most 64) over the 64 lanes
@@ -437,20 +445,25 @@ __global__ __launch_bounds__(64 * UW) void sk_update(const Prob* __restrict__ pr
   const int tid = threadIdx.x;
   const int t = tid & 63, part = tid >> 6;
   const double tau = tau_arr[j];   // written by sk_start or by this column's matvec
-  // Every load of the kernel is issued here, before anything waits: the
-  // duty workgroups' partial dot products (lanes tid < 2i), Y1 at row s,
-  // this row's panel entries (v_l, p_l for l = part, part + UW, ...), v_i,
-  // W[r, s], the partials of S v at row s (wave 1) and the b+1 row parts and
-  // nch column parts of this row block's S v.
-  const int nd = (nblk + DUTY_BLK - 1) / DUTY_BLK;   // 16 partials per 16384 rows
-  const bool dot_lane = tid < 2 * i;
-  constexpr int ND = 8;
-  double pc[ND];
+  if (tid < 2 * i) {
+    // c[l] = sum of the symv duty workgroups' partial dot products
+    const int nd = (nblk + DUTY_BLK - 1) / DUTY_BLK;   // 16 partials per 16384 rows
+    double c = 0.0;
+    for (int d0 = 0; d0 < nd; d0 += 16) {
+      double pc[16];
 #pragma unroll
-  for (int dd = 0; dd < ND; ++dd) pc[dd] = (dot_lane && dd < nd) ? dotpart[(long)tid * dstride + dd] : 0.0;
-  const double ysr = dot_lane ? Y1[s + (long)tid * ldy] : 0.0;
+      for (int dd = 0; dd < 16; ++dd) pc[dd] = (d0 + dd < nd) ? dotpart[(long)tid * dstride + d0 + dd] : 0.0;
+#pragma unroll
+      for (int dd = 0; dd < 16; ++dd) c += pc[dd];
+    }
+    cs[tid] = c;
+    ys_row[tid] = Y1[s + (long)tid * ldy];
+  }
   const long r = (long)(R0 + b) * TS + t;
   const bool inrange = r >= s && r < N;
+  // this row's panel entries (v_l, p_l for l = part, part + UW, ...), v_i, and
+  // W[r, s]: loaded once, before anything waits, and used by both
+  // corrections below
   constexpr int NQ = NBMAX / UW;
   double yv[NQ], yp[NQ];
 #pragma unroll
@@ -463,6 +476,8 @@ __global__ __launch_bounds__(64 * UW) void sk_update(const Prob* __restrict__ pr
   const double vi = inrange ? Y1[r + (long)(2 * i) * ldy] : 0.0;
   const double wrs = (r >= s + 1 && r < N) ? (double)W[r + (long)s * ld] : 0.0;
   const bool next_col = (i + 1 < nbp) && (s <= N - 2);
+  // partial sums of S v at row s (first row of block 0), needed by every
+  // block for the next column: wave 1 starts loading them now
   double srow = 0.0;
   if (next_col && part == 1) {
     const long os = s - (long)R0 * TS;
@@ -470,41 +485,31 @@ __global__ __launch_bounds__(64 * UW) void sk_update(const Prob* __restrict__ pr
     srow = (t == 0) ? Yrow[os] : 0.0;
     for (int c = t; c < nch0; c += 64) srow += Ycol[(long)c * TS + os];
   }
-  // row parts of strips c <= b (contiguous in Yrow[b][c][64]), column parts
-  // of the chunks of strip b
-  constexpr int NR = 8, NC = 2;   // per thread: all of them up to nblk = 128
-  const auto yr = Yrow + (long)b * nblk * TS + t;
-  const int nch = (nblk - b + T - 1) / T;
-  const auto yc = Ycol + (long)b * nchunk * TS + t;
-  double yl[NR], ycl[NC];
-#pragma unroll
-  for (int q = 0; q < NR; ++q) {
-    const int c = part + UW * q;
-    yl[q] = (c <= b) ? yr[(long)c * TS] : 0.0;
-  }
-#pragma unroll
-  for (int q = 0; q < NC; ++q) {
-    const int c = part + UW * q;
-    ycl[q] = (c < nch) ? yc[(long)c * TS] : 0.0;
-  }
-  if (dot_lane) {
-    // c[l] = sum of the duty workgroups' partial dot products
-    double c = 0.0;
-#pragma unroll
-    for (int dd = 0; dd < ND; ++dd) c += pc[dd];
-    for (int dd = ND; dd < nd; ++dd) c += dotpart[(long)tid * dstride + dd];
-    cs[tid] = c;
-    ys_row[tid] = ysr;
-  }
   {
-    double acc = 0.0;
+    // partial sums of this row block: b+1 row parts (one per strip c <= b,
+    // contiguous in Yrow[b][c][64]) and nch column parts (one per chunk of
+    // strip b); loads are issued in batches of 8
+    double acc[8];
 #pragma unroll
-    for (int q = 0; q < NR; ++q) acc += yl[q];
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    const auto yr = Yrow + (long)b * nblk * TS + t;
+    for (int c0 = part; c0 <= b; c0 += 8 * UW) {
 #pragma unroll
-    for (int q = 0; q < NC; ++q) acc += ycl[q];
-    for (int c = part + UW * NR; c <= b; c += UW) acc += yr[(long)c * TS];
-    for (int c = part + UW * NC; c < nch; c += UW) acc += yc[(long)c * TS];
-    red[part][t] = acc;
+      for (int q = 0; q < 8; ++q) {
+        const int c = c0 + UW * q;
+        if (c <= b) acc[q] += yr[(long)c * TS];
+      }
+    }
+    const int nch = (nblk - b + T - 1) / T;
+    const auto yc = Ycol + (long)b * nchunk * TS + t;
+    for (int c0 = part; c0 < nch; c0 += 8 * UW) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int c = c0 + UW * q;
+        if (c < nch) acc[q] += yc[(long)c * TS];
+      }
+    }
+    red[part][t] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   }
   __syncthreads();
   {
