@@ -716,9 +716,10 @@ static int sktrd_run(hipStream_t s, const Batch& b, KernelTimer* timer) {
       const bool timed = timer && timer->used + 2 <= timer->cap;
       if (timed) BSE_HIP(hipEventRecord(timer->ev[timer->used], s));
       // the non-temporal hint once the largest trailing triangle is well past
-      // the last-level cache (measured: 600 MB faster with it, 270 MB slower)
+      // the last-level cache (thresholds of 200, 300 and 400 MB measured on
+      // the n = 8192 reduction; 300 MB was fastest)
       const double tri_bytes = 0.5 * sizeof(WT) * (double)(N0 - sidx) * (double)(N0 - sidx);
-      if (tri_bytes > 400e6) sk_symv<WT, true><<<gs, 256, 0, s>>>(b.dev, j, i, pre, nact);
+      if (tri_bytes > 300e6) sk_symv<WT, true><<<gs, 256, 0, s>>>(b.dev, j, i, pre, nact);
       else sk_symv<WT, false><<<gs, 256, 0, s>>>(b.dev, j, i, pre, nact);
       BSE_LAUNCHED();
       if (timed) {
