@@ -19,8 +19,9 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 inline long round_up(long x, long m) { return (x + m - 1) / m * m; }
 // Extra columns of padding (multiple of 64) added to ld; read once from the
 // environment variable BSE_LD_PAD (tuning knob, default 0).
-long ld_pad();
-inline long square_ld(long N) { return round_up(N < 64 ? 64 : N, 64) + ld_pad(); }
+// Leading dimension of every N x N matrix of a problem: whole 64 x 64 tiles
+// (a padded leading dimension measured slower for the matvec).
+inline long square_ld(long N) { return round_up(N < 64 ? 64 : N, 64); }
 
 // Record a HIP failure for bse_last_error() and turn it into BSE_EDEVICE.
 int set_hip_error(hipError_t e, const char* what, const char* file, int line);
@@ -140,28 +141,6 @@ __device__ inline double block_sum(double v, double* red) {
   const int nw = blockDim.x >> 6;
   for (int i = 0; i < nw; ++i) t += red[i];
   return t;
-}
-
-// Device-wide "last workgroup" detection: every workgroup calls this once
-// after writing its partial results; it returns true in exactly one (the
-// last to arrive), which may then read all partials.  The counter is
-// restored to zero by the last workgroup so it can be reused by the next
-// launch on the same stream.
-template <class CounterPtr>
-__device__ inline bool arrive_last(CounterPtr counter, unsigned int expected, int* flag_smem) {
-  // every thread publishes its own writes at device (agent) scope
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned int prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    int last = (prev == expected - 1) ? 1 : 0;
-    if (last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    *flag_smem = last;
-  }
-  __syncthreads();
-  const bool last = *flag_smem != 0;
-  if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  return last;
 }
 
 }  // namespace bse

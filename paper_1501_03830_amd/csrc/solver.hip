@@ -33,16 +33,6 @@ namespace {
 thread_local std::string g_last_error;
 }
 
-long ld_pad() {
-  static long pad = [] {
-    const char* e = getenv("BSE_LD_PAD");
-    long v = e ? atol(e) : 0;
-    if (v < 0) v = 0;
-    return round_up(v, 64);
-  }();
-  return pad;
-}
-
 int set_hip_error(hipError_t e, const char* what, const char* file, int line) {
   char buf[512];
   snprintf(buf, sizeof(buf), "%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
