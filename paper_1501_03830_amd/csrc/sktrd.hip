@@ -45,6 +45,7 @@ constexpr int TS = 64;       // symv tile
 constexpr int NBMAX = 64;    // panel width bound
 constexpr int DUTY_BLK = 16; // row blocks per workgroup of the panel dot products
 constexpr int TMAX = 16;     // row tiles per strip workgroup (upper bound)
+constexpr int UPD_SMALL = 48;   // row blocks up to which the update uses 4 wavefronts
 
 // Reflector of the first column of a panel (sk_start) and the subdiagonal
 // entry of the column brought up to date by the last update.
@@ -413,11 +414,13 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
 
 // p_i = tau (S v + V c_P - P c_V) for the rows of block b, the in-place store
 // of v_i, and the update of the next column with one partial squared norm of
-// it per workgroup.  Sixteen wavefronts share the 64-row block: the partial
+// it per workgroup.  The UW wavefronts share the 64-row block: the partial
 // sums of S v and the panel sums over l are split over them, so that every
 // thread has only a few loads to wait for.
-constexpr int UW = 16;   // wavefronts per update workgroup
-template <class WT>
+// UW wavefronts per workgroup: 16 while the row blocks have many partials to
+// reduce, 4 for short trailing matrices (small problems of a batch, the end
+// of a reduction), where the larger workgroups only cost occupancy.
+template <class WT, int UW>
 __global__ __launch_bounds__(64 * UW) void sk_update(const Prob* __restrict__ probs, int j, int i,
                                                      const int* __restrict__ wgpre, int nact) {
   __shared__ double cs[2 * NBMAX];
@@ -730,7 +733,8 @@ static int sktrd_run(hipStream_t s, const Batch& b, KernelTimer* timer) {
           timer->bytes += sizeof(WT) * m * (m - 1.0) * 0.5;
         }
       }
-      sk_update<WT><<<gup, 64 * UW, 0, s>>>(b.dev, j, i, pre, nact);
+      if (nblk0 > UPD_SMALL) sk_update<WT, 16><<<gup, 1024, 0, s>>>(b.dev, j, i, pre, nact);
+      else sk_update<WT, 4><<<gup, 256, 0, s>>>(b.dev, j, i, pre, nact);
       BSE_LAUNCHED();
     }
     BSE_TRY(gemm_batched(s, b, nstart, GOP_SKTRD_R2K, k0));
