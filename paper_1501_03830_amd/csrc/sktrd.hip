@@ -111,8 +111,9 @@ __global__ __launch_bounds__(256) void sk_start(const Prob* __restrict__ probs, 
 // row blocks.  Long strips amortise each workgroup's prologue (the reflector
 // from the norm partials, the first loads) and its reductions; short ones
 // keep enough workgroups in flight.  The steps were measured inside the
-// n = 8192 reduction (an isolated sweep without the prologue preferred about
-// half these counts at mid sizes).  The count depends on the problem alone,
+// n = 8192 reduction and on a batch of 256 problems of order 128 .. 2048 (an
+// isolated sweep without the prologue preferred about half these counts at
+// mid sizes).  The count depends on the problem alone,
 // so a problem's summation order -- and its result -- is the same whether it
 // is solved alone or inside a batch.
 template <class WT>
@@ -121,15 +122,11 @@ __host__ __device__ inline int symv_tiles(int nblk) {
     if (nblk >= 224) return 16;
     if (nblk >= 160) return 12;
     if (nblk >= 80) return 8;
-    if (nblk >= 40) return 6;
-    if (nblk >= 24) return 3;
-    return 2;
+    return 6;
   }
   if (nblk >= 160) return 12;
   if (nblk >= 80) return 8;
-  if (nblk >= 40) return 6;
-  if (nblk >= 24) return 3;
-  return 2;
+  return 6;
 }
 
 // One element of a matvec tile (NT: with the non-temporal hint).
