@@ -32,22 +32,54 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_PEAK_TFS = 78.6           # MI355X dense FP64 (matrix and vector), TFLOP/s
+FP32_PEAK_TFS = 157.3          # MI355X dense FP32 matrix, TFLOP/s
 
 
-def stage_work(n: int):
-    """Algorithmic work per stage: (bound, amount, unit).  Flop counts are
+def stage_work(n: int, mixed: bool = False, sweeps: int = 0):
+    """Algorithmic work per stage: (bound, amount, peak).  Flop counts are
     the method's own (triangular structure used), bytes the data a stage
-    must move once."""
+    must move once.  Bisection and inverse iteration are chains of
+    dependent scalar operations (bound "latency", no fraction)."""
     N = 2 * n
-    tri_bytes = sum(8.0 * m * (m - 1) / 2 for m in range(1, N))    # symv reads
-    return {
-        "build_M": ("hbm", 2 * 16.0 * n * (n + 1) / 2 + 8.0 * N * (N + 1) / 2, "B"),
-        "potrf": ("mfma", N ** 3 / 3.0, "flop"),
-        "form_W": ("mfma", 5.0 / 3.0 * n ** 3, "flop"),
-        "sktrd": ("hbm", tri_bytes, "B"),
-        "apply_U": ("mfma", 16.0 * n ** 3, "flop"),
-        "apply_L": ("mfma", 8.0 * n ** 3, "flop"),
+    wbytes = 4.0 if mixed else 8.0
+    tri_bytes = sum(wbytes * m * (m - 1) / 2 for m in range(1, N))    # symv reads
+    work = {
+        "build_M": ("hbm", 2 * 16.0 * n * (n + 1) / 2 + 8.0 * N * (N + 1) / 2, HBM_PEAK_GBS),
+        "potrf": ("mfma", N ** 3 / 3.0, FP64_PEAK_TFS),
+        "form_W": ("mfma", 5.0 / 3.0 * n ** 3, FP64_PEAK_TFS),
+        "sktrd": ("hbm", tri_bytes, HBM_PEAK_GBS),
+        "bisect": ("latency", 0.0, None),
+        "invit": ("latency", 0.0, None),
+        "apply_U": ("mfma", 16.0 * n ** 3, FP32_PEAK_TFS if mixed else FP64_PEAK_TFS),
+        "apply_L": ("mfma", 8.0 * n ** 3, FP64_PEAK_TFS),
     }
+    if mixed:
+        # per sweep 12 n^3 (W Ub) + 8 + 8 (S, G) in FP64 and 16 n^3 (the FP32
+        # update, counted against the FP64 peak here), then 6 n^3 for the
+        # final eigenvalues
+        work["refine"] = ("mfma", (44.0 * sweeps + 6.0) * n ** 3, FP64_PEAK_TFS)
+    else:
+        # one Cholesky QR pass: Gram matrix, its Cholesky, forward substitution
+        work["reorth"] = ("mfma", 2.0 * n * n * N + n ** 3 / 3.0, FP64_PEAK_TFS)
+    return work
+
+
+def stage_roofline(stage_ms: dict, work: dict) -> dict:
+    stages = {}
+    for name, ms in stage_ms.items():
+        entry = {"ms": round(ms, 3)}
+        if name in work and ms > 0:
+            bound, amount, peak = work[name]
+            if bound == "hbm":
+                ach = amount / (ms * 1e-3) / 1e9
+                entry.update(bound="hbm", achieved=round(ach, 1), unit="GB/s", frac=round(ach / peak, 4))
+            elif bound == "mfma":
+                ach = amount / (ms * 1e-3) / 1e12
+                entry.update(bound="mfma", achieved=round(ach, 2), unit="TFLOP/s", frac=round(ach / peak, 4))
+            else:
+                entry.update(bound=bound)
+        stages[name] = entry
+    return stages
 
 
 def cpu_baseline(n_sample: int, n_target: int, s_a: float, s_b: float):
@@ -78,14 +110,17 @@ def cpu_baseline(n_sample: int, n_target: int, s_a: float, s_b: float):
 
 
 def batched_bench(ctx, steps: int, warmup: int, count: int = 256, lo: int = 64, hi: int = 1024,
-                  size_seed: int = 4, s_a: float = 0.1, s_b: float = 0.05):
+                  size_seed: int = 4, s_a: float = 0.1, s_b: float = 0.05, mixed: bool = False):
     """The batched workload: `count` independent problems, n_i log-uniform in
     [lo, hi] (seed size_seed), problem i from seed 1000 + i, one
     bse_solve_batched call per step with inputs resident in HBM, all
     eigenvalues, eigenvectors and weights."""
     import torch
     from bse_inputs import gen_bse, batched_sizes
+    from paper_1501_03830_amd import _lib
     from paper_1501_03830_amd.api import to_colmajor
+
+    prec = _lib.BSE_PREC_FP32_REFINE if mixed else _lib.BSE_PREC_FP64
 
     dev = torch.device("cuda", 0)
     ns = [int(k) for k in batched_sizes(count, lo, hi, seed=size_seed)]
@@ -101,14 +136,14 @@ def batched_bench(ctx, steps: int, warmup: int, count: int = 256, lo: int = 64, 
     Xs = [torch.empty((k, 2 * k), dtype=torch.complex128, device=dev) for k in ns]
     ws = [torch.empty(k, dtype=torch.complex128, device=dev) for k in ns]
     for i in range(warmup):
-        info, rep = ctx.solve_batched_raw(ns, Acs, Bcs, lams, Xs, ds, ws, report=True)
+        info, rep = ctx.solve_batched_raw(ns, Acs, Bcs, lams, Xs, ds, ws, report=True, prec=prec)
         assert all(v == 0 for v in info), info
         print(f"# batched warmup {i}: {rep['total_ms']:.1f} ms", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     reps = []
     t0 = time.perf_counter()
     for i in range(steps):
-        info, rep = ctx.solve_batched_raw(ns, Acs, Bcs, lams, Xs, ds, ws, report=True)
+        info, rep = ctx.solve_batched_raw(ns, Acs, Bcs, lams, Xs, ds, ws, report=True, prec=prec)
         assert all(v == 0 for v in info)
         reps.append(rep)
         print(f"# batched step {i}: {rep['total_ms']:.1f} ms", file=sys.stderr, flush=True)
@@ -116,7 +151,8 @@ def batched_bench(ctx, steps: int, warmup: int, count: int = 256, lo: int = 64, 
     dt = (time.perf_counter() - t0) / steps
     return {
         "workload": f"{count} independent problems, n log-uniform in [{lo},{hi}] (size seed {size_seed}, "
-                    f"problem i seed 1000+i), FP64, eigenvalues + eigenvectors + weights, one bse_solve_batched call",
+                    f"problem i seed 1000+i), {'FP32+refine' if mixed else 'FP64'}, eigenvalues + eigenvectors + weights, "
+                    f"one bse_solve_batched call",
         "solves_per_s": round(count / dt, 2),
         "s_per_batch": round(dt, 4),
         "device_ms_per_batch": round(float(np.mean([r["total_ms"] for r in reps])), 2),
@@ -263,12 +299,14 @@ def mixed_bench(ctx, n, Ac, Bc, drb, lam64, X64, steps: int, warmup: int):
     Y6 = torch.cat([X6[:n], -X6[n:]], 0)
     dots = (Y6.conj() * Xm).sum(0).abs()
     vec = (1.0 - dots).abs()
+    stage_ms = {k: float(np.mean([r["stage_ms"][k] for r in reps])) for k in reps[0]["stage_ms"]}
     return {
         "workload": f"same problem as the FP64 solve, BSE_PREC_FP32_REFINE",
         "s_per_solve": round(dt, 4),
         "vs_fp64": None,
         "device_ms": round(float(np.mean([r["total_ms"] for r in reps])), 2),
-        "stage_ms": {k: round(float(np.mean([r["stage_ms"][k] for r in reps])), 2) for k in reps[0]["stage_ms"]},
+        "stage_ms": {k: round(v, 2) for k, v in stage_ms.items()},
+        "stages": stage_roofline(stage_ms, stage_work(n, mixed=True, sweeps=reps[0]["refine_sweeps"])),
         "refine_sweeps": reps[0]["refine_sweeps"],
         "refine_first_correction": reps[0]["refine_first_correction"],
         "refine_last_correction": reps[0]["refine_correction"],
@@ -276,6 +314,42 @@ def mixed_bench(ctx, n, Ac, Bc, drb, lam64, X64, steps: int, warmup: int):
         "vec_err_vs_fp64_median": float(vec.median()),
         "vec_err_vs_fp64_max": float(vec.max()),
     }
+
+
+def closed_form_check(ctx, n: int, seed: int = 30):
+    """Exact-eigenvalue check at the benchmark size: the closed-form
+    generator (A = U0 diag(a) U0^H, B = U0 diag(b) U0^T, eigenvalues
+    sqrt(a_k^2 - |b_k|^2)), solved by both paths, eigenvalues only.  Errors
+    are max |lambda - lambda_exact| relative to lambda_max (at most ||H||_2)."""
+    import torch
+    from bse_inputs import gen_closed_form
+    from paper_1501_03830_amd import _lib
+    from paper_1501_03830_amd.api import to_colmajor
+
+    t0 = time.time()
+    p = gen_closed_form(n, seed=seed)
+    dev = torch.device("cuda", 0)
+    Ac = to_colmajor(torch.from_numpy(p.A), dev)
+    Bc = to_colmajor(torch.from_numpy(p.B), dev)
+    exact = torch.from_numpy(np.asarray(p.exact_lambda)).to(dev)
+    del p
+    lmax = float(exact.max())
+    out = {"workload": f"closed-form generator n={n} (seed {seed}), eigenvalues only", "lambda_max": lmax}
+    for key, prec in (("fp64", _lib.BSE_PREC_FP64), ("fp32_refine", _lib.BSE_PREC_FP32_REFINE)):
+        lam = torch.empty(n, dtype=torch.float64, device=dev)
+        info, rep = ctx.solve_raw(n, Ac, Bc, lam, None, None, None, None, report=True, prec=prec)
+        assert info == 0, info
+        out[key] = {"max_rel_eig_err": float((lam - exact).abs().max()) / lmax,
+                    "device_ms": round(rep["total_ms"], 2)}
+    print(f"# closed form n={n}: {out} ({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
+    return out
+
+
+def device_info():
+    import torch
+    pr = torch.cuda.get_device_properties(0)
+    return {"name": pr.name, "compute_units": pr.multi_processor_count,
+            "hbm_gib": round(pr.total_memory / 2 ** 30, 1), "gcn_arch": getattr(pr, "gcnArchName", None)}
 
 
 def main():
@@ -294,6 +368,7 @@ def main():
     ap.add_argument("--batched-only", action="store_true", help="only the batched workload")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision solve")
+    ap.add_argument("--no-closed-form", action="store_true", help="skip the exact-eigenvalue check")
     ap.add_argument("--serving-count", type=int, default=200)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
@@ -351,22 +426,8 @@ def main():
     s_per_solve = elapsed / a.steps
 
     # stage roofline (mean over the timed steps)
-    work = stage_work(n)
-    stages = {}
-    for name in reps[0]["stage_ms"]:
-        ms = float(np.mean([r["stage_ms"][name] for r in reps]))
-        entry = {"ms": round(ms, 3)}
-        if name in work:
-            bound, amount, unit = work[name]
-            if ms > 0:
-                if bound == "hbm":
-                    ach = amount / (ms * 1e-3) / 1e9
-                    entry.update(bound="hbm", achieved=round(ach, 1), unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4))
-                else:
-                    ach = amount / (ms * 1e-3) / 1e12
-                    entry.update(bound="mfma", achieved=round(ach, 2), unit="TFLOP/s",
-                                 frac=round(ach / FP64_PEAK_TFS, 4))
-        stages[name] = entry
+    stages = stage_roofline({k: float(np.mean([r["stage_ms"][k] for r in reps])) for k in reps[0]["stage_ms"]},
+                            stage_work(n))
 
     roofline = None
     if not a.no_timing and reps[0]["symv_launches"] > 0:
@@ -404,14 +465,21 @@ def main():
         "stages": stages,
         "roofline": roofline,
         "cpu_baseline": None,
+        "device": device_info(),
     }
     ctx.set_timing(False)
     if not a.no_mixed:
         out["fp32_refine"] = mixed_bench(ctx, n, Ac, Bc, drb, lam.clone(), Xbuf.clone(), a.steps, a.warmup)
         out["fp32_refine"]["vs_fp64"] = round(s_per_solve / out["fp32_refine"]["s_per_solve"], 4)
     del Xbuf
+    if not a.no_closed_form:
+        out["closed_form"] = closed_form_check(ctx, n)
     if not a.no_batched:
         out["batched"] = batched_bench(ctx, a.steps, a.warmup)
+        if not a.no_mixed:
+            bm = batched_bench(ctx, a.steps, a.warmup, mixed=True)
+            out["batched_fp32_refine"] = {k: bm[k] for k in ("workload", "solves_per_s", "s_per_batch",
+                                                            "device_ms_per_batch", "stage_ms")}
     if not a.no_serving:
         out["serving"] = serving_bench((Ac, Bc, drb), count=a.serving_count, big=n)
     if not a.no_cpu_baseline:
