@@ -281,7 +281,7 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
     // duty workgroup (d, g) covers row blocks d*DUTY_BLK .. +DUTY_BLK-1 and the
     // panel columns 32g .. 32g+31: group 0 stores v_i, every group writes its
     // partial dot products of those panel columns with v_i; the update kernel
-    // adds the (at most 16) partials of each column.
+    // adds the partials of each column (16 per 16384 rows).
     const int d = (int)wid >> 2, g = (int)wid & 3;
     const int nd = (nblk + DUTY_BLK - 1) / DUTY_BLK;
     if (d >= nd) return;              // uniform
