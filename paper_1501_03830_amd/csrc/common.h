@@ -17,8 +17,6 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 // that 64 x 64 tiles are aligned, with all tiles of the padded square
 // allocated (kernels read whole tiles and mask, they never read past ld x ld).
 inline long round_up(long x, long m) { return (x + m - 1) / m * m; }
-// Extra columns of padding (multiple of 64) added to ld; read once from the
-// environment variable BSE_LD_PAD (tuning knob, default 0).
 // Leading dimension of every N x N matrix of a problem: whole 64 x 64 tiles
 // (a padded leading dimension measured slower for the matvec).
 inline long square_ld(long N) { return round_up(N < 64 ? 64 : N, 64); }

@@ -146,10 +146,13 @@ __host__ __device__ inline long chunk_sum(long M, long T) {
 __host__ __device__ inline long strip_prefix(int Cl, int nblk, int T) {
   return chunk_sum(nblk, T) - chunk_sum(nblk - Cl, T);
 }
-// Workgroups of one problem's matvec launch: the duty workgroups, then every
-// (strip, chunk) of the trailing triangle, none empty.
-__host__ __device__ inline long symv_workgroups(int nblk, int T) {
-  return 4L * ((nblk + DUTY_BLK - 1) / DUTY_BLK) + chunk_sum(nblk, T);
+// Duty workgroups per DUTY_BLK row blocks at panel column i: one per 16 of the
+// 2i panel columns (at least one, which also stores v_i).
+__host__ __device__ inline int duty_groups(int i) { return i > 0 ? (i + 7) / 8 : 1; }
+// Workgroups of one problem's matvec launch at panel column i: the duty
+// workgroups, then every (strip, chunk) of the trailing triangle, none empty.
+__host__ __device__ inline long symv_workgroups(int nblk, int T, int i) {
+  return (long)duty_groups(i) * ((nblk + DUTY_BLK - 1) / DUTY_BLK) + chunk_sum(nblk, T);
 }
 
 // Problem and workgroup index of this workgroup.  A single problem (or a
@@ -216,8 +219,8 @@ __device__ inline double vval(Ptr W, long ld, int j, int s, int N, double scale,
 // ones (a batch of small problems otherwise spends its time dispatching
 // workgroups that only exit):
 // blockIdx.x < nduty (dispatched first): workgroups (d, g) store v_i for row
-//   blocks d*16 .. d*16+15 and their share of the panel dot products V^T v,
-//   P^T v (summed by the update kernel).
+//   blocks d*16 .. d*16+15 and their share (8 panel columns) of the panel dot
+//   products V^T v, P^T v (summed by the update kernel).
 // the rest: workgroup (Cl, k), in strip-major order, streams the 64-column
 //   strip Cl over row tiles Cl + k*T .. Cl + k*T + T - 1.  Lane = row inside
 //   a tile, wave w owns columns 16w..16w+15 of the strip, so every load
@@ -276,43 +279,58 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
     return uniform_double(i == 0 ? ctrl->scale : sc);
   };
 
-  const int nduty = 4 * ((nblk + DUTY_BLK - 1) / DUTY_BLK);
+  const int ngrp = duty_groups(i);
+  const int nduty = ngrp * ((nblk + DUTY_BLK - 1) / DUTY_BLK);
   if (wid < nduty) {
     // duty workgroup (d, g) covers row blocks d*DUTY_BLK .. +DUTY_BLK-1 and the
-    // panel columns 32g .. 32g+31: group 0 stores v_i, every group writes its
-    // partial dot products of those panel columns with v_i; the update kernel
-    // adds the partials of each column (16 per 16384 rows).
-    const int d = (int)wid >> 2, g = (int)wid & 3;
-    const int nd = (nblk + DUTY_BLK - 1) / DUTY_BLK;
-    if (d >= nd) return;              // uniform
-    if (g > 0 && 32 * g >= 2 * i) return;
-    const int b0 = d * DUTY_BLK, b1 = min(nblk, b0 + DUTY_BLK);
+    // panel columns 16g .. 16g+15 below 2i: group 0 stores v_i, every group
+    // writes its partial dot products of those panel columns with v_i; the
+    // update kernel adds the partials of each column (16 per 16384 rows).  Wave
+    // w takes the 8 columns of half h = w & 1 and every second row block from
+    // w >> 1, all of a block's loads issued at once: a wave waits on 8 blocks'
+    // loads in turn (this bounds the launch's latency for short trailing
+    // matrices).  The two waves of a half add in LDS.
+    const int d = (int)wid / ngrp, g = (int)wid % ngrp;
+    const int b1 = min(nblk, d * DUTY_BLK + DUTY_BLK);
+    // wave-uniform column bases in scalar registers, a 32-bit row offset per
+    // lane: the duty branch stays below the strips' register count
+    const int wvu = __builtin_amdgcn_readfirstlane(wv);
+    const int h = wvu & 1;
+    const int lbase = 16 * g + 8 * h;
+    const auto vcol = W + (long)j * ld;
+    const auto ycol = Y1 + (long)lbase * ldy;
     const double scale = column_scale();
     double acc[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-    for (int b = b0; b < b1; ++b) {
-      const long r = (long)(R0 + b) * TS + lane;
-      const double v = vval(W, ld, j, s, N, scale, r);
+    for (int b = d * DUTY_BLK + (wvu >> 1); b < b1; b += 2) {
+      // rows below (R0 + nblk) * 64 <= ld and the 2 * NBMAX panel columns are
+      // allocated: every load is issued before the store of v
+      const int r = (R0 + b) * TS + lane;
       const bool inrange = r >= s && r < N;
-      if (g == 0 && wv == 0 && inrange) {
-        Y1[r + (long)(2 * i) * ldy] = v;
-        Y2[r + (long)(2 * i + 1) * ldy] = -v;
-      }
+      const double x = vcol[r];
       double y[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const int l = 32 * g + wv + 4 * q;
-        y[q] = (l < 2 * i && inrange) ? Y1[r + (long)l * ldy] : 0.0;
+        const double t = ycol[(long)q * ldy + r];
+        y[q] = (lbase + q < 2 * i && inrange) ? t : 0.0;
+      }
+      const double v = (r == s) ? 1.0 : (inrange ? scale * x : 0.0);
+      if (g == 0 && h == 0 && inrange) {
+        Y1[r + (long)(2 * i) * ldy] = v;
+        Y2[r + (long)(2 * i + 1) * ldy] = -v;
       }
 #pragma unroll
       for (int q = 0; q < 8; ++q) acc[q] += y[q] * v;
     }
     if (i == 0) return;  // uniform
-    // lane 8q ends with the total of acc[q]
+    // lane 8q ends with the wave's total of column lbase + q
     const double tot = wave_sum_many(acc);
-    const int l = 32 * g + wv + 4 * (lane >> 3);
-    if ((lane & 7) == 0 && l < 2 * i) dotpart[(long)l * dstride + d] = tot;
+    double* red = &rsum[0][0][0];
+    if ((lane & 7) == 0) red[wv * 8 + (lane >> 3)] = tot;
+    __syncthreads();
+    if (wv < 2 && lane < 8 && lbase + lane < 2 * i)
+      dotpart[(long)(lbase + lane) * dstride + d] = red[wv * 8 + lane] + red[(wv + 2) * 8 + lane];
     return;
   }
 
@@ -603,7 +621,7 @@ __global__ __launch_bounds__(64 * UW) void sk_update(const Prob* __restrict__ pr
 // wgpre[2p + 1] (update) count the workgroups of the active problems before p.
 template <class WT>
 __global__ __launch_bounds__(1024) void k_plan(const Prob* __restrict__ probs, int nact, int j,
-                                               int* __restrict__ wgpre) {
+                                               int i, int* __restrict__ wgpre) {
   __shared__ int ssum[1024], usum[1024];
   const int tid = threadIdx.x;
   const int per = (nact + 1023) / 1024;
@@ -612,7 +630,7 @@ __global__ __launch_bounds__(1024) void k_plan(const Prob* __restrict__ probs, i
     const int N = probs[p].N;
     const int s = j + 1;
     const int nblk = (N - 1) / TS - s / TS + 1;
-    cs = (int)symv_workgroups(nblk, symv_tiles<WT>(nblk));
+    cs = (int)symv_workgroups(nblk, symv_tiles<WT>(nblk), i);
     cu = nblk;
   };
   int ts = 0, tu = 0;
@@ -703,11 +721,11 @@ static int sktrd_run(hipStream_t s, const Batch& b, KernelTimer* timer) {
       long gx = 0, gu = 0;
       for (int q = 0; q < nact; ++q) {
         const int nbq = (b.host[q].N - 1) / TS - R0 + 1;
-        gx += symv_workgroups(nbq, symv_tiles<WT>(nbq));
+        gx += symv_workgroups(nbq, symv_tiles<WT>(nbq), i);
         gu += nbq;
       }
       if (packed) {
-        k_plan<WT><<<1, 1024, 0, s>>>(b.dev, nact, j, b.wgpre);
+        k_plan<WT><<<1, 1024, 0, s>>>(b.dev, nact, j, i, b.wgpre);
         BSE_LAUNCHED();
       }
       const int* pre = packed ? b.wgpre : nullptr;
