@@ -74,9 +74,16 @@ __device__ inline void chol_matrix(const Prob& P, int sel, BSE_GLOBAL double*& M
   }
 }
 
-// Unblocked Cholesky of the diagonal block at (k0, k0), in LDS.
-__global__ __launch_bounds__(256) void k_potf2(const Prob* __restrict__ probs, int sel, int k0) {
-  __shared__ double a[TB][TB + 1];  // a[col][row]
+// Unblocked Cholesky of the diagonal block at (k0, k0): one wavefront, lane
+// t holds row t of the block in registers.  Step j publishes column j in LDS
+// (double-buffered, so one barrier per step), every lane takes the pivot from
+// there, scales its own entry by the reciprocal of the root (as dpotf2 does)
+// and subtracts its rank-1 share from its entries right of j; lane c's entry
+// of the scaled column is formed by the other lanes with the same expression,
+// so all lanes use identical values.  Entries above the diagonal are scratch
+// and are never stored.
+__global__ __launch_bounds__(TB) void k_potf2(const Prob* __restrict__ probs, int sel, int k0) {
+  __shared__ double colbuf[2][TB];
   const Prob& P = probs[blockIdx.z];
   BSE_GLOBAL double* M;
   long ld;
@@ -86,35 +93,32 @@ __global__ __launch_bounds__(256) void k_potf2(const Prob* __restrict__ probs, i
   if (k0 >= N || *info != 0) return;
   if (sel == 1 && *gbl(P.reorth) == 0) return;   // no cluster Gram-Schmidt
   const int nbk = min(TB, N - k0);
-  const int tid = threadIdx.x;
-  for (int idx = tid; idx < TB * TB; idx += 256) {
-    const int r = idx & 63, c = idx >> 6;
-    a[c][r] = (r < nbk && c < nbk && r >= c) ? M[(long)(k0 + r) + (long)(k0 + c) * ld] : 0.0;
-  }
-  __syncthreads();
-  // thread (row rr, column class cq): updates a[c][rr] for c = cq mod 4
-  const int rr = tid & 63, cq = tid >> 6;
-  for (int j = 0; j < nbk; ++j) {
-    const double piv = a[j][j];
-    if (!(piv > 0.0) || !isfinite(piv)) {
-      if (tid == 0) *info = k0 + j + 1;
-      return;  // uniform: every thread read the same pivot
+  const int t = threadIdx.x;
+  double a[TB];
+#pragma unroll
+  for (int c = 0; c < TB; ++c)
+    a[c] = (t < nbk && c <= t) ? M[(long)(k0 + t) + (long)(k0 + c) * ld] : 0.0;
+#pragma unroll
+  for (int j = 0; j < TB; ++j) {
+    if (j < nbk) {   // uniform
+      double* col = colbuf[j & 1];
+      col[t] = a[j];
+      __syncthreads();
+      const double piv = col[j];
+      if (!(piv > 0.0) || !isfinite(piv)) {
+        if (t == 0) *info = k0 + j + 1;
+        return;  // uniform: every lane read the same pivot
+      }
+      const double ljj = sqrt(piv);
+      const double rinv = 1.0 / ljj;
+      a[j] = (t == j) ? ljj : a[j] * rinv;
+#pragma unroll
+      for (int c = j + 1; c < TB; ++c) a[c] -= a[j] * (col[c] * rinv);
     }
-    const double ljj = sqrt(piv);
-    __syncthreads();
-    if (tid < 64 && rr > j && rr < nbk) a[j][rr] /= ljj;
-    if (tid == 0) a[j][j] = ljj;
-    __syncthreads();
-    if (rr > j && rr < nbk) {
-      const double lrj = a[j][rr];
-      for (int c = j + 1 + ((cq - (j + 1)) & 3); c <= rr; c += 4) a[c][rr] -= lrj * a[j][c];
-    }
-    __syncthreads();
   }
-  for (int idx = tid; idx < TB * TB; idx += 256) {
-    const int r = idx & 63, c = idx >> 6;
-    if (r < nbk && c < nbk && r >= c) M[(long)(k0 + r) + (long)(k0 + c) * ld] = a[c][r];
-  }
+#pragma unroll
+  for (int c = 0; c < TB; ++c)
+    if (t < nbk && c <= t) M[(long)(k0 + t) + (long)(k0 + c) * ld] = a[c];
 }
 
 // For every lower tile pair (R, C), R >= C, of the leading nrows x nrows
@@ -245,13 +249,13 @@ int potrf_batched(hipStream_t s, const Batch& b, int sel, bool reset_info) {
   // halves the passes over the trailing matrix.
   for (int k0 = 0; k0 < Nmax; k0 += 2 * TB) {
     const int nact = count_above(b.count, k0);   // problems with a diagonal block at k0
-    k_potf2<<<dim3(1, 1, (unsigned)nact), 256, 0, s>>>(b.dev, sel, k0);
+    k_potf2<<<dim3(1, 1, (unsigned)nact), TB, 0, s>>>(b.dev, sel, k0);
     BSE_LAUNCHED();
     const int nrest = count_above(nact, k0 + TB);   // problems with rows below it
     if (nrest == 0) continue;
     BSE_TRY(trsm_rows_batched(s, b, nrest, sel, k0));
     BSE_TRY(gemm_batched(s, b, nrest, POPS, k0));
-    k_potf2<<<dim3(1, 1, (unsigned)nrest), 256, 0, s>>>(b.dev, sel, k0 + TB);
+    k_potf2<<<dim3(1, 1, (unsigned)nrest), TB, 0, s>>>(b.dev, sel, k0 + TB);
     BSE_LAUNCHED();
     const int nrest2 = count_above(nrest, k0 + 2 * TB);
     if (nrest2 == 0) continue;

@@ -15,9 +15,12 @@
 // Each thread keeps its vector in registers and runs the substitution in
 // axpy form (once x_l is final it is removed from the remaining rows), so
 // the updates of one step are independent instructions.  The triangular
-// block is the same for every lane: where it is read-only in the launch it
-// is read straight from memory through the scalar cache (FMA operands in
-// scalar registers); the compact-WY factor is assembled in LDS.
+// block is the same for every lane and is staged in LDS, where every lane
+// reads the same address (a broadcast).  The lower-triangular solves run one
+// wavefront per workgroup, which spreads a panel of 16384 rows over 256
+// compute units; the block is read from LDS with its diagonal replaced by
+// the reciprocal (the scalar cache, read step by step, left every wave
+// waiting on cache misses, ~70 us per 16384-row panel).
 #include "common.h"
 #include "kernels.h"
 
@@ -26,21 +29,51 @@ namespace bse {
 namespace {
 
 constexpr int NB = 64;
+#define BSE_LDS __attribute__((address_space(3)))
 
-// x <- L^{-1} x for the lower-triangular L at Lp (column-major, ld), of
-// order 64 (FULL) or nbk < 64 (the remaining unknowns are untouched)
+// Stage the lower-triangular block at Lp (column-major, ld) of order 64
+// (FULL) or nbk < 64 into Ls[col][row], the diagonal replaced by its
+// reciprocal; entries outside the nbk x nbk block are zero.  Run by a
+// 64-lane workgroup, lane = row; ends with a barrier.
 template <bool FULL>
-__device__ inline void lower_solve64(const BSE_CONST double* Lp, long ld, int nbk, double (&x)[NB]) {
+__device__ inline void stage_lower64(const BSE_GLOBAL double* Lp, long ld, int nbk, BSE_LDS double (*Ls)[NB]) {
+  const int t = threadIdx.x;
+#pragma unroll 16
+  for (int l = 0; l < NB; ++l)
+    Ls[l][t] = (FULL || (l < nbk && t < nbk)) ? Lp[t + (long)l * ld] : 0.0;
+  __syncthreads();
+  if (FULL || t < nbk) Ls[t][t] = 1.0 / Ls[t][t];
+  __syncthreads();
+}
+
+// x <- L^{-1} x with L staged by stage_lower64.  The reads of each step are
+// taken in groups of 16 rows with a scheduling barrier after each group: left
+// free, the compiler hoists the whole triangle's reads and spills.
+template <bool FULL, int L0, int L1>
+__device__ __attribute__((always_inline)) inline void lower_solve_steps(const BSE_LDS double (*Ls)[NB], int nbk,
+                                                                        double (&x)[NB]) {
 #pragma unroll
-  for (int l = 0; l < NB; ++l) {
+  for (int l = L0; l < L1; ++l) {
     if (FULL || l < nbk) {
-      const BSE_CONST double* col = Lp + (long)l * ld;
-      x[l] = x[l] / col[l];
+      x[l] *= Ls[l][l];
 #pragma unroll
-      for (int r = l + 1; r < NB; ++r)
-        if (FULL || r < nbk) x[r] -= col[r] * x[l];
+      for (int r = l + 1; r < NB; ++r) {
+        if (FULL || r < nbk) x[r] -= Ls[l][r] * x[l];
+        if (((r - l) & 15) == 0) __builtin_amdgcn_sched_barrier(0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
+}
+// (four loops of 16 steps: one loop of 64 is past the compiler's limit for
+// a full unroll, and x must stay in registers)
+template <bool FULL>
+__device__ __attribute__((always_inline)) inline void lower_solve64(const BSE_LDS double (*Ls)[NB], int nbk,
+                                                                    double (&x)[NB]) {
+  lower_solve_steps<FULL, 0, 16>(Ls, nbk, x);
+  lower_solve_steps<FULL, 16, 32>(Ls, nbk, x);
+  lower_solve_steps<FULL, 32, 48>(Ls, nbk, x);
+  lower_solve_steps<FULL, 48, 64>(Ls, nbk, x);
 }
 
 // x <- U^{-1} x, U upper, Us[col][row]
@@ -55,8 +88,10 @@ __device__ inline void upper_solve64(const double (*Us)[NB + 1], double (&x)[NB]
 
 // Cholesky panel: rows k0+nbk .. Nm-1 of the panel columns k0 .. k0+nbk-1
 // of matrix sel (0: M, 1: the Gram matrix) <- themselves times L_kk^{-T}.
+// One wavefront of 64 rows per workgroup.
 template <bool FULL>
-__global__ __launch_bounds__(256) void k_trsm_rows(const Prob* __restrict__ probs, int sel, int k0) {
+__global__ __launch_bounds__(NB) void k_trsm_rows(const Prob* __restrict__ probs, int sel, int k0) {
+  __shared__ double Ls[NB][NB];
   const Prob& P = probs[blockIdx.z];
   double* Mp;
   long ld;
@@ -75,38 +110,43 @@ __global__ __launch_bounds__(256) void k_trsm_rows(const Prob* __restrict__ prob
   const int nbk = min(NB, Nm - k0);
   if (FULL != (nbk == NB)) return;                  // uniform: the other variant
   const int first = k0 + nbk;
-  const long r = first + (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= Nm) return;
+  if (first + (long)blockIdx.x * NB >= Nm) return;   // uniform: past this problem's rows
   // the diagonal block is not written by this launch (only the rows below)
-  const BSE_CONST double* Lkk = ro(Mp + (long)k0 + (long)k0 * ld);
   BSE_GLOBAL double* __restrict__ M = gbl(Mp);
+  stage_lower64<FULL>(M + (long)k0 + (long)k0 * ld, ld, nbk, (BSE_LDS double(*)[NB])Ls);
+  const long r = first + (long)blockIdx.x * NB + threadIdx.x;
+  if (r >= Nm) return;
   double x[NB];
 #pragma unroll
   for (int c = 0; c < NB; ++c) x[c] = (FULL || c < nbk) ? M[r + (long)(k0 + c) * ld] : 0.0;
-  lower_solve64<FULL>(Lkk, ld, nbk, x);
+  lower_solve64<FULL>((const BSE_LDS double(*)[NB])Ls, nbk, x);
 #pragma unroll
   for (int c = 0; c < NB; ++c)
     if (FULL || c < nbk) M[r + (long)(k0 + c) * ld] = x[c];
 }
 
 // Gram-Schmidt forward substitution, diagonal block b0: rows b0 .. b0+63 of
-// V_+^T (n x N, ld n) <- L_bb^{-1} times themselves, one column per thread.
+// V_+^T (n x N, ld n) <- L_bb^{-1} times themselves, one column per thread,
+// one wavefront per workgroup.
 template <bool FULL>
-__global__ __launch_bounds__(256) void k_trsm_cols(const Prob* __restrict__ probs, int b0) {
+__global__ __launch_bounds__(NB) void k_trsm_cols(const Prob* __restrict__ probs, int b0) {
+  __shared__ double Ls[NB][NB];
   const Prob& P = probs[blockIdx.z];
   const int n = P.n, N = P.N;
   if (b0 >= n || gbl(P.info)[1] != 0) return;   // uniform
   if (*gbl(P.reorth) == 0) return;              // uniform: no Gram-Schmidt
   const int nbk = min(NB, n - b0);
   if (FULL != (nbk == NB)) return;              // uniform: the other variant
-  const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if ((long)blockIdx.x * NB >= N) return;       // uniform: past this problem's columns
+  // Gram factor, read-only here
+  stage_lower64<FULL>(gbl(P.inv) + (long)b0 + (long)b0 * n, n, nbk, (BSE_LDS double(*)[NB])Ls);
+  const long j = (long)blockIdx.x * NB + threadIdx.x;
   if (j >= N) return;
-  const BSE_CONST double* Lbb = ro(P.inv + (long)b0 + (long)b0 * n);   // Gram factor, read-only here
   BSE_GLOBAL double* __restrict__ v = gbl(P.Vt) + b0 + j * n;
   double x[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) x[i] = (FULL || i < nbk) ? v[i] : 0.0;
-  lower_solve64<FULL>(Lbb, n, nbk, x);
+  lower_solve64<FULL>((const BSE_LDS double(*)[NB])Ls, nbk, x);
 #pragma unroll
   for (int i = 0; i < NB; ++i)
     if (FULL || i < nbk) v[i] = x[i];
@@ -174,10 +214,10 @@ int trsm_rows_batched(hipStream_t s, const Batch& b, int nact, int sel, int k0) 
   if (nact <= 0) return 0;
   const long rows = (long)(sel == 0 ? b.host[0].N : b.host[0].n) - k0 - NB;
   if (rows <= 0) return 0;
-  const dim3 g((unsigned)((rows + 255) / 256), 1, (unsigned)nact);
-  k_trsm_rows<true><<<g, 256, 0, s>>>(b.dev, sel, k0);
+  const dim3 g((unsigned)((rows + NB - 1) / NB), 1, (unsigned)nact);
+  k_trsm_rows<true><<<g, NB, 0, s>>>(b.dev, sel, k0);
   BSE_LAUNCHED();
-  k_trsm_rows<false><<<g, 256, 0, s>>>(b.dev, sel, k0);
+  k_trsm_rows<false><<<g, NB, 0, s>>>(b.dev, sel, k0);
   BSE_LAUNCHED();
   return 0;
 }
@@ -185,10 +225,10 @@ int trsm_rows_batched(hipStream_t s, const Batch& b, int nact, int sel, int k0) 
 int trsm_cols_batched(hipStream_t s, const Batch& b, int nact, int b0) {
   if (nact <= 0) return 0;
   const long N0 = b.maxN();
-  const dim3 g((unsigned)((N0 + 255) / 256), 1, (unsigned)nact);
-  k_trsm_cols<true><<<g, 256, 0, s>>>(b.dev, b0);
+  const dim3 g((unsigned)((N0 + NB - 1) / NB), 1, (unsigned)nact);
+  k_trsm_cols<true><<<g, NB, 0, s>>>(b.dev, b0);
   BSE_LAUNCHED();
-  k_trsm_cols<false><<<g, 256, 0, s>>>(b.dev, b0);
+  k_trsm_cols<false><<<g, NB, 0, s>>>(b.dev, b0);
   BSE_LAUNCHED();
   return 0;
 }
