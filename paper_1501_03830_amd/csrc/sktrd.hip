@@ -118,22 +118,21 @@ __global__ __launch_bounds__(256) void sk_start(const Prob* __restrict__ probs, 
 // is solved alone or inside a batch.
 template <class WT>
 __host__ __device__ inline int symv_tiles(int nblk) {
-  if (sizeof(WT) == 8) {
-    if (nblk >= 224) return 16;
-    if (nblk >= 160) return 12;
-    if (nblk >= 80) return 8;
-    return 6;
-  }
+  // FP32 takes the same table (16 tiles at full size measured slightly
+  // faster over the FP32 reduction than 12)
+  if (nblk >= 224) return 16;
   if (nblk >= 160) return 12;
   if (nblk >= 80) return 8;
   return 6;
 }
 
-// One element of a matvec tile (NT: with the non-temporal hint).
+// One element of a matvec tile (NT: with the non-temporal hint), kept in
+// its storage type until it is used (an FP32 tile in flight then takes half
+// the registers).
 template <bool NT, class Ptr>
-__device__ inline double tile_load(Ptr p) {
-  if (NT) return (double)__builtin_nontemporal_load(p);
-  return (double)*p;
+__device__ inline auto tile_load(Ptr p) {
+  if (NT) return __builtin_nontemporal_load(p);
+  return *p;
 }
 
 // Strip workgroups of the matvec: strip Cl (Cl = 0 .. nblk-1) has
@@ -356,15 +355,28 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
   const long col0 = C0 + 16 * wvu;
   const auto vcol = W + (long)j * ld;   // column j holds x; v = scale * x below row s
   const auto colbase = W + col0 * ld;
-  // the first tile and x at the strip's columns are loaded before the
-  // reflector is known
-  double a[16], xr, xc[16];
-  {
-    const int row_off = (int)((long)(R0 + rl0) * TS) + lane;
+  // The tile loop is a software pipeline: the loads of the next step are
+  // issued before the current one is used, with no barrier, no global store
+  // and no dependent load inside the loop (v at the tile's rows is fetched
+  // with the tile).  A step is one 64-row tile in FP64 and two in FP32, so
+  // that an FP32 wave has as many bytes in flight as an FP64 one.  The first
+  // step's loads and x at the strip's columns are issued before the
+  // reflector is known.
+  constexpr int SP = sizeof(WT) == 4 ? 2 : 1;   // tiles per step
+  auto load_step = [&](int rl, WT(&t)[SP][16], double(&x)[SP]) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) a[q] = tile_load<NT>(colbase + (long)q * ld + row_off);
-    xr = vcol[row_off];
-  }
+    for (int p = 0; p < SP; ++p) {
+      if (p == 0 || rl + p < rl1) {
+        const int off = (int)((long)(R0 + rl + p) * TS) + lane;   // 32-bit lane offset (rows < 2^28)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) t[p][q] = tile_load<NT>(colbase + (long)q * ld + off);
+        x[p] = vcol[off];
+      }
+    }
+  };
+  WT a[SP][16];
+  double xr[SP], xc[16];
+  load_step(rl0, a, xr);
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const long c = col0 + q;
@@ -381,39 +393,40 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
 #pragma unroll
   for (int q = 0; q < 16; ++q) cacc[q] = 0.0;
   const bool strip_inside = C0 >= s;
-  // no barrier, no global store and no dependent load inside this loop: v at
-  // the tile's rows is fetched with the tile itself, and the next tile's
-  // loads are issued before the current tile is used (software pipeline)
-  for (int rl = rl0; rl < rl1; ++rl) {
-    const long rbase = (long)(R0 + rl) * TS;
-    const long row = rbase + lane;
-    double an[16], xn = 0.0;
-    if (rl + 1 < rl1) {
-      const int noff = (int)(rbase + TS) + lane;   // 32-bit lane offset (rows < 2^28)
+  for (int rl = rl0; rl < rl1; rl += SP) {
+    WT an[SP][16];
+    double xn[SP];
+    if (rl + SP < rl1) load_step(rl + SP, an, xn);
 #pragma unroll
-      for (int q = 0; q < 16; ++q) an[q] = tile_load<NT>(colbase + (long)q * ld + noff);
-      xn = vcol[noff];
-    }
-    const double vr = (row == s) ? 1.0 : ((row > s && row < N) ? scale * xr : 0.0);
-    const bool interior = (rl > Cl) && strip_inside && (rbase + TS <= N);
-    if (!interior) {
+    for (int p = 0; p < SP; ++p) {
+      if (p == 0 || rl + p < rl1) {
+        const long rbase = (long)(R0 + rl + p) * TS;
+        const long row = rbase + lane;
+        const double vr = (row == s) ? 1.0 : ((row > s && row < N) ? scale * xr[p] : 0.0);
+        const bool interior = (rl + p > Cl) && strip_inside && (rbase + TS <= N);
+        if (!interior) {
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const long col = col0 + q;
-        if (!(row > col && col >= s && row < N)) a[q] = 0.0;
+          for (int q = 0; q < 16; ++q) {
+            const long col = col0 + q;
+            if (!(row > col && col >= s && row < N)) a[p][q] = 0.0;
+          }
+        }
+        double racc = 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          racc += a[p][q] * vc[q];
+          cacc[q] += a[p][q] * vr;
+        }
+        rsum[rl + p - rl0][wv][lane] = racc;
       }
     }
-    double racc = 0.0;
+    if (rl + SP < rl1) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      racc += a[q] * vc[q];
-      cacc[q] += a[q] * vr;
-    }
-    rsum[rl - rl0][wv][lane] = racc;
-    if (rl + 1 < rl1) {
+      for (int p = 0; p < SP; ++p) {
 #pragma unroll
-      for (int q = 0; q < 16; ++q) a[q] = an[q];
-      xr = xn;
+        for (int q = 0; q < 16; ++q) a[p][q] = an[p][q];
+        xr[p] = xn[p];
+      }
     }
   }
   // column sums over the 64 lanes: lane 4q ends with the total of column q
