@@ -459,8 +459,16 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ 
 
   // Epilogue through LDS, EC columns at a time.  In a 16 x 16 f64 block the
   // entry (i, j) lives in lane 16 (i mod 4) + j, accumulator element i / 4.
+  // The old C values of 8 elements per thread are loaded before any of them
+  // is stored: the compiler cannot move a load of C above a store to C, so
+  // the element loop made one round trip per element (a few percent of the
+  // K = 128 updates).  Batches of 8 keep the register count, and so the
+  // occupancy, of the main loop.
   double* Cs = smem;  // Cs[(c - c0) * (BM + 1) + r]
   const bool split = p.splits > 1;
+  const bool read_c = !split && p.beta != 0.0;
+  constexpr int PER = 8, NBAT = EC * BM / (256 * PER);
+  static_assert(NBAT * 256 * PER == EC * BM, "epilogue chunk is not a whole number of batches");
 #pragma unroll
   for (int c0 = 0; c0 < BN; c0 += EC) {
     __syncthreads();
@@ -477,23 +485,36 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ 
         }
       }
     __syncthreads();
-    for (int idx = tid; idx < EC * BM; idx += 256) {
-      const int rl = idx % BM, cl = c0 + idx / BM;
-      const int row = i0 + rl, col = j0 + cl;
-      if (row >= p.M || col >= p.N) continue;
-      if ((p.c_uplo == 1 || p.c_uplo == 3) && row < col) continue;
-      if (p.c_uplo == 2 && row <= col) continue;
-      const double val = Cs[(cl - c0) * (BM + 1) + rl];
-      if (split) {
-        gbl(p.part)[(long)slice * p.M * p.N + (long)row + (long)col * p.M] = val;
-      } else if (p.Cf) {
-        BSE_GLOBAL float* c = gbl(p.Cf + (long)row + (long)col * p.ldc);
+#pragma unroll
+    for (int h = 0; h < NBAT; ++h) {
+      bool ok[PER];
+      double cold[PER];
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int idx = tid + 256 * (h * PER + u);
+        const int rl = idx % BM, cl = c0 + idx / BM;
+        const int row = i0 + rl, col = j0 + cl;
+        ok[u] = row < p.M && col < p.N && !((p.c_uplo == 1 || p.c_uplo == 3) && row < col) &&
+                !(p.c_uplo == 2 && row <= col);
+        cold[u] = 0.0;
+        if (ok[u] && read_c) {
+          const long o = (long)row + (long)col * p.ldc;
+          cold[u] = p.Cf ? (double)gbl(p.Cf)[o] : gbl(p.C)[o];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        if (!ok[u]) continue;
+        const int idx = tid + 256 * (h * PER + u);
+        const int rl = idx % BM, cl = c0 + idx / BM;
+        const int row = i0 + rl, col = j0 + cl;
+        const double val = Cs[(cl - c0) * (BM + 1) + rl];
         const double out = p.alpha * val;
-        *c = (float)((p.beta == 0.0) ? out : out + p.beta * (double)(*c));
-      } else {
-        BSE_GLOBAL double* c = gbl(p.C + (long)row + (long)col * p.ldc);
-        const double out = p.alpha * val;
-        *c = (p.beta == 0.0) ? out : out + p.beta * (*c);
+        const double res = read_c ? out + p.beta * cold[u] : out;
+        const long o = (long)row + (long)col * p.ldc;
+        if (split) gbl(p.part)[(long)slice * p.M * p.N + (long)row + (long)col * p.M] = val;
+        else if (p.Cf) gbl(p.Cf)[o] = (float)res;
+        else gbl(p.C)[o] = res;
       }
     }
   }
@@ -656,22 +677,41 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const Prob* __restrict__ 
         }
     }
     __syncthreads();
-    for (int idx = tid; idx < EC * TBM; idx += 256) {
-      const int rl = idx % TBM, cl = idx / TBM;
-      const int row = i0 + rl, col = j0 + pass * EC + cl;
-      if (row >= p.M || col >= p.N) continue;
-      const double val = (double)Cs[cl * (TBM + 1) + rl];
-      if (split) {
-        gbl(p.part)[(long)slice * p.M * p.N + (long)row + (long)col * p.M] = val;
-      } else if (p.Cf) {
-        BSE_GLOBAL float* c = gbl(p.Cf + (long)row + (long)col * p.ldc);
+    // the old C values of 4 elements per thread are loaded before any of
+    // them is stored (one round trip per element otherwise; 4 keeps the
+    // main loop's occupancy)
+    constexpr int PER = 4, NB16 = EC * TBM / (256 * PER);
+    static_assert(NB16 * 256 * PER == EC * TBM, "epilogue pass is not a whole number of batches");
+    const bool read_c = !split && p.beta != 0.0;
+#pragma unroll
+    for (int h = 0; h < NB16; ++h) {
+      bool ok[PER];
+      double cold[PER];
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int idx = tid + 256 * (h * PER + u);
+        const int rl = idx % TBM, cl = idx / TBM;
+        const int row = i0 + rl, col = j0 + pass * EC + cl;
+        ok[u] = row < p.M && col < p.N;
+        cold[u] = 0.0;
+        if (ok[u] && read_c) {
+          const long o = (long)row + (long)col * p.ldc;
+          cold[u] = p.Cf ? (double)gbl(p.Cf)[o] : (p.Cin ? gbl(p.Cin)[o] : gbl(p.C)[o]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        if (!ok[u]) continue;
+        const int idx = tid + 256 * (h * PER + u);
+        const int rl = idx % TBM, cl = idx / TBM;
+        const int row = i0 + rl, col = j0 + pass * EC + cl;
+        const double val = (double)Cs[cl * (TBM + 1) + rl];
         const double out = p.alpha * val;
-        *c = (float)((p.beta == 0.0) ? out : out + p.beta * (double)(*c));
-      } else {
-        BSE_GLOBAL double* c = gbl(p.C + (long)row + (long)col * p.ldc);
-        const double out = p.alpha * val;
-        if (p.beta == 0.0) *c = out;
-        else *c = out + p.beta * (p.Cin ? gbl(p.Cin)[(long)row + (long)col * p.ldc] : *c);
+        const double res = read_c ? out + p.beta * cold[u] : out;
+        const long o = (long)row + (long)col * p.ldc;
+        if (split) gbl(p.part)[(long)slice * p.M * p.N + (long)row + (long)col * p.M] = val;
+        else if (p.Cf) gbl(p.Cf)[o] = (float)res;
+        else gbl(p.C)[o] = res;
       }
     }
   }
@@ -694,22 +734,30 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const Prob* __restrict__ 
   const long r = (long)blockIdx.x * 64 + (threadIdx.x & 63);
   const long c0 = (long)blockIdx.y * 64 + (threadIdx.x >> 6) * 16;
   if (r >= p.M) return;
+  // every load (partials and old C) of the thread's 16 entries before any
+  // store, so that they are in flight together
+  const BSE_GLOBAL double* part = gbl(p.part);
+  const bool read_c = p.beta != 0.0;
+  bool ok[16];
+  double res[16];
+#pragma unroll
   for (int q = 0; q < 16; ++q) {
     const long c = c0 + q;
-    if (c >= p.N) break;
-    if ((p.c_uplo == 1 || p.c_uplo == 3) && r < c) continue;
-    if (p.c_uplo == 2 && r <= c) continue;
+    ok[q] = c < p.N && !((p.c_uplo == 1 || p.c_uplo == 3) && r < c) && !(p.c_uplo == 2 && r <= c);
+    res[q] = 0.0;
+    if (!ok[q]) continue;
     double s = 0.0;
-    const BSE_GLOBAL double* part = gbl(p.part);
     for (int k = 0; k < p.splits; ++k) s += part[(long)k * p.M * p.N + r + c * p.M];
     const double out = p.alpha * s;
-    if (p.Cf) {
-      BSE_GLOBAL float* cf = gbl(p.Cf + r + c * p.ldc);
-      *cf = (float)((p.beta == 0.0) ? out : out + p.beta * (double)(*cf));
-    } else {
-      BSE_GLOBAL double* cp = gbl(p.C + r + c * p.ldc);
-      *cp = (p.beta == 0.0) ? out : out + p.beta * (*cp);
-    }
+    const long o = r + c * p.ldc;
+    res[q] = read_c ? out + p.beta * (p.Cf ? (double)gbl(p.Cf)[o] : gbl(p.C)[o]) : out;
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    if (!ok[q]) continue;
+    const long o = r + (c0 + q) * p.ldc;
+    if (p.Cf) gbl(p.Cf)[o] = (float)res[q];
+    else gbl(p.C)[o] = res[q];
   }
 }
 

@@ -76,11 +76,12 @@ __device__ __attribute__((always_inline)) inline void lower_solve64(const BSE_LD
   lower_solve_steps<FULL, 48, 64>(Ls, nbk, x);
 }
 
-// x <- U^{-1} x, U upper, Us[col][row]
+// x <- U^{-1} x, U upper, Us[col][row], with the reciprocal of U's diagonal
+// stored on the diagonal of Us
 __device__ inline void upper_solve64(const double (*Us)[NB + 1], double (&x)[NB]) {
 #pragma unroll
   for (int l = NB - 1; l >= 0; --l) {
-    x[l] = x[l] / Us[l][l];
+    x[l] *= Us[l][l];
 #pragma unroll
     for (int r = 0; r < l; ++r) x[r] -= Us[l][r] * x[l];
   }
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(256) void k_wy_solve(const Prob* __restrict__ probs
   for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
     const int r = idx & 63, c = idx >> 6;
     double v;
-    if (r == c) v = zero[r] ? 1.0 : 1.0 / tau[j0 + r];
+    if (r == c) v = zero[r] ? 1.0 : tau[j0 + r];   // the reciprocal of T^{-1}'s diagonal 1/tau
     else if (r < c && !zero[r] && !zero[c]) v = S[(off + r) + (long)(off + c) * RB];
     else v = 0.0;
     Us[c][r] = v;
