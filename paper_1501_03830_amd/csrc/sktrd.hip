@@ -118,8 +118,14 @@ __global__ __launch_bounds__(256) void sk_start(const Prob* __restrict__ probs, 
 // is solved alone or inside a batch.
 template <class WT>
 __host__ __device__ inline int symv_tiles(int nblk) {
-  // FP32 takes the same table (16 tiles at full size measured slightly
-  // faster over the FP32 reduction than 12)
+  // FP32 tiles carry half the bytes: longer strips from 80 row blocks up
+  // (measured over the FP32 reduction: 16/12 beat the FP64 table by ~8 ms;
+  // 16 from 80 and 12 from 48 lost it again)
+  if (sizeof(WT) == 4) {
+    if (nblk >= 160) return 16;
+    if (nblk >= 80) return 12;
+    return 6;
+  }
   if (nblk >= 224) return 16;
   if (nblk >= 160) return 12;
   if (nblk >= 80) return 8;
