@@ -266,6 +266,39 @@ __device__ inline void grouped_tile(long t, int tiles_m, int tiles_n, int& tm, i
   tn = (int)(in_band / rows);
 }
 
+// Tile (R, C), R >= C, of the lower triangle of an nt x nt tile grid, in
+// bands of GROUP tile rows: a band holds the columns 0 .. its last row,
+// column by column with the band's rows fastest, so consecutive tiles share
+// their B panel and a band's A panels stay in L2 while it is swept (row by
+// row, every tile row re-read all B panels of its columns).
+__device__ inline void grouped_lower_tile(long t, int nt, int& R, int& C) {
+  constexpr int GROUP = 8;
+  int r0 = 0;
+  long before = 0;
+  for (;;) {   // at most nt / GROUP bands
+    const int g = min(GROUP, nt - r0);
+    const long cnt = (long)g * r0 + (long)g * (g + 1) / 2;
+    if (t < before + cnt || r0 + g >= nt) break;
+    before += cnt;
+    r0 += GROUP;
+  }
+  const int g = min(GROUP, nt - r0);
+  long o = t - before;
+  if (o < (long)g * r0) {
+    C = (int)(o / g);
+    R = r0 + (int)(o % g);
+    return;
+  }
+  o -= (long)g * r0;
+  int c = 0;
+  while (o >= g - c) {
+    o -= g - c;
+    ++c;
+  }
+  C = r0 + c;
+  R = r0 + c + (int)o;
+}
+
 template <bool TA, bool TB, int BM, int BN, int BK>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ probs, int op, int step,
                                                        GemmParams single) {
@@ -310,7 +343,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ 
   }
   int tm, tn;
   if (p.c_uplo == 1 || p.c_uplo == 2) {
-    tri_index(tile, tm, tn);
+    grouped_lower_tile(tile, tiles_m, tm, tn);
   } else if (tri) {
     tm = (int)(tile % tiles_m);
     tn = (int)(tile / tiles_m);
