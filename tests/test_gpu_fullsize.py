@@ -1,0 +1,101 @@
+"""Full-size checks at the benchmark order n = 8192 (N = 16384), in the
+launch configuration the benchmark times: one problem per bse_solve call,
+eigenvalues, eigenvectors and weights requested.
+
+The oracle cannot run at this size, so these are properties that hold at
+any size:
+
+* Closed-form spectrum (A = U0 diag(a) U0^H, B = U0 diag(b) U0^T, so every
+  positive eigenvalue is sqrt(a_k^2 - |b_k|^2)): all n eigenvalues of both
+  paths against the exact ones, to 1e-10 lambda_max (lambda_max <= ||H||_2).
+* The benchmark's own workload (the same generator, order and seed): for 24
+  sampled eigenpairs, the residual ||H x_j - lambda_j x_j|| / (lambda_max
+  ||x_j||) with H applied on the host from the generator's A and B, and the
+  pairwise normalisation X1^H X1 - X2^H X2 = I of Theorem 3 on the sampled
+  block.  FP64 to 1e-10; the mixed path's eigenvectors to 1e-6 (one
+  refinement sweep leaves a basis error of about the square of its first
+  correction, ~1e-3 here), its eigenvalues to 1e-10 like the FP64 path's.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from bse_inputs import gen_bse, gen_closed_form
+
+pytestmark = pytest.mark.gpu
+
+N_BENCH = 8192
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1501_03830_amd.api import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def precisions():
+    from paper_1501_03830_amd import _lib
+    return [("fp64", _lib.BSE_PREC_FP64), ("fp32_refine", _lib.BSE_PREC_FP32_REFINE)]
+
+
+def test_fullsize_closed_form_eigenvalues(ctx):
+    say(f"[full size] closed form n={N_BENCH}")
+    p = gen_closed_form(N_BENCH, seed=30)
+    A, B = torch.from_numpy(p.A), torch.from_numpy(p.B)
+    exact = np.asarray(p.exact_lambda)
+    lmax = float(exact.max())
+    for name, prec in precisions():
+        res = ctx.solve(A, B, vectors=False, prec=prec)
+        assert res["info"] == 0
+        lam = res["lam"].cpu().numpy()
+        err = float(np.max(np.abs(lam - exact))) / lmax
+        say(f"  {name}: max |lambda - exact| / lambda_max = {err:.2e}")
+        assert err <= 1e-10
+        assert np.all(np.diff(lam) >= 0)
+
+
+def _apply_H(A, B, x1, x2):
+    """H [x1; x2] with H = [[A, B], [-conj B, -conj A]] (full A, B)."""
+    top = A @ x1 + B @ x2
+    bot = -(np.conj(B @ np.conj(x1)) + np.conj(A @ np.conj(x2)))
+    return top, bot
+
+
+@pytest.mark.parametrize("which", [0, 1])
+def test_fullsize_bench_workload_sampled_pairs(ctx, which):
+    name, prec = precisions()[which]
+    say(f"[full size] benchmark workload n={N_BENCH}, {name}")
+    p = gen_bse(N_BENCH, s_a=0.3, s_b=0.05, seed=3, check_definite=False)
+    res = ctx.solve(torch.from_numpy(p.A), torch.from_numpy(p.B), d_r=torch.from_numpy(p.d), prec=prec)
+    assert res["info"] == 0
+    lam = res["lam"].cpu().numpy()
+    assert np.all(lam > 0) and np.all(np.diff(lam) >= 0)
+    n = N_BENCH
+    rng = np.random.default_rng(7)
+    idx = np.unique(np.concatenate([[0, 1, n // 2, n - 2, n - 1], rng.choice(n, 19, replace=False)]))
+    X = res["X"][:, torch.from_numpy(idx).to(res["X"].device)].cpu().numpy()   # (2n, k)
+    x1, x2 = X[:n], X[n:]
+    top, bot = _apply_H(p.A, p.B, x1, x2)
+    lmax = float(lam[-1])
+    r = np.sqrt(np.sum(np.abs(top - x1 * lam[idx]) ** 2, axis=0) + np.sum(np.abs(bot - x2 * lam[idx]) ** 2, axis=0))
+    xn = np.sqrt(np.sum(np.abs(X) ** 2, axis=0))
+    resid = float(np.max(r / (lmax * xn)))
+    G = x1.conj().T @ x1 - x2.conj().T @ x2
+    nerr = float(np.max(np.abs(G - np.eye(len(idx)))))
+    w = res["w"].cpu().numpy()
+    say(f"  {name}: sampled residual {resid:.2e}, normalisation {nerr:.2e}, "
+        f"lambda in [{lam[0]:.4f}, {lam[-1]:.4f}], sum w = {w.sum():.6f}")
+    tol = 1e-10 if name == "fp64" else 1e-6
+    assert resid <= tol
+    assert nerr <= tol
+    assert np.all(np.isfinite(w))
