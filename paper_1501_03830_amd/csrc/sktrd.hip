@@ -459,11 +459,10 @@ __global__ __launch_bounds__(64 * UW) void sk_update(const Prob* __restrict__ pr
                                                      const int* __restrict__ wgpre, int nact) {
   __shared__ double cs[2 * NBMAX];
   __shared__ double ys_row[2 * NBMAX];   // Y1 row s (v_l[s], p_l[s])
-  __shared__ double red[UW][TS];
-  __shared__ double red2[UW][TS];
-  __shared__ double pr[TS];
+  __shared__ double red[UW][TS];    // partial sums of S v
+  __shared__ double red2[UW][TS];   // panel correction of p_i
+  __shared__ double red3[UW][TS];   // panel correction of the next column
   __shared__ double red4[UW];
-  __shared__ double sval_s;
   long wid;
   const Prob& P = probs[locate_problem(wgpre, 1, nact, wid)];
   const int N = P.N;
@@ -558,9 +557,18 @@ __global__ __launch_bounds__(64 * UW) void sk_update(const Prob* __restrict__ pr
     }
     red[part][t] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   }
+  // p_i at row s (first row of block 0) is needed by every block for the
+  // next column: its S v part now, its panel part after the barrier
+  if (next_col && part == 1) {
+    const double acc = wave_sum(srow);
+    if (t == 0) red4[1] = acc;
+  }
   __syncthreads();
+  // every wave's share of the panel corrections, of p_i (from c) and of the
+  // next column (from row s of the panel, ys_row); wave 0 adds them up after
+  // one more barrier and does the rest alone
   {
-    double corr = 0.0;
+    double corr = 0.0, upd = 0.0;
     if (inrange) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
@@ -568,56 +576,45 @@ __global__ __launch_bounds__(64 * UW) void sk_update(const Prob* __restrict__ pr
         if (l < i) corr += yv[q] * cs[2 * l + 1] - yp[q] * cs[2 * l];
       }
     }
-    red2[part][t] = corr;
-  }
-  __syncthreads();
-  if (part == 0) {
-    double p = 0.0;
-    if (inrange) {
-      double y = 0.0, corr = 0.0;
-#pragma unroll
-      for (int w = 0; w < UW; ++w) {
-        y += red[w][t];
-        corr += red2[w][t];
-      }
-      p = tau * (y + corr);
-      Y1[r + (long)(2 * i + 1) * ldy] = p;
-      Y2[r + (long)(2 * i) * ldy] = p;
-      if (r > s) W[r + (long)j * ld] = vi;  // store v_i in place
-    }
-    pr[t] = p;
-  }
-  if (!next_col) return;  // uniform
-  // p_i at row s (first row of block 0), needed by every block
-  if (part == 1) {
-    const double acc = wave_sum(srow);
-    if (t == 0) red4[1] = acc;
-  } else if (part == 2) {
-    double acc = 0.0;
-    if (t < i) acc = ys_row[2 * t] * cs[2 * t + 1] - ys_row[2 * t + 1] * cs[2 * t];
-    acc = wave_sum(acc);
-    if (t == 0) red4[2] = acc;
-  }
-  __syncthreads();
-  if (tid == 0) sval_s = tau * (red4[1] + red4[2]);
-  {
-    double upd = 0.0;
-    if (r >= s + 1 && r < N) {
+    if (next_col && r >= s + 1 && r < N) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const int l = part + UW * q;
         if (l < i) upd += yv[q] * ys_row[2 * l + 1] - yp[q] * ys_row[2 * l];
       }
     }
-    red2[part][t] = upd;
+    red2[part][t] = corr;
+    red3[part][t] = upd;
+  }
+  if (next_col && part == 2) {
+    double acc = 0.0;
+    if (t < i) acc = ys_row[2 * t] * cs[2 * t + 1] - ys_row[2 * t + 1] * cs[2 * t];
+    acc = wave_sum(acc);
+    if (t == 0) red4[2] = acc;
   }
   __syncthreads();
+  if (part != 0) return;
+  double p = 0.0;
+  if (inrange) {
+    double y = 0.0, corr = 0.0;
+#pragma unroll
+    for (int w = 0; w < UW; ++w) {
+      y += red[w][t];
+      corr += red2[w][t];
+    }
+    p = tau * (y + corr);
+    Y1[r + (long)(2 * i + 1) * ldy] = p;
+    Y2[r + (long)(2 * i) * ldy] = p;
+    if (r > s) W[r + (long)j * ld] = vi;  // store v_i in place
+  }
+  if (!next_col) return;  // uniform
+  const double sval_s = tau * (red4[1] + red4[2]);
   double nrm = 0.0;
-  if (part == 0 && r >= s + 1 && r < N) {
+  if (r >= s + 1 && r < N) {
     double upd = wrs;
 #pragma unroll
-    for (int w = 0; w < UW; ++w) upd += red2[w][t];
-    upd += vi * sval_s - pr[t];
+    for (int w = 0; w < UW; ++w) upd += red3[w][t];
+    upd += vi * sval_s - p;
     // the column as stored (rounded to T) is what the next reflector sees
     const double upds = (double)(WT)upd;
     W[r + (long)s * ld] = (WT)upd;
@@ -632,8 +629,10 @@ __global__ __launch_bounds__(64 * UW) void sk_update(const Prob* __restrict__ pr
     }
     if (r >= s + 2) nrm = upds * upds;
   }
-  nrm = block_sum(nrm, red4);
-  if (tid == 0) normpart[b] = nrm;
+  // only wave 0 holds rows of the column: a wave sum (the block sum it
+  // replaces added the other waves' zeros)
+  nrm = wave_sum(nrm);
+  if (t == 0) normpart[b] = nrm;
 }
 
 // Workgroup prefixes of a batch launch at column j: wgpre[2p] (matvec) and
