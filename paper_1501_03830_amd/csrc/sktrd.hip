@@ -363,13 +363,18 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
   const auto colbase = W + col0 * ld;
   // The tile loop is a software pipeline: the loads of the next step are
   // issued before the current one is used, with no barrier, no global store
-  // and no dependent load inside the loop (v at the tile's rows is fetched
-  // with the tile).  A step is one 64-row tile in FP64 and two in FP32, so
-  // that an FP32 wave has as many bytes in flight as an FP64 one.  The first
-  // step's loads and x at the strip's columns are issued before the
-  // reflector is known.
-  constexpr int SP = sizeof(WT) == 4 ? 2 : 1;   // tiles per step
-  auto load_step = [&](int rl, WT(&t)[SP][16], double(&x)[SP]) {
+  // and no dependent load inside the loop (x at the tile's rows is fetched
+  // with the tile).  Two register buffers take turns (the loop is unrolled
+  // by two): copying a prefetch buffer into a working one made the wave wait
+  // for the prefetched loads at the end of every step.  Tile values and x
+  // stay in their storage type until used: converting an FP32 value on
+  // arrival made the wave wait for that load, and with it for every load
+  // issued before it.  The first step's loads and x at the strip's columns
+  // are issued before the reflector is known.  A step is SP = 1 tile; the
+  // array form (measured against a scalar rewrite of the same loop) compiles
+  // to fewer waits.
+  constexpr int SP = 1;   // tiles per step
+  auto load_step = [&](int rl, WT(&t)[SP][16], WT(&x)[SP]) {
 #pragma unroll
     for (int p = 0; p < SP; ++p) {
       if (p == 0 || rl + p < rl1) {
@@ -380,9 +385,9 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
       }
     }
   };
-  WT a[SP][16];
-  double xr[SP], xc[16];
-  load_step(rl0, a, xr);
+  WT bufA[SP][16], bufB[SP][16];
+  WT xA[SP], xB[SP], xc[16];
+  load_step(rl0, bufA, xA);
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const long c = col0 + q;
@@ -399,10 +404,7 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
 #pragma unroll
   for (int q = 0; q < 16; ++q) cacc[q] = 0.0;
   const bool strip_inside = C0 >= s;
-  for (int rl = rl0; rl < rl1; rl += SP) {
-    WT an[SP][16];
-    double xn[SP];
-    if (rl + SP < rl1) load_step(rl + SP, an, xn);
+  auto process_step = [&](int rl, WT(&a)[SP][16], const WT(&xr)[SP]) {
 #pragma unroll
     for (int p = 0; p < SP; ++p) {
       if (p == 0 || rl + p < rl1) {
@@ -426,14 +428,16 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
         rsum[rl + p - rl0][wv][lane] = racc;
       }
     }
-    if (rl + SP < rl1) {
-#pragma unroll
-      for (int p = 0; p < SP; ++p) {
-#pragma unroll
-        for (int q = 0; q < 16; ++q) a[p][q] = an[p][q];
-        xr[p] = xn[p];
-      }
-    }
+  };
+  for (int rl = rl0;;) {
+    if (rl + SP < rl1) load_step(rl + SP, bufB, xB);
+    process_step(rl, bufA, xA);
+    rl += SP;
+    if (rl >= rl1) break;
+    if (rl + SP < rl1) load_step(rl + SP, bufA, xA);
+    process_step(rl, bufB, xB);
+    rl += SP;
+    if (rl >= rl1) break;
   }
   // column sums over the 64 lanes: lane 4q ends with the total of column q
   const double csum = wave_sum_many(cacc);
