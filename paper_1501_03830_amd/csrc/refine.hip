@@ -104,12 +104,22 @@ __device__ inline double sym_at(const BSE_GLOBAL double* G, long ld, long i, lon
 // which perturbs Ub by about 1e-7 of the correction (far below the error the
 // sweep leaves).  Also per-tile maxima of the correction and the number of
 // clamped blocks.
+//
+// One workgroup per 32 x 32 block of pairs (k, l): it produces the four
+// output tiles at rows {k, n+k} and columns {l, n+l}, so each 2 x 2 block of
+// S and G is read once (by output element it was read four times), and every
+// global access is coalesced: the eight source tiles (S and G, four
+// quadrants) are staged in LDS, lower-triangle entries with lanes along the
+// stored rows and mirrored ones with lanes along the stored columns.
+constexpr int RFB = 32;   // pairs per block side
 __global__ __launch_bounds__(256) void k_ref_F(const Prob* __restrict__ probs, int sweep) {
+  __shared__ double tS[4][RFB][RFB + 1];   // [quadrant][l][k]
+  __shared__ double tG[4][RFB][RFB + 1];
   __shared__ double red[2][4];
   const Prob& P = probs[blockIdx.z];
-  const long N = P.N, n = P.n, ld = P.ld;
-  const long ntile = (N + 63) / 64;
-  if ((long)blockIdx.x >= ntile || (long)blockIdx.y >= ntile) return;   // uniform
+  const long n = P.n, ld = P.ld;
+  const long nblk = (n + RFB - 1) / RFB;
+  if ((long)blockIdx.x >= nblk || (long)blockIdx.y >= nblk) return;   // uniform
   if (finished_before(P, sweep)) return;
   const BSE_GLOBAL double* __restrict__ S = gbl(P.R2);
   const BSE_GLOBAL double* __restrict__ G = gbl(P.R3);
@@ -117,55 +127,99 @@ __global__ __launch_bounds__(256) void k_ref_F(const Prob* __restrict__ probs, i
   BSE_GLOBAL float* __restrict__ F32 = gbl(reinterpret_cast<float*>(P.R1));
   BSE_GLOBAL float* __restrict__ U32 = F32 + ld * ld;
   const BSE_GLOBAL double* __restrict__ Ub = gbl(basis(P, sweep));
-  const long r = (long)blockIdx.x * 64 + (threadIdx.x & 63);
-  const long c0 = (long)blockIdx.y * 64 + (threadIdx.x >> 6) * 16;
+  const long k0 = (long)blockIdx.x * RFB, l0 = (long)blockIdx.y * RFB;
+  const int tid = threadIdx.x;
+  // quadrant q = 2 qr + qc holds (row k + n qr, column l + n qc); S is
+  // skew and G symmetric, both stored as their lower triangles
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const long orow = (q >> 1) ? n : 0, ocol = (q & 1) ? n : 0;
+    // lower entries, lanes along the stored rows (k)
+    for (int idx = tid; idx < RFB * RFB; idx += 256) {
+      const int kk = idx % RFB, ll = idx / RFB;
+      const long k = k0 + kk, l = l0 + ll;
+      const long gr = k + orow, gc = l + ocol;
+      if (k < n && l < n && gr >= gc) {
+        tS[q][ll][kk] = S[gr + gc * ld];
+        tG[q][ll][kk] = G[gr + gc * ld];
+      } else if (k >= n || l >= n) {
+        tS[q][ll][kk] = 0.0;
+        tG[q][ll][kk] = 0.0;
+      }
+    }
+    // mirrored entries, lanes along the stored rows (l)
+    for (int idx = tid; idx < RFB * RFB; idx += 256) {
+      const int ll = idx % RFB, kk = idx / RFB;
+      const long k = k0 + kk, l = l0 + ll;
+      const long gr = k + orow, gc = l + ocol;
+      if (k < n && l < n && gr < gc) {
+        tS[q][ll][kk] = -S[gc + gr * ld];
+        tG[q][ll][kk] = G[gc + gr * ld];
+      }
+    }
+  }
+  __syncthreads();
+  const int kk = tid % RFB, lg = tid / RFB;   // 8 groups of 4 columns
+  const long k = k0 + kk;
   double cmax = 0.0, nclamp = 0.0;
-  if (r < N) {
-    const long k = r < n ? r : r - n;
-    const int pr = r < n ? 0 : 1;
+  if (k < n) {
     const double lk = lam[k];
-    for (int q = 0; q < 16; ++q) {
-      const long c = c0 + q;
-      if (c >= N) break;
-      const long l = c < n ? c : c - n;
-      const int qc = c < n ? 0 : 1;
-      const double rrc = ((r == c) ? 1.0 : 0.0) - sym_at(G, ld, r, c);
-      double e = 0.0;
+    for (int u = 0; u < RFB / 8; ++u) {
+      const int ll = lg * (RFB / 8) + u;
+      const long l = l0 + ll;
+      if (l >= n) break;
+      const double R11 = -tG[0][ll][kk], R12 = -tG[1][ll][kk];
+      const double R21 = -tG[2][ll][kk], R22 = -tG[3][ll][kk];
+      double e11 = 0.0, e12 = 0.0, e21 = 0.0, e22 = 0.0;
       if (k != l) {
-        const double ll = lam[l];
-        const long ka = k, kb = n + k, la = l, lb = n + l;
-        const double S11 = skew_at(S, ld, ka, la), S12 = skew_at(S, ld, ka, lb);
-        const double S21 = skew_at(S, ld, kb, la), S22 = skew_at(S, ld, kb, lb);
-        const double R11 = -sym_at(G, ld, ka, la), R12 = -sym_at(G, ld, ka, lb);
-        const double R21 = -sym_at(G, ld, kb, la), R22 = -sym_at(G, ld, kb, lb);
+        const double ll_ = lam[l];
+        const double S11 = tS[0][ll][kk], S12 = tS[1][ll][kk];
+        const double S21 = tS[2][ll][kk], S22 = tS[3][ll][kk];
         // C = -S_kl - (R_kl sigma_l + sigma_k R_kl) / 2
-        const double c11 = -S11 - 0.5 * (-R12 * ll + lk * R21);
-        const double c12 = -S12 - 0.5 * (R11 * ll + lk * R22);
-        const double c21 = -S21 - 0.5 * (-R22 * ll - lk * R11);
-        const double c22 = -S22 - 0.5 * (R21 * ll - lk * R12);
-        if (fabs(lk - ll) <= DEGEN * fmax(lk, ll)) {
+        const double c11 = -S11 - 0.5 * (-R12 * ll_ + lk * R21);
+        const double c12 = -S12 - 0.5 * (R11 * ll_ + lk * R22);
+        const double c21 = -S21 - 0.5 * (-R22 * ll_ - lk * R11);
+        const double c22 = -S22 - 0.5 * (R21 * ll_ - lk * R12);
+        if (fabs(lk - ll_) <= DEGEN * fmax(lk, ll_)) {
           // degenerate pair: g22 - g11 and g12 + g21 are fixed, the rest is free
-          const double lm = 0.5 * (lk + ll);
+          const double lm = 0.5 * (lk + ll_);
           const double d = (c12 + c21) / (4.0 * lm), h = (c11 - c22) / (4.0 * lm);
-          e = pr == 0 ? (qc == 0 ? -d : h) : (qc == 0 ? h : d);
+          e11 = -d;
+          e12 = h;
+          e21 = h;
+          e22 = d;
         } else {
-          const double det = lk * lk - ll * ll;
-          const double e11 = (c12 * ll - lk * c21) / det;
-          const double e22 = (-ll * c21 + lk * c12) / det;
-          const double e12 = (-ll * c11 - lk * c22) / det;
-          const double e21 = (ll * c22 + lk * c11) / det;
-          const double emax = fmax(fmax(fabs(e11), fabs(e12)), fmax(fabs(e21), fabs(e22)));
+          const double det = lk * lk - ll_ * ll_;
+          const double f11 = (c12 * ll_ - lk * c21) / det;
+          const double f22 = (-ll_ * c21 + lk * c12) / det;
+          const double f12 = (-ll_ * c11 - lk * c22) / det;
+          const double f21 = (ll_ * c22 + lk * c11) / det;
+          const double emax = fmax(fmax(fabs(f11), fabs(f12)), fmax(fabs(f21), fabs(f22)));
           if (emax <= GCAP) {   // NaN or a close pair: orthogonalise only
-            e = pr == 0 ? (qc == 0 ? e11 : e12) : (qc == 0 ? e21 : e22);
+            e11 = f11;
+            e12 = f12;
+            e21 = f21;
+            e22 = f22;
           } else {
-            nclamp += 1.0;
+            nclamp += 4.0;   // one per output entry of the block
           }
         }
       }
-      const double f = 0.5 * rrc + e;
-      if (r != c) cmax = fmax(cmax, fabs(f));
-      F32[r + c * ld] = (float)f;
-      U32[r + c * ld] = (float)Ub[r + c * ld];
+      // F = R/2 + E at (k, l), (k, n+l), (n+k, l), (n+k, n+l); R = I - G
+      const double dg = (k == l) ? 1.0 : 0.0;
+      const double f11 = 0.5 * (dg + R11) + e11, f12 = 0.5 * R12 + e12;
+      const double f21 = 0.5 * R21 + e21, f22 = 0.5 * (dg + R22) + e22;
+      if (k != l) cmax = fmax(cmax, fmax(fabs(f11), fabs(f22)));
+      cmax = fmax(cmax, fmax(fabs(f12), fabs(f21)));
+      const long o11 = k + l * ld, o12 = k + (n + l) * ld, o21 = (n + k) + l * ld, o22 = (n + k) + (n + l) * ld;
+      F32[o11] = (float)f11;
+      F32[o12] = (float)f12;
+      F32[o21] = (float)f21;
+      F32[o22] = (float)f22;
+      U32[o11] = (float)Ub[o11];
+      U32[o12] = (float)Ub[o12];
+      U32[o21] = (float)Ub[o21];
+      U32[o22] = (float)Ub[o22];
     }
   }
   // workgroup maxima / sums
@@ -173,19 +227,20 @@ __global__ __launch_bounds__(256) void k_ref_F(const Prob* __restrict__ probs, i
     cmax = fmax(cmax, __shfl_xor(cmax, off, 64));
     nclamp += __shfl_xor(nclamp, off, 64);
   }
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
+  const int w = tid >> 6;
+  if ((tid & 63) == 0) {
     red[0][w] = cmax;
     red[1][w] = nclamp;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     double m = 0.0, cl = 0.0;
     for (int i = 0; i < 4; ++i) {
       m = fmax(m, red[0][i]);
       cl += red[1][i];
     }
-    const long t = (long)blockIdx.x + (long)blockIdx.y * ntile;
+    // one slot per block, as many blocks as 64 x 64 tiles of the N x N matrix
+    const long t = (long)blockIdx.x + (long)blockIdx.y * nblk;
     BSE_GLOBAL double* __restrict__ part = gbl(P.refmax);
     part[2 * t] = m;
     part[2 * t + 1] = cl;
