@@ -40,7 +40,7 @@ struct Setup {
   int* dstate = nullptr;    // device refinement state words, 1 per slot
   int* dreorth = nullptr;   // device Gram-Schmidt flags, 1 per slot
   double* dref = nullptr;   // device refinement maxima, 2 per slot
-  int* dwgpre = nullptr;    // device workgroup prefixes, 2 (count + 1)
+  int* dwgpre = nullptr;    // device workgroup prefixes, SKTRD_NB rows of 2 (count + 1)
   size_t total = 0;         // workspace bytes of the batch (for reports)
 };
 // Header at `header` (header_bytes(count)); descriptor slot i gets the

@@ -59,6 +59,10 @@ struct GemmParams {
 // sub-blocks of the compact-WY factor).
 constexpr int APPLYU_RB = 256;
 
+// Columns per panel of the skew tridiagonalisation (the batch header keeps
+// the workgroup prefixes of a whole panel).
+constexpr int SKTRD_NB = 64;
+
 // The products of the chain, as functions of (problem, step).
 enum GemmOp {
   GOP_NONE = 0,

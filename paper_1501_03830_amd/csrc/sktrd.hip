@@ -42,7 +42,7 @@ namespace bse {
 namespace {
 
 constexpr int TS = 64;       // symv tile
-constexpr int NBMAX = 64;    // panel width bound
+constexpr int NBMAX = SKTRD_NB;   // panel width
 constexpr int DUTY_BLK = 16; // row blocks per workgroup of the panel dot products
 constexpr int TMAX = 16;     // row tiles per strip workgroup (upper bound)
 constexpr int UPD_SMALL = 48;   // row blocks up to which the update uses 4 wavefronts
@@ -163,7 +163,8 @@ __host__ __device__ inline long symv_workgroups(int nblk, int T, int i) {
 // Problem and workgroup index of this workgroup.  A single problem (or a
 // launch sized per problem) has its problem in blockIdx.z; a batch launch puts
 // all problems' workgroups back to back, problem p from wgpre[2p + which] on
-// (the prefixes of the per-problem counts, written by k_plan just before).
+// (the prefixes of the per-problem counts, written by k_plan at the start of
+// the panel).
 __device__ inline int locate_problem(const int* __restrict__ wgpre, int which, int nact, long& wid) {
   wid = blockIdx.x;
   if (wgpre == nullptr) return blockIdx.z;
@@ -639,17 +640,27 @@ __global__ __launch_bounds__(64 * UW) void sk_update(const Prob* __restrict__ pr
   if (t == 0) normpart[b] = nrm;
 }
 
-// Workgroup prefixes of a batch launch at column j: wgpre[2p] (matvec) and
-// wgpre[2p + 1] (update) count the workgroups of the active problems before p.
+// Workgroup prefixes of the batch launches of a whole panel, one workgroup
+// per column j = k0 + blockIdx.x (i = blockIdx.x): row i of wgpre holds
+// wgpre[2p] (matvec) and wgpre[2p + 1] (update), the workgroups of the
+// problems before p that are still active at column j (problems are sorted
+// by decreasing order, so the active ones come first and the others count
+// zero).  One launch per panel instead of one per column.
 template <class WT>
-__global__ __launch_bounds__(1024) void k_plan(const Prob* __restrict__ probs, int nact, int j,
-                                               int i, int* __restrict__ wgpre) {
+__global__ __launch_bounds__(1024) void k_plan(const Prob* __restrict__ probs, int nact, int k0,
+                                               int stride, int* __restrict__ wgpre_all) {
   __shared__ int ssum[1024], usum[1024];
   const int tid = threadIdx.x;
+  const int i = blockIdx.x, j = k0 + i;
+  int* __restrict__ wgpre = wgpre_all + (long)i * stride;
   const int per = (nact + 1023) / 1024;
   const int p0 = min(nact, tid * per), p1 = min(nact, p0 + per);
   auto counts = [&](int p, int& cs, int& cu) {
     const int N = probs[p].N;
+    if (j >= N - 2) {   // this problem is already reduced
+      cs = cu = 0;
+      return;
+    }
     const int s = j + 1;
     const int nblk = (N - 1) / TS - s / TS + 1;
     cs = (int)symv_workgroups(nblk, symv_tiles<WT>(nblk), i);
@@ -726,10 +737,16 @@ static int sktrd_run(hipStream_t s, const Batch& b, KernelTimer* timer) {
   const int N0 = b.maxN();
   if (N0 < 2) return 0;
   const int nb = NBMAX;
+  const int stride = 2 * (b.count + 1);   // ints per column of the prefix table
   for (int k0 = 0; k0 <= N0 - 2; k0 += nb) {
     const int nstart = b.active_N_above(k0 + 1);   // N - 2 >= k0
     sk_start<WT><<<dim3(1, 1, (unsigned)nstart), 256, 0, s>>>(b.dev, k0);
     BSE_LAUNCHED();
+    const int ncols = min(nb, N0 - 2 - k0);   // columns of this panel with a reflector
+    if (nstart > 1 && b.wgpre != nullptr && ncols > 0) {   // the batch launches of this panel
+      k_plan<WT><<<(unsigned)ncols, 1024, 0, s>>>(b.dev, nstart, k0, stride, b.wgpre);
+      BSE_LAUNCHED();
+    }
     for (int i = 0; i < nb; ++i) {
       const int j = k0 + i;
       if (j >= N0 - 2) break;  // the last column has no reflector to apply
@@ -746,11 +763,7 @@ static int sktrd_run(hipStream_t s, const Batch& b, KernelTimer* timer) {
         gx += symv_workgroups(nbq, symv_tiles<WT>(nbq), i);
         gu += nbq;
       }
-      if (packed) {
-        k_plan<WT><<<1, 1024, 0, s>>>(b.dev, nact, j, i, b.wgpre);
-        BSE_LAUNCHED();
-      }
-      const int* pre = packed ? b.wgpre : nullptr;
+      const int* pre = packed ? b.wgpre + (long)i * stride : nullptr;
       const dim3 gs = packed ? dim3((unsigned)gx, 1, 1) : dim3((unsigned)gx, 1, (unsigned)nact);
       const dim3 gup = packed ? dim3((unsigned)gu, 1, 1) : dim3((unsigned)nblk0, 1, (unsigned)nact);
       const bool timed = timer && timer->used + 2 <= timer->cap;

@@ -115,7 +115,11 @@ static size_t hdr_reorth_off(int count) { return hdr_state_off(count) + (size_t)
 static size_t hdr_ref_off(int count) { return hdr_reorth_off(count) + (size_t)round_up((long)(count * sizeof(int)), 256); }
 static size_t hdr_gdef_off(int count) { return hdr_ref_off(count) + (size_t)round_up((long)(count * 2 * sizeof(double)), 256); }
 static size_t hdr_wgpre_off(int count) { return hdr_gdef_off(count) + (size_t)round_up((long)(count * sizeof(double)), 256); }
-size_t header_bytes(int count) { return hdr_wgpre_off(count) + (size_t)round_up((long)(2 * (count + 1) * sizeof(int)), 256); }
+// workgroup prefixes of the tridiagonalisation: one row of 2 (count + 1) per
+// column of a panel
+size_t header_bytes(int count) {
+  return hdr_wgpre_off(count) + (size_t)round_up((long)(SKTRD_NB * 2 * (count + 1) * sizeof(int)), 256);
+}
 
 // Workspace pointers of one problem.
 static void bind_problem(const Plan& p, char* base, Prob* P) {
