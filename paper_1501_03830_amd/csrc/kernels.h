@@ -17,8 +17,9 @@ struct Batch {
   int count = 0;
   const Prob* host = nullptr;  // host mirror, sorted by decreasing N
   const Prob* dev = nullptr;   // device copy
-  // device scratch of 2 (count + 1) ints: per-launch workgroup prefixes that
-  // let a batch's reduction kernels run without empty workgroups
+  // device scratch of SKTRD_NB rows of 2 (count + 1) ints: the workgroup
+  // prefixes of one panel's launches, which let a batch's reduction kernels
+  // run without empty workgroups
   int* wgpre = nullptr;
   int maxN() const { return count ? host[0].N : 0; }
   int maxn() const { return count ? host[0].n : 0; }
