@@ -330,13 +330,21 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ 
   const int tiles_m = (p.M + BM - 1) / BM, tiles_n = (p.N + BN - 1) / BN;
   const long ntiles = (p.M <= 0 || p.N <= 0) ? 0
                       : ((p.c_uplo == 1 || p.c_uplo == 2) ? (long)tiles_m * (tiles_m + 1) / 2 : (long)tiles_m * tiles_n);
-  // With a triangular operand the tiles' K ranges differ: a contiguous range
-  // per XCD would give one XCD all the long tiles, so those products keep the
+  // With a triangular operand the tiles' K ranges differ.  A triangular A
+  // makes K depend on the tile row only: tiles go column by column (rows
+  // fastest) and every XCD takes a contiguous range, i.e. whole columns with
+  // all their K lengths, and the B panel of a column stays on one XCD.  With
+  // a triangular B, K depends on the column, and a contiguous range per XCD
+  // would give one XCD all the long tiles, so those products keep the
   // dispatch order (long and short tiles interleaved over the XCDs).
+  // The remap covers this problem's own tiles (a batch's grid is sized for
+  // its largest problem, and a remap over the whole grid would put all of a
+  // small problem's tiles on the first XCDs).
   const bool tri = p.a_tri || p.b_tri;
-  long tile = tri ? (long)blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
+  const long total = ntiles * p.splits;
+  if ((long)blockIdx.x >= total) return;  // uniform: beyond this problem's tiles
+  long tile = p.b_tri ? (long)blockIdx.x : xcd_remap(blockIdx.x, total);
   int slice = 0;
-  if (tile >= ntiles * p.splits) return;  // uniform: beyond this problem's tiles
   if (p.splits > 1) {
     slice = (int)(tile % p.splits);
     tile /= p.splits;
@@ -586,9 +594,11 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const Prob* __restrict__ 
   const BSE_GLOBAL float* __restrict__ Bg = gbl(p.Bf);
   const int tiles_m = (p.M + TBM - 1) / TBM, tiles_n = (p.N + TBN - 1) / TBN;
   const long ntiles = (p.M <= 0 || p.N <= 0) ? 0 : (long)tiles_m * tiles_n;
-  long tile = xcd_remap(blockIdx.x, gridDim.x);
+  // remap over this problem's own tiles (see the FP64 kernel)
+  const long total = ntiles * p.splits;
+  if ((long)blockIdx.x >= total) return;  // uniform: beyond this problem's tiles
+  long tile = xcd_remap(blockIdx.x, total);
   int slice = 0;
-  if (tile >= ntiles * p.splits) return;  // uniform: beyond this problem's tiles
   if (p.splits > 1) {
     slice = (int)(tile % p.splits);
     tile /= p.splits;
