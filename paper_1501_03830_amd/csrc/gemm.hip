@@ -720,6 +720,38 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const Prob* __restrict__ 
         }
     }
     __syncthreads();
+    if (p.Cf && !split) {
+      // FP32 C (the basis update of the mixed back-transformation): 8 old
+      // values per batch, kept in FP32 (8 registers, as the 4 doubles below)
+      constexpr int PF = 8, NBF = EC * TBM / (256 * PF);
+      static_assert(NBF * 256 * PF == EC * TBM, "epilogue pass is not a whole number of batches");
+      const bool read_cf = p.beta != 0.0;
+#pragma unroll
+      for (int h = 0; h < NBF; ++h) {
+        bool ok[PF];
+        float cold[PF];
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+          const int idx = tid + 256 * (h * PF + u);
+          const int rl = idx % TBM, cl = idx / TBM;
+          const int row = i0 + rl, col = j0 + pass * EC + cl;
+          ok[u] = row < p.M && col < p.N;
+          cold[u] = 0.0f;
+          if (ok[u] && read_cf) cold[u] = gbl(p.Cf)[(long)row + (long)col * p.ldc];
+        }
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+          if (!ok[u]) continue;
+          const int idx = tid + 256 * (h * PF + u);
+          const int rl = idx % TBM, cl = idx / TBM;
+          const int row = i0 + rl, col = j0 + pass * EC + cl;
+          const double out = p.alpha * (double)Cs[cl * (TBM + 1) + rl];
+          const double res = read_cf ? out + p.beta * (double)cold[u] : out;
+          gbl(p.Cf)[(long)row + (long)col * p.ldc] = (float)res;
+        }
+      }
+      continue;
+    }
     // the old C values of 4 elements per thread are loaded before any of
     // them is stored (one round trip per element otherwise; 4 keeps the
     // main loop's occupancy)
