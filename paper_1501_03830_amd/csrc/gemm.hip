@@ -526,6 +526,38 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ 
         }
       }
     __syncthreads();
+    if (p.Cf && !split) {
+      // FP32 C (the rank-2k update of the FP32 copy of W): the chunk's old
+      // values in one batch, kept in FP32 (as many registers as 8 doubles)
+      constexpr int PF = 2 * PER, NBF = EC * BM / (256 * PF);
+      static_assert(NBF * 256 * PF == EC * BM, "epilogue chunk is not a whole number of batches");
+#pragma unroll
+      for (int h = 0; h < NBF; ++h) {
+        bool ok[PF];
+        float cold[PF];
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+          const int idx = tid + 256 * (h * PF + u);
+          const int rl = idx % BM, cl = c0 + idx / BM;
+          const int row = i0 + rl, col = j0 + cl;
+          ok[u] = row < p.M && col < p.N && !((p.c_uplo == 1 || p.c_uplo == 3) && row < col) &&
+                  !(p.c_uplo == 2 && row <= col);
+          cold[u] = 0.0f;
+          if (ok[u] && read_c) cold[u] = gbl(p.Cf)[(long)row + (long)col * p.ldc];
+        }
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+          if (!ok[u]) continue;
+          const int idx = tid + 256 * (h * PF + u);
+          const int rl = idx % BM, cl = c0 + idx / BM;
+          const int row = i0 + rl, col = j0 + cl;
+          const double out = p.alpha * Cs[(cl - c0) * (BM + 1) + rl];
+          const double res = read_c ? out + p.beta * (double)cold[u] : out;
+          gbl(p.Cf)[(long)row + (long)col * p.ldc] = (float)res;
+        }
+      }
+      continue;
+    }
 #pragma unroll
     for (int h = 0; h < NBAT; ++h) {
       bool ok[PER];
