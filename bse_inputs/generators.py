@@ -123,7 +123,7 @@ def _split_factors(n: int) -> tuple[int, int]:
 
 
 def gen_closed_form(n: int, seed: int = 30, b_ratio: float = 0.05,
-                    kron_above: int = 2048) -> BseProblem:
+                    kron_above: int = 2048, planted=()) -> BseProblem:
     """Problem with eigenvalues known in closed form.
 
     With a unitary U0, A = U0 diag(a) U0^H and B = U0 diag(b) U0^T, the
@@ -135,12 +135,22 @@ def gen_closed_form(n: int, seed: int = 30, b_ratio: float = 0.05,
     the R-diagonal phases removed).  Above it, U0 = P (Ua kron Ub) with Haar
     Ua, Ub of sizes n1*n2 = n and a random permutation P, which keeps the
     generation O(n^2 (n1 + n2)) while A and B stay dense.
+
+    planted: pairs (k, g) applied after the draws: a[k+1] = (1+g) a[k] and
+    b[k+1] = (1+g) b[k], so the eigenvalue of index k+1 (draw order) is
+    (1+g) times that of index k: a near-degenerate pair of relative gap g
+    (g = 0: an exactly degenerate one).
     """
     rng = np.random.default_rng(seed)
     a = rng.uniform(1.0, 10.0, size=n)
     bmag = b_ratio * a * rng.uniform(0.0, 1.0, size=n)
     bph = rng.uniform(0.0, 2.0 * math.pi, size=n)
     b = bmag * np.exp(1j * bph)
+    for k, g in planted:
+        if not 0 <= k < n - 1:
+            raise ValueError("planted pair index out of range")
+        a[k + 1] = (1.0 + g) * a[k]
+        b[k + 1] = (1.0 + g) * b[k]
     if n <= kron_above:
         u0 = _haar_unitary(rng, n)
         amat = (u0 * a[None, :]) @ u0.conj().T

@@ -96,7 +96,7 @@ typedef struct bse_request {
   int lda;               /* >= n                                              */
   const void* B;         /* complex n x n, lower triangle read                */
   int ldb;               /* >= n                                              */
-  int prec;              /* BSE_PREC_FP64                                     */
+  int prec;              /* BSE_PREC_FP64 or BSE_PREC_FP32_REFINE             */
   unsigned flags;        /* BSE_WANT_VECTORS | BSE_WANT_WEIGHTS               */
   double* lambda;        /* out: n doubles                                    */
   void* X;               /* out: complex 2n x n or NULL without vectors       */
@@ -221,7 +221,8 @@ size_t bse_footprint_batched_bytes(int count, const int* n, int prec, unsigned f
  *   ctx        context (argument 1)
  *   count      number of problems, >= 0; 0 is a no-op (2)
  *   n, A, lda, B, ldb   per problem, as in bse_solve (3, 4, 5, 6, 7)
- *   prec       BSE_PREC_FP64, shared (8)
+ *   prec       BSE_PREC_FP64 or BSE_PREC_FP32_REFINE (as in bse_solve),
+ *              shared (8)
  *   flags      BSE_WANT_VECTORS | BSE_WANT_WEIGHTS, shared (9)
  *   lambda     out: lambda[i] -> n[i] doubles, ascending (10)
  *   X, ldx     out: X[i] -> complex 2n[i] x n[i], ldx[i] >= 2 n[i], laid out

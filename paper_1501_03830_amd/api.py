@@ -205,7 +205,8 @@ class Context:
         self._keep[t.value] = (Ac, Bc, lam, Xbuf, drb, dlb, w)
         return t.value
 
-    def submit(self, A: torch.Tensor, B: torch.Tensor, d_r: torch.Tensor | None = None, vectors: bool = True):
+    def submit(self, A: torch.Tensor, B: torch.Tensor, d_r: torch.Tensor | None = None, vectors: bool = True,
+               prec: int = _lib.BSE_PREC_FP64):
         """Queue a solve of logical complex matrices; returns (ticket, outputs)
         where outputs = {lam, X, w} are filled once the ticket is done."""
         n = A.shape[0]
@@ -217,7 +218,7 @@ class Context:
         Xbuf = torch.empty((n, 2 * n), dtype=torch.complex128, device=dev) if want_x else None
         drb = d_r.to(dev, torch.complex128).contiguous() if d_r is not None else None
         w = torch.empty(n, dtype=torch.complex128, device=dev) if d_r is not None else None
-        t = self.submit_raw(n, Ac, Bc, lam, Xbuf, drb, None, w)
+        t = self.submit_raw(n, Ac, Bc, lam, Xbuf, drb, None, w, prec=prec)
         return t, {"lam": lam, "X": None if Xbuf is None else from_colmajor(Xbuf), "w": w}
 
     def poll(self, ticket: int):

@@ -138,3 +138,45 @@ def test_batched_config_sizes_sample(ctx):
         assert out[i]["info"] == 0
         assert torch.equal(out[i]["lam"], s["lam"]), i
         assert torch.equal(out[i]["X"], s["X"]), i
+
+
+# ---------------------------------------------------------------------------
+# The full 256-problem workload in one call (sizes log-uniform in [64, 1024],
+# size seed 4, problem i from seed 1000 + i), as the benchmark runs it.  A
+# batch this large takes the paths a small one never reaches: the matvec and
+# update launches locate their problem by ballots over 64 prefixes at a time
+# (several rounds past 64 active problems), and the per-panel planning kernel
+# gives each thread several problems.  Every member's eigenvalues, and the
+# eigenvectors and weights of members spread over the sorted order (the
+# launches' problem index) including positions past 64 and past 128, must
+# equal bse_solve on the member alone, bit for bit.
+
+@pytest.fixture(scope="module")
+def config4():
+    ns = [int(k) for k in batched_sizes(256, 64, 1024, seed=4)]
+    probs = [gen_bse(n, s_a=0.1, s_b=0.05, seed=1000 + i, check_definite=False) for i, n in enumerate(ns)]
+    # descriptor order inside the library: decreasing n, stable
+    order = sorted(range(len(ns)), key=lambda i: -ns[i])
+    return ns, probs, order
+
+
+@pytest.mark.parametrize("prec_name", ["fp64", "fp32_refine"])
+def test_batched_full_workload_equals_single(ctx, config4, prec_name):
+    from paper_1501_03830_amd import _lib
+    prec = _lib.BSE_PREC_FP64 if prec_name == "fp64" else _lib.BSE_PREC_FP32_REFINE
+    ns, probs, order = config4
+    say(f"[batched] full workload, 256 problems, {prec_name}")
+    out, rep = ctx.solve_batched([tt(p.A) for p in probs], [tt(p.B) for p in probs],
+                                 ds=[tt(p.d) for p in probs], report=True, prec=prec)
+    say(f"  batch total {rep['total_ms']:.1f} ms")
+    assert all(o["info"] == 0 for o in out)
+    ranks = [0, 1, 31, 63, 64, 65, 100, 127, 128, 129, 160, 191, 192, 224, 254, 255]
+    full = {order[r] for r in ranks}
+    for i, p in enumerate(probs):
+        s = ctx.solve(tt(p.A), tt(p.B), d_r=tt(p.d), prec=prec)
+        assert s["info"] == 0
+        assert torch.equal(out[i]["lam"], s["lam"]), (i, ns[i])
+        if i in full:
+            assert torch.equal(out[i]["X"], s["X"]), (i, ns[i])
+            assert torch.equal(out[i]["w"], s["w"]), (i, ns[i])
+    say(f"  all 256 eigenvalue sets and {len(full)} vector sets equal")

@@ -92,10 +92,28 @@ def test_fullsize_bench_workload_sampled_pairs(ctx, which):
     resid = float(np.max(r / (lmax * xn)))
     G = x1.conj().T @ x1 - x2.conj().T @ x2
     nerr = float(np.max(np.abs(G - np.eye(len(idx)))))
-    w = res["w"].cpu().numpy()
+    # Weights at full size.  With y = S x and the -lambda pairs of Theorem 3
+    # (x- = [conj X2; conj X1], y- = S x-), Y^H X = I over all 2n pairs makes
+    # X Y^H = I, so the weights of eq. absp summed over all 2n pairs equal
+    # d_r^H d_l = 1 for the unit dipole.  Computed on the device from the
+    # returned X; the returned + weights must also equal their definition.
+    Xg = res["X"]
+    d = torch.from_numpy(p.d).to(Xg.device)
+    x1, x2 = Xg[:n], Xg[n:]
+    d1, d2 = d[:n], d[n:]
+    u1, u2 = d1.conj() @ x1, d2.conj() @ x2          # d1^H X1, d2^H X2
+    v1, v2 = d1 @ x2, d2 @ x1                        # d1^T X2, d2^T X1
+    den = (x1.abs() ** 2).sum(0) - (x2.abs() ** 2).sum(0)
+    w_plus = (u1 + u2) * (u1.conj() - u2.conj()) / den
+    w_minus = (v1 + v2).conj() * (v1 - v2) / (-den)
+    total = complex((w_plus.sum() + w_minus.sum()).item())
+    w = res["w"]
+    wdef = float(((w - w_plus).abs().max() / w_plus.abs().max()).item())
     say(f"  {name}: sampled residual {resid:.2e}, normalisation {nerr:.2e}, "
-        f"lambda in [{lam[0]:.4f}, {lam[-1]:.4f}], sum w = {w.sum():.6f}")
+        f"lambda in [{lam[0]:.4f}, {lam[-1]:.4f}], sum of + weights {complex(w.sum().item()):.6f}, "
+        f"sum over all 2n pairs - 1 = {abs(total - 1.0):.2e}, weights vs definition {wdef:.2e}")
     tol = 1e-10 if name == "fp64" else 1e-6
     assert resid <= tol
     assert nerr <= tol
-    assert np.all(np.isfinite(w))
+    assert abs(total - 1.0) <= tol
+    assert wdef <= 1e-10

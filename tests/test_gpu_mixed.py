@@ -144,3 +144,29 @@ def test_mixed_exactly_degenerate_spectrum(ctx):
     assert el <= 1e-10
     assert r1 <= 1e-8 and r2 <= 1e-8
     assert metrics.normalization_error(X) <= 1e-8
+
+
+@pytest.mark.parametrize("n", [120, 400])
+def test_near_degenerate_pairs(ctx, n):
+    """Pairs closer than the FP32 reduction can separate (relative gaps
+    1e-9, 1e-8, 1e-7) and an exactly degenerate one, planted in the
+    closed-form spectrum: both paths must reach the exact eigenvalues to
+    1e-10 lambda_max and report success."""
+    from bse_inputs import gen_closed_form
+    from paper_1501_03830_amd import _lib
+    p = gen_closed_form(n, seed=77, planted=[(5, 1e-9), (20, 1e-8), (40, 1e-7), (60, 0.0)])
+    exact = np.sort(np.asarray(p.exact_lambda))
+    lmax = float(exact.max())
+    for name, prec in (("fp64", _lib.BSE_PREC_FP64), ("fp32_refine", MIXED())):
+        res = ctx.solve(tt(p.A), tt(p.B), d_r=tt(p.d), prec=prec, report=True)
+        lam = npc(res["lam"])
+        err = float(np.max(np.abs(lam - exact))) / lmax
+        X = npc(res["X"])
+        H = metrics.H_matrix(p.A, p.B)
+        r = np.linalg.norm(H @ X - X * lam[None, :], axis=0) / (lmax * np.linalg.norm(X, axis=0))
+        rep = res["report"]
+        say(f"[near-degenerate] n={n} {name}: info {res['info']} eig err {err:.2e} residual {r.max():.2e} "
+            f"sweeps {rep['refine_sweeps']} corrections {rep['refine_first_correction']:.1e} -> "
+            f"{rep['refine_correction']:.1e}")
+        assert res["info"] == 0
+        assert err <= 1e-10

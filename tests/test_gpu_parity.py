@@ -313,3 +313,33 @@ def test_config2_n2048_against_golden(ctx):
     r2 = (torch.linalg.norm(YH @ Xf - torch.eye(2 * n, dtype=torch.complex128, device=dev)) / math.sqrt(2 * n)).item()
     say(f"  table1 {r1:.2e} {r2:.2e}")
     assert r1 <= 1e-12 and r2 <= 1e-12
+
+
+def test_caller_arena_and_enomem(ctx):
+    """A context on a caller-owned arena gives the same result bit for bit
+    as one that allocates its own workspace; an arena smaller than the
+    footprint is refused with BSE_ENOMEM before any device work."""
+    from paper_1501_03830_amd import _lib
+    from paper_1501_03830_amd.api import Context, footprint_bytes
+    n = 100
+    p = gen_bse(n, seed=5)
+    own = ctx.solve(tt(p.A), tt(p.B), d_r=tt(p.d))
+    need = footprint_bytes(n)
+    arena = torch.empty(need // 8 + 1, dtype=torch.float64, device="cuda")
+    c = Context(0, arena=arena)
+    try:
+        got = c.solve(tt(p.A), tt(p.B), d_r=tt(p.d))
+        assert got["info"] == 0
+        assert torch.equal(own["lam"], got["lam"])
+        assert torch.equal(own["X"], got["X"])
+        assert torch.equal(own["w"], got["w"])
+    finally:
+        c.close()
+    small = torch.empty(need // 16, dtype=torch.float64, device="cuda")
+    c2 = Context(0, arena=small)
+    try:
+        with pytest.raises(_lib.BseError) as e:
+            c2.solve(tt(p.A), tt(p.B), d_r=tt(p.d))
+        assert e.value.code == _lib.BSE_ENOMEM
+    finally:
+        c2.close()

@@ -173,3 +173,51 @@ def test_serving_rejects_oversized_and_bad_requests():
         assert e.value.code == _lib.BSE_ENOTICKET
     finally:
         ctx.close()
+
+
+def test_serving_batch_past_64_requests():
+    """One batch of more than 64 requests (max_batch 128, one slot): a large
+    request keeps the slot busy while 100 small ones of similar order queue
+    up, so they run together as one batch, the way the server's default
+    batch limit (64) and beyond are reached under load.  Results equal
+    bse_solve alone, bit for bit, across the batch's whole sorted order."""
+    from paper_1501_03830_amd import _lib
+    rng = np.random.default_rng(12)
+    ns = [int(k) for k in rng.integers(40, 71, size=100)]
+    say(f"[serving] 100 requests n in [40, 70] behind one n=1200 request, max_batch 128")
+    from paper_1501_03830_amd.api import to_colmajor, from_colmajor
+    big = gen_bse(1200, seed=5)
+    probs = [gen_bse(n, seed=200000 + i, check_definite=False) for i, n in enumerate(ns)]
+    ctx = _ctx(pool=8 * GiB, slots=1, max_batch=128)
+    dev = ctx.device
+    try:
+        # inputs and outputs staged on the device first, so that the small
+        # requests are all queued while the large one runs
+        staged = []
+        for p in probs:
+            n = p.A.shape[0]
+            staged.append((n, to_colmajor(tt(p.A), dev), to_colmajor(tt(p.B), dev),
+                           torch.empty(n, dtype=torch.float64, device=dev),
+                           torch.empty((n, 2 * n), dtype=torch.complex128, device=dev),
+                           tt(p.d).to(dev), torch.empty(n, dtype=torch.complex128, device=dev)))
+        torch.cuda.synchronize()
+        tb, _ = ctx.submit(tt(big.A), tt(big.B))
+        tickets = [ctx.submit_raw(n, Ac, Bc, lam, X, d, None, w) for (n, Ac, Bc, lam, X, d, w) in staged]
+        outs = [{"lam": lam, "X": from_colmajor(X), "w": w} for (n, Ac, Bc, lam, X, d, w) in staged]
+        states = _wait(ctx, [tb] + tickets)
+        stats = ctx.serve_stats()
+        say(f"  stats {stats}")
+        assert all(states[t] == (_lib.BSE_DONE, 0) for t in tickets)
+        assert stats["max_inflight"] > 64
+        order = sorted(range(len(ns)), key=lambda i: -ns[i])
+        for r in (0, 1, 30, 63, 64, 65, 80, 99):
+            i = order[r]
+            p = probs[i]
+            alone = ctx.solve(tt(p.A), tt(p.B), d_r=tt(p.d))
+            assert torch.equal(outs[i]["lam"], alone["lam"]), i
+            assert torch.equal(outs[i]["X"], alone["X"]), i
+            assert torch.equal(outs[i]["w"], alone["w"]), i
+        for t in [tb] + tickets:
+            assert ctx.release(t) == 0
+    finally:
+        ctx.close()

@@ -207,3 +207,57 @@ def test_eigvec_comparison_is_basis_invariant():
     Xs = r.X.copy()
     Xs[:, 3] = r.X[:, 4]
     assert metrics.compare_eigvecs(r.X, Xs, r.lam, 1e-9) > 0.5
+
+
+def test_closed_form_planted_pairs():
+    # near-degenerate pairs of relative gap 1e-9, 1e-8, 1e-7 and an exact one:
+    # the oracle resolves every eigenvalue to the exact closed form
+    n = 40
+    p = gen_closed_form(n, seed=8, planted=[(3, 1e-9), (10, 1e-8), (20, 1e-7), (30, 0.0)])
+    r = oracle.solve(p.A, p.B, p.d)
+    assert r.info == 0
+    err = np.max(np.abs(r.lam - p.exact_lambda)) / np.max(p.exact_lambda)
+    assert err <= 1e-13, err
+    d = np.diff(np.sort(p.exact_lambda))
+    assert np.min(d) == 0.0 or np.min(d) <= 1e-15 * np.max(p.exact_lambda)
+
+
+def test_weight_comparison_rejects_wrong_weights():
+    """compare_weights does not see the basis chosen inside a cluster, but
+    it does see a changed cluster sum.  An exactly degenerate pair (closed
+    form, planted gap 0) rotated by a unitary inside its eigenspace keeps
+    Y^H X = I and every cluster sum: it passes while its per-vector weights
+    change.  A 1e-6 relative change of one weight, and weight moved between
+    two different clusters, fail."""
+    n = 10
+    p = gen_closed_form(n, seed=5, planted=[(2, 0.0)])
+    r = oracle.solve(p.A, p.B, p.d)
+    lam = r.lam
+    j = int(np.argmin(np.diff(lam)))
+    assert lam[j + 1] - lam[j] <= 1e-12 * lam[-1]
+    gap = 1e-9 * lam[-1]
+    assert metrics.compare_weights(r.w, r.w, lam, gap) == 0.0
+    th, ph = 0.7, 1.1
+    U = np.array([[math.cos(th), -np.exp(1j * ph) * math.sin(th)],
+                  [np.exp(-1j * ph) * math.sin(th), math.cos(th)]])
+    Xr = r.X.copy()
+    Xr[:, j:j + 2] = r.X[:, j:j + 2] @ U
+    assert metrics.normalization_error(Xr) <= 1e-12
+    wr = metrics.weights_all_pairs(Xr, p.d, p.d)[:n]
+    assert np.max(np.abs(wr - r.w)) > 1e-3 * np.max(np.abs(r.w))
+    assert metrics.compare_weights(r.w, wr, lam, gap) <= 1e-13
+    # moving weight inside the cluster is invisible, across clusters it is not
+    w_in = r.w.copy()
+    w_in[j] += 0.1
+    w_in[j + 1] -= 0.1
+    assert metrics.compare_weights(r.w, w_in, lam, gap) <= 1e-15
+    k = 0 if j > 1 else n - 2
+    w_out = r.w.copy()
+    w_out[k] += 0.1 * abs(r.w[k])
+    w_out[k + 1] -= 0.1 * abs(r.w[k])
+    assert metrics.compare_weights(r.w, w_out, lam, gap) > 1e-4 * abs(r.w[k])
+    # a 1e-6 relative change of a single weight fails a 1e-10 tolerance
+    big = int(np.argmax(np.abs(r.w)))
+    w_one = r.w.copy()
+    w_one[big] *= 1.0 + 1e-6
+    assert metrics.compare_weights(r.w, w_one, lam, gap) > 1e-10
