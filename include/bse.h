@@ -37,7 +37,10 @@
  *  the leading k x k minor of the real embedding M is not positive definite,
  *  i.e. eq. cond fails (Algorithm 1 requires it), in which case no outputs
  *  are written;  BSE_ENOMEM when a caller-provided arena is too small;
- *  BSE_EDEVICE on a HIP runtime error (details from bse_last_error()).
+ *  BSE_ENOCONV when the FP64 refinement of BSE_PREC_FP32_REFINE did not meet
+ *  its stopping test within its sweep limit (outputs are written from the
+ *  last sweep);  BSE_EDEVICE on a HIP runtime error (details from
+ *  bse_last_error()).
  */
 #ifndef BSE_H_
 #define BSE_H_
@@ -55,6 +58,9 @@ extern "C" {
 #define BSE_ENOTICKET (-1002)
 #define BSE_EUNSUPPORTED (-1003)
 #define BSE_EBUSY (-1004)
+#define BSE_ENOCONV (-1005)   /* BSE_PREC_FP32_REFINE: the refinement did not
+                                 meet its stopping test within its sweep limit;
+                                 the outputs hold the last sweep's result     */
 
 /* precision policies */
 #define BSE_PREC_FP64 0        /* every stage in FP64                          */
@@ -181,10 +187,13 @@ size_t bse_footprint_bytes(int n, int prec, unsigned flags);
  *            then the eigenpairs are refined in FP64 against the FP64 W by
  *            sweeps of an Ogita-Aishima-type iteration on the real Schur
  *            form of W (not in the paper), until the largest correction is
- *            below 1e-2 with no near-degenerate pair left out (at most 4
- *            sweeps); eigenvalues are then taken from the refined basis
- *            (error about 3.5e-5 x correction^4 relative, i.e. below 4e-13;
- *            eigenvector error about correction^2) (7)
+ *            below 1e-2 with no pair left out (at most 6 sweeps; pairs closer
+ *            than 1e-6 relative, which the FP32 reduction cannot separate,
+ *            are resolved by an exact FP64 rotation of their cluster);
+ *            eigenvalues are then taken from the refined basis (error about
+ *            3.5e-5 x correction^4 relative, i.e. below 4e-13; eigenvector
+ *            error about correction^2).  Returns BSE_ENOCONV when the sweep
+ *            limit is reached first (7)
  *   flags    BSE_WANT_VECTORS | BSE_WANT_WEIGHTS (8)
  *   lambda   out: n doubles, the positive eigenvalues ascending (9)
  *   X, ldx   out: complex 2n x n, ldx >= 2n; rows 0..n-1 hold X1, rows

@@ -14,6 +14,7 @@ BSE_EDEVICE = -1001
 BSE_ENOTICKET = -1002
 BSE_EUNSUPPORTED = -1003
 BSE_EBUSY = -1004
+BSE_ENOCONV = -1005
 
 BSE_QUEUED, BSE_RUNNING, BSE_DONE, BSE_FAILED = 0, 1, 2, 3
 STATE_NAMES = {0: "queued", 1: "running", 2: "done", 3: "failed"}

@@ -83,7 +83,21 @@ struct Prob {
   int* reorth;          // 1: run the cluster Gram-Schmidt (header)
   double* gdef;         // largest |G - I| inside a cluster, first pass (header)
   int* perm;            // n: output column j takes eigenpair perm[j]
+  // refinement clusters of close pairs (mixed-precision path)
+  int* clstart;         // n: first pair of the cluster of pair k
+  int* clflag;          // n: at a cluster's first pair, 1 when it needs the exact rotation
+  double* clmax;        // n: at a cluster's first pair, largest entry of its rotation minus I
+  double* clT;          // n x REF_CMAX4 doubles: the rotation of the cluster starting at pair k
 };
+
+// Refinement clusters: at most this many pairs (a 2c x 2c rotation per
+// cluster, stored in 4 c_max^2 doubles at the cluster's first pair's slot).
+constexpr int REF_CMAX = 16;
+constexpr int REF_CMAX4 = 4 * REF_CMAX;
+
+// info[1] value of a mixed-precision problem whose refinement did not reach
+// its stopping test within the sweep limit (a Gram-Schmidt failure is > 0).
+constexpr int INFO_NOCONV = -1;
 
 // Address-space views of pointers taken from a descriptor.  A pointer loaded
 // from memory is generic to the compiler, which then emits flat instructions

@@ -57,4 +57,38 @@ int run_chain(Lane* L, const Setup& S, int count, bool vectors, bse_report* rep)
 
 int set_error(int code, const char* msg);
 
+// Return code of one problem from its info words: info[0] (Cholesky of M,
+// > 0: not definite) first, then info[1]: INFO_NOCONV (refinement not
+// converged) or > 0 (cluster Gram matrix not definite, with eigenvectors).
+inline int info_code(int i0, int i1, bool vectors) {
+  if (i0 != 0) return i0;
+  if (i1 == INFO_NOCONV) return BSE_ENOCONV;
+  if (vectors && i1 > 0) return BSE_EDEVICE;
+  return 0;
+}
+
+bool valid_prec(int prec);
+// Argument checks of bse_solve from argument 2 on (0 or -i with the message
+// for bse_last_error()).
+int check_solve_args(int n, const void* A, int lda, const void* B, int ldb, int prec, unsigned flags,
+                     const double* lambda, const void* X, int ldx, const void* d_r, const void* w);
+// One problem (arguments already checked) on the lane's stream, with its
+// workspace at `base`: the batch header (header_bytes(1)) and then the
+// problem (problem_bytes(2n, prec)).  Returns what bse_solve returns.
+int solve_single_in(Lane* L, char* base, int n, const void* A, int lda, const void* B, int ldb, int prec,
+                    unsigned flags, double* lambda, void* X, int ldx, const void* d_r, const void* d_l,
+                    void* w, bse_report* rep);
+
 }  // namespace bse
+
+// A context: device, the caller's stream, workspace and the request server.
+namespace bse { struct Server; }
+struct bse_ctx {
+  int device = 0;
+  void* arena = nullptr;        // caller-provided workspace (not owned)
+  size_t arena_bytes = 0;
+  void* own = nullptr;          // library-owned workspace
+  size_t own_bytes = 0;
+  bse::Lane lane;               // the caller's stream and host mirrors
+  bse::Server* server = nullptr;   // request server, made on first use
+};

@@ -21,14 +21,27 @@
 // only along the E that commute with [0 1; -1 0] (rotations inside the
 // eigenspace, which are free); the anti-commuting part, which pairs the real
 // and imaginary parts, is still determined and is applied (minimum-norm
-// solution) for pairs closer than DEGEN relative.  Any other block whose
-// solution exceeds GCAP (close but distinct eigenvalues) is left to the
-// orthogonalisation part alone, as in the original method's treatment of
-// clusters.  The error of Ub falls quadratically; a problem stops after the
-// sweep whose largest correction is below STOP_TOL with no clamped block,
-// then its eigenvalues are taken from the refined basis (error of order
-// STOP_TOL^4 relative) and sorted.  Each problem converges on its own: kernels
-// skip problems that finished in an earlier sweep.
+// solution) for pairs closer than DEGEN relative.
+//
+// Pairs closer than the FP32 reduction can resolve arrive mixed by large
+// angles, and the first-order solution for them exceeds GCAP.  As in Ogita
+// and Aishima's treatment of clustered eigenvalues, runs of consecutive pairs
+// closer than CGAP relative form clusters (at most REF_CMAX pairs), and a
+// cluster with such a block is rotated exactly: with the cluster's 2c x 2c
+// blocks G_c = R R^T and S_c of the sweep, K = R^{-1} S_c R^{-T} is skew and
+// its real Schur basis Q (pairs a, b with K a = -mu b, K b = mu a) gives the
+// cluster's columns of the new basis as Ub_c R^{-T} Q.  Q comes from Jacobi
+// on K^T K (eigenvalues mu^2, each twice) followed by Gram-Schmidt that builds
+// each pair from one vector a and b = -K a / mu.  The cluster's block of F
+// becomes R^{-T} Q - I and the first-order corrections of its columns from
+// outside the cluster are carried along (F[l, c] <- F[l, c] R^{-T} Q).  A
+// block outside any cluster whose solution exceeds GCAP is left to the
+// orthogonalisation part and counted.  The error of Ub falls quadratically; a
+// problem stops after the sweep whose largest correction is below STOP_TOL
+// with no block left out, then its eigenvalues are taken from the refined
+// basis (error of order STOP_TOL^4 relative) and sorted.  A problem still
+// short of that after MAX_SWEEPS reports INFO_NOCONV.  Each problem converges
+// on its own: kernels skip problems that finished in an earlier sweep.
 #include <cmath>
 #include <cstring>
 
@@ -39,9 +52,15 @@ namespace bse {
 
 namespace {
 
-constexpr int MAX_SWEEPS = 4;
+constexpr int MAX_SWEEPS = 6;
 constexpr double GCAP = 0.25;
 constexpr double DEGEN = 1e-10;
+// Pairs closer than this (relative) may arrive mixed by angles the
+// first-order correction cannot undo: the FP32 basis mixes a pair of
+// relative gap g by about 1e-8 / g (measured: largest first correction
+// ~1e-3 at gaps near 1e-5 on the n = 8192 workload), i.e. beyond GCAP below
+// g ~ 4e-8; 1e-6 leaves a factor of 25.
+constexpr double CGAP = 1e-6;
 // A sweep whose largest correction entry is e leaves an eigenvalue error of
 // about 3.5e-5 e^4 relative (measured on clustered s_a = 0.3 spectra,
 // e = 6e-3 .. 6e-2); e <= 1e-2 keeps it near 4e-13, far below 1e-10.
@@ -116,6 +135,7 @@ __global__ __launch_bounds__(256) void k_ref_F(const Prob* __restrict__ probs, i
   __shared__ double tS[4][RFB][RFB + 1];   // [quadrant][l][k]
   __shared__ double tG[4][RFB][RFB + 1];
   __shared__ double red[2][4];
+  __shared__ int cst[2][RFB];              // cluster starts of the k and l pairs
   const Prob& P = probs[blockIdx.z];
   const long n = P.n, ld = P.ld;
   const long nblk = (n + RFB - 1) / RFB;
@@ -129,6 +149,10 @@ __global__ __launch_bounds__(256) void k_ref_F(const Prob* __restrict__ probs, i
   const BSE_GLOBAL double* __restrict__ Ub = gbl(basis(P, sweep));
   const long k0 = (long)blockIdx.x * RFB, l0 = (long)blockIdx.y * RFB;
   const int tid = threadIdx.x;
+  if (tid < 2 * RFB) {
+    const long q = (tid < RFB ? k0 : l0 - RFB) + tid;
+    cst[tid / RFB][tid % RFB] = (q < n) ? gbl(P.clstart)[q] : -1 - tid;
+  }
   // quadrant q = 2 qr + qc holds (row k + n qr, column l + n qc); S is
   // skew and G symmetric, both stored as their lower triangles
 #pragma unroll
@@ -200,6 +224,10 @@ __global__ __launch_bounds__(256) void k_ref_F(const Prob* __restrict__ probs, i
             e12 = f12;
             e21 = f21;
             e22 = f22;
+          } else if (cst[0][kk] == cst[1][ll]) {
+            // inside a cluster: the exact rotation of the cluster replaces
+            // this block (k_ref_rr)
+            gbl(P.clflag)[cst[0][kk]] = 1;
           } else {
             nclamp += 4.0;   // one per output entry of the block
           }
@@ -247,6 +275,299 @@ __global__ __launch_bounds__(256) void k_ref_F(const Prob* __restrict__ probs, i
   }
 }
 
+// Clusters of the sweep: runs of consecutive pairs whose eigenvalue
+// estimates differ by at most CGAP relative, cut into pieces of REF_CMAX
+// pairs.  clstart[k] = first pair of k's cluster; the cluster flags and
+// maxima are cleared.  One workgroup per problem: each thread takes a chunk
+// of pairs, and the last run start before every chunk comes from a scan.
+__device__ inline bool cluster_break(const BSE_GLOBAL double* lam, int k) {
+  if (k == 0) return true;
+  const double a = lam[k], b = lam[k - 1];
+  return !(fabs(a - b) <= CGAP * fmax(a, b));
+}
+
+__global__ __launch_bounds__(1024) void k_ref_clusters(const Prob* __restrict__ probs, int sweep) {
+  __shared__ int last[1024];
+  const Prob& P = probs[blockIdx.z];
+  if (finished_before(P, sweep)) return;
+  const int n = P.n;
+  const BSE_GLOBAL double* __restrict__ lam = gbl(P.shift);
+  const int T = blockDim.x;
+  const int chunk = (n + T - 1) / T;
+  const int b = threadIdx.x * chunk, e = min(n, b + chunk);
+  int lb = -1;
+  for (int k = b; k < e; ++k)
+    if (cluster_break(lam, k)) lb = k;
+  last[threadIdx.x] = lb;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int t = 0; t < T; ++t) {
+      const int v = last[t];
+      last[t] = run;
+      if (v >= 0) run = v;
+    }
+  }
+  __syncthreads();
+  int r = last[threadIdx.x];
+  BSE_GLOBAL int* __restrict__ cs = gbl(P.clstart);
+  for (int k = b; k < e; ++k) {
+    if (cluster_break(lam, k)) r = k;
+    cs[k] = r + ((k - r) / REF_CMAX) * REF_CMAX;
+    gbl(P.clflag)[k] = 0;
+    gbl(P.clmax)[k] = 0.0;
+  }
+}
+
+// Pairs (basis columns k and n + k) of the cluster that starts at pair k0
+// with c pairs, as indices 0..2c-1 of its block.
+__device__ inline long cluster_col(int i, int c, long k0, long n) { return i < c ? k0 + i : n + k0 + (i - c); }
+
+__device__ inline int cluster_size(const BSE_GLOBAL int* cs, int k0, int n) {
+  int c = 1;
+  while (k0 + c < n && c < REF_CMAX && cs[k0 + c] == k0) ++c;
+  return c;
+}
+
+// Exact rotation of one flagged cluster (one wavefront per cluster start):
+// T = R^{-T} Q as described at the top of this file, into the cluster's
+// block of F (T - I, FP32) and its slot of clT (FP64), with max |T - I| in
+// clmax.  If G_c is not numerically positive definite or Q cannot be
+// completed, nothing is written except a large clmax (the sweep counts as
+// not converged).
+constexpr int RM = 2 * REF_CMAX;
+__global__ __launch_bounds__(64) void k_ref_rr(const Prob* __restrict__ probs, int sweep) {
+  __shared__ double Km[RM][RM + 1];
+  __shared__ double Mm[RM][RM + 1];
+  __shared__ double Vm[RM][RM + 1];
+  __shared__ double Rm[RM][RM + 1];
+  __shared__ double Qm[RM][RM + 1];
+  __shared__ double vec[RM];
+  __shared__ int ord[RM];
+  const Prob& P = probs[blockIdx.z];
+  const int n = P.n;
+  const int k0 = blockIdx.x;
+  if (k0 >= n || finished_before(P, sweep)) return;
+  const BSE_GLOBAL int* __restrict__ cs = gbl(P.clstart);
+  if (cs[k0] != k0 || gbl(P.clflag)[k0] == 0) return;
+  const int c = cluster_size(cs, k0, n);
+  const int m = 2 * c;
+  const long ld = P.ld;
+  const int lane = threadIdx.x;
+  const BSE_GLOBAL double* __restrict__ S = gbl(P.R2);
+  const BSE_GLOBAL double* __restrict__ G = gbl(P.R3);
+  for (int idx = lane; idx < m * m; idx += 64) {
+    const int i = idx % m, j = idx / m;
+    const long gi = cluster_col(i, c, k0, n), gj = cluster_col(j, c, k0, n);
+    Km[i][j] = skew_at(S, ld, gi, gj);
+    Rm[i][j] = sym_at(G, ld, gi, gj);
+  }
+  __syncthreads();
+  // G_c = R R^T, lower, column by column
+  bool ok = true;
+  for (int j = 0; j < m; ++j) {
+    const double djj = Rm[j][j];
+    ok = ok && (djj > 0.0);
+    const double d = sqrt(fmax(djj, 1e-300));
+    __syncthreads();
+    if (lane == j) Rm[j][j] = d;
+    if (lane > j && lane < m) Rm[lane][j] /= d;
+    __syncthreads();
+    for (int idx = lane; idx < m * m; idx += 64) {
+      const int i = idx % m, l = idx / m;
+      if (l > j && i >= l) Rm[i][l] -= Rm[i][j] * Rm[l][j];
+    }
+    __syncthreads();
+  }
+  // X = R^{-1} S_c (lane = column), then K = X R^{-T} (lane = row)
+  if (lane < m) {
+    for (int i = 0; i < m; ++i) {
+      double x = Km[i][lane];
+      for (int l = 0; l < i; ++l) x -= Rm[i][l] * Mm[l][lane];
+      Mm[i][lane] = x / Rm[i][i];
+    }
+  }
+  __syncthreads();
+  if (lane < m) {
+    for (int j = 0; j < m; ++j) {
+      double y = Mm[lane][j];
+      for (int l = 0; l < j; ++l) y -= Rm[j][l] * Vm[lane][l];
+      Vm[lane][j] = y / Rm[j][j];
+    }
+  }
+  __syncthreads();
+  for (int idx = lane; idx < m * m; idx += 64) {
+    const int i = idx % m, j = idx / m;
+    Km[i][j] = 0.5 * (Vm[i][j] - Vm[j][i]);
+  }
+  __syncthreads();
+  // K^T K and V = I
+  for (int idx = lane; idx < m * m; idx += 64) {
+    const int i = idx % m, j = idx / m;
+    double t = 0.0;
+    for (int l = 0; l < m; ++l) t += Km[l][i] * Km[l][j];
+    Mm[i][j] = t;
+    Vm[i][j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  // cyclic Jacobi on K^T K
+  for (int sw = 0; sw < 30; ++sw) {
+    double off = 0.0, dia = 0.0;
+    for (int idx = lane; idx < m * m; idx += 64) {
+      const int i = idx % m, j = idx / m;
+      if (i == j) dia = fmax(dia, fabs(Mm[i][j]));
+      else off = fmax(off, fabs(Mm[i][j]));
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+      off = fmax(off, __shfl_xor(off, o, 64));
+      dia = fmax(dia, __shfl_xor(dia, o, 64));
+    }
+    if (off <= 1e-15 * dia) break;
+    for (int p = 0; p < m - 1; ++p) {
+      for (int q = p + 1; q < m; ++q) {
+        const double apq = Mm[p][q];
+        if (apq == 0.0) continue;
+        const double theta = (Mm[q][q] - Mm[p][p]) / (2.0 * apq);
+        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double cr = 1.0 / sqrt(t * t + 1.0), sr = t * cr;
+        __syncthreads();
+        if (lane < m) {
+          const double mp = Mm[lane][p], mq = Mm[lane][q];
+          Mm[lane][p] = cr * mp - sr * mq;
+          Mm[lane][q] = sr * mp + cr * mq;
+          const double vp = Vm[lane][p], vq = Vm[lane][q];
+          Vm[lane][p] = cr * vp - sr * vq;
+          Vm[lane][q] = sr * vp + cr * vq;
+        }
+        __syncthreads();
+        if (lane < m) {
+          const double mp = Mm[p][lane], mq = Mm[q][lane];
+          Mm[p][lane] = cr * mp - sr * mq;
+          Mm[q][lane] = sr * mp + cr * mq;
+        }
+        __syncthreads();
+        if (lane == 0) {
+          Mm[p][q] = 0.0;
+          Mm[q][p] = 0.0;
+        }
+        __syncthreads();
+      }
+    }
+  }
+  // eigenvectors of K^T K by increasing eigenvalue
+  if (lane < m) {
+    const double d = Mm[lane][lane];
+    int rank = 0;
+    for (int j = 0; j < m; ++j) rank += (Mm[j][j] < d) || (Mm[j][j] == d && j < lane);
+    ord[rank] = lane;
+  }
+  __syncthreads();
+  // pairs (a, b = -K a / mu), each orthogonal to the pairs before it
+  int np = 0;
+  for (int r = 0; r < m && np < c; ++r) {
+    const int col = ord[r];
+    double v = (lane < m) ? Vm[lane][col] : 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int j = 0; j < np; ++j) {
+        const double qa = (lane < m) ? Qm[lane][j] : 0.0;
+        v -= wave_sum(qa * v) * qa;
+        const double qb = (lane < m) ? Qm[lane][c + j] : 0.0;
+        v -= wave_sum(qb * v) * qb;
+      }
+    }
+    const double nv = sqrt(wave_sum(v * v));
+    if (nv < 0.5) continue;
+    v /= nv;
+    if (lane < m) vec[lane] = v;
+    __syncthreads();
+    double ka = 0.0;
+    if (lane < m)
+      for (int j = 0; j < m; ++j) ka += Km[lane][j] * vec[j];
+    __syncthreads();
+    double bv = -ka;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int j = 0; j < np; ++j) {
+        const double qa = (lane < m) ? Qm[lane][j] : 0.0;
+        bv -= wave_sum(qa * bv) * qa;
+        const double qb = (lane < m) ? Qm[lane][c + j] : 0.0;
+        bv -= wave_sum(qb * bv) * qb;
+      }
+      bv -= wave_sum(v * bv) * v;
+    }
+    const double nb = sqrt(wave_sum(bv * bv));
+    if (!(nb > 0.0)) continue;
+    bv /= nb;
+    if (lane < m) {
+      Qm[lane][np] = v;
+      Qm[lane][c + np] = bv;
+    }
+    __syncthreads();
+    ++np;
+  }
+  ok = ok && (np == c);
+  if (!ok) {
+    if (lane == 0) gbl(P.clmax)[k0] = 1e300;
+    return;
+  }
+  // T = R^{-T} Q (lane = column), into Km
+  if (lane < m) {
+    for (int i = m - 1; i >= 0; --i) {
+      double t = Qm[i][lane];
+      for (int l = i + 1; l < m; ++l) t -= Rm[l][i] * Km[l][lane];
+      Km[i][lane] = t / Rm[i][i];
+    }
+  }
+  __syncthreads();
+  BSE_GLOBAL float* __restrict__ F32 = gbl(reinterpret_cast<float*>(P.R1));
+  BSE_GLOBAL double* __restrict__ Tg = gbl(P.clT) + (long)k0 * REF_CMAX4;
+  double mx = 0.0;
+  for (int idx = lane; idx < m * m; idx += 64) {
+    const int i = idx % m, j = idx / m;
+    const double t = Km[i][j], f = t - ((i == j) ? 1.0 : 0.0);
+    F32[cluster_col(i, c, k0, n) + cluster_col(j, c, k0, n) * ld] = (float)f;
+    Tg[i + j * m] = t;
+    mx = fmax(mx, fabs(f));
+  }
+  for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  if (lane == 0) gbl(P.clmax)[k0] = mx;
+}
+
+// The first-order corrections of a rotated cluster's columns from outside
+// the cluster follow the rotation: F[l, c] <- F[l, c] T for every row l
+// outside the cluster (one workgroup per cluster start).
+__global__ __launch_bounds__(256) void k_ref_rr_rows(const Prob* __restrict__ probs, int sweep) {
+  __shared__ double Ts[RM * RM];
+  const Prob& P = probs[blockIdx.z];
+  const int n = P.n;
+  const int k0 = blockIdx.x;
+  if (k0 >= n || finished_before(P, sweep)) return;
+  const BSE_GLOBAL int* __restrict__ cs = gbl(P.clstart);
+  if (cs[k0] != k0 || gbl(P.clflag)[k0] == 0) return;
+  if (!(gbl(P.clmax)[k0] < 1e300)) return;   // no rotation was made
+  const int c = cluster_size(cs, k0, n);
+  const int m = 2 * c;
+  const long ld = P.ld, N = P.N;
+  const BSE_GLOBAL double* __restrict__ Tg = gbl(P.clT) + (long)k0 * REF_CMAX4;
+  for (int idx = threadIdx.x; idx < m * m; idx += 256) Ts[idx] = Tg[idx];
+  __syncthreads();
+  BSE_GLOBAL float* __restrict__ F32 = gbl(reinterpret_cast<float*>(P.R1));
+  for (long l = threadIdx.x; l < N; l += 256) {
+    const bool inside = (l >= k0 && l < k0 + c) || (l >= n + k0 && l < n + k0 + c);
+    if (inside) continue;
+    double f[RM];
+#pragma unroll
+    for (int i = 0; i < RM; ++i) f[i] = (i < m) ? (double)F32[l + cluster_col(i, c, k0, n) * ld] : 0.0;
+#pragma unroll
+    for (int j = 0; j < RM; ++j) {
+      if (j >= m) break;
+      double t = 0.0;
+#pragma unroll
+      for (int i = 0; i < RM; ++i) t += f[i] * Ts[i + j * m];
+      F32[l + cluster_col(j, c, k0, n) * ld] = (float)t;
+    }
+  }
+}
+
 // reduce the tile maxima; decide whether this problem is done after `sweep`
 __global__ __launch_bounds__(256) void k_ref_decide(const Prob* __restrict__ probs, int sweep) {
   __shared__ double red[2][4];
@@ -260,6 +581,8 @@ __global__ __launch_bounds__(256) void k_ref_decide(const Prob* __restrict__ pro
     m = fmax(m, part[2 * t]);
     cl += part[2 * t + 1];
   }
+  // exact cluster rotations of this sweep (zero where none was made)
+  for (long k = threadIdx.x; k < P.n; k += 256) m = fmax(m, gbl(P.clmax)[k]);
   for (int off = 32; off >= 1; off >>= 1) {
     m = fmax(m, __shfl_xor(m, off, 64));
     cl += __shfl_xor(cl, off, 64);
@@ -280,6 +603,7 @@ __global__ __launch_bounds__(256) void k_ref_decide(const Prob* __restrict__ pro
     gbl(P.refout)[1] = cc;
     const bool converged = (mm < STOP_TOL) && (cc == 0.0);
     if (converged || sweep == MAX_SWEEPS - 1) *gbl(P.refstate) = sweep + 1;
+    if (!converged && sweep == MAX_SWEEPS - 1 && gbl(P.info)[1] == 0) gbl(P.info)[1] = INFO_NOCONV;
   }
 }
 
@@ -367,7 +691,13 @@ int refine_batched(hipStream_t s, const Batch& b, const RefineIO& io, RefineStat
     BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_G, sweep));
     k_ref_lambda<<<dim3((unsigned)((n0 + 63) / 64), 1, (unsigned)b.count), 64, 0, s>>>(b.dev, sweep);
     BSE_LAUNCHED();
+    k_ref_clusters<<<dim3(1, 1, (unsigned)b.count), 1024, 0, s>>>(b.dev, sweep);
+    BSE_LAUNCHED();
     k_ref_F<<<grid_NN(b), 256, 0, s>>>(b.dev, sweep);
+    BSE_LAUNCHED();
+    k_ref_rr<<<dim3((unsigned)n0, 1, (unsigned)b.count), 64, 0, s>>>(b.dev, sweep);
+    BSE_LAUNCHED();
+    k_ref_rr_rows<<<dim3((unsigned)n0, 1, (unsigned)b.count), 256, 0, s>>>(b.dev, sweep);
     BSE_LAUNCHED();
     k_ref_decide<<<dim3(1, 1, (unsigned)b.count), 256, 0, s>>>(b.dev, sweep);
     BSE_LAUNCHED();

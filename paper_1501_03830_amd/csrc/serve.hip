@@ -163,7 +163,7 @@ int solve_batch(Server* S, int k, std::vector<Req*>& batch, size_t hdr_off) {
   BSE_TRY(run_chain(L, St, count, vectors, nullptr));
   for (int i = 0; i < count; ++i) {
     const int i0 = L->hinfo[2 * i], i1 = L->hinfo[2 * i + 1];
-    batch[i]->info = (i0 != 0) ? i0 : ((vectors && i1 != 0) ? BSE_EDEVICE : 0);
+    batch[i]->info = info_code(i0, i1, vectors);
   }
   return 0;
 }

@@ -17,15 +17,6 @@
 #include "driver.h"
 #include "serve.h"
 
-struct bse_ctx {
-  int device = 0;
-  void* arena = nullptr;        // caller-provided workspace (not owned)
-  size_t arena_bytes = 0;
-  void* own = nullptr;          // library-owned workspace
-  size_t own_bytes = 0;
-  bse::Lane lane;               // the caller's stream and host mirrors
-  bse::Server* server = nullptr;   // request server, made on first use
-};
 
 namespace bse {
 
@@ -63,7 +54,7 @@ struct Plan {
          off_bt = 0, off_gscr = 0;
   size_t gscr_bytes = 0;
   // mixed-precision path only
-  size_t off_W32 = 0, off_R = 0, off_refmax = 0, off_perm = 0;
+  size_t off_W32 = 0, off_R = 0, off_refmax = 0, off_perm = 0, off_cl = 0;
   size_t total = 0;
 };
 
@@ -100,6 +91,8 @@ static Plan make_plan(long N, int prec) {
     const size_t nt = (size_t)(p.ld / 64);
     p.off_refmax = take(2 * nt * nt * sizeof(double));
     p.off_perm = take((size_t)p.n * sizeof(int));
+    // clusters: start and flag (ints), maxima and rotations (doubles)
+    p.off_cl = take((size_t)p.n * (2 * sizeof(int) + (1 + REF_CMAX4) * sizeof(double)) + 256);
   }
   p.total = cur;
   return p;
@@ -154,6 +147,11 @@ static void bind_problem(const Plan& p, char* base, Prob* P) {
     P->Z32 = reinterpret_cast<float*>(P->R4);
     P->refmax = reinterpret_cast<double*>(base + p.off_refmax);
     P->perm = reinterpret_cast<int*>(base + p.off_perm);
+    char* cl = base + p.off_cl;
+    P->clmax = reinterpret_cast<double*>(cl);
+    P->clT = P->clmax + p.n;
+    P->clstart = reinterpret_cast<int*>(P->clT + (size_t)p.n * REF_CMAX4);
+    P->clflag = P->clstart + p.n;
   }
 }
 
@@ -410,6 +408,56 @@ int run_chain(Lane* L, const Setup& S, int count, bool vectors, bse_report* rep)
   return 0;
 }
 
+bool valid_prec(int prec) { return prec == BSE_PREC_FP64 || prec == BSE_PREC_FP32_REFINE; }
+
+int check_solve_args(int n, const void* A, int lda, const void* B, int ldb, int prec, unsigned flags,
+                     const double* lambda, const void* X, int ldx, const void* d_r, const void* w) {
+  if (n <= 0) return set_error(-2, "n must be positive");
+  if (!A) return set_error(-3, "A is NULL");
+  if (lda < n) return set_error(-4, "lda < n");
+  if (!B) return set_error(-5, "B is NULL");
+  if (ldb < n) return set_error(-6, "ldb < n");
+  if (!valid_prec(prec)) return set_error(-7, "unsupported precision policy");
+  if (flags & ~(BSE_WANT_VECTORS | BSE_WANT_WEIGHTS)) return set_error(-8, "unknown flags");
+  if (!lambda) return set_error(-9, "lambda is NULL");
+  const bool vec = (flags & BSE_WANT_VECTORS) != 0;
+  const bool wts = (flags & BSE_WANT_WEIGHTS) != 0;
+  if (wts && !vec) return set_error(-8, "weights need eigenvectors");
+  if (vec && !X) return set_error(-10, "X is NULL");
+  if (vec && ldx < 2 * n) return set_error(-11, "ldx < 2n");
+  if (wts && !d_r) return set_error(-12, "d_r is NULL");
+  if (wts && !w) return set_error(-14, "w is NULL");
+  return 0;
+}
+
+int solve_single_in(Lane* L, char* base, int n, const void* A, int lda, const void* B, int ldb, int prec,
+                    unsigned flags, double* lambda, void* X, int ldx, const void* d_r, const void* d_l,
+                    void* w, bse_report* rep) {
+  const long N = 2L * n;
+  char* pbase = base + header_bytes(1);
+  Setup S;
+  BSE_TRY(setup_batch(L, 1, &N, prec, base, &pbase, &S));
+  const bool vec = (flags & BSE_WANT_VECTORS) != 0;
+  Prob& P = L->hprobs[0];
+  P.A = static_cast<const double*>(A);
+  P.lda = lda;
+  P.B = static_cast<const double*>(B);
+  P.ldb = ldb;
+  P.lambda = lambda;
+  P.X = static_cast<double*>(X);
+  P.ldx = ldx;
+  P.dr = static_cast<const double*>(d_r);
+  P.dl = static_cast<const double*>(d_l);
+  P.w = static_cast<double*>(w);
+  P.flags = flags;
+  BSE_TRY(run_chain(L, S, 1, vec, rep));
+  if (rep) rep->n = n;
+  const int code = info_code(L->hinfo[0], L->hinfo[1], vec);
+  if (code == BSE_EDEVICE) return set_error(BSE_EDEVICE, "cluster Gram matrix not positive definite");
+  if (code == BSE_ENOCONV) return set_error(BSE_ENOCONV, "refinement did not converge within the sweep limit");
+  return code;
+}
+
 static int prologue(bse_ctx* ctx) {
   if (!ctx) return set_error(-1, "null context");
   BSE_HIP(hipSetDevice(ctx->device));
@@ -473,8 +521,6 @@ int bse_ctx_set_timing(bse_ctx* ctx, int enable) {
   return 0;
 }
 
-static bool valid_prec(int prec) { return prec == BSE_PREC_FP64 || prec == BSE_PREC_FP32_REFINE; }
-
 size_t bse_footprint_bytes(int n, int prec, unsigned flags) {
   (void)flags;
   if (n <= 0 || !valid_prec(prec)) return 0;
@@ -496,42 +542,11 @@ int bse_solve(bse_ctx* ctx, int n, const void* A, int lda, const void* B, int ld
               unsigned flags, double* lambda, void* X, int ldx, const void* d_r, const void* d_l,
               void* w, bse_report* rep) {
   if (!ctx) return set_error(-1, "ctx is NULL");
-  if (n <= 0) return set_error(-2, "n must be positive");
-  if (!A) return set_error(-3, "A is NULL");
-  if (lda < n) return set_error(-4, "lda < n");
-  if (!B) return set_error(-5, "B is NULL");
-  if (ldb < n) return set_error(-6, "ldb < n");
-  if (!valid_prec(prec)) return set_error(-7, "unsupported precision policy");
-  if (flags & ~(BSE_WANT_VECTORS | BSE_WANT_WEIGHTS)) return set_error(-8, "unknown flags");
-  if (!lambda) return set_error(-9, "lambda is NULL");
-  const bool vec = (flags & BSE_WANT_VECTORS) != 0;
-  const bool wts = (flags & BSE_WANT_WEIGHTS) != 0;
-  if (wts && !vec) return set_error(-8, "weights need eigenvectors");
-  if (vec && !X) return set_error(-10, "X is NULL");
-  if (vec && ldx < 2 * n) return set_error(-11, "ldx < 2n");
-  if (wts && !d_r) return set_error(-12, "d_r is NULL");
-  if (wts && !w) return set_error(-14, "w is NULL");
+  BSE_TRY(check_solve_args(n, A, lda, B, ldb, prec, flags, lambda, X, ldx, d_r, w));
   BSE_TRY(prologue(ctx));
-  Setup S;
-  const long N = 2L * n;
-  BSE_TRY(setup_ctx_batch(ctx, 1, &N, prec, &S));
-  Prob& P = ctx->lane.hprobs[0];
-  P.A = static_cast<const double*>(A);
-  P.lda = lda;
-  P.B = static_cast<const double*>(B);
-  P.ldb = ldb;
-  P.lambda = lambda;
-  P.X = static_cast<double*>(X);
-  P.ldx = ldx;
-  P.dr = static_cast<const double*>(d_r);
-  P.dl = static_cast<const double*>(d_l);
-  P.w = static_cast<double*>(w);
-  P.flags = flags;
-  BSE_TRY(run_chain(&ctx->lane, S, 1, vec, rep));
-  if (rep) rep->n = n;
-  if (ctx->lane.hinfo[0] != 0) return ctx->lane.hinfo[0];
-  if (vec && ctx->lane.hinfo[1] != 0) return set_error(BSE_EDEVICE, "cluster Gram matrix not positive definite");
-  return 0;
+  char* base = nullptr;
+  BSE_TRY(get_workspace(ctx, header_bytes(1) + problem_bytes(2L * n, prec), &base));
+  return solve_single_in(&ctx->lane, base, n, A, lda, B, ldb, prec, flags, lambda, X, ldx, d_r, d_l, w, rep);
 }
 
 int bse_solve_batched(bse_ctx* ctx, int count, const int* n, const void* const* A, const int* lda,
@@ -598,7 +613,7 @@ int bse_solve_batched(bse_ctx* ctx, int count, const int* n, const void* const* 
   for (int k = 0; k < count; ++k) {
     const int i = order[k];
     const int i0 = ctx->lane.hinfo[2 * k], i1 = ctx->lane.hinfo[2 * k + 1];
-    info[i] = (i0 != 0) ? i0 : ((vec && i1 != 0) ? BSE_EDEVICE : 0);
+    info[i] = info_code(i0, i1, vec);
   }
   return 0;
 }

@@ -149,12 +149,17 @@ def test_mixed_exactly_degenerate_spectrum(ctx):
 @pytest.mark.parametrize("n", [120, 400])
 def test_near_degenerate_pairs(ctx, n):
     """Pairs closer than the FP32 reduction can separate (relative gaps
-    1e-9, 1e-8, 1e-7) and an exactly degenerate one, planted in the
-    closed-form spectrum: both paths must reach the exact eigenvalues to
-    1e-10 lambda_max and report success."""
+    1e-9 .. 3e-6, one chain of three) and an exactly degenerate one, planted
+    in the closed-form spectrum: both paths must reach the exact eigenvalues
+    to 1e-10 lambda_max and report success (the refinement rotates each
+    cluster of close pairs exactly instead of leaving it out)."""
     from bse_inputs import gen_closed_form
     from paper_1501_03830_amd import _lib
-    p = gen_closed_form(n, seed=77, planted=[(5, 1e-9), (20, 1e-8), (40, 1e-7), (60, 0.0)])
+    # isolated pairs at relative gaps 1e-9 .. 3e-6, an exact degeneracy and a
+    # chain of three (gaps 1e-9 then 3e-9), which must be rotated as one
+    # cluster
+    p = gen_closed_form(n, seed=77, planted=[(5, 1e-9), (20, 1e-8), (40, 1e-7), (60, 0.0),
+                                            (80, 1e-9), (81, 3e-9), (100, 1e-6), (110, 3e-6)])
     exact = np.sort(np.asarray(p.exact_lambda))
     lmax = float(exact.max())
     for name, prec in (("fp64", _lib.BSE_PREC_FP64), ("fp32_refine", MIXED())):
