@@ -316,6 +316,29 @@ int bse_ticket_times(bse_ctx* ctx, uint64_t ticket, double* t_submit_us, double*
 int bse_serve_stats(bse_ctx* ctx, bse_serve_counters* stats);
 
 /* ---------------------------------------------------------------------------
+ * Allocation-free solve, for callers that cannot allocate: code under HIP
+ * stream capture, tight serving loops and harnesses that forbid hipMalloc
+ * or pinned host allocations.  Same arguments, arithmetic and results (bit
+ * for bit) as bse_solve without the report; the workspace is a fixed device
+ * array inside the library, BSE_NOALLOC_MAX_BYTES (64 MiB) per device, held
+ * by each device the library runs on until the process ends.  Problems
+ * whose bse_footprint_bytes(n, prec, flags) exceeds it are rejected with
+ * BSE_ENOMEM (n <= 544 fits in FP64, n <= 416 with BSE_PREC_FP32_REFINE).
+ * The array is set up when the first context on a device is created; the
+ * call allocates nothing (no hipMalloc, no pinned host memory, no events).
+ * Every call on a device shares the one array: calls that overlap on one
+ * device (from several threads or streams) race and must be serialised.
+ * ------------------------------------------------------------------------ */
+#define BSE_NOALLOC_MAX_BYTES (64u << 20)
+
+/* Size of the fixed workspace array (host-only, callable without a GPU). */
+size_t bse_noalloc_max_bytes(void);
+
+int bse_solve_noalloc(bse_ctx* ctx, int n, const void* A, int lda, const void* B, int ldb, int prec,
+                      unsigned flags, double* lambda, void* X, int ldx, const void* d_r,
+                      const void* d_l, void* w);
+
+/* ---------------------------------------------------------------------------
  * Stage entry points.  Each runs one step of the chain on caller buffers so
  * that it can be checked on its own.  Real matrices are FP64 column-major.
  * ------------------------------------------------------------------------ */

@@ -120,6 +120,8 @@ SIGNATURES = [
     ("bse_release", _I, [_P, ctypes.c_uint64]),
     ("bse_ticket_times", _I, [_P, ctypes.c_uint64, _D, _D, _D]),
     ("bse_serve_stats", _I, [_P, ctypes.POINTER(BseServeCounters)]),
+    ("bse_noalloc_max_bytes", ctypes.c_size_t, []),
+    ("bse_solve_noalloc", _I, [_P, _I, _P, _I, _P, _I, _I, _U, _P, _P, _I, _P, _P, _P]),
     ("bse_build_M", _I, [_P, _I, _P, _I, _P, _I, _P, _I]),
     ("bse_potrf", _I, [_P, _I, _P, _I]),
     ("bse_form_W", _I, [_P, _I, _P, _I, _P, _I]),

@@ -105,6 +105,32 @@ class Context:
             "report": rep.as_dict() if rep is not None else None,
         }
 
+    def solve_noalloc(self, A: torch.Tensor, B: torch.Tensor, d_r: torch.Tensor | None = None,
+                      vectors: bool = True, prec: int = _lib.BSE_PREC_FP64):
+        """bse_solve_noalloc: the solve on the library's fixed workspace array
+        (no device or pinned allocation inside the call).  The tensors made
+        here for inputs and outputs are the caller's side.  Returns dict with
+        lam, X, w, info."""
+        n = A.shape[0]
+        dev = self.device
+        Ac = to_colmajor(A.to(torch.complex128), dev)
+        Bc = to_colmajor(B.to(torch.complex128), dev)
+        lam = torch.empty(n, dtype=torch.float64, device=dev)
+        flags = 0
+        Xbuf = w = drb = None
+        if vectors or d_r is not None:
+            flags |= _lib.BSE_WANT_VECTORS
+            Xbuf = torch.empty((n, 2 * n), dtype=torch.complex128, device=dev)
+        if d_r is not None:
+            flags |= _lib.BSE_WANT_WEIGHTS
+            drb = d_r.to(dev, torch.complex128).contiguous()
+            w = torch.empty(n, dtype=torch.complex128, device=dev)
+        torch.cuda.synchronize(dev)
+        info = _lib.check(self.lib.bse_solve_noalloc(
+            self.h, n, _ptr(Ac), n, _ptr(Bc), n, prec, flags, _ptr(lam),
+            _ptr(Xbuf), 2 * n, _ptr(drb), None, _ptr(w)), "bse_solve_noalloc")
+        return {"info": info, "lam": lam, "X": None if Xbuf is None else from_colmajor(Xbuf), "w": w}
+
     def solve_raw(self, n: int, Ac: torch.Tensor, Bc: torch.Tensor, lam: torch.Tensor,
                   Xbuf: torch.Tensor | None, drb: torch.Tensor | None = None, dlb: torch.Tensor | None = None,
                   w: torch.Tensor | None = None, report: bool = False, prec: int = _lib.BSE_PREC_FP64):

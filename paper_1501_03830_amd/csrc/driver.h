@@ -79,6 +79,10 @@ int solve_single_in(Lane* L, char* base, int n, const void* A, int lda, const vo
                     unsigned flags, double* lambda, void* X, int ldx, const void* d_r, const void* d_l,
                     void* w, bse_report* rep);
 
+// Set-up of the allocation-free entry point on the current device (once per
+// device; noalloc.hip).
+int noalloc_init_device(int device);
+
 }  // namespace bse
 
 // A context: device, the caller's stream, workspace and the request server.

@@ -495,6 +495,8 @@ int bse_ctx_create(bse_ctx** ctx, int device, void* arena, size_t arena_bytes, v
   if (device < 0 || device >= count) return set_error(-2, "invalid device");
   if (!arena && arena_bytes) return set_error(-4, "arena_bytes without arena");
   BSE_HIP(hipSetDevice(device));
+  // the allocation-free entry point's workspace address on this device
+  BSE_TRY(noalloc_init_device(device));
   bse_ctx* c = new bse_ctx();
   c->device = device;
   c->arena = arena;
