@@ -11,6 +11,7 @@ from .generators import (  # noqa: F401
     gen_closed_form,
     gen_b_zero,
     gen_real,
+    gen_real_closed_form,
     gen_not_definite,
     batched_sizes,
     serving_stream,

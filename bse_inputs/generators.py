@@ -210,6 +210,35 @@ def gen_real(n: int, seed: int = 0, s_a: float = 0.1, s_b: float = 0.05) -> BseP
     raise RuntimeError("no positive definite draw found")
 
 
+def gen_real_closed_form(n: int, seed: int = 40, b_ratio: float = 0.5, planted=()) -> BseProblem:
+    """Real problem with eigenvalues known in closed form.
+
+    With a real orthogonal Q0, A = Q0 diag(a) Q0^T and B = Q0 diag(b) Q0^T
+    decouple H into n 2x2 problems [[a_k, b_k], [-b_k, -a_k]] whose positive
+    eigenvalue is sqrt(a_k^2 - b_k^2).  Draw order: a ~ U[1,10]^n,
+    b = b_ratio * a * U[-1,1], then Q0 (QR of a Gaussian with the R-diagonal
+    signs removed), then a unit complex dipole.  planted: pairs (k, g) set
+    a[k+1] = (1+g) a[k], b[k+1] = (1+g) b[k] after the draws (g = 0: an
+    exactly degenerate eigenvalue)."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(1.0, 10.0, size=n)
+    b = b_ratio * a * rng.uniform(-1.0, 1.0, size=n)
+    for k, g in planted:
+        if not 0 <= k < n - 1:
+            raise ValueError("planted pair index out of range")
+        a[k + 1] = (1.0 + g) * a[k]
+        b[k + 1] = (1.0 + g) * b[k]
+    q, r = np.linalg.qr(rng.standard_normal((n, n)))
+    q = q * np.sign(np.diag(r))[None, :]
+    amat = (q * a[None, :]) @ q.T
+    bmat = (q * b[None, :]) @ q.T
+    amat = 0.5 * (amat + amat.T)
+    bmat = 0.5 * (bmat + bmat.T)
+    d = _unit_dipole(rng, n)
+    lam = np.sort(np.sqrt(a * a - b * b))
+    return BseProblem(amat.astype(np.complex128), bmat.astype(np.complex128), d, seed, exact_lambda=lam)
+
+
 def gen_not_definite(n: int, k: int, seed: int = 0) -> BseProblem:
     """A problem whose Omega fails to be positive definite.
 

@@ -210,6 +210,63 @@ int bse_solve(bse_ctx* ctx, int n, const void* A, int lda, const void* B, int ld
               unsigned flags, double* lambda, void* X, int ldx, const void* d_r, const void* d_l,
               void* w, bse_report* rep);
 
+/*
+ * Real Bethe-Salpeter problem (eq. H-real, Section 3.2, Theorem 5,
+ * Algorithm 2): A, B real symmetric n x n (FP64, column-major, lower
+ * triangles read) with A + B > 0 and A - B > 0.  The real embedding is then
+ * M = blkdiag(A + B, A - B), whose Cholesky factor is blkdiag(L1, L2) with
+ * the two factors of Algorithm 2 step 1, and W = L^T J L = [0 L1^T L2;
+ * -L2^T L1 0]: its eigenvalues are +-i sigma_j for the singular values
+ * sigma_j of L2^T L1 (Algorithm 2 step 2) and its Schur vectors carry the
+ * singular vectors, so the same reduction, tridiagonal solve and
+ * back-transformation give Lambda_+ and X1, X2 of Algorithm 2 step 3 (with
+ * Theorem 5's factor 1/2 and Lambda_+^{-1/2}).
+ *   A, lda, B, ldb (3-6): real; prec (7), flags (8), lambda (9) as in
+ *   bse_solve; X, ldx (10, 11): REAL 2n x n, ldx >= 2n, X1 over X2 with
+ *   X1^T X1 - X2^T X2 = I, each column's largest-modulus entry positive
+ *   (inside a group of equal eigenvalues, a real orthonormal basis of the
+ *   eigenspace); d_r, d_l, w (12-14): complex dipoles and weights as in
+ *   bse_solve; rep (15).  Returns +k when the leading k x k minor of A + B
+ *   (k <= n) or the leading (k - n) x (k - n) minor of A - B (k > n) is not
+ *   positive definite.
+ */
+int bse_solve_real(bse_ctx* ctx, int n, const double* A, int lda, const double* B, int ldb, int prec,
+                   unsigned flags, double* lambda, double* X, int ldx, const void* d_r, const void* d_l, void* w,
+                   bse_report* rep);
+
+/*
+ * Tamm-Dancoff approximation (Section 2.2, Theorem 4): the Bethe-Salpeter
+ * problem with the off-diagonal blocks B and -conj(B) set to zero, i.e. the
+ * Hermitian eigenproblem of A, solved by the same structure-preserving chain
+ * as bse_solve (embedding, Cholesky, W, tridiagonalisation, bisection and
+ * inverse iteration, back-transformation).  Arguments as bse_solve without
+ * B and ldb (argument numbers shift accordingly): A, lda (3, 4); prec (5);
+ * flags (6); lambda (7): the n eigenvalues of A, ascending, which under eq.
+ * cond bound those of the full H from above (Theorem 4); X, ldx (8, 9): the
+ * eigenvectors as x_j = [v_j; 0] with A v_j = lambda_j v_j, v_j^H v_j = 1
+ * (rows n..2n-1 hold rounding-level values of the zero block); d_r, d_l
+ * (10, 11) and w (12): the TDA weights of eq. absp, (d_r^H x_j)(x_j^H d_l)
+ * here; rep (13).  Returns +k when the leading k x k minor of the real
+ * embedding of A is not positive definite (A itself is not).
+ */
+int bse_solve_tda(bse_ctx* ctx, int n, const void* A, int lda, int prec, unsigned flags, double* lambda,
+                  void* X, int ldx, const void* d_r, const void* d_l, void* w, bse_report* rep);
+
+/*
+ * Broadened spectra (eq. DOS and eq. absp, with each delta function replaced
+ * by the Gaussian exp(-t^2 / (2 sigma^2)) / (sqrt(2 pi) sigma) that Section 4
+ * uses for its spectral-density figure) on the uniform grid
+ * omega_k = omega0 + k domega, k = 0..npts-1:
+ *   dos[k] = 1/(2n) sum over the 2n eigenvalues +-lambda_j of H,
+ *   eps[k] = sum_j w_j delta(omega_k - lambda_j)  (complex).
+ *   lambda (3): n positive eigenvalues (device), w (4): n complex weights
+ *   (device; needed for eps), npts (5) > 0, omega0 (6), domega (7) >= 0,
+ *   sigma (8) > 0, dos (9): npts doubles or NULL, eps (10): npts complex or
+ *   NULL (not both NULL).  Device outputs, stream-ordered, synchronous.
+ */
+int bse_spectra(bse_ctx* ctx, int n, const double* lambda, const void* w, int npts, double omega0,
+                double domega, double sigma, double* dos, void* eps);
+
 /* Device workspace, in bytes, of one bse_solve_batched call over `count`
  * problems of orders n[0..count) (host-only arithmetic, callable without a
  * GPU).  0 for invalid arguments. */
@@ -337,6 +394,20 @@ size_t bse_noalloc_max_bytes(void);
 int bse_solve_noalloc(bse_ctx* ctx, int n, const void* A, int lda, const void* B, int ldb, int prec,
                       unsigned flags, double* lambda, void* X, int ldx, const void* d_r,
                       const void* d_l, void* w);
+
+/* Host-only check of the launch sequence a bse_solve_batched call over
+ * `count` problems of orders n[0..count) would issue (count 1: bse_solve),
+ * for the path where every problem is definite and the refinement takes all
+ * its sweeps.  Nothing is allocated or launched and no GPU is needed: every
+ * launch is checked against the dispatch limits (non-empty grid, at most
+ * 2^32 - 1 work-items per dimension, workgroups of at most 1024 work-items,
+ * dynamic LDS <= 160 KiB, kernel arguments <= 4 KiB).  Returns 0, or
+ * BSE_EDEVICE naming the first launch that violates a limit, or -i for an
+ * invalid argument i.  summary (host, may be NULL): text, one line with the
+ * status, launch count and workspace bytes, then one line per kernel with
+ * its launch count, smallest and largest grid, largest workgroup and
+ * argument bytes. */
+int bse_plan_check(int count, const int* n, int prec, unsigned flags, char* summary, size_t summary_bytes);
 
 /* ---------------------------------------------------------------------------
  * Stage entry points.  Each runs one step of the chain on caller buffers so

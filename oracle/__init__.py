@@ -29,4 +29,6 @@ from .bse_oracle import (  # noqa: F401
     solve,
 )
 from .real_bse import solve_real  # noqa: F401
+from . import sbr  # noqa: F401
+from . import spectra  # noqa: F401
 from . import metrics  # noqa: F401

@@ -109,6 +109,9 @@ SIGNATURES = [
     ("bse_ctx_set_timing", _I, [_P, _I]),
     ("bse_footprint_bytes", ctypes.c_size_t, [_I, _I, _U]),
     ("bse_solve", _I, [_P, _I, _P, _I, _P, _I, _I, _U, _P, _P, _I, _P, _P, _P, ctypes.POINTER(BseReport)]),
+    ("bse_solve_real", _I, [_P, _I, _P, _I, _P, _I, _I, _U, _P, _P, _I, _P, _P, _P, ctypes.POINTER(BseReport)]),
+    ("bse_solve_tda", _I, [_P, _I, _P, _I, _I, _U, _P, _P, _I, _P, _P, _P, ctypes.POINTER(BseReport)]),
+    ("bse_spectra", _I, [_P, _I, _P, _P, _I, ctypes.c_double, ctypes.c_double, ctypes.c_double, _P, _P]),
     ("bse_footprint_batched_bytes", ctypes.c_size_t, [_I, ctypes.POINTER(_I), _I, _U]),
     ("bse_solve_batched", _I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_P), ctypes.POINTER(_I),
                                ctypes.POINTER(_P), ctypes.POINTER(_I), _I, _U, ctypes.POINTER(_P),
@@ -122,6 +125,7 @@ SIGNATURES = [
     ("bse_serve_stats", _I, [_P, ctypes.POINTER(BseServeCounters)]),
     ("bse_noalloc_max_bytes", ctypes.c_size_t, []),
     ("bse_solve_noalloc", _I, [_P, _I, _P, _I, _P, _I, _I, _U, _P, _P, _I, _P, _P, _P]),
+    ("bse_plan_check", _I, [_I, ctypes.POINTER(_I), _I, _U, ctypes.c_char_p, ctypes.c_size_t]),
     ("bse_build_M", _I, [_P, _I, _P, _I, _P, _I, _P, _I]),
     ("bse_potrf", _I, [_P, _I, _P, _I]),
     ("bse_form_W", _I, [_P, _I, _P, _I, _P, _I]),

@@ -105,6 +105,70 @@ class Context:
             "report": rep.as_dict() if rep is not None else None,
         }
 
+    def solve_real(self, A: torch.Tensor, B: torch.Tensor, d_r: torch.Tensor | None = None, vectors: bool = True,
+                   report: bool = False, prec: int = _lib.BSE_PREC_FP64):
+        """Real problem (Algorithm 2): A, B real (n, n) (lower triangles
+        used).  Returns dict with lam (n,), X real (2n, n) or None, w (n,)
+        complex or None, info, report."""
+        n = A.shape[0]
+        dev = self.device
+        Ac = to_colmajor(A.real.to(torch.float64), dev)
+        Bc = to_colmajor(B.real.to(torch.float64), dev)
+        lam = torch.empty(n, dtype=torch.float64, device=dev)
+        flags = 0
+        Xbuf = w = drb = None
+        if vectors or d_r is not None:
+            flags |= _lib.BSE_WANT_VECTORS
+            Xbuf = torch.empty((n, 2 * n), dtype=torch.float64, device=dev)
+        if d_r is not None:
+            flags |= _lib.BSE_WANT_WEIGHTS
+            drb = d_r.to(dev, torch.complex128).contiguous()
+            w = torch.empty(n, dtype=torch.complex128, device=dev)
+        rep = _lib.BseReport() if report else None
+        info = _lib.check(self.lib.bse_solve_real(
+            self.h, n, _ptr(Ac), n, _ptr(Bc), n, prec, flags, _ptr(lam), _ptr(Xbuf), 2 * n, _ptr(drb), None,
+            _ptr(w), ctypes.byref(rep) if rep is not None else None), "bse_solve_real")
+        return {"info": info, "lam": lam, "X": None if Xbuf is None else from_colmajor(Xbuf), "w": w,
+                "report": rep.as_dict() if rep is not None else None}
+
+    def solve_tda(self, A: torch.Tensor, d_r: torch.Tensor | None = None, vectors: bool = True,
+                  report: bool = False, prec: int = _lib.BSE_PREC_FP64):
+        """Tamm-Dancoff solve (B = 0): eigenvalues of A ascending, x_j =
+        [v_j; 0], TDA weights.  Same return layout as solve()."""
+        n = A.shape[0]
+        dev = self.device
+        Ac = to_colmajor(A.to(torch.complex128), dev)
+        lam = torch.empty(n, dtype=torch.float64, device=dev)
+        flags = 0
+        Xbuf = w = drb = None
+        if vectors or d_r is not None:
+            flags |= _lib.BSE_WANT_VECTORS
+            Xbuf = torch.empty((n, 2 * n), dtype=torch.complex128, device=dev)
+        if d_r is not None:
+            flags |= _lib.BSE_WANT_WEIGHTS
+            drb = d_r.to(dev, torch.complex128).contiguous()
+            w = torch.empty(n, dtype=torch.complex128, device=dev)
+        rep = _lib.BseReport() if report else None
+        info = _lib.check(self.lib.bse_solve_tda(
+            self.h, n, _ptr(Ac), n, prec, flags, _ptr(lam), _ptr(Xbuf), 2 * n, _ptr(drb), None, _ptr(w),
+            ctypes.byref(rep) if rep is not None else None), "bse_solve_tda")
+        return {"info": info, "lam": lam, "X": None if Xbuf is None else from_colmajor(Xbuf), "w": w,
+                "report": rep.as_dict() if rep is not None else None}
+
+    def spectra(self, lam: torch.Tensor, w: torch.Tensor | None, omega0: float, domega: float, npts: int,
+                sigma: float, dos: bool = True):
+        """Broadened density of states and absorption spectrum on the grid
+        omega0 + k domega (device tensors in, device tensors out)."""
+        n = lam.shape[0]
+        dev = self.device
+        lam = lam.to(dev, torch.float64).contiguous()
+        wc = None if w is None else w.to(dev, torch.complex128).contiguous()
+        d = torch.empty(npts, dtype=torch.float64, device=dev) if dos else None
+        e = torch.empty(npts, dtype=torch.complex128, device=dev) if wc is not None else None
+        _lib.check(self.lib.bse_spectra(self.h, n, _ptr(lam), _ptr(wc), npts, omega0, domega, sigma,
+                                        _ptr(d), _ptr(e)), "bse_spectra")
+        return d, e
+
     def solve_noalloc(self, A: torch.Tensor, B: torch.Tensor, d_r: torch.Tensor | None = None,
                       vectors: bool = True, prec: int = _lib.BSE_PREC_FP64):
         """bse_solve_noalloc: the solve on the library's fixed workspace array

@@ -17,6 +17,8 @@
 //   * Q = (1/sqrt 2)[I -iI; I iI] and S = diag(I, -I) only combine rows, so
 //     they are folded with the 1/sqrt(lambda) scaling into the kernel that
 //     writes the interleaved complex output (remark 3: O(n^2) work).
+#include <vector>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -212,6 +214,102 @@ __global__ __launch_bounds__(256) void k_phase_weights(const Prob* __restrict__ 
   }
 }
 
+// Real problems (FLAG_REAL_IN, eq. H-real).  The eigenvectors of a real H
+// are real up to a phase, so after the canonical phase every column is real
+// to rounding, except inside a group of equal eigenvalues whose computed
+// basis is a complex combination of real eigenvectors.  k_real_flags marks
+// the columns whose imaginary part exceeds 1e-8 of their norm.
+__global__ __launch_bounds__(256) void k_real_flags(const Prob* __restrict__ probs) {
+  __shared__ double red[4];
+  const Prob& P = probs[blockIdx.z];
+  const int n = P.n, N = P.N;
+  const int j = blockIdx.x;
+  if (j >= n) return;   // uniform
+  const BSE_GLOBAL double* __restrict__ x = gbl(P.X) + 2 * (long)j * P.ldx;
+  double im = 0.0, tot = 0.0;
+  for (int r = threadIdx.x; r < N; r += 256) {
+    const double a = x[2 * r], b = x[2 * r + 1];
+    im += b * b;
+    tot += a * a + b * b;
+  }
+  im = block_sum(im, red);
+  tot = block_sum(tot, red);
+  if (threadIdx.x == 0) gbl(P.cid)[j] = (im > 1e-16 * tot) ? 1 : 0;
+}
+
+// One workgroup per group of equal eigenvalues (first column g0, c columns):
+// the real and imaginary parts of its columns span its real eigenspace.
+// Modified Gram-Schmidt, twice, in the inner product <p, q> = p1^T q1 -
+// p2^T q2 of Theorem 3's normalisation (positive on the eigenvectors of the
+// positive eigenvalues) over the candidates Re x_g0, Im x_g0, Re x_g0+1, ...
+// keeps each candidate with at least half its norm left, until c are kept;
+// they replace the group's columns with zero imaginary parts.  Work space:
+// the same columns of P.W (free once X is written).
+__global__ __launch_bounds__(256) void k_realify(const Prob* __restrict__ probs, const int* __restrict__ groups,
+                                                 int ngroups) {
+  __shared__ double red[4];
+  const Prob& P = probs[0];
+  const int g = blockIdx.x;
+  if (g >= ngroups) return;
+  const int g0 = groups[2 * g], c = groups[2 * g + 1];
+  const long N = P.N, n = P.n, ld = P.ld, ldx = P.ldx;
+  BSE_GLOBAL double* __restrict__ X = gbl(P.X);
+  BSE_GLOBAL double* __restrict__ T = gbl(P.W);
+  int kept = 0;
+  for (int cand = 0; cand < 2 * c && kept < c; ++cand) {
+    const long col = g0 + cand / 2;
+    const int part = cand & 1;
+    BSE_GLOBAL double* t = T + (long)(g0 + kept) * ld;
+    double nn = 0.0;
+    for (long r = threadIdx.x; r < N; r += 256) {
+      const double v = X[2 * (r + col * ldx) + part];
+      t[r] = v;
+      nn += (r < n ? 1.0 : -1.0) * v * v;
+    }
+    const double orig = block_sum(nn, red);
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int q = 0; q < kept; ++q) {
+        const BSE_GLOBAL double* u = T + (long)(g0 + q) * ld;
+        double d = 0.0;
+        for (long r = threadIdx.x; r < N; r += 256) d += (r < n ? 1.0 : -1.0) * u[r] * t[r];
+        d = block_sum(d, red);
+        for (long r = threadIdx.x; r < N; r += 256) t[r] -= d * u[r];
+        __syncthreads();
+      }
+    }
+    nn = 0.0;
+    for (long r = threadIdx.x; r < N; r += 256) nn += (r < n ? 1.0 : -1.0) * t[r] * t[r];
+    const double res = block_sum(nn, red);
+    if (orig > 0.0 && res > 0.0 && res >= 0.25 * orig) {
+      const double f = 1.0 / sqrt(res);
+      for (long r = threadIdx.x; r < N; r += 256) t[r] *= f;
+      __syncthreads();
+      ++kept;
+    }
+  }
+  if (kept < c) {
+    if (threadIdx.x == 0) gbl(P.info)[1] = 1;   // no real basis found
+    return;
+  }
+  for (int q = 0; q < c; ++q) {
+    const BSE_GLOBAL double* u = T + (long)(g0 + q) * ld;
+    for (long r = threadIdx.x; r < N; r += 256) {
+      X[2 * (r + (long)(g0 + q) * ldx)] = u[r];
+      X[2 * (r + (long)(g0 + q) * ldx) + 1] = 0.0;
+    }
+  }
+}
+
+// the real parts of X into the caller's real 2n x n output
+__global__ __launch_bounds__(256) void k_real_copy(const Prob* __restrict__ probs) {
+  const Prob& P = probs[blockIdx.z];
+  const long N = P.N, n = P.n;
+  const long r = (long)blockIdx.x * 256 + threadIdx.x;
+  const long j = blockIdx.y;
+  if (r >= N || j >= n) return;
+  gbl(P.Xr)[r + j * P.ldxr] = gbl(P.X)[2 * (r + j * P.ldx)];
+}
+
 // strictly lower triangle of W into its FP32 copy (the part the reduction
 // reads)
 __global__ __launch_bounds__(256) void k_to_f32(const Prob* __restrict__ probs) {
@@ -234,8 +332,7 @@ __global__ __launch_bounds__(256) void k_to_f32(const Prob* __restrict__ probs) 
 int to_f32_batched(hipStream_t s, const Batch& b) {
   if (b.count <= 0) return 0;
   const long N0 = b.maxN();
-  k_to_f32<<<dim3((unsigned)((N0 + 63) / 64), (unsigned)((N0 + 63) / 64), (unsigned)b.count), 256, 0, s>>>(b.dev);
-  BSE_LAUNCHED();
+  BSE_LAUNCH(k_to_f32, dim3((unsigned)((N0 + 63) / 64), (unsigned)((N0 + 63) / 64), (unsigned)b.count), 256, 0, s, b.dev);
   return 0;
 }
 
@@ -265,8 +362,7 @@ int apply_UD_batched(hipStream_t s, const Batch& b) {
   if (b.count <= 0) return 0;
   const int N0 = b.maxN(), n0 = b.maxn();
   // Z = [Re(D V_+) | Im(D V_+)]
-  k_scatter_DV<<<dim3((unsigned)((N0 + 63) / 64), (unsigned)((n0 + 63) / 64), (unsigned)b.count), 256, 0, s>>>(b.dev);
-  BSE_LAUNCHED();
+  BSE_LAUNCH(k_scatter_DV, dim3((unsigned)((N0 + 63) / 64), (unsigned)((n0 + 63) / 64), (unsigned)b.count), 256, 0, s, b.dev);
   // Z <- U Z with U = H_0 ... H_{N-3}, last block of reflectors first
   const int nrefl0 = N0 - 2;   // H_{N-2} is the identity
   if (nrefl0 <= 0) return 0;
@@ -275,8 +371,7 @@ int apply_UD_batched(hipStream_t s, const Batch& b) {
     const int j0 = q * NBQ;
     const int nact = b.active_N_above(j0 + 2);   // N - 2 > j0
     const int m0 = N0 - j0 - 1;
-    k_extract_V<<<dim3((unsigned)((m0 + 63) / 64), 1, (unsigned)nact), 256, 0, s>>>(b.dev, q);
-    BSE_LAUNCHED();
+    BSE_LAUNCH(k_extract_V, dim3((unsigned)((m0 + 63) / 64), 1, (unsigned)nact), 256, 0, s, b.dev, q);
     BSE_TRY(gemm_batched(s, b, nact, GOP_APPLYU_S, q));
     BSE_TRY(gemm_batched(s, b, nact, GOP_APPLYU_W1, q));
     for (int h = NBQ / 64 - 1; h >= 0; --h) {
@@ -288,13 +383,50 @@ int apply_UD_batched(hipStream_t s, const Batch& b) {
   return 0;
 }
 
+int real_output_single(hipStream_t s, const Batch& b) {
+  if (b.count != 1) return set_error(BSE_EUNSUPPORTED, "real problems are solved one at a time");
+  const Prob& P = b.host[0];
+  const int n = P.n, N = P.N;
+  BSE_LAUNCH(k_real_flags, dim3((unsigned)n, 1, 1), 256, 0, s, b.dev);
+  std::vector<int> flag(n);
+  std::vector<double> lam(n);
+  BSE_HIP(hipMemcpyAsync(flag.data(), P.cid, n * sizeof(int), hipMemcpyDeviceToHost, s));
+  BSE_HIP(hipMemcpyAsync(lam.data(), P.lambda, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  BSE_HIP(hipStreamSynchronize(s));
+  // groups: runs of eigenvalues closer than 1e-8 lambda_max (consecutive)
+  // that hold a flagged column
+  std::vector<int> groups;
+  const double tol = 1e-8 * (n > 0 ? lam[n - 1] : 0.0);
+  for (int j = 0; j < n;) {
+    int e = j + 1;
+    while (e < n && lam[e] - lam[e - 1] <= tol) ++e;
+    bool any = false;
+    for (int k = j; k < e; ++k) any = any || flag[k] != 0;
+    if (any) {
+      groups.push_back(j);
+      groups.push_back(e - j);
+    }
+    j = e;
+  }
+  if (!groups.empty()) {
+    // the group list goes to the inverse-iteration factors' space (free here)
+    int* dgroups = reinterpret_cast<int*>(P.inv);
+    BSE_HIP(hipMemcpyAsync(dgroups, groups.data(), groups.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    const int ng = (int)groups.size() / 2;
+    BSE_LAUNCH(k_realify, dim3((unsigned)ng), 256, 0, s, b.dev, dgroups, ng);
+    // canonical sign and the weights of the new columns
+    BSE_LAUNCH(k_phase_weights, dim3((unsigned)n, 1, 1), 256, 0, s, b.dev);
+    BSE_HIP(hipStreamSynchronize(s));   // the group list is host memory
+  }
+  BSE_LAUNCH(k_real_copy, dim3((unsigned)((N + 255) / 256), (unsigned)n, 1), 256, 0, s, b.dev);
+  return 0;
+}
+
 int finish_batched(hipStream_t s, const Batch& b) {
   if (b.count <= 0) return 0;
   const int n0 = b.maxn();
-  k_finish_X<<<dim3((unsigned)((n0 + 63) / 64), (unsigned)((n0 + 63) / 64), (unsigned)b.count), 256, 0, s>>>(b.dev);
-  BSE_LAUNCHED();
-  k_phase_weights<<<dim3((unsigned)n0, 1, (unsigned)b.count), 256, 0, s>>>(b.dev);
-  BSE_LAUNCHED();
+  BSE_LAUNCH(k_finish_X, dim3((unsigned)((n0 + 63) / 64), (unsigned)((n0 + 63) / 64), (unsigned)b.count), 256, 0, s, b.dev);
+  BSE_LAUNCH(k_phase_weights, dim3((unsigned)n0, 1, (unsigned)b.count), 256, 0, s, b.dev);
   return 0;
 }
 

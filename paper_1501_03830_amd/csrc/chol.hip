@@ -25,7 +25,12 @@ __global__ __launch_bounds__(256) void k_build_M(const Prob* __restrict__ probs)
   const int cbase = blockIdx.y * TB + (threadIdx.x >> 6) * 16;
   if (r >= N) return;
   const BSE_GLOBAL double* __restrict__ A = gbl(P.A);
+  // no B: the Tamm-Dancoff Hamiltonian (B = 0)
   const BSE_GLOBAL double* __restrict__ B = gbl(P.B);
+  const bool hasB = P.B != nullptr;
+  // real A, B (eq. H-real): M = blkdiag(A + B, A - B), whose Cholesky
+  // factor is blkdiag(L1, L2) with the two factors of Algorithm 2 step 1
+  const bool real_in = (P.flags & FLAG_REAL_IN) != 0;
   const long lda = P.lda, ldb = P.ldb, ldm = P.ld;
   BSE_GLOBAL double* __restrict__ M = gbl(P.L);
   for (int q = 0; q < 16; ++q) {
@@ -36,18 +41,25 @@ __global__ __launch_bounds__(256) void k_build_M(const Prob* __restrict__ probs)
       const int bi = r >= n, bj = c >= n;
       const int i = r - bi * n, j = c - bj * n;
       double ar, ai, br, bim;
-      if (i >= j) {
+      if (real_in) {
+        const long ia = (i >= j) ? (long)i + (long)j * lda : (long)j + (long)i * lda;
+        const long ib = (i >= j) ? (long)i + (long)j * ldb : (long)j + (long)i * ldb;
+        ar = A[ia];
+        ai = 0.0;
+        br = B[ib];
+        bim = 0.0;
+      } else if (i >= j) {
         const long ia = 2 * ((long)i + (long)j * lda), ib = 2 * ((long)i + (long)j * ldb);
         ar = A[ia];
         ai = A[ia + 1];
-        br = B[ib];
-        bim = B[ib + 1];
+        br = hasB ? B[ib] : 0.0;
+        bim = hasB ? B[ib + 1] : 0.0;
       } else {  // upper triangle: A[i,j] = conj(A[j,i]), B[i,j] = B[j,i]
         const long ia = 2 * ((long)j + (long)i * lda), ib = 2 * ((long)j + (long)i * ldb);
         ar = A[ia];
         ai = -A[ia + 1];
-        br = B[ib];
-        bim = B[ib + 1];
+        br = hasB ? B[ib] : 0.0;
+        bim = hasB ? B[ib + 1] : 0.0;
       }
       if (i == j) ai = 0.0;  // a Hermitian diagonal is real
       if (!bi && !bj) val = ar + br;          // Re(A+B)
@@ -207,30 +219,26 @@ dim3 grid2d(long m, long n, int z = 1) {
 int build_M_batched(hipStream_t s, const Batch& b) {
   if (b.count <= 0) return 0;
   const long N = b.maxN();
-  k_build_M<<<grid2d(N, N, b.count), 256, 0, s>>>(b.dev);
-  BSE_LAUNCHED();
+  BSE_LAUNCH(k_build_M, grid2d(N, N, b.count), 256, 0, s, b.dev);
   return 0;
 }
 
 int copy_matrix(hipStream_t s, int m, int n, const double* src, long lds, double* dst, long ldd) {
   if (m <= 0 || n <= 0) return 0;
-  k_copy<<<grid2d(m, n), 256, 0, s>>>(m, n, src, lds, dst, ldd);
-  BSE_LAUNCHED();
+  BSE_LAUNCH(k_copy, grid2d(m, n), 256, 0, s, m, n, src, lds, dst, ldd);
   return 0;
 }
 
 int zero_upper(hipStream_t s, int N, double* A, long lda) {
   if (N <= 0) return 0;
-  k_zero_upper<<<grid2d(N, N), 256, 0, s>>>(N, A, lda);
-  BSE_LAUNCHED();
+  BSE_LAUNCH(k_zero_upper, grid2d(N, N), 256, 0, s, N, A, lda);
   return 0;
 }
 
 int potrf_batched(hipStream_t s, const Batch& b, int sel, bool reset_info) {
   if (b.count <= 0) return 0;
   if (reset_info) {
-    k_reset_info<<<dim3(1, 1, (unsigned)b.count), 64, 0, s>>>(b.dev, sel);
-    BSE_LAUNCHED();
+    BSE_LAUNCH(k_reset_info, dim3(1, 1, (unsigned)b.count), 64, 0, s, b.dev, sel);
   }
   // order of the factored matrix: N (sel 0) or n (sel 1); both sort with N
   auto order = [sel](const Prob& P) { return sel == 0 ? P.N : P.n; };
@@ -249,14 +257,12 @@ int potrf_batched(hipStream_t s, const Batch& b, int sel, bool reset_info) {
   // halves the passes over the trailing matrix.
   for (int k0 = 0; k0 < Nmax; k0 += 2 * TB) {
     const int nact = count_above(b.count, k0);   // problems with a diagonal block at k0
-    k_potf2<<<dim3(1, 1, (unsigned)nact), TB, 0, s>>>(b.dev, sel, k0);
-    BSE_LAUNCHED();
+    BSE_LAUNCH(k_potf2, dim3(1, 1, (unsigned)nact), TB, 0, s, b.dev, sel, k0);
     const int nrest = count_above(nact, k0 + TB);   // problems with rows below it
     if (nrest == 0) continue;
     BSE_TRY(trsm_rows_batched(s, b, nrest, sel, k0));
     BSE_TRY(gemm_batched(s, b, nrest, POPS, k0));
-    k_potf2<<<dim3(1, 1, (unsigned)nrest), TB, 0, s>>>(b.dev, sel, k0 + TB);
-    BSE_LAUNCHED();
+    BSE_LAUNCH(k_potf2, dim3(1, 1, (unsigned)nrest), TB, 0, s, b.dev, sel, k0 + TB);
     const int nrest2 = count_above(nrest, k0 + 2 * TB);
     if (nrest2 == 0) continue;
     BSE_TRY(trsm_rows_batched(s, b, nrest2, sel, k0 + TB));
@@ -271,16 +277,13 @@ int form_W_batched(hipStream_t s, const Batch& b, bool full) {
   // C = L11^T L21 into W11, then W11 = C - C^T
   BSE_TRY(gemm_batched(s, b, b.count, GOP_FORMW_C, 0));
   const long nt = (n + TB - 1) / TB;
-  k_skew_pairs<<<dim3((unsigned)(nt * (nt + 1) / 2), 1, (unsigned)b.count), 256, 0, s>>>(b.dev, 0, full ? 1 : 0);
-  BSE_LAUNCHED();
+  BSE_LAUNCH(k_skew_pairs, dim3((unsigned)(nt * (nt + 1) / 2), 1, (unsigned)b.count), 256, 0, s, b.dev, 0, full ? 1 : 0);
   // W21 = -L22^T L11
   BSE_TRY(gemm_batched(s, b, b.count, GOP_FORMW_21, 0));
-  k_zero_W22<<<grid2d(n, n, b.count), 256, 0, s>>>(b.dev);
-  BSE_LAUNCHED();
+  BSE_LAUNCH(k_zero_W22, grid2d(n, n, b.count), 256, 0, s, b.dev);
   if (full) {
     const long Nt = (N + TB - 1) / TB;
-    k_skew_pairs<<<dim3((unsigned)(Nt * (Nt + 1) / 2), 1, (unsigned)b.count), 256, 0, s>>>(b.dev, 1, 1);
-    BSE_LAUNCHED();
+    BSE_LAUNCH(k_skew_pairs, dim3((unsigned)(Nt * (Nt + 1) / 2), 1, (unsigned)b.count), 256, 0, s, b.dev, 1, 1);
   }
   return 0;
 }

@@ -23,11 +23,20 @@ inline long square_ld(long N) { return round_up(N < 64 ? 64 : N, 64); }
 
 // Record a HIP failure for bse_last_error() and turn it into BSE_EDEVICE.
 int set_hip_error(hipError_t e, const char* what, const char* file, int line);
+// Record a message for bse_last_error() and return code.
+int set_error(int code, const char* msg);
+
+// Host-only dry run of a launch plan (bse_plan_check): while it is on for
+// the calling thread, runtime calls wrapped in BSE_HIP are skipped and
+// kernels are checked but not launched.
+bool dry_run();
 
 #define BSE_HIP(call)                                                        \
   do {                                                                       \
-    hipError_t e_ = (call);                                                  \
-    if (e_ != hipSuccess) return ::bse::set_hip_error(e_, #call, __FILE__, __LINE__); \
+    if (!::bse::dry_run()) {                                                 \
+      hipError_t e_ = (call);                                                \
+      if (e_ != hipSuccess) return ::bse::set_hip_error(e_, #call, __FILE__, __LINE__); \
+    }                                                                        \
   } while (0)
 
 #define BSE_LAUNCHED()                                                       \
@@ -41,6 +50,36 @@ int set_hip_error(hipError_t e, const char* what, const char* file, int line);
     int rc_ = (expr);                                                        \
     if (rc_ != 0) return rc_;                                                \
   } while (0)
+
+// Every kernel launch is checked against the device's dispatch limits first
+// (grid dimensions >= 1, grid x workgroup within the 32-bit work-item count
+// of a dispatch packet in each dimension, workgroup <= 1024 work-items,
+// dynamic LDS <= 160 KiB, kernel arguments <= 4 KiB) and recorded for the
+// dry run; a violation is an error (BSE_EDEVICE with the kernel's name), not
+// a dispatch.
+int check_launch(const char* name, dim3 grid, dim3 block, size_t dyn_lds, size_t kernarg_bytes);
+
+template <class... P>
+constexpr size_t kernarg_bytes() {
+  size_t off = 0;
+  ((off = (off + alignof(P) - 1) / alignof(P) * alignof(P) + sizeof(P)), ...);
+  return off;
+}
+
+template <class... P, class... A>
+inline int launch_kernel(const char* name, void (*kern)(P...), dim3 grid, dim3 block, size_t lds, hipStream_t s,
+                         A&&... args) {
+  BSE_TRY(check_launch(name, grid, block, lds, kernarg_bytes<P...>()));
+  if (dry_run()) return 0;
+  kern<<<grid, block, lds, s>>>(static_cast<P>(args)...);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_hip_error(e, name, __FILE__, __LINE__);
+  return 0;
+}
+
+// kernel<<<grid, block, lds, stream>>>(args...), checked; a kernel name with
+// template arguments goes in parentheses
+#define BSE_LAUNCH(kern, ...) BSE_TRY(::bse::launch_kernel(#kern, kern, __VA_ARGS__))
 
 // Everything one problem of a (possibly one-element) batch needs on the
 // device: its sizes, the caller's input/output buffers and its own slice of
@@ -88,7 +127,15 @@ struct Prob {
   int* clflag;          // n: at a cluster's first pair, 1 when it needs the exact rotation
   double* clmax;        // n: at a cluster's first pair, largest entry of its rotation minus I
   double* clT;          // n x REF_CMAX4 doubles: the rotation of the cluster starting at pair k
+  // real problems (FLAG_REAL_IN): A, B real n x n; X is assembled in the
+  // workspace and its real part written to Xr (2n x n doubles, ld ldxr)
+  double* Xr;
+  long ldxr;
 };
+
+// Internal descriptor flag (beside BSE_WANT_*): A and B are real (FP64)
+// matrices, the real Bethe-Salpeter problem of eq. H-real (Algorithm 2).
+constexpr unsigned FLAG_REAL_IN = 1u << 16;
 
 // Refinement clusters: at most this many pairs (a 2c x 2c rotation per
 // cluster, stored in 4 c_max^2 doubles at the cluster's first pair's slot).

@@ -71,10 +71,12 @@ bool valid_prec(int prec);
 // Argument checks of bse_solve from argument 2 on (0 or -i with the message
 // for bse_last_error()).
 int check_solve_args(int n, const void* A, int lda, const void* B, int ldb, int prec, unsigned flags,
-                     const double* lambda, const void* X, int ldx, const void* d_r, const void* w);
+                     const double* lambda, const void* X, int ldx, const void* d_r, const void* w,
+                     bool need_B = true);
 // One problem (arguments already checked) on the lane's stream, with its
 // workspace at `base`: the batch header (header_bytes(1)) and then the
-// problem (problem_bytes(2n, prec)).  Returns what bse_solve returns.
+// problem (problem_bytes(2n, prec)).  B == NULL solves the Tamm-Dancoff
+// Hamiltonian (B = 0).  Returns what bse_solve returns.
 int solve_single_in(Lane* L, char* base, int n, const void* A, int lda, const void* B, int ldb, int prec,
                     unsigned flags, double* lambda, void* X, int ldx, const void* d_r, const void* d_l,
                     void* w, bse_report* rep);

@@ -876,21 +876,22 @@ constexpr int CFG_BM[NCFG] = {64, 128, 128, 64};
 constexpr int CFG_BN[NCFG] = {64, 128, 64, 64};
 
 template <bool TA, bool TB>
-void launch_t(hipStream_t s, int cfg, dim3 grid, const Prob* probs, int op, int step, const GemmParams& single) {
+int launch_t(hipStream_t s, int cfg, dim3 grid, const Prob* probs, int op, int step, const GemmParams& single) {
   switch (cfg) {
-    case 1: gemm_f64_kernel<TA, TB, 128, 128, 16><<<grid, 256, 0, s>>>(probs, op, step, single); break;
-    case 2: gemm_f64_kernel<TA, TB, 128, 64, 16><<<grid, 256, 0, s>>>(probs, op, step, single); break;
-    case 3: gemm_f64_kernel<TA, TB, 64, 64, 32><<<grid, 256, 0, s>>>(probs, op, step, single); break;
-    default: gemm_f64_kernel<TA, TB, 64, 64, 16><<<grid, 256, 0, s>>>(probs, op, step, single); break;
+    case 1: BSE_LAUNCH((gemm_f64_kernel<TA, TB, 128, 128, 16>), grid, 256, 0, s, probs, op, step, single); break;
+    case 2: BSE_LAUNCH((gemm_f64_kernel<TA, TB, 128, 64, 16>), grid, 256, 0, s, probs, op, step, single); break;
+    case 3: BSE_LAUNCH((gemm_f64_kernel<TA, TB, 64, 64, 32>), grid, 256, 0, s, probs, op, step, single); break;
+    default: BSE_LAUNCH((gemm_f64_kernel<TA, TB, 64, 64, 16>), grid, 256, 0, s, probs, op, step, single); break;
   }
+  return 0;
 }
 
-void launch(hipStream_t s, bool ta, bool tb, int cfg, dim3 grid, const Prob* probs, int op, int step,
-            const GemmParams& single) {
-  if (!ta && !tb) launch_t<false, false>(s, cfg, grid, probs, op, step, single);
-  else if (!ta && tb) launch_t<false, true>(s, cfg, grid, probs, op, step, single);
-  else if (ta && !tb) launch_t<true, false>(s, cfg, grid, probs, op, step, single);
-  else launch_t<true, true>(s, cfg, grid, probs, op, step, single);
+int launch(hipStream_t s, bool ta, bool tb, int cfg, dim3 grid, const Prob* probs, int op, int step,
+           const GemmParams& single) {
+  if (!ta && !tb) return launch_t<false, false>(s, cfg, grid, probs, op, step, single);
+  if (!ta && tb) return launch_t<false, true>(s, cfg, grid, probs, op, step, single);
+  if (ta && !tb) return launch_t<true, false>(s, cfg, grid, probs, op, step, single);
+  return launch_t<true, true>(s, cfg, grid, probs, op, step, single);
 }
 
 // workgroups of a product with configuration cfg
@@ -939,16 +940,13 @@ int gemm_batched(hipStream_t s, const Batch& b, int nact, int op, int step) {
     }
     const dim3 grid((unsigned)wg, 1, (unsigned)nact);
     if (tb != 0) return set_error(BSE_EUNSUPPORTED, "gemm_batched: FP32 product with a transposed B");
-    if (ta == 0) gemm_f32_kernel<false><<<grid, 256, 0, s>>>(b.dev, op, step, dummy);
-    else gemm_f32_kernel<true><<<grid, 256, 0, s>>>(b.dev, op, step, dummy);
+    if (ta == 0) BSE_LAUNCH(gemm_f32_kernel<false>, grid, 256, 0, s, b.dev, op, step, dummy);
+    else BSE_LAUNCH(gemm_f32_kernel<true>, grid, 256, 0, s, b.dev, op, step, dummy);
   } else {
-    launch(s, ta != 0, tb != 0, cfg, dim3((unsigned)maxwg, 1, (unsigned)nact), b.dev, op, step, dummy);
+    BSE_TRY(launch(s, ta != 0, tb != 0, cfg, dim3((unsigned)maxwg, 1, (unsigned)nact), b.dev, op, step, dummy));
   }
-  BSE_LAUNCHED();
   if (any_split) {
-    k_splitk_reduce<<<dim3((unsigned)((maxm + 63) / 64), (unsigned)((maxn + 63) / 64), (unsigned)nact), 256, 0, s>>>(
-        b.dev, op, step, dummy);
-    BSE_LAUNCHED();
+    BSE_LAUNCH(k_splitk_reduce, dim3((unsigned)((maxm + 63) / 64), (unsigned)((maxn + 63) / 64), (unsigned)nact), 256, 0, s, b.dev, op, step, dummy);
   }
   return 0;
 }

@@ -157,6 +157,11 @@ int apply_UD_batched(hipStream_t s, const Batch& b);
 // P.X from G = L Z (in P.W, made by GOP_APPLY_L), canonical phase and the
 // weights
 int finish_batched(hipStream_t s, const Batch& b);
+// Real problems (a batch of one with FLAG_REAL_IN): after finish_batched,
+// makes every column of X real (a real basis inside groups of equal
+// eigenvalues, then the canonical sign and the weights again) and writes
+// the real parts to P.Xr.  Synchronises the stream.
+int real_output_single(hipStream_t s, const Batch& b);
 // lower triangle of P.W into P.W32 (mixed-precision path)
 int to_f32_batched(hipStream_t s, const Batch& b);
 

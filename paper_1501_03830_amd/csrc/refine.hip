@@ -679,28 +679,20 @@ dim3 grid_NN(const Batch& b) {
 int refine_batched(hipStream_t s, const Batch& b, const RefineIO& io, RefineStats* st) {
   if (b.count <= 0) return 0;
   const int n0 = b.maxn();
-  k_ref_reset<<<dim3(1, 1, (unsigned)b.count), 64, 0, s>>>(b.dev);
-  BSE_LAUNCHED();
-  k_ref_scale<<<grid_NN(b), 256, 0, s>>>(b.dev, 1.41421356237309504880);
-  BSE_LAUNCHED();
+  BSE_LAUNCH(k_ref_reset, dim3(1, 1, (unsigned)b.count), 64, 0, s, b.dev);
+  BSE_LAUNCH(k_ref_scale, grid_NN(b), 256, 0, s, b.dev, 1.41421356237309504880);
   int sweeps = 0;
   for (int sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
     BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_P, sweep));
     BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_PB, sweep));
     BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_S, sweep));
     BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_G, sweep));
-    k_ref_lambda<<<dim3((unsigned)((n0 + 63) / 64), 1, (unsigned)b.count), 64, 0, s>>>(b.dev, sweep);
-    BSE_LAUNCHED();
-    k_ref_clusters<<<dim3(1, 1, (unsigned)b.count), 1024, 0, s>>>(b.dev, sweep);
-    BSE_LAUNCHED();
-    k_ref_F<<<grid_NN(b), 256, 0, s>>>(b.dev, sweep);
-    BSE_LAUNCHED();
-    k_ref_rr<<<dim3((unsigned)n0, 1, (unsigned)b.count), 64, 0, s>>>(b.dev, sweep);
-    BSE_LAUNCHED();
-    k_ref_rr_rows<<<dim3((unsigned)n0, 1, (unsigned)b.count), 256, 0, s>>>(b.dev, sweep);
-    BSE_LAUNCHED();
-    k_ref_decide<<<dim3(1, 1, (unsigned)b.count), 256, 0, s>>>(b.dev, sweep);
-    BSE_LAUNCHED();
+    BSE_LAUNCH(k_ref_lambda, dim3((unsigned)((n0 + 63) / 64), 1, (unsigned)b.count), 64, 0, s, b.dev, sweep);
+    BSE_LAUNCH(k_ref_clusters, dim3(1, 1, (unsigned)b.count), 1024, 0, s, b.dev, sweep);
+    BSE_LAUNCH(k_ref_F, grid_NN(b), 256, 0, s, b.dev, sweep);
+    BSE_LAUNCH(k_ref_rr, dim3((unsigned)n0, 1, (unsigned)b.count), 64, 0, s, b.dev, sweep);
+    BSE_LAUNCH(k_ref_rr_rows, dim3((unsigned)n0, 1, (unsigned)b.count), 256, 0, s, b.dev, sweep);
+    BSE_LAUNCH(k_ref_decide, dim3(1, 1, (unsigned)b.count), 256, 0, s, b.dev, sweep);
     BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_U, sweep));
     sweeps = sweep + 1;
     // every problem's state and largest correction, to decide on the host
@@ -725,12 +717,9 @@ int refine_batched(hipStream_t s, const Batch& b, const RefineIO& io, RefineStat
   // eigenvalues from each problem's final basis, sorted; eigenvectors to Z
   BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_PF, -1));
   BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_PFB, -1));
-  k_ref_final<<<dim3((unsigned)n0, 1, (unsigned)b.count), 256, 0, s>>>(b.dev);
-  BSE_LAUNCHED();
-  k_ref_sort<<<dim3((unsigned)((n0 + 255) / 256), 1, (unsigned)b.count), 256, 0, s>>>(b.dev);
-  BSE_LAUNCHED();
-  k_ref_out<<<grid_NN(b), 256, 0, s>>>(b.dev);
-  BSE_LAUNCHED();
+  BSE_LAUNCH(k_ref_final, dim3((unsigned)n0, 1, (unsigned)b.count), 256, 0, s, b.dev);
+  BSE_LAUNCH(k_ref_sort, dim3((unsigned)((n0 + 255) / 256), 1, (unsigned)b.count), 256, 0, s, b.dev);
+  BSE_LAUNCH(k_ref_out, grid_NN(b), 256, 0, s, b.dev);
   return 0;
 }
 

@@ -740,12 +740,10 @@ static int sktrd_run(hipStream_t s, const Batch& b, KernelTimer* timer) {
   const int stride = 2 * (b.count + 1);   // ints per column of the prefix table
   for (int k0 = 0; k0 <= N0 - 2; k0 += nb) {
     const int nstart = b.active_N_above(k0 + 1);   // N - 2 >= k0
-    sk_start<WT><<<dim3(1, 1, (unsigned)nstart), 256, 0, s>>>(b.dev, k0);
-    BSE_LAUNCHED();
+    BSE_LAUNCH(sk_start<WT>, dim3(1, 1, (unsigned)nstart), 256, 0, s, b.dev, k0);
     const int ncols = min(nb, N0 - 2 - k0);   // columns of this panel with a reflector
     if (nstart > 1 && b.wgpre != nullptr && ncols > 0) {   // the batch launches of this panel
-      k_plan<WT><<<(unsigned)ncols, 1024, 0, s>>>(b.dev, nstart, k0, stride, b.wgpre);
-      BSE_LAUNCHED();
+      BSE_LAUNCH(k_plan<WT>, (unsigned)ncols, 1024, 0, s, b.dev, nstart, k0, stride, b.wgpre);
     }
     for (int i = 0; i < nb; ++i) {
       const int j = k0 + i;
@@ -772,9 +770,8 @@ static int sktrd_run(hipStream_t s, const Batch& b, KernelTimer* timer) {
       // the last-level cache (thresholds of 200, 300 and 400 MB measured on
       // the n = 8192 reduction; 300 MB was fastest)
       const double tri_bytes = 0.5 * sizeof(WT) * (double)(N0 - sidx) * (double)(N0 - sidx);
-      if (tri_bytes > 300e6) sk_symv<WT, true><<<gs, 256, 0, s>>>(b.dev, j, i, pre, nact);
-      else sk_symv<WT, false><<<gs, 256, 0, s>>>(b.dev, j, i, pre, nact);
-      BSE_LAUNCHED();
+      if (tri_bytes > 300e6) BSE_LAUNCH((sk_symv<WT, true>), gs, 256, 0, s, b.dev, j, i, pre, nact);
+      else BSE_LAUNCH((sk_symv<WT, false>), gs, 256, 0, s, b.dev, j, i, pre, nact);
       if (timed) {
         BSE_HIP(hipEventRecord(timer->ev[timer->used + 1], s));
         timer->used += 2;
@@ -783,9 +780,8 @@ static int sktrd_run(hipStream_t s, const Batch& b, KernelTimer* timer) {
           timer->bytes += sizeof(WT) * m * (m - 1.0) * 0.5;
         }
       }
-      if (nblk0 > UPD_SMALL) sk_update<WT, 16><<<gup, 1024, 0, s>>>(b.dev, j, i, pre, nact);
-      else sk_update<WT, 4><<<gup, 256, 0, s>>>(b.dev, j, i, pre, nact);
-      BSE_LAUNCHED();
+      if (nblk0 > UPD_SMALL) BSE_LAUNCH((sk_update<WT, 16>), gup, 1024, 0, s, b.dev, j, i, pre, nact);
+      else BSE_LAUNCH((sk_update<WT, 4>), gup, 256, 0, s, b.dev, j, i, pre, nact);
     }
     BSE_TRY(gemm_batched(s, b, nstart, GOP_SKTRD_R2K, k0));
   }

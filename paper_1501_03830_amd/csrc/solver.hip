@@ -372,6 +372,7 @@ int run_chain(Lane* L, const Setup& S, int count, bool vectors, bse_report* rep)
       BSE_TRY(gemm_batched(s, b, b.count, GOP_APPLY_L, 0));
       BSE_TRY(mark(L, timed, ev++));
       BSE_TRY(finish_batched(s, b));
+      if (b.count == 1 && (b.host[0].flags & FLAG_REAL_IN)) BSE_TRY(real_output_single(s, b));
     } else {
       BSE_TRY(mark(L, timed, ev++));
     }
@@ -411,12 +412,13 @@ int run_chain(Lane* L, const Setup& S, int count, bool vectors, bse_report* rep)
 bool valid_prec(int prec) { return prec == BSE_PREC_FP64 || prec == BSE_PREC_FP32_REFINE; }
 
 int check_solve_args(int n, const void* A, int lda, const void* B, int ldb, int prec, unsigned flags,
-                     const double* lambda, const void* X, int ldx, const void* d_r, const void* w) {
+                     const double* lambda, const void* X, int ldx, const void* d_r, const void* w,
+                     bool need_B) {
   if (n <= 0) return set_error(-2, "n must be positive");
   if (!A) return set_error(-3, "A is NULL");
   if (lda < n) return set_error(-4, "lda < n");
-  if (!B) return set_error(-5, "B is NULL");
-  if (ldb < n) return set_error(-6, "ldb < n");
+  if (need_B && !B) return set_error(-5, "B is NULL");
+  if (need_B && ldb < n) return set_error(-6, "ldb < n");
   if (!valid_prec(prec)) return set_error(-7, "unsupported precision policy");
   if (flags & ~(BSE_WANT_VECTORS | BSE_WANT_WEIGHTS)) return set_error(-8, "unknown flags");
   if (!lambda) return set_error(-9, "lambda is NULL");
@@ -549,6 +551,58 @@ int bse_solve(bse_ctx* ctx, int n, const void* A, int lda, const void* B, int ld
   char* base = nullptr;
   BSE_TRY(get_workspace(ctx, header_bytes(1) + problem_bytes(2L * n, prec), &base));
   return solve_single_in(&ctx->lane, base, n, A, lda, B, ldb, prec, flags, lambda, X, ldx, d_r, d_l, w, rep);
+}
+
+int bse_solve_tda(bse_ctx* ctx, int n, const void* A, int lda, int prec, unsigned flags, double* lambda,
+                  void* X, int ldx, const void* d_r, const void* d_l, void* w, bse_report* rep) {
+  if (!ctx) return set_error(-1, "ctx is NULL");
+  // argument numbers of bse_solve_tda: B and ldb are absent
+  int rc = check_solve_args(n, A, lda, nullptr, n, prec, flags, lambda, X, ldx, d_r, w, false);
+  if (rc <= -7) rc += 2;
+  if (rc != 0) return rc;
+  BSE_TRY(prologue(ctx));
+  char* base = nullptr;
+  BSE_TRY(get_workspace(ctx, header_bytes(1) + problem_bytes(2L * n, prec), &base));
+  return solve_single_in(&ctx->lane, base, n, A, lda, nullptr, n, prec, flags, lambda, X, ldx, d_r, d_l, w, rep);
+}
+
+int bse_solve_real(bse_ctx* ctx, int n, const double* A, int lda, const double* B, int ldb, int prec,
+                   unsigned flags, double* lambda, double* X, int ldx, const void* d_r, const void* d_l, void* w,
+                   bse_report* rep) {
+  if (!ctx) return set_error(-1, "ctx is NULL");
+  BSE_TRY(check_solve_args(n, A, lda, B, ldb, prec, flags, lambda, X, ldx, d_r, w));
+  BSE_TRY(prologue(ctx));
+  char* base = nullptr;
+  BSE_TRY(get_workspace(ctx, header_bytes(1) + problem_bytes(2L * n, prec), &base));
+  Lane* L = &ctx->lane;
+  const long N = 2L * n;
+  char* pbase = base + header_bytes(1);
+  Setup S;
+  BSE_TRY(setup_batch(L, 1, &N, prec, base, &pbase, &S));
+  const bool vec = (flags & BSE_WANT_VECTORS) != 0;
+  Prob& P = L->hprobs[0];
+  P.A = A;
+  P.lda = lda;
+  P.B = B;
+  P.ldb = ldb;
+  P.lambda = lambda;
+  // the complex eigenvectors are assembled in the Z buffer (free once G =
+  // L Z is formed; ld >= 2n rows by n complex columns fit), then written
+  // to X as real vectors
+  P.X = vec ? P.Z : nullptr;
+  P.ldx = 2L * n;
+  P.Xr = X;
+  P.ldxr = ldx;
+  P.dr = static_cast<const double*>(d_r);
+  P.dl = static_cast<const double*>(d_l);
+  P.w = static_cast<double*>(w);
+  P.flags = flags | FLAG_REAL_IN;
+  BSE_TRY(run_chain(L, S, 1, vec, rep));
+  if (rep) rep->n = n;
+  const int code = info_code(L->hinfo[0], L->hinfo[1], vec);
+  if (code == BSE_EDEVICE) return set_error(BSE_EDEVICE, "no orthonormal real eigenvector basis");
+  if (code == BSE_ENOCONV) return set_error(BSE_ENOCONV, "refinement did not converge within the sweep limit");
+  return code;
 }
 
 int bse_solve_batched(bse_ctx* ctx, int count, const int* n, const void* const* A, const int* lda,

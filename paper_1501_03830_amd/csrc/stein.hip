@@ -446,28 +446,23 @@ __global__ __launch_bounds__(256) void k_transpose(int rows, int cols, const dou
 int bisect_batched(hipStream_t s, const Batch& b) {
   if (b.count <= 0) return 0;
   const int n0 = b.maxn();
-  k_tridiag_prep<<<dim3(1, 1, (unsigned)b.count), 1024, 0, s>>>(b.dev);
-  BSE_LAUNCHED();
-  k_bisect<<<dim3((unsigned)(((long)n0 * MS_LANES + 63) / 64), 1, (unsigned)b.count), 64, 0, s>>>(b.dev);
-  BSE_LAUNCHED();
+  BSE_LAUNCH(k_tridiag_prep, dim3(1, 1, (unsigned)b.count), 1024, 0, s, b.dev);
+  BSE_LAUNCH(k_bisect, dim3((unsigned)(((long)n0 * MS_LANES + 63) / 64), 1, (unsigned)b.count), 64, 0, s, b.dev);
   return 0;
 }
 
 int invit_batched(hipStream_t s, const Batch& b) {
   if (b.count <= 0) return 0;
   const int n0 = b.maxn();
-  k_shifts<<<dim3(1, 1, (unsigned)b.count), 64, 0, s>>>(b.dev);
-  BSE_LAUNCHED();
-  k_invit<<<dim3((unsigned)((n0 + 63) / 64), 1, (unsigned)b.count), 64, 0, s>>>(b.dev);
-  BSE_LAUNCHED();
+  BSE_LAUNCH(k_shifts, dim3(1, 1, (unsigned)b.count), 64, 0, s, b.dev);
+  BSE_LAUNCH(k_invit, dim3((unsigned)((n0 + 63) / 64), 1, (unsigned)b.count), 64, 0, s, b.dev);
   return 0;
 }
 
 int reorth_batched(hipStream_t s, const Batch& b, const int* dflags, int* hflags, int nslots) {
   if (b.count <= 0) return 0;
   const int n0 = b.maxn();
-  k_cluster_ids<<<dim3(1, 1, (unsigned)b.count), 1024, 0, s>>>(b.dev);
-  BSE_LAUNCHED();
+  BSE_LAUNCH(k_cluster_ids, dim3(1, 1, (unsigned)b.count), 1024, 0, s, b.dev);
   if (b.host[0].prec == BSE_PREC_FP32_REFINE) {
     // skip the launches altogether when no problem has a near-degenerate
     // cluster (otherwise the kernels skip the problems without one)
@@ -484,13 +479,11 @@ int reorth_batched(hipStream_t s, const Batch& b, const int* dflags, int* hflags
   const dim3 g2((unsigned)((n0 + 63) / 64), (unsigned)((n0 + 63) / 64), (unsigned)b.count);
   for (int pass = 0; pass < 2; ++pass) {
     if (pass == 1) {
-      k_reorth_gate<<<dim3((unsigned)b.count), 64, 0, s>>>(b.dev);
-      BSE_LAUNCHED();
+      BSE_LAUNCH(k_reorth_gate, dim3((unsigned)b.count), 64, 0, s, b.dev);
     }
     // G = Vt Vt^T (lower), then drop the entries between clusters
     BSE_TRY(gemm_batched(s, b, b.count, GOP_GRAM, 0));
-    k_mask_gram<<<g2, 256, 0, s>>>(b.dev);
-    BSE_LAUNCHED();
+    BSE_LAUNCH(k_mask_gram, g2, 256, 0, s, b.dev);
     BSE_TRY(potrf_batched(s, b, 1, pass == 0));
     // Vt <- L^{-1} Vt: blocked forward substitution over 128-row blocks, each
     // two direct solves with 64 x 64 diagonal blocks around the update of the
@@ -517,8 +510,7 @@ int reorth_batched(hipStream_t s, const Batch& b, const int* dflags, int* hflags
 
 int transpose_to(hipStream_t s, int rows, int cols, const double* src, long lds, double* dst, long ldd) {
   dim3 g((unsigned)((rows + 63) / 64), (unsigned)((cols + 63) / 64));
-  k_transpose<<<g, 256, 0, s>>>(rows, cols, src, lds, dst, ldd);
-  BSE_LAUNCHED();
+  BSE_LAUNCH(k_transpose, g, 256, 0, s, rows, cols, src, lds, dst, ldd);
   return 0;
 }
 

@@ -216,10 +216,8 @@ int trsm_rows_batched(hipStream_t s, const Batch& b, int nact, int sel, int k0) 
   const long rows = (long)(sel == 0 ? b.host[0].N : b.host[0].n) - k0 - NB;
   if (rows <= 0) return 0;
   const dim3 g((unsigned)((rows + NB - 1) / NB), 1, (unsigned)nact);
-  k_trsm_rows<true><<<g, NB, 0, s>>>(b.dev, sel, k0);
-  BSE_LAUNCHED();
-  k_trsm_rows<false><<<g, NB, 0, s>>>(b.dev, sel, k0);
-  BSE_LAUNCHED();
+  BSE_LAUNCH(k_trsm_rows<true>, g, NB, 0, s, b.dev, sel, k0);
+  BSE_LAUNCH(k_trsm_rows<false>, g, NB, 0, s, b.dev, sel, k0);
   return 0;
 }
 
@@ -227,18 +225,15 @@ int trsm_cols_batched(hipStream_t s, const Batch& b, int nact, int b0) {
   if (nact <= 0) return 0;
   const long N0 = b.maxN();
   const dim3 g((unsigned)((N0 + NB - 1) / NB), 1, (unsigned)nact);
-  k_trsm_cols<true><<<g, NB, 0, s>>>(b.dev, b0);
-  BSE_LAUNCHED();
-  k_trsm_cols<false><<<g, NB, 0, s>>>(b.dev, b0);
-  BSE_LAUNCHED();
+  BSE_LAUNCH(k_trsm_cols<true>, g, NB, 0, s, b.dev, b0);
+  BSE_LAUNCH(k_trsm_cols<false>, g, NB, 0, s, b.dev, b0);
   return 0;
 }
 
 int wy_solve_batched(hipStream_t s, const Batch& b, int nact, int q, int h) {
   if (nact <= 0) return 0;
   const long N0 = b.maxN();
-  k_wy_solve<<<dim3((unsigned)((N0 + 255) / 256), 1, (unsigned)nact), 256, 0, s>>>(b.dev, q, h);
-  BSE_LAUNCHED();
+  BSE_LAUNCH(k_wy_solve, dim3((unsigned)((N0 + 255) / 256), 1, (unsigned)nact), 256, 0, s, b.dev, q, h);
   return 0;
 }
 

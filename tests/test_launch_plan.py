@@ -1,0 +1,81 @@
+"""Host-only dry run of the launch plan (bse_plan_check): the sequence of
+kernel launches the library would issue for a solve or a batch, checked
+against the dispatch limits without a GPU, at the benchmark and serving
+sizes (n = 8192 and 16384, both precision policies) and for the 256-problem
+batch.  Also checks launch counts that follow from the method: one skew
+matvec and one update per reflector column (N - 2 per problem of order
+N = 2n), one bisection launch, and the mixed path's FP32 products."""
+
+import ctypes
+
+import pytest
+
+from bse_inputs import batched_sizes
+from paper_1501_03830_amd import _lib
+
+
+def plan(ns, prec, flags=_lib.BSE_WANT_VECTORS | _lib.BSE_WANT_WEIGHTS):
+    lib = _lib.load()
+    buf = ctypes.create_string_buffer(1 << 16)
+    arr = (ctypes.c_int * len(ns))(*ns)
+    rc = lib.bse_plan_check(len(ns), arr, prec, flags, buf, len(buf))
+    lines = buf.value.decode().strip().splitlines()
+    head = lines[0].split()
+    kern = {}
+    for ln in lines[1:]:
+        name, rest = ln.split(" launches ")
+        f = rest.split()
+        kern[name] = {"launches": int(f[0]), "grid_min": tuple(map(int, f[2:5])),
+                      "grid_max": tuple(map(int, f[6:9])), "block_max": int(f[10]), "kernarg_max": int(f[12])}
+    return rc, int(head[3]), int(head[5]), kern
+
+
+def count(kern, prefix):
+    return sum(v["launches"] for k, v in kern.items() if k.lstrip("(").startswith(prefix))
+
+
+@pytest.mark.parametrize("n", [1, 2, 64, 2048, 8192, 16384])
+@pytest.mark.parametrize("prec", [_lib.BSE_PREC_FP64, _lib.BSE_PREC_FP32_REFINE])
+def test_plan_within_dispatch_limits(n, prec):
+    rc, total, ws, kern = plan([n], prec)
+    assert rc == 0, _lib.last_error()
+    N = 2 * n
+    assert count(kern, "sk_symv") == max(N - 2, 0)
+    assert count(kern, "sk_update") == max(N - 2, 0)
+    assert kern["k_bisect"]["launches"] == 1
+    if prec == _lib.BSE_PREC_FP32_REFINE:
+        assert count(kern, "gemm_f32_kernel") > 0
+        assert kern["k_ref_F"]["launches"] >= 1
+    else:
+        assert count(kern, "gemm_f32_kernel") == 0
+    for name, v in kern.items():
+        assert min(v["grid_min"]) >= 1, name
+        assert v["grid_max"][0] * v["block_max"] <= 0xFFFFFFFF, name
+        assert v["block_max"] <= 1024, name
+        assert v["kernarg_max"] <= 4096, name
+    assert ws == _lib.load().bse_footprint_bytes(n, prec, 3)
+
+
+@pytest.mark.parametrize("prec", [_lib.BSE_PREC_FP64, _lib.BSE_PREC_FP32_REFINE])
+def test_plan_of_the_256_problem_batch(prec):
+    ns = [int(k) for k in batched_sizes(256, 64, 1024, seed=4)]
+    rc, total, ws, kern = plan(ns, prec)
+    assert rc == 0, _lib.last_error()
+    # one launch per reflector column of the largest problem serves the batch
+    assert count(kern, "sk_symv") == 2 * max(ns) - 2
+    assert ws == _lib.load().bse_footprint_batched_bytes(len(ns), (ctypes.c_int * len(ns))(*ns), prec, 3)
+
+
+def test_plan_eigenvalues_only_skips_vectors():
+    rc, total, ws, kern = plan([4096], _lib.BSE_PREC_FP64, flags=0)
+    assert rc == 0
+    assert "k_invit" not in kern and "k_finish_X" not in kern
+
+
+def test_plan_rejects_bad_arguments():
+    lib = _lib.load()
+    arr = (ctypes.c_int * 1)(0)
+    assert lib.bse_plan_check(1, arr, 0, 0, None, 0) == -2
+    arr = (ctypes.c_int * 1)(8)
+    assert lib.bse_plan_check(1, arr, 7, 0, None, 0) == -3
+    assert lib.bse_plan_check(0, arr, 0, 0, None, 0) == -1
