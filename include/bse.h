@@ -72,6 +72,11 @@ extern "C" {
 /* flags for bse_solve */
 #define BSE_WANT_VECTORS 1u    /* write X (else only lambda)                   */
 #define BSE_WANT_WEIGHTS 2u    /* write the absorption weights w (needs X)      */
+#define BSE_TWO_STAGE 4u       /* reduce W to tridiagonal form in two stages
+                                  (dense to band on the matrix cores, then
+                                  bulge chasing; Section 3.3's successive band
+                                  reduction); eigenvalues only, FP64, single
+                                  problems (bse_solve, bse_solve_tda)          */
 
 /* stage indices of bse_report.stage_ms */
 #define BSE_STAGE_BUILD_M 0    /* Algorithm 1 step 1                           */
@@ -436,6 +441,12 @@ int bse_form_W(bse_ctx* ctx, int N, const double* L, int ldl, double* W, int ldw
  * k = 0..N-2 (tau[N-2] = 0), and v_k below the subdiagonal of W's column k
  * (v_k[k+1] = 1 implicit).  N >= 2. */
 int bse_sktrd(bse_ctx* ctx, int N, double* W, int ldw, double* alpha, double* tau);
+
+/* Algorithm 3 step 1 in two stages (Section 3.3, successive band
+ * reduction): the same alpha (up to signs, which do not change the
+ * eigenvalues) from the skew-symmetric W (lower triangle read, N x N,
+ * ldw >= N, overwritten).  N >= 2, N <= 32768 + 64. */
+int bse_sktrd2(bse_ctx* ctx, int N, double* W, int ldw, double* alpha);
 
 /* Algorithm 3 step 2 (remark 2): the n = N/2 positive eigenvalues of
  * T_s = tridiag(alpha, 0, alpha) (ascending, by bisection) and, when V is

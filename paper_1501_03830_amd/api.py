@@ -69,7 +69,7 @@ class Context:
     # ------------------------------------------------------------------ solve
     def solve(self, A: torch.Tensor, B: torch.Tensor, d_r: torch.Tensor | None = None,
               d_l: torch.Tensor | None = None, vectors: bool = True, report: bool = False,
-              prec: int = _lib.BSE_PREC_FP64):
+              prec: int = _lib.BSE_PREC_FP64, extra_flags: int = 0):
         """Full eigensolve.  A, B: complex128 (n, n) logical matrices (lower
         triangles used).  Returns dict with lam (n,), X (2n, n) or None,
         w (n,) or None, info, report."""
@@ -92,6 +92,7 @@ class Context:
             drb = d_r.to(dev, torch.complex128).contiguous()
             dlb = None if d_l is None else d_l.to(dev, torch.complex128).contiguous()
             w = torch.empty(n, dtype=torch.complex128, device=dev)
+        flags |= extra_flags
         rep = _lib.BseReport() if report else None
         info = _lib.check(self.lib.bse_solve(
             self.h, n, _ptr(Ac), n, _ptr(Bc), n, prec, flags, _ptr(lam),
@@ -197,7 +198,8 @@ class Context:
 
     def solve_raw(self, n: int, Ac: torch.Tensor, Bc: torch.Tensor, lam: torch.Tensor,
                   Xbuf: torch.Tensor | None, drb: torch.Tensor | None = None, dlb: torch.Tensor | None = None,
-                  w: torch.Tensor | None = None, report: bool = False, prec: int = _lib.BSE_PREC_FP64):
+                  w: torch.Tensor | None = None, report: bool = False, prec: int = _lib.BSE_PREC_FP64,
+                  extra_flags: int = 0):
         """bse_solve on buffers that are already column-major on the device
         (as made by to_colmajor); nothing is copied.  Returns (info, report)."""
         flags = 0
@@ -205,6 +207,7 @@ class Context:
             flags |= _lib.BSE_WANT_VECTORS
         if drb is not None:
             flags |= _lib.BSE_WANT_WEIGHTS
+        flags |= extra_flags
         rep = _lib.BseReport() if report else None
         info = _lib.check(self.lib.bse_solve(
             self.h, n, _ptr(Ac), n, _ptr(Bc), n, prec, flags, _ptr(lam),
@@ -367,6 +370,14 @@ class Context:
         tau = torch.empty(N - 1, dtype=torch.float64, device=self.device)
         _lib.check(self.lib.bse_sktrd(self.h, N, _ptr(Wb), N, _ptr(alpha), _ptr(tau)), "bse_sktrd")
         return from_colmajor(Wb), alpha, tau
+
+    def sktrd2(self, W: torch.Tensor):
+        """Two-stage reduction of a full skew W; returns alpha (N-1,)."""
+        N = W.shape[0]
+        Wb = to_colmajor(W.to(torch.float64), self.device)
+        alpha = torch.empty(N - 1, dtype=torch.float64, device=self.device)
+        _lib.check(self.lib.bse_sktrd2(self.h, N, _ptr(Wb), N, _ptr(alpha)), "bse_sktrd2")
+        return alpha
 
     def tridiag_eig(self, alpha: torch.Tensor, vectors: bool = True):
         N = alpha.shape[0] + 1

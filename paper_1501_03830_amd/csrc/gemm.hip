@@ -211,6 +211,64 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
       }
       break;
     }
+    case GOP_SBR_X:
+    case GOP_SBR_XT:
+    case GOP_SBR_S:
+    case GOP_SBR_Y:
+    case GOP_SBR_Z:
+    case GOP_SBR_S2:
+    case GOP_SBR_YY:
+    case GOP_SBR_R2K: {
+      // panel of the two-stage reduction at column k0 = step: reflectors of
+      // rows r0 = k0 + SBR_B .. N-1, explicit in Vp (P.Vb, ld), T and the
+      // small products in P.S (64 x 64 blocks at 0: S, 4096: T, 8192: Z,
+      // 12288: S2), X in P.W1 and Y in P.W2 (both ld x 64)
+      const int k0 = step;
+      const int r0 = k0 + SBR_B;
+      const int m = P.N - r0;
+      if (m < 2) break;
+      const int nr = (m - 1 < SBR_B) ? m - 1 : SBR_B;   // reflectors in the panel
+      const int B2 = SBR_B * SBR_B;
+      double* Tm = P.S + B2;
+      double* Zm = P.S + 2 * B2;
+      double* S2 = P.S + 3 * B2;
+      double* W22 = P.W + r0 + (long)r0 * ld;
+      switch (op) {
+        case GOP_SBR_X:    // L22 V (zero upper triangle: triangular A)
+          g.ta = 0; g.tb = 0; g.M = m; g.N = nr; g.K = m; g.a_tri = 1;
+          g.A = W22; g.lda = ld; g.B = P.Vb; g.ldb = ld; g.C = P.W1; g.ldc = ld;
+          break;
+        case GOP_SBR_XT:   // - L22^T V
+          g.ta = 1; g.tb = 0; g.M = m; g.N = nr; g.K = m; g.a_tri = 1; g.alpha = -1.0; g.beta = 1.0;
+          g.A = W22; g.lda = ld; g.B = P.Vb; g.ldb = ld; g.C = P.W1; g.ldc = ld;
+          break;
+        case GOP_SBR_S:
+          g.ta = 1; g.tb = 0; g.M = nr; g.N = nr; g.K = m;
+          g.A = P.Vb; g.lda = ld; g.B = P.Vb; g.ldb = ld; g.C = P.S; g.ldc = SBR_B;
+          break;
+        case GOP_SBR_Y:
+          g.ta = 0; g.tb = 0; g.M = m; g.N = nr; g.K = nr;
+          g.A = P.W1; g.lda = ld; g.B = Tm; g.ldb = SBR_B; g.C = P.W2; g.ldc = ld;
+          break;
+        case GOP_SBR_Z:
+          g.ta = 1; g.tb = 0; g.M = nr; g.N = nr; g.K = m;
+          g.A = P.Vb; g.lda = ld; g.B = P.W2; g.ldb = ld; g.C = Zm; g.ldc = SBR_B;
+          break;
+        case GOP_SBR_S2:
+          g.ta = 1; g.tb = 0; g.M = nr; g.N = nr; g.K = nr;
+          g.A = Tm; g.lda = SBR_B; g.B = Zm; g.ldb = SBR_B; g.C = S2; g.ldc = SBR_B;
+          break;
+        case GOP_SBR_YY:
+          g.ta = 0; g.tb = 0; g.M = m; g.N = nr; g.K = nr; g.alpha = -0.5; g.beta = 1.0;
+          g.A = P.Vb; g.lda = ld; g.B = S2; g.ldb = SBR_B; g.C = P.W2; g.ldc = ld;
+          break;
+        default:   // GOP_SBR_R2K, strict lower triangle
+          g.ta = 0; g.tb = 1; g.M = m; g.N = m; g.K = 2 * nr; g.beta = 1.0;
+          g.A = P.Y1; g.lda = ld; g.B = P.Y2; g.ldb = ld; g.C = W22; g.ldc = ld; g.c_uplo = 2;
+          break;
+      }
+      break;
+    }
     default:
       break;
   }

@@ -89,7 +89,20 @@ enum GemmOp {
   GOP_REF_PB,      // refinement: rows n.. of W Ub = W21 Ub[0:n] (W22 = 0)
   GOP_REF_PF,      // final eigenvalues: rows ..n-1 of W Ub, first n columns
   GOP_REF_PFB,     // final eigenvalues: rows n.. of W Ub, first n columns
+  // two-stage reduction, panel at column `step` (rows r0 = step + SBR_B ..):
+  GOP_SBR_X,       // X = L22 Vp (L22 the strict lower part of the trailing block)
+  GOP_SBR_XT,      // X -= L22^T Vp
+  GOP_SBR_S,       // S = Vp^T Vp
+  GOP_SBR_Y,       // Y = X T
+  GOP_SBR_Z,       // Z = Vp^T Y
+  GOP_SBR_S2,      // S2 = T^T Z
+  GOP_SBR_YY,      // Y <- Y - (1/2) Vp S2
+  GOP_SBR_R2K,     // W22 += [Vp Y][Y -Vp]^T (full block)
 };
+
+// Bandwidth of the two-stage reduction's band (the panel width of its first
+// stage).
+constexpr int SBR_B = 64;
 __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step);
 // Product `op` at `step` for the first nact problems of the batch.
 int gemm_batched(hipStream_t s, const Batch& b, int nact, int op, int step);
@@ -134,6 +147,15 @@ struct KernelTimer {
 // W = U T U^T in place: alpha (N-1), tau (N-1), reflectors below the
 // subdiagonal of P.W.
 int sktrd_batched(hipStream_t s, const Batch& b, KernelTimer* timer);
+
+// ---------------------------------------------------------------- sbr.hip
+// Two-stage skew tridiagonalisation of P.W (strict lower triangle, zero
+// upper triangle) for a batch of one: dense to band of width SBR_B (panel
+// Householder QR, MFMA two-sided updates), then band to tridiagonal by bulge
+// chasing (one persistent launch).  alpha as sktrd_batched; the reflectors
+// are not kept (eigenvalue path).  `work` holds the chase's progress words
+// and error flag (device, N + 64 ints).
+int sbr_single(hipStream_t s, const Batch& b, int* work);
 
 // ---------------------------------------------------------------- stein.hip
 // positive eigenvalues of tridiag(alpha, 0, alpha) into P.lambda

@@ -1,0 +1,559 @@
+// Two-stage skew tridiagonalisation (successive band reduction), the route
+// Section 3.3 names for moving the reduction's Level-2 work onto Level-3
+// products.
+//
+// Stage 1, dense to band of width B = SBR_B.  For each panel of B columns at
+// k0, the rows below the band (r0 = k0 + B .. N-1) are factored P = Q R by
+// Householder reflectors (LAPACK dlarfg convention), Q = I - V T V^T; the
+// trailing skew block becomes Q^T W22 Q.  With Y = W22 V T and S2 = T^T V^T Y
+// (skew), Q^T W22 Q = W22 + V Y'^T - Y' V^T for Y' = Y - (1/2) V S2: the
+// skew form of the symmetric two-sided block update (the term that the
+// symmetric case splits in halves is skew here and is absorbed the same
+// way).  W is kept as its strict lower triangle L (the upper triangle is
+// zero), so W22 V = L V - L^T V is two triangular MFMA products and the
+// rank-2B update touches the strict lower triangle only.
+//
+// The panel factorisation is one launch per column.  Launch j finishes the
+// reflector of column j - 1 from the previous launch's per-workgroup partial
+// sums (every workgroup reduces them in the same order): with x that column
+// below its diagonal, x^T x and x^T a_c for the columns c to its right were
+// summed in one pass, so beta, tau and every tau v^T a_c follow without a
+// second reduction (v = (x - beta e_1) / (x_0 - beta)); it then applies the
+// reflector to its own rows and forms the partial sums of column j.
+//
+// Stage 2, band to tridiagonal (bulge chasing).  Sweep s annihilates column
+// s below its subdiagonal with a reflector on rows s+1 .. s+B; applied from
+// both sides it fills a block below the band, whose first column the next
+// reflector (on the next B rows) annihilates, and so on down the matrix.
+// Fill stays within 2B - 1 below the diagonal.  Steps of consecutive sweeps
+// overlap only while sweep s - 1 is within two steps of sweep s, so step t
+// of sweep s may run once sweep s - 1 has completed step t + 2 (found by
+// tracking the entries every step reads and writes on a model of the
+// algorithm).  One persistent launch runs the sweeps on a fixed set of
+// workgroups (sweep s on workgroup s mod G, in order), each publishing its
+// progress with a release store and waiting for its predecessor with
+// acquire loads; the wait is bounded, and a workgroup that runs out of it
+// raises an error flag that makes every other wait give up, so every
+// workgroup exits.
+#include <climits>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace bse {
+
+namespace {
+
+constexpr int BW = SBR_B;
+constexpr int PR = 256;   // panel rows per workgroup, one per thread
+constexpr int PP = BW + 1;  // partial sums per workgroup: x^T x, x^T a_c (c < BW)
+constexpr int PMAX_WG = 128;   // panel workgroups at most (N <= 32768 + BW)
+constexpr int CH_WG = 128;   // workgroups of the bulge-chasing launch
+constexpr int DONE = INT_MAX;
+constexpr long SPIN_MAX = 1L << 22;
+
+// Sum over the 64 lanes of each of 16 values: each exchange hands half of
+// the remaining values to the partner lane (17 shuffles).  On return lane l
+// holds the total of value (l >> 2) & 15.
+__device__ inline double wave_sum16(double (&x)[16]) {
+  const int lane = threadIdx.x & 63;
+  int off = 32;
+#pragma unroll
+  for (int h = 8; h >= 1; h >>= 1) {
+    const bool up = (lane & off) != 0;
+#pragma unroll
+    for (int q = 0; q < h; ++q) {
+      const double snd = up ? x[q] : x[q + h];
+      const double kp = up ? x[q + h] : x[q];
+      x[q] = kp + __shfl_xor(snd, off, 64);
+    }
+    off >>= 1;
+  }
+  double r = x[0];
+  r += __shfl_xor(r, 2, 64);
+  r += __shfl_xor(r, 1, 64);
+  return r;
+}
+
+// partial sums [2][nwg][PP], then row buffers [2][BW] (in P.Yrow)
+__device__ inline double* panel_part(const Prob& P) { return P.Yrow; }
+
+// The panel at k0, in one launch.  Workgroup g holds rows 256g .. 256g+255
+// of the panel in registers (one row per thread, all B columns) for the
+// whole factorisation.  Column step j finishes reflector j - 1 from the
+// partial sums every workgroup published in step j - 1 (each workgroup
+// reduces them in the same order), applies it to its rows, then publishes
+// its partial sums for column j: x^T x and x^T a_c for the columns c to the
+// right, from which beta, tau and every tau v^T a_c follow without a second
+// reduction (v = (x - beta e_1) / (x_0 - beta)).  Steps are separated by a
+// grid barrier: an arrival counter (release increments, acquire loads) with
+// a bounded wait; a workgroup that runs out of it raises the error flag,
+// which ends every other wait, so all workgroups exit.  The grid (at most
+// PMAX_WG workgroups) is far below what the device holds at once.
+__device__ inline bool grid_wait(int* counter, int target, int* err) {
+  long spins = 0;
+  while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > SPIN_MAX) {
+      __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  (void)__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+  return true;
+}
+
+__global__ __launch_bounds__(PR) void k_sbr_panel(const Prob* __restrict__ probs, int k0, int* __restrict__ counter,
+                                                  int* __restrict__ err) {
+  __shared__ double tot[PP];
+  __shared__ double wv[BW];
+  __shared__ double red[PR / 64][PP];
+  __shared__ double stage[PMAX_WG * PP];
+  __shared__ int ok_flag;
+  const Prob& P = probs[0];
+  const long ld = P.ld;
+  const int N = P.N;
+  const int r0 = k0 + BW;
+  const int m = N - r0;
+  const int nr = min(m - 1, BW);
+  const int g = blockIdx.x, nwg = gridDim.x;
+  const long i = (long)g * PR + threadIdx.x;   // panel row
+  double* Pw = P.W + r0 + (long)k0 * ld;
+  double* part = panel_part(P);
+  double* rowbuf = part + 2L * nwg * PP;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool in = i < m;
+  double a[BW];
+#pragma unroll
+  for (int c = 0; c < BW; ++c) a[c] = in ? Pw[i + (long)c * ld] : 0.0;
+  for (int j = 0; j <= nr; ++j) {
+    if (j >= 1) {
+      // wait for every workgroup's partial sums of column j - 1
+      if (threadIdx.x == 0) ok_flag = grid_wait(counter, nwg * j, err) ? 1 : 0;
+      __syncthreads();
+      if (!ok_flag) return;
+      const int c0 = j - 1;
+      const double* pp = part + (long)(c0 & 1) * nwg * PP;
+      {
+        constexpr int NS = (PMAX_WG * PP + PR - 1) / PR;
+        double st[NS];
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+          const int e = threadIdx.x + u * PR;
+          st[u] = (e < nwg * PP) ? pp[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+          const int e = threadIdx.x + u * PR;
+          if (e < nwg * PP) stage[e] = st[u];
+        }
+      }
+      __syncthreads();
+      // column c summed over the workgroups in order, in four interleaved
+      // partial chains combined in a fixed order
+      for (int e = threadIdx.x; e < 4 * PP; e += PR) {
+        const int c = e % PP, h = e / PP;
+        double acc = 0.0;
+        for (int q = h; q < nwg; q += 4) acc += stage[q * PP + c];
+        red[h][c] = acc;
+      }
+      __syncthreads();
+      if (threadIdx.x < PP)
+        tot[threadIdx.x] = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+      __syncthreads();
+      const double* rb = rowbuf + (c0 & 1) * BW;
+      const double sigma = tot[0];
+      const double x0 = rb[c0];
+      double beta = x0, tau = 0.0, scale = 0.0;
+      if (sigma > 0.0) {
+        beta = -copysign(sqrt(x0 * x0 + sigma), x0);
+        tau = (beta - x0) / beta;
+        scale = 1.0 / (x0 - beta);
+      }
+      if (threadIdx.x < BW) {
+        const int c = threadIdx.x;
+        wv[c] = (c > c0) ? tau * (rb[c] + scale * (tot[1 + c] - x0 * rb[c])) : 0.0;
+      }
+      __syncthreads();
+      if (in && i >= c0) {
+        // v_i = 1 on the diagonal row (which becomes beta), x_i scale below
+        double xc = 0.0;
+#pragma unroll
+        for (int c = 0; c < BW; ++c) xc = (c == c0) ? a[c] : xc;
+        const double vi = (i == c0) ? 1.0 : xc * scale;
+        const double keep = (i == c0) ? beta : vi;
+#pragma unroll
+        for (int c = 0; c < BW; ++c) {
+          if (c == c0) a[c] = keep;
+          else if (c > c0) a[c] -= wv[c] * vi;
+        }
+      }
+      if (g == 0 && threadIdx.x == 0) P.tau[k0 + c0] = tau;
+    }
+    if (j < nr) {
+      // x = column j below row j (own rows), sums of x^2 (rows > j) and of
+      // x a_c (rows >= j) for c > j; row j itself goes to the row buffer
+      double xv = 0.0;
+#pragma unroll
+      for (int c = 0; c < BW; ++c) xv = (c == j) ? a[c] : xv;
+      if (!(in && i >= j)) xv = 0.0;
+      const double s0 = wave_sum((i > j && in) ? xv * xv : 0.0);
+      if (lane == 0) red[wave][0] = s0;
+#pragma unroll
+      for (int gq = 0; gq < BW / 16; ++gq) {
+        double pr[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) pr[q] = xv * a[16 * gq + q];
+        const double t = wave_sum16(pr);
+        if ((lane & 3) == 0) red[wave][1 + 16 * gq + (lane >> 2)] = t;
+      }
+      __syncthreads();
+      double* mine = part + (long)(j & 1) * nwg * PP + (long)g * PP;
+      if (threadIdx.x < PP) {
+        const int c = threadIdx.x;
+        double acc = 0.0;
+        if (c == 0 || c - 1 > j) {
+          for (int w = 0; w < PR / 64; ++w) acc += red[w][c];
+        }
+        mine[c] = acc;
+      }
+      if (i == j) {
+        double* rb = rowbuf + (j & 1) * BW;
+#pragma unroll
+        for (int c = 0; c < BW; ++c)
+          if (c >= j) rb[c] = a[c];
+      }
+      // arrive: this workgroup's sums are published
+      __syncthreads();
+      if (threadIdx.x == 0) __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  if (in) {
+#pragma unroll
+    for (int c = 0; c < BW; ++c) Pw[i + (long)c * ld] = a[c];
+  }
+}
+
+// arrival counter of the panel launch to zero (and the panels' error flag,
+// before the first panel)
+__global__ void k_sbr_panel_reset(int* __restrict__ counter, int* __restrict__ err, int first) {
+  if (threadIdx.x == 0) {
+    *counter = 0;
+    if (first) *err = 0;
+  }
+}
+
+// Explicit reflectors of the panel at k0 (ones on the diagonal, zeros
+// above) into P.Vb, rows 0 .. m-1 of the panel.
+__global__ __launch_bounds__(256) void k_sbr_extract(const Prob* __restrict__ probs, int k0) {
+  const Prob& P = probs[0];
+  const long ld = P.ld;
+  const int r0 = k0 + BW;
+  const int m = P.N - r0;
+  const int nr = min(m - 1, BW);
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= m) return;
+  const BSE_GLOBAL double* __restrict__ Pw = gbl(P.W) + r0 + (long)k0 * ld;
+  BSE_GLOBAL double* __restrict__ V = gbl(P.Vb);
+  for (int c = 0; c < BW; ++c) {
+    double v = 0.0;
+    if (c < nr) v = (i < c) ? 0.0 : ((i == c) ? 1.0 : Pw[i + (long)c * ld]);
+    V[i + (long)c * ld] = v;
+  }
+}
+
+// T of the compact WY form Q = I - V T V^T from S = V^T V and tau (LAPACK
+// dlarft, forward): T[j, j] = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] S[0:j, j].
+__global__ __launch_bounds__(64) void k_sbr_T(const Prob* __restrict__ probs, int k0) {
+  __shared__ double Ts[BW][BW + 1];
+  const Prob& P = probs[0];
+  const int m = P.N - (k0 + BW);
+  const int nr = min(m - 1, BW);
+  const BSE_GLOBAL double* __restrict__ S = gbl(P.S);
+  const BSE_GLOBAL double* __restrict__ tau = gbl(P.tau) + k0;
+  __shared__ double Ss[BW][BW + 1];
+  const int r = threadIdx.x;
+  for (int c = 0; c < BW; ++c) {
+    Ts[r][c] = 0.0;
+    Ss[r][c] = (r < nr && c < nr) ? S[r + c * BW] : 0.0;
+  }
+  __syncthreads();
+  for (int jj = 0; jj < nr; ++jj) {
+    const double tj = tau[jj];
+    if (r < jj) {
+      double acc = 0.0;
+      for (int l = r; l < jj; ++l) acc += Ts[r][l] * Ss[l][jj];
+      Ts[r][jj] = -tj * acc;
+    } else if (r == jj) {
+      Ts[r][jj] = tj;
+    }
+    __syncthreads();
+  }
+  BSE_GLOBAL double* __restrict__ T = gbl(P.S) + BW * BW;
+  for (int c = 0; c < BW; ++c) T[r + c * BW] = Ts[r][c];
+}
+
+// Y1 = [V | Y'], Y2 = [Y' | -V] for the rank-2B update (Y' in P.W2)
+__global__ __launch_bounds__(256) void k_sbr_pack(const Prob* __restrict__ probs, int k0) {
+  const Prob& P = probs[0];
+  const long ld = P.ld;
+  const int m = P.N - (k0 + BW);
+  const int nr = min(m - 1, BW);
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= m) return;
+  const BSE_GLOBAL double* __restrict__ V = gbl(P.Vb);
+  const BSE_GLOBAL double* __restrict__ Y = gbl(P.W2);
+  BSE_GLOBAL double* __restrict__ Y1 = gbl(P.Y1);
+  BSE_GLOBAL double* __restrict__ Y2 = gbl(P.Y2);
+  for (int c = 0; c < nr; ++c) {
+    const double v = V[i + (long)c * ld], y = Y[i + (long)c * ld];
+    Y1[i + (long)c * ld] = v;
+    Y1[i + (long)(nr + c) * ld] = y;
+    Y2[i + (long)c * ld] = y;
+    Y2[i + (long)(nr + c) * ld] = -v;
+  }
+}
+
+// Zero the chase's fill zone, B < i - j <= 2B (the panel reflectors of
+// stage 1 were stored there); progress words to 0, error flag to 0.
+__global__ __launch_bounds__(256) void k_sbr_prepare(const Prob* __restrict__ probs, int* __restrict__ prog,
+                                                     int* __restrict__ err) {
+  const Prob& P = probs[0];
+  const long ld = P.ld;
+  const int N = P.N;
+  const long j = (long)blockIdx.x * 2 + (threadIdx.x >> 7);   // two columns per workgroup
+  const int q = threadIdx.x & 127;                            // offset BW+1 .. 2BW
+  if (j < N) {
+    const long i = j + BW + 1 + q;
+    if (q < BW && i < N) gbl(P.W)[i + j * ld] = 0.0;
+    if (q == 0) prog[j] = 0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *err = 0;
+}
+
+__device__ inline int load_progress(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The band is shared between the workgroups of consecutive sweeps, so the
+// chase reads and writes it with relaxed atomic accesses at agent scope
+// (coherent across the device's L2 caches without whole-cache write-backs);
+// ordering comes from one release store and one acquire load of the
+// progress words per step, made by one thread on either side of a
+// workgroup barrier.
+__device__ inline double ld_band(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_band(double* p, double x) {
+  __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bulge chasing, persistent: workgroup w runs sweeps w, w + G, ...
+//
+// One step (rows r0 .. r1 of the reflector, len <= B) works on four pieces,
+// all loaded into registers at its start (lane = row, wave = group of
+// columns) so that every global load of the step is in flight at once:
+// the column col being annihilated; the block left of the reflector's rows
+// (columns col+1 .. r0-1, wave w taking every fourth column); the diagonal
+// block (lower part, wave w taking columns 16w .. 16w+15); and the block
+// below (rows r1+1 .. r0+2B-1, same columns).  Then H = I - tau v v^T is
+// applied: from the left to the left block, as W + v p^T - p v^T with
+// p = tau W v to the diagonal block (v^T W v = 0 for skew W), and from the
+// right to the block below.
+__global__ __launch_bounds__(256) void k_sbr_chase(const Prob* __restrict__ probs, int* __restrict__ prog,
+                                                   int* __restrict__ err) {
+  __shared__ double v[BW];
+  __shared__ double pv[BW];
+  __shared__ double rpart[4][BW];
+  __shared__ double csum[BW];
+  __shared__ double coef[2];   // tau, and 1 if the reflector is not the identity
+  __shared__ int abort_flag;
+  const Prob& P = probs[0];
+  const int N = P.N;
+  const long ld = P.ld;
+  double* __restrict__ W = P.W;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int s = blockIdx.x; s < N - 2; s += gridDim.x) {
+    int col = s, r0 = s + 1, t = 0;
+    while (r0 < N - 1) {
+      const int r1 = min(r0 + BW - 1, N - 1);
+      const int len = r1 - r0 + 1;
+      if (s > 0) {
+        if (tid == 0) {
+          long spins = 0;
+          int ok = 1;
+          while (load_progress(prog + s - 1) < t + 3) {
+            if (load_progress(err) != 0 || ++spins > SPIN_MAX) {
+              ok = 0;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+          }
+          if (!ok) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          // acquire: the predecessor's band writes happen before this step
+          else (void)__hip_atomic_load(prog + s - 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+          abort_flag = !ok;
+        }
+        __syncthreads();
+        if (abort_flag) return;
+      }
+      const int q0 = r1 + 1;
+      const int q1 = min(r0 + 2 * BW - 1, N - 1);
+      const int nq = q1 >= q0 ? q1 - q0 + 1 : 0;
+      // loads: the column (wave 0), then the three blocks
+      double x = 0.0;
+      if (wave == 0 && lane < len) x = ld_band(W + (r0 + lane) + (long)col * ld);
+      double aL[16], aD[16], aR[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int c = col + 1 + wave + 4 * q;
+        aL[q] = (lane < len && c < r0) ? ld_band(W + (r0 + lane) + (long)c * ld) : 0.0;
+        const int j = 16 * wave + q;
+        aD[q] = (lane < len && j < lane) ? ld_band(W + (r0 + lane) + (long)(r0 + j) * ld) : 0.0;
+        aR[q] = (lane < nq && j < len) ? ld_band(W + (q0 + lane) + (long)(r0 + j) * ld) : 0.0;
+      }
+      // (1) the reflector
+      if (wave == 0) {
+        const double sig = wave_sum((lane >= 1 && lane < len) ? x * x : 0.0);
+        const double x0 = __shfl(x, 0, 64);
+        double beta = x0, tau = 0.0, scale = 0.0;
+        if (sig > 0.0) {
+          beta = -copysign(sqrt(x0 * x0 + sig), x0);
+          tau = (beta - x0) / beta;
+          scale = 1.0 / (x0 - beta);
+        }
+        v[lane] = (lane == 0) ? 1.0 : ((lane < len) ? x * scale : 0.0);
+        if (lane == 0) {
+          coef[0] = tau;
+          coef[1] = (sig > 0.0) ? 1.0 : 0.0;
+        }
+        if (lane < len) st_band(W + (r0 + lane) + (long)col * ld, (lane == 0) ? beta : 0.0);
+      }
+      __syncthreads();
+      const double tau = coef[0];
+      if (coef[1] != 0.0) {
+        const double vi = v[lane];
+        // (2) left block: w_c = tau v^T a_c, a_c -= w_c v
+        {
+          double pr[16];
+#pragma unroll
+          for (int q = 0; q < 16; ++q) pr[q] = aL[q] * vi;
+          const double tot = wave_sum16(pr);
+#pragma unroll
+          for (int q = 0; q < 16; ++q) {
+            const double wc = tau * __shfl(tot, 4 * q, 64);
+            aL[q] -= wc * vi;
+          }
+        }
+        // (3) diagonal block, D = L - L^T with L its strict lower part:
+        // rows of L v by thread partials, columns of L^T v by lane sums
+        {
+          double rs = 0.0, pr[16];
+#pragma unroll
+          for (int q = 0; q < 16; ++q) {
+            const int j = 16 * wave + q;
+            rs += aD[q] * ((j < BW) ? v[j] : 0.0);
+            pr[q] = aD[q] * vi;
+          }
+          rpart[wave][lane] = rs;
+          const double ct = wave_sum16(pr);
+          if ((lane & 3) == 0) csum[16 * wave + (lane >> 2)] = ct;
+          __syncthreads();
+          if (tid < BW)
+            pv[tid] = (tid < len) ? tau * (rpart[0][tid] + rpart[1][tid] + rpart[2][tid] + rpart[3][tid] - csum[tid])
+                                  : 0.0;
+          __syncthreads();
+          const double pi = pv[lane];
+#pragma unroll
+          for (int q = 0; q < 16; ++q) {
+            const int j = 16 * wave + q;
+            aD[q] += vi * pv[j] - pi * v[j];
+          }
+        }
+        // (4) block below: u = tau R v (row sums), R -= u v^T
+        {
+          double rs = 0.0;
+#pragma unroll
+          for (int q = 0; q < 16; ++q) rs += aR[q] * v[16 * wave + q];
+          __syncthreads();
+          rpart[wave][lane] = rs;
+          __syncthreads();
+          const double u = tau * (rpart[0][lane] + rpart[1][lane] + rpart[2][lane] + rpart[3][lane]);
+#pragma unroll
+          for (int q = 0; q < 16; ++q) aR[q] -= u * v[16 * wave + q];
+        }
+        // stores
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int c = col + 1 + wave + 4 * q;
+          if (lane < len && c < r0) st_band(W + (r0 + lane) + (long)c * ld, aL[q]);
+          const int j = 16 * wave + q;
+          if (lane < len && j < lane) st_band(W + (r0 + lane) + (long)(r0 + j) * ld, aD[q]);
+          if (lane < nq && j < len) st_band(W + (q0 + lane) + (long)(r0 + j) * ld, aR[q]);
+        }
+      }
+      // release: this step's band writes, by one thread after the barrier
+      __syncthreads();
+      if (tid == 0) __hip_atomic_store(prog + s, t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      col = r0;
+      r0 = r1 + 1;
+      ++t;
+    }
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(prog + s, DONE, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// alpha[k] = T[k, k+1] = -(subdiagonal entry)
+__global__ __launch_bounds__(256) void k_sbr_alpha(const Prob* __restrict__ probs) {
+  const Prob& P = probs[0];
+  const long k = (long)blockIdx.x * 256 + threadIdx.x;
+  if (k >= P.N - 1) return;
+  gbl(P.alpha)[k] = -gbl(P.W)[(k + 1) + k * P.ld];
+}
+
+}  // namespace
+
+int sbr_single(hipStream_t s, const Batch& b, int* work) {
+  if (b.count != 1) return set_error(BSE_EUNSUPPORTED, "the two-stage reduction runs one problem at a time");
+  const Prob& P = b.host[0];
+  const int N = P.N;
+  if (N < 2) return 0;
+  for (int k0 = 0;; k0 += BW) {
+    const int r0 = k0 + BW;
+    const int m = N - r0;
+    if (m < 2) break;
+    const int nr = m - 1 < BW ? m - 1 : BW;
+    const unsigned nwg = (unsigned)((m + PR - 1) / PR);
+    if (nwg > (unsigned)PMAX_WG) return set_error(BSE_EUNSUPPORTED, "two-stage reduction: order too large");
+    BSE_LAUNCH(k_sbr_panel_reset, dim3(1), dim3(64), 0, s, work + N + 1, work + N + 2, k0 == 0 ? 1 : 0);
+    BSE_LAUNCH(k_sbr_panel, dim3(nwg), dim3(PR), 0, s, b.dev, k0, work + N + 1, work + N + 2);
+    BSE_LAUNCH(k_sbr_extract, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, b.dev, k0);
+    BSE_TRY(gemm_batched(s, b, 1, GOP_SBR_X, k0));
+    BSE_TRY(gemm_batched(s, b, 1, GOP_SBR_XT, k0));
+    BSE_TRY(gemm_batched(s, b, 1, GOP_SBR_S, k0));
+    BSE_LAUNCH(k_sbr_T, dim3(1), dim3(64), 0, s, b.dev, k0);
+    BSE_TRY(gemm_batched(s, b, 1, GOP_SBR_Y, k0));
+    BSE_TRY(gemm_batched(s, b, 1, GOP_SBR_Z, k0));
+    BSE_TRY(gemm_batched(s, b, 1, GOP_SBR_S2, k0));
+    BSE_TRY(gemm_batched(s, b, 1, GOP_SBR_YY, k0));
+    BSE_LAUNCH(k_sbr_pack, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, b.dev, k0);
+    BSE_TRY(gemm_batched(s, b, 1, GOP_SBR_R2K, k0));
+  }
+  int* prog = work;
+  int* err = work + N;
+  BSE_LAUNCH(k_sbr_prepare, dim3((unsigned)((N + 1) / 2)), dim3(256), 0, s, b.dev, prog, err);
+  if (N > 2) {
+    const unsigned G = (unsigned)(N - 2 < CH_WG ? N - 2 : CH_WG);
+    BSE_LAUNCH(k_sbr_chase, dim3(G), dim3(256), 0, s, b.dev, prog, err);
+  }
+  BSE_LAUNCH(k_sbr_alpha, dim3((unsigned)((N - 1 + 255) / 256)), dim3(256), 0, s, b.dev);
+  int herr[3] = {0, 0, 0};
+  BSE_HIP(hipMemcpyAsync(herr, err, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+  BSE_HIP(hipStreamSynchronize(s));
+  if (herr[0] != 0) return set_error(BSE_EDEVICE, "bulge chasing: a sweep waited too long for its predecessor");
+  if (herr[2] != 0) return set_error(BSE_EDEVICE, "two-stage panel: a workgroup waited too long at a column barrier");
+  return 0;
+}
+
+}  // namespace bse

@@ -328,8 +328,13 @@ int run_chain(Lane* L, const Setup& S, int count, bool vectors, bse_report* rep)
     if (live > 0) BSE_TRY(upload(L, S, live));
   }
   // the mixed path keeps the full FP64 W for the refinement and reduces an
-  // FP32 copy of its lower triangle
+  // FP32 copy of its lower triangle; the two-stage reduction updates the
+  // full skew matrix
+  const bool two = b.count == 1 && (L->hprobs[0].flags & BSE_TWO_STAGE) != 0;
   BSE_TRY(form_W_batched(s, b, mixed));
+  // the two-stage reduction keeps W as its strict lower triangle over a zero
+  // upper triangle
+  if (two) BSE_TRY(zero_upper(s, L->hprobs[0].N, L->hprobs[0].W, L->hprobs[0].ld));
   if (mixed) BSE_TRY(to_f32_batched(s, b));
   BSE_TRY(mark(L, timed, ev++));
   KernelTimer ktimer;
@@ -344,7 +349,8 @@ int run_chain(Lane* L, const Setup& S, int count, bool vectors, bse_report* rep)
     ktimer.ev = L->kev.data();
     ktimer.cap = (int)L->kev.size();
   }
-  BSE_TRY(sktrd_batched(s, b, L->timing ? &ktimer : nullptr));
+  if (two) BSE_TRY(sbr_single(s, b, reinterpret_cast<int*>(L->hprobs[0].Ycol)));
+  else BSE_TRY(sktrd_batched(s, b, L->timing ? &ktimer : nullptr));
   BSE_TRY(mark(L, timed, ev++));
   BSE_TRY(bisect_batched(s, b));
   BSE_TRY(mark(L, timed, ev++));
@@ -420,11 +426,13 @@ int check_solve_args(int n, const void* A, int lda, const void* B, int ldb, int 
   if (need_B && !B) return set_error(-5, "B is NULL");
   if (need_B && ldb < n) return set_error(-6, "ldb < n");
   if (!valid_prec(prec)) return set_error(-7, "unsupported precision policy");
-  if (flags & ~(BSE_WANT_VECTORS | BSE_WANT_WEIGHTS)) return set_error(-8, "unknown flags");
+  if (flags & ~(BSE_WANT_VECTORS | BSE_WANT_WEIGHTS | BSE_TWO_STAGE)) return set_error(-8, "unknown flags");
   if (!lambda) return set_error(-9, "lambda is NULL");
   const bool vec = (flags & BSE_WANT_VECTORS) != 0;
   const bool wts = (flags & BSE_WANT_WEIGHTS) != 0;
   if (wts && !vec) return set_error(-8, "weights need eigenvectors");
+  if ((flags & BSE_TWO_STAGE) && (vec || prec != BSE_PREC_FP64))
+    return set_error(BSE_EUNSUPPORTED, "the two-stage reduction gives FP64 eigenvalues only");
   if (vec && !X) return set_error(-10, "X is NULL");
   if (vec && ldx < 2 * n) return set_error(-11, "ldx < 2n");
   if (wts && !d_r) return set_error(-12, "d_r is NULL");
@@ -833,6 +841,27 @@ int bse_sktrd(bse_ctx* ctx, int N, double* W, int ldw, double* alpha, double* ta
   BSE_TRY(copy_matrix(s, N, N, P.W, P.ld, W, ldw));
   BSE_HIP(hipMemcpyAsync(alpha, P.alpha, (N - 1) * sizeof(double), hipMemcpyDeviceToDevice, s));
   BSE_HIP(hipMemcpyAsync(tau, P.tau, (N - 1) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  BSE_HIP(hipStreamSynchronize(s));
+  return 0;
+}
+
+int bse_sktrd2(bse_ctx* ctx, int N, double* W, int ldw, double* alpha) {
+  if (!ctx) return set_error(-1, "ctx is NULL");
+  if (N < 2) return set_error(-2, "N must be >= 2");
+  if (!W) return set_error(-3, "W is NULL");
+  if (ldw < N) return set_error(-4, "ldw < N");
+  if (!alpha) return set_error(-5, "alpha is NULL");
+  BSE_TRY(prologue(ctx));
+  Setup S;
+  BSE_TRY(setup_single(ctx, N, &S));
+  const Prob& P = ctx->lane.hprobs[0];
+  hipStream_t s = ctx->lane.stream;
+  BSE_TRY(upload(&ctx->lane, S, 1));
+  BSE_TRY(copy_matrix(s, N, N, W, ldw, P.W, P.ld));
+  BSE_TRY(zero_upper(s, N, P.W, P.ld));
+  BSE_TRY(sbr_single(s, single_batch(ctx, S), reinterpret_cast<int*>(P.Ycol)));
+  BSE_TRY(copy_matrix(s, N, N, P.W, P.ld, W, ldw));
+  BSE_HIP(hipMemcpyAsync(alpha, P.alpha, (N - 1) * sizeof(double), hipMemcpyDeviceToDevice, s));
   BSE_HIP(hipStreamSynchronize(s));
   return 0;
 }

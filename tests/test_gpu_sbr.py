@@ -1,0 +1,107 @@
+"""Two-stage skew tridiagonalisation (BSE_TWO_STAGE, bse_sktrd2: dense to
+band on the matrix cores, then bulge chasing) against the oracle, through the
+C ABI.
+
+Both the one-stage and the two-stage reduction keep U e_1 = e_1, so by the
+implicit-Q argument they give the same |alpha| (tolerance 1e-10 of max|alpha|:
+forward errors of the two reductions, ~N eps kappa, at the sizes here), and
+the same eigenvalues (1e-13 lambda_max end to end, as the one-stage parity
+tests).  Sizes span one and several 64-column panels with ragged tails;
+random skew matrices of odd order check the reduction alone.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import bse_oracle as bo
+from bse_inputs import gen_bse, gen_closed_form
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def tt(a):
+    return torch.from_numpy(np.ascontiguousarray(a))
+
+
+def npc(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1501_03830_amd.api import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("n", [1, 2, 33, 64, 65, 100, 150])
+def test_sktrd2_alpha_matches_one_stage(ctx, n):
+    say(f"[sktrd2] n={n}")
+    p = gen_bse(n, seed=30 + n)
+    Lo, _ = bo.cholesky(bo.build_M(p.A, p.B))
+    Wo = bo.form_W(Lo)
+    ao, _, _ = bo.skew_tridiagonalize(Wo)
+    a2 = npc(ctx.sktrd2(tt(Wo)))
+    d = float(np.max(np.abs(np.abs(a2) - np.abs(ao)))) / float(np.max(np.abs(ao)))
+    lam_o = bo.bisect_positive(ao)
+    lam, _ = ctx.tridiag_eig(torch.from_numpy(a2), vectors=False)
+    el = float(np.max(np.abs(npc(lam) - lam_o))) / float(lam_o.max())
+    say(f"  |alpha| {d:.2e}  eigenvalues {el:.2e}")
+    assert d <= 1e-10 and el <= 1e-13
+
+
+@pytest.mark.parametrize("N", [3, 5, 129, 131, 257])
+def test_sktrd2_random_skew(ctx, N):
+    g = np.random.default_rng(N).standard_normal((N, N))
+    W = g - g.T
+    ao, _, _ = bo.skew_tridiagonalize(W)
+    a2 = npc(ctx.sktrd2(tt(W)))
+    d = float(np.max(np.abs(np.abs(a2) - np.abs(ao)))) / float(np.max(np.abs(ao)))
+    say(f"[sktrd2] random skew N={N}: |alpha| {d:.2e}")
+    assert d <= 1e-10
+
+
+@pytest.mark.parametrize("n", [1, 2, 33, 64, 100, 300])
+def test_two_stage_solve_matches_oracle(ctx, n):
+    from paper_1501_03830_amd import _lib
+    p = gen_bse(n, s_a=0.3, s_b=0.05, seed=800 + n)
+    r = ctx.solve(tt(p.A), tt(p.B), vectors=False, extra_flags=_lib.BSE_TWO_STAGE)
+    assert r["info"] == 0
+    lo = oracle.solve(p.A, p.B).lam
+    el = float(np.max(np.abs(npc(r["lam"]) - lo))) / float(lo.max())
+    say(f"[two-stage solve] n={n}: eig {el:.2e}")
+    assert el <= 1e-13
+
+
+@pytest.mark.parametrize("n", [2048, 8192])
+def test_two_stage_closed_form(ctx, n):
+    from paper_1501_03830_amd import _lib
+    p = gen_closed_form(n, seed=30)
+    exact = np.asarray(p.exact_lambda)
+    r = ctx.solve(tt(p.A), tt(p.B), vectors=False, extra_flags=_lib.BSE_TWO_STAGE, report=True)
+    assert r["info"] == 0
+    err = float(np.max(np.abs(npc(r["lam"]) - exact))) / float(exact.max())
+    say(f"[two-stage closed form] n={n}: eig {err:.2e}, {r['report']['total_ms']:.1f} ms "
+        f"(sktrd {r['report']['stage_ms']['sktrd']:.1f} ms)")
+    assert err <= 1e-10
+
+
+def test_two_stage_flag_limits(ctx):
+    from paper_1501_03830_amd import _lib
+    p = gen_bse(20, seed=3)
+    with pytest.raises(_lib.BseError) as e:
+        ctx.solve(tt(p.A), tt(p.B), vectors=True, extra_flags=_lib.BSE_TWO_STAGE)
+    assert e.value.code == _lib.BSE_EUNSUPPORTED
+    with pytest.raises(_lib.BseError) as e:
+        ctx.solve(tt(p.A), tt(p.B), vectors=False, prec=_lib.BSE_PREC_FP32_REFINE, extra_flags=_lib.BSE_TWO_STAGE)
+    assert e.value.code == _lib.BSE_EUNSUPPORTED
