@@ -371,7 +371,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ 
   __shared__ double smem[SMEM];
 
   int stp = step;
-  if (probs && op >= GOP_REF_P) {
+  if (probs && is_refine_op(op)) {
     // refinement products: skip problems that finished in an earlier sweep;
     // step < 0 means the problem's own final sweep
     const int st = *gbl(probs[blockIdx.z].refstate);
@@ -674,7 +674,7 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const Prob* __restrict__ 
   static_assert(EC * (TBM + 1) <= 2 * (AS + BS), "epilogue chunk does not fit");
   __shared__ float smem[2 * (AS + BS)];
   int stp = step;
-  if (probs && op >= GOP_REF_P) {
+  if (probs && is_refine_op(op)) {
     const int st = *gbl(probs[blockIdx.z].refstate);
     if (step >= 0 && st != 0 && st <= step) return;
     if (step < 0) stp = st;
@@ -886,7 +886,7 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const Prob* __restrict__ 
 __global__ __launch_bounds__(256) void k_splitk_reduce(const Prob* __restrict__ probs, int op, int step,
                                                        GemmParams single) {
   int stp = step;
-  if (probs && op >= GOP_REF_P) {
+  if (probs && is_refine_op(op)) {
     const int st = *gbl(probs[blockIdx.z].refstate);
     if (step >= 0 && st != 0 && st <= step) return;
     if (step < 0) stp = st;

@@ -100,6 +100,10 @@ enum GemmOp {
   GOP_SBR_R2K,     // W22 += [Vp Y][Y -Vp]^T (full block)
 };
 
+// Refinement products, which read the problem's refinement state (the sweep
+// it converged in) to skip finished problems; no other product reads it.
+__host__ __device__ constexpr bool is_refine_op(int op) { return op >= GOP_REF_P && op <= GOP_REF_PFB; }
+
 // Bandwidth of the two-stage reduction's band (the panel width of its first
 // stage).
 constexpr int SBR_B = 64;

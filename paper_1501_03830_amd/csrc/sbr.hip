@@ -519,6 +519,9 @@ int sbr_single(hipStream_t s, const Batch& b, int* work) {
   const Prob& P = b.host[0];
   const int N = P.N;
   if (N < 2) return 0;
+  // the panel's error word is read after the chase whether or not a panel
+  // ran (orders up to BW + 1 have none), so it is cleared first
+  BSE_LAUNCH(k_sbr_panel_reset, dim3(1), dim3(64), 0, s, work + N + 1, work + N + 2, 1);
   for (int k0 = 0;; k0 += BW) {
     const int r0 = k0 + BW;
     const int m = N - r0;
@@ -526,7 +529,7 @@ int sbr_single(hipStream_t s, const Batch& b, int* work) {
     const int nr = m - 1 < BW ? m - 1 : BW;
     const unsigned nwg = (unsigned)((m + PR - 1) / PR);
     if (nwg > (unsigned)PMAX_WG) return set_error(BSE_EUNSUPPORTED, "two-stage reduction: order too large");
-    BSE_LAUNCH(k_sbr_panel_reset, dim3(1), dim3(64), 0, s, work + N + 1, work + N + 2, k0 == 0 ? 1 : 0);
+    if (k0 > 0) BSE_LAUNCH(k_sbr_panel_reset, dim3(1), dim3(64), 0, s, work + N + 1, work + N + 2, 0);
     BSE_LAUNCH(k_sbr_panel, dim3(nwg), dim3(PR), 0, s, b.dev, k0, work + N + 1, work + N + 2);
     BSE_LAUNCH(k_sbr_extract, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, b.dev, k0);
     BSE_TRY(gemm_batched(s, b, 1, GOP_SBR_X, k0));

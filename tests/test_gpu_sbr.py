@@ -96,6 +96,30 @@ def test_two_stage_closed_form(ctx, n):
     assert err <= 1e-10
 
 
+@pytest.mark.parametrize("n", [300, 2048])
+def test_two_stage_after_mixed_solve(ctx, n):
+    """Regression: a mixed-precision solve leaves its refinement state word
+    (the sweep it converged in) in the context's workspace header.  The
+    two-stage products once took it for theirs and skipped every panel past
+    that sweep number, so a two-stage solve after a mixed one on the same
+    context returned wrong eigenvalues.  Same context and order; the mixed
+    solve afterwards must give the same bits as before."""
+    from paper_1501_03830_amd import _lib
+    p = gen_closed_form(n, seed=32)
+    exact = np.asarray(p.exact_lambda)
+    A, B = tt(p.A), tt(p.B)
+    mixed = ctx.solve(A, B, vectors=True, prec=_lib.BSE_PREC_FP32_REFINE, report=True)
+    assert mixed["info"] == 0 and mixed["report"]["refine_sweeps"] >= 1
+    for rep in range(2):
+        r = ctx.solve(A, B, vectors=False, extra_flags=_lib.BSE_TWO_STAGE)
+        assert r["info"] == 0
+        err = float(np.max(np.abs(npc(r["lam"]) - exact))) / float(exact.max())
+        say(f"[two-stage after mixed] n={n} call {rep}: eig {err:.2e}")
+        assert err <= 1e-10
+    mixed2 = ctx.solve(A, B, vectors=True, prec=_lib.BSE_PREC_FP32_REFINE)
+    assert torch.equal(mixed2["lam"], mixed["lam"]) and torch.equal(mixed2["X"], mixed["X"])
+
+
 def test_two_stage_flag_limits(ctx):
     from paper_1501_03830_amd import _lib
     p = gen_bse(20, seed=3)
