@@ -67,7 +67,12 @@ extern "C" {
 #define BSE_PREC_FP32_REFINE 1 /* W stored and reduced in FP32 (FP64 sums and
                                   norms), FP64 tridiagonal solve and
                                   back-transform, then FP64 refinement of the
-                                  eigenpairs against the FP64 W               */
+                                  eigenpairs against the FP64 W.  A call that
+                                  wants eigenvalues only (no
+                                  BSE_WANT_VECTORS) runs the FP64 path: the
+                                  refinement needs the eigenvector basis, and
+                                  the FP64 reduction alone is faster and as
+                                  accurate                                    */
 
 /* flags for bse_solve */
 #define BSE_WANT_VECTORS 1u    /* write X (else only lambda)                   */
@@ -150,6 +155,10 @@ typedef struct bse_report {
                                       the first sweep (the size of the
                                       unrefined eigenvector error)           */
   double refine_correction;        /* ... and of the last sweep              */
+  int graph;                       /* 1 when the chain after the Cholesky ran
+                                      as a replayed HIP graph (its stages are
+                                      then not timed one by one: their sum is
+                                      reported under BSE_STAGE_FORM_W)        */
 } bse_report;
 
 /* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
@@ -174,6 +183,35 @@ int bse_ctx_destroy(bse_ctx* ctx);
  * later calls on this context.  Adds two hipEventRecord per launch.
  * Returns -1 for a NULL context. */
 int bse_ctx_set_timing(bse_ctx* ctx, int enable);
+
+/* Tile table of the tridiagonalisation's skew matrix-vector kernel: row
+ * tiles per strip workgroup as a function of the trailing matrix's 64-row
+ * blocks nblk, in five buckets per storage type: nblk >= t0 -> v0,
+ * >= t1 -> v1, >= t2 -> v2, >= t3 -> v3, else v4.  `table` (host) holds
+ * 2 x 9 ints [t0 t1 t2 t3 v0 v1 v2 v3 v4], the FP64 row then the FP32 row;
+ * thresholds non-increasing and >= 0, tile counts in [1, 16].  The table sets
+ * each problem's summation order (so results depend on it, bit for bit the
+ * same alone and in a batch).  bse_set_tile_table replaces it for the whole
+ * process (validated; the context's device gets the new copy at once, other
+ * devices when a context is created on them); it must not run while solves
+ * are in flight.  The project's autotuner (paper_1501_03830_amd/autotune.py)
+ * measures candidates on the benchmark workloads and writes the table the
+ * Python binding applies.  Return 0, -1/-2 for NULL arguments, -3 for an
+ * invalid table. */
+int bse_get_tile_table(int* table);
+int bse_set_tile_table(bse_ctx* ctx, const int* table);
+
+/* Graph replay (enable != 0, the default) or plain stream launches for later
+ * bse_solve / bse_solve_batched calls on this context.  With replay, the
+ * launches after the Cholesky of an FP64 call (W, reduction, tridiagonal
+ * eigensolve, back-transformation: thousands of kernels for one batch) are
+ * captured into a HIP graph the first time a batch shape (the problems'
+ * orders, the policy, whether vectors are wanted) is solved on this context
+ * and replayed on the context's stream afterwards; results are bit for bit
+ * those of plain launches.  Up to 8 shapes are kept per context.  Calls with
+ * per-launch timing, the mixed policy, BSE_TWO_STAGE or real inputs always
+ * launch plainly.  Returns -1 for a NULL context. */
+int bse_ctx_set_graphs(bse_ctx* ctx, int enable);
 
 /* Device workspace, in bytes, that bse_solve needs for size n (host-only
  * arithmetic, callable without a GPU).  0 for invalid arguments. */

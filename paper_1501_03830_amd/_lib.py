@@ -44,6 +44,7 @@ class BseReport(ctypes.Structure):
         ("refine_sweeps", ctypes.c_int),
         ("refine_first_correction", ctypes.c_double),
         ("refine_correction", ctypes.c_double),
+        ("graph", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -59,6 +60,7 @@ class BseReport(ctypes.Structure):
             "refine_sweeps": self.refine_sweeps,
             "refine_first_correction": self.refine_first_correction,
             "refine_correction": self.refine_correction,
+            "graph": self.graph,
         }
 
 
@@ -108,6 +110,9 @@ SIGNATURES = [
     ("bse_ctx_create", _I, [ctypes.POINTER(_P), _I, _P, ctypes.c_size_t, _P]),
     ("bse_ctx_destroy", _I, [_P]),
     ("bse_ctx_set_timing", _I, [_P, _I]),
+    ("bse_ctx_set_graphs", _I, [_P, _I]),
+    ("bse_get_tile_table", _I, [ctypes.POINTER(_I)]),
+    ("bse_set_tile_table", _I, [_P, ctypes.POINTER(_I)]),
     ("bse_footprint_bytes", ctypes.c_size_t, [_I, _I, _U]),
     ("bse_solve", _I, [_P, _I, _P, _I, _P, _I, _I, _U, _P, _P, _I, _P, _P, _P, ctypes.POINTER(BseReport)]),
     ("bse_solve_real", _I, [_P, _I, _P, _I, _P, _I, _I, _U, _P, _P, _I, _P, _P, _P, ctypes.POINTER(BseReport)]),

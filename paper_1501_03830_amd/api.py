@@ -37,7 +37,7 @@ class Context:
     """A bse_ctx bound to a CUDA/HIP device and the current torch stream."""
 
     def __init__(self, device: int | torch.device = 0, stream: torch.cuda.Stream | None = None,
-                 arena: torch.Tensor | None = None):
+                 arena: torch.Tensor | None = None, apply_tuning: bool = True):
         if not torch.cuda.is_available():
             raise RuntimeError("libbse needs a GPU; none is visible")
         self.lib = _lib.load()
@@ -50,6 +50,25 @@ class Context:
         _lib.check(self.lib.bse_ctx_create(ctypes.byref(h), self.device.index, arena_ptr, arena_bytes,
                                            _P(self.stream.cuda_stream)), "bse_ctx_create")
         self.h = h
+        if apply_tuning:
+            self.apply_tuning()
+
+    def apply_tuning(self, path: str | None = None) -> bool:
+        """Apply the autotuner's tile table (tuning.json next to this file,
+        written by paper_1501_03830_amd.autotune) if there is one."""
+        import json
+        import os
+        path = path or os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
+        if not os.path.exists(path):
+            return False
+        table = json.load(open(path))["table"]
+        arr = (ctypes.c_int * 18)(*(list(table[0]) + list(table[1])))
+        _lib.check(self.lib.bse_set_tile_table(self.h, arr), "bse_set_tile_table")
+        return True
+
+    def set_graphs(self, enable: bool):
+        """Graph replay of the chain after the Cholesky (FP64 calls)."""
+        _lib.check(self.lib.bse_ctx_set_graphs(self.h, 1 if enable else 0), "bse_ctx_set_graphs")
 
     def set_timing(self, enable: bool):
         """Per-launch hipEvent timing of the dominant skew matvec kernel."""

@@ -23,6 +23,16 @@ struct Lane {
   bool events = false;
   bool timing = false;                 // per-launch timing of the skew matvec
   std::vector<hipEvent_t> kev;         // event pool for it
+  // graph replay of the chain after the Cholesky (FP64 batches): captured
+  // once per batch shape on a stream of the lane's own, replayed on `stream`
+  bool graphs = false;
+  hipStream_t cap = nullptr;
+  struct GraphEntry {
+    std::vector<long> key;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::vector<GraphEntry> gcache;      // most recently used last
+  long graph_captures = 0, graph_replays = 0;
 };
 int lane_reserve(Lane* L, int count);   // host mirrors for `count` problems
 void lane_release(Lane* L);             // frees events and host mirrors
@@ -68,6 +78,12 @@ inline int info_code(int i0, int i1, bool vectors) {
 }
 
 bool valid_prec(int prec);
+// The precision policy a call runs with: BSE_PREC_FP32_REFINE refines an
+// eigenvector basis, so a call that wants eigenvalues only runs the FP64
+// path (faster than the FP32 reduction plus the refinement, and as accurate).
+inline int run_prec(int prec, unsigned flags) {
+  return (prec == BSE_PREC_FP32_REFINE && !(flags & BSE_WANT_VECTORS)) ? BSE_PREC_FP64 : prec;
+}
 // Argument checks of bse_solve from argument 2 on (0 or -i with the message
 // for bse_last_error()).
 int check_solve_args(int n, const void* A, int lda, const void* B, int ldb, int prec, unsigned flags,

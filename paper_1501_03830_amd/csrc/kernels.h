@@ -151,6 +151,12 @@ struct KernelTimer {
 // W = U T U^T in place: alpha (N-1), tau (N-1), reflectors below the
 // subdiagonal of P.W.
 int sktrd_batched(hipStream_t s, const Batch& b, KernelTimer* timer);
+// Tile table of the skew matvec (2 x 9 ints: thresholds t0..t3 and tile
+// counts v0..v4, FP64 then FP32): read, replace (host copy, validated), and
+// copy to the current device.
+int tile_table_get(int* tab);
+int tile_table_set(const int* tab);
+int tile_table_upload();
 
 // ---------------------------------------------------------------- sbr.hip
 // Two-stage skew tridiagonalisation of P.W (strict lower triangle, zero

@@ -63,6 +63,7 @@ extern "C" int bse_solve_noalloc(bse_ctx* ctx, int n, const void* A, int lda, co
                                  const void* d_l, void* w) {
   if (!ctx) return set_error(-1, "ctx is NULL");
   BSE_TRY(check_solve_args(n, A, lda, B, ldb, prec, flags, lambda, X, ldx, d_r, w));
+  prec = run_prec(prec, flags);
   const size_t need = header_bytes(1) + problem_bytes(2L * n, prec);
   if (need > (size_t)BSE_NOALLOC_MAX_BYTES)
     return set_error(BSE_ENOMEM, "problem too large for the no-alloc scratch array (bse_noalloc_max_bytes)");

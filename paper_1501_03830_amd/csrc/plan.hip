@@ -94,6 +94,7 @@ extern "C" int bse_plan_check(int count, const int* n, int prec, unsigned flags,
   for (int i = 0; i < count; ++i)
     if (n[i] <= 0) return set_error(-2, "n must be positive");
   const bool vec = (flags & BSE_WANT_VECTORS) != 0;
+  prec = run_prec(prec, flags);
   std::vector<int> order(count);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n[a] > n[b]; });

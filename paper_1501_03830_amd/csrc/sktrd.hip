@@ -110,26 +110,36 @@ __global__ __launch_bounds__(256) void sk_start(const Prob* __restrict__ probs, 
 // Row tiles per strip workgroup of the matvec for a trailing matrix of nblk
 // row blocks.  Long strips amortise each workgroup's prologue (the reflector
 // from the norm partials, the first loads) and its reductions; short ones
-// keep enough workgroups in flight.  The steps were measured inside the
-// n = 8192 reduction and on a batch of 256 problems of order 128 .. 2048 (an
-// isolated sweep without the prologue preferred about half these counts at
-// mid sizes).  The count depends on the problem alone,
+// keep enough workgroups in flight.  The count depends on the problem alone,
 // so a problem's summation order -- and its result -- is the same whether it
 // is solved alone or inside a batch.
+//
+// The counts come from a table of five size buckets per storage type:
+// nblk >= t0 -> v0, >= t1 -> v1, >= t2 -> v2, >= t3 -> v3, else v4 (entries
+// [t0 t1 t2 t3 v0 v1 v2 v3 v4], FP64 first).  The built-in table was measured
+// inside the n = 8192 reduction and on a batch of 256 problems of order
+// 128 .. 2048 (an isolated sweep without the prologue preferred about half
+// these counts at mid sizes); FP32 tiles carry half the bytes, so their
+// strips are longer from 80 row blocks up (16/12 beat the FP64 table by
+// ~8 ms; 16 from 80 and 12 from 48 lost it again).  bse_set_tile_table
+// replaces it (the autotuner's table); host and device copies are kept
+// equal, since the host sizes the grids the device decodes.
+constexpr int TILE_TAB = 9;
+__constant__ int c_tiles[2][TILE_TAB] = {{224, 160, 80, 0, 16, 12, 8, 6, 6}, {160, 80, 0, 0, 16, 12, 6, 6, 6}};
+static int h_tiles[2][TILE_TAB] = {{224, 160, 80, 0, 16, 12, 8, 6, 6}, {160, 80, 0, 0, 16, 12, 6, 6, 6}};
+
 template <class WT>
 __host__ __device__ inline int symv_tiles(int nblk) {
-  // FP32 tiles carry half the bytes: longer strips from 80 row blocks up
-  // (measured over the FP32 reduction: 16/12 beat the FP64 table by ~8 ms;
-  // 16 from 80 and 12 from 48 lost it again)
-  if (sizeof(WT) == 4) {
-    if (nblk >= 160) return 16;
-    if (nblk >= 80) return 12;
-    return 6;
-  }
-  if (nblk >= 224) return 16;
-  if (nblk >= 160) return 12;
-  if (nblk >= 80) return 8;
-  return 6;
+#if defined(__HIP_DEVICE_COMPILE__)
+  const int* t = c_tiles[sizeof(WT) == 4 ? 1 : 0];
+#else
+  const int* t = h_tiles[sizeof(WT) == 4 ? 1 : 0];
+#endif
+  if (nblk >= t[0]) return t[4];
+  if (nblk >= t[1]) return t[5];
+  if (nblk >= t[2]) return t[6];
+  if (nblk >= t[3]) return t[7];
+  return t[8];
 }
 
 // One element of a matvec tile (NT: with the non-temporal hint), kept in
@@ -785,6 +795,32 @@ static int sktrd_run(hipStream_t s, const Batch& b, KernelTimer* timer) {
     }
     BSE_TRY(gemm_batched(s, b, nstart, GOP_SKTRD_R2K, k0));
   }
+  return 0;
+}
+
+int tile_table_get(int* tab) {
+  for (int p = 0; p < 2; ++p)
+    for (int k = 0; k < TILE_TAB; ++k) tab[p * TILE_TAB + k] = h_tiles[p][k];
+  return 0;
+}
+
+int tile_table_set(const int* tab) {
+  for (int p = 0; p < 2; ++p) {
+    const int* t = tab + p * TILE_TAB;
+    for (int k = 0; k < 3; ++k)
+      if (t[k] < t[k + 1]) return set_error(-3, "tile table: thresholds must not increase");
+    if (t[3] < 0) return set_error(-3, "tile table: negative threshold");
+    for (int k = 4; k < TILE_TAB; ++k)
+      if (t[k] < 1 || t[k] > TMAX) return set_error(-3, "tile table: tile counts must be in [1, 16]");
+  }
+  for (int p = 0; p < 2; ++p)
+    for (int k = 0; k < TILE_TAB; ++k) h_tiles[p][k] = tab[p * TILE_TAB + k];
+  return 0;
+}
+
+// the host table into the current device's constant copy
+int tile_table_upload() {
+  BSE_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_tiles), h_tiles, sizeof(h_tiles), 0, hipMemcpyHostToDevice));
   return 0;
 }
 

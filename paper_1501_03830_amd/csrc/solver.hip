@@ -205,6 +205,10 @@ int lane_reserve(Lane* L, int count) {
 }
 
 void lane_release(Lane* L) {
+  for (auto& g : L->gcache) (void)hipGraphExecDestroy(g.exec);
+  L->gcache.clear();
+  if (L->cap) (void)hipStreamDestroy(L->cap);
+  L->cap = nullptr;
   if (L->events)
     for (int i = 0; i <= BSE_NUM_STAGES; ++i) (void)hipEventDestroy(L->ev[i]);
   L->events = false;
@@ -294,6 +298,109 @@ static const int kStageOrder[BSE_NUM_STAGES] = {
     BSE_STAGE_BUILD_M, BSE_STAGE_POTRF,   BSE_STAGE_FORM_W,  BSE_STAGE_SKTRD,   BSE_STAGE_BISECT, BSE_STAGE_INVIT,
     BSE_STAGE_REORTH,  BSE_STAGE_APPLY_U, BSE_STAGE_REFINE,  BSE_STAGE_APPLY_L, BSE_STAGE_FINISH};
 
+// The chain after the Cholesky of M: W, the reduction, the tridiagonal
+// eigensolve and the back-transformation, for the live problems of b.
+static int chain_tail(hipStream_t s, Lane* L, const Setup& S, const Batch& b, bool vectors, bool mixed, bool two,
+                      bool timed, int& ev, KernelTimer* ktimer, RefineStats* rstats) {
+  // the mixed path keeps the full FP64 W for the refinement and reduces an
+  // FP32 copy of its lower triangle
+  BSE_TRY(form_W_batched(s, b, mixed));
+  // the two-stage reduction keeps W as its strict lower triangle over a zero
+  // upper triangle
+  if (two) BSE_TRY(zero_upper(s, L->hprobs[0].N, L->hprobs[0].W, L->hprobs[0].ld));
+  if (mixed) BSE_TRY(to_f32_batched(s, b));
+  BSE_TRY(mark(L, timed, ev++));
+  if (two) BSE_TRY(sbr_single(s, b, reinterpret_cast<int*>(L->hprobs[0].Ycol)));
+  else BSE_TRY(sktrd_batched(s, b, ktimer));
+  BSE_TRY(mark(L, timed, ev++));
+  BSE_TRY(bisect_batched(s, b));
+  BSE_TRY(mark(L, timed, ev++));
+  // the refinement needs the eigenvector basis even when only eigenvalues
+  // are wanted
+  if (vectors || mixed) {
+    BSE_TRY(invit_batched(s, b));
+    BSE_TRY(mark(L, timed, ev++));
+    BSE_TRY(reorth_batched(s, b, S.dreorth, L->hstate, S.count));
+    BSE_TRY(mark(L, timed, ev++));
+    BSE_TRY(apply_UD_batched(s, b));
+    BSE_TRY(mark(L, timed, ev++));
+    if (mixed) {
+      RefineIO io;
+      io.dstate = S.dstate;
+      io.dout = S.dref;
+      io.hstate = L->hstate;
+      io.hout = L->hrefout;
+      io.nslots = S.count;
+      BSE_TRY(refine_batched(s, b, io, rstats));
+    }
+    BSE_TRY(mark(L, timed, ev++));
+    if (vectors) {
+      BSE_TRY(gemm_batched(s, b, b.count, GOP_APPLY_L, 0));
+      BSE_TRY(mark(L, timed, ev++));
+      BSE_TRY(finish_batched(s, b));
+      if (b.count == 1 && (b.host[0].flags & FLAG_REAL_IN)) BSE_TRY(real_output_single(s, b));
+    } else {
+      BSE_TRY(mark(L, timed, ev++));
+    }
+  } else {
+    for (int i = 0; i < 5; ++i) BSE_TRY(mark(L, timed, ev++));
+  }
+  return 0;
+}
+
+// The chain tail as a graph: looked up by the batch shape (the launches'
+// grids and arguments depend only on the live problems' orders, the policy,
+// whether vectors are wanted and the address of the descriptor header; the
+// caller's buffers and the workspace addresses are read by the kernels from
+// the descriptors, which are uploaded per call), captured on the lane's
+// own stream at the first call of a shape and replayed on the lane's stream.
+static int chain_tail_graph(Lane* L, const Setup& S, const Batch& b, bool vectors) {
+  std::vector<long> key;
+  key.reserve(6 + b.count);
+  key.push_back(b.count);
+  key.push_back(b.host[0].prec);
+  key.push_back(vectors ? 1 : 0);
+  key.push_back((long)reinterpret_cast<intptr_t>(S.dprobs));
+  key.push_back((long)reinterpret_cast<intptr_t>(S.dwgpre));
+  for (int i = 0; i < b.count; ++i) key.push_back(b.host[i].N);
+  size_t hit = L->gcache.size();
+  for (size_t i = 0; i < L->gcache.size(); ++i)
+    if (L->gcache[i].key == key) hit = i;
+  if (hit == L->gcache.size()) {
+    if (!L->cap) BSE_HIP(hipStreamCreateWithFlags(&L->cap, hipStreamNonBlocking));
+    BSE_HIP(hipStreamBeginCapture(L->cap, hipStreamCaptureModeThreadLocal));
+    int ev = 0;
+    RefineStats rs;
+    const int rc = chain_tail(L->cap, L, S, b, vectors, false, false, false, ev, nullptr, &rs);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(L->cap, &graph);
+    if (rc != 0) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return set_hip_error(e, "hipStreamEndCapture", __FILE__, __LINE__);
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return set_hip_error(ei, "hipGraphInstantiate", __FILE__, __LINE__);
+    constexpr size_t kMaxGraphs = 8;
+    if (L->gcache.size() >= kMaxGraphs) {
+      (void)hipGraphExecDestroy(L->gcache.front().exec);
+      L->gcache.erase(L->gcache.begin());
+    }
+    Lane::GraphEntry g;
+    g.key = std::move(key);
+    g.exec = exec;
+    L->gcache.push_back(std::move(g));
+    hit = L->gcache.size() - 1;
+    ++L->graph_captures;
+  } else {
+    ++L->graph_replays;
+  }
+  BSE_HIP(hipGraphLaunch(L->gcache[hit].exec, L->stream));
+  return 0;
+}
+
 int run_chain(Lane* L, const Setup& S, int count, bool vectors, bse_report* rep) {
   hipStream_t s = L->stream;
   const bool timed = rep != nullptr;
@@ -327,16 +434,8 @@ int run_chain(Lane* L, const Setup& S, int count, bool vectors, bse_report* rep)
     b.count = live;
     if (live > 0) BSE_TRY(upload(L, S, live));
   }
-  // the mixed path keeps the full FP64 W for the refinement and reduces an
-  // FP32 copy of its lower triangle; the two-stage reduction updates the
-  // full skew matrix
   const bool two = b.count == 1 && (L->hprobs[0].flags & BSE_TWO_STAGE) != 0;
-  BSE_TRY(form_W_batched(s, b, mixed));
-  // the two-stage reduction keeps W as its strict lower triangle over a zero
-  // upper triangle
-  if (two) BSE_TRY(zero_upper(s, L->hprobs[0].N, L->hprobs[0].W, L->hprobs[0].ld));
-  if (mixed) BSE_TRY(to_f32_batched(s, b));
-  BSE_TRY(mark(L, timed, ev++));
+  const bool real_in = b.count == 1 && (L->hprobs[0].flags & FLAG_REAL_IN) != 0;
   KernelTimer ktimer;
   if (L->timing && b.count > 0) {
     const long N0 = b.maxN();
@@ -349,41 +448,15 @@ int run_chain(Lane* L, const Setup& S, int count, bool vectors, bse_report* rep)
     ktimer.ev = L->kev.data();
     ktimer.cap = (int)L->kev.size();
   }
-  if (two) BSE_TRY(sbr_single(s, b, reinterpret_cast<int*>(L->hprobs[0].Ycol)));
-  else BSE_TRY(sktrd_batched(s, b, L->timing ? &ktimer : nullptr));
-  BSE_TRY(mark(L, timed, ev++));
-  BSE_TRY(bisect_batched(s, b));
-  BSE_TRY(mark(L, timed, ev++));
   RefineStats rstats;
-  // the refinement needs the eigenvector basis even when only eigenvalues
-  // are wanted
-  if (vectors || mixed) {
-    BSE_TRY(invit_batched(s, b));
-    BSE_TRY(mark(L, timed, ev++));
-    BSE_TRY(reorth_batched(s, b, S.dreorth, L->hstate, S.count));
-    BSE_TRY(mark(L, timed, ev++));
-    BSE_TRY(apply_UD_batched(s, b));
-    BSE_TRY(mark(L, timed, ev++));
-    if (mixed) {
-      RefineIO io;
-      io.dstate = S.dstate;
-      io.dout = S.dref;
-      io.hstate = L->hstate;
-      io.hout = L->hrefout;
-      io.nslots = S.count;
-      BSE_TRY(refine_batched(s, b, io, &rstats));
-    }
-    BSE_TRY(mark(L, timed, ev++));
-    if (vectors) {
-      BSE_TRY(gemm_batched(s, b, b.count, GOP_APPLY_L, 0));
-      BSE_TRY(mark(L, timed, ev++));
-      BSE_TRY(finish_batched(s, b));
-      if (b.count == 1 && (b.host[0].flags & FLAG_REAL_IN)) BSE_TRY(real_output_single(s, b));
-    } else {
-      BSE_TRY(mark(L, timed, ev++));
-    }
+  // graph replay: FP64 chains without host decisions after the Cholesky
+  const bool graph = L->graphs && !L->timing && !mixed && !two && !real_in && b.count > 0;
+  if (graph) {
+    // the tail's stage events are not recorded: its time goes to form_W
+    BSE_TRY(chain_tail_graph(L, S, b, vectors));
+    for (; ev < BSE_NUM_STAGES; ++ev) BSE_TRY(mark(L, timed, ev));
   } else {
-    for (int i = 0; i < 5; ++i) BSE_TRY(mark(L, timed, ev++));
+    BSE_TRY(chain_tail(s, L, S, b, vectors, mixed, two, timed, ev, L->timing ? &ktimer : nullptr, &rstats));
   }
   BSE_TRY(mark(L, timed, ev++));
   BSE_TRY(read_infos(L, S, count));
@@ -401,6 +474,7 @@ int run_chain(Lane* L, const Setup& S, int count, bool vectors, bse_report* rep)
     rep->refine_sweeps = rstats.sweeps;
     rep->refine_first_correction = rstats.first_correction;
     rep->refine_correction = rstats.last_correction;
+    rep->graph = graph ? 1 : 0;
     if (L->timing) {
       double tot = 0.0;
       for (int i = 0; i + 1 < ktimer.used; i += 2) {
@@ -507,11 +581,14 @@ int bse_ctx_create(bse_ctx** ctx, int device, void* arena, size_t arena_bytes, v
   BSE_HIP(hipSetDevice(device));
   // the allocation-free entry point's workspace address on this device
   BSE_TRY(noalloc_init_device(device));
+  // the matvec tile table in force, also on this device
+  BSE_TRY(tile_table_upload());
   bse_ctx* c = new bse_ctx();
   c->device = device;
   c->arena = arena;
   c->arena_bytes = arena_bytes;
   c->lane.stream = static_cast<hipStream_t>(stream);
+  c->lane.graphs = true;
   *ctx = c;
   return 0;
 }
@@ -527,6 +604,30 @@ int bse_ctx_destroy(bse_ctx* ctx) {
   return 0;
 }
 
+int bse_get_tile_table(int* table) {
+  if (!table) return set_error(-1, "table is NULL");
+  return tile_table_get(table);
+}
+
+int bse_set_tile_table(bse_ctx* ctx, const int* table) {
+  if (!ctx) return set_error(-1, "ctx is NULL");
+  if (!table) return set_error(-2, "table is NULL");
+  BSE_TRY(prologue(ctx));
+  BSE_HIP(hipStreamSynchronize(ctx->lane.stream));
+  BSE_TRY(tile_table_set(table));
+  BSE_TRY(tile_table_upload());
+  // captured graphs hold grids sized with the old table
+  for (auto& g : ctx->lane.gcache) (void)hipGraphExecDestroy(g.exec);
+  ctx->lane.gcache.clear();
+  return 0;
+}
+
+int bse_ctx_set_graphs(bse_ctx* ctx, int enable) {
+  if (!ctx) return set_error(-1, "ctx is NULL");
+  ctx->lane.graphs = enable != 0;
+  return 0;
+}
+
 int bse_ctx_set_timing(bse_ctx* ctx, int enable) {
   if (!ctx) return set_error(-1, "ctx is NULL");
   ctx->lane.timing = enable != 0;
@@ -534,18 +635,16 @@ int bse_ctx_set_timing(bse_ctx* ctx, int enable) {
 }
 
 size_t bse_footprint_bytes(int n, int prec, unsigned flags) {
-  (void)flags;
   if (n <= 0 || !valid_prec(prec)) return 0;
-  return header_bytes(1) + make_plan(2L * n, prec).total;
+  return header_bytes(1) + make_plan(2L * n, run_prec(prec, flags)).total;
 }
 
 size_t bse_footprint_batched_bytes(int count, const int* n, int prec, unsigned flags) {
-  (void)flags;
   if (count <= 0 || !n || !valid_prec(prec)) return 0;
   size_t total = header_bytes(count);
   for (int i = 0; i < count; ++i) {
     if (n[i] <= 0) return 0;
-    total += make_plan(2L * n[i], prec).total;
+    total += make_plan(2L * n[i], run_prec(prec, flags)).total;
   }
   return total;
 }
@@ -556,6 +655,7 @@ int bse_solve(bse_ctx* ctx, int n, const void* A, int lda, const void* B, int ld
   if (!ctx) return set_error(-1, "ctx is NULL");
   BSE_TRY(check_solve_args(n, A, lda, B, ldb, prec, flags, lambda, X, ldx, d_r, w));
   BSE_TRY(prologue(ctx));
+  prec = run_prec(prec, flags);
   char* base = nullptr;
   BSE_TRY(get_workspace(ctx, header_bytes(1) + problem_bytes(2L * n, prec), &base));
   return solve_single_in(&ctx->lane, base, n, A, lda, B, ldb, prec, flags, lambda, X, ldx, d_r, d_l, w, rep);
@@ -569,6 +669,7 @@ int bse_solve_tda(bse_ctx* ctx, int n, const void* A, int lda, int prec, unsigne
   if (rc <= -7) rc += 2;
   if (rc != 0) return rc;
   BSE_TRY(prologue(ctx));
+  prec = run_prec(prec, flags);
   char* base = nullptr;
   BSE_TRY(get_workspace(ctx, header_bytes(1) + problem_bytes(2L * n, prec), &base));
   return solve_single_in(&ctx->lane, base, n, A, lda, nullptr, n, prec, flags, lambda, X, ldx, d_r, d_l, w, rep);
@@ -580,6 +681,7 @@ int bse_solve_real(bse_ctx* ctx, int n, const double* A, int lda, const double* 
   if (!ctx) return set_error(-1, "ctx is NULL");
   BSE_TRY(check_solve_args(n, A, lda, B, ldb, prec, flags, lambda, X, ldx, d_r, w));
   BSE_TRY(prologue(ctx));
+  prec = run_prec(prec, flags);
   char* base = nullptr;
   BSE_TRY(get_workspace(ctx, header_bytes(1) + problem_bytes(2L * n, prec), &base));
   Lane* L = &ctx->lane;
@@ -649,6 +751,7 @@ int bse_solve_batched(bse_ctx* ctx, int count, const int* n, const void* const* 
     if (wts && !w[i]) return set_errorf(-14, "w[%d] is NULL", i);
   }
   BSE_TRY(prologue(ctx));
+  prec = run_prec(prec, flags);
   // descriptors sorted by decreasing n (stable)
   std::vector<int> order(count);
   std::iota(order.begin(), order.end(), 0);
@@ -719,7 +822,9 @@ int bse_submit(bse_ctx* ctx, const bse_request* req, uint64_t* ticket) {
   if (!ticket) return set_error(-3, "ticket is NULL");
   BSE_TRY(prologue(ctx));
   if (!ctx->server) BSE_TRY(server_create(ctx->device, 0, 0, 0, &ctx->server));
-  return server_submit(ctx->server, req, ctx->lane.stream, ticket);
+  bse_request r = *req;
+  r.prec = run_prec(r.prec, r.flags);
+  return server_submit(ctx->server, &r, ctx->lane.stream, ticket);
 }
 
 int bse_poll(bse_ctx* ctx, uint64_t ticket, int* state, int* info) {

@@ -80,3 +80,15 @@ def test_package_import_does_not_load_library():
     import sys
     mod = importlib.reload(sys.modules["paper_1501_03830_amd"])
     assert hasattr(mod, "Context")
+
+
+def test_tile_table_host_validation(lib):
+    """The tile table accessors are host-only; invalid tables are rejected
+    before any device call (a NULL context is argument 1)."""
+    import ctypes
+    t = (ctypes.c_int * 18)()
+    assert lib.bse_get_tile_table(t) == 0
+    row64, row32 = list(t[:9]), list(t[9:])
+    assert row64[:4] == sorted(row64[:4], reverse=True)
+    assert all(1 <= v <= 16 for v in row64[4:] + row32[4:])
+    assert lib.bse_set_tile_table(None, t) == -1

@@ -94,11 +94,19 @@ def test_mixed_batched_equals_single(ctx):
 
 
 def test_mixed_eigenvalues_only(ctx):
+    """An eigenvalue-only call with the mixed policy runs the FP64 path (the
+    refinement needs the eigenvector basis): bit for bit the FP64 call's
+    eigenvalues, and within the target of the refined ones."""
+    from paper_1501_03830_amd import _lib
     p = gen_bse(150, s_a=0.3, seed=9)
-    a = ctx.solve(tt(p.A), tt(p.B), vectors=False, prec=MIXED())
+    a = ctx.solve(tt(p.A), tt(p.B), vectors=False, prec=MIXED(), report=True)
+    f = ctx.solve(tt(p.A), tt(p.B), vectors=False, prec=_lib.BSE_PREC_FP64)
     b = ctx.solve(tt(p.A), tt(p.B), vectors=True, prec=MIXED())
     assert a["X"] is None
-    assert torch.equal(a["lam"], b["lam"])
+    assert a["report"]["prec"] == _lib.BSE_PREC_FP64 and a["report"]["refine_sweeps"] == 0
+    assert torch.equal(a["lam"], f["lam"])
+    lmax = float(b["lam"].max())
+    assert float((a["lam"] - b["lam"]).abs().max()) <= 1e-10 * lmax
 
 
 def test_mixed_config2_n2048_against_golden(ctx):

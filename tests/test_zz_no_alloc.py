@@ -48,10 +48,13 @@ def test_noalloc_equals_solve_two_calls(ctx, prec_name):
         assert torch.equal(a["lam"], b["lam"])
         assert torch.equal(a["X"], b["X"])
         assert torch.equal(a["w"], b["w"])
-        # eigenvalue-only call on the same array
+        # eigenvalue-only call on the same array (the mixed policy runs the
+        # FP64 path for it, as bse_solve does)
         c = ctx.solve_noalloc(tt(p.A), tt(p.B), vectors=False, prec=prec)
         torch.cuda.synchronize()
-        assert c["info"] == 0 and torch.equal(c["lam"], b["lam"])
+        e = ctx.solve(tt(p.A), tt(p.B), vectors=False, prec=prec)
+        torch.cuda.synchronize()
+        assert c["info"] == 0 and torch.equal(c["lam"], e["lam"])
 
 
 def test_noalloc_rejects_oversized(ctx):
