@@ -186,17 +186,35 @@ def batched_bench(ctx, steps: int, warmup: int, count: int = 256, lo: int = 64, 
         print(f"# batched step {i}: {rep['total_ms']:.1f} ms", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
-    return {
+    out = {
         "workload": f"{count} independent problems, n log-uniform in [{lo},{hi}] (size seed {size_seed}, "
                     f"problem i seed 1000+i), {'FP32+refine' if mixed else 'FP64'}, eigenvalues + eigenvectors + weights, "
                     f"one bse_solve_batched call",
         "solves_per_s": round(count / dt, 2),
         "s_per_batch": round(dt, 4),
         "device_ms_per_batch": round(float(np.mean([r["total_ms"] for r in reps])), 2),
-        "stage_ms": {k: round(float(np.mean([r["stage_ms"][k] for r in reps])), 2) for k in reps[0]["stage_ms"]},
+        "graph_replay": bool(reps[0]["graph"]),
         "sum_n3": float(sum(k ** 3 for k in ns)),
         "n_max": max(ns), "n_min": min(ns),
     }
+    if reps[0]["graph"]:
+        # a replayed graph records no stage events: the stage split (and the
+        # rate without replay) comes from as many steps with plain launches
+        ctx.set_graphs(False)
+        preps = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            info, rep = ctx.solve_batched_raw(ns, Acs, Bcs, lams, Xs, ds, ws, report=True, prec=prec)
+            assert all(v == 0 for v in info)
+            preps.append(rep)
+        torch.cuda.synchronize()
+        dtp = (time.perf_counter() - t0) / steps
+        ctx.set_graphs(True)
+        out["solves_per_s_plain_launches"] = round(count / dtp, 2)
+        reps = preps
+    out["stage_ms"] = {k: round(float(np.mean([r["stage_ms"][k] for r in reps])), 2) for k in reps[0]["stage_ms"]}
+    return out
 
 
 def serving_bench(big_inputs, count: int = 200, lo: int = 128, hi: int = 2048, big: int = 8192,
@@ -287,6 +305,121 @@ def serving_bench(big_inputs, count: int = 200, lo: int = 128, hi: int = 2048, b
     }
 
 
+def serving_full(count: int = 2000, lo: int = 128, hi: int = 4096, big: int = 16384, big_frac: float = 0.02,
+                 seed: int = 5, load: float = 0.7, calib: int = 200, pool_gib: int = 160, slots: int = 4,
+                 max_batch: int = 64, max_span_s: float = 780.0):
+    """The serving workload as stated: a Poisson stream of `count` requests,
+    n log-uniform in [lo, hi] with probability 1 - big_frac, else n = big
+    (stream seed `seed`).  Requests of order <= hi are drawn on the device at
+    submission (bse_inputs.device, request i from seed 100000 + i); the n = big
+    requests solve one closed-form problem (exact eigenvalues known).  The
+    saturation rate is measured closed-loop on the first `calib` requests of
+    the stream; the timed run replays all `count` arrivals at `load` x that
+    rate (open loop; the rate is raised if needed so that the arrivals span
+    at most max_span_s).  Every result is checked: the n = big eigenvalues
+    against the closed form, every other request by the residual
+    ||H x_j - lambda_j x_j|| / (lambda_max ||x_j||) of all its eigenpairs
+    (computed on the device after completion, outside the latency)."""
+    import torch
+    from bse_inputs import gen_closed_form, serving_stream
+    from bse_inputs.device import gen_bse_device
+    from paper_1501_03830_amd.api import Context, to_colmajor, from_colmajor
+
+    dev = torch.device("cuda", 0)
+    _, ns = serving_stream(count, 1.0, lo, hi, big, big_frac, seed)
+    ns = [int(k) for k in ns]
+    t0 = time.time()
+    pb = gen_closed_form(big, seed=31)
+    bigA = to_colmajor(torch.from_numpy(pb.A), dev)
+    bigB = to_colmajor(torch.from_numpy(pb.B), dev)
+    bigd = torch.from_numpy(pb.d).to(dev)
+    exact = torch.from_numpy(np.asarray(pb.exact_lambda)).to(dev)
+    del pb
+    print(f"# serving (full): {count} requests, {sum(1 for k in ns if k == big)} at n={big}; closed-form "
+          f"problem ready in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+
+    def apply_H(Ac, Bc, X):
+        n = Ac.shape[0]
+        A = Ac.transpose(0, 1)
+        B = Bc.transpose(0, 1)
+        x1, x2 = X[:n], X[n:]
+        return torch.cat([A @ x1 + B @ x2, -(B.conj() @ x1 + A.conj() @ x2)], 0)
+
+    def run(arrivals, idx, check):
+        ctx = Context(0)
+        ctx.serve_config(pool_gib << 30, slots, max_batch)
+        pending, lat, worst = {}, [], {"resid": 0.0, "big_eig": 0.0}
+        nxt, done = 0, 0
+        t_start = time.perf_counter()
+        while nxt < len(idx) or pending:
+            now = time.perf_counter() - t_start
+            while nxt < len(idx) and arrivals[nxt] <= now:
+                i = idx[nxt]
+                k = ns[i]
+                if k == big:
+                    Ac, Bc, d = bigA, bigB, bigd
+                else:
+                    Ac, Bc, d = gen_bse_device(k, 100000 + i, dev)
+                lam = torch.empty(k, dtype=torch.float64, device=dev)
+                X = torch.empty((k, 2 * k), dtype=torch.complex128, device=dev)
+                w = torch.empty(k, dtype=torch.complex128, device=dev)
+                t = ctx.submit_raw(k, Ac, Bc, lam, X, d, None, w)
+                pending[t] = (i, k, Ac, Bc, lam, X)
+                nxt += 1
+            for t in list(pending):
+                st, info = ctx.poll(t)
+                if st < 2:
+                    continue
+                i, k, Ac, Bc, lam, X = pending.pop(t)
+                assert info == 0, (i, k, info)
+                a, _, c = ctx.ticket_times(t)
+                lat.append((c - a) * 1e-3)
+                if check:
+                    if k == big:
+                        e = float((lam - exact).abs().max() / exact.max())
+                        worst["big_eig"] = max(worst["big_eig"], e)
+                    else:
+                        Xl = from_colmajor(X)
+                        R = apply_H(Ac, Bc, Xl) - Xl * lam[None, :]
+                        r = (torch.linalg.vector_norm(R, dim=0) /
+                             (lam.max() * torch.linalg.vector_norm(Xl, dim=0))).max()
+                        worst["resid"] = max(worst["resid"], float(r))
+                ctx.release(t)
+                done += 1
+                if done % 100 == 0:
+                    print(f"# serving: {done}/{len(idx)} done, {time.perf_counter() - t_start:.0f}s",
+                          file=sys.stderr, flush=True)
+            time.sleep(0.0005)
+        span = time.perf_counter() - t_start
+        stats = ctx.serve_stats()
+        ctx.close()
+        return span, np.array(lat), stats, worst
+
+    cidx = list(range(min(calib, count)))
+    span1, _, _, _ = run([0.0] * len(cidx), cidx, False)
+    sat = len(cidx) / span1
+    qps = max(load * sat, count / max_span_s)
+    arrivals, _ = serving_stream(count, qps, lo, hi, big, big_frac, seed)
+    arrivals = [float(x) - float(arrivals[0]) for x in arrivals]
+    print(f"# serving (full): calibration {sat:.3f} solves/s on {len(cidx)} requests; open loop at "
+          f"{qps:.3f} req/s", file=sys.stderr, flush=True)
+    span2, lat, st2, worst = run(arrivals, list(range(count)), True)
+    return {
+        "workload": f"{count} requests, Poisson arrivals, n log-uniform in [{lo},{hi}] w.p. {1 - big_frac:.2f} else "
+                    f"n={big} (stream seed {seed}; n<= {hi} drawn on the device from seed 100000+i, n={big} the "
+                    f"closed-form problem), FP64, eigenvalues + eigenvectors + weights",
+        "calibration": {"requests": len(cidx), "solves_per_s": round(sat, 3)},
+        "load": load, "qps": round(qps, 3), "slots": slots, "max_batch": max_batch, "pool_gib": pool_gib,
+        "solves_per_s": round(count / span2, 3), "makespan_s": round(span2, 1),
+        "p50_ms": round(float(np.percentile(lat, 50)), 1), "p99_ms": round(float(np.percentile(lat, 99)), 1),
+        "max_ms": round(float(lat.max()), 1),
+        "max_relative_residual_small": worst["resid"],
+        "max_rel_eig_err_big_closed_form": worst["big_eig"],
+        "batches": st2["batches"], "max_inflight": st2["max_inflight"],
+        "peak_pool_gib": round(st2["peak_used_bytes"] / 2 ** 30, 2),
+    }
+
+
 def calibrate_copy(gib: int = 1, reps: int = 5):
     """A plain device copy of a known size (gib GiB read + gib GiB written per
     launch), for scaling the HBM byte counters of rocprofv3 --pmc
@@ -372,12 +505,14 @@ def closed_form_check(ctx, n: int, seed: int = 30):
     del p
     lmax = float(exact.max())
     out = {"workload": f"closed-form generator n={n} (seed {seed}), eigenvalues only", "lambda_max": lmax}
-    for key, prec in (("fp64", _lib.BSE_PREC_FP64), ("fp32_refine", _lib.BSE_PREC_FP32_REFINE)):
+    # eigenvalue-only calls: the mixed policy runs the FP64 path for them;
+    # the two-stage reduction is the third line
+    for key, prec, fl in (("fp64", _lib.BSE_PREC_FP64, 0), ("fp64_two_stage", _lib.BSE_PREC_FP64, _lib.BSE_TWO_STAGE)):
         lam = torch.empty(n, dtype=torch.float64, device=dev)
-        info, rep = ctx.solve_raw(n, Ac, Bc, lam, None, None, None, None, report=True, prec=prec)
+        info, rep = ctx.solve_raw(n, Ac, Bc, lam, None, None, None, None, report=True, prec=prec, extra_flags=fl)
         assert info == 0, info
         out[key] = {"max_rel_eig_err": float((lam - exact).abs().max()) / lmax,
-                    "device_ms": round(rep["total_ms"], 2)}
+                    "device_ms": round(rep["total_ms"], 2), "sktrd_ms": round(rep["stage_ms"]["sktrd"], 2)}
     print(f"# closed form n={n}: {out} ({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
     return out
 
@@ -408,6 +543,12 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision solve")
     ap.add_argument("--no-closed-form", action="store_true", help="skip the exact-eigenvalue check")
     ap.add_argument("--serving-count", type=int, default=200)
+    ap.add_argument("--serving-full", action="store_true",
+                    help="only the serving workload as stated (2000 requests, n in [128,4096] + 2%% at 16384)")
+    ap.add_argument("--sf-count", type=int, default=2000)
+    ap.add_argument("--sf-hi", type=int, default=4096)
+    ap.add_argument("--sf-big", type=int, default=16384)
+    ap.add_argument("--sf-calib", type=int, default=200)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     a = ap.parse_args()
@@ -419,6 +560,10 @@ def main():
 
     if a.calibrate_copy:
         calibrate_copy()
+        return
+    if a.serving_full:
+        print(json.dumps({"serving_full": serving_full(count=a.sf_count, hi=a.sf_hi, big=a.sf_big,
+                                                       calib=a.sf_calib)}), flush=True)
         return
 
     import torch
@@ -465,8 +610,21 @@ def main():
     elapsed = time.perf_counter() - t0
     s_per_solve = elapsed / a.steps
 
-    # stage roofline (mean over the timed steps)
-    stages = stage_roofline({k: float(np.mean([r["stage_ms"][k] for r in reps])) for k in reps[0]["stage_ms"]},
+    # stage roofline: a replayed graph records no stage events, so the split
+    # comes from steps with plain launches (mean over them)
+    sreps = reps
+    plain_ms = None
+    if reps[0]["graph"]:
+        ctx.set_graphs(False)
+        sreps = []
+        for i in range(max(1, min(2, a.steps))):
+            info, rep = ctx.solve_raw(n, Ac, Bc, lam, Xbuf, drb, None, w, report=True)
+            assert info == 0
+            sreps.append(rep)
+            print(f"# plain-launch step {i}: {rep['total_ms']:.1f} ms", file=sys.stderr, flush=True)
+        ctx.set_graphs(True)
+        plain_ms = float(np.mean([r["total_ms"] for r in sreps]))
+    stages = stage_roofline({k: float(np.mean([r["stage_ms"][k] for r in sreps])) for k in sreps[0]["stage_ms"]},
                             stage_work(n))
 
     roofline = None
@@ -514,6 +672,8 @@ def main():
                    "n": n, "s_a": a.s_a, "s_b": a.s_b, "seed": a.seed, "precision": "fp64"},
         "solves_per_s": round(1.0 / s_per_solve, 4),
         "device_ms_per_step": round(float(np.mean([r["total_ms"] for r in reps])), 2),
+        "graph_replay": bool(reps[0]["graph"]),
+        "device_ms_plain_launches": None if plain_ms is None else round(plain_ms, 2),
         "stages": stages,
         "roofline": roofline,
         "cpu_baseline": None,
