@@ -32,3 +32,4 @@ from .real_bse import solve_real  # noqa: F401
 from . import sbr  # noqa: F401
 from . import spectra  # noqa: F401
 from . import metrics  # noqa: F401
+from . import mrrr  # noqa: F401
