@@ -82,6 +82,15 @@ extern "C" {
                                   bulge chasing; Section 3.3's successive band
                                   reduction); eigenvalues only, FP64, single
                                   problems (bse_solve, bse_solve_tda)          */
+#define BSE_EIGVEC_TWISTED 8u  /* eigenvectors of the tridiagonal T_s by
+                                  twisted factorisations (the per-vector step
+                                  of MRRR, Section 3.3) instead of inverse
+                                  iteration; eigenvalues closer than 1000 eps
+                                  |lambda| to a neighbour still use inverse
+                                  iteration, and clusters are orthogonalised
+                                  as before (the representation tree of MRRR
+                                  is not built).  FP64 and mixed; any entry
+                                  point that takes flags                     */
 
 /* stage indices of bse_report.stage_ms */
 #define BSE_STAGE_BUILD_M 0    /* Algorithm 1 step 1                           */
@@ -491,6 +500,17 @@ int bse_sktrd2(bse_ctx* ctx, int N, double* W, int ldw, double* alpha);
  * non-NULL, orthonormal eigenvectors V (N x n, ldv >= N) by inverse iteration
  * reorthogonalised inside clusters.  alpha: N-1 doubles.  N even, >= 2. */
 int bse_tridiag_eig(bse_ctx* ctx, int N, const double* alpha, double* lambda, double* V, int ldv);
+
+/* bse_tridiag_eig with flags: BSE_EIGVEC_TWISTED computes the eigenvectors
+ * by twisted factorisations (the per-vector step of MRRR, which Section 3.3
+ * names as the alternative to inverse iteration): for eigenvalue lambda,
+ * the top-down and bottom-up LDL^T factorisations of T_s - lambda I, the
+ * twist index r minimising |gamma_r|, and the vector with z_r = 1 from the
+ * two bidiagonal factors.  Eigenvalues within 1000 eps |lambda| of a
+ * neighbour use inverse iteration; clusters are orthogonalised as in
+ * bse_tridiag_eig.  Other flag bits: -7. */
+int bse_tridiag_eig_flags(bse_ctx* ctx, int N, const double* alpha, double* lambda, double* V, int ldv,
+                          unsigned flags);
 
 #ifdef __cplusplus
 }

@@ -23,7 +23,8 @@ eigenvectors of symmetric tridiagonal matrices", 2004), for T_s itself:
 
 Pivots smaller than pivmin in modulus are replaced by -pivmin, as in the
 Sturm count of the bisection.  Where a recurrence meets z = 0, the row
-equation of T_s - lam I two entries away gives the next entry.  The
+equation of T_s - lam I two entries away gives the next entry (0 where that
+row's coupling is exactly zero, a split of T_s).  The
 representation tree of the full method (new shifted representations for
 clusters of close eigenvalues) is not part of this step: a cluster's
 vectors are orthogonalised by the same Gram-Schmidt as after inverse
@@ -78,12 +79,12 @@ def twisted_eigenvectors(alpha: np.ndarray, lam: np.ndarray) -> np.ndarray:
             if z[k + 1] != 0.0:
                 z[k] = -(alpha[k] / dp[k, j]) * z[k + 1]
             else:   # row k+1: alpha_k z_k - lam z_{k+1} + alpha_{k+1} z_{k+2} = 0
-                z[k] = -(alpha[k + 1] / alpha[k]) * z[k + 2]
+                z[k] = -(alpha[k + 1] / alpha[k]) * z[k + 2] if alpha[k] != 0.0 else 0.0
         for k in range(r, N - 1):
             if z[k] != 0.0:
                 z[k + 1] = -(alpha[k] / dm[k + 1, j]) * z[k]
             else:   # row k: alpha_{k-1} z_{k-1} - lam z_k + alpha_k z_{k+1} = 0
-                z[k + 1] = -(alpha[k - 1] / alpha[k]) * z[k - 1]
+                z[k + 1] = -(alpha[k - 1] / alpha[k]) * z[k - 1] if alpha[k] != 0.0 else 0.0
         Z[:, j] = z / np.linalg.norm(z)
     return Z
 

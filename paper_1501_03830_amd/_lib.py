@@ -25,6 +25,7 @@ BSE_PREC_FP32_REFINE = 1
 BSE_WANT_VECTORS = 1
 BSE_WANT_WEIGHTS = 2
 BSE_TWO_STAGE = 4
+BSE_EIGVEC_TWISTED = 8
 
 BSE_NUM_STAGES = 11
 STAGE_NAMES = ["build_M", "potrf", "form_W", "sktrd", "bisect", "invit", "reorth", "apply_U",
@@ -138,6 +139,7 @@ SIGNATURES = [
     ("bse_sktrd", _I, [_P, _I, _P, _I, _P, _P]),
     ("bse_sktrd2", _I, [_P, _I, _P, _I, _P]),
     ("bse_tridiag_eig", _I, [_P, _I, _P, _P, _P, _I]),
+    ("bse_tridiag_eig_flags", _I, [_P, _I, _P, _P, _P, _I, _U]),
 ]
 
 _lib = None

@@ -235,12 +235,12 @@ class Context:
         return info, (rep.as_dict() if rep is not None else None)
 
     def solve_batched_raw(self, ns, Acs, Bcs, lams, Xbufs=None, ds=None, ws=None, report: bool = False,
-                          prec: int = _lib.BSE_PREC_FP64):
+                          prec: int = _lib.BSE_PREC_FP64, extra_flags: int = 0):
         """bse_solve_batched on column-major device buffers (as made by
         to_colmajor), one entry per problem; nothing is copied.  Returns
         (info list, report)."""
         count = len(ns)
-        flags = 0
+        flags = extra_flags
         if Xbufs is not None:
             flags |= _lib.BSE_WANT_VECTORS
         if ds is not None:
@@ -265,7 +265,7 @@ class Context:
         return list(info), (rep.as_dict() if rep is not None else None)
 
     def solve_batched(self, As, Bs, ds=None, vectors: bool = True, report: bool = False,
-                      prec: int = _lib.BSE_PREC_FP64):
+                      prec: int = _lib.BSE_PREC_FP64, extra_flags: int = 0):
         """Batched eigensolve of independent problems (lists of complex128
         (n_i, n_i) logical matrices; ds: optional list of complex 2n_i dipole
         vectors used as d_r = d_l).  Returns a list of per-problem dicts like
@@ -279,7 +279,7 @@ class Context:
         Xbufs = [torch.empty((k, 2 * k), dtype=torch.complex128, device=dev) for k in ns] if want_x else None
         dbs = [d.to(dev, torch.complex128).contiguous() for d in ds] if ds is not None else None
         ws = [torch.empty(k, dtype=torch.complex128, device=dev) for k in ns] if ds is not None else None
-        info, rep = self.solve_batched_raw(ns, Acs, Bcs, lams, Xbufs, dbs, ws, report, prec)
+        info, rep = self.solve_batched_raw(ns, Acs, Bcs, lams, Xbufs, dbs, ws, report, prec, extra_flags)
         out = []
         for i in range(len(ns)):
             out.append({
@@ -398,12 +398,13 @@ class Context:
         _lib.check(self.lib.bse_sktrd2(self.h, N, _ptr(Wb), N, _ptr(alpha)), "bse_sktrd2")
         return alpha
 
-    def tridiag_eig(self, alpha: torch.Tensor, vectors: bool = True):
+    def tridiag_eig(self, alpha: torch.Tensor, vectors: bool = True, flags: int = 0):
         N = alpha.shape[0] + 1
         a = alpha.to(self.device, torch.float64).contiguous()
         lam = torch.empty(N // 2, dtype=torch.float64, device=self.device)
         Vb = torch.empty((N // 2, N), dtype=torch.float64, device=self.device) if vectors else None
-        _lib.check(self.lib.bse_tridiag_eig(self.h, N, _ptr(a), _ptr(lam), _ptr(Vb), N), "bse_tridiag_eig")
+        _lib.check(self.lib.bse_tridiag_eig_flags(self.h, N, _ptr(a), _ptr(lam), _ptr(Vb), N, flags),
+                   "bse_tridiag_eig_flags")
         return lam, (None if Vb is None else from_colmajor(Vb))
 
 

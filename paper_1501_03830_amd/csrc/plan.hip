@@ -89,7 +89,7 @@ extern "C" int bse_plan_check(int count, const int* n, int prec, unsigned flags,
   if (count <= 0) return set_error(-1, "count must be positive");
   if (!n) return set_error(-2, "n is NULL");
   if (!valid_prec(prec)) return set_error(-3, "unsupported precision policy");
-  if (flags & ~(BSE_WANT_VECTORS | BSE_WANT_WEIGHTS | BSE_TWO_STAGE)) return set_error(-4, "unknown flags");
+  if (flags & ~(BSE_WANT_VECTORS | BSE_WANT_WEIGHTS | BSE_TWO_STAGE | BSE_EIGVEC_TWISTED)) return set_error(-4, "unknown flags");
   if ((flags & BSE_TWO_STAGE) && count != 1) return set_error(-4, "the two-stage reduction runs one problem at a time");
   for (int i = 0; i < count; ++i)
     if (n[i] <= 0) return set_error(-2, "n must be positive");

@@ -500,7 +500,7 @@ int check_solve_args(int n, const void* A, int lda, const void* B, int ldb, int 
   if (need_B && !B) return set_error(-5, "B is NULL");
   if (need_B && ldb < n) return set_error(-6, "ldb < n");
   if (!valid_prec(prec)) return set_error(-7, "unsupported precision policy");
-  if (flags & ~(BSE_WANT_VECTORS | BSE_WANT_WEIGHTS | BSE_TWO_STAGE)) return set_error(-8, "unknown flags");
+  if (flags & ~(BSE_WANT_VECTORS | BSE_WANT_WEIGHTS | BSE_TWO_STAGE | BSE_EIGVEC_TWISTED)) return set_error(-8, "unknown flags");
   if (!lambda) return set_error(-9, "lambda is NULL");
   const bool vec = (flags & BSE_WANT_VECTORS) != 0;
   const bool wts = (flags & BSE_WANT_WEIGHTS) != 0;
@@ -728,7 +728,7 @@ int bse_solve_batched(bse_ctx* ctx, int count, const int* n, const void* const* 
   if (!B) return set_error(-6, "B is NULL");
   if (!ldb) return set_error(-7, "ldb is NULL");
   if (!valid_prec(prec)) return set_error(-8, "unsupported precision policy");
-  if (flags & ~(BSE_WANT_VECTORS | BSE_WANT_WEIGHTS)) return set_error(-9, "unknown flags");
+  if (flags & ~(BSE_WANT_VECTORS | BSE_WANT_WEIGHTS | BSE_EIGVEC_TWISTED)) return set_error(-9, "unknown flags");
   if (!lambda) return set_error(-10, "lambda is NULL");
   const bool vec = (flags & BSE_WANT_VECTORS) != 0;
   const bool wts = (flags & BSE_WANT_WEIGHTS) != 0;
@@ -795,7 +795,7 @@ static int check_request(const bse_request* r) {
   if (!r->B) return set_error(-2, "request: B is NULL");
   if (r->ldb < r->n) return set_error(-2, "request: ldb < n");
   if (!valid_prec(r->prec)) return set_error(-2, "request: unsupported precision policy");
-  if (r->flags & ~(BSE_WANT_VECTORS | BSE_WANT_WEIGHTS)) return set_error(-2, "request: unknown flags");
+  if (r->flags & ~(BSE_WANT_VECTORS | BSE_WANT_WEIGHTS | BSE_EIGVEC_TWISTED)) return set_error(-2, "request: unknown flags");
   if (!r->lambda) return set_error(-2, "request: lambda is NULL");
   const bool vec = (r->flags & BSE_WANT_VECTORS) != 0;
   const bool wts = (r->flags & BSE_WANT_WEIGHTS) != 0;
@@ -971,17 +971,20 @@ int bse_sktrd2(bse_ctx* ctx, int N, double* W, int ldw, double* alpha) {
   return 0;
 }
 
-int bse_tridiag_eig(bse_ctx* ctx, int N, const double* alpha, double* lambda, double* V, int ldv) {
+int bse_tridiag_eig_flags(bse_ctx* ctx, int N, const double* alpha, double* lambda, double* V, int ldv,
+                          unsigned flags) {
   if (!ctx) return set_error(-1, "ctx is NULL");
   if (N < 2 || (N & 1)) return set_error(-2, "N must be even and >= 2");
   if (!alpha) return set_error(-3, "alpha is NULL");
   if (!lambda) return set_error(-4, "lambda is NULL");
   if (V && ldv < N) return set_error(-6, "ldv < N");
+  if (flags & ~BSE_EIGVEC_TWISTED) return set_error(-7, "unknown flags");
   BSE_TRY(prologue(ctx));
   Setup S;
   BSE_TRY(setup_single(ctx, N, &S));
   Prob& P = ctx->lane.hprobs[0];
   P.lambda = lambda;
+  P.flags = flags;
   hipStream_t s = ctx->lane.stream;
   BSE_TRY(upload(&ctx->lane, S, 1));
   const Batch b = single_batch(ctx, S);
@@ -996,6 +999,10 @@ int bse_tridiag_eig(bse_ctx* ctx, int N, const double* alpha, double* lambda, do
   }
   BSE_HIP(hipStreamSynchronize(s));
   return 0;
+}
+
+int bse_tridiag_eig(bse_ctx* ctx, int N, const double* alpha, double* lambda, double* V, int ldv) {
+  return bse_tridiag_eig_flags(ctx, N, alpha, lambda, V, ldv, 0u);
 }
 
 }  // extern "C"

@@ -192,6 +192,18 @@ __device__ inline double perturb(double d, double pert) {
   return (fabs(d) < pert) ? (d < 0.0 ? -pert : pert) : d;
 }
 
+// Eigenvalues closer than this many eps |lambda| to a neighbour are
+// numerically degenerate for the twisted factorisations (both would see the
+// same shifted matrix and return the same vector): inverse iteration, whose
+// pushed-apart shifts and independent starts separate them, computes those.
+constexpr double TWIST_DEGEN = 1000.0;
+
+__device__ inline bool twist_degenerate(const BSE_CONST double* __restrict__ lam, int j, int n) {
+  const double lj = lam[j];
+  const double tol = TWIST_DEGEN * EPS * fabs(lj);
+  return (j > 0 && lj - lam[j - 1] <= tol) || (j + 1 < n && lam[j + 1] - lj <= tol);
+}
+
 // Workspace per eigenvector j (n of them), element k at [k*n + j]:
 //   fd (U diagonal), fu (first superdiagonal), fu2 (second), fl (multiplier),
 //   fs (row interchange flag).  Vt holds the iterate.
@@ -200,6 +212,9 @@ __global__ __launch_bounds__(64) void k_invit(const Prob* __restrict__ probs) {
   const int N = P.N, n = P.n;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
+  // with BSE_EIGVEC_TWISTED, only the degenerate eigenvalues (k_twisted
+  // computed every other vector)
+  if ((P.flags & BSE_EIGVEC_TWISTED) && !twist_degenerate(ro(P.lambda), j, n)) return;
   const BSE_CONST double* __restrict__ alpha = ro(P.alpha);
   const BSE_CONST double* __restrict__ scal = ro(P.scal);
   const BSE_GLOBAL double* __restrict__ shift = gbl(P.shift);
@@ -347,6 +362,175 @@ __global__ __launch_bounds__(64) void k_invit(const Prob* __restrict__ probs) {
   }
 }
 
+// Eigenvector j of T_s by a twisted factorisation (the per-vector step of
+// MRRR, Section 3.3's alternative to inverse iteration), one thread per
+// eigenvalue, for problems with BSE_EIGVEC_TWISTED:
+//   d+_0 = -lam,  d+_{k+1} = -lam - alpha_k^2 / d+_k       (top down)
+//   d-_{N-1} = -lam,  d-_k = -lam - alpha_k^2 / d-_{k+1}   (bottom up)
+//   gamma_k = d+_k + d-_k + lam,  r = argmin |gamma_k|
+//   z_r = 1, z_k = -(alpha_k / d+_k) z_{k+1} (k < r),
+//   z_{k+1} = -(alpha_k / d-_{k+1}) z_k (k >= r), then normalised.
+// Pivots below pivmin in modulus become -pivmin (as in the Sturm count); a
+// recurrence that meets z = 0 takes the row equation two entries away (0
+// where that row's coupling is exactly zero, a split of T_s).  d+
+// and d- go to the first two factor arrays of inverse iteration ([k*n + j],
+// coalesced over the eigenvalues); loads are issued UB steps ahead of the
+// dependent arithmetic.  Degenerate eigenvalues are left to inverse
+// iteration (k_invit runs after this kernel and writes only those).
+__global__ __launch_bounds__(64) void k_twisted(const Prob* __restrict__ probs) {
+  const Prob& P = probs[blockIdx.z];
+  if (!(P.flags & BSE_EIGVEC_TWISTED)) return;   // uniform
+  const int N = P.N, n = P.n;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const BSE_CONST double* __restrict__ alpha = ro(P.alpha);
+  const BSE_CONST double* __restrict__ lamv = ro(P.lambda);
+  if (twist_degenerate(lamv, j, n)) return;
+  const double pivmin = ro(P.scal)[0];
+  const long sz = (long)N * n;
+  BSE_GLOBAL double* __restrict__ dp = gbl(P.inv);
+  BSE_GLOBAL double* __restrict__ dm = gbl(P.inv + sz);
+  BSE_GLOBAL double* __restrict__ Vt = gbl(P.Vt);
+  const long ldn = n;
+  const double lam = lamv[j];
+  auto fix = [&](double q) { return fabs(q) < pivmin ? -pivmin : q; };
+  constexpr int UB = 32;
+
+  // top down
+  double d = fix(-lam);
+  dp[j] = d;
+  {
+    int k = 0;
+    for (; k + UB <= N - 1; k += UB) {
+      double a[UB];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) a[u] = alpha[k + u];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        d = fix(-lam - a[u] * a[u] / d);
+        dp[(long)(k + u + 1) * ldn + j] = d;
+      }
+    }
+    for (; k < N - 1; ++k) {
+      const double a = alpha[k];
+      d = fix(-lam - a * a / d);
+      dp[(long)(k + 1) * ldn + j] = d;
+    }
+  }
+  // bottom up, with the twists
+  d = fix(-lam);
+  dm[(long)(N - 1) * ldn + j] = d;
+  double gmin = fabs(dp[(long)(N - 1) * ldn + j] + d + lam);
+  int r = N - 1;
+  {
+    int k = N - 2;
+    for (; k - UB + 1 >= 0; k -= UB) {
+      double a[UB], pk[UB];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        a[u] = alpha[k - u];
+        pk[u] = dp[(long)(k - u) * ldn + j];
+      }
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        d = fix(-lam - a[u] * a[u] / d);
+        dm[(long)(k - u) * ldn + j] = d;
+        const double g = fabs(pk[u] + d + lam);
+        if (g < gmin) {
+          gmin = g;
+          r = k - u;
+        }
+      }
+    }
+    for (; k >= 0; --k) {
+      const double a = alpha[k];
+      d = fix(-lam - a * a / d);
+      dm[(long)k * ldn + j] = d;
+      const double g = fabs(dp[(long)k * ldn + j] + d + lam);
+      if (g < gmin) {
+        gmin = g;
+        r = k;
+      }
+    }
+  }
+  // the vector: upwards from r, then downwards, UB steps of loads at a time
+  // (a step's factor does not depend on the vector, only its use does)
+  double ss = 1.0;
+  Vt[(long)r * ldn + j] = 1.0;
+  {
+    double z1 = 1.0, z2 = 0.0;   // z_{k+1}, z_{k+2}
+    int k = r - 1;
+    for (; k - UB + 1 >= 0; k -= UB) {
+      double pk[UB], a[UB];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        pk[u] = dp[(long)(k - u) * ldn + j];
+        a[u] = alpha[k - u];
+      }
+      const double a_top = (k + 1 <= N - 2) ? alpha[k + 1] : 0.0;
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const double an = (u == 0) ? a_top : a[u - 1];   // alpha_{k-u+1}
+        const double z = (z1 != 0.0) ? -(a[u] / pk[u]) * z1 : (a[u] != 0.0 ? -(an / a[u]) * z2 : 0.0);
+        Vt[(long)(k - u) * ldn + j] = z;
+        ss += z * z;
+        z2 = z1;
+        z1 = z;
+      }
+    }
+    for (; k >= 0; --k) {
+      const double a = alpha[k];
+      const double an = (k + 1 <= N - 2) ? alpha[k + 1] : 0.0;
+      const double z = (z1 != 0.0) ? -(a / dp[(long)k * ldn + j]) * z1 : (a != 0.0 ? -(an / a) * z2 : 0.0);
+      Vt[(long)k * ldn + j] = z;
+      ss += z * z;
+      z2 = z1;
+      z1 = z;
+    }
+  }
+  {
+    double z1 = 1.0, z0 = 0.0;   // z_k, z_{k-1}
+    int k = r;
+    for (; k + UB <= N - 1; k += UB) {
+      double mk[UB], a[UB];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        mk[u] = dm[(long)(k + u + 1) * ldn + j];
+        a[u] = alpha[k + u];
+      }
+      const double a_bot = (k >= 1) ? alpha[k - 1] : 0.0;
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const double ap = (u == 0) ? a_bot : a[u - 1];   // alpha_{k+u-1}
+        const double z = (z1 != 0.0) ? -(a[u] / mk[u]) * z1 : (a[u] != 0.0 ? -(ap / a[u]) * z0 : 0.0);
+        Vt[(long)(k + u + 1) * ldn + j] = z;
+        ss += z * z;
+        z0 = z1;
+        z1 = z;
+      }
+    }
+    for (; k < N - 1; ++k) {
+      const double a = alpha[k];
+      const double ap = (k >= 1) ? alpha[k - 1] : 0.0;
+      const double z = (z1 != 0.0) ? -(a / dm[(long)(k + 1) * ldn + j]) * z1 : (a != 0.0 ? -(ap / a) * z0 : 0.0);
+      Vt[(long)(k + 1) * ldn + j] = z;
+      ss += z * z;
+      z0 = z1;
+      z1 = z;
+    }
+  }
+  const double inv = 1.0 / sqrt(ss);
+  int k = 0;
+  for (; k + UB <= N; k += UB) {
+    double vv[UB];
+#pragma unroll
+    for (int u = 0; u < UB; ++u) vv[u] = Vt[(long)(k + u) * ldn + j];
+#pragma unroll
+    for (int u = 0; u < UB; ++u) Vt[(long)(k + u) * ldn + j] = vv[u] * inv;
+  }
+  for (; k < N; ++k) Vt[(long)k * ldn + j] *= inv;
+}
+
 // cid[j] = index of the cluster of eigenvalue j (consecutive gaps <= ortol)
 __global__ __launch_bounds__(1024) void k_cluster_ids(const Prob* __restrict__ probs) {
   __shared__ int sums[1024];
@@ -454,6 +638,10 @@ int bisect_batched(hipStream_t s, const Batch& b) {
 int invit_batched(hipStream_t s, const Batch& b) {
   if (b.count <= 0) return 0;
   const int n0 = b.maxn();
+  // launched whatever the flags (its problems without BSE_EIGVEC_TWISTED
+  // exit at once): the launch sequence depends on the shape alone, as a
+  // captured graph of the chain requires
+  BSE_LAUNCH(k_twisted, dim3((unsigned)((n0 + 63) / 64), 1, (unsigned)b.count), 64, 0, s, b.dev);
   BSE_LAUNCH(k_shifts, dim3(1, 1, (unsigned)b.count), 64, 0, s, b.dev);
   BSE_LAUNCH(k_invit, dim3((unsigned)((n0 + 63) / 64), 1, (unsigned)b.count), 64, 0, s, b.dev);
   return 0;
