@@ -115,6 +115,7 @@ struct Prob {
   // mixed-precision path (prec == BSE_PREC_FP32_REFINE)
   int prec;
   float* W32;           // FP32 copy of W reduced to tridiagonal form (ld x ld)
+  float *Y1f, *Y2f;     // FP32 copies of Y1, Y2 for the rank-2k update (in R3)
   double *R1, *R2, *R3, *R4;   // refinement work, ld x ld each
   double* refmax;       // refinement: per-tile partial maxima (2 per tile)
   double* refout;       // refinement: [largest correction, clamped pairs] (header)

@@ -104,9 +104,16 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
       g.ta = 0; g.tb = 1; g.M = m2; g.N = m2; g.K = 2 * nbp; g.beta = 1.0;
       g.A = P.Y1 + e; g.lda = ld; g.B = P.Y2 + e; g.ldb = ld; g.C = P.W + e + (long)e * ld; g.ldc = ld;
       g.c_uplo = 2;
-      if (P.prec == BSE_PREC_FP32_REFINE) {   // W held in FP32
+      if (P.prec == BSE_PREC_FP32_REFINE) {
+        // W held in FP32: the product on the FP32 matrix cores from FP32
+        // copies of the panel vectors (k_y_to_f32), accumulated in FP32
         g.C = nullptr;
         g.Cf = P.W32 + e + (long)e * ld;
+        g.f32 = 1;
+        g.A = nullptr;
+        g.B = nullptr;
+        g.Af = P.Y1f + e;
+        g.Bf = P.Y2f + e;
       }
       break;
     }
@@ -659,9 +666,10 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 // rate, so a tile needs four times the FP64 tile's reuse to stay off the
 // memory bound.)  In a 16 x 16 f32 block the entry (i, j) lives in lane
 // j + 16 (i / 4), accumulator element i mod 4; the f64 instruction
-// interleaves the rows the other way.  Full (not triangular) outputs, B not
-// transposed.
-template <bool TA>
+// interleaves the rows the other way.  Full outputs, or the lower
+// (c_uplo 1) or strictly lower (c_uplo 2) triangle of a square one in
+// triangular tile order; B transposed or not.
+template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void gemm_f32_kernel(const Prob* __restrict__ probs, int op, int step,
                                                        GemmParams single) {
   constexpr int TBM = F32_TILE, TBN = F32_TILE, TBK = 16;
@@ -683,7 +691,8 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const Prob* __restrict__ 
   const BSE_GLOBAL float* __restrict__ Ag = gbl(p.Af);
   const BSE_GLOBAL float* __restrict__ Bg = gbl(p.Bf);
   const int tiles_m = (p.M + TBM - 1) / TBM, tiles_n = (p.N + TBN - 1) / TBN;
-  const long ntiles = (p.M <= 0 || p.N <= 0) ? 0 : (long)tiles_m * tiles_n;
+  const bool tri_c = p.c_uplo == 1 || p.c_uplo == 2;
+  const long ntiles = (p.M <= 0 || p.N <= 0) ? 0 : (tri_c ? (long)tiles_m * (tiles_m + 1) / 2 : (long)tiles_m * tiles_n);
   // remap over this problem's own tiles (see the FP64 kernel)
   const long total = ntiles * p.splits;
   if ((long)blockIdx.x >= total) return;  // uniform: beyond this problem's tiles
@@ -694,10 +703,15 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const Prob* __restrict__ 
     tile /= p.splits;
   }
   int tm, tn;
-  grouped_tile(tile, tiles_m, tiles_n, tm, tn);
+  if (tri_c) grouped_lower_tile(tile, tiles_m, tm, tn);
+  else grouped_tile(tile, tiles_m, tiles_n, tm, tn);
   const int i0 = tm * TBM, j0 = tn * TBN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave & 1, wc = wave >> 1;
+  // output entries kept: all, the lower triangle, or the strictly lower one
+  auto in_c = [&](int row, int col) {
+    return row < p.M && col < p.N && (p.c_uplo != 1 || row >= col) && (p.c_uplo != 2 || row > col);
+  };
   int kbeg = 0, kend = p.K;
   if (p.splits > 1) {
     const int s0 = slice * p.kchunk;
@@ -740,15 +754,24 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const Prob* __restrict__ 
   auto load_b = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < E; ++q) {
-      const int k = k0 + (tid & 15);
-      const int j = j0 + (tid >> 4) + 16 * q;
-      rb[q] = (j < p.N && k < kend) ? Bg[(long)k + (long)j * p.ldb] : 0.0f;
+      int j, k;
+      if (!TB) {
+        k = k0 + (tid & 15);
+        j = j0 + (tid >> 4) + 16 * q;
+      } else {   // B stored N x K: the lanes run along j
+        j = j0 + (tid & 127);
+        k = k0 + (tid >> 7) + 2 * q;
+      }
+      rb[q] = (j < p.N && k < kend) ? (TB ? Bg[(long)j + (long)k * p.ldb] : Bg[(long)k + (long)j * p.ldb]) : 0.0f;
     }
   };
   auto store_b = [&](int buf) {
     float* sb = smem + 2 * AS + buf * BS;
 #pragma unroll
-    for (int q = 0; q < E; ++q) sb[(tid & 15) * LB + (tid >> 4) + 16 * q] = rb[q];
+    for (int q = 0; q < E; ++q) {
+      if (!TB) sb[(tid & 15) * LB + (tid >> 4) + 16 * q] = rb[q];
+      else sb[((tid >> 7) + 2 * q) * LB + (tid & 127)] = rb[q];
+    }
   };
 
   int buf = 0;
@@ -825,7 +848,7 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const Prob* __restrict__ 
           const int idx = tid + 256 * (h * PF + u);
           const int rl = idx % TBM, cl = idx / TBM;
           const int row = i0 + rl, col = j0 + pass * EC + cl;
-          ok[u] = row < p.M && col < p.N;
+          ok[u] = in_c(row, col);
           cold[u] = 0.0f;
           if (ok[u] && read_cf) cold[u] = gbl(p.Cf)[(long)row + (long)col * p.ldc];
         }
@@ -857,7 +880,7 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const Prob* __restrict__ 
         const int idx = tid + 256 * (h * PER + u);
         const int rl = idx % TBM, cl = idx / TBM;
         const int row = i0 + rl, col = j0 + pass * EC + cl;
-        ok[u] = row < p.M && col < p.N;
+        ok[u] = in_c(row, col);
         cold[u] = 0.0;
         if (ok[u] && read_c) {
           const long o = (long)row + (long)col * p.ldc;
@@ -997,9 +1020,10 @@ int gemm_batched(hipStream_t s, const Batch& b, int nact, int op, int step) {
       if (g.M > 0 && g.N > 0) wg = std::max(wg, g.ntiles * g.splits);
     }
     const dim3 grid((unsigned)wg, 1, (unsigned)nact);
-    if (tb != 0) return set_error(BSE_EUNSUPPORTED, "gemm_batched: FP32 product with a transposed B");
-    if (ta == 0) BSE_LAUNCH(gemm_f32_kernel<false>, grid, 256, 0, s, b.dev, op, step, dummy);
-    else BSE_LAUNCH(gemm_f32_kernel<true>, grid, 256, 0, s, b.dev, op, step, dummy);
+    if (ta == 0 && tb == 0) BSE_LAUNCH((gemm_f32_kernel<false, false>), grid, 256, 0, s, b.dev, op, step, dummy);
+    else if (ta == 0) BSE_LAUNCH((gemm_f32_kernel<false, true>), grid, 256, 0, s, b.dev, op, step, dummy);
+    else if (tb == 0) BSE_LAUNCH((gemm_f32_kernel<true, false>), grid, 256, 0, s, b.dev, op, step, dummy);
+    else BSE_LAUNCH((gemm_f32_kernel<true, true>), grid, 256, 0, s, b.dev, op, step, dummy);
   } else {
     BSE_TRY(launch(s, ta != 0, tb != 0, cfg, dim3((unsigned)maxwg, 1, (unsigned)nact), b.dev, op, step, dummy));
   }

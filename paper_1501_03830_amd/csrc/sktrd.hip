@@ -461,6 +461,27 @@ __global__ __launch_bounds__(256) void sk_symv(const Prob* __restrict__ probs, i
         rsum[t][0][lane] + rsum[t][1][lane] + rsum[t][2][lane] + rsum[t][3][lane];
 }
 
+// FP32 copies of the panel's columns [v_l p_l] (Y1) and [p_l -v_l] (Y2),
+// rows e = k0 + nbp .. N-1, for the rank-2k update of the FP32 W on the FP32
+// matrix cores (mixed-precision problems only).  Grid: rows x 2 NBMAX
+// columns x problems.
+__global__ __launch_bounds__(256) void k_y_to_f32(const Prob* __restrict__ probs, int k0) {
+  const Prob& P = probs[blockIdx.z];
+  if (P.prec != BSE_PREC_FP32_REFINE) return;   // uniform
+  const int N = P.N;
+  if (k0 > N - 2) return;
+  const int nbp = min(NBMAX, N - 1 - k0);
+  const int e = k0 + nbp;
+  if (N - e < 2 || e > N - 2) return;   // no update (as GOP_SKTRD_R2K)
+  const int c = blockIdx.y;
+  if (c >= 2 * nbp) return;
+  const long r = e + (long)blockIdx.x * 256 + threadIdx.x;
+  if (r >= N) return;
+  const long o = r + (long)c * P.ld;
+  gbl(P.Y1f)[o] = (float)gbl(P.Y1)[o];
+  gbl(P.Y2f)[o] = (float)gbl(P.Y2)[o];
+}
+
 // p_i = tau (S v + V c_P - P c_V) for the rows of block b, the in-place store
 // of v_i, and the update of the next column with one partial squared norm of
 // it per workgroup.  The UW wavefronts share the 64-row block: the partial
@@ -793,6 +814,8 @@ static int sktrd_run(hipStream_t s, const Batch& b, KernelTimer* timer) {
       if (nblk0 > UPD_SMALL) BSE_LAUNCH((sk_update<WT, 16>), gup, 1024, 0, s, b.dev, j, i, pre, nact);
       else BSE_LAUNCH((sk_update<WT, 4>), gup, 256, 0, s, b.dev, j, i, pre, nact);
     }
+    if constexpr (sizeof(WT) == 4)
+      BSE_LAUNCH(k_y_to_f32, dim3((unsigned)((N0 + 255) / 256), 2 * NBMAX, (unsigned)nstart), 256, 0, s, b.dev, k0);
     BSE_TRY(gemm_batched(s, b, nstart, GOP_SKTRD_R2K, k0));
   }
   return 0;

@@ -145,6 +145,9 @@ static void bind_problem(const Plan& p, char* base, Prob* P) {
     P->R3 = R + 2 * sq;
     P->R4 = R + 3 * sq;
     P->Z32 = reinterpret_cast<float*>(P->R4);
+    // R3 is free until the refinement: the reduction's FP32 panel copies
+    P->Y1f = reinterpret_cast<float*>(P->R3);
+    P->Y2f = P->Y1f + (size_t)p.ld * 2 * SKTRD_NB;
     P->refmax = reinterpret_cast<double*>(base + p.off_refmax);
     P->perm = reinterpret_cast<int*>(base + p.off_perm);
     char* cl = base + p.off_cl;
