@@ -186,8 +186,6 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
       break;
     case GOP_REF_P:
     case GOP_REF_PB:
-    case GOP_REF_PF:
-    case GOP_REF_PFB:
     case GOP_REF_S:
     case GOP_REF_G:
     case GOP_REF_U: {
@@ -195,14 +193,13 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
       double* Ub = (step & 1) ? P.R4 : P.Z;
       double* Un = (step & 1) ? P.Z : P.R4;
       g.M = P.N; g.N = P.N; g.K = P.N;
-      if (op == GOP_REF_P || op == GOP_REF_PF) {
-        // rows 0..n-1 of W Ub = [W11 W12] Ub (W full, FP64); the final
-        // eigenvalues need only the first n columns
-        g.M = P.n; g.N = (op == GOP_REF_PF) ? P.n : P.N;
+      if (op == GOP_REF_P) {
+        // rows 0..n-1 of W Ub = [W11 W12] Ub (W full, FP64)
+        g.M = P.n; g.N = P.N;
         g.ta = 0; g.tb = 0; g.A = P.W; g.lda = ld; g.B = Ub; g.ldb = ld; g.C = P.R1; g.ldc = ld;
-      } else if (op == GOP_REF_PB || op == GOP_REF_PFB) {
+      } else if (op == GOP_REF_PB) {
         // rows n..N-1 of W Ub = W21 Ub[0:n, :], since W22 = 0
-        g.M = P.n; g.N = (op == GOP_REF_PFB) ? P.n : P.N; g.K = P.n;
+        g.M = P.n; g.N = P.N; g.K = P.n;
         g.ta = 0; g.tb = 0; g.A = P.W + P.n; g.lda = ld; g.B = Ub; g.ldb = ld; g.C = P.R1 + P.n; g.ldc = ld;
       } else if (op == GOP_REF_S) {  // Ub^T (W Ub), lower triangle
         g.ta = 1; g.tb = 0; g.A = Ub; g.lda = ld; g.B = P.R1; g.ldb = ld; g.C = P.R2; g.ldc = ld; g.c_uplo = 1;

@@ -87,8 +87,6 @@ enum GemmOp {
   GOP_REF_G,       // refinement: G = Ub^T Ub (lower)
   GOP_REF_U,       // refinement: next basis = Ub + Ub F (the product in FP32)
   GOP_REF_PB,      // refinement: rows n.. of W Ub = W21 Ub[0:n] (W22 = 0)
-  GOP_REF_PF,      // final eigenvalues: rows ..n-1 of W Ub, first n columns
-  GOP_REF_PFB,     // final eigenvalues: rows n.. of W Ub, first n columns
   // two-stage reduction, panel at column `step` (rows r0 = step + SBR_B ..):
   GOP_SBR_X,       // X = L22 Vp (L22 the strict lower part of the trailing block)
   GOP_SBR_XT,      // X -= L22^T Vp
@@ -102,7 +100,7 @@ enum GemmOp {
 
 // Refinement products, which read the problem's refinement state (the sweep
 // it converged in) to skip finished problems; no other product reads it.
-__host__ __device__ constexpr bool is_refine_op(int op) { return op >= GOP_REF_P && op <= GOP_REF_PFB; }
+__host__ __device__ constexpr bool is_refine_op(int op) { return op >= GOP_REF_P && op <= GOP_REF_PB; }
 
 // Bandwidth of the two-stage reduction's band (the panel width of its first
 // stage).
@@ -216,5 +214,8 @@ struct RefineStats {
   double last_correction = 0.0;
 };
 int refine_batched(hipStream_t s, const Batch& b, const RefineIO& io, RefineStats* st);
+// The refined eigenvalues, from the final basis in Z and G = L Z in P.W (after
+// L is applied), sorted (P.lambda, P.perm).
+int refine_final_batched(hipStream_t s, const Batch& b);
 
 }  // namespace bse

@@ -607,23 +607,29 @@ __global__ __launch_bounds__(256) void k_ref_decide(const Prob* __restrict__ pro
   }
 }
 
-// lambda_k from the final basis Ub (sweep count = refstate) and the first n
-// columns of P = W Ub (R1): one workgroup per pair
+// lambda_k = -b_k^T W a_k / sqrt(det [a_k b_k]^T [a_k b_k]) for the final
+// basis pair [a_k b_k] = sqrt(2) [Z_k Z_{n+k}], taken after L is applied
+// (G = L Z in P.W): with W = L^T J L, b^T W a = (L b)^T J (L a), so
+//   b_k^T W a_k = 2 sum_{i<n} (G[i, n+k] G[n+i, k] - G[n+i, n+k] G[i, k])
+// and the factors of 2 cancel against those of the Gram determinant.  This
+// spares a product with W of n columns; G is the FP64 product the output
+// needs anyway.  One workgroup per pair.
 __global__ __launch_bounds__(256) void k_ref_final(const Prob* __restrict__ probs) {
   __shared__ double red[4][4];
   const Prob& P = probs[blockIdx.z];
   const long n = P.n, N = P.N, ld = P.ld;
   const long k = blockIdx.x;
   if (k >= n) return;   // uniform
-  const BSE_GLOBAL double* __restrict__ U = gbl(basis(P, *gbl(P.refstate)));
-  const BSE_GLOBAL double* __restrict__ PW = gbl(P.R1);
-  const BSE_GLOBAL double* ua = U + k * ld;
-  const BSE_GLOBAL double* ub = U + (n + k) * ld;
-  const BSE_GLOBAL double* pa = PW + k * ld;
+  const BSE_GLOBAL double* __restrict__ Z = gbl(P.Z);
+  const BSE_GLOBAL double* __restrict__ G = gbl(P.W);
+  const BSE_GLOBAL double* za = Z + k * ld;
+  const BSE_GLOBAL double* zb = Z + (n + k) * ld;
+  const BSE_GLOBAL double* ga = G + k * ld;
+  const BSE_GLOBAL double* gb = G + (n + k) * ld;
   double s = 0.0, gaa = 0.0, gbb = 0.0, gab = 0.0;
+  for (long r = threadIdx.x; r < n; r += 256) s += gb[r] * ga[n + r] - gb[n + r] * ga[r];
   for (long r = threadIdx.x; r < N; r += 256) {
-    const double a = ua[r], b = ub[r];
-    s += b * pa[r];
+    const double a = za[r], b = zb[r];
     gaa += a * a;
     gbb += b * b;
     gab += a * b;
@@ -714,12 +720,17 @@ int refine_batched(hipStream_t s, const Batch& b, const RefineIO& io, RefineStat
     if (all_done) break;
   }
   if (st) st->sweeps = sweeps;
-  // eigenvalues from each problem's final basis, sorted; eigenvectors to Z
-  BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_PF, -1));
-  BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_PFB, -1));
+  // the final basis / sqrt(2) to Z, where L is applied to it; the eigenvalues
+  // follow from that product (refine_final_batched)
+  BSE_LAUNCH(k_ref_out, grid_NN(b), 256, 0, s, b.dev);
+  return 0;
+}
+
+int refine_final_batched(hipStream_t s, const Batch& b) {
+  if (b.count <= 0) return 0;
+  const int n0 = b.maxn();
   BSE_LAUNCH(k_ref_final, dim3((unsigned)n0, 1, (unsigned)b.count), 256, 0, s, b.dev);
   BSE_LAUNCH(k_ref_sort, dim3((unsigned)((n0 + 255) / 256), 1, (unsigned)b.count), 256, 0, s, b.dev);
-  BSE_LAUNCH(k_ref_out, grid_NN(b), 256, 0, s, b.dev);
   return 0;
 }
 

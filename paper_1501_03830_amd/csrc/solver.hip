@@ -337,11 +337,13 @@ static int chain_tail(hipStream_t s, Lane* L, const Setup& S, const Batch& b, bo
       BSE_TRY(refine_batched(s, b, io, rstats));
     }
     BSE_TRY(mark(L, timed, ev++));
-    if (vectors) {
+    // the mixed path applies L for its eigenvalues as well
+    if (vectors || mixed) {
       BSE_TRY(gemm_batched(s, b, b.count, GOP_APPLY_L, 0));
       BSE_TRY(mark(L, timed, ev++));
-      BSE_TRY(finish_batched(s, b));
-      if (b.count == 1 && (b.host[0].flags & FLAG_REAL_IN)) BSE_TRY(real_output_single(s, b));
+      if (mixed) BSE_TRY(refine_final_batched(s, b));
+      if (vectors) BSE_TRY(finish_batched(s, b));
+      if (vectors && b.count == 1 && (b.host[0].flags & FLAG_REAL_IN)) BSE_TRY(real_output_single(s, b));
     } else {
       BSE_TRY(mark(L, timed, ev++));
     }
