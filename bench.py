@@ -54,10 +54,11 @@ def stage_work(n: int, mixed: bool = False, sweeps: int = 0):
         "apply_L": ("mfma", 8.0 * n ** 3, FP64_PEAK_TFS),
     }
     if mixed:
-        # per sweep 12 n^3 (W Ub) + 8 + 8 (S, G) in FP64 and 16 n^3 (the
-        # FP32 update), each part against its own peak (the final
-        # eigenvalues come from the product with L of the output, O(n^2))
-        work["refine"] = ("mfma_split", (28.0 * sweeps * n ** 3, 16.0 * sweeps * n ** 3),
+        # per sweep 8 n^3 (Y = L Ub, L triangular) + 8 (C = Y_top^T Y_bot)
+        # + 8 (G, lower) in FP64 and 16 n^3 (the FP32 update), each part
+        # against its own peak (the final eigenvalues come from the product
+        # with L of the output, O(n^2))
+        work["refine"] = ("mfma_split", (24.0 * sweeps * n ** 3, 16.0 * sweeps * n ** 3),
                           (FP64_PEAK_TFS, FP32_PEAK_TFS))
     else:
         # one Cholesky QR pass: Gram matrix, its Cholesky, forward substitution

@@ -184,25 +184,21 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
       g.ta = 0; g.tb = 0; g.M = P.N; g.N = P.N; g.K = P.N;
       g.A = P.L; g.lda = ld; g.B = P.Z; g.ldb = ld; g.C = P.W; g.ldc = ld; g.a_tri = 1;
       break;
-    case GOP_REF_P:
-    case GOP_REF_PB:
-    case GOP_REF_S:
+    case GOP_REF_Y:
+    case GOP_REF_C:
     case GOP_REF_G:
     case GOP_REF_U: {
       // the basis of sweep `step` alternates between Z (even) and R4 (odd)
       double* Ub = (step & 1) ? P.R4 : P.Z;
       double* Un = (step & 1) ? P.Z : P.R4;
       g.M = P.N; g.N = P.N; g.K = P.N;
-      if (op == GOP_REF_P) {
-        // rows 0..n-1 of W Ub = [W11 W12] Ub (W full, FP64)
-        g.M = P.n; g.N = P.N;
-        g.ta = 0; g.tb = 0; g.A = P.W; g.lda = ld; g.B = Ub; g.ldb = ld; g.C = P.R1; g.ldc = ld;
-      } else if (op == GOP_REF_PB) {
-        // rows n..N-1 of W Ub = W21 Ub[0:n, :], since W22 = 0
-        g.M = P.n; g.N = P.N; g.K = P.n;
-        g.ta = 0; g.tb = 0; g.A = P.W + P.n; g.lda = ld; g.B = Ub; g.ldb = ld; g.C = P.R1 + P.n; g.ldc = ld;
-      } else if (op == GOP_REF_S) {  // Ub^T (W Ub), lower triangle
-        g.ta = 1; g.tb = 0; g.A = Ub; g.lda = ld; g.B = P.R1; g.ldb = ld; g.C = P.R2; g.ldc = ld; g.c_uplo = 1;
+      if (op == GOP_REF_Y) {
+        // Y = L Ub (L lower triangular: the K loop skips its zero upper part)
+        g.ta = 0; g.tb = 0; g.A = P.L; g.lda = ld; g.B = Ub; g.ldb = ld; g.C = P.R1; g.ldc = ld; g.a_tri = 1;
+      } else if (op == GOP_REF_C) {
+        // C = Y[0:n]^T Y[n:N] (full): with W = L^T J L, Ub^T W Ub = Y^T J Y = C - C^T
+        g.K = P.n;
+        g.ta = 1; g.tb = 0; g.A = P.R1; g.lda = ld; g.B = P.R1 + P.n; g.ldb = ld; g.C = P.R2; g.ldc = ld;
       } else if (op == GOP_REF_G) {  // Ub^T Ub, lower triangle
         g.ta = 1; g.tb = 0; g.A = Ub; g.lda = ld; g.B = Ub; g.ldb = ld; g.C = P.R3; g.ldc = ld; g.c_uplo = 1;
       } else {

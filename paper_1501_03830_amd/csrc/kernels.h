@@ -82,11 +82,10 @@ enum GemmOp {
   GOP_APPLYU_WB,   // block solve with T^{-1}: sub-block h -= S_h,>h (later rows); step 4q + h
   GOP_APPLYU_Z,    // Z -= V (T V^T Z)
   GOP_APPLY_L,     // G = L Z
-  GOP_REF_P,       // refinement: rows ..n-1 of P = W Ub (basis Ub of sweep `step`)
-  GOP_REF_S,       // refinement: S = Ub^T P (lower)
+  GOP_REF_Y,       // refinement: Y = L Ub (basis Ub of sweep `step`; L lower triangular)
+  GOP_REF_C,       // refinement: C = Y[0:n]^T Y[n:N], so that Ub^T W Ub = C - C^T
   GOP_REF_G,       // refinement: G = Ub^T Ub (lower)
   GOP_REF_U,       // refinement: next basis = Ub + Ub F (the product in FP32)
-  GOP_REF_PB,      // refinement: rows n.. of W Ub = W21 Ub[0:n] (W22 = 0)
   // two-stage reduction, panel at column `step` (rows r0 = step + SBR_B ..):
   GOP_SBR_X,       // X = L22 Vp (L22 the strict lower part of the trailing block)
   GOP_SBR_XT,      // X -= L22^T Vp
@@ -100,7 +99,7 @@ enum GemmOp {
 
 // Refinement products, which read the problem's refinement state (the sweep
 // it converged in) to skip finished problems; no other product reads it.
-__host__ __device__ constexpr bool is_refine_op(int op) { return op >= GOP_REF_P && op <= GOP_REF_PB; }
+__host__ __device__ constexpr bool is_refine_op(int op) { return op >= GOP_REF_Y && op <= GOP_REF_U; }
 
 // Bandwidth of the two-stage reduction's band (the panel width of its first
 // stage).

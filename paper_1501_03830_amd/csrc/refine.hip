@@ -7,9 +7,10 @@
 // Ub = sqrt(2) [a_1 .. a_n | b_1 .. b_n] satisfy
 //     Ub^T Ub = I,   Ub^T W Ub = Sigma = [0 Lambda; -Lambda 0].
 // Given an approximate Ub (from the FP32 reduction), one sweep computes in
-// FP64 (W is the exact FP64 W of Algorithm 1 step 3)
-//     P = W Ub,  S = Ub^T P,  G = Ub^T Ub,  R = I - G,
-// (P in two products: W22 = 0 leaves the bottom rows a product over n only),
+// FP64, with W = L^T J L from the FP64 Cholesky factor of Algorithm 1 step 2,
+//     Y = L Ub,  S = Ub^T W Ub = Y^T J Y = C - C^T (C = Y[0:n]^T Y[n:N]),
+//     G = Ub^T Ub,  R = I - G,
+// (two products of N^3 flops each for S: L is triangular and C has depth n),
 // the refined lambda_k of each pair from its 2 x 2 blocks,
 //     lambda_k = s_k / sqrt(det G_kk),  s_k = -S[n+k, k],
 // and the correction Ub <- Ub + Ub F, F = R/2 + E with E skew.  E is zero on
@@ -41,7 +42,9 @@
 // with no block left out, then its eigenvalues are taken from the refined
 // basis (error of order STOP_TOL^4 relative) and sorted.  A problem still
 // short of that after MAX_SWEEPS reports INFO_NOCONV.  Each problem converges
-// on its own: kernels skip problems that finished in an earlier sweep.
+// on its own: kernels skip problems that finished in an earlier sweep.  The
+// final eigenvalues use the same identity on the product L Ub that the
+// output needs (k_ref_final, after L is applied).
 #include <cmath>
 #include <cstring>
 
@@ -110,6 +113,37 @@ __global__ __launch_bounds__(64) void k_ref_lambda(const Prob* __restrict__ prob
   gbl(P.shift)[k] = s / sqrt(gaa * gbb - gab * gab);
 }
 
+// S = Ub^T W Ub = C - C^T (lower triangle, in place in R2) from
+// C = Y[0:n]^T Y[n:N], Y = L Ub: workgroup (I, J), I >= J, of 64 x 64 tiles
+// stages the partner tile (J, I) in LDS, both tiles read along their columns,
+// and writes the lower tile (I, J).  Upper tiles are only read, so the
+// workgroups do not overlap.
+__global__ __launch_bounds__(256) void k_ref_skew(const Prob* __restrict__ probs, int sweep) {
+  __shared__ double t[64][65];
+  const Prob& P = probs[blockIdx.z];
+  if (finished_before(P, sweep)) return;   // uniform
+  const long N = P.N, ld = P.ld;
+  const int I = blockIdx.x, J = blockIdx.y;
+  const long r0 = (long)I * 64, c0 = (long)J * 64;
+  if (J > I || r0 >= N) return;   // uniform
+  BSE_GLOBAL double* __restrict__ C = gbl(P.R2);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // t[i][j] = C[c0 + j, r0 + i], the partner of C[r0 + i, c0 + j]
+  for (int i = wv; i < 64; i += 4) {
+    const long col = r0 + i, row = c0 + lane;
+    t[i][lane] = (col < N && row < N) ? C[row + col * ld] : 0.0;
+  }
+  __syncthreads();
+  const long row = r0 + lane;
+  if (row >= N) return;
+  for (int j = wv; j < 64; j += 4) {
+    const long col = c0 + j;
+    if (col > row || col >= N) continue;
+    BSE_GLOBAL double* e = C + row + col * ld;
+    *e = *e - t[lane][j];
+  }
+}
+
 // entry (i, j) of the full matrices from their stored lower triangles
 __device__ inline double skew_at(const BSE_GLOBAL double* S, long ld, long i, long j) {
   return (i >= j) ? S[i + j * ld] : -S[j + i * ld];
@@ -118,7 +152,7 @@ __device__ inline double sym_at(const BSE_GLOBAL double* G, long ld, long i, lon
   return (i >= j) ? G[i + j * ld] : G[j + i * ld];
 }
 
-// F and a copy of Ub, both rounded to FP32, into R1 (P = W Ub is no longer
+// F and a copy of Ub, both rounded to FP32, into R1 (Y = L Ub is no longer
 // needed): the basis update Ub + Ub F takes its correction product in FP32,
 // which perturbs Ub by about 1e-7 of the correction (far below the error the
 // sweep leaves).  Also per-tile maxima of the correction and the number of
@@ -689,9 +723,14 @@ int refine_batched(hipStream_t s, const Batch& b, const RefineIO& io, RefineStat
   BSE_LAUNCH(k_ref_scale, grid_NN(b), 256, 0, s, b.dev, 1.41421356237309504880);
   int sweeps = 0;
   for (int sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
-    BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_P, sweep));
-    BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_PB, sweep));
-    BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_S, sweep));
+    // S = Ub^T W Ub through Y = L Ub (W = L^T J L): 2 N^3 flops where the
+    // product with W and then with Ub^T took 2.5 N^3
+    BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_Y, sweep));
+    BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_C, sweep));
+    {
+      const unsigned nt = (unsigned)((b.maxN() + 63) / 64);
+      BSE_LAUNCH(k_ref_skew, dim3(nt, nt, (unsigned)b.count), 256, 0, s, b.dev, sweep);
+    }
     BSE_TRY(gemm_batched(s, b, b.count, GOP_REF_G, sweep));
     BSE_LAUNCH(k_ref_lambda, dim3((unsigned)((n0 + 63) / 64), 1, (unsigned)b.count), 64, 0, s, b.dev, sweep);
     BSE_LAUNCH(k_ref_clusters, dim3(1, 1, (unsigned)b.count), 1024, 0, s, b.dev, sweep);
