@@ -305,9 +305,9 @@ static const int kStageOrder[BSE_NUM_STAGES] = {
 // eigensolve and the back-transformation, for the live problems of b.
 static int chain_tail(hipStream_t s, Lane* L, const Setup& S, const Batch& b, bool vectors, bool mixed, bool two,
                       bool timed, int& ev, KernelTimer* ktimer, RefineStats* rstats) {
-  // the mixed path keeps the full FP64 W for the refinement and reduces an
-  // FP32 copy of its lower triangle
-  BSE_TRY(form_W_batched(s, b, mixed));
+  // the reduction reads W's lower triangle (the mixed path an FP32 copy of
+  // it; its refinement works from L, W = L^T J L)
+  BSE_TRY(form_W_batched(s, b, false));
   // the two-stage reduction keeps W as its strict lower triangle over a zero
   // upper triangle
   if (two) BSE_TRY(zero_upper(s, L->hprobs[0].N, L->hprobs[0].W, L->hprobs[0].ld));
