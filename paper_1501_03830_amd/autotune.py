@@ -5,10 +5,10 @@ type; bse_set_tile_table).
     python -m paper_1501_03830_amd.autotune [--out tuning.json] [--quick]
 
 Coordinate descent over the table's tile counts, on the workloads they
-decide: the small-size buckets on the batched workload (256 problems, n
-log-uniform in [64, 1024], FP64 and FP32 + refinement), the large-size
-buckets on single n = 8192 solves (FP64 and FP32 + refinement; the
-reduction's own time).  Each candidate is timed as the median device time
+decide: the bottom bucket (below 33 row blocks, every problem of the batched
+workload) on that workload (256 problems, n log-uniform in [64, 1024], FP64
+and FP32 + refinement), the four buckets above it on single n = 8192 solves
+(FP64 and FP32 + refinement; the reduction's own time).  Each candidate is timed as the median device time
 of a few calls after a warm-up; a bucket keeps its current count unless a
 candidate is at least 1% faster.  The chosen table, the device and every
 measurement are written to the output (JSON), which the Python binding
@@ -31,8 +31,8 @@ ROOT = os.path.dirname(HERE)
 DEFAULT_OUT = os.path.join(HERE, "tuning.json")
 
 # bucket layout of a table row: [t0 t1 t2 t3 v0 v1 v2 v3 v4]
-SMALL_SPLIT = 24      # t3: batched problems (n <= 1024) have nblk <= 32
-CANDIDATES = {"small": [2, 3, 4, 6, 8], "large": [8, 12, 16]}
+SMALL_SPLIT = 33      # t3: batched problems (n <= 1024) have nblk <= 32
+CANDIDATES = {"small": [2, 3, 4, 6, 8], "mid": [3, 4, 6, 8], "large": [8, 12, 16]}
 
 
 def get_table(lib):
@@ -127,9 +127,10 @@ def main():
 
     log = []
     precs = [("fp64", _lib.BSE_PREC_FP64, 0), ("fp32_refine", _lib.BSE_PREC_FP32_REFINE, 1)]
-    # small buckets: v4 (nblk < t3), v3 (t3 <= nblk < t2), on the batched workload
+    # the bottom bucket v4 (nblk < t3: every batched problem) on the batched
+    # workload
     for name, prec, row in precs:
-        for slot in (8, 7):
+        for slot in (8,):
             if not bucket_used(table[row], slot):
                 continue
             best_v = table[row][slot]
@@ -148,17 +149,18 @@ def main():
                 if ms < 0.99 * best_ms:
                     best_ms, best_v = ms, v
             table[row][slot] = best_v
-    # large buckets: v0 .. v2 on single n = 8192 solves (the reduction)
+    # v0 .. v3 on single n = 8192 solves (the reduction): trailing orders
+    # from 16384 down to about 2100
     if big is not None:
         for name, prec, row in precs:
-            for slot in (4, 5, 6):
+            for slot in (4, 5, 6, 7):
                 if not bucket_used(table[row], slot):
                     continue
                 best_v = table[row][slot]
                 set_table(lib, ctx, table)
                 best_ms = time_single(prec)
                 log.append({"workload": "n8192", "prec": name, "slot": slot, "tiles": best_v, "ms": best_ms})
-                for v in CANDIDATES["large"]:
+                for v in CANDIDATES["mid" if slot == 7 else "large"]:
                     if v == table[row][slot]:
                         continue
                     trial = [r[:] for r in table]
