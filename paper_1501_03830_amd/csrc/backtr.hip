@@ -375,7 +375,7 @@ int apply_UD_batched(hipStream_t s, const Batch& b) {
     BSE_TRY(gemm_batched(s, b, nact, GOP_APPLYU_S, q));
     BSE_TRY(gemm_batched(s, b, nact, GOP_APPLYU_W1, q));
     for (int h = NBQ / 64 - 1; h >= 0; --h) {
-      if (h < NBQ / 64 - 1) BSE_TRY(gemm_batched(s, b, nact, GOP_APPLYU_WB, 4 * q + h));
+      if (h < NBQ / 64 - 1) BSE_TRY(gemm_batched(s, b, nact, GOP_APPLYU_WB, APPLYU_SUB * q + h));
       BSE_TRY(wy_solve_batched(s, b, nact, q, h));
     }
     BSE_TRY(gemm_batched(s, b, nact, GOP_APPLYU_Z, q));

@@ -146,10 +146,10 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
     case GOP_APPLYU_WB:
     case GOP_APPLYU_Z: {
       // reflector block q of RB (H_j0 .. H_j0+nbk-1, j0 = RB q); the block
-      // solve's products carry their sub-block h in step = 4 q + h
+      // solve's products carry their sub-block h in step = APPLYU_SUB q + h
       constexpr int RB = APPLYU_RB;
-      const int q = (op == GOP_APPLYU_WB) ? step / 4 : step;
-      const int h = (op == GOP_APPLYU_WB) ? step % 4 : 0;
+      const int q = (op == GOP_APPLYU_WB) ? step / APPLYU_SUB : step;
+      const int h = (op == GOP_APPLYU_WB) ? step % APPLYU_SUB : 0;
       const int nrefl = P.N - 2;
       const int j0 = q * RB;
       if (nrefl <= 0 || j0 >= nrefl) break;

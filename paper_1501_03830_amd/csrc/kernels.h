@@ -59,6 +59,7 @@ struct GemmParams {
 // Reflectors per block of the back-transformation with U (four 64-row
 // sub-blocks of the compact-WY factor).
 constexpr int APPLYU_RB = 256;
+constexpr int APPLYU_SUB = APPLYU_RB / 64;   // 64-row sub-blocks per reflector block
 
 // Columns per panel of the skew tridiagonalisation (the batch header keeps
 // the workgroup prefixes of a whole panel).
@@ -79,7 +80,7 @@ enum GemmOp {
   GOP_GRAM_UPD_PANEL,  // forward substitution: second half of the block at `step`
   GOP_APPLYU_S,    // V^T V of reflector block `step`
   GOP_APPLYU_W1,   // V^T Z
-  GOP_APPLYU_WB,   // block solve with T^{-1}: sub-block h -= S_h,>h (later rows); step 4q + h
+  GOP_APPLYU_WB,   // block solve with T^{-1}: sub-block h -= S_h,>h (later rows); step APPLYU_SUB q + h
   GOP_APPLYU_Z,    // Z -= V (T V^T Z)
   GOP_APPLY_L,     // G = L Z
   GOP_REF_Y,       // refinement: Y = L Ub (basis Ub of sweep `step`; L lower triangular)

@@ -153,11 +153,12 @@ __global__ __launch_bounds__(NB) void k_trsm_cols(const Prob* __restrict__ probs
     if (FULL || i < nbk) v[i] = x[i];
 }
 
-// Compact-WY factor of reflector block q (RB = 256 reflectors):
+// Compact-WY factor of reflector block q (RB = APPLYU_RB reflectors):
 // T^{-1} = diag(1/tau) + strict_upper(S), S = V^T V, is block upper
 // triangular in 64 x 64 blocks, so W2 = T W1 is a block back substitution:
-// for h = 3 .. 0, rows h of W1 minus S[h, h+1:] W2[h+1:] (a GEMM, skipped
-// for h = 3), then the solve with the diagonal block (this kernel).  A
+// for h = RB/64 - 1 .. 0, rows h of W1 minus S[h, h+1:] W2[h+1:] (a GEMM,
+// skipped for the last h), then the solve with the diagonal block (this
+// kernel).  A
 // reflector with tau = 0 is the identity: its row of W2 is zero (its
 // right-hand side is set to zero and its row and column of the block are
 // left out).
