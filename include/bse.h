@@ -65,9 +65,12 @@ extern "C" {
 /* precision policies */
 #define BSE_PREC_FP64 0        /* every stage in FP64                          */
 #define BSE_PREC_FP32_REFINE 1 /* W stored and reduced in FP32 (FP64 sums and
-                                  norms), FP64 tridiagonal solve and
-                                  back-transform, then FP64 refinement of the
-                                  eigenpairs against the FP64 W.  A call that
+                                  norms, rank-2k updates on the FP32 matrix
+                                  cores), FP64 tridiagonal solve, U applied
+                                  on the FP32 matrix cores, then FP64
+                                  refinement of the eigenpairs against
+                                  W = L^T J L through the FP64 Cholesky
+                                  factor L.  A call that
                                   wants eigenvalues only (no
                                   BSE_WANT_VECTORS) runs the FP64 path: the
                                   refinement needs the eigenvector basis, and
@@ -122,7 +125,8 @@ typedef struct bse_request {
   const void* B;         /* complex n x n, lower triangle read                */
   int ldb;               /* >= n                                              */
   int prec;              /* BSE_PREC_FP64 or BSE_PREC_FP32_REFINE             */
-  unsigned flags;        /* BSE_WANT_VECTORS | BSE_WANT_WEIGHTS               */
+  unsigned flags;        /* BSE_WANT_VECTORS | BSE_WANT_WEIGHTS |
+                            BSE_EIGVEC_TWISTED                               */
   double* lambda;        /* out: n doubles                                    */
   void* X;               /* out: complex 2n x n or NULL without vectors       */
   int ldx;               /* >= 2n with vectors                                */
@@ -234,9 +238,10 @@ size_t bse_footprint_bytes(int n, int prec, unsigned flags);
  *   A, lda   complex n x n, lda >= n, lower triangle read (3, 4)
  *   B, ldb   complex n x n, ldb >= n, lower triangle read (5, 6)
  *   prec     BSE_PREC_FP64, or BSE_PREC_FP32_REFINE: W is reduced to
- *            tridiagonal form in FP32 storage (FP64 sums and norms), the
- *            tridiagonal eigensolve and the back-transformation run in FP64,
- *            then the eigenpairs are refined in FP64 against the FP64 W by
+ *            tridiagonal form in FP32 storage (FP64 sums and norms, FP32
+ *            matrix-core rank-2k updates), the tridiagonal eigensolve runs in
+ *            FP64 and U is applied on the FP32 matrix cores, then the
+ *            eigenpairs are refined in FP64 against W = L^T J L by
  *            sweeps of an Ogita-Aishima-type iteration on the real Schur
  *            form of W (not in the paper), until the largest correction is
  *            below 1e-2 with no pair left out (at most 6 sweeps; pairs closer
@@ -246,7 +251,8 @@ size_t bse_footprint_bytes(int n, int prec, unsigned flags);
  *            3.5e-5 x correction^4 relative, i.e. below 4e-13; eigenvector
  *            error about correction^2).  Returns BSE_ENOCONV when the sweep
  *            limit is reached first (7)
- *   flags    BSE_WANT_VECTORS | BSE_WANT_WEIGHTS (8)
+ *   flags    BSE_WANT_VECTORS | BSE_WANT_WEIGHTS | BSE_TWO_STAGE |
+ *            BSE_EIGVEC_TWISTED (8)
  *   lambda   out: n doubles, the positive eigenvalues ascending (9)
  *   X, ldx   out: complex 2n x n, ldx >= 2n; rows 0..n-1 hold X1, rows
  *            n..2n-1 hold X2; each column is scaled by a unit phase so that
@@ -341,7 +347,7 @@ size_t bse_footprint_batched_bytes(int count, const int* n, int prec, unsigned f
  *   n, A, lda, B, ldb   per problem, as in bse_solve (3, 4, 5, 6, 7)
  *   prec       BSE_PREC_FP64 or BSE_PREC_FP32_REFINE (as in bse_solve),
  *              shared (8)
- *   flags      BSE_WANT_VECTORS | BSE_WANT_WEIGHTS, shared (9)
+ *   flags      BSE_WANT_VECTORS | BSE_WANT_WEIGHTS | BSE_EIGVEC_TWISTED, shared (9)
  *   lambda     out: lambda[i] -> n[i] doubles, ascending (10)
  *   X, ldx     out: X[i] -> complex 2n[i] x n[i], ldx[i] >= 2 n[i], laid out
  *              and phased as in bse_solve; both arrays may be NULL without
