@@ -308,7 +308,7 @@ def serving_bench(big_inputs, count: int = 200, lo: int = 128, hi: int = 2048, b
 
 def serving_full(count: int = 2000, lo: int = 128, hi: int = 4096, big: int = 16384, big_frac: float = 0.02,
                  seed: int = 5, load: float = 0.7, calib: int = 200, pool_gib: int = 160, slots: int = 4,
-                 max_batch: int = 64, max_span_s: float = 780.0):
+                 max_batch: int = 64, max_span_s: float = 780.0, qps: float | None = None):
     """The serving workload as stated: a Poisson stream of `count` requests,
     n log-uniform in [lo, hi] with probability 1 - big_frac, else n = big
     (stream seed `seed`).  Requests of order <= hi are drawn on the device at
@@ -317,7 +317,8 @@ def serving_full(count: int = 2000, lo: int = 128, hi: int = 4096, big: int = 16
     saturation rate is measured closed-loop on the first `calib` requests of
     the stream; the timed run replays all `count` arrivals at `load` x that
     rate (open loop; the rate is raised if needed so that the arrivals span
-    at most max_span_s).  Every result is checked: the n = big eigenvalues
+    at most max_span_s).  A given `qps` replaces the calibration and the
+    span limit.  Every result is checked: the n = big eigenvalues
     against the closed form, every other request by the residual
     ||H x_j - lambda_j x_j|| / (lambda_max ||x_j||) of all its eigenpairs
     (computed on the device after completion, outside the latency)."""
@@ -397,20 +398,22 @@ def serving_full(count: int = 2000, lo: int = 128, hi: int = 4096, big: int = 16
         return span, np.array(lat), stats, worst
 
     cidx = list(range(min(calib, count)))
-    span1, _, _, _ = run([0.0] * len(cidx), cidx, False)
-    sat = len(cidx) / span1
-    qps = max(load * sat, count / max_span_s)
+    sat = None
+    if qps is None:
+        span1, _, _, _ = run([0.0] * len(cidx), cidx, False)
+        sat = len(cidx) / span1
+        qps = max(load * sat, count / max_span_s)
     arrivals, _ = serving_stream(count, qps, lo, hi, big, big_frac, seed)
     arrivals = [float(x) - float(arrivals[0]) for x in arrivals]
-    print(f"# serving (full): calibration {sat:.3f} solves/s on {len(cidx)} requests; open loop at "
+    print(f"# serving (full): calibration {sat} solves/s on {len(cidx)} requests; open loop at "
           f"{qps:.3f} req/s", file=sys.stderr, flush=True)
     span2, lat, st2, worst = run(arrivals, list(range(count)), True)
     return {
         "workload": f"{count} requests, Poisson arrivals, n log-uniform in [{lo},{hi}] w.p. {1 - big_frac:.2f} else "
                     f"n={big} (stream seed {seed}; n<= {hi} drawn on the device from seed 100000+i, n={big} the "
                     f"closed-form problem), FP64, eigenvalues + eigenvectors + weights",
-        "calibration": {"requests": len(cidx), "solves_per_s": round(sat, 3)},
-        "load": load, "qps": round(qps, 3), "slots": slots, "max_batch": max_batch, "pool_gib": pool_gib,
+        "calibration": None if sat is None else {"requests": len(cidx), "solves_per_s": round(sat, 3)},
+        "load": load if sat is not None else None, "qps": round(qps, 3), "slots": slots, "max_batch": max_batch, "pool_gib": pool_gib,
         "solves_per_s": round(count / span2, 3), "makespan_s": round(span2, 1),
         "p50_ms": round(float(np.percentile(lat, 50)), 1), "p99_ms": round(float(np.percentile(lat, 99)), 1),
         "max_ms": round(float(lat.max()), 1),
@@ -550,6 +553,7 @@ def main():
     ap.add_argument("--sf-hi", type=int, default=4096)
     ap.add_argument("--sf-big", type=int, default=16384)
     ap.add_argument("--sf-calib", type=int, default=200)
+    ap.add_argument("--sf-qps", type=float, default=None, help="arrival rate (skips the calibration)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     a = ap.parse_args()
@@ -564,7 +568,7 @@ def main():
         return
     if a.serving_full:
         print(json.dumps({"serving_full": serving_full(count=a.sf_count, hi=a.sf_hi, big=a.sf_big,
-                                                       calib=a.sf_calib)}), flush=True)
+                                                       calib=a.sf_calib, qps=a.sf_qps)}), flush=True)
         return
 
     import torch
