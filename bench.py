@@ -493,8 +493,10 @@ def mixed_bench(ctx, n, Ac, Bc, drb, lam64, X64, steps: int, warmup: int):
 def closed_form_check(ctx, n: int, seed: int = 30):
     """Exact-eigenvalue check at the benchmark size: the closed-form
     generator (A = U0 diag(a) U0^H, B = U0 diag(b) U0^T, eigenvalues
-    sqrt(a_k^2 - |b_k|^2)), solved by both paths, eigenvalues only.  Errors
-    are max |lambda - lambda_exact| relative to lambda_max (at most ||H||_2)."""
+    sqrt(a_k^2 - |b_k|^2)), solved by the one-stage and the two-stage
+    reduction, eigenvalues only; and a real closed-form problem through
+    Algorithm 2 with eigenvectors.  Errors are max |lambda - lambda_exact|
+    relative to lambda_max (at most ||H||_2)."""
     import torch
     from bse_inputs import gen_closed_form
     from paper_1501_03830_amd import _lib
@@ -517,6 +519,19 @@ def closed_form_check(ctx, n: int, seed: int = 30):
         assert info == 0, info
         out[key] = {"max_rel_eig_err": float((lam - exact).abs().max()) / lmax,
                     "device_ms": round(rep["total_ms"], 2), "sktrd_ms": round(rep["stage_ms"]["sktrd"], 2)}
+    # Algorithm 2 (real A, B) on a real closed-form problem of the same order,
+    # with eigenvectors
+    from bse_inputs import gen_real_closed_form
+    pr = gen_real_closed_form(n, seed=41)
+    exact_r = torch.from_numpy(np.asarray(pr.exact_lambda)).to(dev)
+    res = ctx.solve_real(torch.from_numpy(pr.A.real.copy()), torch.from_numpy(pr.B.real.copy()),
+                         vectors=True, report=True)
+    assert res["info"] == 0, res["info"]
+    out["real_fp64"] = {"workload": f"real closed-form generator n={n} (seed 41), bse_solve_real, eigenvalues "
+                                    f"+ eigenvectors",
+                        "max_rel_eig_err": float((res["lam"] - exact_r).abs().max() / exact_r.max()),
+                        "device_ms": round(res["report"]["total_ms"], 2)}
+    del pr, res
     print(f"# closed form n={n}: {out} ({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
     return out
 
