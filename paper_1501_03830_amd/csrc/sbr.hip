@@ -13,9 +13,10 @@
 // zero), so W22 V = L V - L^T V is two triangular MFMA products and the
 // rank-2B update touches the strict lower triangle only.
 //
-// The panel factorisation is one launch per column.  Launch j finishes the
-// reflector of column j - 1 from the previous launch's per-workgroup partial
-// sums (every workgroup reduces them in the same order): with x that column
+// The panel factorisation is one launch per panel, its column steps
+// separated by a grid barrier.  Step j finishes the reflector of column
+// j - 1 from the previous step's per-workgroup partial sums (every
+// workgroup reduces them in the same order): with x that column
 // below its diagonal, x^T x and x^T a_c for the columns c to its right were
 // summed in one pass, so beta, tau and every tau v^T a_c follow without a
 // second reduction (v = (x - beta e_1) / (x_0 - beta)); it then applies the
@@ -86,24 +87,35 @@ __device__ inline double* panel_part(const Prob& P) { return P.Yrow; }
 // its partial sums for column j: x^T x and x^T a_c for the columns c to the
 // right, from which beta, tau and every tau v^T a_c follow without a second
 // reduction (v = (x - beta e_1) / (x_0 - beta)).  Steps are separated by a
-// grid barrier: an arrival counter (release increments, acquire loads) with
-// a bounded wait; a workgroup that runs out of it raises the error flag,
-// which ends every other wait, so all workgroups exit.  The grid (at most
-// PMAX_WG workgroups) is far below what the device holds at once.
-__device__ inline bool grid_wait(int* counter, int target, int* err) {
+// grid barrier made of one flag word per workgroup: a workgroup publishes
+// its sums, then stores the number of the step it finished into its own
+// flag (release); the next step waits until every flag has reached it, read
+// by wave 0 with one load per flag in a single round trip (relaxed loads,
+// then an acquire fence).  One word per writer avoids the serialised
+// read-modify-writes of a shared arrival counter.  The wait is bounded; a
+// workgroup that runs out of it raises the error flag, which ends every
+// other wait, so all workgroups exit.  The grid (at most PMAX_WG
+// workgroups) is far below what the device holds at once.
+__device__ inline bool flags_wait(const int* flags, int nwg, int target, int* err) {
+  const int lane = threadIdx.x & 63;
   long spins = 0;
-  while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+  for (;;) {
+    int lo = INT_MAX;
+    for (int q = lane; q < nwg; q += 64)
+      lo = min(lo, __hip_atomic_load(flags + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (__all(lo >= target)) break;
     if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > SPIN_MAX) {
-      __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (lane == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return false;
     }
     __builtin_amdgcn_s_sleep(1);
   }
-  (void)__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+  // pairs with every flag's release store: their workgroups' sums are visible
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return true;
 }
 
-__global__ __launch_bounds__(PR) void k_sbr_panel(const Prob* __restrict__ probs, int k0, int* __restrict__ counter,
+__global__ __launch_bounds__(PR) void k_sbr_panel(const Prob* __restrict__ probs, int k0, int* __restrict__ flags,
                                                   int* __restrict__ err) {
   __shared__ double tot[PP];
   __shared__ double wv[BW];
@@ -129,7 +141,10 @@ __global__ __launch_bounds__(PR) void k_sbr_panel(const Prob* __restrict__ probs
   for (int j = 0; j <= nr; ++j) {
     if (j >= 1) {
       // wait for every workgroup's partial sums of column j - 1
-      if (threadIdx.x == 0) ok_flag = grid_wait(counter, nwg * j, err) ? 1 : 0;
+      if (threadIdx.x < 64) {
+        const bool ok = flags_wait(flags, nwg, j, err);
+        if (threadIdx.x == 0) ok_flag = ok ? 1 : 0;
+      }
       __syncthreads();
       if (!ok_flag) return;
       const int c0 = j - 1;
@@ -223,9 +238,9 @@ __global__ __launch_bounds__(PR) void k_sbr_panel(const Prob* __restrict__ probs
         for (int c = 0; c < BW; ++c)
           if (c >= j) rb[c] = a[c];
       }
-      // arrive: this workgroup's sums are published
+      // arrive: this workgroup's sums of column j are published
       __syncthreads();
-      if (threadIdx.x == 0) __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (threadIdx.x == 0) __hip_atomic_store(flags + g, j + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
   if (in) {
@@ -234,13 +249,12 @@ __global__ __launch_bounds__(PR) void k_sbr_panel(const Prob* __restrict__ probs
   }
 }
 
-// arrival counter of the panel launch to zero (and the panels' error flag,
-// before the first panel)
-__global__ void k_sbr_panel_reset(int* __restrict__ counter, int* __restrict__ err, int first) {
-  if (threadIdx.x == 0) {
-    *counter = 0;
-    if (first) *err = 0;
-  }
+// Flags of the panel launch to zero (and the panels' error flag, before the
+// first panel)
+__global__ void k_sbr_panel_reset(int* __restrict__ flags, int* __restrict__ err) {
+  if (flags)
+    for (int q = threadIdx.x; q < PMAX_WG; q += blockDim.x) flags[q] = 0;
+  if (err && threadIdx.x == 0) *err = 0;
 }
 
 // Explicit reflectors of the panel at k0 (ones on the diagonal, zeros
@@ -338,9 +352,9 @@ __device__ inline int load_progress(const int* p) {
 // The band is shared between the workgroups of consecutive sweeps, so the
 // chase reads and writes it with relaxed atomic accesses at agent scope
 // (coherent across the device's L2 caches without whole-cache write-backs);
-// ordering comes from one release store and one acquire load of the
-// progress words per step, made by one thread on either side of a
-// workgroup barrier.
+// ordering comes from one release store of the progress word per step and,
+// on the waiting side, an acquire fence after the relaxed load that saw it,
+// made by one thread on either side of a workgroup barrier.
 __device__ inline double ld_band(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -390,8 +404,10 @@ __global__ __launch_bounds__(256) void k_sbr_chase(const Prob* __restrict__ prob
             __builtin_amdgcn_s_sleep(1);
           }
           if (!ok) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          // acquire: the predecessor's band writes happen before this step
-          else (void)__hip_atomic_load(prog + s - 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+          // acquire fence after the relaxed load that saw the predecessor's
+          // release store: its band writes happen before this step (a fence,
+          // not a second acquire load: one memory round trip less per step)
+          else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
           abort_flag = !ok;
         }
         __syncthreads();
@@ -519,9 +535,14 @@ int sbr_single(hipStream_t s, const Batch& b, int* work) {
   const Prob& P = b.host[0];
   const int N = P.N;
   if (N < 2) return 0;
-  // the panel's error word is read after the chase whether or not a panel
-  // ran (orders up to BW + 1 have none), so it is cleared first
-  BSE_LAUNCH(k_sbr_panel_reset, dim3(1), dim3(64), 0, s, work + N + 1, work + N + 2, 1);
+  // work (P.Ycol, ld * ld / 32 ints): progress words [N], the chase's error
+  // word, the panels' error word at N + 2, the panel flags from N + 4.  The
+  // panels' error word is read after the chase whether or not a panel ran
+  // (orders up to BW + 1 have none), so it is cleared first.
+  int* flags = work + N + 4;
+  if (N - BW >= 2 && (long)N + 4 + PMAX_WG > P.ld * P.ld / 32)
+    return set_error(BSE_EUNSUPPORTED, "two-stage reduction: work area too small");
+  BSE_LAUNCH(k_sbr_panel_reset, dim3(1), dim3(64), 0, s, nullptr, work + N + 2);
   for (int k0 = 0;; k0 += BW) {
     const int r0 = k0 + BW;
     const int m = N - r0;
@@ -529,8 +550,8 @@ int sbr_single(hipStream_t s, const Batch& b, int* work) {
     const int nr = m - 1 < BW ? m - 1 : BW;
     const unsigned nwg = (unsigned)((m + PR - 1) / PR);
     if (nwg > (unsigned)PMAX_WG) return set_error(BSE_EUNSUPPORTED, "two-stage reduction: order too large");
-    if (k0 > 0) BSE_LAUNCH(k_sbr_panel_reset, dim3(1), dim3(64), 0, s, work + N + 1, work + N + 2, 0);
-    BSE_LAUNCH(k_sbr_panel, dim3(nwg), dim3(PR), 0, s, b.dev, k0, work + N + 1, work + N + 2);
+    BSE_LAUNCH(k_sbr_panel_reset, dim3(1), dim3(PMAX_WG), 0, s, flags, nullptr);
+    BSE_LAUNCH(k_sbr_panel, dim3(nwg), dim3(PR), 0, s, b.dev, k0, flags, work + N + 2);
     BSE_LAUNCH(k_sbr_extract, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, b.dev, k0);
     BSE_TRY(gemm_batched(s, b, 1, GOP_SBR_X, k0));
     BSE_TRY(gemm_batched(s, b, 1, GOP_SBR_XT, k0));
