@@ -83,8 +83,10 @@ extern "C" {
 #define BSE_TWO_STAGE 4u       /* reduce W to tridiagonal form in two stages
                                   (dense to band on the matrix cores, then
                                   bulge chasing; Section 3.3's successive band
-                                  reduction); eigenvalues only, FP64, single
-                                  problems (bse_solve, bse_solve_tda)          */
+                                  reduction); eigenvectors go back through
+                                  both stages' reflectors.  FP64, single
+                                  problems (bse_solve, bse_solve_tda,
+                                  bse_solve_real)                             */
 #define BSE_EIGVEC_TWISTED 8u  /* eigenvectors of the tridiagonal T_s by
                                   twisted factorisations (the per-vector step
                                   of MRRR, Section 3.3) instead of inverse

@@ -126,7 +126,7 @@ class Context:
         }
 
     def solve_real(self, A: torch.Tensor, B: torch.Tensor, d_r: torch.Tensor | None = None, vectors: bool = True,
-                   report: bool = False, prec: int = _lib.BSE_PREC_FP64):
+                   report: bool = False, prec: int = _lib.BSE_PREC_FP64, extra_flags: int = 0):
         """Real problem (Algorithm 2): A, B real (n, n) (lower triangles
         used).  Returns dict with lam (n,), X real (2n, n) or None, w (n,)
         complex or None, info, report."""
@@ -144,6 +144,7 @@ class Context:
             flags |= _lib.BSE_WANT_WEIGHTS
             drb = d_r.to(dev, torch.complex128).contiguous()
             w = torch.empty(n, dtype=torch.complex128, device=dev)
+        flags |= extra_flags
         rep = _lib.BseReport() if report else None
         info = _lib.check(self.lib.bse_solve_real(
             self.h, n, _ptr(Ac), n, _ptr(Bc), n, prec, flags, _ptr(lam), _ptr(Xbuf), 2 * n, _ptr(drb), None,

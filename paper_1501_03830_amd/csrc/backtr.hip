@@ -64,14 +64,17 @@ __global__ __launch_bounds__(256) void k_scatter_DV(const Prob* __restrict__ pro
   }
 }
 
-// Explicit reflector block q: Vb[r, l] for rows r in [j0+1, N), j0 = 256 q:
-//   0 above row j0+l+1, 1 at row j0+l+1, W[r, j0+l] below (and its FP32 copy
+// Explicit reflector block q: Vb[r, l] for rows r in [j0+o, N), j0 = 256 q,
+// o = refl_off(P) (1 after the one-stage reduction, the band width after the
+// two-stage one, whose first stage stores reflector k below the band):
+//   0 above row j0+l+o, 1 at row j0+l+o, W[r, j0+l] below (and its FP32 copy
 //   Vb32 in the mixed-precision path, whose products with the FP32 basis run
 //   on the FP32 matrix cores).
 __global__ __launch_bounds__(256) void k_extract_V(const Prob* __restrict__ probs, int q) {
   const Prob& P = probs[blockIdx.z];
   const int N = P.N;
-  const int nrefl = N - 2;
+  const int o = refl_off(P);
+  const int nrefl = N - 1 - o;
   const int j0 = q * NBQ;
   if (j0 >= nrefl) return;  // uniform
   const int nbk = min(NBQ, nrefl - j0);
@@ -81,10 +84,10 @@ __global__ __launch_bounds__(256) void k_extract_V(const Prob* __restrict__ prob
   BSE_GLOBAL double* __restrict__ Vb = gbl(P.Vb);
   BSE_GLOBAL float* __restrict__ Vb32 = gbl(P.Vb32);
   const long ldw = P.ld, ldv = P.ld;
-  const long r = (long)j0 + 1 + (long)blockIdx.x * 64 + (threadIdx.x & 63);
+  const long r = (long)j0 + o + (long)blockIdx.x * 64 + (threadIdx.x & 63);
   if (r >= N) return;
   for (int l = threadIdx.x >> 6; l < nbk; l += 4) {
-    const long diag = (long)j0 + l + 1;
+    const long diag = (long)j0 + l + o;
     double v;
     if (r < diag) v = 0.0;
     else if (r == diag) v = 1.0;
@@ -363,14 +366,19 @@ int apply_UD_batched(hipStream_t s, const Batch& b) {
   const int N0 = b.maxN(), n0 = b.maxn();
   // Z = [Re(D V_+) | Im(D V_+)]
   BSE_LAUNCH(k_scatter_DV, dim3((unsigned)((N0 + 63) / 64), (unsigned)((n0 + 63) / 64), (unsigned)b.count), 256, 0, s, b.dev);
-  // Z <- U Z with U = H_0 ... H_{N-3}, last block of reflectors first
-  const int nrefl0 = N0 - 2;   // H_{N-2} is the identity
+  // after the two-stage reduction (a batch of one): Z <- Q2 Z for the
+  // chase's reflectors, then the band reduction's below as U
+  const int o = refl_off(b.host[0]);
+  if (o > 1) BSE_TRY(sbr_q2_apply(s, b));
+  // Z <- U Z with U = H_0 ... H_{N-2-o}, last block of reflectors first (the
+  // one-stage H_{N-2} is the identity)
+  const int nrefl0 = N0 - 1 - o;
   if (nrefl0 <= 0) return 0;
   const int nblocks0 = (nrefl0 + NBQ - 1) / NBQ;
   for (int q = nblocks0 - 1; q >= 0; --q) {
     const int j0 = q * NBQ;
-    const int nact = b.active_N_above(j0 + 2);   // N - 2 > j0
-    const int m0 = N0 - j0 - 1;
+    const int nact = b.active_N_above(j0 + 1 + o);   // N - 1 - o > j0
+    const int m0 = N0 - j0 - o;
     BSE_LAUNCH(k_extract_V, dim3((unsigned)((m0 + 63) / 64), 1, (unsigned)nact), 256, 0, s, b.dev, q);
     BSE_TRY(gemm_batched(s, b, nact, GOP_APPLYU_S, q));
     BSE_TRY(gemm_batched(s, b, nact, GOP_APPLYU_W1, q));

@@ -100,6 +100,8 @@ struct Prob {
   const double* dl;
   double* w;            // complex n weights (output) or null
   unsigned flags;
+  int uoff;             // reflector k of the back-transformation acts on rows k + uoff ..:
+                        // SBR_B after the two-stage reduction, 1 (or 0) after the one-stage one
   // workspace
   double *L, *W, *Z, *Vt, *inv, *alpha, *tau, *e2, *scal, *shift, *gscr;
   size_t gscr_bytes;

@@ -150,13 +150,14 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
       constexpr int RB = APPLYU_RB;
       const int q = (op == GOP_APPLYU_WB) ? step / APPLYU_SUB : step;
       const int h = (op == GOP_APPLYU_WB) ? step % APPLYU_SUB : 0;
-      const int nrefl = P.N - 2;
+      const int o = refl_off(P);   // reflector k acts on rows k + o ..
+      const int nrefl = P.N - 1 - o;
       const int j0 = q * RB;
       if (nrefl <= 0 || j0 >= nrefl) break;
       const int nbk = (nrefl - j0 < RB) ? nrefl - j0 : RB;
-      const int m = P.N - j0 - 1;
-      const double* Vb = P.Vb + (j0 + 1);
-      double* Zs = P.Z + (j0 + 1);
+      const int m = P.N - j0 - o;
+      const double* Vb = P.Vb + (j0 + o);
+      double* Zs = P.Z + (j0 + o);
       if (op == GOP_APPLYU_S) {         // S = V^T V
         g.ta = 1; g.tb = 0; g.M = nbk; g.N = nbk; g.K = m;
         g.A = Vb; g.lda = ld; g.B = Vb; g.ldb = ld; g.C = P.S; g.ldc = RB;
@@ -164,7 +165,7 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
         g.ta = 1; g.tb = 0; g.M = nbk; g.N = P.N; g.K = m;
         g.A = Vb; g.lda = ld; g.B = Zs; g.ldb = ld; g.C = P.W1; g.ldc = RB;
         if (P.prec == BSE_PREC_FP32_REFINE) {   // FP32 basis, FP32 matrix cores
-          g.f32 = 1; g.Af = P.Vb32 + (j0 + 1); g.Bf = P.Z32 + (j0 + 1);
+          g.f32 = 1; g.Af = P.Vb32 + (j0 + o); g.Bf = P.Z32 + (j0 + o);
         }
       } else if (op == GOP_APPLYU_WB) {  // W1[h] -= S[h, h+1:] W2[h+1:] (64-row sub-blocks)
         const int r0 = NB * h, c0 = NB * (h + 1);
@@ -175,7 +176,7 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
         g.ta = 0; g.tb = 0; g.M = m; g.N = P.N; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
         g.A = Vb; g.lda = ld; g.B = P.W2; g.ldb = RB; g.C = Zs; g.ldc = ld;
         if (P.prec == BSE_PREC_FP32_REFINE) {
-          g.f32 = 1; g.Af = P.Vb32 + (j0 + 1); g.Bf = P.W2f; g.C = nullptr; g.Cf = P.Z32 + (j0 + 1);
+          g.f32 = 1; g.Af = P.Vb32 + (j0 + o); g.Bf = P.W2f; g.C = nullptr; g.Cf = P.Z32 + (j0 + o);
         }
       }
       break;

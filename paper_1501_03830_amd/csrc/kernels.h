@@ -105,6 +105,11 @@ __host__ __device__ constexpr bool is_refine_op(int op) { return op >= GOP_REF_Y
 // Bandwidth of the two-stage reduction's band (the panel width of its first
 // stage).
 constexpr int SBR_B = 64;
+// Row offset of the reflectors the block back-transformation applies:
+// reflector k acts on rows k + off .. N-1 (and N - 1 - off of them are
+// stored), off = 1 after the one-stage reduction, SBR_B for the band
+// reduction of the two-stage one.
+__host__ __device__ inline int refl_off(const Prob& P) { return P.uoff > 1 ? P.uoff : 1; }
 __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step);
 // Product `op` at `step` for the first nact problems of the batch.
 int gemm_batched(hipStream_t s, const Batch& b, int nact, int op, int step);
@@ -160,10 +165,18 @@ int tile_table_upload();
 // Two-stage skew tridiagonalisation of P.W (strict lower triangle, zero
 // upper triangle) for a batch of one: dense to band of width SBR_B (panel
 // Householder QR, MFMA two-sided updates), then band to tridiagonal by bulge
-// chasing (one persistent launch).  alpha as sktrd_batched; the reflectors
-// are not kept (eigenvalue path).  `work` holds the chase's progress words
-// and error flag (device, N + 64 ints).
-int sbr_single(hipStream_t s, const Batch& b, int* work);
+// chasing (one persistent launch).  alpha as sktrd_batched.  `work` holds
+// the chase's progress words and error flags (device, N + 4 + 128 ints).
+// With `vectors` both stages' reflectors are kept for sbr_q2_apply and the
+// block back-transformation: the band reduction's below the band in P.W (as
+// the one-stage ones, at row offset SBR_B), the chase's in P.W's upper
+// triangle (reflector (s, t) in row s, from column s + 1 + SBR_B t on).
+int sbr_single(hipStream_t s, const Batch& b, int* work, bool vectors);
+// Z <- Q2 Z for the chase's reflectors (Q2 their product in the order they
+// were made), on P.Z (N x N, ld); uses P.inv for the compact-WY factors.
+int sbr_q2_apply(hipStream_t s, const Batch& b);
+// bytes of P.inv that sbr_q2_apply needs for an order-N problem
+size_t sbr_q2_T_bytes(long N);
 
 // ---------------------------------------------------------------- stein.hip
 // positive eigenvalues of tridiag(alpha, 0, alpha) into P.lambda

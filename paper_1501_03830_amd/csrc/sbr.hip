@@ -374,8 +374,14 @@ __device__ inline void st_band(double* p, double x) {
 // applied: from the left to the left block, as W + v p^T - p v^T with
 // p = tau W v to the diagonal block (v^T W v = 0 for skew W), and from the
 // right to the block below.
+// With store_v the reflectors are also written to W's upper triangle (free
+// during the chase, whose band is the lower one) for the back-transformation:
+// reflector (s, t) on rows r0 .. r0 + len - 1 in row s, columns r0 ..
+// r0 + len - 1, tau in place of v's leading 1.  For fixed column the
+// reflectors of consecutive sweeps are then consecutive rows, which is how
+// the back-transformation reads them.
 __global__ __launch_bounds__(256) void k_sbr_chase(const Prob* __restrict__ probs, int* __restrict__ prog,
-                                                   int* __restrict__ err) {
+                                                   int* __restrict__ err, int store_v) {
   __shared__ double v[BW];
   __shared__ double pv[BW];
   __shared__ double rpart[4][BW];
@@ -438,11 +444,13 @@ __global__ __launch_bounds__(256) void k_sbr_chase(const Prob* __restrict__ prob
           tau = (beta - x0) / beta;
           scale = 1.0 / (x0 - beta);
         }
-        v[lane] = (lane == 0) ? 1.0 : ((lane < len) ? x * scale : 0.0);
+        const double vl = (lane == 0) ? 1.0 : ((lane < len) ? x * scale : 0.0);
+        v[lane] = vl;
         if (lane == 0) {
           coef[0] = tau;
           coef[1] = (sig > 0.0) ? 1.0 : 0.0;
         }
+        if (store_v && lane < len) W[s + (long)(r0 + lane) * ld] = (lane == 0) ? tau : vl;
         if (lane < len) st_band(W + (r0 + lane) + (long)col * ld, (lane == 0) ? beta : 0.0);
       }
       __syncthreads();
@@ -528,9 +536,257 @@ __global__ __launch_bounds__(256) void k_sbr_alpha(const Prob* __restrict__ prob
   gbl(P.alpha)[k] = -gbl(P.W)[(k + 1) + k * P.ld];
 }
 
+// The chase's fill zone (B < i - j <= 2B) holds the part of the band
+// reduction's reflectors next to the band.  With eigenvectors wanted it is
+// copied out before the chase zeroes it (restore = 0: W -> buf) and back
+// afterwards (restore = 1), B doubles per column in buf.
+__global__ __launch_bounds__(256) void k_sbr_fill(const Prob* __restrict__ probs, double* __restrict__ buf,
+                                                  int restore) {
+  const Prob& P = probs[0];
+  const long ld = P.ld;
+  const int N = P.N;
+  const long j = (long)blockIdx.x * 4 + (threadIdx.x >> 6);   // four columns per workgroup
+  const int q = threadIdx.x & 63;
+  if (j >= N) return;
+  const long i = j + BW + 1 + q;
+  if (i >= N) return;
+  BSE_GLOBAL double* __restrict__ w = gbl(P.W) + i + j * ld;
+  BSE_GLOBAL double* __restrict__ c = gbl(buf) + j * BW + q;
+  if (restore) *w = *c;
+  else *c = *w;
+}
+
+// ---- back-transformation with the chase's reflectors (Q2) ----
+//
+// Q2 = H(0,0) H(0,1) ... H(1,0) ... in the order the chase made them (sweep
+// s, step t), so Q2 Z applies them last first.  Reflector (s, t) acts on rows
+// s + 1 + B t .. s + B + B t, and two of them overlap only if they are of the
+// same step and close sweeps, or of neighbouring steps.  They are applied in
+// groups: group (sb, t) holds the step-t reflectors of the B sweeps
+// s0 = B sb .. s0 + B - 1, on the window of 2B - 1 rows from R0 = s0 + 1 + B t
+// (reflector l of the group covers window rows l .. l + B - 1), as one block
+// reflector I - V T V^T (T upper triangular, dlarft forward).  Reflector
+// (s, t) overlaps only reflectors of step t of sweeps less than B apart, of
+// step t - 1 of the B sweeps after s and of step t + 1 of the B sweeps before
+// s; of each such pair the one made later must be applied first.  Blocks of
+// sweeps last first, inside a block the steps first to last, inside a group
+// the sweeps last first, meet every one of these.  Sweep block sb has
+// nsb - sb groups.
+__host__ __device__ inline int q2_nsb(long N) { return N > 2 ? (int)((N - 2 + BW - 1) / BW) : 0; }
+__host__ __device__ inline long q2_group(int nsb, int sb, int t) {
+  return (long)sb * nsb - (long)sb * (sb - 1) / 2 + t;
+}
+
+// The group's reflectors into Vs[l][i] (reflector l at window row l + i,
+// leading 1 explicit) and their tau: reflector l exists if sweep s0 + l has a
+// step t (s0 + l <= N - 3 and R0 + l < N - 1); one that does not is zero
+// with tau 0.  Lanes run over l, so each load reads consecutive rows of one
+// column of W's upper triangle.
+__device__ inline void q2_load_V(const BSE_GLOBAL double* __restrict__ W, long ld, int N, int s0, int R0,
+                                 double (*Vs)[BW + 1], double* taus) {
+  const int tid = threadIdx.x, l = tid & 63;
+  const int s = s0 + l;
+  const bool live = s <= N - 3 && R0 + l < N - 1;
+  for (int m = tid >> 6; m < 2 * BW - 1; m += 4) {
+    const int i = m - l;
+    if (i < 0 || i >= BW) continue;
+    const long R = (long)R0 + m;
+    double v = (live && R < N) ? W[s + R * ld] : 0.0;
+    if (i == 0) {
+      if (taus) taus[l] = v;
+      v = live ? 1.0 : 0.0;
+    }
+    Vs[l][i] = v;
+  }
+}
+
+// T of every group (one workgroup per group): S = V^T V over the window,
+// then T[j, j] = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] S[0:j, j].
+__global__ __launch_bounds__(256) void k_sbr_q2T(const Prob* __restrict__ probs, double* __restrict__ Tbuf) {
+  __shared__ double Vs[BW][BW + 1];
+  __shared__ double Ss[BW][BW + 1];
+  __shared__ double Ts[BW][BW + 1];
+  __shared__ double taus[BW];
+  const Prob& P = probs[0];
+  const int N = P.N;
+  const long ld = P.ld;
+  const int nsb = q2_nsb(N);
+  const long g = blockIdx.x;
+  int lo = 0, hi = nsb - 1;   // the last sweep block whose first group is at or before g
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (q2_group(nsb, mid, 0) <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  const int sb = lo, t = (int)(g - q2_group(nsb, sb, 0));
+  const int s0 = BW * sb, R0 = s0 + 1 + BW * t;
+  const int tid = threadIdx.x;
+  q2_load_V(gbl(P.W), ld, N, s0, R0, Vs, taus);
+  for (int idx = tid; idx < BW * BW; idx += 256) Ts[idx & 63][idx >> 6] = 0.0;
+  __syncthreads();
+  for (int idx = tid; idx < BW * BW; idx += 256) {
+    const int k = idx & 63, j = idx >> 6;
+    double acc = 0.0;
+    if (k < j) {
+      const int d = j - k;   // window row k + i = j + (i - d)
+      for (int i = d; i < BW; ++i) acc += Vs[k][i] * Vs[j][i - d];
+    }
+    Ss[k][j] = acc;
+  }
+  __syncthreads();
+  for (int j = 0; j < BW; ++j) {
+    const double tj = taus[j];
+    if (tid < j) {
+      double acc = 0.0;
+      for (int q = tid; q < j; ++q) acc += Ts[tid][q] * Ss[q][j];
+      Ts[tid][j] = -tj * acc;
+    } else if (tid == j) {
+      Ts[j][j] = tj;
+    }
+    __syncthreads();
+  }
+  BSE_GLOBAL double* __restrict__ T = gbl(Tbuf) + g * (BW * BW);
+  for (int idx = tid; idx < BW * BW; idx += 256) T[idx] = Ts[idx & 63][idx >> 6];
+}
+
+// Z <- Q2 Z.  Workgroup c owns columns 64c .. 64c + 63 of Z and applies every
+// group to them in the order above, so workgroups never wait for each other.
+// The window of the current group lives in an LDS ring of 2B rows (global
+// row R in slot (R - s0 - 1) mod 2B): the next group of the same sweep block
+// starts B rows lower, so only its last B rows are loaded and the first B of
+// the current one stored.  Per group, on the matrix cores (wave w owns the
+// 16 columns 16w .. 16w + 15):
+//   W1 = V^T Zwin  (64 x 64, the band of V limits each row tile to 79 window rows)
+//   W2 = T W1      (T upper triangular, read from Tbuf)
+//   Zwin -= V W2
+// In a 16 x 16 block of v_mfma_f64_16x16x4f64 the A operand of lane L is
+// A[L mod 16][L / 16], the B operand B[L / 16][L mod 16], and accumulator
+// element v of lane L is D[4v + L / 16][L mod 16].
+constexpr int QC = 64;   // columns of Z per workgroup
+__global__ __launch_bounds__(256) void k_sbr_q2(const Prob* __restrict__ probs, const double* __restrict__ Tbuf) {
+  __shared__ double Zs[2 * BW][QC + 1];
+  __shared__ double Vs[BW][BW + 1];
+  __shared__ double Ws[BW][QC + 1];
+  const Prob& P = probs[0];
+  const int N = P.N;
+  const long ld = P.ld;
+  const int nsb = q2_nsb(N);
+  const int c0 = blockIdx.x * QC;
+  if (c0 >= N) return;   // uniform
+  BSE_GLOBAL double* __restrict__ Z = gbl(P.Z);
+  const BSE_GLOBAL double* __restrict__ W = gbl(P.W);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int cl = 16 * wave + (lane & 15);   // this lane's column in the B operands and results
+  const int kq = lane >> 4;
+  for (int sb = nsb - 1; sb >= 0; --sb) {
+    const int s0 = BW * sb, nt = nsb - sb;
+    for (int t = 0; t < nt; ++t) {
+      const int R0 = s0 + 1 + BW * t;
+      const int base = BW * t;   // slot of window row m: (base + m) mod 2B
+      // the new window rows (all of them for the block's first group), lanes along rows
+      const int mlo = (t == 0) ? 0 : BW - 1;
+      const int nrow = 2 * BW - 1 - mlo;
+      for (int idx = tid; idx < nrow * QC; idx += 256) {
+        const int m = mlo + idx % nrow, c = idx / nrow;
+        const long R = (long)R0 + m;
+        Zs[(base + m) & (2 * BW - 1)][c] = (R < N && c0 + c < N) ? Z[R + (long)(c0 + c) * ld] : 0.0;
+      }
+      q2_load_V(W, ld, N, s0, R0, Vs, nullptr);
+      __syncthreads();
+      // W1 = V^T Zwin
+      d4_t acc[8];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = d4_t{0.0, 0.0, 0.0, 0.0};
+      for (int m0 = 0; m0 < 2 * BW; m0 += 4) {
+        const int m = m0 + kq;
+        const double bz = (m < 2 * BW - 1) ? Zs[(base + m) & (2 * BW - 1)][cl] : 0.0;
+#pragma unroll
+        for (int lt = 0; lt < 4; ++lt) {
+          if (m0 + 3 < 16 * lt || m0 > 16 * lt + 15 + BW - 1) continue;   // uniform: outside the band
+          const int l = 16 * lt + (lane & 15), i = m - l;
+          const double a = (i >= 0 && i < BW) ? Vs[l][i] : 0.0;
+          acc[lt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bz, acc[lt], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int lt = 0; lt < 4; ++lt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Ws[16 * lt + 4 * v + kq][cl] = acc[lt][v];
+      __syncthreads();
+      // W2 = T W1 (T[i][k] = 0 for k < i)
+      const BSE_GLOBAL double* __restrict__ Tg = gbl(Tbuf) + q2_group(nsb, sb, t) * (BW * BW);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = d4_t{0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < BW; k0 += 4) {
+        const int k = k0 + kq;
+        const double bw = Ws[k][cl];
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+          if (k0 + 3 < 16 * it) continue;   // uniform
+          const double a = Tg[(16 * it + (lane & 15)) + (long)k * BW];
+          acc[it] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bw, acc[it], 0, 0, 0);
+        }
+      }
+      __syncthreads();   // every wave has read W1
+#pragma unroll
+      for (int it = 0; it < 4; ++it)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Ws[16 * it + 4 * v + kq][cl] = acc[it][v];
+      __syncthreads();
+      // Zwin -= V W2 (window row 2B - 1 is outside the window: its slot is
+      // left as it is, V being zero there)
+#pragma unroll
+      for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[mt][v] = Zs[(base + 16 * mt + 4 * v + kq) & (2 * BW - 1)][cl];
+      for (int l0 = 0; l0 < BW; l0 += 4) {
+        const int l = l0 + kq;
+        const double bw = Ws[l][cl];
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) {
+          if (l0 > 16 * mt + 15 || l0 + 3 < 16 * mt - (BW - 1)) continue;   // uniform: outside the band
+          const int m = 16 * mt + (lane & 15), i = m - l;
+          const double a = (i >= 0 && i < BW) ? -Vs[l][i] : 0.0;
+          acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bw, acc[mt], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Zs[(base + 16 * mt + 4 * v + kq) & (2 * BW - 1)][cl] = acc[mt][v];
+      __syncthreads();
+      // rows leaving the window: the first B, or all of it after the block's last group
+      const int nout = (t + 1 < nt) ? BW : 2 * BW - 1;
+      for (int idx = tid; idx < nout * QC; idx += 256) {
+        const int m = idx % nout, c = idx / nout;
+        const long R = (long)R0 + m;
+        if (R < N && c0 + c < N) Z[R + (long)(c0 + c) * ld] = Zs[(base + m) & (2 * BW - 1)][c];
+      }
+      __syncthreads();   // the next group's loads reuse these slots
+    }
+  }
+}
+
 }  // namespace
 
-int sbr_single(hipStream_t s, const Batch& b, int* work) {
+size_t sbr_q2_T_bytes(long N) {
+  const long nsb = q2_nsb(N);
+  return (size_t)(nsb * (nsb + 1) / 2) * BW * BW * sizeof(double);
+}
+
+int sbr_q2_apply(hipStream_t s, const Batch& b) {
+  if (b.count != 1) return set_error(BSE_EUNSUPPORTED, "the two-stage reduction runs one problem at a time");
+  const Prob& P = b.host[0];
+  const int N = P.N;
+  const int nsb = q2_nsb(N);
+  if (nsb == 0) return 0;
+  const long ng = (long)nsb * (nsb + 1) / 2;
+  BSE_LAUNCH(k_sbr_q2T, dim3((unsigned)ng), dim3(256), 0, s, b.dev, P.inv);
+  BSE_LAUNCH(k_sbr_q2, dim3((unsigned)((N + QC - 1) / QC)), dim3(256), 0, s, b.dev, P.inv);
+  return 0;
+}
+
+int sbr_single(hipStream_t s, const Batch& b, int* work, bool vectors) {
   if (b.count != 1) return set_error(BSE_EUNSUPPORTED, "the two-stage reduction runs one problem at a time");
   const Prob& P = b.host[0];
   const int N = P.N;
@@ -566,11 +822,15 @@ int sbr_single(hipStream_t s, const Batch& b, int* work) {
   }
   int* prog = work;
   int* err = work + N;
+  // the band reduction's reflectors next to the band, kept in Z (free until
+  // the eigenvectors are scattered into it: ld x ld >= N x B doubles)
+  if (vectors) BSE_LAUNCH(k_sbr_fill, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, s, b.dev, P.Z, 0);
   BSE_LAUNCH(k_sbr_prepare, dim3((unsigned)((N + 1) / 2)), dim3(256), 0, s, b.dev, prog, err);
   if (N > 2) {
     const unsigned G = (unsigned)(N - 2 < CH_WG ? N - 2 : CH_WG);
-    BSE_LAUNCH(k_sbr_chase, dim3(G), dim3(256), 0, s, b.dev, prog, err);
+    BSE_LAUNCH(k_sbr_chase, dim3(G), dim3(256), 0, s, b.dev, prog, err, vectors ? 1 : 0);
   }
+  if (vectors) BSE_LAUNCH(k_sbr_fill, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, s, b.dev, P.Z, 1);
   BSE_LAUNCH(k_sbr_alpha, dim3((unsigned)((N - 1 + 255) / 256)), dim3(256), 0, s, b.dev);
   int herr[3] = {0, 0, 0};
   BSE_HIP(hipMemcpyAsync(herr, err, 3 * sizeof(int), hipMemcpyDeviceToHost, s));

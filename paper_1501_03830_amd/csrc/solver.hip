@@ -77,7 +77,8 @@ static Plan make_plan(long N, int prec) {
   p.off_Vt = take((size_t)p.n * N * sizeof(double));
   // inverse iteration factors (4 double arrays + 1 byte array, N x n each);
   // later reused for the n x n Gram matrix of the reorthogonalisation
-  p.off_inv = take((size_t)4 * N * p.n * sizeof(double) + (size_t)N * p.n + 256);
+  // (and for the compact-WY factors of the two-stage back-transformation)
+  p.off_inv = take(std::max((size_t)4 * N * p.n * sizeof(double) + (size_t)N * p.n + 256, sbr_q2_T_bytes(N)));
   // alpha, tau, e2 (ld each), shift (n), scal (16), cid (n ints)
   p.off_small = take((size_t)(3 * p.ld + p.n + 16) * sizeof(double) + (size_t)p.n * sizeof(int));
   p.off_sk = take(sktrd_work_bytes(N, p.ld));
@@ -313,7 +314,7 @@ static int chain_tail(hipStream_t s, Lane* L, const Setup& S, const Batch& b, bo
   if (two) BSE_TRY(zero_upper(s, L->hprobs[0].N, L->hprobs[0].W, L->hprobs[0].ld));
   if (mixed) BSE_TRY(to_f32_batched(s, b));
   BSE_TRY(mark(L, timed, ev++));
-  if (two) BSE_TRY(sbr_single(s, b, reinterpret_cast<int*>(L->hprobs[0].Ycol)));
+  if (two) BSE_TRY(sbr_single(s, b, reinterpret_cast<int*>(L->hprobs[0].Ycol), vectors || mixed));
   else BSE_TRY(sktrd_batched(s, b, ktimer));
   BSE_TRY(mark(L, timed, ev++));
   BSE_TRY(bisect_batched(s, b));
@@ -410,6 +411,10 @@ int run_chain(Lane* L, const Setup& S, int count, bool vectors, bse_report* rep)
   hipStream_t s = L->stream;
   const bool timed = rep != nullptr;
   if (timed) BSE_TRY(ensure_events(L));
+  // a single problem with BSE_TWO_STAGE takes the two-stage reduction, whose
+  // first-stage reflectors the back-transformation applies at row offset SBR_B
+  for (int i = 0; i < count; ++i)
+    L->hprobs[i].uoff = (count == 1 && (L->hprobs[i].flags & BSE_TWO_STAGE) != 0) ? SBR_B : 1;
   BSE_TRY(upload(L, S, count));
   Batch b;
   b.count = count;
@@ -510,8 +515,8 @@ int check_solve_args(int n, const void* A, int lda, const void* B, int ldb, int 
   const bool vec = (flags & BSE_WANT_VECTORS) != 0;
   const bool wts = (flags & BSE_WANT_WEIGHTS) != 0;
   if (wts && !vec) return set_error(-8, "weights need eigenvectors");
-  if ((flags & BSE_TWO_STAGE) && (vec || prec != BSE_PREC_FP64))
-    return set_error(BSE_EUNSUPPORTED, "the two-stage reduction gives FP64 eigenvalues only");
+  if ((flags & BSE_TWO_STAGE) && prec != BSE_PREC_FP64)
+    return set_error(BSE_EUNSUPPORTED, "the two-stage reduction runs the FP64 path only");
   if (vec && !X) return set_error(-10, "X is NULL");
   if (vec && ldx < 2 * n) return set_error(-11, "ldx < 2n");
   if (wts && !d_r) return set_error(-12, "d_r is NULL");
@@ -969,7 +974,7 @@ int bse_sktrd2(bse_ctx* ctx, int N, double* W, int ldw, double* alpha) {
   BSE_TRY(upload(&ctx->lane, S, 1));
   BSE_TRY(copy_matrix(s, N, N, W, ldw, P.W, P.ld));
   BSE_TRY(zero_upper(s, N, P.W, P.ld));
-  BSE_TRY(sbr_single(s, single_batch(ctx, S), reinterpret_cast<int*>(P.Ycol)));
+  BSE_TRY(sbr_single(s, single_batch(ctx, S), reinterpret_cast<int*>(P.Ycol), false));
   BSE_TRY(copy_matrix(s, N, N, P.W, P.ld, W, ldw));
   BSE_HIP(hipMemcpyAsync(alpha, P.alpha, (N - 1) * sizeof(double), hipMemcpyDeviceToDevice, s));
   BSE_HIP(hipStreamSynchronize(s));

@@ -168,7 +168,7 @@ __global__ __launch_bounds__(256) void k_wy_solve(const Prob* __restrict__ probs
   __shared__ int zero[NB];
   const Prob& P = probs[blockIdx.z];
   const int N = P.N;
-  const int nrefl = N - 2;
+  const int nrefl = N - 1 - refl_off(P);
   const int jb = q * RB;
   if (jb >= nrefl) return;   // uniform
   if ((long)blockIdx.x * blockDim.x >= N) return;   // uniform

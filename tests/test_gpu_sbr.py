@@ -120,12 +120,108 @@ def test_two_stage_after_mixed_solve(ctx, n):
     assert torch.equal(mixed2["lam"], mixed["lam"]) and torch.equal(mixed2["X"], mixed["X"])
 
 
+def _check_vectors(A, B, d, r, ro, tag):
+    """Eigenvalues, eigenvectors (up to phase and cluster span), the residual
+    and normalisation metrics and the weights against the oracle, with the
+    one-stage parity suite's tolerances."""
+    from oracle import metrics
+    lam, X, w = npc(r["lam"]), npc(r["X"]), npc(r["w"])
+    As, Bs = bo.symmetrize_lower(A, B)
+    normH = np.linalg.norm(metrics.H_matrix(As, Bs), 2)
+    el = float(np.max(np.abs(lam - ro.lam))) / normH
+    gap = 1e-6 * normH
+    ev = metrics.compare_eigvecs(ro.X, X, ro.lam, gap)
+    r1, r2 = metrics.table1_metrics(As, Bs, lam, X)
+    we = metrics.compare_weights(ro.w, w, ro.lam, gap)
+    say(f"  {tag}: eig {el:.2e} vec {ev:.2e} table1 {r1:.2e} {r2:.2e} weights {we:.2e}")
+    assert el <= 1e-13
+    assert ev <= 1e-9
+    assert r1 <= 1e-12 and r2 <= 1e-12
+    assert metrics.normalization_error(X) <= 1e-12
+    assert we <= 1e-10
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 33, 64, 65, 100, 200])
+def test_two_stage_vectors_match_oracle(ctx, n):
+    """Eigenvectors through both stages' reflectors (the chase's as 64-sweep
+    block reflectors, then the band reduction's at row offset 64): the same
+    bar as the one-stage path.  Orders below and above one sweep block, one
+    band and several of each."""
+    from paper_1501_03830_amd import _lib
+    p = gen_bse(n, s_a=0.3, s_b=0.05, seed=900 + n)
+    ro = oracle.solve(p.A, p.B, p.d)
+    r = ctx.solve(tt(p.A), tt(p.B), d_r=tt(p.d), extra_flags=_lib.BSE_TWO_STAGE)
+    assert r["info"] == 0
+    _check_vectors(p.A, p.B, p.d, r, ro, f"[two-stage vectors] n={n}")
+
+
+def test_two_stage_vectors_equal_one_stage(ctx):
+    """n = 300 (N = 600: ten sweep blocks, nine bands): the two paths'
+    eigenvectors agree to the forward error of the two reductions."""
+    from paper_1501_03830_amd import _lib
+    from oracle import metrics
+    p = gen_bse(300, s_a=0.3, s_b=0.05, seed=77)
+    A, B = tt(p.A), tt(p.B)
+    r1 = ctx.solve(A, B)
+    r2 = ctx.solve(A, B, extra_flags=_lib.BSE_TWO_STAGE)
+    lam1 = npc(r1["lam"])
+    el = float(np.max(np.abs(npc(r2["lam"]) - lam1))) / float(lam1.max())
+    ev = metrics.compare_eigvecs(npc(r1["X"]), npc(r2["X"]), lam1, 1e-6 * float(lam1.max()))
+    rr1, rr2 = metrics.table1_metrics(*bo.symmetrize_lower(p.A, p.B), npc(r2["lam"]), npc(r2["X"]))
+    say(f"[two-stage vs one-stage] n=300: eig {el:.2e} vec {ev:.2e} table1 {rr1:.2e} {rr2:.2e}")
+    assert el <= 1e-13 and ev <= 1e-9 and rr1 <= 1e-12 and rr2 <= 1e-12
+
+
+def test_two_stage_vectors_closed_form_2048(ctx):
+    """n = 2048 with eigenvectors: exact eigenvalues, and the eigenpairs'
+    residual certificate on a sample of columns."""
+    from paper_1501_03830_amd import _lib
+    from oracle import metrics
+    p = gen_closed_form(2048, seed=33)
+    exact = np.asarray(p.exact_lambda)
+    r = ctx.solve(tt(p.A), tt(p.B), extra_flags=_lib.BSE_TWO_STAGE, report=True)
+    assert r["info"] == 0
+    lam, X = npc(r["lam"]), npc(r["X"])
+    err = float(np.max(np.abs(lam - exact))) / float(exact.max())
+    As, Bs = bo.symmetrize_lower(p.A, p.B)
+    H = metrics.H_matrix(As, Bs)
+    cols = np.random.default_rng(5).choice(2048, 48, replace=False)
+    res = max(float(np.linalg.norm(H @ X[:, j] - lam[j] * X[:, j]) / np.linalg.norm(X[:, j])) for j in cols)
+    res /= float(exact.max())
+    say(f"[two-stage vectors closed form] n=2048: eig {err:.2e} residual {res:.2e}, "
+        f"{r['report']['total_ms']:.1f} ms (apply_U {r['report']['stage_ms']['apply_U']:.1f} ms)")
+    assert err <= 1e-10 and res <= 1e-12
+
+
+def test_two_stage_real_path(ctx):
+    """Algorithm 2 (real A, B) through the two-stage reduction and its
+    back-transformation: eigenvalues, eigenvectors and weights against the
+    real oracle."""
+    from paper_1501_03830_amd import _lib
+    from bse_inputs import gen_real
+    from oracle import metrics
+    n = 120
+    p = gen_real(n, seed=12)
+    lo, Xo, info = oracle.solve_real(p.A, p.B)
+    assert info == 0
+    r = ctx.solve_real(tt(p.A.real), tt(p.B.real), d_r=tt(p.d), extra_flags=_lib.BSE_TWO_STAGE)
+    assert r["info"] == 0
+    lam, X, w = npc(r["lam"]), npc(r["X"]), npc(r["w"])
+    normH = float(lo.max())
+    el = float(np.max(np.abs(lam - lo))) / normH
+    ev = metrics.compare_eigvecs(Xo.astype(np.complex128), X.astype(np.complex128), lo, 1e-6 * normH)
+    wo = oracle.absorption_weights(Xo.astype(np.complex128), p.d, p.d)
+    we = metrics.compare_weights(wo, w, lo, 1e-6 * normH)
+    say(f"[two-stage real] n={n}: eig {el:.2e} vec {ev:.2e} w {we:.2e}")
+    assert el <= 1e-13 and ev <= 1e-9 and we <= 1e-10
+
+
 def test_two_stage_flag_limits(ctx):
     from paper_1501_03830_amd import _lib
     p = gen_bse(20, seed=3)
     with pytest.raises(_lib.BseError) as e:
-        ctx.solve(tt(p.A), tt(p.B), vectors=True, extra_flags=_lib.BSE_TWO_STAGE)
+        ctx.solve(tt(p.A), tt(p.B), vectors=False, prec=_lib.BSE_PREC_FP32_REFINE, extra_flags=_lib.BSE_TWO_STAGE)
     assert e.value.code == _lib.BSE_EUNSUPPORTED
     with pytest.raises(_lib.BseError) as e:
-        ctx.solve(tt(p.A), tt(p.B), vectors=False, prec=_lib.BSE_PREC_FP32_REFINE, extra_flags=_lib.BSE_TWO_STAGE)
+        ctx.solve(tt(p.A), tt(p.B), vectors=True, prec=_lib.BSE_PREC_FP32_REFINE, extra_flags=_lib.BSE_TWO_STAGE)
     assert e.value.code == _lib.BSE_EUNSUPPORTED
