@@ -37,6 +37,7 @@
 // raises an error flag that makes every other wait give up, so every
 // workgroup exits.
 #include <climits>
+#include <type_traits>
 
 #include "common.h"
 #include "kernels.h"
@@ -653,19 +654,168 @@ __global__ __launch_bounds__(256) void k_sbr_q2T(const Prob* __restrict__ probs,
 // group to them in the order above, so workgroups never wait for each other.
 // The window of the current group lives in an LDS ring of 2B rows (global
 // row R in slot (R - s0 - 1) mod 2B): the next group of the same sweep block
-// starts B rows lower, so only its last B rows are loaded and the first B of
-// the current one stored.  Per group, on the matrix cores (wave w owns the
-// 16 columns 16w .. 16w + 15):
-//   W1 = V^T Zwin  (64 x 64, the band of V limits each row tile to 79 window rows)
-//   W2 = T W1      (T upper triangular, read from Tbuf)
+// starts B rows lower, so only its last B rows are new and the first B rows
+// of the current one leave.  Per group, on the matrix cores:
+//   W1 = V^T Zwin  (64 x 64; the band of V limits a row tile to 79 window rows)
+//   W2 = T W1      (T upper triangular)
 //   Zwin -= V W2
-// In a 16 x 16 block of v_mfma_f64_16x16x4f64 the A operand of lane L is
+// Eight wavefronts, two per SIMD: wave w owns the 16 columns 16 (w mod 4) ..
+// and half h = w / 4 of the row tiles of each product, split so that both
+// halves issue the same number of MFMAs.  The group's T and the next
+// group's new rows of Z and reflectors are loaded into registers at the
+// start of a group, so their latency hides behind its products.  In a
+// 16 x 16 block of v_mfma_f64_16x16x4f64 the A operand of lane L is
 // A[L mod 16][L / 16], the B operand B[L / 16][L mod 16], and accumulator
 // element v of lane L is D[4v + L / 16][L mod 16].
-constexpr int QC = 64;   // columns of Z per workgroup
-__global__ __launch_bounds__(256) void k_sbr_q2(const Prob* __restrict__ probs, const double* __restrict__ Tbuf) {
+constexpr int QC = 64;    // columns of Z per workgroup
+constexpr int QT = 512;   // threads per workgroup
+constexpr int VLD = BW + 2;   // row stride of Vs: rows l and l + 1 of a band diagonal fall in different banks
+constexpr int ZPF = BW * QC / QT;   // prefetched Z entries per thread
+constexpr int VPF = BW * BW / QT;   // reflector entries per thread
+
+// Reflector entries of group (s0, R0) that thread tid loads: lane l = tid mod
+// 64 (reflector l), phase p = tid / 64, the window rows m = l + i of its band
+// with m = p mod 8: i = ((p - l) mod 8) + 8 u, so every thread takes exactly
+// VPF entries and eight neighbouring lanes read eight consecutive rows of one
+// column of W's upper triangle.  Loads are unconditional (an entry outside
+// the reflector reads W[0] and is masked out when stored): a load under a
+// branch, or a select on its value, makes the compiler wait for it at once,
+// and these are meant to stay in flight through a whole group.
+__device__ inline void q2_fetch_V(const BSE_GLOBAL double* __restrict__ W, long ld, int N, int s0, int R0,
+                                  double (&v)[VPF], unsigned& mask) {
+  const int tid = threadIdx.x, l = tid & 63;
+  const int i0 = ((tid >> 6) - l) & 7;
+  const int s = s0 + l;
+  const bool live = s <= N - 3 && R0 + l < N - 1;
+  mask = 0;
+#pragma unroll
+  for (int u = 0; u < VPF; ++u) {
+    const int i = i0 + 8 * u;
+    const long R = (long)R0 + l + i;
+    const bool ok = live && i > 0 && R < N;
+    v[u] = W[ok ? s + R * ld : 0];
+    mask |= (ok ? 1u : 0u) << u;
+  }
+}
+// V[l + i][l] into Vs[l][i] (the leading 1 explicit)
+__device__ inline void q2_put_V(const double (&v)[VPF], unsigned mask, int N, int s0, int R0, double (*Vs)[VLD]) {
+  const int tid = threadIdx.x, l = tid & 63;
+  const int i0 = ((tid >> 6) - l) & 7;
+  const bool live = s0 + l <= N - 3 && R0 + l < N - 1;
+#pragma unroll
+  for (int u = 0; u < VPF; ++u) {
+    const int i = i0 + 8 * u;
+    Vs[l][i] = (i == 0) ? (live ? 1.0 : 0.0) : (((mask >> u) & 1u) ? v[u] : 0.0);
+  }
+}
+// Window rows B - 1 .. 2B - 2 of the group at R1 (the rows it has beyond the
+// previous group's window), lanes along rows; unconditional loads as above.
+__device__ inline void q2_fetch_Z(const BSE_GLOBAL double* __restrict__ Z, long ld, int N, int c0, int R1,
+                                  double (&z)[ZPF], unsigned& mask) {
+  mask = 0;
+#pragma unroll
+  for (int u = 0; u < ZPF; ++u) {
+    const int idx = threadIdx.x + QT * u;
+    const int m = (BW - 1) + idx % BW, c = idx / BW;
+    const long R = (long)R1 + m;
+    const bool ok = R < N && c0 + c < N;
+    z[u] = Z[ok ? R + (long)(c0 + c) * ld : 0];
+    mask |= (ok ? 1u : 0u) << u;
+  }
+}
+
+// The three products of one group for half H of the row tiles (H is a
+// compile-time constant, so every tile's range of K steps is fixed and the
+// loops carry no branches; two independent accumulators are interleaved
+// throughout).  tr holds this wave's 20 MFMA A operands of T: i-tile
+// it0 = H (16 - 4 it0 K steps from k = 16 it0), then i-tile it1 = 3 - H.
+template <int H>
+__device__ inline void q2_products(double (*Zs)[QC + 1], double (*Vs)[VLD], double (*Ws)[QC + 1],
+                                   const double (&tr)[20], int base, int cl) {
+  const int lane = threadIdx.x & 63, kq = lane >> 4, li = lane & 15;
+  auto zrow = [&](int m) { return (base + m) & (2 * BW - 1); };
+  // W1 = V^T Zwin: l-tiles 2H and 2H + 1, window rows 16 lt .. 16 lt + 79
+  {
+    d4_t a0 = d4_t{0.0, 0.0, 0.0, 0.0}, a1 = a0;
+    const int la = 32 * H + li, lb = la + 16;
+#pragma unroll 4
+    for (int st = 0; st < 20; ++st) {
+      const int ma = 32 * H + 4 * st + kq, mb = ma + 16;
+      const double za = Zs[zrow(ma)][cl];
+      const double zb = (mb < 2 * BW - 1) ? Zs[zrow(mb)][cl] : 0.0;   // row 2B - 1 is outside the window
+      const int ia = ma - la, ib = mb - lb;
+      const double va = (ia >= 0 && ia < BW) ? Vs[la][ia] : 0.0;
+      const double vb = (ib >= 0 && ib < BW) ? Vs[lb][ib] : 0.0;
+      a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(va, za, a0, 0, 0, 0);
+      a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(vb, zb, a1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Ws[32 * H + 4 * v + kq][cl] = a0[v];
+      Ws[32 * H + 16 + 4 * v + kq][cl] = a1[v];
+    }
+  }
+  __syncthreads();
+  // W2 = T W1: i-tiles it0 = H (n0 K steps), it1 = 3 - H (n1 steps), T[i][k] = 0 for k < i
+  {
+    constexpr int it0 = H, it1 = 3 - H, n0 = 16 - 4 * it0, n1 = 16 - 4 * it1;
+    d4_t a0 = d4_t{0.0, 0.0, 0.0, 0.0}, a1 = a0;
+#pragma unroll
+    for (int st = 0; st < n0; ++st) {
+      a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(tr[st], Ws[16 * it0 + 4 * st + kq][cl], a0, 0, 0, 0);
+      if (st < n1) a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(tr[n0 + st], Ws[16 * it1 + 4 * st + kq][cl], a1, 0, 0, 0);
+    }
+    __syncthreads();   // every wave has read W1
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Ws[16 * it0 + 4 * v + kq][cl] = a0[v];
+      Ws[16 * it1 + 4 * v + kq][cl] = a1[v];
+    }
+  }
+  __syncthreads();
+  // Zwin -= V W2: m-tile mt needs l in [16 mt - 63, 16 mt + 15]; the tiles
+  // go in pairs of equal step counts: H = 0: (3, 4) and (0, 7); H = 1:
+  // (2, 5) and (1, 6)
+  auto pair = [&](auto MA, auto MB) {
+    constexpr int ma = decltype(MA)::value, mb = decltype(MB)::value;
+    constexpr int sa = (16 * ma - 64 > 0) ? 16 * ma - 64 : 0, sb = (16 * mb - 64 > 0) ? 16 * mb - 64 : 0;
+    constexpr int ea = (16 * ma + 16 < BW) ? 16 * ma + 16 : BW;
+    constexpr int ns = (ea - sa) / 4;
+    d4_t a0, a1;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      a0[v] = Zs[zrow(16 * ma + 4 * v + kq)][cl];
+      a1[v] = Zs[zrow(16 * mb + 4 * v + kq)][cl];
+    }
+    const int mra = 16 * ma + li, mrb = 16 * mb + li;
+#pragma unroll 4
+    for (int st = 0; st < ns; ++st) {
+      const int la = sa + 4 * st + kq, lb = sb + 4 * st + kq;
+      const int ia = mra - la, ib = mrb - lb;
+      const double va = (ia >= 0 && ia < BW) ? -Vs[la][ia] : 0.0;
+      const double vb = (ib >= 0 && ib < BW) ? -Vs[lb][ib] : 0.0;
+      a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(va, Ws[la][cl], a0, 0, 0, 0);
+      a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(vb, Ws[lb][cl], a1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Zs[zrow(16 * ma + 4 * v + kq)][cl] = a0[v];
+      Zs[zrow(16 * mb + 4 * v + kq)][cl] = a1[v];
+    }
+  };
+  if constexpr (H == 0) {
+    pair(std::integral_constant<int, 3>{}, std::integral_constant<int, 4>{});
+    pair(std::integral_constant<int, 0>{}, std::integral_constant<int, 7>{});
+  } else {
+    pair(std::integral_constant<int, 2>{}, std::integral_constant<int, 5>{});
+    pair(std::integral_constant<int, 1>{}, std::integral_constant<int, 6>{});
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(QT) void k_sbr_q2(const Prob* __restrict__ probs, const double* __restrict__ Tbuf) {
   __shared__ double Zs[2 * BW][QC + 1];
-  __shared__ double Vs[BW][BW + 1];
+  __shared__ double Vs[BW][VLD];
   __shared__ double Ws[BW][QC + 1];
   const Prob& P = probs[0];
   const int N = P.N;
@@ -675,94 +825,75 @@ __global__ __launch_bounds__(256) void k_sbr_q2(const Prob* __restrict__ probs, 
   if (c0 >= N) return;   // uniform
   BSE_GLOBAL double* __restrict__ Z = gbl(P.Z);
   const BSE_GLOBAL double* __restrict__ W = gbl(P.W);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int cl = 16 * wave + (lane & 15);   // this lane's column in the B operands and results
-  const int kq = lane >> 4;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int ct = wave & 3, h = wave >> 2;
+  const int cl = 16 * ct + (lane & 15);   // this lane's column in the B operands and results
+  const int kq = lane >> 4, li = lane & 15;
+  // row tiles of this half: W1 l-tiles {2h, 2h+1} (20 steps each); W2
+  // i-tiles {0, 3} or {1, 2} (20 steps in all); Zwin m-tiles {0, 3, 4, 7}
+  // or {1, 2, 5, 6} (40 steps in all)
+  const int it0 = h ? 1 : 0, it1 = h ? 2 : 3;
+  const int nk0 = 16 - 4 * it0;   // k steps of i-tile it0 (T[i][k] = 0 for k < i)
+  double zpf[ZPF], vpf[VPF];
+  unsigned zmask = 0, vmask = 0;
   for (int sb = nsb - 1; sb >= 0; --sb) {
     const int s0 = BW * sb, nt = nsb - sb;
     for (int t = 0; t < nt; ++t) {
       const int R0 = s0 + 1 + BW * t;
       const int base = BW * t;   // slot of window row m: (base + m) mod 2B
-      // the new window rows (all of them for the block's first group), lanes along rows
-      const int mlo = (t == 0) ? 0 : BW - 1;
-      const int nrow = 2 * BW - 1 - mlo;
-      for (int idx = tid; idx < nrow * QC; idx += 256) {
-        const int m = mlo + idx % nrow, c = idx / nrow;
-        const long R = (long)R0 + m;
-        Zs[(base + m) & (2 * BW - 1)][c] = (R < N && c0 + c < N) ? Z[R + (long)(c0 + c) * ld] : 0.0;
-      }
-      q2_load_V(W, ld, N, s0, R0, Vs, nullptr);
-      __syncthreads();
-      // W1 = V^T Zwin
-      d4_t acc[8];
+      if (t == 0) {
+        // first group of the block: the whole window and its reflectors
+        for (int idx = tid; idx < (2 * BW - 1) * QC; idx += QT) {
+          const int m = idx % (2 * BW - 1), c = idx / (2 * BW - 1);
+          const long R = (long)R0 + m;
+          Zs[(base + m) & (2 * BW - 1)][c] = (R < N && c0 + c < N) ? Z[R + (long)(c0 + c) * ld] : 0.0;
+        }
+        q2_fetch_V(W, ld, N, s0, R0, vpf, vmask);
+      } else {
+        // rows 63 .. 126 of this window, fetched during the previous group
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc[q] = d4_t{0.0, 0.0, 0.0, 0.0};
-      for (int m0 = 0; m0 < 2 * BW; m0 += 4) {
-        const int m = m0 + kq;
-        const double bz = (m < 2 * BW - 1) ? Zs[(base + m) & (2 * BW - 1)][cl] : 0.0;
-#pragma unroll
-        for (int lt = 0; lt < 4; ++lt) {
-          if (m0 + 3 < 16 * lt || m0 > 16 * lt + 15 + BW - 1) continue;   // uniform: outside the band
-          const int l = 16 * lt + (lane & 15), i = m - l;
-          const double a = (i >= 0 && i < BW) ? Vs[l][i] : 0.0;
-          acc[lt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bz, acc[lt], 0, 0, 0);
+        for (int u = 0; u < ZPF; ++u) {
+          const int idx = tid + QT * u;
+          const int m = (BW - 1) + idx % BW, c = idx / BW;
+          Zs[(base + m) & (2 * BW - 1)][c] = ((zmask >> u) & 1u) ? zpf[u] : 0.0;
         }
       }
-#pragma unroll
-      for (int lt = 0; lt < 4; ++lt)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Ws[16 * lt + 4 * v + kq][cl] = acc[lt][v];
-      __syncthreads();
-      // W2 = T W1 (T[i][k] = 0 for k < i)
+      q2_put_V(vpf, vmask, N, s0, R0, Vs);
+      // this group's T (registers), then the next group's rows and reflectors
       const BSE_GLOBAL double* __restrict__ Tg = gbl(Tbuf) + q2_group(nsb, sb, t) * (BW * BW);
+      double tr[20];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc[q] = d4_t{0.0, 0.0, 0.0, 0.0};
-      for (int k0 = 0; k0 < BW; k0 += 4) {
-        const int k = k0 + kq;
-        const double bw = Ws[k][cl];
+      for (int j = 0; j < 20; ++j) {
+        const int it = (j < nk0) ? it0 : it1;
+        const int k0 = (j < nk0) ? 16 * it0 + 4 * j : 16 * it1 + 4 * (j - nk0);
+        tr[j] = Tg[(16 * it + li) + (long)(k0 + kq) * BW];
+      }
+      if (t + 1 < nt) {
+        q2_fetch_Z(Z, ld, N, c0, R0 + BW, zpf, zmask);
+        q2_fetch_V(W, ld, N, s0, R0 + BW, vpf, vmask);
+      }
+      __syncthreads();
+      if (h == 0) q2_products<0>(Zs, Vs, Ws, tr, base, cl);
+      else q2_products<1>(Zs, Vs, Ws, tr, base, cl);
+      // rows leaving the window: the first B (a fixed count per thread), or
+      // all of it after the block's last group
+      if (t + 1 < nt) {
 #pragma unroll
-        for (int it = 0; it < 4; ++it) {
-          if (k0 + 3 < 16 * it) continue;   // uniform
-          const double a = Tg[(16 * it + (lane & 15)) + (long)k * BW];
-          acc[it] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bw, acc[it], 0, 0, 0);
+        for (int u = 0; u < BW * QC / QT; ++u) {
+          const int idx = tid + QT * u;
+          const int m = idx % BW, c = idx / BW;
+          const long R = (long)R0 + m;
+          if (R < N && c0 + c < N) Z[R + (long)(c0 + c) * ld] = Zs[(base + m) & (2 * BW - 1)][c];
+        }
+      } else {
+        for (int idx = tid; idx < (2 * BW - 1) * QC; idx += QT) {
+          const int m = idx % (2 * BW - 1), c = idx / (2 * BW - 1);
+          const long R = (long)R0 + m;
+          if (R < N && c0 + c < N) Z[R + (long)(c0 + c) * ld] = Zs[(base + m) & (2 * BW - 1)][c];
         }
       }
-      __syncthreads();   // every wave has read W1
-#pragma unroll
-      for (int it = 0; it < 4; ++it)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Ws[16 * it + 4 * v + kq][cl] = acc[it][v];
-      __syncthreads();
-      // Zwin -= V W2 (window row 2B - 1 is outside the window: its slot is
-      // left as it is, V being zero there)
-#pragma unroll
-      for (int mt = 0; mt < 8; ++mt)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[mt][v] = Zs[(base + 16 * mt + 4 * v + kq) & (2 * BW - 1)][cl];
-      for (int l0 = 0; l0 < BW; l0 += 4) {
-        const int l = l0 + kq;
-        const double bw = Ws[l][cl];
-#pragma unroll
-        for (int mt = 0; mt < 8; ++mt) {
-          if (l0 > 16 * mt + 15 || l0 + 3 < 16 * mt - (BW - 1)) continue;   // uniform: outside the band
-          const int m = 16 * mt + (lane & 15), i = m - l;
-          const double a = (i >= 0 && i < BW) ? -Vs[l][i] : 0.0;
-          acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bw, acc[mt], 0, 0, 0);
-        }
-      }
-#pragma unroll
-      for (int mt = 0; mt < 8; ++mt)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Zs[(base + 16 * mt + 4 * v + kq) & (2 * BW - 1)][cl] = acc[mt][v];
-      __syncthreads();
-      // rows leaving the window: the first B, or all of it after the block's last group
-      const int nout = (t + 1 < nt) ? BW : 2 * BW - 1;
-      for (int idx = tid; idx < nout * QC; idx += 256) {
-        const int m = idx % nout, c = idx / nout;
-        const long R = (long)R0 + m;
-        if (R < N && c0 + c < N) Z[R + (long)(c0 + c) * ld] = Zs[(base + m) & (2 * BW - 1)][c];
-      }
-      __syncthreads();   // the next group's loads reuse these slots
+      __syncthreads();   // the next group's rows reuse these slots
     }
   }
 }
@@ -782,7 +913,7 @@ int sbr_q2_apply(hipStream_t s, const Batch& b) {
   if (nsb == 0) return 0;
   const long ng = (long)nsb * (nsb + 1) / 2;
   BSE_LAUNCH(k_sbr_q2T, dim3((unsigned)ng), dim3(256), 0, s, b.dev, P.inv);
-  BSE_LAUNCH(k_sbr_q2, dim3((unsigned)((N + QC - 1) / QC)), dim3(256), 0, s, b.dev, P.inv);
+  BSE_LAUNCH(k_sbr_q2, dim3((unsigned)((N + QC - 1) / QC)), dim3(QT), 0, s, b.dev, P.inv);
   return 0;
 }
 
