@@ -494,8 +494,8 @@ def closed_form_check(ctx, n: int, seed: int = 30):
     """Exact-eigenvalue check at the benchmark size: the closed-form
     generator (A = U0 diag(a) U0^H, B = U0 diag(b) U0^T, eigenvalues
     sqrt(a_k^2 - |b_k|^2)), solved by the one-stage and the two-stage
-    reduction, eigenvalues only; and a real closed-form problem through
-    Algorithm 2 with eigenvectors.  Errors are max |lambda - lambda_exact|
+    reduction, eigenvalues only, and by the two-stage one with eigenvectors;
+    and a real closed-form problem through Algorithm 2 with eigenvectors.  Errors are max |lambda - lambda_exact|
     relative to lambda_max (at most ||H||_2)."""
     import torch
     from bse_inputs import gen_closed_form
@@ -519,6 +519,27 @@ def closed_form_check(ctx, n: int, seed: int = 30):
         assert info == 0, info
         out[key] = {"max_rel_eig_err": float((lam - exact).abs().max()) / lmax,
                     "device_ms": round(rep["total_ms"], 2), "sktrd_ms": round(rep["stage_ms"]["sktrd"], 2)}
+    # the two-stage reduction with eigenvectors (both stages' reflectors
+    # applied back): exact eigenvalues and residuals of 32 sampled eigenpairs
+    lam = torch.empty(n, dtype=torch.float64, device=dev)
+    X = torch.empty((n, 2 * n), dtype=torch.complex128, device=dev)
+    info, rep = ctx.solve_raw(n, Ac, Bc, lam, X, None, None, None, report=True, extra_flags=_lib.BSE_TWO_STAGE)
+    assert info == 0, info
+    A = Ac.transpose(0, 1)
+    B = Bc.transpose(0, 1)
+    Af = torch.tril(A) + torch.tril(A, -1).conj().transpose(0, 1)
+    Bf = torch.tril(B) + torch.tril(B, -1).transpose(0, 1)
+    cols = torch.arange(0, n, max(1, n // 32), device=dev)
+    Xs = X[cols].transpose(0, 1)
+    x1, x2 = Xs[:n], Xs[n:]
+    lc = lam[cols][None, :]
+    r = torch.cat([Af @ x1 + Bf @ x2 - x1 * lc, -(Bf.conj() @ x1) - (Af.conj() @ x2) - x2 * lc])
+    out["fp64_two_stage_vectors"] = {
+        "max_rel_eig_err": float((lam - exact).abs().max()) / lmax,
+        "max_rel_residual_sampled": float(r.abs().max()) / lmax,
+        "device_ms": round(rep["total_ms"], 2), "sktrd_ms": round(rep["stage_ms"]["sktrd"], 2),
+        "apply_U_ms": round(rep["stage_ms"]["apply_U"], 2)}
+    del X, Af, Bf, Xs, x1, x2, r
     # Algorithm 2 (real A, B) on a real closed-form problem of the same order,
     # with eigenvectors
     from bse_inputs import gen_real_closed_form
