@@ -64,6 +64,9 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
       g.ta = 0; g.tb = 1; g.M = rest; g.N = rest < NB ? rest : NB; g.K = NB; g.alpha = -1.0; g.beta = 1.0;
       g.A = a21; g.lda = ldm; g.B = a21; g.ldb = ldm;
       g.C = Mx + (k0 + NB) + (long)(k0 + NB) * ldm; g.ldc = ldm; g.c_uplo = 3;
+      if (gram) {
+        g.band_lam = P.lambda; g.band_scal = P.scal; g.band_r0 = g.band_c0 = k0 + NB; g.band_cfix = -1; g.band_n = P.n;
+      }
       break;
     }
     case GOP_POTRF_SYRK:
@@ -83,6 +86,9 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
       g.ta = 0; g.tb = 1; g.M = rest; g.N = rest; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
       g.A = a21; g.lda = ldm; g.B = a21; g.ldb = ldm;
       g.C = Mx + (k0 + nbk) + (long)(k0 + nbk) * ldm; g.ldc = ldm; g.c_uplo = 1;
+      if (gram) {
+        g.band_lam = P.lambda; g.band_scal = P.scal; g.band_r0 = g.band_c0 = k0 + nbk; g.band_cfix = -1; g.band_n = P.n;
+      }
       break;
     }
     case GOP_FORMW_C:   // W11 <- L11^T L21
@@ -120,6 +126,7 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
     case GOP_GRAM:  // G <- Vt Vt^T (lower)
       g.ta = 0; g.tb = 1; g.M = P.n; g.N = P.n; g.K = P.N;
       g.A = P.Vt; g.lda = P.n; g.B = P.Vt; g.ldb = P.n; g.C = P.inv; g.ldc = P.n; g.c_uplo = 1;
+      g.band_lam = P.lambda; g.band_scal = P.scal; g.band_r0 = g.band_c0 = 0; g.band_cfix = -1; g.band_n = P.n;
       break;
     case GOP_GRAM_UPD_PANEL: {  // rows b0+64..b0+127 -= L[.., b0:b0+64] (rows b0..b0+63)
       const int b0 = step;
@@ -128,6 +135,7 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
       g.ta = 0; g.tb = 0; g.M = rest < NB ? rest : NB; g.N = P.N; g.K = NB; g.alpha = -1.0; g.beta = 1.0;
       g.A = P.inv + (b0 + NB) + (long)b0 * P.n; g.lda = P.n; g.B = P.Vt + b0; g.ldb = P.n;
       g.C = P.Vt + b0 + NB; g.ldc = P.n;
+      g.band_lam = P.lambda; g.band_scal = P.scal; g.band_r0 = b0 + NB; g.band_cfix = b0 + NB - 1; g.band_n = P.n;
       break;
     }
     case GOP_GRAM_UPD: {  // rows below the 128-row block -= L21 (rows of the block)
@@ -139,6 +147,7 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
       g.ta = 0; g.tb = 0; g.M = rest; g.N = P.N; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
       g.A = P.inv + (b0 + nbk) + (long)b0 * P.n; g.lda = P.n; g.B = P.Vt + b0; g.ldb = P.n;
       g.C = P.Vt + b0 + nbk; g.ldc = P.n;
+      g.band_lam = P.lambda; g.band_scal = P.scal; g.band_r0 = b0 + nbk; g.band_cfix = b0 + nbk - 1; g.band_n = P.n;
       break;
     }
     case GOP_APPLYU_S:
@@ -420,6 +429,14 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const Prob* __restrict__ 
   const int i0 = tm * BM, j0 = tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave & 1, wc = wave >> 1;
+  if (p.band_lam && p.splits == 1) {
+    // a tile of the reorthogonalisation's products outside the band is zero
+    // and stays zero (uniform)
+    const BSE_GLOBAL double* __restrict__ lam = gbl(p.band_lam);
+    const int rlo = p.band_r0 + i0;
+    const int chi = p.band_cfix >= 0 ? p.band_cfix : min(p.band_c0 + j0 + BN - 1, p.band_n - 1);
+    if (rlo < p.band_n && lam[rlo] - lam[chi] > REORTH_BAND * gbl(p.band_scal)[1]) return;
+  }
 
   // K range that can hold non-zero products for this tile
   int kbeg = 0, kend = p.K;

@@ -54,7 +54,21 @@ struct GemmParams {
   const float* Af;
   const float* Bf;
   const double* Cin;
+  // Band of the reorthogonalisation's Gram matrix (band_lam non-null): C row
+  // r belongs to eigenvalue band_r0 + r; a tile whose rows' first eigenvalue
+  // exceeds the last eigenvalue of its columns (band_c0 + column, or the
+  // fixed index band_cfix >= 0 for products whose K runs over eigenvalues)
+  // by more than REORTH_BAND * band_scal[1] holds only zeros and is skipped.
+  const double* band_lam;
+  const double* band_scal;
+  int band_r0, band_c0, band_cfix, band_n;
 };
+
+// Eigenvalue pairs farther apart than this fraction of ||T_s||_1 are left
+// out of the reorthogonalisation: inverse iteration leaves such vectors
+// orthogonal to about eps / REORTH_BAND already, and the Gram matrix with
+// those entries dropped has a Cholesky factor without fill outside the band.
+constexpr double REORTH_BAND = 0.1;
 
 // Reflectors per block of the back-transformation with U (four 64-row
 // sub-blocks of the compact-WY factor).

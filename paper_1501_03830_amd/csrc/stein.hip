@@ -17,6 +17,12 @@
 //    1e-3 ||T_s||_1): Gram-Schmidt in ascending order, realised as a Cholesky
 //    QR of the Gram matrix with the entries between different clusters
 //    removed (the Q factor of that QR is exactly the Gram-Schmidt result).
+//    Inside a cluster, pairs farther apart than REORTH_BAND ||T_s||_1 are
+//    removed too: inverse iteration already leaves them orthogonal to about
+//    eps / REORTH_BAND, the Gram matrix becomes banded in eigenvalue order,
+//    its Cholesky factor has no fill outside the band, and the products skip
+//    the tiles outside it (a long chain of close eigenvalues, e.g. most of
+//    the spectrum at n = 8192, no longer costs a dense n x n Cholesky QR).
 #include <cfloat>
 
 #include "common.h"
@@ -576,15 +582,20 @@ __global__ __launch_bounds__(256) void k_mask_gram(const Prob* __restrict__ prob
   const long ldg = n;
   BSE_GLOBAL double* __restrict__ G = gbl(P.inv);
   const BSE_GLOBAL int* __restrict__ cid = gbl(P.cid);
+  const BSE_GLOBAL double* __restrict__ lam = gbl(P.lambda);
+  const double band = REORTH_BAND * gbl(P.scal)[1];
   const long r = (long)blockIdx.x * 64 + (threadIdx.x & 63);
   const long c0 = (long)blockIdx.y * 64 + (threadIdx.x >> 6) * 16;
   __shared__ double wmax[4];
   double def = 0.0;   // largest |G - I| over this thread's entries inside a cluster
   const int cr = r < n ? cid[r] : -1;
+  const double lr = r < n ? lam[r] : 0.0;
   for (int q = 0; q < 16 && r < n; ++q) {
     const long c = c0 + q;
     if (c >= n || c > r) break;
-    if (cid[c] != cr) G[r + c * ldg] = 0.0;
+    // entries between clusters, and pairs farther apart than the band (whose
+    // tiles the Gram product may have skipped), are dropped
+    if (cid[c] != cr || lr - lam[c] > band) G[r + c * ldg] = 0.0;
     else def = fmax(def, fabs(G[r + c * ldg] - (c == r ? 1.0 : 0.0)));
   }
   // the workgroup's largest defect joins the problem's (non-negative doubles
@@ -669,7 +680,8 @@ int reorth_batched(hipStream_t s, const Batch& b, const int* dflags, int* hflags
     if (pass == 1) {
       BSE_LAUNCH(k_reorth_gate, dim3((unsigned)b.count), 64, 0, s, b.dev);
     }
-    // G = Vt Vt^T (lower), then drop the entries between clusters
+    // G = Vt Vt^T (lower, band tiles), then drop the entries between
+    // clusters and outside the band
     BSE_TRY(gemm_batched(s, b, b.count, GOP_GRAM, 0));
     BSE_LAUNCH(k_mask_gram, g2, 256, 0, s, b.dev);
     BSE_TRY(potrf_batched(s, b, 1, pass == 0));
