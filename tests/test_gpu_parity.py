@@ -164,6 +164,31 @@ def test_tridiag_eig(ctx, n):
         assert err <= 1e-9, (s_, e_, err)
 
 
+def test_tridiag_eig_band_reorth(ctx):
+    """The Clement matrix (zero diagonal, off-diagonals sqrt(k (N - k)), k =
+    1 .. N-1) has the eigenvalues N - 1, N - 3, ..., -(N - 1), equally spaced
+    by 2.  At N = 4096 the spacing is below the cluster criterion 1e-3
+    ||T_s||_1, so all n = 2048 positive eigenvalues form one chain cluster,
+    while the reorthogonalisation keeps only pairs within 0.1 ||T_s||_1 (a
+    band of about 400 of the 2048).  Exact eigenvalues, residual and
+    orthonormality."""
+    N = 4096
+    n = N // 2
+    k = np.arange(1, N, dtype=np.float64)
+    alpha = np.sqrt(k * (N - k))
+    exact = np.arange(1, N, 2, dtype=np.float64)
+    tn = bo.gershgorin_bound(alpha)
+    assert 2.0 <= 1e-3 * tn   # one chain
+    lam, V = ctx.tridiag_eig(tt(alpha))
+    lam, V = npc(lam), npc(V)
+    el = float(np.max(np.abs(lam - exact))) / tn
+    Ts = bo.tridiag_T_s(alpha)
+    res = float(np.max(np.abs(Ts @ V - V * lam[None, :]))) / tn
+    orth = float(np.max(np.abs(V.T @ V - np.eye(n))))
+    say(f"[tridiag_eig band] Clement N={N}: eig {el:.2e} residual {res:.2e} orthogonality {orth:.2e}")
+    assert el <= 1e-13 and res <= 1e-13 and orth <= 1e-13 * max(1.0, math.sqrt(n) / 8)
+
+
 def test_tridiag_eig_split_degenerate(ctx):
     say("[tridiag_eig] split degenerate")
     blk = [1.0, 0.7, 2.0, 0.3, 1.1]

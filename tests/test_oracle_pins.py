@@ -128,6 +128,22 @@ def test_bisection_matches_library():
         assert np.max(np.abs(lam - ev)) <= 2 * N * EPS * bo.gershgorin_bound(alpha)
 
 
+def test_bisection_clement_closed_form():
+    """The Clement matrix (zero diagonal, off-diagonals sqrt(k (N - k))) has
+    the eigenvalues N - 1, N - 3, ..., -(N - 1): the positive half from
+    bisection, and the inverse-iteration vectors of this equally spaced,
+    chained spectrum, against the closed form."""
+    for N in [2, 8, 64, 256]:
+        k = np.arange(1, N, dtype=np.float64)
+        alpha = np.sqrt(k * (N - k))
+        lam = bo.bisect_positive(alpha)
+        exact = np.arange(1, N, 2, dtype=np.float64)
+        assert np.max(np.abs(lam - exact)) <= 4 * EPS * N
+    V = bo.inverse_iteration(alpha, lam)
+    Ts = bo.tridiag_T_s(alpha)
+    assert np.max(np.abs(Ts @ V - V * lam[None, :])) <= 1e-12 * N
+
+
 def test_inverse_iteration_split_degenerate():
     # alpha with zeros splits T_s into identical blocks: eigenvalues are exactly
     # repeated and the reorthogonalised vectors must still be an orthonormal
