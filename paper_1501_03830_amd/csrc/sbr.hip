@@ -731,7 +731,8 @@ __device__ inline void q2_fetch_Z(const BSE_GLOBAL double* __restrict__ Z, long 
 // it0 = H (16 - 4 it0 K steps from k = 16 it0), then i-tile it1 = 3 - H.
 template <int H>
 __device__ inline void q2_products(double (*Zs)[QC + 1], double (*Vs)[VLD], double (*Ws)[QC + 1],
-                                   const double (&tr)[20], int base, int cl) {
+                                   double (&tr)[20], const BSE_GLOBAL double* __restrict__ Tnext, int base,
+                                   int cl) {
   const int lane = threadIdx.x & 63, kq = lane >> 4, li = lane & 15;
   auto zrow = [&](int m) { return (base + m) & (2 * BW - 1); };
   // W1 = V^T Zwin: l-tiles 2H and 2H + 1, window rows 16 lt .. 16 lt + 79
@@ -764,6 +765,13 @@ __device__ inline void q2_products(double (*Zs)[QC + 1], double (*Vs)[VLD], doub
     for (int st = 0; st < n0; ++st) {
       a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(tr[st], Ws[16 * it0 + 4 * st + kq][cl], a0, 0, 0, 0);
       if (st < n1) a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(tr[n0 + st], Ws[16 * it1 + 4 * st + kq][cl], a1, 0, 0, 0);
+    }
+    // the next group's T into the same registers: a group's time to arrive
+    if (Tnext) {
+#pragma unroll
+      for (int st = 0; st < n0; ++st) tr[st] = Tnext[(16 * it0 + li) + (long)(16 * it0 + 4 * st + kq) * BW];
+#pragma unroll
+      for (int st = 0; st < n1; ++st) tr[n0 + st] = Tnext[(16 * it1 + li) + (long)(16 * it1 + 4 * st + kq) * BW];
     }
     __syncthreads();   // every wave has read W1
 #pragma unroll
@@ -835,7 +843,7 @@ __global__ __launch_bounds__(QT) void k_sbr_q2(const Prob* __restrict__ probs, c
   // or {1, 2, 5, 6} (40 steps in all)
   const int it0 = h ? 1 : 0, it1 = h ? 2 : 3;
   const int nk0 = 16 - 4 * it0;   // k steps of i-tile it0 (T[i][k] = 0 for k < i)
-  double zpf[ZPF], vpf[VPF];
+  double zpf[ZPF], vpf[VPF], tr[20];
   unsigned zmask = 0, vmask = 0;
   for (int sb = nsb - 1; sb >= 0; --sb) {
     const int s0 = BW * sb, nt = nsb - sb;
@@ -860,25 +868,40 @@ __global__ __launch_bounds__(QT) void k_sbr_q2(const Prob* __restrict__ probs, c
         }
       }
       q2_put_V(vpf, vmask, N, s0, R0, Vs);
-      // this group's T (registers), then the next group's rows and reflectors
-      const BSE_GLOBAL double* __restrict__ Tg = gbl(Tbuf) + q2_group(nsb, sb, t) * (BW * BW);
-      double tr[20];
+      // this group's T: in registers since the previous group's W2 step,
+      // except for the first group
+      if (sb == nsb - 1 && t == 0) {
+        const BSE_GLOBAL double* __restrict__ Tg = gbl(Tbuf) + q2_group(nsb, sb, t) * (BW * BW);
 #pragma unroll
-      for (int j = 0; j < 20; ++j) {
-        const int it = (j < nk0) ? it0 : it1;
-        const int k0 = (j < nk0) ? 16 * it0 + 4 * j : 16 * it1 + 4 * (j - nk0);
-        tr[j] = Tg[(16 * it + li) + (long)(k0 + kq) * BW];
+        for (int j = 0; j < 20; ++j) {
+          const int it = (j < nk0) ? it0 : it1;
+          const int k0 = (j < nk0) ? 16 * it0 + 4 * j : 16 * it1 + 4 * (j - nk0);
+          tr[j] = Tg[(16 * it + li) + (long)(k0 + kq) * BW];
+        }
       }
+      // the group after this one: (sb, t + 1), else the first of block sb - 1
+      const long gnext = (t + 1 < nt) ? q2_group(nsb, sb, t + 1) : (sb > 0 ? q2_group(nsb, sb - 1, 0) : -1);
+      const BSE_GLOBAL double* __restrict__ Tnext = gnext >= 0 ? gbl(Tbuf) + gnext * (BW * BW) : nullptr;
+      // the next group's rows and reflectors
       if (t + 1 < nt) {
         q2_fetch_Z(Z, ld, N, c0, R0 + BW, zpf, zmask);
         q2_fetch_V(W, ld, N, s0, R0 + BW, vpf, vmask);
       }
       __syncthreads();
-      if (h == 0) q2_products<0>(Zs, Vs, Ws, tr, base, cl);
-      else q2_products<1>(Zs, Vs, Ws, tr, base, cl);
+      if (h == 0) q2_products<0>(Zs, Vs, Ws, tr, Tnext, base, cl);
+      else q2_products<1>(Zs, Vs, Ws, tr, Tnext, base, cl);
       // rows leaving the window: the first B (a fixed count per thread), or
       // all of it after the block's last group
-      if (t + 1 < nt) {
+      if (t + 1 < nt && c0 + QC <= N) {
+        // rows R0 .. R0 + 63 lie above row N - 1 when the block has a next
+        // group: no bounds to test, straight-line stores
+#pragma unroll
+        for (int u = 0; u < BW * QC / QT; ++u) {
+          const int idx = tid + QT * u;
+          const int m = idx % BW, c = idx / BW;
+          Z[(long)R0 + m + (long)(c0 + c) * ld] = Zs[(base + m) & (2 * BW - 1)][c];
+        }
+      } else if (t + 1 < nt) {
 #pragma unroll
         for (int u = 0; u < BW * QC / QT; ++u) {
           const int idx = tid + QT * u;
