@@ -1,7 +1,7 @@
 """Accuracy measures fixed by the paper, plus phase- and basis-invariant
 comparisons of eigenvector sets.
 
-TEST INFRASTRUCTURE ONLY.  Used to judge both the oracle and the GPU path;
+TEST INFRASTRUCTURE ONLY.  Used to assess both the oracle and the GPU path;
 none of it is part of the solver.
 """
 
