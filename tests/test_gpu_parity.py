@@ -169,8 +169,8 @@ def test_tridiag_eig_band_reorth(ctx):
     1 .. N-1) has the eigenvalues N - 1, N - 3, ..., -(N - 1), equally spaced
     by 2.  At N = 4096 the spacing is below the cluster criterion 1e-3
     ||T_s||_1, so all n = 2048 positive eigenvalues form one chain cluster,
-    while the reorthogonalisation keeps only pairs within 0.1 ||T_s||_1 (a
-    band of about 400 of the 2048).  Exact eigenvalues, residual and
+    while the reorthogonalisation keeps only pairs within 0.01 ||T_s||_1 (a
+    band of about 40 of the 2048).  Exact eigenvalues, residual and
     orthonormality."""
     N = 4096
     n = N // 2

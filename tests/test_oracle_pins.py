@@ -144,6 +144,29 @@ def test_bisection_clement_closed_form():
     assert np.max(np.abs(Ts @ V - V * lam[None, :])) <= 1e-12 * N
 
 
+def test_inverse_iteration_far_pairs_orthogonal():
+    """Inverse iteration alone (no reorthogonalisation) leaves eigenvectors
+    whose eigenvalues are farther apart than 0.01 ||T_s||_1 orthogonal to
+    far below 1e-13: the measured basis for leaving such pairs out of the
+    GPU's cluster reorthogonalisation (inner products scale like
+    eps ||T_s|| / |lambda_i - lambda_j|)."""
+    cases = []
+    p = gen_bse(384, s_a=0.3, s_b=0.05, seed=3)
+    Lo, _ = bo.cholesky(bo.build_M(p.A, p.B))
+    ao, _, _ = bo.skew_tridiagonalize(bo.form_W(Lo))
+    cases.append(ao)
+    N = 1024
+    k = np.arange(1, N, dtype=np.float64)
+    cases.append(np.sqrt(k * (N - k)))
+    for alpha in cases:
+        lam = bo.bisect_positive(alpha)
+        tn = bo.gershgorin_bound(alpha)
+        V = bo.inverse_iteration(alpha, lam)
+        G = np.abs(V.T @ V - np.eye(lam.shape[0]))
+        far = np.abs(lam[:, None] - lam[None, :]) > 0.01 * tn
+        assert np.max(G[far]) <= 2e-14
+
+
 def test_inverse_iteration_split_degenerate():
     # alpha with zeros splits T_s into identical blocks: eigenvalues are exactly
     # repeated and the reorthogonalised vectors must still be an orthonormal
