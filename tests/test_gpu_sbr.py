@@ -193,6 +193,52 @@ def test_two_stage_vectors_closed_form_2048(ctx):
     assert err <= 1e-10 and res <= 1e-12
 
 
+def test_two_stage_vectors_closed_form_8192(ctx):
+    """The benchmark order (n = 8192, N = 16384) through the two-stage
+    reduction with eigenvectors, in the launch configuration the benchmark
+    uses: exact eigenvalues, and the residuals of 32 sampled eigenpairs
+    computed on the device from the logical A and B."""
+    from paper_1501_03830_amd import _lib
+    from paper_1501_03830_amd.api import to_colmajor
+    n = 8192
+    p = gen_closed_form(n, seed=30)
+    dev = torch.device("cuda", 0)
+    Ac = to_colmajor(torch.from_numpy(p.A), dev)
+    Bc = to_colmajor(torch.from_numpy(p.B), dev)
+    exact = torch.from_numpy(np.asarray(p.exact_lambda)).to(dev)
+    del p
+    lam = torch.empty(n, dtype=torch.float64, device=dev)
+    X = torch.empty((n, 2 * n), dtype=torch.complex128, device=dev)
+    info, rep = ctx.solve_raw(n, Ac, Bc, lam, X, report=True, extra_flags=_lib.BSE_TWO_STAGE)
+    assert info == 0
+    lmax = float(exact.max())
+    err = float((lam - exact).abs().max()) / lmax
+    A = Ac.transpose(0, 1)
+    B = Bc.transpose(0, 1)
+    Af = torch.tril(A) + torch.tril(A, -1).conj().transpose(0, 1)
+    Bf = torch.tril(B) + torch.tril(B, -1).transpose(0, 1)
+    cols = torch.arange(0, n, n // 32, device=dev)
+    Xs = X[cols].transpose(0, 1)
+    x1, x2 = Xs[:n], Xs[n:]
+    lc = lam[cols][None, :]
+    r = torch.cat([Af @ x1 + Bf @ x2 - x1 * lc, -(Bf.conj() @ x1) - (Af.conj() @ x2) - x2 * lc])
+    res = float(r.abs().max()) / lmax
+    say(f"[two-stage vectors] n={n}: eig {err:.2e} sampled residual {res:.2e}, {rep['total_ms']:.0f} ms")
+    assert err <= 1e-10 and res <= 1e-12
+
+
+def test_two_stage_with_twisted_vectors(ctx):
+    """BSE_TWO_STAGE together with BSE_EIGVEC_TWISTED: the tridiagonal
+    eigenvectors by twisted factorisations, back through both stages."""
+    from paper_1501_03830_amd import _lib
+    for n in (50, 130):
+        p = gen_bse(n, s_a=0.3, s_b=0.05, seed=950 + n)
+        ro = oracle.solve(p.A, p.B, p.d)
+        r = ctx.solve(tt(p.A), tt(p.B), d_r=tt(p.d), extra_flags=_lib.BSE_TWO_STAGE | _lib.BSE_EIGVEC_TWISTED)
+        assert r["info"] == 0
+        _check_vectors(p.A, p.B, p.d, r, ro, f"[two-stage + twisted] n={n}")
+
+
 def test_two_stage_real_path(ctx):
     """Algorithm 2 (real A, B) through the two-stage reduction and its
     back-transformation: eigenvalues, eigenvectors and weights against the
