@@ -94,8 +94,16 @@ __device__ inline void chol_matrix(const Prob& P, int sel, BSE_GLOBAL double*& M
 // of the scaled column is formed by the other lanes with the same expression,
 // so all lanes use identical values.  Entries above the diagonal are scratch
 // and are never stored.
+// x of lane l, bit for bit, in every lane (the readlane builtin moves one
+// 32-bit word, so a double goes as its two halves)
+__device__ inline double readlane_f64(double x, int l) {
+  const long long b = __double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffLL), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)((unsigned long long)b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 __global__ __launch_bounds__(TB) void k_potf2(const Prob* __restrict__ probs, int sel, int k0) {
-  __shared__ double colbuf[2][TB];
   const Prob& P = probs[blockIdx.z];
   BSE_GLOBAL double* M;
   long ld;
@@ -106,6 +114,8 @@ __global__ __launch_bounds__(TB) void k_potf2(const Prob* __restrict__ probs, in
   if (sel == 1 && *gbl(P.reorth) == 0) return;   // no cluster Gram-Schmidt
   const int nbk = min(TB, N - k0);
   const int t = threadIdx.x;
+  // one wavefront, lane t holding row t: column j's entries reach every lane
+  // by readlane (no LDS round trip and no barrier per column)
   double a[TB];
 #pragma unroll
   for (int c = 0; c < TB; ++c)
@@ -113,19 +123,17 @@ __global__ __launch_bounds__(TB) void k_potf2(const Prob* __restrict__ probs, in
 #pragma unroll
   for (int j = 0; j < TB; ++j) {
     if (j < nbk) {   // uniform
-      double* col = colbuf[j & 1];
-      col[t] = a[j];
-      __syncthreads();
-      const double piv = col[j];
+      const double colj = a[j];   // column j before scaling (row t)
+      const double piv = readlane_f64(colj, j);
       if (!(piv > 0.0) || !isfinite(piv)) {
         if (t == 0) *info = k0 + j + 1;
         return;  // uniform: every lane read the same pivot
       }
       const double ljj = sqrt(piv);
       const double rinv = 1.0 / ljj;
-      a[j] = (t == j) ? ljj : a[j] * rinv;
+      a[j] = (t == j) ? ljj : colj * rinv;
 #pragma unroll
-      for (int c = j + 1; c < TB; ++c) a[c] -= a[j] * (col[c] * rinv);
+      for (int c = j + 1; c < TB; ++c) a[c] -= a[j] * (readlane_f64(colj, c) * rinv);
     }
   }
 #pragma unroll
