@@ -56,6 +56,34 @@ def test_plan_within_dispatch_limits(n, prec):
     assert ws == _lib.load().bse_footprint_bytes(n, prec, 3)
 
 
+@pytest.mark.parametrize("n", [1, 2, 33, 64, 2048, 8192, 16384])
+def test_plan_two_stage_with_vectors(n):
+    """The two-stage reduction with eigenvectors: panels, one chase, the
+    fill-zone copies, the Q2 factors of all nsb (nsb + 1) / 2 groups in one
+    launch (nsb = ceil((N - 2) / 64) sweep blocks), Q2 on ceil(N / 64) column
+    panels, then the block back-transformation of the band reduction's
+    N - 65 reflectors; every launch within the dispatch limits."""
+    rc, total, ws, kern = plan([n], _lib.BSE_PREC_FP64,
+                               _lib.BSE_WANT_VECTORS | _lib.BSE_WANT_WEIGHTS | _lib.BSE_TWO_STAGE)
+    assert rc == 0, _lib.last_error()
+    N = 2 * n
+    assert count(kern, "sk_symv") == 0
+    nsb = (N - 2 + 63) // 64 if N > 2 else 0
+    if nsb:
+        assert kern["k_sbr_chase"]["launches"] == 1
+        assert kern["k_sbr_q2T"]["launches"] == 1
+        assert kern["k_sbr_q2T"]["grid_max"][0] == nsb * (nsb + 1) // 2
+        assert kern["k_sbr_q2"]["grid_max"][0] == (N + 63) // 64
+        assert kern["k_sbr_fill"]["launches"] == 2
+    if N - 65 > 0:
+        assert kern["k_extract_V"]["launches"] == (N - 65 + 255) // 256
+    for name, v in kern.items():
+        assert min(v["grid_min"]) >= 1, name
+        assert v["grid_max"][0] * v["block_max"] <= 0xFFFFFFFF, name
+        assert v["block_max"] <= 1024, name
+        assert v["kernarg_max"] <= 4096, name
+
+
 @pytest.mark.parametrize("prec", [_lib.BSE_PREC_FP64, _lib.BSE_PREC_FP32_REFINE])
 def test_plan_of_the_256_problem_batch(prec):
     ns = [int(k) for k in batched_sizes(256, 64, 1024, seed=4)]
