@@ -153,7 +153,7 @@ class Context:
                 "report": rep.as_dict() if rep is not None else None}
 
     def solve_tda(self, A: torch.Tensor, d_r: torch.Tensor | None = None, vectors: bool = True,
-                  report: bool = False, prec: int = _lib.BSE_PREC_FP64):
+                  report: bool = False, prec: int = _lib.BSE_PREC_FP64, extra_flags: int = 0):
         """Tamm-Dancoff solve (B = 0): eigenvalues of A ascending, x_j =
         [v_j; 0], TDA weights.  Same return layout as solve()."""
         n = A.shape[0]
@@ -169,6 +169,7 @@ class Context:
             flags |= _lib.BSE_WANT_WEIGHTS
             drb = d_r.to(dev, torch.complex128).contiguous()
             w = torch.empty(n, dtype=torch.complex128, device=dev)
+        flags |= extra_flags
         rep = _lib.BseReport() if report else None
         info = _lib.check(self.lib.bse_solve_tda(
             self.h, n, _ptr(Ac), n, prec, flags, _ptr(lam), _ptr(Xbuf), 2 * n, _ptr(drb), None, _ptr(w),

@@ -63,6 +63,25 @@ def test_tda_matches_oracle(ctx, n):
     assert el <= 1e-13 and ev <= 1e-9 and we <= 1e-10 and z <= 1e-13
 
 
+@pytest.mark.parametrize("n", [40, 300])
+def test_tda_two_stage_with_vectors(ctx, n):
+    """bse_solve_tda through the two-stage reduction and both stages'
+    back-transformations: the same bar as the one-stage TDA path."""
+    from paper_1501_03830_amd import _lib
+    p = gen_bse(n, s_a=0.3, s_b=0.05, seed=320 + n)
+    res = ctx.solve_tda(tt(p.A), d_r=tt(p.d), extra_flags=_lib.BSE_TWO_STAGE)
+    assert res["info"] == 0
+    lam, X, w = npc(res["lam"]), npc(res["X"]), npc(res["w"])
+    lo, Xo, wo = spectra.tda_solve(p.A, p.d)
+    normH = float(lo.max())
+    el = float(np.max(np.abs(lam - lo))) / normH
+    ev = metrics.compare_eigvecs(Xo, X, lo, 1e-6 * normH)
+    we = metrics.compare_weights(wo, w, lo, 1e-6 * normH)
+    z = float(np.max(np.abs(X[n:])))
+    say(f"[tda two-stage] n={n}: eig {el:.2e} vec {ev:.2e} w {we:.2e} zero block {z:.2e}")
+    assert el <= 1e-13 and ev <= 1e-9 and we <= 1e-10 and z <= 1e-13
+
+
 @pytest.mark.parametrize("n,s_a", [(200, 0.3), (2048, 0.3), (1000, 0.1)])
 def test_tda_overestimates_on_gpu(ctx, n, s_a):
     """Theorem 4 on the GPU results: the TDA eigenvalues bound the full
