@@ -192,7 +192,7 @@ class Context:
         return d, e
 
     def solve_noalloc(self, A: torch.Tensor, B: torch.Tensor, d_r: torch.Tensor | None = None,
-                      vectors: bool = True, prec: int = _lib.BSE_PREC_FP64):
+                      vectors: bool = True, prec: int = _lib.BSE_PREC_FP64, extra_flags: int = 0):
         """bse_solve_noalloc: the solve on the library's fixed workspace array
         (no device or pinned allocation inside the call).  The tensors made
         here for inputs and outputs are the caller's side.  Returns dict with
@@ -211,6 +211,7 @@ class Context:
             flags |= _lib.BSE_WANT_WEIGHTS
             drb = d_r.to(dev, torch.complex128).contiguous()
             w = torch.empty(n, dtype=torch.complex128, device=dev)
+        flags |= extra_flags
         torch.cuda.synchronize(dev)
         info = _lib.check(self.lib.bse_solve_noalloc(
             self.h, n, _ptr(Ac), n, _ptr(Bc), n, prec, flags, _ptr(lam),

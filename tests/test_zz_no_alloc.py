@@ -57,6 +57,25 @@ def test_noalloc_equals_solve_two_calls(ctx, prec_name):
         assert c["info"] == 0 and torch.equal(c["lam"], e["lam"])
 
 
+def test_noalloc_two_stage_equals_solve(ctx):
+    """The two-stage reduction with eigenvectors on the fixed array (its
+    chase reflectors, fill-zone copy and Q2 factors all live in the
+    problem's workspace): bit for bit bse_solve with the same flag, on two
+    calls in a row, the second smaller."""
+    from paper_1501_03830_amd import _lib
+    for k, n in enumerate((260, 90)):
+        p = gen_bse(n, s_a=0.3, s_b=0.05, seed=4200 + k)
+        say(f"[noalloc] two-stage call {k + 1}: n={n}")
+        a = ctx.solve_noalloc(tt(p.A), tt(p.B), d_r=tt(p.d), extra_flags=_lib.BSE_TWO_STAGE)
+        torch.cuda.synchronize()
+        b = ctx.solve(tt(p.A), tt(p.B), d_r=tt(p.d), extra_flags=_lib.BSE_TWO_STAGE)
+        torch.cuda.synchronize()
+        assert a["info"] == 0 and b["info"] == 0
+        assert torch.equal(a["lam"], b["lam"])
+        assert torch.equal(a["X"], b["X"])
+        assert torch.equal(a["w"], b["w"])
+
+
 def test_noalloc_rejects_oversized(ctx):
     from paper_1501_03830_amd import _lib
     lib = ctx.lib
