@@ -102,25 +102,28 @@ __device__ inline int sturm_count(Ptr e2, int N, double x, double pivmin) {
 }
 
 // Bisection for eigenvalue j of T_s (the (n+j)-th smallest), run as
-// multisection by a group of MS_LANES lanes with results bit for bit those of
+// multisection by a group of 2^L lanes with results bit for bit those of
 // plain bisection: each round, lane g evaluates the Sturm count at node g + 1
-// of the next MS_LEVELS levels of the bisection tree (heap order, midpoints
-// formed exactly as the sequential loop forms them), then every lane replays
-// the MS_LEVELS bisection steps -- tolerance test, midpoint, count, half --
-// reading each count from the lane that owns the node.  One round costs one
-// Sturm count instead of three; with 8 lanes per eigenvalue a solve of
-// order n runs n/8 wavefronts, about one per SIMD at n = 8192 (16 lanes gave
-// two per SIMD and fewer rounds, and measured slower: the counts are chains
-// of dependent divisions).
-constexpr int MS_LANES = 8;
-constexpr int MS_LEVELS = 3;   // nodes 1 .. 7
+// of the next L levels of the bisection tree (heap order, midpoints formed
+// exactly as the sequential loop forms them), then every lane replays the L
+// bisection steps -- tolerance test, midpoint, count, half -- reading each
+// count from the lane that owns the node.  One round costs one Sturm count
+// instead of L; with 8 lanes per eigenvalue (L = 3) a solve of order n runs
+// n/8 wavefronts, about one per SIMD at n = 8192 (16 lanes gave two per SIMD
+// and fewer rounds, and measured slower: the counts are chains of dependent
+// divisions).  The 2^L - 1 counts of a round buy L levels, so multisection
+// spends (2^L)/L lane-counts per level against 1 for plain bisection: a
+// launch with enough eigenvalues to fill the device (a batch) runs L = 0,
+// one lane per eigenvalue and the plain loop, with the same results.
+template <int L>
 __global__ __launch_bounds__(64) void k_bisect(const Prob* __restrict__ probs) {
+  constexpr int LANES = 1 << L;
   const Prob& P = probs[blockIdx.z];
   const int N = P.N, n = P.n;
   const int lane = threadIdx.x & 63;
-  const int g = lane % MS_LANES;
+  const int g = lane % LANES;
   const int base = lane - g;   // first lane of this eigenvalue's group
-  const int j = (int)(((long)blockIdx.x * blockDim.x + threadIdx.x) / MS_LANES);
+  const int j = (int)(((long)blockIdx.x * blockDim.x + threadIdx.x) / LANES);
   if (j >= n) return;   // the whole group
   const BSE_CONST double* __restrict__ e2 = ro(P.e2);
   const BSE_CONST double* __restrict__ scal = ro(P.scal);
@@ -129,43 +132,59 @@ __global__ __launch_bounds__(64) void k_bisect(const Prob* __restrict__ probs) {
   double lo = 0.0;
   double hi = scal[1] * (1.0 + 4.0 * EPS) + 4.0 * pivmin;
   const int target = n + j;
-  const int node = g + 1;
-  const int depth = 31 - __clz(node);
-  int steps = 0;
-  bool done = false;
-  while (!done) {   // uniform inside the group
-    double a = lo, b = hi;
-    for (int lev = depth - 1; lev >= 0; --lev) {
-      const double m = 0.5 * (a + b);
-      if ((node >> lev) & 1) a = m;
-      else b = m;
-    }
-    const int c = (node < (1 << MS_LEVELS)) ? sturm_count(e2, N, 0.5 * (a + b), pivmin) : 0;
-    int nd = 1;
-    for (int lev = 0; lev < MS_LEVELS; ++lev) {
+  if constexpr (L == 0) {
+    for (int steps = 0;; ++steps) {
       const double tol = fmax(2.0 * EPS * fmax(fabs(lo), fabs(hi)), 4.0 * pivmin);
-      if (hi - lo <= tol || steps >= 200) {
-        done = true;
-        break;
-      }
+      if (hi - lo <= tol || steps >= 200) break;
       const double mid = 0.5 * (lo + hi);
       if (mid <= lo || mid >= hi) {
         hi = lo;
-        done = true;
         break;
       }
-      const int cn = __shfl(c, base + nd - 1, 64);
-      ++steps;
-      if (cn <= target) {
-        lo = mid;
-        nd = 2 * nd + 1;
-      } else {
-        hi = mid;
-        nd = 2 * nd;
+      if (sturm_count(e2, N, mid, pivmin) <= target) lo = mid;
+      else hi = mid;
+    }
+    lam[j] = 0.5 * (lo + hi);
+    return;
+  } else {
+    const int node = g + 1;
+    const int depth = 31 - __clz(node);
+    int steps = 0;
+    bool done = false;
+    while (!done) {   // uniform inside the group
+      double a = lo, b = hi;
+      for (int lev = depth - 1; lev >= 0; --lev) {
+        const double m = 0.5 * (a + b);
+        if ((node >> lev) & 1) a = m;
+        else b = m;
+      }
+      const int c = (node < (1 << L)) ? sturm_count(e2, N, 0.5 * (a + b), pivmin) : 0;
+      int nd = 1;
+      for (int lev = 0; lev < L; ++lev) {
+        const double tol = fmax(2.0 * EPS * fmax(fabs(lo), fabs(hi)), 4.0 * pivmin);
+        if (hi - lo <= tol || steps >= 200) {
+          done = true;
+          break;
+        }
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) {
+          hi = lo;
+          done = true;
+          break;
+        }
+        const int cn = __shfl(c, base + nd - 1, 64);
+        ++steps;
+        if (cn <= target) {
+          lo = mid;
+          nd = 2 * nd + 1;
+        } else {
+          hi = mid;
+          nd = 2 * nd;
+        }
       }
     }
+    if (g == 0) lam[j] = 0.5 * (lo + hi);
   }
-  if (g == 0) lam[j] = 0.5 * (lo + hi);
 }
 
 __global__ void k_shifts(const Prob* __restrict__ probs) {
@@ -642,7 +661,14 @@ int bisect_batched(hipStream_t s, const Batch& b) {
   if (b.count <= 0) return 0;
   const int n0 = b.maxn();
   BSE_LAUNCH(k_tridiag_prep, dim3(1, 1, (unsigned)b.count), 1024, 0, s, b.dev);
-  BSE_LAUNCH(k_bisect, dim3((unsigned)(((long)n0 * MS_LANES + 63) / 64), 1, (unsigned)b.count), 64, 0, s, b.dev);
+  // eigenvalues of the launch: multisection (8 lanes each) while it leaves
+  // the device at most two wavefronts per SIMD, else plain bisection
+  long neig = 0;
+  for (int i = 0; i < b.count; ++i) neig += b.host[i].n;
+  if (neig * 8 <= 131072)
+    BSE_LAUNCH(k_bisect<3>, dim3((unsigned)(((long)n0 * 8 + 63) / 64), 1, (unsigned)b.count), 64, 0, s, b.dev);
+  else
+    BSE_LAUNCH(k_bisect<0>, dim3((unsigned)((n0 + 63) / 64), 1, (unsigned)b.count), 64, 0, s, b.dev);
   return 0;
 }
 
