@@ -851,12 +851,15 @@ __global__ __launch_bounds__(QT) void k_sbr_q2(const Prob* __restrict__ probs, c
       const int R0 = s0 + 1 + BW * t;
       const int base = BW * t;   // slot of window row m: (base + m) mod 2B
       if (t == 0) {
-        // first group of the block: the whole window and its reflectors
+        // first group of the block: the whole window and its reflectors; the
+        // ring's 128th slot (outside every window) is zeroed, so that it never
+        // holds uninitialised data (it only meets zero entries of V)
         for (int idx = tid; idx < (2 * BW - 1) * QC; idx += QT) {
           const int m = idx % (2 * BW - 1), c = idx / (2 * BW - 1);
           const long R = (long)R0 + m;
           Zs[(base + m) & (2 * BW - 1)][c] = (R < N && c0 + c < N) ? Z[R + (long)(c0 + c) * ld] : 0.0;
         }
+        for (int c = tid; c < QC; c += QT) Zs[(base + 2 * BW - 1) & (2 * BW - 1)][c] = 0.0;
         q2_fetch_V(W, ld, N, s0, R0, vpf, vmask);
       } else {
         // rows 63 .. 126 of this window, fetched during the previous group
