@@ -17,6 +17,8 @@ namespace bse {
 namespace {
 
 constexpr int TB = 64;
+// the sub-panel index rides in the low bits of the panel products' step
+static_assert(CHOL_PANEL % TB == 0 && CHOL_PANEL / TB < TB, "Cholesky panel of whole 64-column sub-panels");
 
 __global__ __launch_bounds__(256) void k_build_M(const Prob* __restrict__ probs) {
   const Prob& P = probs[blockIdx.z];
@@ -258,23 +260,28 @@ int potrf_batched(hipStream_t s, const Batch& b, int sel, bool reset_info) {
     while (c < from && order(b.host[c]) > k) ++c;
     return c;
   };
-  // Panels of 128 columns, each factored as two 64-column halves: the
-  // diagonal block (k_potf2), the rows below it (trsm_rows_batched), and
-  // between the halves the product that brings the second half up to date.
-  // The trailing update then runs once per 128 columns (K = 128), which
-  // halves the passes over the trailing matrix.
-  for (int k0 = 0; k0 < Nmax; k0 += 2 * TB) {
-    const int nact = count_above(b.count, k0);   // problems with a diagonal block at k0
-    BSE_LAUNCH(k_potf2, dim3(1, 1, (unsigned)nact), TB, 0, s, b.dev, sel, k0);
-    const int nrest = count_above(nact, k0 + TB);   // problems with rows below it
-    if (nrest == 0) continue;
-    BSE_TRY(trsm_rows_batched(s, b, nrest, sel, k0));
-    BSE_TRY(gemm_batched(s, b, nrest, POPS, k0));
-    BSE_LAUNCH(k_potf2, dim3(1, 1, (unsigned)nrest), TB, 0, s, b.dev, sel, k0 + TB);
-    const int nrest2 = count_above(nrest, k0 + 2 * TB);
-    if (nrest2 == 0) continue;
-    BSE_TRY(trsm_rows_batched(s, b, nrest2, sel, k0 + TB));
-    BSE_TRY(gemm_batched(s, b, nrest2, SOPS, k0));
+  // Panels of CHOL_PANEL columns, each factored in 64-column sub-panels:
+  // sub-panel h is first brought up to date with the sub-panels before it
+  // (one product with K = 64 h), then its diagonal block is factored
+  // (k_potf2) and the rows below it are solved (trsm_rows_batched).  The
+  // trailing update then runs once per panel with K = CHOL_PANEL, so that
+  // the product's tiles carry enough work to hide their loads and stores.
+  for (int k0 = 0; k0 < Nmax; k0 += CHOL_PANEL) {
+    int nact = b.count;
+    bool rows_below = true;
+    for (int h = 0; h < CHOL_PANEL / TB; ++h) {
+      const int kh = k0 + h * TB;
+      nact = count_above(nact, kh);   // problems with a diagonal block at kh
+      if (nact == 0) { rows_below = false; break; }
+      if (h > 0) BSE_TRY(gemm_batched(s, b, nact, POPS, k0 + h));
+      BSE_LAUNCH(k_potf2, dim3(1, 1, (unsigned)nact), TB, 0, s, b.dev, sel, kh);
+      nact = count_above(nact, kh + TB);   // problems with rows below it
+      if (nact == 0) { rows_below = false; break; }
+      BSE_TRY(trsm_rows_batched(s, b, nact, sel, kh));
+    }
+    if (!rows_below) break;
+    const int nrest = count_above(nact, k0 + CHOL_PANEL);
+    if (nrest > 0) BSE_TRY(gemm_batched(s, b, nrest, SOPS, k0));
   }
   return 0;
 }

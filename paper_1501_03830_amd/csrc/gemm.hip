@@ -50,36 +50,40 @@ __host__ __device__ GemmParams gemm_params(int op, const Prob& P, int step) {
   switch (op) {
     case GOP_POTRF_PANEL:
     case GOP_GRAM_PANEL: {
-      // the 128-column panel at `step`, between its two 64-column halves:
-      // A[k0+64:, k0+64:k0+128] -= A21 A21[0:64]^T with A21 = A[k0+64:, k0:k0+64]
-      // (lower triangle of the diagonal block, all of the rows below it)
+      // sub-panel h >= 1 of the panel at k0 (step = k0 + h), brought up to
+      // date with the sub-panels before it in the same panel (left-looking):
+      // A[kh:, kh:kh+64] -= A[kh:, k0:kh] A[kh:kh+64, k0:kh]^T with
+      // kh = k0 + 64 h (lower triangle of the diagonal block, all of the
+      // rows below it)
       const bool gram = (op == GOP_GRAM_PANEL);
       double* Mx = gram ? P.inv : P.L;
       const int Nm = gram ? P.n : P.N;
       const long ldm = gram ? (long)P.n : ld;
-      const int k0 = step;
-      const int rest = Nm - k0 - NB;
-      if (rest <= 0) break;
-      double* a21 = Mx + (k0 + NB) + (long)k0 * ldm;
-      g.ta = 0; g.tb = 1; g.M = rest; g.N = rest < NB ? rest : NB; g.K = NB; g.alpha = -1.0; g.beta = 1.0;
+      const int h = step & (NB - 1);
+      const int k0 = step - h;
+      const int kh = k0 + NB * h;
+      const int rest = Nm - kh;
+      if (h <= 0 || rest <= 0) break;
+      double* a21 = Mx + kh + (long)k0 * ldm;
+      g.ta = 0; g.tb = 1; g.M = rest; g.N = rest < NB ? rest : NB; g.K = NB * h; g.alpha = -1.0; g.beta = 1.0;
       g.A = a21; g.lda = ldm; g.B = a21; g.ldb = ldm;
-      g.C = Mx + (k0 + NB) + (long)(k0 + NB) * ldm; g.ldc = ldm; g.c_uplo = 3;
+      g.C = Mx + kh + (long)kh * ldm; g.ldc = ldm; g.c_uplo = 3;
       if (gram) {
-        g.band_lam = P.lambda; g.band_scal = P.scal; g.band_r0 = g.band_c0 = k0 + NB; g.band_cfix = -1; g.band_n = P.n;
+        g.band_lam = P.lambda; g.band_scal = P.scal; g.band_r0 = g.band_c0 = kh; g.band_cfix = -1; g.band_n = P.n;
       }
       break;
     }
     case GOP_POTRF_SYRK:
     case GOP_GRAM_SYRK: {
-      // trailing update after the 128-column panel at `step` (the panel itself
-      // is solved by k_potf2, trsm_rows_batched and the panel product):
-      // A22 -= A21 A21^T, lower triangle
+      // trailing update after the CHOL_PANEL-column panel at `step` (the
+      // panel itself is solved by k_potf2, trsm_rows_batched and the
+      // sub-panel products): A22 -= A21 A21^T, lower triangle
       const bool gram = (op == GOP_GRAM_SYRK);
       double* Mx = gram ? P.inv : P.L;
       const int Nm = gram ? P.n : P.N;
       const long ldm = gram ? (long)P.n : ld;
       const int k0 = step;
-      const int nbk = (Nm - k0 < 2 * NB) ? Nm - k0 : 2 * NB;
+      const int nbk = (Nm - k0 < CHOL_PANEL) ? Nm - k0 : CHOL_PANEL;
       const int rest = Nm - k0 - nbk;
       if (nbk <= 0 || rest <= 0) break;  // M = N = 0: nothing to do
       double* a21 = Mx + (k0 + nbk) + (long)k0 * ldm;

@@ -81,12 +81,17 @@ constexpr int APPLYU_SUB = APPLYU_RB / 64;   // 64-row sub-blocks per reflector 
 // the workgroup prefixes of a whole panel).
 constexpr int SKTRD_NB = 64;
 
+// Columns per panel of the blocked Cholesky factorisations: the panel is
+// factored in 64-column sub-panels, and the trailing update after it is one
+// product with K = CHOL_PANEL.
+constexpr int CHOL_PANEL = 256;
+
 // The products of the chain, as functions of (problem, step).
 enum GemmOp {
   GOP_NONE = 0,
   GOP_POTRF_SYRK,  // Cholesky of M: trailing update after the panel at `step`
   GOP_GRAM_SYRK,   // Cholesky of the Gram matrix: trailing update
-  GOP_POTRF_PANEL, // Cholesky of M: second half of a 128-column panel
+  GOP_POTRF_PANEL, // Cholesky of M: sub-panel h of the panel at k0 (step = k0 + h)
   GOP_GRAM_PANEL,  // Cholesky of the Gram matrix: the same
   GOP_FORMW_C,     // L11^T L21
   GOP_FORMW_21,    // -L22^T L11
