@@ -57,6 +57,21 @@ def test_plan_within_dispatch_limits(n, prec):
     assert ws == _lib.load().bse_footprint_bytes(n, prec, 3)
 
 
+@pytest.mark.parametrize("n", [1, 2, 33, 100, 2048, 8192])
+def test_plan_cholesky_sub_panels(n):
+    """The blocked Cholesky factorisations run one diagonal-block factor
+    (k_potf2) per 64-column sub-panel and one row solve (k_trsm_rows) per
+    sub-panel with rows below it: for M (order N = 2n) and for the cluster
+    reorthogonalisation's Gram matrix (order n), whose second pass is issued
+    always and skipped on the device when the first suffices."""
+    rc, total, ws, kern = plan([n], _lib.BSE_PREC_FP64)
+    assert rc == 0, _lib.last_error()
+    N = 2 * n
+    blocks = lambda m: (m + 63) // 64
+    assert kern["k_potf2"]["launches"] == blocks(N) + 2 * blocks(n)
+    assert count(kern, "k_trsm_rows<true>") == (blocks(N) - 1) + 2 * (blocks(n) - 1)
+
+
 @pytest.mark.parametrize("n", [1, 2, 33, 64, 2048, 8192, 16384])
 def test_plan_two_stage_with_vectors(n):
     """The two-stage reduction with eigenvectors: panels, one chase, the
