@@ -134,8 +134,9 @@ __global__ __launch_bounds__(TB) void k_potf2(const Prob* __restrict__ probs, in
       const double ljj = sqrt(piv);
       const double rinv = 1.0 / ljj;
       a[j] = (t == j) ? ljj : colj * rinv;
+      // L[c][j] is lane c's scaled entry (the same product colj * rinv)
 #pragma unroll
-      for (int c = j + 1; c < TB; ++c) a[c] -= a[j] * (readlane_f64(colj, c) * rinv);
+      for (int c = j + 1; c < TB; ++c) a[c] -= a[j] * readlane_f64(a[j], c);
     }
   }
 #pragma unroll
