@@ -937,30 +937,54 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const Prob* __restrict__ 
   const long r = (long)blockIdx.x * 64 + (threadIdx.x & 63);
   const long c0 = (long)blockIdx.y * 64 + (threadIdx.x >> 6) * 16;
   if (r >= p.M) return;
-  // every load (partials and old C) of the thread's 16 entries before any
-  // store, so that they are in flight together
+  // The thread's 16 entries go through the partials split by split, with
+  // the 16 loads of a split in flight together (the sum of each entry keeps
+  // the order k = 0, 1, ...); the old C values are loaded first.  Columns
+  // past N are read at column N - 1 (in bounds) and never stored.
   const BSE_GLOBAL double* part = gbl(p.part);
   const bool read_c = p.beta != 0.0;
   bool ok[16];
-  double res[16];
+  double cold[16];   // old C (FP64 C)
+  float coldf[16];   // old C (FP32 C), widened where it is used
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const long c = c0 + q;
     ok[q] = c < p.N && !((p.c_uplo == 1 || p.c_uplo == 3) && r < c) && !(p.c_uplo == 2 && r <= c);
-    res[q] = 0.0;
-    if (!ok[q]) continue;
-    double s = 0.0;
-    for (int k = 0; k < p.splits; ++k) s += part[(long)k * p.M * p.N + r + c * p.M];
-    const double out = p.alpha * s;
-    const long o = r + c * p.ldc;
-    res[q] = read_c ? out + p.beta * (p.Cf ? (double)gbl(p.Cf)[o] : gbl(p.C)[o]) : out;
+    cold[q] = 0.0;
+    coldf[q] = 0.0f;
+  }
+  if (read_c) {   // uniform
+    if (p.Cf) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (ok[q]) coldf[q] = gbl(p.Cf)[r + (c0 + q) * p.ldc];
+    } else {
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (ok[q]) cold[q] = gbl(p.C)[r + (c0 + q) * p.ldc];
+    }
+  }
+  const long MN = (long)p.M * p.N;
+  const long cmax = (long)p.N - 1;
+  double sum[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) sum[q] = 0.0;
+  for (int k = 0; k < p.splits; ++k) {
+    const BSE_GLOBAL double* pk = part + (long)k * MN + r;
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = pk[min(c0 + q, cmax) * p.M];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) sum[q] += v[q];
   }
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     if (!ok[q]) continue;
+    const double out = p.alpha * sum[q];
+    const double res = read_c ? out + p.beta * (p.Cf ? (double)coldf[q] : cold[q]) : out;
     const long o = r + (c0 + q) * p.ldc;
-    if (p.Cf) gbl(p.Cf)[o] = (float)res[q];
-    else gbl(p.C)[o] = res[q];
+    if (p.Cf) gbl(p.Cf)[o] = (float)res;
+    else gbl(p.C)[o] = res;
   }
 }
 
